@@ -1,0 +1,419 @@
+"""FP64 CPU oracle of the differentiable face render.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product path.  It shares no code
+with the HIP library.  The ray tracing, shading and their derivatives live in
+oracle.cpp (brute force, FP64, dual numbers); this module binds it and adds the
+parts that are plain array definitions in FP64 numpy:
+
+* `smooth`, `loss_and_grad`: 3x3 Gaussian smoothing (sigma = 1) of the render
+  and the L1 photometric loss (Sec. 4 Eq. energy, Sec. 4 "Variance
+  Reduction");
+* `blend`, `blend_vjp`: the morphable model (Sec. 3.1 identity + expression,
+  Sec. 3.2 statistical albedo);
+* `euler_matrix`, `pose_apply`, `pose_vjp`: rigid pose of the mesh (the
+  rotation/translation of Sec. 3.1 "Camera model", applied to the object);
+* `adam`: Adam with the learning rates of Sec. 5 "Implementation Details".
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.cpp")
+
+VIS_OCCLUDED, VIS_VISIBLE, VIS_CULLED, VIS_NONE = 0, 1, 2, 3
+FLAG_EDGE, FLAG_TIE, FLAG_TRANGE, FLAG_COSO, FLAG_COSL, FLAG_G1 = 1, 2, 4, 8, 16, 32
+NO_FORCE_HIT = -2
+NO_FORCE_VIS = 0xFF
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with g++ (FP64, no FMA contraction)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", "-pthread",
+               _SRC, "-o", _SO + ".tmp"]
+        subprocess.check_call(cmd)
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class OrScene(ctypes.Structure):
+    _fields_ = [
+        ("n_verts", ctypes.c_int32), ("n_tris", ctypes.c_int32), ("n_lights", ctypes.c_int32),
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("spp", ctypes.c_int32),
+        ("verts", ctypes.c_void_p), ("tris", ctypes.c_void_p), ("diffuse", ctypes.c_void_p),
+        ("specular", ctypes.c_void_p), ("roughness", ctypes.c_void_p),
+        ("light_p0", ctypes.c_void_p), ("light_e1", ctypes.c_void_p), ("light_e2", ctypes.c_void_p),
+        ("light_rad", ctypes.c_void_p), ("light_shape", ctypes.c_void_p),
+        ("cam_R", ctypes.c_void_p), ("cam_T", ctypes.c_void_p),
+        ("fov_y", ctypes.c_float), ("brdf_variant", ctypes.c_int32), ("components", ctypes.c_int32),
+        ("pad_", ctypes.c_int32), ("seed", ctypes.c_uint64), ("step", ctypes.c_uint32),
+        ("pad2_", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        L.oracle_philox.argtypes = [ctypes.c_uint64, ctypes.c_int64, P, P]
+        L.oracle_vertex_normals.argtypes = [P, P]
+        L.oracle_normals_vjp.argtypes = [P, P, P]
+        L.oracle_render.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, ctypes.c_int32]
+        L.oracle_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int32]
+        L.oracle_edge_grad.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_int32]
+        L.oracle_edge_count.argtypes = [P]
+        L.oracle_edge_count.restype = ctypes.c_int32
+        L.oracle_camera_ray.argtypes = [P, ctypes.c_double, ctypes.c_double, P]
+        L.oracle_closest_hit.argtypes = [P, P, P, P, P]
+        L.oracle_line_crossings.argtypes = [P, P, P, P, ctypes.c_int32]
+        L.oracle_line_crossings.restype = ctypes.c_int32
+        L.oracle_occluded.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, P]
+        L.oracle_occluded.restype = ctypes.c_int32
+        L.oracle_brdf.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, ctypes.c_double, P, P]
+        L.oracle_g1_of_a.argtypes = [ctypes.c_double]
+        L.oracle_g1_of_a.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+class _Bound:
+    """Keeps the FP32 arrays of a scene alive while the C side reads them."""
+
+    def __init__(self, scene, brdf_variant=0, components=3):
+        f32 = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+        i32 = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+        L = scene.lights
+        self.keep = [f32(scene.verts), i32(scene.tris), f32(scene.diffuse), f32(scene.specular),
+                     f32(scene.roughness), f32(L.p0), f32(L.e1), f32(L.e2), f32(L.rad), i32(L.shape),
+                     f32(scene.camera.R), f32(scene.camera.T)]
+        s = OrScene()
+        s.n_verts, s.n_tris, s.n_lights = scene.n_verts, scene.n_tris, L.count
+        s.width, s.height, s.spp = scene.camera.W, scene.camera.H, scene.spp
+        (s.verts, s.tris, s.diffuse, s.specular, s.roughness, s.light_p0, s.light_e1, s.light_e2,
+         s.light_rad, s.light_shape, s.cam_R, s.cam_T) = [a.ctypes.data for a in self.keep]
+        s.fov_y = scene.camera.fov_y
+        s.brdf_variant, s.components = int(brdf_variant), int(components)
+        s.seed, s.step = int(scene.seed), int(scene.step)
+        self.s = s
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+# ---------------------------------------------------------------------------
+# Counter-based generator
+# ---------------------------------------------------------------------------
+
+def philox(key: int, counters: np.ndarray) -> np.ndarray:
+    """Philox4x32-10 outputs [n,4] uint32 for counters [n,4] uint32."""
+    c = np.ascontiguousarray(counters, dtype=np.uint32).reshape(-1, 4)
+    out = np.zeros_like(c)
+    lib().oracle_philox(ctypes.c_uint64(key), c.shape[0], _ptr(c), _ptr(out))
+    return out
+
+
+def unit24(x: np.ndarray) -> np.ndarray:
+    return (np.asarray(x, dtype=np.uint32) >> 8).astype(np.float64) * 2.0 ** -24
+
+
+# ---------------------------------------------------------------------------
+# Render, decisions and interior gradient
+# ---------------------------------------------------------------------------
+
+def vertex_normals(scene) -> np.ndarray:
+    b = _Bound(scene)
+    out = np.zeros((scene.n_verts, 3))
+    lib().oracle_vertex_normals(b.ref, _ptr(out))
+    return out
+
+
+def normals_vjp(scene, g_n: np.ndarray) -> np.ndarray:
+    b = _Bound(scene)
+    g = np.ascontiguousarray(g_n, dtype=np.float64)
+    out = np.zeros((scene.n_verts, 3))
+    lib().oracle_normals_vjp(b.ref, _ptr(g), _ptr(out))
+    return out
+
+
+def render(scene, pixels=None, force_hit=None, force_vis=None, brdf_variant=0, components=3, nthreads=None):
+    """FP64 render of all pixels (or a subset of pixel ids y*W+x).
+
+    Returns dict: rgb [n,3], hit [n,S], pflag [n,S], vis [n,S,L], sflag [n,S,L]."""
+    b = _Bound(scene, brdf_variant, components)
+    W, H, S, L = scene.camera.W, scene.camera.H, scene.spp, scene.lights.count
+    pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int32)
+    n = W * H if pix is None else pix.shape[0]
+    rgb = np.zeros((n, 3))
+    hit = np.zeros((n, S), np.int32)
+    pflag = np.zeros((n, S), np.uint8)
+    vis = np.zeros((n, S, L), np.uint8)
+    sflag = np.zeros((n, S, L), np.uint8)
+    fh = None if force_hit is None else np.ascontiguousarray(force_hit, dtype=np.int32)
+    fv = None if force_vis is None else np.ascontiguousarray(force_vis, dtype=np.uint8)
+    lib().oracle_render(b.ref, n, _ptr(pix), _ptr(fh), _ptr(fv), _ptr(rgb), _ptr(hit), _ptr(pflag),
+                        _ptr(vis), _ptr(sflag), nthreads or default_threads())
+    return dict(rgb=rgb, hit=hit, pflag=pflag, vis=vis, sflag=sflag)
+
+
+def grad(scene, hit, vis, dEdp, pixels=None, brdf_variant=0, components=3, nthreads=None,
+         include_normals_path=True):
+    """Interior gradient of sum_p dEdp[p] . rgb[p] with decisions (hit, vis) fixed.
+
+    dEdp is [n,3] for the pixel subset (or [H*W,3] / [H,W,3] for all pixels).
+    Returns dict of FP64 arrays: verts [N,3] (total, including the path through
+    the vertex normals unless include_normals_path is False), normals [N,3],
+    diffuse [N,3], specular [N,3], rough [N], light [L,9] (p0,e1,e2), rad [L,3],
+    cam [12] (R row-major, T)."""
+    b = _Bound(scene, brdf_variant, components)
+    N, L = scene.n_verts, scene.lights.count
+    pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int32)
+    n = scene.camera.W * scene.camera.H if pix is None else pix.shape[0]
+    g = np.ascontiguousarray(np.asarray(dEdp, dtype=np.float64).reshape(n, 3))
+    out = dict(verts=np.zeros((N, 3)), normals=np.zeros((N, 3)), diffuse=np.zeros((N, 3)),
+               specular=np.zeros((N, 3)), rough=np.zeros(N), light=np.zeros((L, 9)),
+               rad=np.zeros((L, 3)), cam=np.zeros(12))
+    h = np.ascontiguousarray(hit, dtype=np.int32)
+    v = np.ascontiguousarray(vis, dtype=np.uint8)
+    lib().oracle_grad(b.ref, n, _ptr(pix), _ptr(h), _ptr(v), _ptr(g), _ptr(out["verts"]),
+                      _ptr(out["normals"]), _ptr(out["diffuse"]), _ptr(out["specular"]), _ptr(out["rough"]),
+                      _ptr(out["light"]), _ptr(out["rad"]), _ptr(out["cam"]), nthreads or default_threads())
+    if include_normals_path:
+        out["verts"] = out["verts"] + normals_vjp(scene, out["normals"])
+    return out
+
+
+def edge_count(scene) -> int:
+    return int(lib().oracle_edge_count(_Bound(scene).ref))
+
+
+def edge_grad(scene, dEdp_full, n_samples, select=None, brdf_variant=0, components=3, nthreads=None):
+    """Primary-visibility boundary term of edge sampling (n_samples samples over
+    the silhouette edges).  Returns dict: verts [N,3], cam [12], edge [n,4]
+    (edge id, pixel id, hit of the minus ray, hit of the plus ray), flag [n],
+    ltot (total film length of the silhouette)."""
+    b = _Bound(scene, brdf_variant, components)
+    N = scene.n_verts
+    sel = None if select is None else np.ascontiguousarray(select, dtype=np.int32)
+    n_sel = n_samples if sel is None else sel.shape[0]
+    g = np.ascontiguousarray(np.asarray(dEdp_full, dtype=np.float64).reshape(-1, 3))
+    gv = np.zeros((N, 3))
+    gc = np.zeros(12)
+    edge = np.zeros((n_sel, 4), np.int32)
+    flag = np.zeros(n_sel, np.uint8)
+    ltot = np.zeros(1)
+    lib().oracle_edge_grad(b.ref, int(n_samples), n_sel, _ptr(sel), _ptr(g), _ptr(gv), _ptr(gc), _ptr(edge),
+                           _ptr(flag), _ptr(ltot), nthreads or default_threads())
+    return dict(verts=gv, cam=gc, edge=edge, flag=flag, ltot=float(ltot[0]))
+
+
+# ---------------------------------------------------------------------------
+# Single-stage probes
+# ---------------------------------------------------------------------------
+
+def _d3(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(3))
+
+
+def camera_ray(scene, fx: float, fy: float) -> np.ndarray:
+    b = _Bound(scene)
+    out = np.zeros(3)
+    lib().oracle_camera_ray(b.ref, fx, fy, _ptr(out))
+    return out
+
+
+def closest_hit(scene, o, d):
+    """Returns (id, flags, t, u, v) of the closest hit of o + t d, t > 0."""
+    b = _Bound(scene)
+    oi = np.zeros(2, np.int32)
+    od = np.zeros(3)
+    o, d = _d3(o), _d3(d)
+    lib().oracle_closest_hit(b.ref, _ptr(o), _ptr(d), _ptr(oi), _ptr(od))
+    return int(oi[0]), int(oi[1]), float(od[0]), float(od[1]), float(od[2])
+
+
+def line_crossings(scene, o, d, cap: int = 64) -> np.ndarray:
+    b = _Bound(scene)
+    ts = np.zeros(cap)
+    o, d = _d3(o), _d3(d)
+    n = lib().oracle_line_crossings(b.ref, _ptr(o), _ptr(d), _ptr(ts), cap)
+    return np.sort(ts[:min(n, cap)])
+
+
+def occluded(scene, o, d, tmin, tmax, exclude=-1):
+    b = _Bound(scene)
+    fl = np.zeros(1, np.uint8)
+    o, d = _d3(o), _d3(d)
+    occ = lib().oracle_occluded(b.ref, _ptr(o), _ptr(d), float(tmin), float(tmax), int(exclude), _ptr(fl))
+    return bool(occ), int(fl[0])
+
+
+def brdf(n, l, o, c, s, r, variant=0, components=3):
+    """Returns (f_r [3], terms {D, G1(o), G1(l), Fresnel weight})."""
+    out = np.zeros(3)
+    terms = np.zeros(4)
+    args = [_d3(x) for x in (n, l, o, c, s)]
+    lib().oracle_brdf(int(variant), int(components), *[_ptr(a) for a in args], float(r), _ptr(out), _ptr(terms))
+    return out, terms
+
+
+def g1_of_a(a: float) -> float:
+    return float(lib().oracle_g1_of_a(float(a)))
+
+
+# ---------------------------------------------------------------------------
+# Smoothing and photometric loss (FP64 numpy)
+# ---------------------------------------------------------------------------
+
+def gauss3_weights(sigma: float = 1.0) -> np.ndarray:
+    """3x3 Gaussian taps exp(-(dx^2+dy^2)/(2 sigma^2)), normalised to sum 1."""
+    d = np.array([-1.0, 0.0, 1.0])
+    K = np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / (2.0 * sigma * sigma))
+    return K / K.sum()
+
+
+def smooth(img: np.ndarray) -> np.ndarray:
+    """p~[y,x] = sum_{dy,dx} K[dy,dx] p[clamp(y+dy), clamp(x+dx)] (clamp-to-edge)."""
+    img = np.asarray(img, dtype=np.float64)
+    H, W = img.shape[:2]
+    K = gauss3_weights()
+    out = np.zeros_like(img)
+    ys, xs = np.arange(H), np.arange(W)
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            yy = np.clip(ys + dy, 0, H - 1)
+            xx = np.clip(xs + dx, 0, W - 1)
+            out += K[dy + 1, dx + 1] * img[yy][:, xx]
+    return out
+
+
+def smooth_adjoint(g: np.ndarray) -> np.ndarray:
+    """Transpose of `smooth`: scatter K[dy,dx] g[y,x] into the clamped source pixel."""
+    g = np.asarray(g, dtype=np.float64)
+    H, W = g.shape[:2]
+    K = gauss3_weights()
+    out = np.zeros_like(g)
+    ys, xs = np.arange(H), np.arange(W)
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            yy = np.clip(ys + dy, 0, H - 1)
+            xx = np.clip(xs + dx, 0, W - 1)
+            src_y = np.repeat(yy, W)
+            src_x = np.tile(xx, H)
+            np.add.at(out, (src_y, src_x), (K[dy + 1, dx + 1] * g).reshape(H * W, -1))
+    return out
+
+
+def loss_and_grad(img: np.ndarray, target: np.ndarray, smoothing: bool = True):
+    """E = sum |p~ - p^R| over pixels and channels; returns (E, dE/dp, p~).
+    sign(0) = 0."""
+    img = np.asarray(img, dtype=np.float64)
+    ps = smooth(img) if smoothing else img
+    diff = ps - np.asarray(target, dtype=np.float64)
+    E = float(np.abs(diff).sum())
+    g = np.sign(diff)
+    dEdp = smooth_adjoint(g) if smoothing else g
+    return E, dEdp, ps
+
+
+# ---------------------------------------------------------------------------
+# Morphable model, pose and Adam (FP64 numpy)
+# ---------------------------------------------------------------------------
+
+def blend(mean: np.ndarray, basis: np.ndarray, coef: np.ndarray) -> np.ndarray:
+    """mean + Sigma coef, with Sigma stored component-major ([K, 3N])."""
+    return np.asarray(mean, np.float64) + np.asarray(coef, np.float64) @ np.asarray(basis, np.float64)
+
+
+def blend_vjp(basis: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """Sigma^T g for a gradient g over the 3N blended values."""
+    return np.asarray(basis, np.float64) @ np.asarray(g, np.float64).reshape(-1)
+
+
+def _rx(a):
+    c, s = math.cos(a), math.sin(a)
+    return np.array([[1, 0, 0], [0, c, -s], [0, s, c]], np.float64)
+
+
+def _ry(a):
+    c, s = math.cos(a), math.sin(a)
+    return np.array([[c, 0, s], [0, 1, 0], [-s, 0, c]], np.float64)
+
+
+def _rz(a):
+    c, s = math.cos(a), math.sin(a)
+    return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]], np.float64)
+
+
+def _drx(a):
+    c, s = math.cos(a), math.sin(a)
+    return np.array([[0, 0, 0], [0, -s, -c], [0, c, -s]], np.float64)
+
+
+def _dry(a):
+    c, s = math.cos(a), math.sin(a)
+    return np.array([[-s, 0, c], [0, 0, 0], [-c, 0, -s]], np.float64)
+
+
+def _drz(a):
+    c, s = math.cos(a), math.sin(a)
+    return np.array([[-s, -c, 0], [c, -s, 0], [0, 0, 0]], np.float64)
+
+
+def euler_matrix(rx: float, ry: float, rz: float) -> np.ndarray:
+    """R = Rz(rz) @ Ry(ry) @ Rx(rx)."""
+    return _rz(rz) @ _ry(ry) @ _rx(rx)
+
+
+def pose_apply(v: np.ndarray, pose: np.ndarray) -> np.ndarray:
+    """World positions R v + t of object-space vertices v [N,3]; pose = (rx,ry,rz,tx,ty,tz)."""
+    p = np.asarray(pose, np.float64)
+    R = euler_matrix(*p[:3])
+    return np.asarray(v, np.float64).reshape(-1, 3) @ R.T + p[3:]
+
+
+def pose_vjp(v: np.ndarray, pose: np.ndarray, g_w: np.ndarray):
+    """Returns (g_v [N,3], g_pose [6]) for world-position gradient g_w [N,3]."""
+    p = np.asarray(pose, np.float64)
+    v = np.asarray(v, np.float64).reshape(-1, 3)
+    g_w = np.asarray(g_w, np.float64).reshape(-1, 3)
+    R = euler_matrix(*p[:3])
+    g_v = g_w @ R
+    gR = g_w.T @ v                                    # dE/dR = sum g_w v^T
+    Rx, Ry, Rz = _rx(p[0]), _ry(p[1]), _rz(p[2])
+    dR = [Rz @ Ry @ _drx(p[0]), Rz @ _dry(p[1]) @ Rx, _drz(p[2]) @ Ry @ Rx]
+    g_pose = np.array([(gR * d).sum() for d in dR] + list(g_w.sum(axis=0)))
+    return g_v, g_pose
+
+
+def adam(theta, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (Kingma & Ba) at step number t >= 1; returns (theta, m, v)."""
+    theta = np.asarray(theta, np.float64)
+    g = np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return theta - lr * mhat / (np.sqrt(vhat) + eps), m, v

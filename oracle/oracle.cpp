@@ -1,0 +1,966 @@
+// FP64 CPU oracle of the differentiable face render.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+// baseline leg of the benchmark load this library.  It shares no code with the
+// HIP path: it has its own counter-based generator, its own brute-force
+// intersection (every triangle, no acceleration structure), its own shading
+// and its own derivatives (forward-mode dual numbers, not a hand-written
+// adjoint).
+//
+// What it computes (Dib et al. 2021, "Practical Face Reconstruction via
+// Differentiable Ray Tracing"):
+//   * pixel colours p^S = F(chi), a Monte-Carlo estimate of the rendering
+//     equation with direct light only and shadows from shadow rays
+//     (Sec. 3.3 "Shadows approximation", Sec. 4 Eq. energy);
+//   * the Cook-Torrance BRDF of Appendix A (Eq. brdf, brdf_diffuse,
+//     brdf_spec, brdf_d, halfVector, brdf_g, brdf_g1, brdf_g1_a, brdf_g1_chi,
+//     brdf_f);
+//   * the derivative of the estimate with every discrete decision held fixed
+//     (the "interior" gradient that back-propagation through a ray tracer
+//     gives, Sec. 4), and the primary-visibility boundary term of edge
+//     sampling (Sec. 4 "Edge Sampling").
+// Readings of points the paper leaves open (sampling, normals, epsilons,
+// half vector, Fresnel exponent, D normalisation) are listed where they are
+// used.
+//
+// All scene inputs are FP32 arrays, promoted exactly to FP64.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <thread>
+#include <utility>
+#include <vector>
+
+extern "C" {
+
+// Mirrors the ctypes structure in oracle/__init__.py.
+struct OrScene {
+  int32_t n_verts, n_tris, n_lights, width, height, spp;
+  const float* verts;      // [N*3] world-space positions
+  const int32_t* tris;     // [F*3]
+  const float* diffuse;    // [N*3]
+  const float* specular;   // [N*3]
+  const float* roughness;  // [N]
+  const float* light_p0;   // [L*3]
+  const float* light_e1;   // [L*3]
+  const float* light_e2;   // [L*3]
+  const float* light_rad;  // [L*3]
+  const int32_t* light_shape;  // [L] 0 parallelogram, 1 triangle
+  const float* cam_R;      // [9] camera-to-world, row-major
+  const float* cam_T;      // [3]
+  float fov_y;
+  int32_t brdf_variant;    // 0 = as printed, 1 = normalised D + Schlick^5
+  int32_t components;      // bit 0 diffuse, bit 1 specular
+  int32_t pad_;
+  uint64_t seed;
+  uint32_t step;
+  uint32_t pad2_;
+};
+
+}  // extern "C"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kShadowTmin = 1e-4;   // shadow-ray start offset (reading)
+constexpr double kFlagEps = 1e-6;      // decision-ambiguity band (world units)
+constexpr double kRoughMin = 1e-3, kRoughMax = 1.0;
+constexpr double kMissFar = 1e4;       // length of a primary-ray segment that hits nothing
+
+// Flag bits.
+constexpr uint8_t FLAG_EDGE = 1;    // ray passes within kFlagEps of a triangle boundary
+constexpr uint8_t FLAG_TIE = 2;     // two hits within kFlagEps in t
+constexpr uint8_t FLAG_TRANGE = 4;  // a crossing within kFlagEps of the segment ends
+constexpr uint8_t FLAG_COSO = 8;    // |n_s . o| < kFlagEps
+constexpr uint8_t FLAG_COSL = 16;   // |n_s . l| or |n_j . l| < kFlagEps
+constexpr uint8_t FLAG_G1 = 32;     // a G1 argument within kFlagEps of its 1.6 branch point
+
+// Visibility codes of one (sample, light) pair.
+constexpr uint8_t VIS_OCCLUDED = 0, VIS_VISIBLE = 1, VIS_CULLED = 2, VIS_NONE = 3;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// -> 64-bit multiplies, with a Weyl-sequence key schedule.
+// ---------------------------------------------------------------------------
+struct Rand4 { uint32_t x[4]; };
+
+Rand4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint64_t key) {
+  uint32_t k0 = (uint32_t)(key & 0xffffffffu), k1 = (uint32_t)(key >> 32);
+  uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+    const uint32_t n1 = (uint32_t)p1;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    const uint32_t n3 = (uint32_t)p0;
+    x0 = n0; x1 = n1; x2 = n2; x3 = n3;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return Rand4{{x0, x1, x2, x3}};
+}
+
+// 24 high bits -> [0,1): exact in both FP32 and FP64.
+inline double unit24(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
+
+// Counter layout: (pixel = y*W + x, sample, purpose, step); purpose 0 is the
+// pixel jitter, 1 + j the point on light j; edge samples use purpose
+// 0x80000000 (edge pick) and 0x80000001 + j (light j), with pixel = sample id.
+constexpr uint32_t PURPOSE_JITTER = 0u;
+constexpr uint32_t PURPOSE_EDGE = 0x80000000u;
+
+// ---------------------------------------------------------------------------
+// Forward-mode dual numbers: value + K directional derivatives.
+// ---------------------------------------------------------------------------
+template <int K>
+struct Dual {
+  double v;
+  double d[K];
+  Dual() : v(0.0) { std::memset(d, 0, sizeof(d)); }
+  Dual(double x) : v(x) { std::memset(d, 0, sizeof(d)); }  // NOLINT: implicit constant
+  static Dual seed(double x, int k) { Dual r(x); r.d[k] = 1.0; return r; }
+};
+
+template <int K> Dual<K> operator+(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r; r.v = a.v + b.v; for (int k = 0; k < K; ++k) r.d[k] = a.d[k] + b.d[k]; return r; }
+template <int K> Dual<K> operator-(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r; r.v = a.v - b.v; for (int k = 0; k < K; ++k) r.d[k] = a.d[k] - b.d[k]; return r; }
+template <int K> Dual<K> operator-(const Dual<K>& a) {
+  Dual<K> r; r.v = -a.v; for (int k = 0; k < K; ++k) r.d[k] = -a.d[k]; return r; }
+template <int K> Dual<K> operator*(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r; r.v = a.v * b.v; for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r; }
+template <int K> Dual<K> operator/(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r; r.v = a.v / b.v; const double ib = 1.0 / b.v;
+  for (int k = 0; k < K; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib; return r; }
+template <int K> Dual<K> operator+(const Dual<K>& a, double b) { Dual<K> r = a; r.v += b; return r; }
+template <int K> Dual<K> operator+(double a, const Dual<K>& b) { return b + a; }
+template <int K> Dual<K> operator-(const Dual<K>& a, double b) { Dual<K> r = a; r.v -= b; return r; }
+template <int K> Dual<K> operator-(double a, const Dual<K>& b) { return (-b) + a; }
+template <int K> Dual<K> operator*(const Dual<K>& a, double b) {
+  Dual<K> r; r.v = a.v * b; for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b; return r; }
+template <int K> Dual<K> operator*(double a, const Dual<K>& b) { return b * a; }
+template <int K> Dual<K> operator/(const Dual<K>& a, double b) { return a * (1.0 / b); }
+template <int K> Dual<K> operator/(double a, const Dual<K>& b) { return Dual<K>(a) / b; }
+template <int K> Dual<K> sqrt(const Dual<K>& a) {
+  Dual<K> r; r.v = std::sqrt(a.v); const double g = 0.5 / r.v;
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * g; return r; }
+template <int K> Dual<K> exp(const Dual<K>& a) {
+  Dual<K> r; r.v = std::exp(a.v); for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * r.v; return r; }
+template <int K> Dual<K> log(const Dual<K>& a) {
+  Dual<K> r; r.v = std::log(a.v); for (int k = 0; k < K; ++k) r.d[k] = a.d[k] / a.v; return r; }
+// x^y for x > 0
+template <int K> Dual<K> pow(const Dual<K>& x, const Dual<K>& y) { return exp(y * log(x)); }
+
+inline double val(double x) { return x; }
+template <int K> double val(const Dual<K>& x) { return x.v; }
+inline double pow(double x, double y) { return std::pow(x, y); }
+using std::sqrt;
+
+template <class S>
+struct Vec3 {
+  S x, y, z;
+  Vec3() : x(0.0), y(0.0), z(0.0) {}
+  Vec3(S a, S b, S c) : x(a), y(b), z(c) {}
+};
+template <class S> Vec3<S> operator+(const Vec3<S>& a, const Vec3<S>& b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class S> Vec3<S> operator-(const Vec3<S>& a, const Vec3<S>& b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class S, class T> Vec3<S> operator*(const Vec3<S>& a, const T& s) { return {a.x * s, a.y * s, a.z * s}; }
+template <class S> S dot(const Vec3<S>& a, const Vec3<S>& b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class S> Vec3<S> cross(const Vec3<S>& a, const Vec3<S>& b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+template <class S> S norm(const Vec3<S>& a) { return sqrt(dot(a, a)); }
+template <class S> Vec3<S> normalize(const Vec3<S>& a) { S n = norm(a); return {a.x / n, a.y / n, a.z / n}; }
+template <class S> Vec3<S> mul3(const S R[9], const Vec3<S>& v) {  // row-major R @ v
+  return {R[0] * v.x + R[1] * v.y + R[2] * v.z, R[3] * v.x + R[4] * v.y + R[5] * v.z,
+          R[6] * v.x + R[7] * v.y + R[8] * v.z}; }
+template <class S> Vec3<S> mul3T(const S R[9], const Vec3<S>& v) {  // R^T @ v
+  return {R[0] * v.x + R[3] * v.y + R[6] * v.z, R[1] * v.x + R[4] * v.y + R[7] * v.z,
+          R[2] * v.x + R[5] * v.y + R[8] * v.z}; }
+
+using V3 = Vec3<double>;
+
+inline V3 load3(const float* p, int i) { return V3(p[3 * i], p[3 * i + 1], p[3 * i + 2]); }
+
+// ---------------------------------------------------------------------------
+// Vertex normals: area-weighted sum of incident face normals, normalised.
+// (The paper only names "the normal at vertex v_i", Sec. 3.2.)
+// ---------------------------------------------------------------------------
+template <class S>
+Vec3<S> face_cross(const Vec3<S>& a, const Vec3<S>& b, const Vec3<S>& c) { return cross(b - a, c - a); }
+
+std::vector<V3> vertex_normals(const OrScene& sc) {
+  std::vector<V3> acc(sc.n_verts);
+  for (int f = 0; f < sc.n_tris; ++f) {
+    const int i0 = sc.tris[3 * f], i1 = sc.tris[3 * f + 1], i2 = sc.tris[3 * f + 2];
+    V3 n = face_cross(load3(sc.verts, i0), load3(sc.verts, i1), load3(sc.verts, i2));
+    acc[i0] = acc[i0] + n; acc[i1] = acc[i1] + n; acc[i2] = acc[i2] + n;
+  }
+  for (auto& n : acc) n = normalize(n);
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Brute-force ray casting with decision flags.
+// ---------------------------------------------------------------------------
+struct TriGeo { V3 a, b, c, centre; double radius; };
+
+std::vector<TriGeo> tri_geometry(const OrScene& sc) {
+  std::vector<TriGeo> g(sc.n_tris);
+  for (int f = 0; f < sc.n_tris; ++f) {
+    TriGeo& t = g[f];
+    t.a = load3(sc.verts, sc.tris[3 * f]);
+    t.b = load3(sc.verts, sc.tris[3 * f + 1]);
+    t.c = load3(sc.verts, sc.tris[3 * f + 2]);
+    t.centre = (t.a + t.b + t.c) * (1.0 / 3.0);
+    t.radius = std::max({norm(t.a - t.centre), norm(t.b - t.centre), norm(t.c - t.centre)});
+  }
+  return g;
+}
+
+// Distance between segments [p1,q1] and [p2,q2]: minimise |p1 + s d1 - p2 - t d2|
+// over s, t in [0,1] (closed form of the 2x2 normal equations, then clamping).
+double segment_distance(const V3& p1, const V3& q1, const V3& p2, const V3& q2) {
+  const V3 d1 = q1 - p1, d2 = q2 - p2, r = p1 - p2;
+  const double a = dot(d1, d1), e = dot(d2, d2), f = dot(d2, r);
+  double s, t;
+  if (a <= 0.0 && e <= 0.0) return norm(r);
+  if (a <= 0.0) {
+    s = 0.0; t = std::clamp(f / e, 0.0, 1.0);
+  } else {
+    const double c = dot(d1, r);
+    if (e <= 0.0) {
+      t = 0.0; s = std::clamp(-c / a, 0.0, 1.0);
+    } else {
+      const double b = dot(d1, d2), den = a * e - b * b;
+      s = den > 0.0 ? std::clamp((b * f - c * e) / den, 0.0, 1.0) : 0.0;
+      t = (b * s + f) / e;
+      if (t < 0.0) { t = 0.0; s = std::clamp(-c / a, 0.0, 1.0); }
+      else if (t > 1.0) { t = 1.0; s = std::clamp((b - c) / a, 0.0, 1.0); }
+    }
+  }
+  return norm((p1 + d1 * s) - (p2 + d2 * t));
+}
+
+// Moller-Trumbore solve of o + t d = a + u (b - a) + v (c - a); det == 0 -> no solution.
+struct Crossing { bool ok; double t, u, v; };
+Crossing cross_plane(const V3& o, const V3& d, const TriGeo& g) {
+  const V3 e1 = g.b - g.a, e2 = g.c - g.a;
+  const V3 p = cross(d, e2);
+  const double det = dot(e1, p);
+  if (det == 0.0) return {false, 0, 0, 0};
+  const double inv = 1.0 / det;
+  const V3 s = o - g.a;
+  const double u = dot(s, p) * inv;
+  const V3 q = cross(s, e1);
+  const double v = dot(d, q) * inv;
+  const double t = dot(e2, q) * inv;
+  return {true, t, u, v};
+}
+
+inline bool inside(const Crossing& c) { return c.ok && c.u >= 0.0 && c.v >= 0.0 && c.u + c.v <= 1.0; }
+
+bool near_boundary(const V3& o, const V3& d, double t0, double t1, const TriGeo& g) {
+  const V3 p = o + d * t0, q = o + d * t1;
+  return segment_distance(p, q, g.a, g.b) < kFlagEps || segment_distance(p, q, g.b, g.c) < kFlagEps ||
+         segment_distance(p, q, g.c, g.a) < kFlagEps;
+}
+
+// Conservative reject: can the segment [t0,t1] come within `slack` of the triangle?
+bool may_touch(const V3& o, const V3& d, double t0, double t1, const TriGeo& g, double slack) {
+  const double tc = std::clamp(dot(g.centre - o, d), t0, t1);
+  const V3 p = o + d * tc;
+  return norm(p - g.centre) <= g.radius + slack;
+}
+
+struct HitResult { int id; double t, u, v; uint8_t flags; };
+
+// Closest hit along o + t d, t > 0; ties in t go to the lowest triangle id.
+HitResult closest_hit(const std::vector<TriGeo>& tg, const V3& o, const V3& d) {
+  struct Cand { int id; Crossing c; };
+  std::vector<Cand> cand;
+  for (int f = 0; f < (int)tg.size(); ++f) {
+    if (!may_touch(o, d, 0.0, kMissFar, tg[f], 1e-5)) continue;
+    cand.push_back({f, cross_plane(o, d, tg[f])});
+  }
+  HitResult h{-1, kMissFar, 0, 0, 0};
+  for (const Cand& c : cand)
+    if (inside(c.c) && c.c.t > 0.0 && (c.c.t < h.t || (c.c.t == h.t && c.id < h.id)))
+      h = {c.id, c.c.t, c.c.u, c.c.v, 0};
+  const double tend = (h.id >= 0 ? h.t : kMissFar) + kFlagEps;
+  for (const Cand& c : cand) {
+    if (near_boundary(o, d, 0.0, tend, tg[c.id])) h.flags |= FLAG_EDGE;
+    if (h.id >= 0 && c.id != h.id && inside(c.c) && c.c.t > 0.0 && std::fabs(c.c.t - h.t) < kFlagEps)
+      h.flags |= FLAG_TIE;
+  }
+  return h;
+}
+
+// Is any triangle other than `exclude` crossed strictly inside (tmin, tmax)?
+bool occluded(const std::vector<TriGeo>& tg, const V3& o, const V3& d, double tmin, double tmax,
+              int exclude, uint8_t* flags) {
+  bool occ = false;
+  for (int f = 0; f < (int)tg.size(); ++f) {
+    if (f == exclude) continue;
+    if (!may_touch(o, d, tmin, tmax, tg[f], 1e-5)) continue;
+    const Crossing c = cross_plane(o, d, tg[f]);
+    if (inside(c) && c.t > tmin && c.t < tmax) occ = true;
+    if (near_boundary(o, d, tmin, tmax, tg[f])) *flags |= FLAG_EDGE;
+    if (inside(c) && (std::fabs(c.t - tmin) < kFlagEps || std::fabs(c.t - tmax) < kFlagEps))
+      *flags |= FLAG_TRANGE;
+  }
+  return occ;
+}
+
+// ---------------------------------------------------------------------------
+// Camera and light sampling.
+// ---------------------------------------------------------------------------
+struct CamConst { double tan_half, aspect; int W, H; };
+
+CamConst cam_const(const OrScene& sc) {
+  return {std::tan(0.5 * (double)sc.fov_y), (double)sc.width / (double)sc.height, sc.width, sc.height};
+}
+
+// Film point (fx, fy) in pixel units -> camera-space direction (unnormalised).
+V3 film_dir(const CamConst& cc, double fx, double fy) {
+  return V3((2.0 * fx / cc.W - 1.0) * cc.tan_half * cc.aspect, (1.0 - 2.0 * fy / cc.H) * cc.tan_half, -1.0);
+}
+
+// Point on light j from two uniforms: parallelogram p0 + u0 e1 + u1 e2;
+// triangle p0 + sqrt(u0)(1-u1) e1 + sqrt(u0) u1 e2 (uniform area density).
+inline void light_weights(int shape, double u0, double u1, double* w1, double* w2) {
+  if (shape == 1) { const double su = std::sqrt(u0); *w1 = su * (1.0 - u1); *w2 = su * u1; }
+  else { *w1 = u0; *w2 = u1; }
+}
+
+// ---------------------------------------------------------------------------
+// Shading: everything downstream of the decisions, templated so that the
+// same code gives values (S = double) and derivatives (S = Dual<K>).
+// ---------------------------------------------------------------------------
+template <class S>
+struct SampleParams {     // what one camera sample depends on
+  Vec3<S> v[3], n[3], c[3], s[3];
+  S r[3];
+  S R[9];
+  Vec3<S> T;
+};
+
+template <class S>
+struct LightParams { Vec3<S> p0, e1, e2, rad; int shape; };
+
+template <class S>
+struct Frame { Vec3<S> x, ns, wo, c, s; S r; };
+
+// Shading frame of a camera sample through film point (fx, fy) that hits the
+// (fixed) triangle of `p`: barycentrics recomputed as smooth functions of the
+// triangle, the ray origin and direction.
+template <class S>
+Frame<S> shading_frame(const SampleParams<S>& p, const CamConst& cc, double fx, double fy) {
+  const V3 dc = film_dir(cc, fx, fy);
+  const Vec3<S> dcs(S(dc.x), S(dc.y), S(dc.z));
+  const Vec3<S> d = normalize(mul3(p.R, dcs));
+  const Vec3<S>& o = p.T;
+  const Vec3<S> e1 = p.v[1] - p.v[0], e2 = p.v[2] - p.v[0];
+  const Vec3<S> pv = cross(d, e2);
+  const S det = dot(e1, pv);
+  const Vec3<S> sv = o - p.v[0];
+  const S b1 = dot(sv, pv) / det;
+  const Vec3<S> qv = cross(sv, e1);
+  const S b2 = dot(d, qv) / det;
+  const S b0 = S(1.0) - b1 - b2;
+  Frame<S> f;
+  f.x = p.v[0] * b0 + p.v[1] * b1 + p.v[2] * b2;
+  f.ns = normalize(p.n[0] * b0 + p.n[1] * b1 + p.n[2] * b2);
+  f.wo = Vec3<S>(-d.x, -d.y, -d.z);
+  f.c = p.c[0] * b0 + p.c[1] * b1 + p.c[2] * b2;
+  f.s = p.s[0] * b0 + p.s[1] * b1 + p.s[2] * b2;
+  S r = p.r[0] * b0 + p.r[1] * b1 + p.r[2] * b2;
+  if (val(r) < kRoughMin) r = S(kRoughMin);      // clamp: the gradient passes only inside
+  if (val(r) > kRoughMax) r = S(kRoughMax);
+  f.r = r;
+  return f;
+}
+
+// Walter et al.'s rational approximation of the Smith G1 for a Beckmann-like
+// lobe, with a = 1 / (r tan(acos(n.v))) = n.v / (r sqrt(1 - (n.v)^2)).
+template <class S>
+S smith_g1(const S& nv, const S& hv, const S& r, uint8_t* flags) {
+  if (!(val(hv) / val(nv) > 0.0)) return S(0.0);
+  const double s2 = 1.0 - val(nv) * val(nv);
+  if (s2 <= 0.0) return S(1.0);
+  const S a = nv / (r * sqrt(S(1.0) - nv * nv));
+  if (flags && std::fabs(val(a) - 1.6) < kFlagEps * 1.6) *flags |= FLAG_G1;
+  if (val(a) < 1.6) return (3.535 * a + 2.181 * a * a) / (1.0 + 2.276 * a + 2.577 * a * a);
+  return S(1.0);
+}
+
+// Cook-Torrance f_r = c/pi + D G F / (4 (o.n)(l.n)) (Appendix A).
+//   variant 0 (as printed): D = (2/r + 2)/(2 pi) (n.h)^(2/r - 2), F = s + (1-s)(1 - o.h)
+//   variant 1: D = 1/(pi r) (n.h)^(2/r - 2) (unit projected integral),
+//              F = s + (1-s)(1 - o.h)^5 (Schlick)
+// The half vector is normalize(l + o): the printed denominator |l . o| is read
+// as the norm of l + o, which the text's "normalized halfway vector" requires.
+template <class S>
+Vec3<S> brdf(const Frame<S>& f, const Vec3<S>& l, const S& cos_o, const S& cos_l, int variant,
+             int components, uint8_t* flags) {
+  Vec3<S> out(S(0.0), S(0.0), S(0.0));
+  if (components & 1) out = f.c * (1.0 / kPi);
+  if (components & 2) {
+    const Vec3<S> h = normalize(l + f.wo);
+    const S nh = dot(f.ns, h);
+    const S ex = 2.0 / f.r - 2.0;
+    const S nd = variant == 1 ? 1.0 / (kPi * f.r) : (2.0 / f.r + 2.0) / (2.0 * kPi);
+    const S D = nd * pow(nh, ex);
+    const S oh = dot(f.wo, h), lh = dot(l, h);
+    const S G = smith_g1(cos_o, oh, f.r, flags) * smith_g1(cos_l, lh, f.r, flags);
+    const S om = 1.0 - oh;
+    S fw = om;
+    if (variant == 1) fw = om * om * om * om * om;
+    const S spec = D * G / (4.0 * cos_o * cos_l);
+    const Vec3<S> F(f.s.x + (1.0 - f.s.x) * fw, f.s.y + (1.0 - f.s.y) * fw, f.s.z + (1.0 - f.s.z) * fw);
+    out = out + F * spec;
+  }
+  return out;
+}
+
+// Contribution of light j to one camera sample (radiance, before the 1/S
+// weight): V L_j * f_r * (n_s . l) * (-n_j . l) A_j / |q - x|^2.
+// With A_j (-n_j . l) = -kappa (e1 x e2) . l, kappa = 1 (parallelogram) or
+// 1/2 (triangle).  `vis` is the frozen decision; culled pairs give zero.
+template <class S>
+Vec3<S> light_contribution(const Frame<S>& f, const LightParams<S>& L, double w1, double w2, uint8_t vis,
+                           int variant, int components, uint8_t* flags) {
+  if (vis != VIS_VISIBLE) return Vec3<S>(S(0.0), S(0.0), S(0.0));
+  const Vec3<S> q = L.p0 + L.e1 * S(w1) + L.e2 * S(w2);
+  const Vec3<S> dq = q - f.x;
+  const S dist2 = dot(dq, dq);
+  const Vec3<S> l = dq * (1.0 / sqrt(dist2));
+  const S cos_s = dot(f.ns, l);
+  const S cos_o = dot(f.ns, f.wo);
+  const double kappa = L.shape == 1 ? 0.5 : 1.0;
+  const S cosA = -(kappa * dot(cross(L.e1, L.e2), l));
+  const Vec3<S> fr = brdf(f, l, cos_o, cos_s, variant, components, flags);
+  const S g = cos_s * cosA / dist2;
+  return Vec3<S>(L.rad.x * fr.x * g, L.rad.y * fr.y * g, L.rad.z * fr.z * g);
+}
+
+// ---------------------------------------------------------------------------
+// Scene access helpers.
+// ---------------------------------------------------------------------------
+struct Prepared {
+  const OrScene* sc;
+  CamConst cc;
+  std::vector<V3> normals;
+  std::vector<TriGeo> tg;
+  double R[9];
+  V3 T;
+};
+
+Prepared prepare(const OrScene* sc) {
+  Prepared p;
+  p.sc = sc;
+  p.cc = cam_const(*sc);
+  p.normals = vertex_normals(*sc);
+  p.tg = tri_geometry(*sc);
+  for (int i = 0; i < 9; ++i) p.R[i] = sc->cam_R[i];
+  p.T = V3(sc->cam_T[0], sc->cam_T[1], sc->cam_T[2]);
+  return p;
+}
+
+SampleParams<double> sample_params_d(const Prepared& P, int tri) {
+  const OrScene& sc = *P.sc;
+  SampleParams<double> sp;
+  for (int k = 0; k < 3; ++k) {
+    const int vi = sc.tris[3 * tri + k];
+    sp.v[k] = load3(sc.verts, vi);
+    sp.n[k] = P.normals[vi];
+    sp.c[k] = load3(sc.diffuse, vi);
+    sp.s[k] = load3(sc.specular, vi);
+    sp.r[k] = sc.roughness[vi];
+  }
+  for (int i = 0; i < 9; ++i) sp.R[i] = P.R[i];
+  sp.T = P.T;
+  return sp;
+}
+
+LightParams<double> light_params_d(const OrScene& sc, int j) {
+  return {load3(sc.light_p0, j), load3(sc.light_e1, j), load3(sc.light_e2, j), load3(sc.light_rad, j),
+          sc.light_shape[j]};
+}
+
+// Decision pass of one light for a shading frame (FP64): cull tests, then the
+// shadow ray from x towards q over t in (1e-4, |q - x|), excluding the hit
+// triangle.
+uint8_t light_decision(const Prepared& P, const Frame<double>& f, int j, double w1, double w2, int hit,
+                       uint8_t* flags) {
+  const OrScene& sc = *P.sc;
+  const LightParams<double> L = light_params_d(sc, j);
+  const V3 q = L.p0 + L.e1 * w1 + L.e2 * w2;
+  const V3 dq = q - f.x;
+  const double dist = norm(dq);
+  const V3 l = dq * (1.0 / dist);
+  const double cs = dot(f.ns, l);
+  const double cl = -dot(normalize(cross(L.e1, L.e2)), l);
+  if (std::fabs(cs) < kFlagEps || std::fabs(cl) < kFlagEps) *flags |= FLAG_COSL;
+  if (cs <= 0.0 || cl <= 0.0) return VIS_CULLED;
+  const bool occ = occluded(P.tg, f.x, l, kShadowTmin, dist, hit, flags);
+  return occ ? VIS_OCCLUDED : VIS_VISIBLE;
+}
+
+template <class Fn>
+void parallel_for(int n, int nthreads, Fn fn) {
+  if (nthreads <= 1 || n < 2) { for (int i = 0; i < n; ++i) fn(i, 0); return; }
+  nthreads = std::min(nthreads, n);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nthreads; ++t)
+    th.emplace_back([&, t]() { for (int i = t; i < n; i += nthreads) fn(i, t); });
+  for (auto& x : th) x.join();
+}
+
+// ---------------------------------------------------------------------------
+// Gradient slots of one (sample, light) evaluation.
+// ---------------------------------------------------------------------------
+constexpr int SLOT_V = 0, SLOT_N = 9, SLOT_C = 18, SLOT_S = 27, SLOT_R = 36;
+constexpr int SLOT_LP0 = 39, SLOT_LE1 = 42, SLOT_LE2 = 45, SLOT_LRAD = 48;
+constexpr int SLOT_CR = 51, SLOT_CT = 60, NSLOT = 63;
+using D63 = Dual<NSLOT>;
+
+Vec3<D63> seed3(const V3& v, int slot) {
+  return Vec3<D63>(D63::seed(v.x, slot), D63::seed(v.y, slot + 1), D63::seed(v.z, slot + 2));
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+// Philox outputs for n counters (c0,c1,c2,c3) = ctr[4*i..4*i+3].
+void oracle_philox(uint64_t key, int64_t n, const uint32_t* ctr, uint32_t* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    Rand4 r = philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], key);
+    for (int k = 0; k < 4; ++k) out[4 * i + k] = r.x[k];
+  }
+}
+
+void oracle_vertex_normals(const OrScene* sc, double* out) {
+  std::vector<V3> n = vertex_normals(*sc);
+  for (int i = 0; i < sc->n_verts; ++i) { out[3 * i] = n[i].x; out[3 * i + 1] = n[i].y; out[3 * i + 2] = n[i].z; }
+}
+
+// Vector-Jacobian product of the vertex normals: g_v += (dn/dv)^T g_n, by
+// forward-mode duals over each vertex's one-ring.
+void oracle_normals_vjp(const OrScene* sc, const double* g_n, double* g_v) {
+  using D3 = Dual<3>;
+  const int N = sc->n_verts, F = sc->n_tris;
+  std::vector<std::vector<int>> faces(N);
+  for (int f = 0; f < F; ++f) for (int k = 0; k < 3; ++k) faces[sc->tris[3 * f + k]].push_back(f);
+  for (int i = 0; i < N; ++i) {
+    std::vector<int> ring;
+    for (int f : faces[i]) for (int k = 0; k < 3; ++k) ring.push_back(sc->tris[3 * f + k]);
+    std::sort(ring.begin(), ring.end());
+    ring.erase(std::unique(ring.begin(), ring.end()), ring.end());
+    const V3 gni(g_n[3 * i], g_n[3 * i + 1], g_n[3 * i + 2]);
+    for (int m : ring) {
+      auto pos = [&](int vi) {
+        const V3 p = load3(sc->verts, vi);
+        if (vi == m) return Vec3<D3>(D3::seed(p.x, 0), D3::seed(p.y, 1), D3::seed(p.z, 2));
+        return Vec3<D3>(D3(p.x), D3(p.y), D3(p.z));
+      };
+      Vec3<D3> acc(D3(0.0), D3(0.0), D3(0.0));
+      for (int f : faces[i])
+        acc = acc + face_cross(pos(sc->tris[3 * f]), pos(sc->tris[3 * f + 1]), pos(sc->tris[3 * f + 2]));
+      const Vec3<D3> n = normalize(acc);
+      for (int k = 0; k < 3; ++k) g_v[3 * m + k] += gni.x * n.x.d[k] + gni.y * n.y.d[k] + gni.z * n.z.d[k];
+    }
+  }
+}
+
+// Forward render of a pixel subset (all pixels when pix == nullptr).
+//   force_hit [n_pix*S]   : -2 = decide here, else the hit id (-1 = miss) to use
+//   force_vis [n_pix*S*L] : 0xFF = decide here, else a VIS_* code to use
+// Outputs (nullable): rgb [n_pix*3], hit [n_pix*S], pflag [n_pix*S],
+// vis [n_pix*S*L], sflag [n_pix*S*L].
+int oracle_render(const OrScene* sc, int32_t n_pix, const int32_t* pix, const int32_t* force_hit,
+                  const uint8_t* force_vis, double* out_rgb, int32_t* out_hit, uint8_t* out_pflag,
+                  uint8_t* out_vis, uint8_t* out_sflag, int32_t nthreads) {
+  const Prepared P = prepare(sc);
+  const int S = sc->spp, L = sc->n_lights, W = sc->width;
+  if (!pix) n_pix = sc->width * sc->height;
+  parallel_for(n_pix, nthreads, [&](int ip, int) {
+    const int pid = pix ? pix[ip] : ip;
+    const int px = pid % W, py = pid / W;
+    double acc[3] = {0, 0, 0};
+    for (int s = 0; s < S; ++s) {
+      const size_t rs = (size_t)ip * S + s;
+      const Rand4 rj = philox4x32_10((uint32_t)pid, (uint32_t)s, PURPOSE_JITTER, sc->step, sc->seed);
+      const double fx = px + unit24(rj.x[0]), fy = py + unit24(rj.x[1]);
+      const V3 d = normalize(mul3(P.R, film_dir(P.cc, fx, fy)));
+      HitResult h = closest_hit(P.tg, P.T, d);
+      if (force_hit && force_hit[rs] != -2) h.id = force_hit[rs];
+      uint8_t pflag = h.flags;
+      if (out_hit) out_hit[rs] = h.id;
+      uint8_t* vis_row = out_vis ? out_vis + rs * L : nullptr;
+      uint8_t* sf_row = out_sflag ? out_sflag + rs * L : nullptr;
+      if (h.id < 0) {
+        if (out_pflag) out_pflag[rs] = pflag;
+        for (int j = 0; j < L; ++j) { if (vis_row) vis_row[j] = VIS_NONE; if (sf_row) sf_row[j] = 0; }
+        continue;
+      }
+      const SampleParams<double> sp = sample_params_d(P, h.id);
+      const Frame<double> fr = shading_frame(sp, P.cc, fx, fy);
+      const double cos_o = dot(fr.ns, fr.wo);
+      if (std::fabs(cos_o) < kFlagEps) pflag |= FLAG_COSO;
+      if (out_pflag) out_pflag[rs] = pflag;
+      for (int j = 0; j < L; ++j) {
+        const Rand4 rl = philox4x32_10((uint32_t)pid, (uint32_t)s, 1u + (uint32_t)j, sc->step, sc->seed);
+        double w1, w2;
+        light_weights(sc->light_shape[j], unit24(rl.x[0]), unit24(rl.x[1]), &w1, &w2);
+        uint8_t sflag = 0;
+        uint8_t vis = VIS_NONE;
+        if (cos_o > 0.0) vis = light_decision(P, fr, j, w1, w2, h.id, &sflag);
+        if (force_vis && force_vis[rs * L + j] != 0xFF) vis = force_vis[rs * L + j];
+        const Vec3<double> c = light_contribution(fr, light_params_d(*sc, j), w1, w2, vis, sc->brdf_variant,
+                                                  sc->components, &sflag);
+        acc[0] += c.x; acc[1] += c.y; acc[2] += c.z;
+        if (vis_row) vis_row[j] = vis;
+        if (sf_row) sf_row[j] = sflag;
+      }
+    }
+    if (out_rgb) for (int k = 0; k < 3; ++k) out_rgb[3 * ip + k] = acc[k] / S;
+  });
+  return 0;
+}
+
+// Interior gradient of sum_p dEdp[p] . rgb[p] over a pixel subset, with the
+// decisions (hit [n_pix*S], vis [n_pix*S*L], as produced by oracle_render and
+// possibly replaced) held fixed.  All outputs are accumulated (+=):
+//   g_verts [N*3] (direct path only), g_normals [N*3], g_diffuse [N*3],
+//   g_specular [N*3], g_rough [N], g_light [L*9] (p0, e1, e2), g_rad [L*3],
+//   g_cam [12] (R row-major, then T).
+int oracle_grad(const OrScene* sc, int32_t n_pix, const int32_t* pix, const int32_t* hit, const uint8_t* vis,
+                const double* dEdp, double* g_verts, double* g_normals, double* g_diffuse, double* g_specular,
+                double* g_rough, double* g_light, double* g_rad, double* g_cam, int32_t nthreads) {
+  const Prepared P = prepare(sc);
+  const int S = sc->spp, L = sc->n_lights, W = sc->width, N = sc->n_verts;
+  if (!pix) n_pix = sc->width * sc->height;
+  nthreads = std::max(1, std::min<int>(nthreads, n_pix));
+  struct Acc { std::vector<double> v, n, c, s, r, l, rad, cam; };
+  std::vector<Acc> accs(nthreads);
+  for (auto& a : accs) {
+    a.v.assign(3 * N, 0); a.n.assign(3 * N, 0); a.c.assign(3 * N, 0); a.s.assign(3 * N, 0);
+    a.r.assign(N, 0); a.l.assign(9 * L, 0); a.rad.assign(3 * L, 0); a.cam.assign(12, 0);
+  }
+  parallel_for(n_pix, nthreads, [&](int ip, int tid) {
+    Acc& A = accs[tid];
+    const int pid = pix ? pix[ip] : ip;
+    const int px = pid % W, py = pid / W;
+    const double g[3] = {dEdp[3 * ip] / S, dEdp[3 * ip + 1] / S, dEdp[3 * ip + 2] / S};
+    if (g[0] == 0.0 && g[1] == 0.0 && g[2] == 0.0) return;
+    for (int s = 0; s < S; ++s) {
+      const size_t rs = (size_t)ip * S + s;
+      const int tri = hit[rs];
+      if (tri < 0) continue;
+      const Rand4 rj = philox4x32_10((uint32_t)pid, (uint32_t)s, PURPOSE_JITTER, sc->step, sc->seed);
+      const double fx = px + unit24(rj.x[0]), fy = py + unit24(rj.x[1]);
+      const SampleParams<double> spd = sample_params_d(P, tri);
+      SampleParams<D63> sp;
+      for (int k = 0; k < 3; ++k) {
+        sp.v[k] = seed3(spd.v[k], SLOT_V + 3 * k);
+        sp.n[k] = seed3(spd.n[k], SLOT_N + 3 * k);
+        sp.c[k] = seed3(spd.c[k], SLOT_C + 3 * k);
+        sp.s[k] = seed3(spd.s[k], SLOT_S + 3 * k);
+        sp.r[k] = D63::seed(spd.r[k], SLOT_R + k);
+      }
+      for (int i = 0; i < 9; ++i) sp.R[i] = D63::seed(P.R[i], SLOT_CR + i);
+      sp.T = seed3(P.T, SLOT_CT);
+      const Frame<D63> fr = shading_frame(sp, P.cc, fx, fy);
+      int vid[3];
+      for (int k = 0; k < 3; ++k) vid[k] = sc->tris[3 * tri + k];
+      for (int j = 0; j < L; ++j) {
+        const uint8_t vs = vis[rs * L + j];
+        if (vs != VIS_VISIBLE) continue;
+        const Rand4 rl = philox4x32_10((uint32_t)pid, (uint32_t)s, 1u + (uint32_t)j, sc->step, sc->seed);
+        double w1, w2;
+        light_weights(sc->light_shape[j], unit24(rl.x[0]), unit24(rl.x[1]), &w1, &w2);
+        const LightParams<double> ld = light_params_d(*sc, j);
+        LightParams<D63> lp{seed3(ld.p0, SLOT_LP0), seed3(ld.e1, SLOT_LE1), seed3(ld.e2, SLOT_LE2),
+                            seed3(ld.rad, SLOT_LRAD), ld.shape};
+        const Vec3<D63> c = light_contribution(fr, lp, w1, w2, vs, sc->brdf_variant, sc->components, nullptr);
+        double gs[NSLOT];
+        for (int k = 0; k < NSLOT; ++k) gs[k] = g[0] * c.x.d[k] + g[1] * c.y.d[k] + g[2] * c.z.d[k];
+        for (int k = 0; k < 3; ++k)
+          for (int a = 0; a < 3; ++a) {
+            A.v[3 * vid[k] + a] += gs[SLOT_V + 3 * k + a];
+            A.n[3 * vid[k] + a] += gs[SLOT_N + 3 * k + a];
+            A.c[3 * vid[k] + a] += gs[SLOT_C + 3 * k + a];
+            A.s[3 * vid[k] + a] += gs[SLOT_S + 3 * k + a];
+          }
+        for (int k = 0; k < 3; ++k) A.r[vid[k]] += gs[SLOT_R + k];
+        for (int a = 0; a < 9; ++a) A.l[9 * j + a] += gs[SLOT_LP0 + a];
+        for (int a = 0; a < 3; ++a) A.rad[3 * j + a] += gs[SLOT_LRAD + a];
+        for (int a = 0; a < 12; ++a) A.cam[a] += gs[SLOT_CR + a];
+      }
+    }
+  });
+  auto add = [](double* dst, const std::vector<double>& src) { if (dst) for (size_t i = 0; i < src.size(); ++i) dst[i] += src[i]; };
+  for (const Acc& a : accs) {
+    add(g_verts, a.v); add(g_normals, a.n); add(g_diffuse, a.c); add(g_specular, a.s);
+    add(g_rough, a.r); add(g_light, a.l); add(g_rad, a.rad); add(g_cam, a.cam);
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Primary-visibility boundary term (edge sampling, Sec. 4).
+//
+// Silhouette edges: interior edges whose two faces differ in facing w.r.t. the
+// camera centre, plus every edge with one face.  Facing of a face is the sign
+// of ((v1 - v0) x (v2 - v0)) . (T - v0), evaluated in FP64 in that order.
+// Each silhouette edge gets probability proportional to its length on the
+// film (pixel units); a sample picks the edge by the running sum, a point
+// y = a + u (b - a) on it, and shades two rays through y -/+ eps m, with m the
+// unit film normal perp(b - a) and eps = 1e-3 pixel.  The estimate
+//     sum_k  (ltot / n_samples) (f_minus - f_plus) . dEdp[pixel(y)] (m . dy/dtheta)
+// is added to the two edge vertices and the camera.  dy/dtheta is the film
+// velocity of the 3D edge point that projects to y (perspective-correct
+// parameter held fixed).
+//   edge_out [n_sel*4] per selected sample: edge id, pixel id (-1 outside),
+//   hit id of the minus ray, hit id of the plus ray;  flag_out [n_sel].
+//   sel: sample ids to evaluate (nullptr = all).  dEdp is the full [H*W*3].
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+struct EdgeList { std::vector<int> a, b, f0, f1; };
+
+EdgeList build_edges(const OrScene& sc) {
+  std::map<std::pair<int, int>, std::vector<int>> m;
+  for (int f = 0; f < sc.n_tris; ++f)
+    for (int k = 0; k < 3; ++k) {
+      int i = sc.tris[3 * f + k], j = sc.tris[3 * f + (k + 1) % 3];
+      if (i > j) std::swap(i, j);
+      m[{i, j}].push_back(f);
+    }
+  EdgeList e;
+  for (auto& kv : m) {
+    e.a.push_back(kv.first.first); e.b.push_back(kv.first.second);
+    e.f0.push_back(kv.second[0]); e.f1.push_back(kv.second.size() > 1 ? kv.second[1] : -1);
+  }
+  return e;
+}
+
+template <class S>
+struct FilmPt { S x, y, depth; };
+
+// Pixel coordinates of world point X: camera frame R^T (X - T), pinhole.
+template <class S>
+FilmPt<S> project(const Vec3<S>& X, const S R[9], const Vec3<S>& T, const CamConst& cc) {
+  const Vec3<S> pc = mul3T(R, X - T);
+  const S z = -pc.z;
+  FilmPt<S> f;
+  f.x = (pc.x / z / (cc.tan_half * cc.aspect) + 1.0) * (0.5 * cc.W);
+  f.y = (1.0 - pc.y / z / cc.tan_half) * (0.5 * cc.H);
+  f.depth = z;
+  return f;
+}
+
+}  // namespace
+
+extern "C" {
+
+int oracle_edge_grad(const OrScene* sc, int32_t n_samples, int32_t n_sel, const int32_t* sel,
+                     const double* dEdp, double* g_verts, double* g_cam, int32_t* edge_out, uint8_t* flag_out,
+                     double* ltot_out, int32_t nthreads) {
+  const Prepared P = prepare(sc);
+  const OrScene& s = *sc;
+  const EdgeList E = build_edges(s);
+  const int nE = (int)E.a.size(), W = s.width, H = s.height, L = s.n_lights;
+  // Facing of each face.
+  std::vector<uint8_t> front(s.n_tris);
+  for (int f = 0; f < s.n_tris; ++f) {
+    const V3 v0 = load3(s.verts, s.tris[3 * f]), v1 = load3(s.verts, s.tris[3 * f + 1]),
+             v2 = load3(s.verts, s.tris[3 * f + 2]);
+    const V3 n = cross(v1 - v0, v2 - v0);
+    const V3 w = P.T - v0;
+    front[f] = (n.x * w.x + n.y * w.y + n.z * w.z) > 0.0;
+  }
+  // Film length of each silhouette edge and the running sum.
+  std::vector<double> len(nE, 0.0), cdf(nE + 1, 0.0);
+  for (int e = 0; e < nE; ++e) {
+    const bool sil = E.f1[e] < 0 || front[E.f0[e]] != front[E.f1[e]];
+    if (!sil) continue;
+    const FilmPt<double> pa = project(load3(s.verts, E.a[e]), P.R, P.T, P.cc);
+    const FilmPt<double> pb = project(load3(s.verts, E.b[e]), P.R, P.T, P.cc);
+    if (pa.depth <= 0.0 || pb.depth <= 0.0) continue;
+    len[e] = std::hypot(pb.x - pa.x, pb.y - pa.y);
+  }
+  for (int e = 0; e < nE; ++e) cdf[e + 1] = cdf[e] + len[e];
+  const double ltot = cdf[nE];
+  if (ltot_out) *ltot_out = ltot;
+  if (ltot <= 0.0 || n_samples <= 0) return 0;
+  if (!sel) n_sel = n_samples;
+  nthreads = std::max(1, std::min<int>(nthreads, n_sel));
+  std::vector<std::vector<double>> gv(nthreads, std::vector<double>(3 * s.n_verts, 0.0));
+  std::vector<std::vector<double>> gc(nthreads, std::vector<double>(12, 0.0));
+  parallel_for(n_sel, nthreads, [&](int is, int tid) {
+    const int k = sel ? sel[is] : is;
+    const Rand4 re = philox4x32_10((uint32_t)k, 0u, PURPOSE_EDGE, s.step, s.seed);
+    const double target = unit24(re.x[0]) * ltot;
+    const double u = unit24(re.x[1]);
+    // first e with cdf[e+1] > target
+    const int e = (int)(std::upper_bound(cdf.begin() + 1, cdf.end(), target) - (cdf.begin() + 1));
+    uint8_t flag = 0;
+    if (std::fabs(target - cdf[e]) < 1e-9 * ltot || std::fabs(target - cdf[e + 1]) < 1e-9 * ltot) flag |= FLAG_TIE;
+    const V3 A = load3(s.verts, E.a[e]), B = load3(s.verts, E.b[e]);
+    const FilmPt<double> pa = project(A, P.R, P.T, P.cc), pb = project(B, P.R, P.T, P.cc);
+    const double yx = pa.x + u * (pb.x - pa.x), yy = pa.y + u * (pb.y - pa.y);
+    const double lx = pb.x - pa.x, ly = pb.y - pa.y, ll = std::hypot(lx, ly);
+    const double mx = -ly / ll, my = lx / ll;
+    const int pxi = (int)std::floor(yx), pyi = (int)std::floor(yy);
+    const bool in_img = pxi >= 0 && pxi < W && pyi >= 0 && pyi < H;
+    const int pid = in_img ? pyi * W + pxi : -1;
+    int hits[2] = {-1, -1};
+    double fpm[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    if (in_img) {
+      for (int side = 0; side < 2; ++side) {
+        const double sg = side == 0 ? -1.0 : 1.0;
+        const double fx = yx + sg * 1e-3 * mx, fy = yy + sg * 1e-3 * my;
+        const V3 d = normalize(mul3(P.R, film_dir(P.cc, fx, fy)));
+        const HitResult h = closest_hit(P.tg, P.T, d);
+        flag |= h.flags;
+        hits[side] = h.id;
+        if (h.id < 0) continue;
+        const Frame<double> fr = shading_frame(sample_params_d(P, h.id), P.cc, fx, fy);
+        const double cos_o = dot(fr.ns, fr.wo);
+        if (std::fabs(cos_o) < kFlagEps) flag |= FLAG_COSO;
+        if (cos_o <= 0.0) continue;
+        for (int j = 0; j < L; ++j) {
+          const Rand4 rl = philox4x32_10((uint32_t)k, 0u, PURPOSE_EDGE + 1u + (uint32_t)j, s.step, s.seed);
+          double w1, w2;
+          light_weights(s.light_shape[j], unit24(rl.x[0]), unit24(rl.x[1]), &w1, &w2);
+          const uint8_t vis = light_decision(P, fr, j, w1, w2, h.id, &flag);
+          const Vec3<double> c = light_contribution(fr, light_params_d(s, j), w1, w2, vis, s.brdf_variant,
+                                                    s.components, &flag);
+          fpm[side][0] += c.x; fpm[side][1] += c.y; fpm[side][2] += c.z;
+        }
+      }
+    }
+    if (edge_out) { edge_out[4 * is] = e; edge_out[4 * is + 1] = pid; edge_out[4 * is + 2] = hits[0]; edge_out[4 * is + 3] = hits[1]; }
+    if (flag_out) flag_out[is] = flag;
+    if (!in_img) return;
+    const double dlt = (fpm[0][0] - fpm[1][0]) * dEdp[3 * pid] + (fpm[0][1] - fpm[1][1]) * dEdp[3 * pid + 1] +
+                       (fpm[0][2] - fpm[1][2]) * dEdp[3 * pid + 2];
+    const double wgt = ltot / n_samples * dlt;
+    if (wgt == 0.0) return;
+    // Film velocity of the edge point: X(w) = (1-w) A + w B, w perspective-correct.
+    const double w = (u / pb.depth) / ((1.0 - u) / pa.depth + u / pb.depth);
+    using D18 = Dual<18>;
+    Vec3<D18> Ad(D18::seed(A.x, 0), D18::seed(A.y, 1), D18::seed(A.z, 2));
+    Vec3<D18> Bd(D18::seed(B.x, 3), D18::seed(B.y, 4), D18::seed(B.z, 5));
+    D18 Rd[9];
+    for (int i = 0; i < 9; ++i) Rd[i] = D18::seed(P.R[i], 6 + i);
+    Vec3<D18> Td(D18::seed(P.T.x, 15), D18::seed(P.T.y, 16), D18::seed(P.T.z, 17));
+    const Vec3<D18> X = Ad * D18(1.0 - w) + Bd * D18(w);
+    const FilmPt<D18> y = project(X, Rd, Td, P.cc);
+    double vn[18];
+    for (int i = 0; i < 18; ++i) vn[i] = mx * y.x.d[i] + my * y.y.d[i];
+    std::vector<double>& G = gv[tid];
+    for (int a = 0; a < 3; ++a) { G[3 * E.a[e] + a] += wgt * vn[a]; G[3 * E.b[e] + a] += wgt * vn[3 + a]; }
+    for (int i = 0; i < 12; ++i) gc[tid][i] += wgt * vn[6 + i];
+  });
+  for (int t = 0; t < nthreads; ++t) {
+    if (g_verts) for (int i = 0; i < 3 * s.n_verts; ++i) g_verts[i] += gv[t][i];
+    if (g_cam) for (int i = 0; i < 12; ++i) g_cam[i] += gc[t][i];
+  }
+  return 0;
+}
+
+// Number of unique edges (for sizing).
+int32_t oracle_edge_count(const OrScene* sc) { return (int32_t)build_edges(*sc).a.size(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Probes of single stages, used by the oracle's own pins.
+// ---------------------------------------------------------------------------
+extern "C" {
+
+// World-space unit direction of the camera ray through film point (fx, fy).
+void oracle_camera_ray(const OrScene* sc, double fx, double fy, double* out_d) {
+  const Prepared P = prepare(sc);
+  const V3 d = normalize(mul3(P.R, film_dir(P.cc, fx, fy)));
+  out_d[0] = d.x; out_d[1] = d.y; out_d[2] = d.z;
+}
+
+// Closest hit of ray o + t d (d unit): out_i = {id, flags}, out_d = {t, u, v}.
+void oracle_closest_hit(const OrScene* sc, const double* o, const double* d, int32_t* out_i, double* out_d) {
+  const std::vector<TriGeo> tg = tri_geometry(*sc);
+  const HitResult h = closest_hit(tg, V3(o[0], o[1], o[2]), V3(d[0], d[1], d[2]));
+  out_i[0] = h.id; out_i[1] = h.flags;
+  out_d[0] = h.t; out_d[1] = h.u; out_d[2] = h.v;
+}
+
+// All plane crossings of the full line o + t d, t in (-inf, inf), that fall
+// inside a triangle: returns the count; ts[] receives their t (up to cap).
+int32_t oracle_line_crossings(const OrScene* sc, const double* o, const double* d, double* ts, int32_t cap) {
+  const std::vector<TriGeo> tg = tri_geometry(*sc);
+  const V3 O(o[0], o[1], o[2]), D(d[0], d[1], d[2]);
+  int32_t n = 0;
+  for (const TriGeo& g : tg) {
+    const Crossing c = cross_plane(O, D, g);
+    if (inside(c)) { if (n < cap) ts[n] = c.t; ++n; }
+  }
+  return n;
+}
+
+// Occlusion of segment o + t d, t in (tmin, tmax), excluding triangle `exclude`.
+int32_t oracle_occluded(const OrScene* sc, const double* o, const double* d, double tmin, double tmax,
+                        int32_t exclude, uint8_t* flags) {
+  const std::vector<TriGeo> tg = tri_geometry(*sc);
+  uint8_t f = 0;
+  const bool occ = occluded(tg, V3(o[0], o[1], o[2]), V3(d[0], d[1], d[2]), tmin, tmax, exclude, &f);
+  if (flags) *flags = f;
+  return occ ? 1 : 0;
+}
+
+// Cook-Torrance f_r for unit n, l, o (all pointing away from the surface) and
+// reflectances c, s (RGB), roughness r (clamped as in shading).
+//   out_rgb [3]; out_terms = {D, G1(o), G1(l), Fresnel weight (1 - o.h)^k}.
+void oracle_brdf(int32_t variant, int32_t components, const double* n, const double* l, const double* o,
+                 const double* c, const double* s, double r, double* out_rgb, double* out_terms) {
+  Frame<double> f;
+  f.ns = V3(n[0], n[1], n[2]);
+  f.wo = V3(o[0], o[1], o[2]);
+  f.c = V3(c[0], c[1], c[2]);
+  f.s = V3(s[0], s[1], s[2]);
+  f.r = std::min(std::max(r, kRoughMin), kRoughMax);
+  const V3 L(l[0], l[1], l[2]);
+  const double cos_o = dot(f.ns, f.wo), cos_l = dot(f.ns, L);
+  const V3 fr = brdf(f, L, cos_o, cos_l, variant, components, nullptr);
+  out_rgb[0] = fr.x; out_rgb[1] = fr.y; out_rgb[2] = fr.z;
+  if (out_terms) {
+    const V3 h = normalize(L + f.wo);
+    const double nh = dot(f.ns, h);
+    const double nd = variant == 1 ? 1.0 / (kPi * f.r) : (2.0 / f.r + 2.0) / (2.0 * kPi);
+    out_terms[0] = nd * std::pow(nh, 2.0 / f.r - 2.0);
+    out_terms[1] = smith_g1(cos_o, dot(f.wo, h), f.r, (uint8_t*)nullptr);
+    out_terms[2] = smith_g1(cos_l, dot(L, h), f.r, (uint8_t*)nullptr);
+    const double om = 1.0 - dot(f.wo, h);
+    out_terms[3] = variant == 1 ? om * om * om * om * om : om;
+  }
+}
+
+// G1 as a function of a directly (branch included), for the pins of Eq. brdf_g1.
+double oracle_g1_of_a(double a) {
+  if (a < 1.6) return (3.535 * a + 2.181 * a * a) / (1.0 + 2.276 * a + 2.577 * a * a);
+  return 1.0;
+}
+
+}  // extern "C"

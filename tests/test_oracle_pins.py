@@ -1,0 +1,377 @@
+"""Pins of the FP64 oracle against facts it does not itself compute:
+closed forms, textbook functions, invariants and brute force.  Each test says
+which part of the paper the pinned function follows."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2101_05356_amd import scenes
+from tests import helpers
+
+pytestmark = pytest.mark.usefixtures("oracle_lib")
+
+
+# ---------------------------------------------------------------- generator
+
+def test_philox_is_a_bijection_per_key_and_uniform(oracle_lib):
+    o = oracle_lib
+    n = 1 << 16
+    ctr = np.zeros((n, 4), np.uint32)
+    ctr[:, 0] = np.arange(n)
+    out = o.philox(0x0123456789ABCDEF, ctr)
+    # distinct counters -> distinct 128-bit outputs (a bijection for a fixed key)
+    assert len({tuple(r) for r in out}) == n
+    # deterministic
+    assert np.array_equal(out, o.philox(0x0123456789ABCDEF, ctr))
+    # key and every counter word matter
+    assert not np.array_equal(out, o.philox(0x0123456789ABCDEE, ctr))
+    for w in range(1, 4):
+        c2 = ctr.copy()
+        c2[:, w] = 1
+        assert np.mean(o.philox(0x0123456789ABCDEF, c2) == out) < 1e-3
+    # uniformity of the [0,1) mapping: chi-square over 64 bins, every word
+    u = o.unit24(out)
+    for w in range(4):
+        hist = np.bincount((u[:, w] * 64).astype(int), minlength=64)
+        chi2 = ((hist - n / 64) ** 2 / (n / 64)).sum()
+        assert chi2 < 120.0          # 63 dof; p ~ 1e-5
+    # avalanche: flipping one counter bit flips about half of the output bits
+    c3 = ctr.copy()
+    c3[:, 0] ^= 1 << 7
+    flips = np.unpackbits((o.philox(0x0123456789ABCDEF, c3) ^ out).view(np.uint8)).mean()
+    assert abs(flips - 0.5) < 0.01
+
+
+def test_unit24_exact_and_in_range(oracle_lib):
+    x = np.array([0, 255, 256, 0x80000000, 0xFFFFFFFF], np.uint32)
+    u = oracle_lib.unit24(x)
+    assert u[0] == 0.0 and u[1] == 0.0 and u[2] == 2.0 ** -24
+    assert u[3] == 0.5 and u[4] == 1.0 - 2.0 ** -24
+    assert np.all(u.astype(np.float32).astype(np.float64) == u)   # exact in FP32
+
+
+# ---------------------------------------------------------------- camera (Sec. 3.1 pinhole)
+
+def test_camera_ray_closed_forms(oracle_lib):
+    o = oracle_lib
+    sc = helpers.plane_scene(W=64, H=48, fov_deg=45.0, lights=helpers.one_light([0, 0, 1], [1, 0, 0], [0, 1, 0], [1, 1, 1]))
+    d = o.camera_ray(sc, 32.0, 24.0)                   # film centre -> optical axis
+    assert np.allclose(d, [0, 0, -1], atol=1e-15)
+    d = o.camera_ray(sc, 32.0, 0.0)                    # top edge: angle fov/2
+    assert math.isclose(math.degrees(math.acos(-d[2])), 45.0 / 2, rel_tol=1e-6)
+    assert d[1] > 0                                     # +y is up
+    d = o.camera_ray(sc, 0.0, 24.0)                    # left edge: atan(aspect tan(fov/2))
+    assert math.isclose(math.atan2(-d[0], -d[2]), math.atan(64 / 48 * math.tan(math.radians(22.5))), rel_tol=1e-6)
+    # a rotated camera rotates the ray
+    R = oracle_lib.euler_matrix(0.3, -0.2, 0.1)
+    sc.camera = scenes.Camera(R=R.astype(np.float32), T=sc.camera.T, fov_y=sc.camera.fov_y, W=64, H=48)
+    d2 = o.camera_ray(sc, 10.5, 7.25)
+    sc0 = helpers.plane_scene(W=64, H=48, fov_deg=45.0, lights=sc.lights)
+    assert np.allclose(d2, R.astype(np.float32).astype(np.float64) @ o.camera_ray(sc0, 10.5, 7.25), atol=1e-12)
+
+
+# ---------------------------------------------------------------- intersection
+
+def test_single_triangle_hit_recovers_barycentrics(oracle_lib):
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        tri = rng.normal(size=(3, 3))
+        sc = helpers.plane_scene(lights=helpers.one_light([0, 0, 1], [1, 0, 0], [0, 1, 0], [1, 1, 1]))
+        sc.verts = tri.astype(np.float32)
+        sc.tris = np.array([[0, 1, 2]], np.int32)
+        v = sc.verts.astype(np.float64)
+        u, w = rng.uniform(0.05, 0.45, 2)
+        p = v[0] + u * (v[1] - v[0]) + w * (v[2] - v[0])
+        org = p + rng.normal(size=3) * 3
+        d = (p - org) / np.linalg.norm(p - org)
+        tid, fl, t, bu, bv = oracle_lib.closest_hit(sc, org, d)
+        assert tid == 0 and fl == 0
+        assert math.isclose(t, np.linalg.norm(p - org), rel_tol=1e-12)
+        assert abs(bu - u) < 1e-12 and abs(bv - w) < 1e-12
+        # the opposite direction misses (t > 0 only)
+        assert oracle_lib.closest_hit(sc, org, -d)[0] == -1
+
+
+def test_closed_mesh_is_watertight_and_crossings_even(oracle_lib):
+    verts, tris, _ = scenes.latlong_ellipsoid(40, 30)
+    sc = helpers.plane_scene(lights=helpers.one_light([0, 0, 1], [1, 0, 0], [0, 1, 0], [1, 1, 1]))
+    sc.verts, sc.tris = verts, tris
+    rng = np.random.default_rng(1)
+    for _ in range(300):
+        inside_pt = rng.uniform(-0.3, 0.3, 3)            # deep inside the (0.8,1,0.9) ellipsoid
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        org = inside_pt - 5.0 * d
+        tid, fl, t, _, _ = oracle_lib.closest_hit(sc, org, d)
+        assert tid >= 0, "a line through the interior must hit a closed mesh"
+        ts = oracle_lib.line_crossings(sc, org, d)
+        if fl == 0:
+            assert len(ts) % 2 == 0 and len(ts) >= 2
+
+
+def test_grazing_an_edge_is_flagged(oracle_lib):
+    sc = helpers.plane_scene(lights=helpers.one_light([0, 0, 1], [1, 0, 0], [0, 1, 0], [1, 1, 1]))
+    # the shared diagonal of the two plane triangles is the line x = y
+    for off, flagged in ((0.0, True), (5e-7, True), (1e-5, False)):
+        p = np.array([0.3 + off, 0.3 - off, 0.0])
+        org = p + np.array([0.1, -0.2, 2.0])
+        d = (p - org) / np.linalg.norm(p - org)
+        tid, fl, *_ = oracle_lib.closest_hit(sc, org, d)
+        assert tid in (0, 1)
+        assert bool(fl & oracle_lib.FLAG_EDGE) == flagged
+
+
+def test_occlusion_symmetric_and_monotone(oracle_lib):
+    verts, tris, _ = scenes.latlong_ellipsoid(24, 16)
+    sc = helpers.plane_scene(lights=helpers.one_light([0, 0, 1], [1, 0, 0], [0, 1, 0], [1, 1, 1]))
+    sc.verts, sc.tris = verts, tris
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        a, b = rng.uniform(-2, 2, (2, 3))
+        L = np.linalg.norm(b - a)
+        d = (b - a) / L
+        occ_ab, f1 = oracle_lib.occluded(sc, a, d, 1e-4, L - 1e-4)
+        occ_ba, f2 = oracle_lib.occluded(sc, b, -d, 1e-4, L - 1e-4)
+        if not (f1 or f2):
+            assert occ_ab == occ_ba
+            # brute force on the full line: an occluded segment has a crossing inside it
+            ts = oracle_lib.line_crossings(sc, a, d)
+            assert occ_ab == bool(np.any((ts > 1e-4) & (ts < L - 1e-4)))
+
+
+# ---------------------------------------------------------------- BRDF (Appendix A)
+
+def _rand_dir_above(rng, n):
+    while True:
+        v = rng.normal(size=3)
+        v /= np.linalg.norm(v)
+        if np.dot(v, n) > 0.05:
+            return v
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_brdf_reciprocity(oracle_lib, variant):
+    rng = np.random.default_rng(3)
+    n = np.array([0.0, 0.0, 1.0])
+    for _ in range(200):
+        l, o = _rand_dir_above(rng, n), _rand_dir_above(rng, n)
+        c, s = rng.uniform(0, 1, 3), rng.uniform(0, 1, 3)
+        r = rng.uniform(0.05, 1.0)
+        f1, _ = oracle_lib.brdf(n, l, o, c, s, r, variant)
+        f2, _ = oracle_lib.brdf(n, o, l, c, s, r, variant)
+        assert np.allclose(f1, f2, rtol=1e-12, atol=0)
+
+
+def test_ndf_projected_integral_full_hemisphere(oracle_lib):
+    """Same integral without the visibility cut, via the D term's own closed
+    form in n.h (the BRDF probe at l = o gives h = o)."""
+    n = np.array([0.0, 0.0, 1.0])
+    for variant, expect in ((0, lambda r: 1 + r), (1, lambda r: 1.0)):
+        for r in (0.1, 0.3, 0.7, 1.0):
+            mus, wts = np.polynomial.legendre.leggauss(600)
+            mus, wts = 0.5 * (mus + 1.0), 0.5 * wts
+            acc = 0.0
+            for mu, wt in zip(mus, wts):
+                v = np.array([math.sqrt(max(0.0, 1 - mu * mu)), 0.0, mu])
+                _, terms = oracle_lib.brdf(n, v, v, [0, 0, 0], [1, 1, 1], r, variant, components=2)
+                acc += terms[0] * mu * 2 * math.pi * wt
+            assert math.isclose(acc, expect(r), rel_tol=1e-6)
+
+
+def test_g1_against_exact_beckmann_smith(oracle_lib):
+    """Walter et al.'s rational form approximates the Beckmann Smith G1
+    2 / (1 + erf(a) + exp(-a^2)/(a sqrt(pi))) to within about half a percent."""
+    for a in np.linspace(0.05, 3.0, 60):
+        exact = 2.0 / (1.0 + math.erf(a) + math.exp(-a * a) / (a * math.sqrt(math.pi)))
+        assert abs(oracle_lib.g1_of_a(a) - exact) < 6e-3
+    assert oracle_lib.g1_of_a(1e-9) < 1e-8                      # -> 0 as a -> 0
+    assert oracle_lib.g1_of_a(1.6) == 1.0 and oracle_lib.g1_of_a(7.0) == 1.0
+    assert abs(oracle_lib.g1_of_a(1.6 - 1e-12) - 1.0) < 6e-5    # continuity at the branch
+
+
+def test_g1_argument_in_brdf(oracle_lib):
+    """G1(v) uses a = 1/(r tan(acos(n.v))): check through the BRDF probe."""
+    n = np.array([0.0, 0.0, 1.0])
+    for r in (0.3, 0.6):
+        for th in (0.3, 0.9, 1.3):
+            v = np.array([math.sin(th), 0, math.cos(th)])
+            l = np.array([-math.sin(0.2), 0, math.cos(0.2)])
+            _, terms = oracle_lib.brdf(n, l, v, [0, 0, 0], [1, 1, 1], r, 0, components=2)
+            a = 1.0 / (r * math.tan(th))
+            assert math.isclose(terms[1], oracle_lib.g1_of_a(a), rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("variant,k", [(0, 1), (1, 5)])
+def test_fresnel_endpoints_and_exponent(oracle_lib, variant, k):
+    n = np.array([0.0, 0.0, 1.0])
+    s = np.array([0.2, 0.5, 0.9])
+    # o = l -> h = o -> o.h = 1 -> F = s: spec/F ratio is the same for every channel
+    o = np.array([0.3, 0.0, math.sqrt(1 - 0.09)])
+    f, terms = oracle_lib.brdf(n, o, o, [0, 0, 0], s, 0.4, variant, components=2)
+    assert terms[3] == 0.0
+    assert np.allclose(f / s, f[0] / s[0], rtol=1e-12)
+    # Fresnel weight (1 - o.h)^k
+    for th in (0.2, 0.7, 1.1):
+        o = np.array([math.sin(th), 0, math.cos(th)])
+        l = np.array([-math.sin(th), 0, math.cos(th)])
+        h = (o + l) / np.linalg.norm(o + l)
+        _, terms = oracle_lib.brdf(n, l, o, [0, 0, 0], s, 0.4, variant, components=2)
+        assert math.isclose(terms[3], (1 - np.dot(o, h)) ** k, rel_tol=1e-12)
+
+
+def test_brdf_diffuse_is_lambertian(oracle_lib):
+    rng = np.random.default_rng(4)
+    n = np.array([0.0, 0.0, 1.0])
+    c = np.array([0.2, 0.5, 0.8])
+    for _ in range(20):
+        f, _ = oracle_lib.brdf(n, _rand_dir_above(rng, n), _rand_dir_above(rng, n), c, [0.5] * 3, 0.3, 0,
+                               components=1)
+        assert np.allclose(f, c / math.pi, rtol=1e-14)
+
+
+# ---------------------------------------------------------------- estimator (Sec. 3.3, Sec. 4)
+
+@pytest.mark.parametrize("shape", [0, 1])
+def test_lambertian_plane_under_area_light(oracle_lib, shape):
+    """Diffuse-only render of a plane under one area light: each sample's
+    expectation is (c/pi) L Omega_perp(x) (Lambert's polygon formula)."""
+    o = oracle_lib
+    p0, e1, e2 = np.array([-0.3, 0.5, 1.0]), np.array([0.6, 0.0, 0.0]), np.array([0.0, -0.6, 0.2])
+    rad = np.array([2.0, 1.0, 0.5])
+    sc = helpers.plane_scene(W=8, H=8, spp=256, lights=helpers.one_light(p0, e1, e2, rad, shape))
+    r = o.render(sc, components=1)
+    xs, _ = helpers.sample_points_on_plane(o, sc)
+    poly = [p0, p0 + e1, p0 + e1 + e2, p0 + e2] if shape == 0 else [p0, p0 + e1, p0 + e2]
+    n = np.array([0.0, 0.0, 1.0])
+    c = sc.diffuse[0].astype(np.float64)
+    om = np.array([[helpers.projected_solid_angle(x, n, poly) for x in row] for row in xs])
+    expect = (c / math.pi)[None, :] * rad[None, :] * om.mean(axis=1)[:, None]
+    res = (r["rgb"] / expect - 1.0)[:, 0]
+    assert np.std(res) < 0.03
+    assert abs(np.mean(res)) < 4 * np.std(res) / math.sqrt(len(res)) + 2e-4
+    # channel ratios are exactly those of c * L
+    assert np.allclose(r["rgb"][:, 1] / r["rgb"][:, 0], (c[1] * rad[1]) / (c[0] * rad[0]), rtol=1e-12)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_point_light_limit(oracle_lib, variant):
+    """A tiny light gives L A f_r cos cos / d^2 at the light centre (Sec. 3.3:
+    small area lights approximate point lights)."""
+    o = oracle_lib
+    side = 1e-4
+    centre = np.array([0.4, -0.3, 1.2])
+    e1, e2 = np.array([side, 0, 0]), np.array([0, -side, 0])
+    rad = np.array([3.0, 2.0, 1.0])
+    sc = helpers.plane_scene(W=4, H=4, spp=8, lights=helpers.one_light(centre - e1 / 2 - e2 / 2, e1, e2, rad))
+    sc.lights = scenes.Lights(sc.lights.p0, sc.lights.e1, sc.lights.e2, sc.lights.rad, sc.lights.shape)
+    r = o.render(sc, brdf_variant=variant)
+    xs, ds = helpers.sample_points_on_plane(o, sc)
+    n = np.array([0.0, 0.0, 1.0])
+    c, s, rough = sc.diffuse[0], sc.specular[0], float(sc.roughness[0])
+    q = sc.lights.p0[0].astype(np.float64) + 0.5 * sc.lights.e1[0] + 0.5 * sc.lights.e2[0]
+    A = float(np.linalg.norm(np.cross(sc.lights.e1[0].astype(np.float64), sc.lights.e2[0].astype(np.float64))))
+    expect = np.zeros((xs.shape[0], 3))
+    for p in range(xs.shape[0]):
+        for k in range(sc.spp):
+            dq = q - xs[p, k]
+            dist = np.linalg.norm(dq)
+            l = dq / dist
+            f, _ = o.brdf(n, l, -ds[p, k], c, s, rough, variant)
+            expect[p] += rad * f * l[2] * l[2] * A / dist ** 2 / sc.spp
+    assert np.allclose(r["rgb"], expect, rtol=5e-4)
+
+
+def test_occluder_shadow_matches_polygon_clipping(oracle_lib):
+    """Triangle occluder between plane and light: the visibility-weighted
+    diffuse value equals Omega_perp(light) - Omega_perp(light n shadow)."""
+    o = oracle_lib
+    p0, e1, e2 = np.array([1.0, -0.3, 1.0]), np.array([0.6, 0.0, 0.0]), np.array([0.0, 0.6, 0.0])
+    occ = [(0.45, -0.25, 0.5), (0.75, -0.05, 0.5), (0.5, 0.3, 0.5)]
+    sc = helpers.plane_scene(W=6, H=6, spp=256, fov_deg=6.0, extra_tris=[occ],
+                             lights=helpers.one_light(p0, e1 + np.array([0, 0, 0.0]), e2 * -1, [1, 1, 1]))
+    sc.lights = helpers.one_light(p0 + e2, e1, -e2, [1, 1, 1])     # e1 x (-e2) points down
+    r = o.render(sc, components=1)
+    assert np.all(r["hit"] < 2), "camera rays must not see the occluder"
+    xs, _ = helpers.sample_points_on_plane(o, sc)
+    L0, E1, E2 = (sc.lights.p0[0].astype(np.float64), sc.lights.e1[0].astype(np.float64),
+                  sc.lights.e2[0].astype(np.float64))
+    light = [L0, L0 + E1, L0 + E1 + E2, L0 + E2]
+    n = np.array([0.0, 0.0, 1.0])
+    ln = np.array([0.0, 0.0, 1.0])
+    om = np.zeros(xs.shape[:2])
+    frac_shadow = 0
+    for p in range(xs.shape[0]):
+        for k in range(sc.spp):
+            x = xs[p, k]
+            # central projection of the occluder from x onto the light plane z = 1
+            proj = [x + (np.asarray(v) - x) * ((1.0 - x[2]) / (v[2] - x[2])) for v in occ]
+            inter = helpers.convex_intersection(light, proj, ln)
+            sh = helpers.projected_solid_angle(x, n, inter) if inter else 0.0
+            frac_shadow += sh > 0
+            om[p, k] = helpers.projected_solid_angle(x, n, light) - sh
+    assert frac_shadow > 0.2 * om.size, "the test geometry must cast a partial shadow"
+    c = sc.diffuse[0, 0]
+    expect = c / math.pi * om.mean(axis=1)
+    res = r["rgb"][:, 0] / expect - 1.0
+    assert abs(np.mean(res)) < 4 * np.std(res) / math.sqrt(len(res)) + 2e-4
+    assert np.std(res) < 0.2        # binary visibility: per-pixel noise is large, the mean is the pin
+
+
+def test_adding_a_triangle_never_makes_a_sample_visible(oracle_lib):
+    o = oracle_lib
+    sc = scenes.patch_scene(W=16, H=16, spp=4)
+    base = o.render(sc)
+    sc2 = scenes.patch_scene(W=16, H=16, spp=4)
+    # a blocker between the patch and its lowest light, outside the camera's view cone
+    cen = sc.lights.p0 + 0.5 * sc.lights.e1 + 0.5 * sc.lights.e2
+    j = int(np.argmin(cen[:, 2]))
+    c = 0.45 * cen[j].astype(np.float64)
+    a = np.cross(c, [0.0, 0.0, 1.0])
+    a /= np.linalg.norm(a)
+    b = np.cross(c / np.linalg.norm(c), a)
+    tri = np.array([c + 0.5 * a, c - 0.5 * a + 0.4 * b, c - 0.5 * a - 0.4 * b], np.float32)
+    sc2.verts = np.concatenate([sc.verts, tri])
+    sc2.tris = np.concatenate([sc.tris, np.array([[0, 1, 2]]) + sc.n_verts]).astype(np.int32)
+    N = sc2.verts.shape[0]
+    pad = lambda a, v: np.concatenate([a, np.tile(a[:1], (3, 1)) if a.ndim == 2 else a[:3]])
+    sc2.diffuse, sc2.specular, sc2.roughness = pad(sc.diffuse, 0), pad(sc.specular, 0), pad(sc.roughness, 0)
+    more = o.render(sc2)
+    same = base["hit"] == more["hit"]
+    assert same.mean() > 0.99
+    b, m = base["vis"][same], more["vis"][same]
+    assert not np.any((b == o.VIS_OCCLUDED) & (m == o.VIS_VISIBLE))
+    assert np.any((b == o.VIS_VISIBLE) & (m == o.VIS_OCCLUDED)), "the blocker must shadow something"
+
+
+# ---------------------------------------------------------------- loss (Sec. 4 Eq. energy, Variance Reduction)
+
+def test_smoothing_weights_and_adjoint(oracle_lib):
+    o = oracle_lib
+    K = o.gauss3_weights()
+    e = math.exp(-0.5)
+    assert math.isclose(K.sum(), 1.0, rel_tol=1e-15)
+    assert math.isclose(K[1, 1], 1.0 / (1 + 2 * e) ** 2, rel_tol=1e-14)
+    assert math.isclose(K[0, 1], e / (1 + 2 * e) ** 2, rel_tol=1e-14)
+    assert math.isclose(K[0, 0], e * e / (1 + 2 * e) ** 2, rel_tol=1e-14)
+    img = np.full((7, 9, 3), 0.37)
+    assert np.allclose(o.smooth(img), 0.37, rtol=1e-15)
+    rng = np.random.default_rng(5)
+    a, b = rng.normal(size=(2, 7, 9, 3))
+    assert math.isclose((o.smooth(a) * b).sum(), (a * o.smooth_adjoint(b)).sum(), rel_tol=1e-12)
+
+
+def test_loss_zero_at_target_and_subgradient(oracle_lib):
+    o = oracle_lib
+    rng = np.random.default_rng(6)
+    img = rng.uniform(0, 1, (6, 5, 3))
+    E, g, ps = o.loss_and_grad(img, o.smooth(img))
+    assert E == 0.0 and np.all(g == 0.0)
+    tgt = rng.uniform(0, 1, (6, 5, 3))
+    E, g, _ = o.loss_and_grad(img, tgt)
+    h = 1e-7
+    for _ in range(10):
+        d = rng.normal(size=img.shape)
+        Ep, _, _ = o.loss_and_grad(img + h * d, tgt)
+        Em, _, _ = o.loss_and_grad(img - h * d, tgt)
+        assert math.isclose((Ep - Em) / (2 * h), (g * d).sum(), rel_tol=1e-5)
