@@ -725,7 +725,9 @@ int oracle_grad(const OrScene* sc, int32_t n_pix, const int32_t* pix, const int3
 // Each silhouette edge gets probability proportional to its length on the
 // film (pixel units); a sample picks the edge by the running sum, a point
 // y = a + u (b - a) on it, and shades two rays through y -/+ eps m, with m the
-// unit film normal perp(b - a) and eps = 1e-3 pixel.  The estimate
+// unit film normal perp(b - a) and eps = 1e-3 pixel.  The pick is stratified:
+// sample k draws its position in the running sum from [k, k+1)/n_samples.
+// The estimate
 //     sum_k  (ltot / n_samples) (f_minus - f_plus) . dEdp[pixel(y)] (m . dy/dtheta)
 // is added to the two edge vertices and the camera.  dy/dtheta is the film
 // velocity of the 3D edge point that projects to y (perspective-correct
@@ -812,7 +814,8 @@ int oracle_edge_grad(const OrScene* sc, int32_t n_samples, int32_t n_sel, const 
   parallel_for(n_sel, nthreads, [&](int is, int tid) {
     const int k = sel ? sel[is] : is;
     const Rand4 re = philox4x32_10((uint32_t)k, 0u, PURPOSE_EDGE, s.step, s.seed);
-    const double target = unit24(re.x[0]) * ltot;
+    // stratified pick over the running sum: sample k covers [k, k+1)/n_samples
+    const double target = ((double)k + unit24(re.x[0])) / (double)n_samples * ltot;
     const double u = unit24(re.x[1]);
     // first e with cdf[e+1] > target
     const int e = (int)(std::upper_bound(cdf.begin() + 1, cdf.end(), target) - (cdf.begin() + 1));
