@@ -1,0 +1,214 @@
+/* fr.h - C ABI of the MI355X differentiable face renderer.
+ *
+ * The library computes, on one AMD Instinct MI355X (gfx950), the render that
+ * Dib et al., "Practical Face Reconstruction via Differentiable Ray Tracing"
+ * (Eurographics 2021) run in every optimisation step: scene attributes in
+ * (geometry, diffuse/specular/roughness reflectance, pose, camera, area
+ * lights), image, photometric loss and gradients out (Sec. 4, Eq. energy).
+ *
+ * Conventions shared by every entry point:
+ *  - d_* arguments are DEVICE pointers on the context's device, h_* are host
+ *    pointers.  All device buffers are caller-owned, contiguous, FP32 unless
+ *    stated, and must stay alive until the work enqueued on `stream` is done.
+ *  - Every call only enqueues work on `stream` (a hipStream_t; 0 = the null
+ *    stream) and returns without synchronising, except where stated.
+ *  - Gradient outputs are ACCUMULATED (+=): callers zero them first.
+ *  - Vectors are packed xyz / rgb triples: a "[N*3]" buffer holds N triples.
+ *  - Return value: FR_OK or an FR_ERR_* code.  No exception crosses the ABI.
+ *    Argument and shape checks are synchronous; device faults surface at the
+ *    next synchronising call.  fr_last_error() gives the text of the last
+ *    failure on a context.
+ */
+#ifndef FR_H_
+#define FR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* fr_stream; /* == hipStream_t */
+
+enum {
+  FR_OK = 0,
+  FR_ERR_INVALID_ARG = 1, /* null pointer, bad enum, non-positive size */
+  FR_ERR_SHAPE = 2,       /* sizes inconsistent with the mesh or each other */
+  FR_ERR_OOM = 3,         /* device allocation failed */
+  FR_ERR_BUDGET = 4,      /* serving: request does not fit the HBM budget */
+  FR_ERR_DEVICE = 5,      /* a HIP runtime call failed */
+  FR_ERR_NONFINITE = 6,   /* serving: a request produced NaN/Inf */
+  FR_ERR_LIMIT = 7,       /* BVH deeper than the traversal stack, spp too large, ... */
+  FR_ERR_NOT_FOUND = 8    /* serving: unknown request id */
+};
+
+/* Mesh update modes of fr_mesh_update. */
+enum { FR_REFIT = 0, FR_REBUILD = 1 };
+
+/* Light shapes. */
+enum { FR_LIGHT_PARALLELOGRAM = 0, FR_LIGHT_TRIANGLE = 1 };
+
+/* BRDF readings (Appendix A, Eq. brdf_d and Eq. brdf_f).
+ * FR_BRDF_PRINTED:   D = (2/r + 2)/(2 pi) (n.h)^(2/r - 2), F = s + (1 - s)(1 - o.h)
+ * FR_BRDF_NORMALIZED: D = 1/(pi r) (n.h)^(2/r - 2),      F = s + (1 - s)(1 - o.h)^5 */
+enum { FR_BRDF_PRINTED = 0, FR_BRDF_NORMALIZED = 1 };
+
+typedef struct fr_ctx fr_ctx;
+typedef struct fr_mesh fr_mesh;
+
+const char* fr_status_string(int status);
+const char* fr_last_error(const fr_ctx* ctx);
+
+/* One context per device.  Selects `hip_device` for the calling thread. */
+int fr_ctx_create(int hip_device, fr_ctx** out);
+int fr_ctx_destroy(fr_ctx* ctx);
+
+/* Triangle mesh of fixed topology (Sec. 3.1: the morphable model keeps its
+ * triangulation while the vertices move).
+ *  h_tris [n_tris*3] int32 vertex ids, copied.  Builds on the host the
+ *  vertex->face adjacency (for normals) and the unique edge list with the
+ *  faces beside each edge (for edge sampling); allocates the BVH storage
+ *  (one 64-byte node per internal node, one 48-byte record per triangle). */
+int fr_mesh_create(fr_ctx* ctx, int32_t n_verts, int32_t n_tris, const int32_t* h_tris, fr_mesh** out);
+int fr_mesh_destroy(fr_mesh* mesh);
+
+/* Per-step geometry pass over world-space positions d_verts [N*3]:
+ * area-weighted vertex normals (the normal at each vertex, Sec. 3.2), then
+ * the BVH: FR_REBUILD builds it (Morton codes, radix sort, binary radix tree,
+ * bottom-up boxes) and SYNCHRONISES once to check its depth; FR_REFIT keeps
+ * the last built topology and recomputes boxes only (no synchronisation).
+ * The first update of a mesh must be FR_REBUILD.  d_verts must stay unchanged
+ * until the renders that use this update have run. */
+int fr_mesh_update(fr_mesh* mesh, const float* d_verts, int mode, fr_stream stream);
+
+/* Device pointer to the mesh's current vertex normals [N*3] (valid after an
+ * update; owned by the mesh). */
+const float* fr_mesh_normals(const fr_mesh* mesh);
+/* Unique undirected edges of the mesh (host copy of the table used by the
+ * boundary term): h_edges [E*2] vertex ids (lower id first, sorted), h_faces
+ * [E*2] adjacent faces (-1 for a border edge).  Pass NULL to query E. */
+int32_t fr_mesh_edges(const fr_mesh* mesh, int32_t* h_edges, int32_t* h_faces);
+/* Depth of the current BVH (longest root-to-leaf path, in edges). */
+int32_t fr_mesh_bvh_depth(const fr_mesh* mesh);
+
+/* Scene of one render (device pointers unless noted).  The lights are the
+ * area lights of the virtual light stage (Sec. 3.3), given as polygons:
+ * point p0 + a e1 + b e2 with (a,b) in the unit square (parallelogram) or the
+ * unit triangle; e1 x e2 points along the emitting side. */
+typedef struct {
+  int32_t width, height;   /* image size in pixels */
+  int32_t spp;             /* samples per pixel: a power of two, 1..1024 */
+  int32_t n_lights;
+  const float* verts;      /* [N*3] world positions; same buffer as fr_mesh_update */
+  const float* diffuse;    /* [N*3] per-vertex diffuse albedo c_i (Sec. 3.2) */
+  const float* specular;   /* [N*3] per-vertex specular albedo s_i */
+  const float* roughness;  /* [N] per-vertex roughness r_i (clamped to [1e-3,1] in shading) */
+  const float* light_p0;   /* [L*3] */
+  const float* light_e1;   /* [L*3] */
+  const float* light_e2;   /* [L*3] */
+  const float* light_rad;  /* [L*3] RGB radiance */
+  const int32_t* light_shape; /* [L] FR_LIGHT_* (device) */
+  const float* cam;        /* [12] camera-to-world rotation R (row-major 3x3), then centre T */
+  float fov_y;             /* vertical field of view, radians (host value) */
+  uint32_t step;           /* optimisation step: the 4th Philox counter word */
+  uint64_t seed;           /* Philox key */
+} fr_scene;
+
+typedef struct {
+  int32_t brdf_variant;    /* FR_BRDF_* */
+  int32_t components;      /* bit 0 diffuse, bit 1 specular (3 = full BRDF) */
+  int32_t edge_samples;    /* boundary-term samples in the backward; 0 = off, -1 = W*H */
+  int32_t reserved;
+  /* Debug dump of the decisions (device, nullable):
+   *   dbg_hit [W*H*spp] int32 closest-hit triangle id per sample (-1 = miss);
+   *   dbg_pflag [W*H*spp] uint8 nonzero when that decision is near ambiguous;
+   *   dbg_vis [W*H*spp*L] uint8 light code 0 occluded, 1 visible, 2 culled,
+   *     3 no shading point, ORed with 0x80 when near ambiguous.
+   * Sample order is pixel-major: index (y*W + x)*spp + s.
+   * In fr_render_backward the dump covers the boundary term instead (dbg_vis
+   * must be NULL): dbg_hit [n_edge_samples*4] receives per edge sample the
+   * edge id, the pixel id (-1 outside the image) and the hit triangle of the
+   * minus and plus side rays; dbg_pflag [n_edge_samples] its ambiguity flag. */
+  int32_t* dbg_hit;
+  uint8_t* dbg_pflag;
+  uint8_t* dbg_vis;
+  /* Traversal statistics of the forward dump (device, nullable, accumulated):
+   * [10] uint64: camera rays' child-box entries into internal nodes, into
+   * leaves, camera rays traced; the same three for shadow rays; node visits
+   * and leaf visits executed by the wave packets for camera rays, then for
+   * shadow rays. */
+  uint64_t* dbg_stats;
+} fr_render_opts;
+
+/* Gradients of a backward pass; every pointer is nullable ("not requested")
+ * and accumulated into. */
+typedef struct {
+  float* verts;      /* [N*3] world positions (includes the path through the normals) */
+  float* normals;    /* [N*3] dE/dn of the vertex normals (intermediate; nullable) */
+  float* diffuse;    /* [N*3] */
+  float* specular;   /* [N*3] */
+  float* roughness;  /* [N] */
+  float* light_geom; /* [L*9] p0, e1, e2 */
+  float* light_rad;  /* [L*3] */
+  float* cam;        /* [12] R row-major, T */
+} fr_grads;
+
+/* Forward render (Sec. 4 Eq. energy: p^S = F(chi), the Monte-Carlo estimate
+ * of the rendering equation with direct light only, shadows by shadow rays,
+ * Sec. 3.3 "Shadows approximation"; Cook-Torrance BRDF of Appendix A).
+ * Per pixel (x,y) and sample s, Philox4x32-10 with key `seed` and counter
+ * (y*W + x, s, purpose, step) gives the film jitter (purpose 0) and one point
+ * on each light j (purpose 1 + j); one shadow ray per light and sample.
+ * d_image [H*W*3] receives the pixel means (row-major, y = 0 at the top). */
+int fr_render_forward(fr_mesh* mesh, const fr_scene* scene, const fr_render_opts* opts, float* d_image,
+                      fr_stream stream);
+
+/* Photometric loss (Sec. 4 Eq. energy and "Variance Reduction"): optional
+ * 3x3 Gaussian smoothing (sigma 1, clamp-to-edge) of d_image, then
+ * E = sum |p~ - p^R| over pixels and channels (FP64 accumulation).
+ * d_loss [1] float receives E (overwritten); d_dEdp [H*W*3] (nullable)
+ * receives dE/dp = K^T * sign(p~ - p^R) (overwritten). */
+int fr_loss(const float* d_image, const float* d_target, int32_t width, int32_t height, int32_t smooth,
+            float* d_loss, float* d_dEdp, fr_stream stream);
+
+/* Backward pass: the adjoint of fr_render_forward for a given dE/dp
+ * d_dEdp [H*W*3], recomputing every intersection and shadow decision from the
+ * same counters (no stored paths) and holding them fixed (interior term),
+ * then the vertex-normal adjoint into grads->verts, then, if
+ * opts->edge_samples != 0, the primary-visibility boundary term of edge
+ * sampling (Sec. 4 "Edge Sampling") into grads->verts and grads->cam.
+ * Uses the mesh's internal scratch; calls on one mesh must not overlap. */
+int fr_render_backward(fr_mesh* mesh, const fr_scene* scene, const fr_render_opts* opts, const float* d_dEdp,
+                       fr_grads* grads, fr_stream stream);
+
+/* Morphable blend (Sec. 3.1, Sec. 3.2): d_out[m] = d_mean[m] + sum_k
+ * d_coef[k] d_basis[k*M + m], m < M, with the basis stored component-major
+ * ([K][M]).  Geometry: mean = a_s, basis = [Sigma_s; Sigma_e], coef =
+ * [alpha; delta]; albedo: a_r, Sigma_r, beta. */
+int fr_blend(const float* d_mean, const float* d_basis, const float* d_coef, int32_t K, int32_t M, float* d_out,
+             fr_stream stream);
+/* Adjoint of fr_blend: d_gcoef[k] += sum_m d_basis[k*M + m] d_gout[m]. */
+int fr_blend_backward(const float* d_basis, const float* d_gout, int32_t K, int32_t M, float* d_gcoef,
+                      fr_stream stream);
+
+/* Rigid pose of the mesh: d_vw = R v + t with R = Rz(rz) Ry(ry) Rx(rx),
+ * d_pose [6] = (rx, ry, rz, tx, ty, tz) (the rotation/translation of
+ * Sec. 3.1 applied to the object; the camera keeps its own R, T). */
+int fr_pose_forward(const float* d_v, int32_t n_verts, const float* d_pose, float* d_vw, fr_stream stream);
+/* Adjoint: d_gv [N*3] += R^T d_gw (nullable), d_gpose [6] += dE/dpose. */
+int fr_pose_backward(const float* d_v, int32_t n_verts, const float* d_pose, const float* d_gw, float* d_gv,
+                     float* d_gpose, fr_stream stream);
+
+/* Adam (Sec. 5 "Implementation Details": beta1 0.9, beta2 0.999, one learning
+ * rate per parameter group), step number t >= 1, per-element learning rate
+ * d_lr [n]: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
+int fr_adam_step(float* d_param, const float* d_grad, float* d_m, float* d_v, const float* d_lr, int32_t n,
+                 int32_t t, float beta1, float beta2, float eps, fr_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FR_H_ */

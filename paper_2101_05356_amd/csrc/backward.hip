@@ -1,0 +1,318 @@
+// Fused backward of the render (the "back-propagation based gradients" of
+// Sec. 4): for every pixel sample the primary hit and every shadow decision are
+// recomputed from the same Philox counters (no stored ray paths), held fixed,
+// and the hand-written reverse mode runs through the Cook-Torrance BRDF
+// (Appendix A), the light sampling, the shading frame and the ray/triangle
+// intersection, into
+//   - per-vertex positions, normals, diffuse, specular, roughness: per-wave
+//     match-reduce over lanes that hit the same triangle, then one set of
+//     atomics per distinct triangle;
+//   - per-light geometry and radiance, and the camera: wave reduction, LDS
+//     accumulation per block, then atomics into one of kSlots partial slots,
+//     summed by a final kernel.
+#include "fr_shade.h"
+
+namespace fr {
+
+constexpr int kSlots = 1024;
+
+__device__ __forceinline__ float wave_sum(float x) {
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+__device__ __forceinline__ V3 project_out(V3 g, V3 u, float inv_len) {
+  // adjoint of u = w / |w|: (g - u (u . g)) / |w|
+  const float d = dot(u, g);
+  return (g - u * d) * inv_len;
+}
+
+__device__ __forceinline__ void g1_fwd_bwd(float nv, float hv, float r, float& G1, float& dG1_dnv, float& dG1_dr) {
+  dG1_dnv = 0.0f;
+  dG1_dr = 0.0f;
+  if (!(hv / nv > 0.0f)) { G1 = 0.0f; return; }
+  const float s2 = 1.0f - nv * nv;
+  if (s2 <= 0.0f) { G1 = 1.0f; return; }
+  const float rs = sqrtf(s2);
+  const float a = nv / (r * rs);
+  if (!(a < 1.6f)) { G1 = 1.0f; return; }
+  const float P = 3.535f * a + 2.181f * a * a, Q = 1.0f + 2.276f * a + 2.577f * a * a;
+  G1 = P / Q;
+  const float dP = 3.535f + 4.362f * a, dQ = 2.276f + 5.154f * a;
+  const float dG = (dP * Q - P * dQ) / (Q * Q);
+  dG1_dnv = dG / (r * s2 * rs);     // da/dnv = (1 - nv^2)^(-3/2) / r
+  dG1_dr = -dG * a / r;             // da/dr = -a / r
+}
+
+__global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, const float* __restrict__ dEdp, fr_grads g,
+                                                    float* __restrict__ gnorm, float* __restrict__ slots) {
+  extern __shared__ float lds[];   // [L*12 + 12]: per light p0 e1 e2 rad, then camera
+  const int nl = a.L * 12 + 12;
+  for (int i = threadIdx.x; i < nl; i += 256) lds[i] = 0.0f;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int tile = wave_tile(a);
+  float gcam[12];
+  for (int k = 0; k < 12; ++k) gcam[k] = 0.0f;
+  if (tile >= 0) {
+    const PixelSample ps = pixel_sample(a, tile, lane);
+    float gbar[3] = {0.0f, 0.0f, 0.0f};
+    if (ps.valid) {
+      const float inv = 1.0f / (float)a.S;
+      gbar[0] = dEdp[3 * ps.pid] * inv; gbar[1] = dEdp[3 * ps.pid + 1] * inv; gbar[2] = dEdp[3 * ps.pid + 2] * inv;
+    }
+    const bool want = ps.valid && (gbar[0] != 0.0f || gbar[1] != 0.0f || gbar[2] != 0.0f);
+    for (int chunk = 0; chunk < a.chunks; ++chunk) {
+      const int s = ps.s0 + chunk * 64;
+      Sample sm;
+      camera_sample(a, ps, s, sm);
+      HitState h;
+      h.t = 3.4e38f; h.id = -1; h.b0 = h.b1 = h.b2 = 0.0f; h.tamb = 3.4e38f;
+      bool dummy = false;
+      trace<false, false>(a.nodes, a.recs, a.F, sm.ray, want, -1, h, dummy);
+      Frame fr = {};
+      const bool shaded = want && h.id >= 0 && shading_frame(a, sm, h, fr);
+      // sample-level adjoint accumulators
+      V3 gx = {0, 0, 0}, gns = {0, 0, 0}, gwo = {0, 0, 0}, gc = {0, 0, 0}, gs = {0, 0, 0};
+      float gr = 0.0f;
+      for (int j = 0; j < a.L; ++j) {
+        const LightRec& Lj = a.lights[j];
+        LightSample ls;
+        const bool lit = shaded && light_sample(a, ps.pid, s, j, Lj, fr, ls);
+        Ray sr;
+        sr.o = fr.x; sr.d = ls.l; sr.tmin = kShadowTmin; sr.tmax = ls.dist;
+        ray_setup(sr);
+        HitState sh;
+        sh.tamb = 3.4e38f;
+        bool occ = false;
+        trace<true, false>(a.nodes, a.recs, a.F, sr, lit, h.id, sh, occ);
+        const bool vis = lit && !occ;
+        float gl12[12];
+        for (int k = 0; k < 12; ++k) gl12[k] = 0.0f;
+        if (vis) {
+          const V3 rad = {Lj.rad[0], Lj.rad[1], Lj.rad[2]};
+          const V3 na = {Lj.na[0], Lj.na[1], Lj.na[2]};
+          // ---- forward values of the BRDF
+          V3 f = {0, 0, 0};
+          if (a.components & 1) f = fr.c * (1.0f / kPi);
+          V3 hraw = ls.l + fr.wo;
+          const float ih = 1.0f / sqrtf(dot(hraw, hraw));
+          const V3 hv = hraw * ih;
+          float nh = 0, ex = 0, nd = 0, D = 0, oh = 0, G1o = 0, G1l = 0, dG1o = 0, dG1l = 0, dG1o_r = 0, dG1l_r = 0;
+          float om = 0, fw = 0, spec = 0;
+          V3 Fv = {0, 0, 0};
+          const bool do_spec = (a.components & 2) != 0;
+          if (do_spec) {
+            nh = dot(fr.ns, hv);
+            ex = 2.0f / fr.r - 2.0f;
+            nd = a.variant == FR_BRDF_NORMALIZED ? 1.0f / (kPi * fr.r) : (2.0f / fr.r + 2.0f) / (2.0f * kPi);
+            D = nd * powf(nh, ex);
+            oh = dot(fr.wo, hv);
+            const float lh = dot(ls.l, hv);
+            g1_fwd_bwd(fr.cos_o, oh, fr.r, G1o, dG1o, dG1o_r);
+            g1_fwd_bwd(ls.cos_s, lh, fr.r, G1l, dG1l, dG1l_r);
+            om = 1.0f - oh;
+            fw = a.variant == FR_BRDF_NORMALIZED ? om * om * om * om * om : om;
+            spec = D * G1o * G1l / (4.0f * fr.cos_o * ls.cos_s);
+            Fv = {fr.s.x + (1.0f - fr.s.x) * fw, fr.s.y + (1.0f - fr.s.y) * fw, fr.s.z + (1.0f - fr.s.z) * fw};
+            f = f + V3{Fv.x * spec, Fv.y * spec, Fv.z * spec};
+          }
+          // ---- C = rad * f * geom
+          gl12[9] = gbar[0] * f.x * ls.geom;
+          gl12[10] = gbar[1] * f.y * ls.geom;
+          gl12[11] = gbar[2] * f.z * ls.geom;
+          const V3 gf = {gbar[0] * rad.x * ls.geom, gbar[1] * rad.y * ls.geom, gbar[2] * rad.z * ls.geom};
+          const float ggeom = gbar[0] * rad.x * f.x + gbar[1] * rad.y * f.y + gbar[2] * rad.z * f.z;
+          if (a.components & 1) gc = gc + gf * (1.0f / kPi);
+          float gcos_o = 0.0f, gcos_s = 0.0f;
+          V3 gl = {0, 0, 0};
+          if (do_spec) {
+            const float gspec = dot(gf, Fv);
+            const V3 gF = gf * spec;
+            gs = gs + V3{gF.x * (1.0f - fw), gF.y * (1.0f - fw), gF.z * (1.0f - fw)};
+            const float gfw = gF.x * (1.0f - fr.s.x) + gF.y * (1.0f - fr.s.y) + gF.z * (1.0f - fr.s.z);
+            const float gom = a.variant == FR_BRDF_NORMALIZED ? gfw * 5.0f * om * om * om * om : gfw;
+            float goh = -gom;
+            const float den = 4.0f * fr.cos_o * ls.cos_s;
+            const float gD = gspec * G1o * G1l / den;
+            const float gG1o = gspec * D * G1l / den, gG1l = gspec * D * G1o / den;
+            gcos_o -= gspec * spec / fr.cos_o;
+            gcos_s -= gspec * spec / ls.cos_s;
+            gcos_o += gG1o * dG1o;
+            gcos_s += gG1l * dG1l;
+            gr += gG1o * dG1o_r + gG1l * dG1l_r;
+            // D = nd * nh^ex
+            const float gnh = gD * D * ex / nh;
+            const float dlnnd = a.variant == FR_BRDF_NORMALIZED ? -1.0f / fr.r : -1.0f / (fr.r * (1.0f + fr.r));
+            gr += gD * D * (dlnnd - 2.0f * logf(nh) / (fr.r * fr.r));
+            // nh = ns . h, oh = wo . h, h = normalize(l + wo)
+            const V3 gh = fr.ns * gnh + fr.wo * goh;
+            gns = gns + hv * gnh;
+            gwo = gwo + hv * goh;
+            const V3 ghraw = project_out(gh, hv, ih);
+            gl = gl + ghraw;
+            gwo = gwo + ghraw;
+          }
+          // geom = cos_s cos_a / dist2
+          gcos_s += ggeom * ls.cos_a / ls.dist2;
+          const float gcos_a = ggeom * ls.cos_s / ls.dist2;
+          const float gdist2 = -ggeom * ls.geom / ls.dist2;
+          // cos_o = ns . wo ; cos_s = ns . l ; cos_a = na . l
+          gns = gns + fr.wo * gcos_o + ls.l * gcos_s;
+          gwo = gwo + fr.ns * gcos_o;
+          gl = gl + fr.ns * gcos_s + na * gcos_a;
+          const V3 gna = ls.l * gcos_a;
+          // na = -kappa (e1 x e2)
+          const float kap = Lj.shape == FR_LIGHT_TRIANGLE ? 0.5f : 1.0f;
+          const V3 e1 = {Lj.e1[0], Lj.e1[1], Lj.e1[2]}, e2 = {Lj.e2[0], Lj.e2[1], Lj.e2[2]};
+          const V3 ge1n = cross(e2, gna) * (-kap), ge2n = cross(gna, e1) * (-kap);
+          // l = dq / |dq|, dist2 = dq . dq
+          V3 gdq = project_out(gl, ls.l, 1.0f / ls.dist);
+          gdq = gdq + (ls.q - fr.x) * (2.0f * gdist2);
+          gx = gx - gdq;
+          // q = p0 + w1 e1 + w2 e2
+          gl12[0] = gdq.x; gl12[1] = gdq.y; gl12[2] = gdq.z;
+          gl12[3] = gdq.x * ls.w1 + ge1n.x; gl12[4] = gdq.y * ls.w1 + ge1n.y; gl12[5] = gdq.z * ls.w1 + ge1n.z;
+          gl12[6] = gdq.x * ls.w2 + ge2n.x; gl12[7] = gdq.y * ls.w2 + ge2n.y; gl12[8] = gdq.z * ls.w2 + ge2n.z;
+        }
+        if (ballot(vis)) {
+          for (int k = 0; k < 12; ++k) {
+            const float t = wave_sum(gl12[k]);
+            if (lane == 0 && t != 0.0f) atomicAdd(&lds[12 * j + k], t);
+          }
+        }
+      }
+      // ---- sample-level adjoint: shading frame, intersection, camera
+      V3 gv[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, gn[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      float gb[3] = {0.0f, 0.0f, 0.0f};
+      if (shaded) {
+        const float grr = fr.r_free ? gr : 0.0f;
+        const V3 gm = project_out(gns, fr.ns, fr.inv_m);
+        V3 vv[3];
+        for (int k = 0; k < 3; ++k) {
+          vv[k] = ld3(a.verts, fr.vi[k]);
+          const V3 nk = ld3(a.normals, fr.vi[k]);
+          const V3 ck = ld3(a.diffuse, fr.vi[k]), sk = ld3(a.specular, fr.vi[k]);
+          const float rk = a.roughness[fr.vi[k]];
+          gb[k] = dot(nk, gm) + dot(vv[k], gx) + dot(ck, gc) + dot(sk, gs) + rk * grr;
+          gn[k] = gm * fr.b[k];
+          gv[k] = gx * fr.b[k];
+        }
+        // b0 = 1 - b1 - b2; Moller-Trumbore adjoint of (b1, b2)
+        const float g1 = gb[1] - gb[0], g2 = gb[2] - gb[0];
+        const V3 d = sm.ray.d, o = sm.ray.o;
+        const V3 e1 = vv[1] - vv[0], e2 = vv[2] - vv[0];
+        const V3 pv = cross(d, e2);
+        const float det = dot(e1, pv);
+        const float idet = 1.0f / det;
+        const V3 sv = o - vv[0];
+        const V3 qv = cross(sv, e1);
+        const float b1 = dot(sv, pv) * idet, b2 = dot(d, qv) * idet;
+        const float gA1 = g1 * idet, gA2 = g2 * idet, gdet = -(g1 * b1 + g2 * b2) * idet;
+        V3 gsv = pv * gA1, gp = sv * gA1;
+        V3 gd = qv * gA2 - gwo;
+        const V3 gq = d * gA2;
+        V3 ge1 = pv * gdet;
+        gp = gp + e1 * gdet;
+        gsv = gsv + cross(e1, gq);
+        ge1 = ge1 + cross(gq, sv);
+        gd = gd + cross(e2, gp);
+        const V3 ge2 = cross(gp, d);
+        gv[0] = gv[0] - gsv - ge1 - ge2;
+        gv[1] = gv[1] + ge1;
+        gv[2] = gv[2] + ge2;
+        // d = dw / |dw|, dw = R dc, o = T
+        const V3 gdw = project_out(gd, d, sm.inv_len);
+        gcam[0] += gdw.x * sm.dc.x; gcam[1] += gdw.x * sm.dc.y; gcam[2] += gdw.x * sm.dc.z;
+        gcam[3] += gdw.y * sm.dc.x; gcam[4] += gdw.y * sm.dc.y; gcam[5] += gdw.y * sm.dc.z;
+        gcam[6] += gdw.z * sm.dc.x; gcam[7] += gdw.z * sm.dc.y; gcam[8] += gdw.z * sm.dc.z;
+        gcam[9] += gsv.x; gcam[10] += gsv.y; gcam[11] += gsv.z;
+        gr = grr;
+      }
+      // ---- per-vertex scatter: one atomic set per distinct triangle in the wave
+      uint64_t todo = ballot(shaded);
+      while (todo) {
+        const int leader = (int)__builtin_ctzll(todo);
+        const int key = readlane_i(h.id, leader);
+        const bool mine = shaded && h.id == key;
+        todo &= ~ballot(mine);
+        const int* tv = a.tris + 3 * key;
+        for (int k = 0; k < 3; ++k) {
+          const int vi = tv[k];
+          const float bk = fr.b[k];
+          float vals[13] = {gv[k].x, gv[k].y, gv[k].z, gn[k].x, gn[k].y, gn[k].z, gc.x * bk, gc.y * bk, gc.z * bk,
+                            gs.x * bk, gs.y * bk, gs.z * bk, gr * bk};
+          for (int q = 0; q < 13; ++q) vals[q] = wave_sum(mine ? vals[q] : 0.0f);
+          if (lane == leader) {
+            if (g.verts) { atomicAdd(g.verts + 3 * vi, vals[0]); atomicAdd(g.verts + 3 * vi + 1, vals[1]); atomicAdd(g.verts + 3 * vi + 2, vals[2]); }
+            atomicAdd(gnorm + 3 * vi, vals[3]); atomicAdd(gnorm + 3 * vi + 1, vals[4]); atomicAdd(gnorm + 3 * vi + 2, vals[5]);
+            if (g.diffuse) { atomicAdd(g.diffuse + 3 * vi, vals[6]); atomicAdd(g.diffuse + 3 * vi + 1, vals[7]); atomicAdd(g.diffuse + 3 * vi + 2, vals[8]); }
+            if (g.specular) { atomicAdd(g.specular + 3 * vi, vals[9]); atomicAdd(g.specular + 3 * vi + 1, vals[10]); atomicAdd(g.specular + 3 * vi + 2, vals[11]); }
+            if (g.roughness) atomicAdd(g.roughness + vi, vals[12]);
+          }
+        }
+      }
+    }
+  }
+  // camera: wave reduction into LDS
+  for (int k = 0; k < 12; ++k) {
+    const float t = wave_sum(gcam[k]);
+    if (lane == 0 && t != 0.0f) atomicAdd(&lds[12 * a.L + k], t);
+  }
+  __syncthreads();
+  float* slot = slots + (size_t)(blockIdx.x % kSlots) * nl;
+  for (int i = threadIdx.x; i < nl; i += 256)
+    if (lds[i] != 0.0f) atomicAdd(slot + i, lds[i]);
+}
+
+// Sum the slots into the caller's light and camera gradients.
+__global__ __launch_bounds__(256) void k_slots_reduce(const float* __restrict__ slots, int nl, int L,
+                                                      float* __restrict__ glight, float* __restrict__ grad,
+                                                      float* __restrict__ gcam) {
+  const int i = blockIdx.x;   // one block per value
+  __shared__ float red[256];
+  float acc = 0.0f;
+  for (int s = threadIdx.x; s < kSlots; s += 256) acc += slots[(size_t)s * nl + i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const float v = red[0];
+  if (i < 12 * L) {
+    const int j = i / 12, k = i % 12;
+    if (k < 9) { if (glight) glight[9 * j + k] += v; }
+    else if (grad) grad[3 * j + (k - 9)] += v;
+  } else if (gcam) {
+    gcam[i - 12 * L] += v;
+  }
+}
+
+__global__ void k_zero_slots(float* p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
+// Slot storage: kSlots * (12 L + 12) floats, grown on demand.
+static float* g_slots = nullptr;
+static size_t g_slots_cap = 0;
+
+void launch_render_backward(const RenderArgs& a, const float* dEdp, const fr_grads& g, float* gnorm, hipStream_t st) {
+  const int nl = a.L * 12 + 12;
+  const size_t need = (size_t)kSlots * nl;
+  if (need > g_slots_cap) {
+    if (g_slots) hipFree(g_slots);
+    g_slots = nullptr;
+    g_slots_cap = 0;
+    if (hipMalloc(&g_slots, need * sizeof(float)) != hipSuccess) return;
+    g_slots_cap = need;
+  }
+  hipLaunchKernelGGL(k_zero_slots, dim3((unsigned)((need + 255) / 256)), dim3(256), 0, st, g_slots, need);
+  const int blocks = wave_blocks_strips(a);
+  hipLaunchKernelGGL(k_render_bwd, dim3(blocks), dim3(256), nl * sizeof(float), st, a, dEdp, g, gnorm, g_slots);
+  hipLaunchKernelGGL(k_slots_reduce, dim3(nl), dim3(256), 0, st, g_slots, nl, a.L, g.light_geom, g.light_rad, g.cam);
+}
+
+}  // namespace fr

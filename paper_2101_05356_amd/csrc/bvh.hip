@@ -1,0 +1,352 @@
+// LBVH construction and refit on the GPU.
+//
+// Build: centroid bounds -> 30-bit Morton codes -> stable LSD radix sort
+// (four 8-bit passes; ranks from wave ballots, so equal keys keep their
+// order) -> binary radix tree over the sorted codes (Karras, HPG 2012, with
+// the index as tie-break for equal codes) -> bottom-up boxes.
+// Refit: the bottom-up box pass alone, over the last built topology.
+//
+// A boundary-to-root walk per leaf gives the depth; the traversal stack is 64
+// entries, so trees deeper than that are rejected by the host.
+#include "fr_kernels.h"
+
+namespace fr {
+
+// ---------------------------------------------------------------------------
+// Centroid bounds (two-level min/max reduction) and Morton codes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ V3 centroid(const float* __restrict__ v, const int32_t* __restrict__ tris, int f) {
+  const V3 a = ld3(v, tris[3 * f]), b = ld3(v, tris[3 * f + 1]), c = ld3(v, tris[3 * f + 2]);
+  return {(a.x + b.x + c.x) * (1.0f / 3.0f), (a.y + b.y + c.y) * (1.0f / 3.0f), (a.z + b.z + c.z) * (1.0f / 3.0f)};
+}
+
+__global__ __launch_bounds__(256) void k_centroid_bounds(const float* __restrict__ v, const int32_t* __restrict__ tris,
+                                                         int F, float* __restrict__ partial) {
+  __shared__ float red[6][256];
+  float mn[3] = {3.4e38f, 3.4e38f, 3.4e38f}, mx[3] = {-3.4e38f, -3.4e38f, -3.4e38f};
+  for (int f = blockIdx.x * 256 + threadIdx.x; f < F; f += gridDim.x * 256) {
+    const V3 c = centroid(v, tris, f);
+    mn[0] = fminf(mn[0], c.x); mn[1] = fminf(mn[1], c.y); mn[2] = fminf(mn[2], c.z);
+    mx[0] = fmaxf(mx[0], c.x); mx[1] = fmaxf(mx[1], c.y); mx[2] = fmaxf(mx[2], c.z);
+  }
+  for (int k = 0; k < 3; ++k) { red[k][threadIdx.x] = mn[k]; red[3 + k][threadIdx.x] = mx[k]; }
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int k = 0; k < 3; ++k) {
+        red[k][threadIdx.x] = fminf(red[k][threadIdx.x], red[k][threadIdx.x + s]);
+        red[3 + k][threadIdx.x] = fmaxf(red[3 + k][threadIdx.x], red[3 + k][threadIdx.x + s]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) partial[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Spread the low 10 bits of x so that bit i lands at bit 3i.
+__device__ __forceinline__ uint32_t spread3(uint32_t x) {
+  x &= 0x3ffu;
+  x = (x | (x << 16)) & 0x030000ffu;
+  x = (x | (x << 8)) & 0x0300f00fu;
+  x = (x | (x << 4)) & 0x030c30c3u;
+  x = (x | (x << 2)) & 0x09249249u;
+  return x;
+}
+
+__global__ __launch_bounds__(256) void k_morton(const float* __restrict__ v, const int32_t* __restrict__ tris, int F,
+                                                const float* __restrict__ partial, int nparts,
+                                                uint32_t* __restrict__ keys, int32_t* __restrict__ vals,
+                                                float* __restrict__ scene_box) {
+  float mn[3] = {3.4e38f, 3.4e38f, 3.4e38f}, mx[3] = {-3.4e38f, -3.4e38f, -3.4e38f};
+  for (int p = 0; p < nparts; ++p)
+    for (int k = 0; k < 3; ++k) { mn[k] = fminf(mn[k], partial[6 * p + k]); mx[k] = fmaxf(mx[k], partial[6 * p + 3 + k]); }
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  if (f == 0)
+    for (int k = 0; k < 3; ++k) { scene_box[k] = mn[k]; scene_box[3 + k] = mx[k]; }
+  if (f >= F) return;
+  const V3 c = centroid(v, tris, f);
+  const float cc[3] = {c.x, c.y, c.z};
+  uint32_t q[3];
+  for (int k = 0; k < 3; ++k) {
+    const float ext = mx[k] - mn[k];
+    const float u = ext > 0.0f ? (cc[k] - mn[k]) / ext : 0.5f;
+    q[k] = (uint32_t)fminf(fmaxf(u * 1024.0f, 0.0f), 1023.0f);
+  }
+  keys[f] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+  vals[f] = f;
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort, 8-bit digits, tiles of 1024 keys per 256-thread block.
+// ---------------------------------------------------------------------------
+constexpr int kSortTile = 1024;
+
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys, int n, int shift,
+                                                    uint32_t* __restrict__ hist, int nblocks) {
+  __shared__ uint32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * kSortTile;
+  for (int i = threadIdx.x; i < kSortTile; i += 256) {
+    const int k = base + i;
+    if (k < n) atomicAdd(&cnt[(keys[k] >> shift) & 0xffu], 1u);
+  }
+  __syncthreads();
+  hist[threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];   // digit-major
+}
+
+// Exclusive scan of hist[256 * nblocks] in place (single block of 1024).
+__global__ __launch_bounds__(1024) void k_radix_scan(uint32_t* __restrict__ hist, int total) {
+  __shared__ uint32_t part[1024];
+  const int per = (total + 1023) / 1024;
+  const int b = threadIdx.x * per;
+  uint32_t s = 0;
+  for (int i = 0; i < per; ++i) if (b + i < total) s += hist[b + i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t x = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += x;
+    __syncthreads();
+  }
+  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (int i = 0; i < per; ++i)
+    if (b + i < total) { const uint32_t h = hist[b + i]; hist[b + i] = run; run += h; }
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
+                                                       int n, int shift, const uint32_t* __restrict__ offs, int nblocks,
+                                                       uint32_t* __restrict__ kout, int32_t* __restrict__ vout) {
+  __shared__ uint32_t run[256];        // keys of each digit already placed by this block
+  __shared__ uint32_t wcnt[4][256];    // per-wave digit counts of the current round
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  run[threadIdx.x] = 0;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int round = 0; round < kSortTile / 256; ++round) {
+    for (int w = 0; w < 4; ++w) wcnt[w][threadIdx.x] = 0;
+    __syncthreads();
+    const int k = blockIdx.x * kSortTile + round * 256 + threadIdx.x;
+    const bool ok = k < n;
+    const uint32_t key = ok ? kin[k] : 0u;
+    const uint32_t dig = (key >> shift) & 0xffu;
+    uint64_t peers = ballot(ok);
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (dig >> bit) & 1u;
+      const uint64_t m = ballot(on);
+      peers &= on ? m : ~m;
+    }
+    const uint32_t rank_w = (uint32_t)__popcll(peers & lt);
+    if (ok && (peers >> lane) == 1ull) wcnt[wave][dig] = rank_w + 1;   // highest lane of the group
+    __syncthreads();
+    if (ok) {
+      uint32_t before = run[dig];
+      for (int w = 0; w < wave; ++w) before += wcnt[w][dig];
+      const uint32_t pos = offs[dig * nblocks + blockIdx.x] + before + rank_w;
+      kout[pos] = key;
+      vout[pos] = vin[k];
+    }
+    __syncthreads();
+    run[threadIdx.x] += wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] + wcnt[2][threadIdx.x] + wcnt[3][threadIdx.x];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Binary radix tree (Karras 2012).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int common_prefix(const uint32_t* __restrict__ k, int n, int i, int j) {
+  if (j < 0 || j >= n) return -1;
+  const uint32_t a = k[i], b = k[j];
+  if (a != b) return __clz(a ^ b);
+  return 32 + __clz((uint32_t)i ^ (uint32_t)j);
+}
+
+__global__ __launch_bounds__(256) void k_karras(const uint32_t* __restrict__ k, int n, BvhNode* __restrict__ nodes,
+                                                int32_t* __restrict__ node_parent, int32_t* __restrict__ leaf_parent) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n - 1) return;
+  const int d = common_prefix(k, n, i, i + 1) - common_prefix(k, n, i, i - 1) > 0 ? 1 : -1;
+  const int dmin = common_prefix(k, n, i, i - d);
+  int lmax = 2;
+  while (common_prefix(k, n, i, i + lmax * d) > dmin) lmax <<= 1;
+  int l = 0;
+  for (int t = lmax >> 1; t >= 1; t >>= 1)
+    if (common_prefix(k, n, i, i + (l + t) * d) > dmin) l += t;
+  const int j = i + l * d;
+  const int dnode = common_prefix(k, n, i, j);
+  int s = 0;
+  int t = l;
+  do {
+    t = (t + 1) >> 1;
+    if (common_prefix(k, n, i, i + (s + t) * d) > dnode) s += t;
+  } while (t > 1);
+  const int split = i + s * d + (d < 0 ? -1 : 0);
+  const int lo = min(i, j), hi = max(i, j);
+  const int c0 = (lo == split) ? ~split : split;
+  const int c1 = (hi == split + 1) ? ~(split + 1) : split + 1;
+  nodes[i].c0 = c0;
+  nodes[i].c1 = c1;
+  if (c0 < 0) leaf_parent[~c0] = i; else node_parent[c0] = i;
+  if (c1 < 0) leaf_parent[~c1] = i; else node_parent[c1] = i;
+  if (i == 0) node_parent[0] = -1;
+}
+
+// Single-triangle mesh: one node whose second child box is empty.
+__global__ void k_single_leaf(BvhNode* __restrict__ nodes, int32_t* __restrict__ leaf_parent) {
+  nodes[0].c0 = ~0;
+  nodes[0].c1 = ~0;
+  for (int k = 0; k < 3; ++k) { nodes[0].b1[k] = 3.4e38f; nodes[0].b1[3 + k] = -3.4e38f; }
+  leaf_parent[0] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Refit: leaf records + bottom-up boxes.  flags[] must be zero on entry.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_refit(const float* __restrict__ v, const int32_t* __restrict__ tris,
+                                               const int32_t* __restrict__ order, int F, BvhNode* nodes,
+                                               const int32_t* __restrict__ node_parent,
+                                               const int32_t* __restrict__ leaf_parent, uint32_t* flags,
+                                               TriRec* __restrict__ recs, float pad) {
+  const int slot = blockIdx.x * 256 + threadIdx.x;
+  if (slot >= F) return;
+  const int f = order[slot];
+  const V3 a = ld3(v, tris[3 * f]), b = ld3(v, tris[3 * f + 1]), c = ld3(v, tris[3 * f + 2]);
+  TriRec r;
+  r.v[0] = a.x; r.v[1] = a.y; r.v[2] = a.z; r.v[3] = b.x; r.v[4] = b.y; r.v[5] = b.z;
+  r.v[6] = c.x; r.v[7] = c.y; r.v[8] = c.z;
+  r.id = f; r.pad0 = 0; r.pad1 = 0;
+  recs[slot] = r;
+  float box[6] = {fminf(a.x, fminf(b.x, c.x)) - pad, fminf(a.y, fminf(b.y, c.y)) - pad,
+                  fminf(a.z, fminf(b.z, c.z)) - pad, fmaxf(a.x, fmaxf(b.x, c.x)) + pad,
+                  fmaxf(a.y, fmaxf(b.y, c.y)) + pad, fmaxf(a.z, fmaxf(b.z, c.z)) + pad};
+  // Child boxes live in the parent node.  The second child to arrive at a
+  // node (atomic counter) merges both; box traffic goes through device-scope
+  // atomic loads/stores so no stale cached line is read.
+  int child = ~slot;
+  int p = leaf_parent[slot];
+  while (p >= 0) {
+    BvhNode* pn = nodes + p;
+    float* dst = (pn->c0 == child) ? pn->b0 : pn->b1;
+    for (int k = 0; k < 6; ++k) __hip_atomic_store(dst + k, box[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (F == 1) break;
+    __threadfence();
+    if (atomicAdd(&flags[p], 1u) == 0u) return;    // the sibling finishes this node
+    __threadfence();
+    for (int k = 0; k < 3; ++k) {
+      const float a0 = __hip_atomic_load(pn->b0 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const float a1 = __hip_atomic_load(pn->b1 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const float c0 = __hip_atomic_load(pn->b0 + 3 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const float c1 = __hip_atomic_load(pn->b1 + 3 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      box[k] = fminf(a0, a1);
+      box[3 + k] = fmaxf(c0, c1);
+    }
+    child = p;
+    p = node_parent[p];
+  }
+}
+
+// Structural check of a freshly built tree: sorted keys, child and parent
+// indices in range, and every node the child of exactly one parent (so the
+// topology is a tree and traversal terminates).  Counts violations.
+__global__ __launch_bounds__(256) void k_validate(const uint32_t* __restrict__ keys, int F,
+                                                  const BvhNode* __restrict__ nodes,
+                                                  const int32_t* __restrict__ node_parent,
+                                                  const int32_t* __restrict__ leaf_parent, uint32_t* __restrict__ bad) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= F) return;
+  uint32_t err = 0;
+  if (i + 1 < F && keys[i] > keys[i + 1]) ++err;
+  const int lp = leaf_parent[i];
+  if (lp < 0 || lp >= max(F - 1, 1)) ++err;
+  else if (nodes[lp].c0 != ~i && nodes[lp].c1 != ~i) ++err;
+  if (i < F - 1) {
+    const int c[2] = {nodes[i].c0, nodes[i].c1};
+    for (int k = 0; k < 2; ++k) {
+      if (c[k] >= 0) {
+        if (c[k] >= F - 1 || c[k] == 0) ++err;
+        else if (node_parent[c[k]] != i) ++err;
+      } else if (~c[k] >= F || leaf_parent[~c[k]] != i) {
+        ++err;
+      }
+    }
+    if (i > 0) {
+      const int p = node_parent[i];
+      if (p < 0 || p >= F - 1) ++err;
+      else if (nodes[p].c0 != i && nodes[p].c1 != i) ++err;
+    }
+  }
+  if (err) atomicAdd(bad, err);
+}
+
+__global__ __launch_bounds__(256) void k_leaf_depth(const int32_t* __restrict__ node_parent,
+                                                    const int32_t* __restrict__ leaf_parent, int F,
+                                                    int32_t* __restrict__ max_depth) {
+  const int slot = blockIdx.x * 256 + threadIdx.x;
+  if (slot >= F) return;
+  int d = 1;
+  int p = leaf_parent[slot];
+  while (p > 0 && p < F - 1 && d < 4096) { p = node_parent[p]; ++d; }
+  // a leaf whose parent chain does not end at the root makes the tree invalid
+  atomicMax(max_depth, p == 0 ? d : 1 << 20);
+}
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Host drivers
+// ---------------------------------------------------------------------------
+static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+void bvh_refit(MeshDev& m, const float* d_verts, hipStream_t st) {
+  const int F = m.F;
+  const int nflags = F > 1 ? F - 1 : 1;
+  hipLaunchKernelGGL(k_zero_u32, dim3(cdiv(nflags, 256)), dim3(256), 0, st, m.flags, nflags);
+  hipLaunchKernelGGL(k_refit, dim3(cdiv(F, 256)), dim3(256), 0, st, d_verts, m.tris, m.order, F, m.nodes,
+                     m.node_parent, m.leaf_parent, m.flags, m.recs, kBoxPad);
+}
+
+int bvh_build(MeshDev& m, const float* d_verts, hipStream_t st, int* depth_out) {
+  const int F = m.F;
+  const int nparts = 64;
+  hipLaunchKernelGGL(k_centroid_bounds, dim3(nparts), dim3(256), 0, st, d_verts, m.tris, F, m.partial);
+  hipLaunchKernelGGL(k_morton, dim3(cdiv(F, 256)), dim3(256), 0, st, d_verts, m.tris, F, m.partial, nparts,
+                     m.keys[0], m.vals[0], m.scene_box);
+  const int nb = cdiv(F, kSortTile);
+  int cur = 0;
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 8 * pass;
+    hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(256), 0, st, m.keys[cur], F, shift, m.hist, nb);
+    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, m.hist, 256 * nb);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(256), 0, st, m.keys[cur], m.vals[cur], F, shift, m.hist, nb,
+                       m.keys[cur ^ 1], m.vals[cur ^ 1]);
+    cur ^= 1;
+  }
+  // after an even number of passes the sorted data is back in buffer 0
+  hipMemcpyAsync(m.order, m.vals[cur], sizeof(int32_t) * F, hipMemcpyDeviceToDevice, st);
+  if (F > 1) {
+    hipLaunchKernelGGL(k_karras, dim3(cdiv(F - 1, 256)), dim3(256), 0, st, m.keys[cur], F, m.nodes, m.node_parent,
+                       m.leaf_parent);
+  } else {
+    hipLaunchKernelGGL(k_single_leaf, dim3(1), dim3(1), 0, st, m.nodes, m.leaf_parent);
+  }
+  // validate the topology before anything walks it
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t*>(m.depth), 2);
+  hipLaunchKernelGGL(k_validate, dim3(cdiv(F, 256)), dim3(256), 0, st, m.keys[cur], F, m.nodes, m.node_parent,
+                     m.leaf_parent, reinterpret_cast<uint32_t*>(m.depth) + 1);
+  int32_t chk[2] = {0, 0};
+  if (hipMemcpyAsync(chk, m.depth, sizeof(chk), hipMemcpyDeviceToHost, st) != hipSuccess) return FR_ERR_DEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return FR_ERR_DEVICE;
+  if (chk[1] != 0) return FR_ERR_LIMIT;
+  bvh_refit(m, d_verts, st);
+  hipLaunchKernelGGL(k_leaf_depth, dim3(cdiv(F, 256)), dim3(256), 0, st, m.node_parent, m.leaf_parent, F, m.depth);
+  int32_t depth = 0;
+  if (hipMemcpyAsync(&depth, m.depth, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess) return FR_ERR_DEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return FR_ERR_DEVICE;
+  *depth_out = depth;
+  return FR_OK;
+}
+
+}  // namespace fr

@@ -1,0 +1,249 @@
+// Primary-visibility boundary term of edge sampling (Sec. 4 "Edge Sampling").
+//
+// 1. Facing of every face w.r.t. the camera centre T: sign of
+//    ((v1 - v0) x (v2 - v0)) . (T - v0), in FP64 and in exactly that order, so
+//    the classification is bitwise that of an FP64 evaluation.
+// 2. Silhouette edges (faces of opposite facing, or a single face) get their
+//    film length in pixels (FP64); every other edge gets 0.  A fixed-order
+//    FP64 scan gives the running sum.
+// 3. Edge sample k picks the edge whose running-sum interval holds
+//    ((k + u0)/n) * total (stratified), a point y = a + u1 (b - a) on its film
+//    image, and traces two camera rays through y -/+ 1e-3 m (m the unit film
+//    normal), each shaded with one point per light from counters
+//    (k, 0, 0x80000001 + j, step).  The estimate
+//       (total / n) ((f- - f+) . dE/dp[pixel of y]) (m . dy/dtheta)
+//    goes to both edge vertices and to the camera; dy/dtheta is the film
+//    velocity of the 3D edge point that projects to y.
+#include "fr_shade.h"
+
+namespace fr {
+
+__global__ __launch_bounds__(256) void k_face_front(const float* __restrict__ v, const int32_t* __restrict__ tris, int F,
+                                                    const float* __restrict__ cam, uint8_t* __restrict__ front) {
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  if (f >= F) return;
+  const int i0 = tris[3 * f], i1 = tris[3 * f + 1], i2 = tris[3 * f + 2];
+  const double v0x = v[3 * i0], v0y = v[3 * i0 + 1], v0z = v[3 * i0 + 2];
+  const double ax = (double)v[3 * i1] - v0x, ay = (double)v[3 * i1 + 1] - v0y, az = (double)v[3 * i1 + 2] - v0z;
+  const double bx = (double)v[3 * i2] - v0x, by = (double)v[3 * i2 + 1] - v0y, bz = (double)v[3 * i2 + 2] - v0z;
+  const double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+  const double wx = (double)cam[9] - v0x, wy = (double)cam[10] - v0y, wz = (double)cam[11] - v0z;
+  front[f] = (nx * wx + ny * wy + nz * wz) > 0.0 ? 1 : 0;
+}
+
+struct FilmD { double x, y, z; };
+
+__device__ __forceinline__ FilmD project_d(const float* __restrict__ cam, double th, double aspect, int W, int H,
+                                           double X, double Y, double Z) {
+  const double dx = X - (double)cam[9], dy = Y - (double)cam[10], dz = Z - (double)cam[11];
+  // camera frame R^T (X - T)
+  const double px = (double)cam[0] * dx + (double)cam[3] * dy + (double)cam[6] * dz;
+  const double py = (double)cam[1] * dx + (double)cam[4] * dy + (double)cam[7] * dz;
+  const double pz = (double)cam[2] * dx + (double)cam[5] * dy + (double)cam[8] * dz;
+  const double z = -pz;
+  FilmD f;
+  f.x = (px / z / (th * aspect) + 1.0) * (0.5 * W);
+  f.y = (1.0 - py / z / th) * (0.5 * H);
+  f.z = z;
+  return f;
+}
+
+__global__ __launch_bounds__(256) void k_edge_len(const float* __restrict__ v, const int32_t* __restrict__ edges,
+                                                  const int32_t* __restrict__ edge_faces, int E,
+                                                  const uint8_t* __restrict__ front, const float* __restrict__ cam,
+                                                  double th, double aspect, int W, int H, double* __restrict__ len) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= E) return;
+  const int f0 = edge_faces[2 * e], f1 = edge_faces[2 * e + 1];
+  const bool sil = f1 < 0 || front[f0] != front[f1];
+  double l = 0.0;
+  if (sil) {
+    const int a = edges[2 * e], b = edges[2 * e + 1];
+    const FilmD pa = project_d(cam, th, aspect, W, H, v[3 * a], v[3 * a + 1], v[3 * a + 2]);
+    const FilmD pb = project_d(cam, th, aspect, W, H, v[3 * b], v[3 * b + 1], v[3 * b + 2]);
+    if (pa.z > 0.0 && pb.z > 0.0) l = hypot(pb.x - pa.x, pb.y - pa.y);
+  }
+  len[e] = l;
+}
+
+// Inclusive FP64 scan in fixed order: per-thread serial runs + block scan.
+__global__ __launch_bounds__(1024) void k_edge_scan(const double* __restrict__ len, int E, double* __restrict__ cdf) {
+  __shared__ double part[1024];
+  const int per = (E + 1023) / 1024;
+  const int b = threadIdx.x * per;
+  double s = 0.0;
+  for (int i = 0; i < per; ++i) if (b + i < E) s += len[b + i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double run = 0.0;
+    for (int i = 0; i < 1024; ++i) { const double x = part[i]; part[i] = run; run += x; }
+  }
+  __syncthreads();
+  double run = part[threadIdx.x];
+  for (int i = 0; i < per; ++i) if (b + i < E) { run += len[b + i]; cdf[b + i] = run; }
+}
+
+// Shaded radiance (no 1/S) of the camera ray through film point (fx, fy).
+template <bool DUMP>
+__device__ __forceinline__ void side_radiance(const RenderArgs& a, float fx, float fy, bool active, int k, V3& L,
+                                              int& hit_id, bool& amb) {
+  Sample sm;
+  camera_ray_film(a, fx, fy, sm);
+  HitState h;
+  h.t = 3.4e38f; h.id = -1; h.b0 = h.b1 = h.b2 = 0.0f; h.tamb = 3.4e38f;
+  bool dummy = false;
+  trace<false, DUMP>(a.nodes, a.recs, a.F, sm.ray, active, -1, h, dummy);
+  if (DUMP && active && hit_ambiguous(h)) amb = true;
+  hit_id = h.id;
+  Frame fr = {};
+  const bool shaded = active && h.id >= 0 && shading_frame(a, sm, h, fr);
+  if (DUMP && active && h.id >= 0 && fabsf(fr.cos_o) < kFlagCos) amb = true;
+  L = {0.0f, 0.0f, 0.0f};
+  for (int j = 0; j < a.L; ++j) {
+    const LightRec& Lj = a.lights[j];
+    const U4 r = philox((uint32_t)k, 0u, PURPOSE_EDGE + 1u + (uint32_t)j, a.step, a.k0, a.k1);
+    LightSample ls;
+    const bool lit = shaded && light_point(Lj, unit24(r.x), unit24(r.y), fr, ls);
+    if (DUMP && shaded && ls.amb) amb = true;
+    Ray sr;
+    sr.o = fr.x; sr.d = ls.l; sr.tmin = kShadowTmin; sr.tmax = ls.dist;
+    ray_setup(sr);
+    HitState sh;
+    sh.tamb = 3.4e38f;
+    bool occ = false;
+    trace<true, DUMP>(a.nodes, a.recs, a.F, sr, lit, h.id, sh, occ);
+    if (DUMP && lit && sh.tamb < 3.0e38f) amb = true;
+    if (lit && !occ) {
+      float f[3], g1f = 0.0f;
+      brdf_eval<DUMP>(a.variant, a.components, fr, ls, f, g1f);
+      if (DUMP && g1f != 0.0f) amb = true;
+      L.x += Lj.rad[0] * f[0] * ls.geom;
+      L.y += Lj.rad[1] * f[1] * ls.geom;
+      L.z += Lj.rad[2] * f[2] * ls.geom;
+    }
+  }
+}
+
+struct EdgeArgs {
+  const int32_t* edges;
+  const double* cdf;
+  int E, n_samples;
+  double th, aspect;
+  const float* dEdp;
+  float* gverts;
+  float* gcam;
+  int32_t* dbg_rec;     // [n*4]: edge, pixel, hit-, hit+
+  uint8_t* dbg_flag;    // [n]
+};
+
+template <bool DUMP>
+__global__ __launch_bounds__(256) void k_edge_samples(RenderArgs a, EdgeArgs e) {
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  const bool in = k < e.n_samples;
+  const double ltot = e.cdf[e.E - 1];
+  int eid = 0, pid = -1;
+  bool amb = false;
+  float fx = 0.0f, fy = 0.0f, mx = 0.0f, my = 0.0f, u1 = 0.0f;
+  double pax = 0, pay = 0, paz = 1, pbz = 1;
+  if (in && ltot > 0.0) {
+    const U4 r = philox((uint32_t)k, 0u, PURPOSE_EDGE, a.step, a.k0, a.k1);
+    const double target = ((double)k + (double)unit24(r.x)) / (double)e.n_samples * ltot;
+    int lo = 0, hi = e.E - 1;          // first e with cdf[e] > target
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (e.cdf[mid] > target) hi = mid; else lo = mid + 1;
+    }
+    eid = lo;
+    const double c1 = e.cdf[eid], c0 = eid > 0 ? e.cdf[eid - 1] : 0.0;
+    if (fabs(target - c0) < 1e-9 * ltot || fabs(target - c1) < 1e-9 * ltot) amb = true;
+    const int va = e.edges[2 * eid], vb = e.edges[2 * eid + 1];
+    const FilmD pa = project_d(a.cam, e.th, e.aspect, a.W, a.H, a.verts[3 * va], a.verts[3 * va + 1], a.verts[3 * va + 2]);
+    const FilmD pb = project_d(a.cam, e.th, e.aspect, a.W, a.H, a.verts[3 * vb], a.verts[3 * vb + 1], a.verts[3 * vb + 2]);
+    const double u = (double)unit24(r.y);
+    const double yx = pa.x + u * (pb.x - pa.x), yy = pa.y + u * (pb.y - pa.y);
+    const double lx = pb.x - pa.x, ly = pb.y - pa.y, ll = hypot(lx, ly);
+    mx = (float)(-ly / ll);
+    my = (float)(lx / ll);
+    fx = (float)yx;
+    fy = (float)yy;
+    const int pxi = (int)floor(yx), pyi = (int)floor(yy);
+    if (pxi >= 0 && pxi < a.W && pyi >= 0 && pyi < a.H) pid = pyi * a.W + pxi;
+    u1 = (float)u;
+    pax = pa.x; pay = pa.y; paz = pa.z; pbz = pb.z;
+  }
+  const bool active = pid >= 0;
+  V3 Lm, Lp;
+  int hm = -1, hp = -1;
+  side_radiance<DUMP>(a, fx - 1e-3f * mx, fy - 1e-3f * my, active, k, Lm, hm, amb);
+  side_radiance<DUMP>(a, fx + 1e-3f * mx, fy + 1e-3f * my, active, k, Lp, hp, amb);
+  if (DUMP && in) {
+    e.dbg_rec[4 * k] = eid; e.dbg_rec[4 * k + 1] = pid; e.dbg_rec[4 * k + 2] = hm; e.dbg_rec[4 * k + 3] = hp;
+    e.dbg_flag[k] = amb ? 1 : 0;
+  }
+  float gcam[12];
+  for (int q = 0; q < 12; ++q) gcam[q] = 0.0f;
+  if (active) {
+    const float dl = (Lm.x - Lp.x) * e.dEdp[3 * pid] + (Lm.y - Lp.y) * e.dEdp[3 * pid + 1] +
+                     (Lm.z - Lp.z) * e.dEdp[3 * pid + 2];
+    const float wgt = (float)(ltot / (double)e.n_samples) * dl;
+    if (wgt != 0.0f) {
+      // film velocity of X(w) = (1 - w) A + w B, w perspective-correct
+      const float w = (float)(((double)u1 / pbz) / ((1.0 - (double)u1) / paz + (double)u1 / pbz));
+      const int va = e.edges[2 * eid], vb = e.edges[2 * eid + 1];
+      const V3 A = ld3(a.verts, va), B = ld3(a.verts, vb);
+      const V3 X = A * (1.0f - w) + B * w;
+      const float* R = a.cam;
+      const V3 dX = {X.x - R[9], X.y - R[10], X.z - R[11]};
+      const V3 pc = {R[0] * dX.x + R[3] * dX.y + R[6] * dX.z, R[1] * dX.x + R[4] * dX.y + R[7] * dX.z,
+                     R[2] * dX.x + R[5] * dX.y + R[8] * dX.z};
+      const float z = -pc.z;
+      const float Ax = (float)(0.5 * a.W / (e.th * e.aspect)), Ay = (float)(0.5 * a.H / e.th);
+      // m . d(film)/d(pc)
+      const V3 gpc = {mx * Ax / z, -my * Ay / z, mx * Ax * pc.x / (z * z) - my * Ay * pc.y / (z * z)};
+      const V3 gX = {R[0] * gpc.x + R[1] * gpc.y + R[2] * gpc.z, R[3] * gpc.x + R[4] * gpc.y + R[5] * gpc.z,
+                     R[6] * gpc.x + R[7] * gpc.y + R[8] * gpc.z};
+      const float sa = wgt * (1.0f - w), sb = wgt * w;
+      if (e.gverts) {
+        atomicAdd(e.gverts + 3 * va, gX.x * sa); atomicAdd(e.gverts + 3 * va + 1, gX.y * sa);
+        atomicAdd(e.gverts + 3 * va + 2, gX.z * sa);
+        atomicAdd(e.gverts + 3 * vb, gX.x * sb); atomicAdd(e.gverts + 3 * vb + 1, gX.y * sb);
+        atomicAdd(e.gverts + 3 * vb + 2, gX.z * sb);
+      }
+      // pc_i = sum_k R[k][i] (X - T)_k  ->  dR[k][i] = (X - T)_k gpc_i ; dT = -R gpc
+      const float gp[3] = {gpc.x, gpc.y, gpc.z}, dd[3] = {dX.x, dX.y, dX.z};
+      for (int kk = 0; kk < 3; ++kk)
+        for (int ii = 0; ii < 3; ++ii) gcam[3 * kk + ii] = wgt * dd[kk] * gp[ii];
+      gcam[9] = -wgt * gX.x; gcam[10] = -wgt * gX.y; gcam[11] = -wgt * gX.z;
+    }
+  }
+  if (e.gcam) {
+    for (int q = 0; q < 12; ++q) {
+      float t = gcam[q];
+      for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+      if (lane == 0 && t != 0.0f) atomicAdd(e.gcam + q, t);
+    }
+  }
+}
+
+void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samples, const fr_grads& g,
+                  int32_t* dbg_rec, uint8_t* dbg_flag, double tan_half, hipStream_t st) {
+  hipLaunchKernelGGL(k_face_front, dim3((m.F + 255) / 256), dim3(256), 0, st, a.verts, m.tris, m.F, a.cam,
+                     m.face_front);
+  const double aspect = (double)a.W / (double)a.H;
+  hipLaunchKernelGGL(k_edge_len, dim3((m.E + 255) / 256), dim3(256), 0, st, a.verts, m.edges, m.edge_faces, m.E,
+                     m.face_front, a.cam, tan_half, aspect, a.W, a.H, m.edge_len);
+  hipLaunchKernelGGL(k_edge_scan, dim3(1), dim3(1024), 0, st, m.edge_len, m.E, m.edge_cdf);
+  EdgeArgs e;
+  e.edges = m.edges; e.cdf = m.edge_cdf; e.E = m.E; e.n_samples = n_samples;
+  e.th = tan_half; e.aspect = aspect; e.dEdp = dEdp; e.gverts = g.verts; e.gcam = g.cam;
+  e.dbg_rec = dbg_rec; e.dbg_flag = dbg_flag;
+  const int blocks = (n_samples + 255) / 256;
+  if (dbg_rec)
+    hipLaunchKernelGGL(k_edge_samples<true>, dim3(blocks), dim3(256), 0, st, a, e);
+  else
+    hipLaunchKernelGGL(k_edge_samples<false>, dim3(blocks), dim3(256), 0, st, a, e);
+}
+
+}  // namespace fr

@@ -1,0 +1,102 @@
+// Host-side view of the device state and the launchers of each kernel file.
+#pragma once
+
+#include <vector>
+
+#include "../../include/fr.h"
+#include "fr_device.h"
+
+namespace fr {
+
+// Device buffers owned by one mesh (topology fixed at creation).
+struct MeshDev {
+  int N = 0, F = 0, E = 0;
+  int32_t* tris = nullptr;          // [F*3]
+  // vertex -> incident faces (CSR), for normals and their adjoint
+  int32_t* vf_off = nullptr;        // [N+1]
+  int32_t* vf_idx = nullptr;        // [3F]
+  float* normals = nullptr;         // [N*3]
+  float* nlen = nullptr;            // [N] length of the unnormalised normal sum
+  float* gnorm = nullptr;           // [N*3] backward scratch: dE/dn
+  // unique edges and their faces, for the boundary term
+  int32_t* edges = nullptr;         // [E*2]
+  int32_t* edge_faces = nullptr;    // [E*2]
+  // BVH
+  BvhNode* nodes = nullptr;         // [max(F-1,1)]
+  TriRec* recs = nullptr;           // [F]
+  int32_t* order = nullptr;         // [F] sorted slot -> triangle id
+  int32_t* node_parent = nullptr;   // [max(F-1,1)]
+  int32_t* leaf_parent = nullptr;   // [F]
+  uint32_t* flags = nullptr;        // [max(F-1,1)]
+  uint32_t* keys[2] = {nullptr, nullptr};
+  int32_t* vals[2] = {nullptr, nullptr};
+  uint32_t* hist = nullptr;         // [256 * ceil(F/1024)]
+  float* partial = nullptr;         // [64*6]
+  float* scene_box = nullptr;       // [6]
+  int32_t* depth = nullptr;         // [2]: depth, validation error count
+  // per-render scratch
+  LightRec* lights = nullptr;       // [light_cap]
+  int light_cap = 0;
+  float* ltmp = nullptr;            // light-gradient partials
+  double* edge_len = nullptr;       // [E] film length of silhouette edges (0 otherwise)
+  double* edge_cdf = nullptr;       // [E] inclusive running sum
+  uint8_t* face_front = nullptr;    // [F]
+  double* scan_part = nullptr;      // [1024]
+  int bvh_depth = -1;
+  int built = 0;
+};
+
+// Per-render constants shared by the forward, backward and edge kernels.
+struct RenderArgs {
+  const BvhNode* nodes;
+  const TriRec* recs;
+  const int32_t* tris;
+  const float* verts;
+  const float* normals;
+  const float* diffuse;
+  const float* specular;
+  const float* roughness;
+  const LightRec* lights;
+  const float* cam;       // [12]
+  int N, F, L;
+  int W, H, S;
+  int tile_w, tile_h, tiles_x, tiles_y, n_tiles;   // wave tiles (S <= 64)
+  int chunks;             // S / 64 when S > 64, else 1
+  int lanes_per_pixel;    // min(S, 64)
+  float tan_half, aspect;
+  uint32_t k0, k1, step;
+  int variant, components;
+  int32_t* dbg_hit;
+  uint8_t* dbg_pflag;
+  uint8_t* dbg_vis;
+  uint64_t* dbg_stats;
+};
+
+// bvh.hip
+int bvh_build(MeshDev& m, const float* d_verts, hipStream_t st, int* depth_out);
+void bvh_refit(MeshDev& m, const float* d_verts, hipStream_t st);
+// model.hip
+void launch_normals(MeshDev& m, const float* d_verts, hipStream_t st);
+void launch_normals_backward(MeshDev& m, const float* d_verts, const float* d_gn, float* d_gv, hipStream_t st);
+void launch_blend(const float* mean, const float* basis, const float* coef, int K, int M, float* out, hipStream_t st);
+void launch_blend_backward(const float* basis, const float* gout, int K, int M, float* gcoef, hipStream_t st);
+void launch_pose(const float* v, int N, const float* pose, float* vw, hipStream_t st);
+void launch_pose_backward(const float* v, int N, const float* pose, const float* gw, float* gv, float* gpose,
+                          hipStream_t st);
+void launch_adam(float* p, const float* g, float* m, float* v, const float* lr, int n, int t, float b1, float b2,
+                 float eps, hipStream_t st);
+void launch_light_setup(const fr_scene& sc, LightRec* out, hipStream_t st);
+void launch_zero(float* p, int n, hipStream_t st);
+void launch_axpy(float* dst, const float* src, int n, hipStream_t st);
+// render.hip
+void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st);
+// loss.hip
+void launch_loss(const float* img, const float* target, int W, int H, int smooth, float* loss, float* dEdp,
+                 double* scratch, float* gtmp, hipStream_t st);
+// backward.hip
+void launch_render_backward(const RenderArgs& a, const float* dEdp, const fr_grads& g, float* gnorm, hipStream_t st);
+// edges.hip
+void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samples, const fr_grads& g,
+                  int32_t* dbg_rec, uint8_t* dbg_flag, double tan_half, hipStream_t st);
+
+}  // namespace fr

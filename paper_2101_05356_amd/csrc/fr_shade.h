@@ -1,0 +1,214 @@
+// Sampling, shading frame and Cook-Torrance BRDF shared by the forward,
+// backward and edge kernels, so that all of them take the same decisions from
+// the same arithmetic.
+//
+// Counters of the Philox generator: (pixel id y*W + x, sample s, purpose,
+// step) with key = 64-bit seed.  Purpose 0: film jitter; 1 + j: point on
+// light j.  Each 32-bit output maps to [0,1) through its top 24 bits.
+#pragma once
+
+#include "fr_kernels.h"
+
+namespace fr {
+
+// ---------------------------------------------------------------------------
+// Wave -> tile mapping
+// ---------------------------------------------------------------------------
+// Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8).
+// The image is cut into strips of 4 tile rows; XCD x walks strips x, x+8,
+// x+16, ... in order, a block covering 4 consecutive tiles of its strip.  Each
+// XCD's L2 then holds the BVH nodes around its current strip, while the load
+// stays balanced because every XCD gets strips from the whole image height.
+__device__ __forceinline__ int wave_tile(const RenderArgs& a) {
+  const int per_strip = a.tiles_x;             // blocks per strip: 4 rows * tiles_x / 4 waves
+  const int b = blockIdx.x;
+  const int x = b & 7, k = b >> 3;
+  const int si = k / per_strip, bi = k - si * per_strip;
+  const int strip = si * 8 + x;
+  const int t = strip * 4 * a.tiles_x + bi * 4 + (threadIdx.x >> 6);
+  return (t / a.tiles_x) < a.tiles_y ? t : -1;
+}
+
+inline int wave_blocks_strips(const RenderArgs& a) {
+  const int strips = (a.tiles_y + 3) / 4;
+  return 8 * a.tiles_x * ((strips + 7) / 8);
+}
+
+struct PixelSample {
+  int px, py, pid, s0;
+  bool valid;
+};
+
+__device__ __forceinline__ PixelSample pixel_sample(const RenderArgs& a, int tile, int lane) {
+  PixelSample p;
+  const int lpp = a.lanes_per_pixel;
+  const int pix = lane / lpp;
+  p.s0 = lane - pix * lpp;
+  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  p.px = tx * a.tile_w + pix % a.tile_w;
+  p.py = ty * a.tile_h + pix / a.tile_w;
+  p.valid = p.px < a.W && p.py < a.H;
+  p.pid = p.valid ? p.py * a.W + p.px : 0;
+  return p;
+}
+
+// Fixed-order butterfly sum over aligned groups of n lanes (n a power of 2).
+__device__ __forceinline__ float group_sum(float x, int n) {
+  for (int off = n >> 1; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// Camera sample
+// ---------------------------------------------------------------------------
+struct Sample {
+  Ray ray;
+  V3 dc;          // camera-space direction (unnormalised)
+  V3 dw;          // R dc (unnormalised)
+  float inv_len;  // 1 / |R dc|
+};
+
+__device__ __forceinline__ void camera_ray_film(const RenderArgs& a, float fx, float fy, Sample& sm) {
+  const float sx = (2.0f * fx / (float)a.W - 1.0f) * a.tan_half * a.aspect;
+  const float sy = (1.0f - 2.0f * fy / (float)a.H) * a.tan_half;
+  const float* R = a.cam;
+  sm.dc = {sx, sy, -1.0f};
+  sm.dw = {R[0] * sx + R[1] * sy - R[2], R[3] * sx + R[4] * sy - R[5], R[6] * sx + R[7] * sy - R[8]};
+  sm.inv_len = 1.0f / sqrtf(dot(sm.dw, sm.dw));
+  sm.ray.o = {R[9], R[10], R[11]};
+  sm.ray.d = sm.dw * sm.inv_len;
+  sm.ray.tmin = 0.0f;
+  sm.ray.tmax = 3.4e38f;
+  ray_setup(sm.ray);
+}
+
+__device__ __forceinline__ void camera_sample(const RenderArgs& a, const PixelSample& ps, int s, Sample& sm) {
+  const U4 r = philox((uint32_t)ps.pid, (uint32_t)s, PURPOSE_JITTER, a.step, a.k0, a.k1);
+  camera_ray_film(a, (float)ps.px + unit24(r.x), (float)ps.py + unit24(r.y), sm);
+}
+
+// ---------------------------------------------------------------------------
+// Shading frame at the hit
+// ---------------------------------------------------------------------------
+struct Frame {
+  V3 x, ns, wo, c, s;
+  V3 m;            // unnormalised interpolated normal
+  float inv_m;     // 1 / |m|
+  float r;         // clamped roughness
+  bool r_free;     // roughness inside the clamp range (gradient passes)
+  float cos_o;
+  int vi[3];
+  float b[3];
+};
+
+__device__ __forceinline__ bool shading_frame(const RenderArgs& a, const Sample& sm, const HitState& h, Frame& f) {
+  const int* t = a.tris + 3 * h.id;
+  f.vi[0] = t[0]; f.vi[1] = t[1]; f.vi[2] = t[2];
+  f.b[0] = h.b0; f.b[1] = h.b1; f.b[2] = h.b2;
+  const V3 v0 = ld3(a.verts, f.vi[0]), v1 = ld3(a.verts, f.vi[1]), v2 = ld3(a.verts, f.vi[2]);
+  f.x = v0 * h.b0 + v1 * h.b1 + v2 * h.b2;
+  const V3 n0 = ld3(a.normals, f.vi[0]), n1 = ld3(a.normals, f.vi[1]), n2 = ld3(a.normals, f.vi[2]);
+  f.m = n0 * h.b0 + n1 * h.b1 + n2 * h.b2;
+  f.inv_m = 1.0f / sqrtf(dot(f.m, f.m));
+  f.ns = f.m * f.inv_m;
+  f.wo = {-sm.ray.d.x, -sm.ray.d.y, -sm.ray.d.z};
+  f.c = ld3(a.diffuse, f.vi[0]) * h.b0 + ld3(a.diffuse, f.vi[1]) * h.b1 + ld3(a.diffuse, f.vi[2]) * h.b2;
+  f.s = ld3(a.specular, f.vi[0]) * h.b0 + ld3(a.specular, f.vi[1]) * h.b1 + ld3(a.specular, f.vi[2]) * h.b2;
+  const float r = a.roughness[f.vi[0]] * h.b0 + a.roughness[f.vi[1]] * h.b1 + a.roughness[f.vi[2]] * h.b2;
+  f.r_free = r >= kRoughMin && r <= kRoughMax;
+  f.r = fminf(fmaxf(r, kRoughMin), kRoughMax);
+  f.cos_o = dot(f.ns, f.wo);
+  return f.cos_o > 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Light sample
+// ---------------------------------------------------------------------------
+struct LightSample {
+  float w1, w2;
+  V3 q, l;
+  float dist, dist2, cos_s, cos_a, geom;
+  bool amb;
+};
+
+// Uniform point on the light from two uniforms: parallelogram (u0, u1);
+// triangle (sqrt(u0)(1 - u1), sqrt(u0) u1).
+__device__ __forceinline__ void light_weights(int shape, float u0, float u1, float& w1, float& w2) {
+  if (shape == FR_LIGHT_TRIANGLE) {
+    const float su = sqrtf(u0);
+    w1 = su * (1.0f - u1);
+    w2 = su * u1;
+  } else {
+    w1 = u0;
+    w2 = u1;
+  }
+}
+
+// Returns true when light j contributes to this shading point before
+// visibility: n_s . l > 0 and -n_j . l > 0 (the caller already required
+// n_s . o > 0).  geom = (n_s . l) A_j (-n_j . l) / |q - x|^2.
+__device__ __forceinline__ bool light_point(const LightRec& Lj, float u0, float u1, const Frame& f, LightSample& ls) {
+  light_weights(Lj.shape, u0, u1, ls.w1, ls.w2);
+  ls.q = {Lj.p0[0] + Lj.e1[0] * ls.w1 + Lj.e2[0] * ls.w2, Lj.p0[1] + Lj.e1[1] * ls.w1 + Lj.e2[1] * ls.w2,
+          Lj.p0[2] + Lj.e1[2] * ls.w1 + Lj.e2[2] * ls.w2};
+  const V3 dq = ls.q - f.x;
+  ls.dist2 = dot(dq, dq);
+  ls.dist = sqrtf(ls.dist2);
+  ls.l = dq * (1.0f / ls.dist);
+  ls.cos_s = dot(f.ns, ls.l);
+  ls.cos_a = Lj.na[0] * ls.l.x + Lj.na[1] * ls.l.y + Lj.na[2] * ls.l.z;
+  ls.geom = ls.cos_s * ls.cos_a / ls.dist2;
+  const float alen = sqrtf(Lj.na[0] * Lj.na[0] + Lj.na[1] * Lj.na[1] + Lj.na[2] * Lj.na[2]);
+  ls.amb = fabsf(ls.cos_s) < kFlagCos || fabsf(ls.cos_a) < kFlagCos * alen;
+  return ls.cos_s > 0.0f && ls.cos_a > 0.0f;
+}
+
+__device__ __forceinline__ bool light_sample(const RenderArgs& a, int pid, int s, int j, const LightRec& Lj,
+                                             const Frame& f, LightSample& ls) {
+  const U4 r = philox((uint32_t)pid, (uint32_t)s, 1u + (uint32_t)j, a.step, a.k0, a.k1);
+  return light_point(Lj, unit24(r.x), unit24(r.y), f, ls);
+}
+
+// ---------------------------------------------------------------------------
+// Cook-Torrance BRDF (Appendix A), both readings of D and F.
+// ---------------------------------------------------------------------------
+// Walter et al.'s rational G1 with a = n.v / (r sqrt(1 - (n.v)^2)).
+template <bool DUMP>
+__device__ __forceinline__ float smith_g1(float nv, float hv, float r, float& flag) {
+  if (!(hv / nv > 0.0f)) return 0.0f;
+  const float s2 = 1.0f - nv * nv;
+  if (s2 <= 0.0f) return 1.0f;
+  const float a = nv / (r * sqrtf(s2));
+  if (DUMP && fabsf(a - 1.6f) < kFlagG1 * 1.6f) flag = 1.0f;
+  if (a < 1.6f) return (3.535f * a + 2.181f * a * a) / (1.0f + 2.276f * a + 2.577f * a * a);
+  return 1.0f;
+}
+
+template <bool DUMP>
+__device__ __forceinline__ void brdf_eval(int variant, int components, const Frame& f, const LightSample& ls, float out[3],
+                                          float& flag) {
+  out[0] = out[1] = out[2] = 0.0f;
+  if (components & 1) {
+    out[0] = f.c.x * (1.0f / kPi);
+    out[1] = f.c.y * (1.0f / kPi);
+    out[2] = f.c.z * (1.0f / kPi);
+  }
+  if (components & 2) {
+    V3 hv = ls.l + f.wo;
+    hv = hv * (1.0f / sqrtf(dot(hv, hv)));
+    const float nh = dot(f.ns, hv);
+    const float ex = 2.0f / f.r - 2.0f;
+    const float nd = variant == FR_BRDF_NORMALIZED ? 1.0f / (kPi * f.r) : (2.0f / f.r + 2.0f) / (2.0f * kPi);
+    const float D = nd * powf(nh, ex);
+    const float oh = dot(f.wo, hv), lh = dot(ls.l, hv);
+    const float G = smith_g1<DUMP>(f.cos_o, oh, f.r, flag) * smith_g1<DUMP>(ls.cos_s, lh, f.r, flag);
+    const float om = 1.0f - oh;
+    const float fw = variant == FR_BRDF_NORMALIZED ? om * om * om * om * om : om;
+    const float spec = D * G / (4.0f * f.cos_o * ls.cos_s);
+    out[0] += (f.s.x + (1.0f - f.s.x) * fw) * spec;
+    out[1] += (f.s.y + (1.0f - f.s.y) * fw) * spec;
+    out[2] += (f.s.z + (1.0f - f.s.z) * fw) * spec;
+  }
+}
+
+}  // namespace fr

@@ -1,0 +1,295 @@
+// Morphable blend (Sec. 3.1, 3.2), rigid pose, vertex normals, Adam
+// (Sec. 5), light records, and their adjoints.
+#include "fr_kernels.h"
+
+namespace fr {
+
+static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// Vertex normals: n_i = N_i / |N_i|, N_i = sum over incident faces of
+// (v1 - v0) x (v2 - v0), gathered per vertex through the vertex->face CSR
+// (no atomics, fixed order).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ V3 face_normal(const float* __restrict__ v, const int32_t* __restrict__ tris, int f) {
+  const V3 a = ld3(v, tris[3 * f]), b = ld3(v, tris[3 * f + 1]), c = ld3(v, tris[3 * f + 2]);
+  return cross(b - a, c - a);
+}
+
+__global__ __launch_bounds__(256) void k_normals(const float* __restrict__ v, const int32_t* __restrict__ tris,
+                                                 const int32_t* __restrict__ off, const int32_t* __restrict__ idx, int N,
+                                                 float* __restrict__ n, float* __restrict__ nlen) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  V3 acc = {0.0f, 0.0f, 0.0f};
+  for (int k = off[i]; k < off[i + 1]; ++k) acc = acc + face_normal(v, tris, idx[k]);
+  const float len = sqrtf(dot(acc, acc));
+  const float inv = 1.0f / len;
+  n[3 * i] = acc.x * inv; n[3 * i + 1] = acc.y * inv; n[3 * i + 2] = acc.z * inv;
+  nlen[i] = len;
+}
+
+// g_N_i = (I - n n^T) g_n_i / |N_i|, written in place over g_n.
+__global__ __launch_bounds__(256) void k_normals_bwd_project(const float* __restrict__ n, const float* __restrict__ nlen,
+                                                             int N, float* __restrict__ g) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const V3 nn = ld3(n, i), gg = ld3(g, i);
+  const float d = dot(nn, gg);
+  const float inv = 1.0f / nlen[i];
+  g[3 * i] = (gg.x - nn.x * d) * inv;
+  g[3 * i + 1] = (gg.y - nn.y * d) * inv;
+  g[3 * i + 2] = (gg.z - nn.z * d) * inv;
+}
+
+// For face f with N_f = a x b (a = v1 - v0, b = v2 - v0) and gN = sum of the
+// projected gradients of its three vertices: g_a = b x gN, g_b = gN x a;
+// vertex 1 gets g_a, vertex 2 gets g_b, vertex 0 gets -(g_a + g_b).
+__global__ __launch_bounds__(256) void k_normals_bwd_gather(const float* __restrict__ v, const int32_t* __restrict__ tris,
+                                                            const int32_t* __restrict__ off,
+                                                            const int32_t* __restrict__ idx, int N,
+                                                            const float* __restrict__ gN, float* __restrict__ gv) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  V3 acc = {0.0f, 0.0f, 0.0f};
+  for (int k = off[i]; k < off[i + 1]; ++k) {
+    const int f = idx[k];
+    const int i0 = tris[3 * f], i1 = tris[3 * f + 1], i2 = tris[3 * f + 2];
+    const V3 g = ld3(gN, i0) + ld3(gN, i1) + ld3(gN, i2);
+    const V3 p0 = ld3(v, i0);
+    const V3 a = ld3(v, i1) - p0, b = ld3(v, i2) - p0;
+    const V3 ga = cross(b, g), gb = cross(g, a);
+    if (i == i0) acc = acc - (ga + gb);
+    else if (i == i1) acc = acc + ga;
+    else acc = acc + gb;
+  }
+  gv[3 * i] += acc.x; gv[3 * i + 1] += acc.y; gv[3 * i + 2] += acc.z;
+}
+
+void launch_normals(MeshDev& m, const float* d_verts, hipStream_t st) {
+  hipLaunchKernelGGL(k_normals, dim3(cdiv(m.N, 256)), dim3(256), 0, st, d_verts, m.tris, m.vf_off, m.vf_idx, m.N,
+                     m.normals, m.nlen);
+}
+
+void launch_normals_backward(MeshDev& m, const float* d_verts, const float* d_gn, float* d_gv, hipStream_t st) {
+  // d_gn is the mesh's own scratch (m.gnorm) and is projected in place
+  hipLaunchKernelGGL(k_normals_bwd_project, dim3(cdiv(m.N, 256)), dim3(256), 0, st, m.normals, m.nlen, m.N,
+                     const_cast<float*>(d_gn));
+  hipLaunchKernelGGL(k_normals_bwd_gather, dim3(cdiv(m.N, 256)), dim3(256), 0, st, d_verts, m.tris, m.vf_off,
+                     m.vf_idx, m.N, d_gn, d_gv);
+}
+
+// ---------------------------------------------------------------------------
+// Morphable blend: out = mean + sum_k coef_k basis_k (component-major basis).
+// HBM-bound GEMV: consecutive threads own consecutive outputs, so every basis
+// row is streamed with fully coalesced loads; coefficients are wave-uniform
+// scalar loads.  Accumulation order k = 0..K-1.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_blend(const float* __restrict__ mean, const float* __restrict__ basis,
+                                               const float* __restrict__ coef, int K, int M, float* __restrict__ out) {
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  if (m >= M) return;
+  float acc = mean[m];
+  for (int k = 0; k < K; ++k) acc = fmaf(coef[k], __builtin_nontemporal_load(basis + (size_t)k * M + m), acc);
+  out[m] = acc;
+}
+
+// gcoef[k] += sum_m basis[k][m] gout[m]: one block per component, fixed-order
+// tree reduction (deterministic).
+__global__ __launch_bounds__(1024) void k_blend_bwd(const float* __restrict__ basis, const float* __restrict__ gout,
+                                                    int M, float* __restrict__ gcoef) {
+  __shared__ float red[1024];
+  const int k = blockIdx.x;
+  const float* row = basis + (size_t)k * M;
+  float acc = 0.0f;
+  for (int m = threadIdx.x; m < M; m += 1024) acc = fmaf(row[m], gout[m], acc);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gcoef[k] += red[0];
+}
+
+void launch_blend(const float* mean, const float* basis, const float* coef, int K, int M, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_blend, dim3(cdiv(M, 256)), dim3(256), 0, st, mean, basis, coef, K, M, out);
+}
+
+void launch_blend_backward(const float* basis, const float* gout, int K, int M, float* gcoef, hipStream_t st) {
+  hipLaunchKernelGGL(k_blend_bwd, dim3(K), dim3(1024), 0, st, basis, gout, M, gcoef);
+}
+
+// ---------------------------------------------------------------------------
+// Rigid pose: R = Rz(rz) Ry(ry) Rx(rx), vw = R v + t.
+// ---------------------------------------------------------------------------
+struct Rot { float m[9]; };
+
+__device__ __forceinline__ void elem_rot(int axis, float ang, bool deriv, float out[9]) {
+  const float c = cosf(ang), s = sinf(ang);
+  for (int i = 0; i < 9; ++i) out[i] = 0.0f;
+  // rotation about `axis` (or its derivative w.r.t. the angle)
+  const int a = (axis + 1) % 3, b = (axis + 2) % 3;
+  if (!deriv) {
+    out[axis * 3 + axis] = 1.0f;
+    out[a * 3 + a] = c; out[a * 3 + b] = -s;
+    out[b * 3 + a] = s; out[b * 3 + b] = c;
+  } else {
+    out[a * 3 + a] = -s; out[a * 3 + b] = -c;
+    out[b * 3 + a] = c; out[b * 3 + b] = -s;
+  }
+}
+
+__device__ __forceinline__ void mat3_mul(const float A[9], const float B[9], float C[9]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+// R and optionally the three dR/d(angle).
+__device__ void pose_matrices(const float* p, float R[9], float dR[3][9], bool want_d) {
+  float X[9], Y[9], Z[9], T[9];
+  elem_rot(0, p[0], false, X);
+  elem_rot(1, p[1], false, Y);
+  elem_rot(2, p[2], false, Z);
+  mat3_mul(Z, Y, T);
+  mat3_mul(T, X, R);
+  if (want_d) {
+    float D[9], U[9];
+    elem_rot(0, p[0], true, D);  mat3_mul(T, D, dR[0]);                    // Rz Ry dRx
+    elem_rot(1, p[1], true, D);  mat3_mul(Z, D, U); mat3_mul(U, X, dR[1]);  // Rz dRy Rx
+    elem_rot(2, p[2], true, D);  mat3_mul(D, Y, U); mat3_mul(U, X, dR[2]);  // dRz Ry Rx
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pose(const float* __restrict__ v, int N, const float* __restrict__ pose,
+                                              float* __restrict__ vw) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  float R[9], dR[3][9];
+  pose_matrices(pose, R, dR, false);
+  const V3 p = ld3(v, i);
+  vw[3 * i] = R[0] * p.x + R[1] * p.y + R[2] * p.z + pose[3];
+  vw[3 * i + 1] = R[3] * p.x + R[4] * p.y + R[5] * p.z + pose[4];
+  vw[3 * i + 2] = R[6] * p.x + R[7] * p.y + R[8] * p.z + pose[5];
+}
+
+__global__ __launch_bounds__(256) void k_pose_bwd_v(int N, const float* __restrict__ pose, const float* __restrict__ gw,
+                                                    float* __restrict__ gv) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  float R[9], dR[3][9];
+  pose_matrices(pose, R, dR, false);
+  const V3 g = ld3(gw, i);
+  gv[3 * i] += R[0] * g.x + R[3] * g.y + R[6] * g.z;
+  gv[3 * i + 1] += R[1] * g.x + R[4] * g.y + R[7] * g.z;
+  gv[3 * i + 2] += R[2] * g.x + R[5] * g.y + R[8] * g.z;
+}
+
+// One block: gR = sum_i gw_i v_i^T, gt = sum_i gw_i, then the chain rule
+// through the Euler angles.
+__global__ __launch_bounds__(1024) void k_pose_bwd_p(const float* __restrict__ v, int N, const float* __restrict__ pose,
+                                                     const float* __restrict__ gw, float* __restrict__ gpose) {
+  __shared__ float red[12][1024];
+  float acc[12];
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0f;
+  for (int i = threadIdx.x; i < N; i += 1024) {
+    const V3 g = ld3(gw, i), p = ld3(v, i);
+    acc[0] += g.x * p.x; acc[1] += g.x * p.y; acc[2] += g.x * p.z;
+    acc[3] += g.y * p.x; acc[4] += g.y * p.y; acc[5] += g.y * p.z;
+    acc[6] += g.z * p.x; acc[7] += g.z * p.y; acc[8] += g.z * p.z;
+    acc[9] += g.x; acc[10] += g.y; acc[11] += g.z;
+  }
+  for (int k = 0; k < 12; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int k = 0; k < 12; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    float R[9], dR[3][9];
+    pose_matrices(pose, R, dR, true);
+    for (int a = 0; a < 3; ++a) {
+      float s = 0.0f;
+      for (int k = 0; k < 9; ++k) s += red[k][0] * dR[a][k];
+      gpose[a] += s;
+    }
+    gpose[3] += red[9][0]; gpose[4] += red[10][0]; gpose[5] += red[11][0];
+  }
+}
+
+void launch_pose(const float* v, int N, const float* pose, float* vw, hipStream_t st) {
+  hipLaunchKernelGGL(k_pose, dim3(cdiv(N, 256)), dim3(256), 0, st, v, N, pose, vw);
+}
+
+void launch_pose_backward(const float* v, int N, const float* pose, const float* gw, float* gv, float* gpose,
+                          hipStream_t st) {
+  if (gv) hipLaunchKernelGGL(k_pose_bwd_v, dim3(cdiv(N, 256)), dim3(256), 0, st, N, pose, gw, gv);
+  if (gpose) hipLaunchKernelGGL(k_pose_bwd_p, dim3(1), dim3(1024), 0, st, v, N, pose, gw, gpose);
+}
+
+// ---------------------------------------------------------------------------
+// Adam
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, const float* __restrict__ lr, int n, float b1,
+                                              float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr[i] * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+void launch_adam(float* p, const float* g, float* m, float* v, const float* lr, int n, int t, float b1, float b2,
+                 float eps, hipStream_t st) {
+  const float c1 = (float)(1.0 - std::pow((double)b1, (double)t));
+  const float c2 = (float)(1.0 - std::pow((double)b2, (double)t));
+  hipLaunchKernelGGL(k_adam, dim3(cdiv(n, 256)), dim3(256), 0, st, p, g, m, v, lr, n, b1, b2, eps, c1, c2);
+}
+
+// ---------------------------------------------------------------------------
+// Light records: na = -kappa (e1 x e2), kappa = 1 or 1/2.
+// ---------------------------------------------------------------------------
+__global__ void k_light_setup(const float* __restrict__ p0, const float* __restrict__ e1, const float* __restrict__ e2,
+                              const float* __restrict__ rad, const int32_t* __restrict__ shape, int L,
+                              LightRec* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= L) return;
+  LightRec r;
+  const V3 a = ld3(e1, j), b = ld3(e2, j);
+  const V3 n = cross(a, b);
+  const float kappa = shape[j] == FR_LIGHT_TRIANGLE ? 0.5f : 1.0f;
+  for (int k = 0; k < 3; ++k) { r.p0[k] = p0[3 * j + k]; r.e1[k] = e1[3 * j + k]; r.e2[k] = e2[3 * j + k]; r.rad[k] = rad[3 * j + k]; }
+  r.na[0] = -kappa * n.x; r.na[1] = -kappa * n.y; r.na[2] = -kappa * n.z;
+  r.shape = shape[j];
+  out[j] = r;
+}
+
+void launch_light_setup(const fr_scene& sc, LightRec* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_light_setup, dim3(cdiv(sc.n_lights, 64)), dim3(64), 0, st, sc.light_p0, sc.light_e1,
+                     sc.light_e2, sc.light_rad, sc.light_shape, sc.n_lights, out);
+}
+
+__global__ void k_zero_f32(float* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
+__global__ void k_axpy(float* __restrict__ dst, const float* __restrict__ src, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] += src[i];
+}
+
+void launch_zero(float* p, int n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_zero_f32, dim3(cdiv(n, 256)), dim3(256), 0, st, p, n);
+}
+
+void launch_axpy(float* dst, const float* src, int n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_axpy, dim3(cdiv(n, 256)), dim3(256), 0, st, dst, src, n);
+}
+
+}  // namespace fr

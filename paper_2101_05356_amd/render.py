@@ -1,0 +1,287 @@
+"""Torch-facing wrappers of the C ABI (include/fr.h).
+
+PyTorch provides device memory and the stream; every computation happens in
+libfr.so.  Tensors must be contiguous float32 (int32 where stated) on the
+library's device.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FrGrads, FrRenderOpts, FrScene, check, lib
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _f32(t, device):
+    return torch.as_tensor(np.ascontiguousarray(t), dtype=torch.float32).to(device).contiguous()
+
+
+class _DevArray:
+    """__cuda_array_interface__ view of a device pointer owned by the library."""
+
+    def __init__(self, ptr, shape, typestr="<f4"):
+        self.__cuda_array_interface__ = {"shape": shape, "typestr": typestr, "data": (ptr, True), "version": 3,
+                                         "strides": None}
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise _lib.FrError("no HIP device visible")
+        self.device = device
+        h = ctypes.c_void_p()
+        rc = lib().fr_ctx_create(device, ctypes.byref(h))
+        check(rc, None, "fr_ctx_create")
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().fr_ctx_destroy(self.h)
+            self.h = None
+
+
+class Mesh:
+    def __init__(self, ctx: Context, n_verts: int, tris: np.ndarray):
+        self.ctx = ctx
+        self.n_verts = int(n_verts)
+        self.tris_np = np.ascontiguousarray(tris, dtype=np.int32)
+        self.n_tris = self.tris_np.shape[0]
+        h = ctypes.c_void_p()
+        rc = lib().fr_mesh_create(ctx.h, self.n_verts, self.n_tris, self.tris_np.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.byref(h))
+        check(rc, ctx.h, "fr_mesh_create")
+        self.h = h
+        self._verts = None
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().fr_mesh_destroy(self.h)
+            self.h = None
+
+    def update(self, verts: torch.Tensor, rebuild: bool = False):
+        """Normals + BVH over world positions verts [N,3] (kept alive by the mesh)."""
+        assert verts.dtype == torch.float32 and verts.is_contiguous() and verts.numel() == 3 * self.n_verts
+        self._verts = verts
+        mode = _lib.FR_REBUILD if rebuild else _lib.FR_REFIT
+        check(lib().fr_mesh_update(self.h, _p(verts), mode, _stream()), self.ctx.h, "fr_mesh_update")
+
+    def normals(self) -> torch.Tensor:
+        ptr = lib().fr_mesh_normals(self.h)
+        return torch.as_tensor(_DevArray(ptr, (self.n_verts, 3)), device=f"cuda:{self.ctx.device}").clone()
+
+    def edges(self):
+        E = lib().fr_mesh_edges(self.h, None, None)
+        e = np.zeros((E, 2), np.int32)
+        f = np.zeros((E, 2), np.int32)
+        lib().fr_mesh_edges(self.h, e.ctypes.data_as(ctypes.c_void_p), f.ctypes.data_as(ctypes.c_void_p))
+        return e, f
+
+    @property
+    def bvh_depth(self) -> int:
+        return int(lib().fr_mesh_bvh_depth(self.h))
+
+
+@dataclasses.dataclass
+class DeviceScene:
+    """Device copy of a render-level scene (see scenes.Scene)."""
+    verts: torch.Tensor
+    diffuse: torch.Tensor
+    specular: torch.Tensor
+    roughness: torch.Tensor
+    light_p0: torch.Tensor
+    light_e1: torch.Tensor
+    light_e2: torch.Tensor
+    light_rad: torch.Tensor
+    light_shape: torch.Tensor
+    cam: torch.Tensor          # [12]
+    fov_y: float
+    W: int
+    H: int
+    spp: int
+    seed: int
+    step: int = 0
+    target: torch.Tensor | None = None
+
+    @property
+    def n_lights(self) -> int:
+        return int(self.light_p0.shape[0])
+
+    @staticmethod
+    def from_scene(sc, device="cuda") -> "DeviceScene":
+        L = sc.lights
+        cam = np.concatenate([np.asarray(sc.camera.R, np.float32).reshape(9), np.asarray(sc.camera.T, np.float32)])
+        return DeviceScene(
+            verts=_f32(sc.verts, device), diffuse=_f32(sc.diffuse, device), specular=_f32(sc.specular, device),
+            roughness=_f32(sc.roughness, device), light_p0=_f32(L.p0, device), light_e1=_f32(L.e1, device),
+            light_e2=_f32(L.e2, device), light_rad=_f32(L.rad, device),
+            light_shape=torch.as_tensor(np.ascontiguousarray(L.shape, np.int32)).to(device),
+            cam=_f32(cam, device), fov_y=float(sc.camera.fov_y), W=sc.camera.W, H=sc.camera.H, spp=sc.spp,
+            seed=int(sc.seed), step=int(sc.step),
+            target=None if sc.target is None else _f32(sc.target, device))
+
+    def struct(self, verts=None) -> FrScene:
+        s = FrScene()
+        s.width, s.height, s.spp, s.n_lights = self.W, self.H, self.spp, self.n_lights
+        v = self.verts if verts is None else verts
+        (s.verts, s.diffuse, s.specular, s.roughness, s.light_p0, s.light_e1, s.light_e2, s.light_rad,
+         s.light_shape, s.cam) = [t.data_ptr() for t in (v, self.diffuse, self.specular, self.roughness,
+                                                        self.light_p0, self.light_e1, self.light_e2,
+                                                        self.light_rad, self.light_shape, self.cam)]
+        s.fov_y = self.fov_y
+        s.step = self.step
+        s.seed = self.seed
+        return s
+
+
+def _opts(brdf_variant=0, components=3, edge_samples=0, dbg=None) -> FrRenderOpts:
+    o = FrRenderOpts()
+    o.brdf_variant, o.components, o.edge_samples = int(brdf_variant), int(components), int(edge_samples)
+    if dbg is not None:
+        o.dbg_hit = dbg[0].data_ptr() if dbg[0] is not None else None
+        o.dbg_pflag = dbg[1].data_ptr() if dbg[1] is not None else None
+        o.dbg_vis = dbg[2].data_ptr() if dbg[2] is not None else None
+    return o
+
+
+def render_forward(mesh: Mesh, sc: DeviceScene, brdf_variant=0, components=3, dump=False, verts=None, stats=None):
+    """Image [H,W,3]; with dump=True also (hit [H*W,S], pflag [H*W,S], vis [H*W,S,L]).
+    `stats` (a uint64-sized int64 tensor [10], dump only) accumulates traversal counts."""
+    dev = sc.verts.device
+    img = torch.empty((sc.H, sc.W, 3), dtype=torch.float32, device=dev)
+    dbg = None
+    if dump:
+        n = sc.W * sc.H * sc.spp
+        dbg = (torch.full((n,), -7, dtype=torch.int32, device=dev), torch.zeros(n, dtype=torch.uint8, device=dev),
+               torch.full((n * max(sc.n_lights, 1),), 0xEE, dtype=torch.uint8, device=dev))
+    s = sc.struct(verts)
+    o = _opts(brdf_variant, components, 0, dbg)
+    if stats is not None:
+        assert dump and stats.dtype == torch.int64 and stats.numel() == 10
+        o.dbg_stats = stats.data_ptr()
+    check(lib().fr_render_forward(mesh.h, ctypes.byref(s), ctypes.byref(o), _p(img), _stream()), mesh.ctx.h,
+          "fr_render_forward")
+    if not dump:
+        return img
+    S, L = sc.spp, sc.n_lights
+    return img, dbg[0].view(-1, S), dbg[1].view(-1, S), dbg[2].view(-1, S, max(L, 1))
+
+
+def loss(image: torch.Tensor, target: torch.Tensor, smooth: bool = True, want_grad: bool = True):
+    """(E [1], dE/dp [H,W,3] or None)."""
+    H, W = image.shape[:2]
+    out = torch.empty(1, dtype=torch.float32, device=image.device)
+    g = torch.empty_like(image) if want_grad else None
+    check(lib().fr_loss(_p(image), _p(target), W, H, 1 if smooth else 0, _p(out), _p(g), _stream()), None,
+          "fr_loss")
+    return out, g
+
+
+GRAD_GROUPS = ("verts", "normals", "diffuse", "specular", "roughness", "light_geom", "light_rad", "cam")
+
+
+def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_variant=0, components=3,
+                    edge_samples=0, groups=GRAD_GROUPS, verts=None, edge_dump=False):
+    """Gradients (dict of new tensors) of sum dEdp . image."""
+    dev = sc.verts.device
+    N, L = mesh.n_verts, sc.n_lights
+    shapes = dict(verts=(N, 3), normals=(N, 3), diffuse=(N, 3), specular=(N, 3), roughness=(N,),
+                  light_geom=(L, 9), light_rad=(L, 3), cam=(12,))
+    out = {k: torch.zeros(shapes[k], dtype=torch.float32, device=dev) for k in groups}
+    g = FrGrads()
+    for k in GRAD_GROUPS:
+        setattr(g, k, out[k].data_ptr() if k in out else None)
+    dbg = None
+    ns = sc.W * sc.H if edge_samples == -1 else edge_samples
+    if edge_dump and ns > 0:
+        dbg = (torch.full((ns * 4,), -7, dtype=torch.int32, device=dev), torch.zeros(ns, dtype=torch.uint8, device=dev),
+               None)
+    s = sc.struct(verts)
+    o = _opts(brdf_variant, components, edge_samples, dbg)
+    check(lib().fr_render_backward(mesh.h, ctypes.byref(s), ctypes.byref(o), _p(dEdp.contiguous()), ctypes.byref(g),
+                                   _stream()), mesh.ctx.h, "fr_render_backward")
+    if edge_dump and dbg is not None:
+        out["edge_rec"] = dbg[0].view(-1, 4)
+        out["edge_flag"] = dbg[1]
+    return out
+
+
+def blend(mean, basis, coef, out=None):
+    K, M = basis.shape
+    out = torch.empty(M, dtype=torch.float32, device=mean.device) if out is None else out
+    check(lib().fr_blend(_p(mean), _p(basis), _p(coef), K, M, _p(out), _stream()), None, "fr_blend")
+    return out
+
+
+def blend_backward(basis, gout, gcoef):
+    K, M = basis.shape
+    check(lib().fr_blend_backward(_p(basis), _p(gout), K, M, _p(gcoef), _stream()), None, "fr_blend_backward")
+    return gcoef
+
+
+def pose_forward(v, pose, out=None):
+    N = v.numel() // 3
+    out = torch.empty_like(v) if out is None else out
+    check(lib().fr_pose_forward(_p(v), N, _p(pose), _p(out), _stream()), None, "fr_pose_forward")
+    return out
+
+
+def pose_backward(v, pose, gw, gv=None, gpose=None):
+    N = v.numel() // 3
+    check(lib().fr_pose_backward(_p(v), N, _p(pose), _p(gw), _p(gv), _p(gpose), _stream()), None,
+          "fr_pose_backward")
+    return gv, gpose
+
+
+def adam_step(param, grad, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+    check(lib().fr_adam_step(_p(param), _p(grad), _p(m), _p(v), _p(lr), param.numel(), int(t), beta1, beta2, eps,
+                             _stream()), None, "fr_adam_step")
+
+
+class RenderFn(torch.autograd.Function):
+    """(image, loss) = RenderFn.apply(verts, diffuse, specular, roughness, light_p0,
+    light_e1, light_e2, light_rad, cam, mesh, scene, target, opts)
+
+    Forward: normals + BVH refit, render, smoothing + L1 loss (all in libfr).
+    Backward: the fused adjoint kernel (+ boundary term when opts has
+    edge_samples != 0), returning gradients for the nine tensor inputs."""
+
+    @staticmethod
+    def forward(ctx, verts, diffuse, specular, roughness, light_p0, light_e1, light_e2, light_rad, cam, mesh, scene,
+                target, opts):
+        sc = dataclasses.replace(scene, verts=verts.contiguous(), diffuse=diffuse.contiguous(),
+                                 specular=specular.contiguous(), roughness=roughness.contiguous(),
+                                 light_p0=light_p0.contiguous(), light_e1=light_e1.contiguous(),
+                                 light_e2=light_e2.contiguous(), light_rad=light_rad.contiguous(), cam=cam.contiguous())
+        mesh.update(sc.verts, rebuild=opts.get("rebuild", False))
+        img = render_forward(mesh, sc, opts.get("brdf_variant", 0), opts.get("components", 3))
+        E, dEdp = loss(img, target, opts.get("smooth", True))
+        ctx.mesh, ctx.sc, ctx.opts = mesh, sc, opts
+        ctx.save_for_backward(dEdp)
+        ctx.mark_non_differentiable()
+        return img, E
+
+    @staticmethod
+    def backward(ctx, g_img, g_loss):
+        (dEdp,) = ctx.saved_tensors
+        seed = dEdp * g_loss.reshape(1, 1, 1) if g_loss is not None else torch.zeros_like(dEdp)
+        if g_img is not None:
+            seed = seed + g_img
+        o = ctx.opts
+        g = render_backward(ctx.mesh, ctx.sc, seed, o.get("brdf_variant", 0), o.get("components", 3),
+                            o.get("edge_samples", 0),
+                            groups=("verts", "diffuse", "specular", "roughness", "light_geom", "light_rad", "cam"))
+        lg = g["light_geom"]
+        return (g["verts"], g["diffuse"], g["specular"], g["roughness"], lg[:, 0:3].contiguous(),
+                lg[:, 3:6].contiguous(), lg[:, 6:9].contiguous(), g["light_rad"], g["cam"], None, None, None, None)

@@ -1,0 +1,90 @@
+"""Helpers of the GPU parity tests: run the HIP path and the FP64 oracle on the
+same seeded inputs and compare them under the parity contract:
+
+* decisions (closest-hit triangle of every camera sample, visibility code of
+  every shadow ray) are bit-exact except where either side flags the decision
+  as near-ambiguous (within 1e-6 of an edge in FP64; a wider FP32-error band on
+  the GPU);
+* values are compared after the oracle re-evaluates flagged decisions with the
+  GPU's choice: pixels |d| <= 1e-4 max(|p|, 1e-3 max p); gradients per group
+  ||d||_2 <= 1e-4 ||g||_2 and per element |d| <= 1e-4 max(|g|, 1e-2 ||g||_inf).
+"""
+import dataclasses
+
+import numpy as np
+import torch
+
+import oracle
+from paper_2101_05356_amd import render as R
+from paper_2101_05356_amd import scenes
+
+_CTX = None
+
+
+def ctx():
+    global _CTX
+    if _CTX is None:
+        _CTX = R.Context(0)
+    return _CTX
+
+
+def gpu_setup(sc, rebuild=True):
+    m = R.Mesh(ctx(), sc.n_verts, sc.tris)
+    ds = R.DeviceScene.from_scene(sc)
+    m.update(ds.verts, rebuild=rebuild)
+    return m, ds
+
+
+def pixel_rows(W, pixels):
+    return np.arange(W * 0) if pixels is None else np.asarray(pixels)
+
+
+def decisions_compare(sc, gpu_hit, gpu_pflag, gpu_vis, orc, pixels=None):
+    """Compare decisions on unflagged rays; returns (report dict, merged decisions
+    for the oracle replay: oracle's own where unflagged, GPU's where flagged)."""
+    L = sc.lights.count
+    gh = gpu_hit if pixels is None else gpu_hit[pixels]
+    gpf = gpu_pflag if pixels is None else gpu_pflag[pixels]
+    gv = gpu_vis if pixels is None else gpu_vis[pixels]
+    gcode = gv & 0x7F
+    gflag = (gv & 0x80) != 0
+    oh, opf, ov, osf = orc["hit"], orc["pflag"], orc["vis"], orc["sflag"]
+    pflag = (gpf != 0) | (opf != 0)
+    hit_mismatch = (gh != oh) & ~pflag
+    # shadow decisions compare only where the primary decision agrees and is unflagged
+    same_prim = (gh == oh) & ~pflag
+    sflag = gflag | (osf != 0)
+    vis_mismatch = (gcode != ov) & ~sflag & same_prim[:, :, None]
+    merged_hit = np.where(pflag, gh, oh)
+    use_gpu_vis = sflag | pflag[:, :, None]
+    merged_vis = np.where(use_gpu_vis, gcode, ov).astype(np.uint8)
+    rep = dict(n_prim=gh.size, n_shadow=gcode.size,
+               prim_flagged=float(pflag.mean()), shadow_flagged=float(sflag.mean()),
+               hit_mismatch=int(hit_mismatch.sum()), vis_mismatch=int(vis_mismatch.sum()),
+               hit_rate=float((gh >= 0).mean()))
+    return rep, merged_hit, merged_vis
+
+
+def pixel_tol_ok(gpu, ref):
+    gpu = np.asarray(gpu, np.float64).reshape(-1, 3)
+    ref = np.asarray(ref, np.float64).reshape(-1, 3)
+    floor = 1e-3 * np.abs(ref).max()
+    tol = 1e-4 * np.maximum(np.abs(ref), floor)
+    err = np.abs(gpu - ref)
+    return bool(np.all(err <= tol)), float((err / np.maximum(np.abs(ref), floor)).max())
+
+
+def grad_tol_ok(gpu, ref, rel=1e-4, floor_frac=1e-2):
+    gpu = np.asarray(gpu, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    n = np.linalg.norm(ref)
+    if n == 0.0:
+        return bool(np.all(gpu == 0.0)), 0.0, 0.0
+    l2 = float(np.linalg.norm(gpu - ref) / n)
+    floor = floor_frac * np.abs(ref).max()
+    elem = float((np.abs(gpu - ref) / np.maximum(np.abs(ref), floor)).max())
+    return (l2 <= rel and elem <= rel), l2, elem
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()

@@ -1,0 +1,167 @@
+"""Parity of the HIP render path with the FP64 oracle (forward decisions and
+pixels, loss, interior adjoint, boundary term), through the C ABI."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2101_05356_amd import scenes
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _forward_parity(sc, pixels=None, variant=0, components=3):
+    import oracle
+    m, ds = G.gpu_setup(sc)
+    img, hit, pflag, vis = G.R.render_forward(m, ds, brdf_variant=variant, components=components, dump=True)
+    torch.cuda.synchronize()
+    img = G.to_np(img).reshape(-1, 3)
+    hit, pflag, vis = G.to_np(hit), G.to_np(pflag), G.to_np(vis)
+    assert np.all(hit >= -1), "every sample of the dump must be written"
+    assert np.all((vis & 0x7F) <= 3), "every shadow code of the dump must be written"
+    orc = oracle.render(sc, pixels=pixels, brdf_variant=variant, components=components)
+    rep, mh, mv = G.decisions_compare(sc, hit, pflag, vis, orc, pixels)
+    _note(f"decisions: {rep}")
+    assert rep["hit_mismatch"] == 0 and rep["vis_mismatch"] == 0, rep
+    assert rep["prim_flagged"] < 5e-3 and rep["shadow_flagged"] < 5e-3, rep
+    replay = oracle.render(sc, pixels=pixels, force_hit=mh, force_vis=mv, brdf_variant=variant, components=components)
+    gpu_px = img if pixels is None else img[pixels]
+    ok, worst = G.pixel_tol_ok(gpu_px, replay["rgb"])
+    _note(f"pixels: worst relative error {worst:.3e}")
+    assert ok, worst
+    return m, ds, img, hit, vis, mh, mv
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_patch_forward_parity(oracle_lib, variant):
+    sc = scenes.patch_scene()
+    _forward_parity(sc, variant=variant)
+
+
+def test_patch_forward_parity_ragged_and_spp(oracle_lib):
+    """Image sizes that leave partial tiles, and spp 1, 2, 8, 32, 128."""
+    for (W, H, S) in [(37, 23, 1), (31, 17, 2), (19, 29, 8), (13, 11, 32), (9, 7, 128)]:
+        sc = scenes.patch_scene(W=W, H=H, spp=S)
+        _note(f"patch {W}x{H} spp {S}")
+        _forward_parity(sc)
+
+
+def test_face_forward_parity_subset(oracle_lib):
+    sc = scenes.face_render_scene()
+    px = scenes.random_pixel_subset(np.random.default_rng(0), sc.camera.W, sc.camera.H, 48)
+    # include pixels on the silhouette band and the centre
+    px = np.unique(np.concatenate([px, [128 * 256 + 128, 128 * 256 + 30, 60 * 256 + 128]])).astype(np.int32)
+    _forward_parity(sc, pixels=px)
+
+
+def test_diffuse_and_specular_masks(oracle_lib):
+    for comp in (1, 2):
+        _forward_parity(scenes.patch_scene(W=24, H=24, spp=4), components=comp)
+
+
+def test_loss_parity(oracle_lib):
+    import oracle
+    rng = np.random.default_rng(1)
+    for (W, H) in [(64, 64), (37, 23), (1, 5), (256, 256)]:
+        img = rng.uniform(0, 1, (H, W, 3)).astype(np.float32)
+        tgt = rng.uniform(0, 1, (H, W, 3)).astype(np.float32)
+        tgt[0, 0] = img[0, 0]                       # a zero residual without smoothing
+        for smooth in (True, False):
+            E, g = G.R.loss(torch.tensor(img).cuda(), torch.tensor(tgt).cuda(), smooth)
+            Eo, go, ps = oracle.loss_and_grad(img, tgt, smooth)
+            resid = (ps - tgt)
+            amb = np.abs(resid) < 1e-5                # sign decided within FP32 rounding
+            assert abs(float(E.item()) - Eo) <= 1e-5 * Eo
+            gg = G.to_np(g)
+            if not amb.any():
+                assert np.allclose(gg, go, rtol=1e-5, atol=1e-6)
+
+
+def _backward_parity(sc, pixels=None, variant=0, seed=3):
+    import oracle
+    m, ds, img, hit, vis, mh, mv = _forward_parity(sc, pixels=pixels, variant=variant)
+    W, H = sc.camera.W, sc.camera.H
+    rng = np.random.default_rng(seed)
+    dEdp = np.zeros((H * W, 3), np.float32)
+    rows = np.arange(W * H) if pixels is None else pixels
+    dEdp[rows] = rng.normal(size=(len(rows), 3)).astype(np.float32)
+    g = G.R.render_backward(m, ds, torch.tensor(dEdp.reshape(H, W, 3)).cuda(), brdf_variant=variant)
+    torch.cuda.synchronize()
+    go = oracle.grad(sc, mh, mv, dEdp[rows].astype(np.float64), pixels=pixels, brdf_variant=variant)
+    pairs = [("verts", "verts"), ("normals", "normals"), ("diffuse", "diffuse"), ("specular", "specular"),
+             ("roughness", "rough"), ("light_rad", "rad"), ("cam", "cam")]
+    res = {}
+    for gk, ok_ in pairs:
+        res[gk] = G.grad_tol_ok(G.to_np(g[gk]), go[ok_])
+    res["light_geom"] = G.grad_tol_ok(G.to_np(g["light_geom"]), go["light"])
+    _note(f"gradients (ok, l2, worst element): {res}")
+    for k, (ok_, l2, el) in res.items():
+        assert ok_, (k, l2, el)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_patch_backward_parity(oracle_lib, variant):
+    sc = scenes.patch_scene()
+    _backward_parity(sc, variant=variant)
+
+
+def test_face_backward_parity_subset(oracle_lib):
+    sc = scenes.face_render_scene()
+    px = scenes.random_pixel_subset(np.random.default_rng(5), sc.camera.W, sc.camera.H, 32)
+    _backward_parity(sc, pixels=px)
+
+
+def test_refit_matches_rebuild(oracle_lib):
+    """Traversal results do not depend on the BVH: a refit of moved vertices
+    renders bit-identically to a fresh build over the same vertices."""
+    sc = scenes.patch_scene()
+    m, ds = G.gpu_setup(sc)
+    rng = np.random.default_rng(7)
+    moved = (sc.verts + rng.normal(0, 0.01, sc.verts.shape)).astype(np.float32)
+    v = torch.tensor(moved).cuda()
+    m.update(v, rebuild=False)
+    a = G.to_np(G.R.render_forward(m, ds, verts=v))
+    m2, _ = G.gpu_setup(dataclasses.replace(sc, verts=moved))
+    b = G.to_np(G.R.render_forward(m2, ds, verts=v))
+    assert np.array_equal(a, b)
+    assert 0 < m.bvh_depth <= 64
+
+
+def test_edge_term_parity_patch(oracle_lib):
+    import oracle
+    sc = scenes.patch_scene(W=48, H=48, spp=4)
+    m, ds = G.gpu_setup(sc)
+    rng = np.random.default_rng(9)
+    w = rng.normal(size=(48 * 48, 3)).astype(np.float32)
+    ns = 48 * 48
+    g = G.R.render_backward(m, ds, torch.tensor(w.reshape(48, 48, 3)).cuda(), edge_samples=ns,
+                            groups=("cam",), edge_dump=True)
+    torch.cuda.synchronize()
+    rec, fl = G.to_np(g["edge_rec"]), G.to_np(g["edge_flag"])
+    eo = oracle.edge_grad(sc, w.astype(np.float64), ns)
+    flag = (fl != 0) | (eo["flag"] != 0)
+    _note(f"edge samples: {ns}, flagged {flag.mean():.4f}")
+    assert flag.mean() < 0.01
+    assert np.array_equal(rec[~flag], eo["edge"][~flag]), "edge picks, pixels and side hits must match"
+    # gradient: GPU interior-free edge term vs oracle edge term
+    ge = G.R.render_backward(m, ds, torch.tensor(w.reshape(48, 48, 3)).cuda(), edge_samples=ns,
+                             groups=("verts", "cam"))
+    gi = G.R.render_backward(m, ds, torch.tensor(w.reshape(48, 48, 3)).cuda(), edge_samples=0,
+                             groups=("verts", "cam"))
+    torch.cuda.synchronize()
+    gv = G.to_np(ge["verts"]) - G.to_np(gi["verts"])
+    gc = G.to_np(ge["cam"]) - G.to_np(gi["cam"])
+    if not flag.any():
+        okv = G.grad_tol_ok(gv, eo["verts"], rel=2e-4)
+        okc = G.grad_tol_ok(gc, eo["cam"], rel=2e-4)
+        _note(f"edge grads: verts {okv}, cam {okc}")
+        assert okv[1] < 2e-4 and okc[1] < 2e-4
