@@ -91,8 +91,8 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
 
 int ensure_lights(fr_mesh* m, int L) {
   if (L <= m->d.light_cap) return FR_OK;
-  if (m->d.lights) hipFree(m->d.lights);
-  if (m->d.ltmp) hipFree(m->d.ltmp);
+  if (m->d.lights) (void)hipFree(m->d.lights);
+  if (m->d.ltmp) (void)hipFree(m->d.ltmp);
   m->d.lights = nullptr;
   m->d.ltmp = nullptr;
   const int cap = std::max(L, 128);
@@ -206,7 +206,7 @@ int fr_mesh_destroy(fr_mesh* m) {
                   d.hist, d.partial, d.scene_box, d.depth, d.lights, d.ltmp, d.edge_len, d.edge_cdf, d.face_front,
                   d.scan_part, m->loss_scratch, m->loss_gtmp};
   for (void* p : ptrs)
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   delete m;
   return FR_OK;
 }
@@ -272,8 +272,8 @@ int fr_loss(const float* d_image, const float* d_target, int32_t W, int32_t H, i
   static thread_local size_t cap = 0;
   const size_t npx = (size_t)W * H;
   if (npx > cap) {
-    if (scratch) hipFree(scratch);
-    if (gtmp) hipFree(gtmp);
+    if (scratch) (void)hipFree(scratch);
+    if (gtmp) (void)hipFree(gtmp);
     scratch = nullptr; gtmp = nullptr; cap = 0;
     if (dalloc(&scratch, (npx + 255) / 256) != hipSuccess || dalloc(&gtmp, 3 * npx) != hipSuccess)
       return FR_ERR_OOM;

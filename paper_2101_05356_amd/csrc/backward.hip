@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, const float* _
       Sample sm;
       camera_sample(a, ps, s, sm);
       HitState h;
-      h.t = 3.4e38f; h.id = -1; h.b0 = h.b1 = h.b2 = 0.0f; h.tamb = 3.4e38f;
+      h.t = 3.4e38f; h.id = -1; h.tamb = 3.4e38f;
       bool dummy = false;
       trace<false, false>(a.nodes, a.recs, a.F, sm.ray, want, -1, h, dummy);
       Frame fr = {};
@@ -198,16 +198,14 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, const float* _
           gn[k] = gm * fr.b[k];
           gv[k] = gx * fr.b[k];
         }
-        // b0 = 1 - b1 - b2; Moller-Trumbore adjoint of (b1, b2)
+        // b0 = 1 - b1 - b2; Moller-Trumbore adjoint of (b1, b2), solved from
+        // o' = o + t d (t held fixed: g_o += g_o', g_d += t g_o')
         const float g1 = gb[1] - gb[0], g2 = gb[2] - gb[0];
-        const V3 d = sm.ray.d, o = sm.ray.o;
-        const V3 e1 = vv[1] - vv[0], e2 = vv[2] - vv[0];
-        const V3 pv = cross(d, e2);
-        const float det = dot(e1, pv);
-        const float idet = 1.0f / det;
-        const V3 sv = o - vv[0];
-        const V3 qv = cross(sv, e1);
-        const float b1 = dot(sv, pv) * idet, b2 = dot(d, qv) * idet;
+        const V3 d = sm.ray.d;
+        Bary B;
+        bary_solve(sm.ray.o, d, fr.t, vv[0], vv[1], vv[2], B);
+        const V3 e1 = B.e1, e2 = B.e2, pv = B.pv, sv = B.sv, qv = B.qv;
+        const float idet = B.idet, b1 = B.b1, b2 = B.b2;
         const float gA1 = g1 * idet, gA2 = g2 * idet, gdet = -(g1 * b1 + g2 * b2) * idet;
         V3 gsv = pv * gA1, gp = sv * gA1;
         V3 gd = qv * gA2 - gwo;
@@ -221,6 +219,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, const float* _
         gv[0] = gv[0] - gsv - ge1 - ge2;
         gv[1] = gv[1] + ge1;
         gv[2] = gv[2] + ge2;
+        gd = gd + gsv * fr.t;
         // d = dw / |dw|, dw = R dc, o = T
         const V3 gdw = project_out(gd, d, sm.inv_len);
         gcam[0] += gdw.x * sm.dc.x; gcam[1] += gdw.x * sm.dc.y; gcam[2] += gdw.x * sm.dc.z;
@@ -303,7 +302,7 @@ void launch_render_backward(const RenderArgs& a, const float* dEdp, const fr_gra
   const int nl = a.L * 12 + 12;
   const size_t need = (size_t)kSlots * nl;
   if (need > g_slots_cap) {
-    if (g_slots) hipFree(g_slots);
+    if (g_slots) (void)hipFree(g_slots);
     g_slots = nullptr;
     g_slots_cap = 0;
     if (hipMalloc(&g_slots, need * sizeof(float)) != hipSuccess) return;

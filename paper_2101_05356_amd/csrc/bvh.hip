@@ -325,7 +325,8 @@ int bvh_build(MeshDev& m, const float* d_verts, hipStream_t st, int* depth_out) 
     cur ^= 1;
   }
   // after an even number of passes the sorted data is back in buffer 0
-  hipMemcpyAsync(m.order, m.vals[cur], sizeof(int32_t) * F, hipMemcpyDeviceToDevice, st);
+  if (hipMemcpyAsync(m.order, m.vals[cur], sizeof(int32_t) * F, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return FR_ERR_DEVICE;
   if (F > 1) {
     hipLaunchKernelGGL(k_karras, dim3(cdiv(F - 1, 256)), dim3(256), 0, st, m.keys[cur], F, m.nodes, m.node_parent,
                        m.leaf_parent);

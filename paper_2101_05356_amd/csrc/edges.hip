@@ -91,7 +91,7 @@ __device__ __forceinline__ void side_radiance(const RenderArgs& a, float fx, flo
   Sample sm;
   camera_ray_film(a, fx, fy, sm);
   HitState h;
-  h.t = 3.4e38f; h.id = -1; h.b0 = h.b1 = h.b2 = 0.0f; h.tamb = 3.4e38f;
+  h.t = 3.4e38f; h.id = -1; h.tamb = 3.4e38f;
   bool dummy = false;
   trace<false, DUMP>(a.nodes, a.recs, a.F, sm.ray, active, -1, h, dummy);
   if (DUMP && active && hit_ambiguous(h)) amb = true;

@@ -117,28 +117,42 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // ---------------------------------------------------------------------------
 // Rays
 // ---------------------------------------------------------------------------
+// The Woop-Benthin-Wald test maps vertices into a ray frame in which the ray
+// is the +z axis: permute axes so that z is the dominant direction component,
+// then shear.  Here the permutation and shear are folded into one per-lane
+// affine map (rows Mx, My, Mz and offsets -M.o): a sheared coordinate costs
+// three FMAs and no per-lane component selects.  Watertightness is kept: a
+// vertex shared by two triangles gets bitwise the same sheared coordinates in
+// both tests, and an edge function evaluated from the other side is the exact
+// negation (products commute, a - b = -(b - a); FMA contraction is off).
 struct Ray {
   V3 o, d;
   V3 inv;                // 1/d with zero components replaced by +-1e-30 first
   V3 oinv;               // -o * inv (slab test: t = b * inv + oinv)
-  float Sx, Sy, Sz;      // Woop shear constants
-  int kx, ky, kz;        // Woop axis permutation
+  V3 Mx, My, Mz;         // shear rows
+  float cx, cy, cz;      // -(M . o)
   float tmin, tmax;
 };
 
 __device__ __forceinline__ float comp(V3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+__device__ __forceinline__ V3 unit_axis(int k, float s) {
+  return {k == 0 ? s : 0.0f, k == 1 ? s : 0.0f, k == 2 ? s : 0.0f};
+}
 
 __device__ __forceinline__ void ray_setup(Ray& r) {
   const float ax = fabsf(r.d.x), ay = fabsf(r.d.y), az = fabsf(r.d.z);
-  int kz = ax > ay ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+  const int kz = ax > ay ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
   int kx = kz == 2 ? 0 : kz + 1;
   int ky = kx == 2 ? 0 : kx + 1;
   const float dz = comp(r.d, kz);
   if (dz < 0.0f) { const int t = kx; kx = ky; ky = t; }
-  r.kx = kx; r.ky = ky; r.kz = kz;
-  r.Sx = comp(r.d, kx) / dz;
-  r.Sy = comp(r.d, ky) / dz;
-  r.Sz = 1.0f / dz;
+  const float Sx = comp(r.d, kx) / dz, Sy = comp(r.d, ky) / dz, Sz = 1.0f / dz;
+  r.Mx = unit_axis(kx, 1.0f) + unit_axis(kz, -Sx);
+  r.My = unit_axis(ky, 1.0f) + unit_axis(kz, -Sy);
+  r.Mz = unit_axis(kz, Sz);
+  r.cx = -fmaf(r.Mx.x, r.o.x, fmaf(r.Mx.y, r.o.y, r.Mx.z * r.o.z));
+  r.cy = -fmaf(r.My.x, r.o.x, fmaf(r.My.y, r.o.y, r.My.z * r.o.z));
+  r.cz = -fmaf(r.Mz.x, r.o.x, fmaf(r.Mz.y, r.o.y, r.Mz.z * r.o.z));
   const float tiny = 1e-30f;
   const V3 dd = {fabsf(r.d.x) < tiny ? copysignf(tiny, r.d.x) : r.d.x,
                  fabsf(r.d.y) < tiny ? copysignf(tiny, r.d.y) : r.d.y,
@@ -148,8 +162,8 @@ __device__ __forceinline__ void ray_setup(Ray& r) {
 }
 
 // Slab test of one (wave-uniform) box against this lane's ray; returns the
-// entry distance in tnear.  The exit distance is widened by 2^-21 relative
-// (robust traversal in the spirit of Ize 2013) and boxes are padded at refit.
+// entry distance in tnear.  Branch-free.  Boxes are padded by kBoxPad at refit,
+// which covers the rounding of the plane distances (conservative traversal).
 __device__ __forceinline__ bool slab(const Ray& r, const float* b, float tmax, float& tnear) {
   const float tx0 = fmaf(b[0], r.inv.x, r.oinv.x), tx1 = fmaf(b[3], r.inv.x, r.oinv.x);
   const float ty0 = fmaf(b[1], r.inv.y, r.oinv.y), ty1 = fmaf(b[4], r.inv.y, r.oinv.y);
@@ -157,25 +171,25 @@ __device__ __forceinline__ bool slab(const Ray& r, const float* b, float tmax, f
   const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), r.tmin));
   const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax));
   tnear = tn;
-  return tn <= tf * 1.00000048f;
+  return tn <= tf;
 }
 
-// Woop-Benthin-Wald watertight test of this lane's ray against a triangle.
-// On a hit within (tmin, tmax): t and barycentrics (b0 for v0, b1, b2).
-// `amb_t` (dump builds only) is lowered to the crossing distance when the ray
-// passes within the ambiguity band of the triangle boundary, or crosses it
-// within kFlagT of tmin / tmax (0 for grazing rays, whose distance is
-// ill-conditioned).
+__device__ __forceinline__ float shear(const V3& M, float c, float x, float y, float z) {
+  return fmaf(x, M.x, fmaf(y, M.y, fmaf(z, M.z, c)));
+}
+
+// Watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013) of this
+// lane's ray against a (wave-uniform) triangle v[9].  Accepts crossings with
+// t in (tmin, tmax) by comparing T against tmin*det and tmax*det (no division);
+// on acceptance t = T/det.  `amb_t` (dump builds only) is lowered to the
+// crossing distance when the ray passes within the ambiguity band of the
+// triangle boundary, or crosses it within kFlagT of tmin / tmax (0 for grazing
+// rays, whose distance is ill-conditioned).
 template <bool DUMP>
-__device__ __forceinline__ bool tri_test(const Ray& r, const float* v, float tmax, float& t, float& b0, float& b1,
-                                         float& b2, float& amb_t) {
-  const V3 A = {v[0] - r.o.x, v[1] - r.o.y, v[2] - r.o.z};
-  const V3 B = {v[3] - r.o.x, v[4] - r.o.y, v[5] - r.o.z};
-  const V3 C = {v[6] - r.o.x, v[7] - r.o.y, v[8] - r.o.z};
-  const float Akz = comp(A, r.kz), Bkz = comp(B, r.kz), Ckz = comp(C, r.kz);
-  const float Ax = comp(A, r.kx) - r.Sx * Akz, Ay = comp(A, r.ky) - r.Sy * Akz;
-  const float Bx = comp(B, r.kx) - r.Sx * Bkz, By = comp(B, r.ky) - r.Sy * Bkz;
-  const float Cx = comp(C, r.kx) - r.Sx * Ckz, Cy = comp(C, r.ky) - r.Sy * Ckz;
+__device__ __forceinline__ bool tri_test(const Ray& r, const float* v, float tmax, float& t, float& amb_t) {
+  const float Ax = shear(r.Mx, r.cx, v[0], v[1], v[2]), Ay = shear(r.My, r.cy, v[0], v[1], v[2]);
+  const float Bx = shear(r.Mx, r.cx, v[3], v[4], v[5]), By = shear(r.My, r.cy, v[3], v[4], v[5]);
+  const float Cx = shear(r.Mx, r.cx, v[6], v[7], v[8]), Cy = shear(r.My, r.cy, v[6], v[7], v[8]);
   float U = Cx * By - Cy * Bx;
   float V = Ax * Cy - Ay * Cx;
   float W = Bx * Ay - By * Ax;
@@ -184,8 +198,11 @@ __device__ __forceinline__ bool tri_test(const Ray& r, const float* v, float tma
     V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
     W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
   }
-  const float Az = r.Sz * Akz, Bz = r.Sz * Bkz, Cz = r.Sz * Ckz;
+  const float Az = shear(r.Mz, r.cz, v[0], v[1], v[2]);
+  const float Bz = shear(r.Mz, r.cz, v[3], v[4], v[5]);
+  const float Cz = shear(r.Mz, r.cz, v[6], v[7], v[8]);
   const float det = U + V + W;
+  const float T = U * Az + V * Bz + W * Cz;
   if (DUMP) {
     // distance (in the sheared plane) of the ray from each edge line
     const float lU = sqrtf((Bx - Cx) * (Bx - Cx) + (By - Cy) * (By - Cy));
@@ -193,8 +210,7 @@ __device__ __forceinline__ bool tri_test(const Ray& r, const float* v, float tma
     const float lW = sqrtf((Ax - Bx) * (Ax - Bx) + (Ay - By) * (Ay - By));
     const float sg = det < 0.0f ? -1.0f : 1.0f;
     const float dU = sg * U / fmaxf(lU, 1e-30f), dV = sg * V / fmaxf(lV, 1e-30f), dW = sg * W / fmaxf(lW, 1e-30f);
-    const float Traw = U * Az + V * Bz + W * Cz;
-    const float tc = det != 0.0f ? Traw / det : 0.0f;
+    const float tc = det != 0.0f ? T / det : 0.0f;
     const float band = kFlagDist + kFlagDistT * fmaxf(fabsf(tc), 1.0f);
     const bool inside_ish = dU > -band && dV > -band && dW > -band;
     const bool at_edge = fminf(fabsf(dU), fminf(fabsf(dV), fabsf(dW))) < band;
@@ -207,20 +223,23 @@ __device__ __forceinline__ bool tri_test(const Ray& r, const float* v, float tma
   }
   if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
   if (det == 0.0f) return false;
-  const float T = U * Az + V * Bz + W * Cz;
-  const float rcp = 1.0f / det;
-  const float tt = T * rcp;
-  if (!(tt > r.tmin && tt < tmax)) return false;
-  t = tt;
-  b0 = U * rcp; b1 = V * rcp; b2 = W * rcp;
+  const bool in_range = det > 0.0f ? (T > r.tmin * det && T < tmax * det) : (T < r.tmin * det && T > tmax * det);
+  if (!in_range) return false;
+  t = T / det;
   return true;
 }
 
 struct HitState {
-  float t, b0, b1, b2;
+  float t;
   int id;
   float tamb;    // dump builds: nearest ambiguous crossing (+inf if none)
 };
+
+// Closest-hit decision is ambiguous when an ambiguous crossing was recorded
+// at or before the hit (or anywhere, for a miss).
+__device__ __forceinline__ bool hit_ambiguous(const HitState& h) {
+  return h.tamb < 3.0e38f && (h.id < 0 || h.tamb <= h.t + kFlagT);
+}
 
 // Traversal statistics of dump builds.  Lane counts: child boxes this lane's
 // ray enters (internal nodes / leaves), i.e. the visits a single-ray
@@ -229,12 +248,6 @@ struct HitState {
 struct TravStats {
   uint32_t lane_int, lane_leaf, wave_int, wave_leaf, rays;
 };
-
-// Closest-hit decision is ambiguous when an ambiguous crossing was recorded
-// at or before the hit (or anywhere, for a miss).
-__device__ __forceinline__ bool hit_ambiguous(const HitState& h) {
-  return h.tamb < 3.0e38f && (h.id < 0 || h.tamb <= h.t + kFlagT);
-}
 
 // Wave-packet traversal.  Every lane of the wave must call it (uniform control
 // flow).  ANY = true: shadow/any-hit query over (tmin, tmax), `occluded` is set
@@ -257,26 +270,22 @@ __device__ __forceinline__ void trace(const BvhNode* __restrict__ nodes, const T
   int budget = 2 * n_tris + 64;
   while (--budget > 0) {
     if (node >= 0) {
-      const float4* np = reinterpret_cast<const float4*>(nodes + node);
-      const float4 q0 = np[0], q1 = np[1], q2 = np[2];
-      const int4 q3 = reinterpret_cast<const int4*>(np)[3];
-      const float bb0[6] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y};
-      const float bb1[6] = {q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+      const BvhNode nd = nodes[node];               // one 64-byte scalar load
       const float tcur = (ANY ? r.tmax : h.t) + tpad;
-      float tn0 = 0.0f, tn1 = 0.0f;
-      const bool h0 = active && slab(r, bb0, tcur, tn0);
-      const bool h1 = active && slab(r, bb1, tcur, tn1);
+      float tn0, tn1;
+      const bool h0 = slab(r, nd.b0, tcur, tn0) & active;
+      const bool h1 = slab(r, nd.b1, tcur, tn1) & active;
       const uint64_t m0 = ballot(h0), m1 = ballot(h1);
       if (DUMP && st) {
         st->wave_int += 1;
-        st->lane_int += (h0 && q3.x >= 0 ? 1 : 0) + (h1 && q3.y >= 0 ? 1 : 0);
-        st->lane_leaf += (h0 && q3.x < 0 ? 1 : 0) + (h1 && q3.y < 0 ? 1 : 0);
+        st->lane_int += (h0 && nd.c0 >= 0 ? 1 : 0) + (h1 && nd.c1 >= 0 ? 1 : 0);
+        st->lane_leaf += (h0 && nd.c0 < 0 ? 1 : 0) + (h1 && nd.c1 < 0 ? 1 : 0);
       }
       if (m0 && m1) {
         const uint64_t both = m0 & m1;
         const int ref = both ? (int)__builtin_ctzll(both) : (int)__builtin_ctzll(m0);
         const bool near0 = readlane_i(tn0 <= tn1 ? 1 : 0, ref) != 0;
-        const int nearc = near0 ? q3.x : q3.y, farc = near0 ? q3.y : q3.x;
+        const int nearc = near0 ? nd.c0 : nd.c1, farc = near0 ? nd.c1 : nd.c0;
         if (sp < kStackDepth) {                 // depth <= 64 is checked at build
           stack = (lane == sp) ? farc : stack;  // entry sp lives in lane sp
           ++sp;
@@ -284,32 +293,23 @@ __device__ __forceinline__ void trace(const BvhNode* __restrict__ nodes, const T
         node = nearc;
         continue;
       }
-      if (m0) { node = q3.x; continue; }
-      if (m1) { node = q3.y; continue; }
+      if (m0) { node = nd.c0; continue; }
+      if (m1) { node = nd.c1; continue; }
     } else {
-      const TriRec* tr = tris + (~node);
-      const float4* tp = reinterpret_cast<const float4*>(tr);
-      const float4 w0 = tp[0], w1 = tp[1], w2 = tp[2];
-      const float v[9] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w, w2.x};
-      const int tid = __float_as_int(w2.y);
+      const TriRec tr = tris[~node];                // 48-byte scalar load
       if (DUMP && st) st->wave_leaf += 1;
-      if (active && tid != exclude) {
-        float t, b0, b1, b2;
-        const float tmax = ANY ? r.tmax : h.t;
-        const bool hit = tri_test<DUMP>(r, v, tmax, t, b0, b1, b2, h.tamb);
-        if (DUMP && !ANY && hit && h.id >= 0 && fabsf(t - h.t) < kFlagT) h.tamb = fminf(h.tamb, t);
-        if (hit) {
-          if (ANY) {
-            occluded = true;
-          } else if (t < h.t || (t == h.t && tid < h.id)) {
-            h.t = t; h.b0 = b0; h.b1 = b1; h.b2 = b2; h.id = tid;
-          }
-        }
-      }
+      float t = 0.0f;
+      const float tmax = ANY ? r.tmax : h.t;
+      const bool hit = tri_test<DUMP>(r, tr.v, tmax, t, h.tamb) & active & (tr.id != exclude);
+      if (DUMP && !ANY && hit && h.id >= 0 && fabsf(t - h.t) < kFlagT) h.tamb = fminf(h.tamb, t);
       if (ANY) {
-        active = active && !occluded;
+        occluded = occluded | hit;
+        active = active & !hit;
         live = ballot(active);
         if (live == 0) break;
+      } else if (hit && (t < h.t || (t == h.t && tr.id < h.id))) {
+        h.t = t;
+        h.id = tr.id;
       }
     }
     if (sp == 0) break;

@@ -99,22 +99,51 @@ struct Frame {
   float cos_o;
   int vi[3];
   float b[3];
+  float t;         // hit distance (origin shift of the barycentric solve)
 };
+
+// Barycentrics of the ray's crossing with the hit triangle, re-solved
+// (Moller-Trumbore) from the point o' = o + t d next to the hit instead of the
+// ray origin: the crossing does not depend on which point of the line is used,
+// and the short o' - v0 avoids the cancellation of a far origin (camera
+// distance / triangle size ~ 100), which costs FP32 barycentrics ~1e-5.
+struct Bary {
+  V3 op, e1, e2, pv, sv, qv;
+  float det, idet, b1, b2;
+};
+
+__device__ __forceinline__ void bary_solve(const V3& o, const V3& d, float t, const V3& v0, const V3& v1,
+                                           const V3& v2, Bary& B) {
+  B.op = {o.x + t * d.x, o.y + t * d.y, o.z + t * d.z};
+  B.e1 = v1 - v0;
+  B.e2 = v2 - v0;
+  B.pv = cross(d, B.e2);
+  B.det = dot(B.e1, B.pv);
+  B.idet = 1.0f / B.det;
+  B.sv = B.op - v0;
+  B.qv = cross(B.sv, B.e1);
+  B.b1 = dot(B.sv, B.pv) * B.idet;
+  B.b2 = dot(d, B.qv) * B.idet;
+}
 
 __device__ __forceinline__ bool shading_frame(const RenderArgs& a, const Sample& sm, const HitState& h, Frame& f) {
   const int* t = a.tris + 3 * h.id;
   f.vi[0] = t[0]; f.vi[1] = t[1]; f.vi[2] = t[2];
-  f.b[0] = h.b0; f.b[1] = h.b1; f.b[2] = h.b2;
   const V3 v0 = ld3(a.verts, f.vi[0]), v1 = ld3(a.verts, f.vi[1]), v2 = ld3(a.verts, f.vi[2]);
-  f.x = v0 * h.b0 + v1 * h.b1 + v2 * h.b2;
+  Bary B;
+  bary_solve(sm.ray.o, sm.ray.d, h.t, v0, v1, v2, B);
+  const float b0 = 1.0f - B.b1 - B.b2, b1 = B.b1, b2 = B.b2;
+  f.b[0] = b0; f.b[1] = b1; f.b[2] = b2;
+  f.t = h.t;
+  f.x = v0 * b0 + v1 * b1 + v2 * b2;
   const V3 n0 = ld3(a.normals, f.vi[0]), n1 = ld3(a.normals, f.vi[1]), n2 = ld3(a.normals, f.vi[2]);
-  f.m = n0 * h.b0 + n1 * h.b1 + n2 * h.b2;
+  f.m = n0 * b0 + n1 * b1 + n2 * b2;
   f.inv_m = 1.0f / sqrtf(dot(f.m, f.m));
   f.ns = f.m * f.inv_m;
   f.wo = {-sm.ray.d.x, -sm.ray.d.y, -sm.ray.d.z};
-  f.c = ld3(a.diffuse, f.vi[0]) * h.b0 + ld3(a.diffuse, f.vi[1]) * h.b1 + ld3(a.diffuse, f.vi[2]) * h.b2;
-  f.s = ld3(a.specular, f.vi[0]) * h.b0 + ld3(a.specular, f.vi[1]) * h.b1 + ld3(a.specular, f.vi[2]) * h.b2;
-  const float r = a.roughness[f.vi[0]] * h.b0 + a.roughness[f.vi[1]] * h.b1 + a.roughness[f.vi[2]] * h.b2;
+  f.c = ld3(a.diffuse, f.vi[0]) * b0 + ld3(a.diffuse, f.vi[1]) * b1 + ld3(a.diffuse, f.vi[2]) * b2;
+  f.s = ld3(a.specular, f.vi[0]) * b0 + ld3(a.specular, f.vi[1]) * b1 + ld3(a.specular, f.vi[2]) * b2;
+  const float r = a.roughness[f.vi[0]] * b0 + a.roughness[f.vi[1]] * b1 + a.roughness[f.vi[2]] * b2;
   f.r_free = r >= kRoughMin && r <= kRoughMax;
   f.r = fminf(fmaxf(r, kRoughMin), kRoughMax);
   f.cos_o = dot(f.ns, f.wo);

@@ -9,11 +9,19 @@ static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 // ---------------------------------------------------------------------------
 // Vertex normals: n_i = N_i / |N_i|, N_i = sum over incident faces of
 // (v1 - v0) x (v2 - v0), gathered per vertex through the vertex->face CSR
-// (no atomics, fixed order).
+// (no atomics, fixed order).  FP64: the edge vectors of a fine mesh are short
+// differences of O(1) coordinates, and the normal adjoint sums one-ring terms
+// that largely cancel, so FP32 would lose ~1e-5 relative there.  These
+// kernels are a negligible part of a step.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ V3 face_normal(const float* __restrict__ v, const int32_t* __restrict__ tris, int f) {
-  const V3 a = ld3(v, tris[3 * f]), b = ld3(v, tris[3 * f + 1]), c = ld3(v, tris[3 * f + 2]);
-  return cross(b - a, c - a);
+struct D3 { double x, y, z; };
+__device__ __forceinline__ D3 d3(const float* __restrict__ p, int i) {
+  return {(double)p[3 * i], (double)p[3 * i + 1], (double)p[3 * i + 2]};
+}
+__device__ __forceinline__ D3 operator+(D3 a, D3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ D3 operator-(D3 a, D3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ D3 crossd(D3 a, D3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 
 __global__ __launch_bounds__(256) void k_normals(const float* __restrict__ v, const int32_t* __restrict__ tris,
@@ -21,25 +29,39 @@ __global__ __launch_bounds__(256) void k_normals(const float* __restrict__ v, co
                                                  float* __restrict__ n, float* __restrict__ nlen) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
-  V3 acc = {0.0f, 0.0f, 0.0f};
-  for (int k = off[i]; k < off[i + 1]; ++k) acc = acc + face_normal(v, tris, idx[k]);
-  const float len = sqrtf(dot(acc, acc));
-  const float inv = 1.0f / len;
-  n[3 * i] = acc.x * inv; n[3 * i + 1] = acc.y * inv; n[3 * i + 2] = acc.z * inv;
-  nlen[i] = len;
+  D3 acc = {0.0, 0.0, 0.0};
+  for (int k = off[i]; k < off[i + 1]; ++k) {
+    const int f = idx[k];
+    const D3 a = d3(v, tris[3 * f]);
+    acc = acc + crossd(d3(v, tris[3 * f + 1]) - a, d3(v, tris[3 * f + 2]) - a);
+  }
+  const double len = sqrt(acc.x * acc.x + acc.y * acc.y + acc.z * acc.z);
+  n[3 * i] = (float)(acc.x / len); n[3 * i + 1] = (float)(acc.y / len); n[3 * i + 2] = (float)(acc.z / len);
+  nlen[i] = (float)len;
 }
 
-// g_N_i = (I - n n^T) g_n_i / |N_i|, written in place over g_n.
-__global__ __launch_bounds__(256) void k_normals_bwd_project(const float* __restrict__ n, const float* __restrict__ nlen,
-                                                             int N, float* __restrict__ g) {
+// g_N_i = (I - n n^T) g_n_i / |N_i|, written in place over g_n.  n and |N| are
+// recomputed in FP64 from the vertices.
+__global__ __launch_bounds__(256) void k_normals_bwd_project(const float* __restrict__ v,
+                                                             const int32_t* __restrict__ tris,
+                                                             const int32_t* __restrict__ off,
+                                                             const int32_t* __restrict__ idx, int N,
+                                                             float* __restrict__ g) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
-  const V3 nn = ld3(n, i), gg = ld3(g, i);
-  const float d = dot(nn, gg);
-  const float inv = 1.0f / nlen[i];
-  g[3 * i] = (gg.x - nn.x * d) * inv;
-  g[3 * i + 1] = (gg.y - nn.y * d) * inv;
-  g[3 * i + 2] = (gg.z - nn.z * d) * inv;
+  D3 acc = {0.0, 0.0, 0.0};
+  for (int k = off[i]; k < off[i + 1]; ++k) {
+    const int f = idx[k];
+    const D3 a = d3(v, tris[3 * f]);
+    acc = acc + crossd(d3(v, tris[3 * f + 1]) - a, d3(v, tris[3 * f + 2]) - a);
+  }
+  const double len = sqrt(acc.x * acc.x + acc.y * acc.y + acc.z * acc.z);
+  const D3 nn = {acc.x / len, acc.y / len, acc.z / len};
+  const D3 gg = d3(g, i);
+  const double d = nn.x * gg.x + nn.y * gg.y + nn.z * gg.z;
+  g[3 * i] = (float)((gg.x - nn.x * d) / len);
+  g[3 * i + 1] = (float)((gg.y - nn.y * d) / len);
+  g[3 * i + 2] = (float)((gg.z - nn.z * d) / len);
 }
 
 // For face f with N_f = a x b (a = v1 - v0, b = v2 - v0) and gN = sum of the
@@ -51,19 +73,19 @@ __global__ __launch_bounds__(256) void k_normals_bwd_gather(const float* __restr
                                                             const float* __restrict__ gN, float* __restrict__ gv) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
-  V3 acc = {0.0f, 0.0f, 0.0f};
+  D3 acc = {0.0, 0.0, 0.0};
   for (int k = off[i]; k < off[i + 1]; ++k) {
     const int f = idx[k];
     const int i0 = tris[3 * f], i1 = tris[3 * f + 1], i2 = tris[3 * f + 2];
-    const V3 g = ld3(gN, i0) + ld3(gN, i1) + ld3(gN, i2);
-    const V3 p0 = ld3(v, i0);
-    const V3 a = ld3(v, i1) - p0, b = ld3(v, i2) - p0;
-    const V3 ga = cross(b, g), gb = cross(g, a);
+    const D3 g = d3(gN, i0) + d3(gN, i1) + d3(gN, i2);
+    const D3 p0 = d3(v, i0);
+    const D3 a = d3(v, i1) - p0, b = d3(v, i2) - p0;
+    const D3 ga = crossd(b, g), gb = crossd(g, a);
     if (i == i0) acc = acc - (ga + gb);
     else if (i == i1) acc = acc + ga;
     else acc = acc + gb;
   }
-  gv[3 * i] += acc.x; gv[3 * i + 1] += acc.y; gv[3 * i + 2] += acc.z;
+  gv[3 * i] += (float)acc.x; gv[3 * i + 1] += (float)acc.y; gv[3 * i + 2] += (float)acc.z;
 }
 
 void launch_normals(MeshDev& m, const float* d_verts, hipStream_t st) {
@@ -73,8 +95,8 @@ void launch_normals(MeshDev& m, const float* d_verts, hipStream_t st) {
 
 void launch_normals_backward(MeshDev& m, const float* d_verts, const float* d_gn, float* d_gv, hipStream_t st) {
   // d_gn is the mesh's own scratch (m.gnorm) and is projected in place
-  hipLaunchKernelGGL(k_normals_bwd_project, dim3(cdiv(m.N, 256)), dim3(256), 0, st, m.normals, m.nlen, m.N,
-                     const_cast<float*>(d_gn));
+  hipLaunchKernelGGL(k_normals_bwd_project, dim3(cdiv(m.N, 256)), dim3(256), 0, st, d_verts, m.tris, m.vf_off,
+                     m.vf_idx, m.N, const_cast<float*>(d_gn));
   hipLaunchKernelGGL(k_normals_bwd_gather, dim3(cdiv(m.N, 256)), dim3(256), 0, st, d_verts, m.tris, m.vf_off,
                      m.vf_idx, m.N, d_gn, d_gv);
 }

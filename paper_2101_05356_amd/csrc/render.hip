@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, float* __restr
     Sample sm;
     camera_sample(a, ps, s, sm);
     HitState h;
-    h.t = 3.4e38f; h.id = -1; h.b0 = h.b1 = h.b2 = 0.0f; h.tamb = 3.4e38f;
+    h.t = 3.4e38f; h.id = -1; h.tamb = 3.4e38f;
     bool dummy = false;
     trace<false, DUMP>(a.nodes, a.recs, a.F, sm.ray, ps.valid, -1, h, dummy, &st);
     const size_t rs = (size_t)ps.pid * a.S + s;

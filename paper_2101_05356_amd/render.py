@@ -32,7 +32,7 @@ class _DevArray:
     """__cuda_array_interface__ view of a device pointer owned by the library."""
 
     def __init__(self, ptr, shape, typestr="<f4"):
-        self.__cuda_array_interface__ = {"shape": shape, "typestr": typestr, "data": (ptr, True), "version": 3,
+        self.__cuda_array_interface__ = {"shape": shape, "typestr": typestr, "data": (ptr, False), "version": 3,
                                          "strides": None}
 
 
@@ -47,8 +47,8 @@ class Context:
         self.h = h
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().fr_ctx_destroy(self.h)
+        if getattr(self, "h", None) and _lib is not None and _lib._lib is not None:
+            _lib._lib.fr_ctx_destroy(self.h)
             self.h = None
 
 
@@ -66,8 +66,8 @@ class Mesh:
         self._verts = None
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().fr_mesh_destroy(self.h)
+        if getattr(self, "h", None) and _lib is not None and _lib._lib is not None:
+            _lib._lib.fr_mesh_destroy(self.h)
             self.h = None
 
     def update(self, verts: torch.Tensor, rebuild: bool = False):

@@ -1,0 +1,77 @@
+"""Parity of the HIP morphable blend, pose, normals and Adam with the FP64
+oracle (Sec. 3.1, 3.2, Sec. 5), through the C ABI."""
+import numpy as np
+import pytest
+
+from paper_2101_05356_amd import scenes
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def t32(a):
+    return torch.tensor(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+@pytest.mark.parametrize("K,M", [(1, 7), (5, 1000), (144, 84006), (80, 12345)])
+def test_blend_and_adjoint(oracle_lib, K, M):
+    import oracle
+    rng = np.random.default_rng(K + M)
+    mean = rng.normal(size=M).astype(np.float32)
+    basis = (rng.normal(size=(K, M)) * 0.1).astype(np.float32)
+    coef = rng.normal(size=K).astype(np.float32)
+    out = G.to_np(G.R.blend(t32(mean), t32(basis), t32(coef)))
+    ref = oracle.blend(mean, basis, coef)
+    # FP32 accumulation of K terms: |err| <= K * eps * sum |terms|
+    bound = K * 1.2e-7 * (np.abs(mean) + np.abs(coef) @ np.abs(basis)) + 1e-7
+    assert np.all(np.abs(out - ref) <= bound)
+    g = rng.normal(size=M).astype(np.float32)
+    gc = t32(np.full(K, 0.5))
+    G.R.blend_backward(t32(basis), t32(g), gc)
+    refg = oracle.blend_vjp(basis, g) + 0.5
+    tol = 1e-6 * (np.abs(basis) @ np.abs(g)) + 1e-6
+    assert np.all(np.abs(G.to_np(gc) - refg) <= tol)
+
+
+def test_pose_and_adjoint(oracle_lib):
+    import oracle
+    rng = np.random.default_rng(3)
+    N = 5000
+    v = rng.normal(size=(N, 3)).astype(np.float32)
+    pose = np.concatenate([rng.uniform(-0.3, 0.3, 3), rng.normal(0, 0.1, 3)]).astype(np.float32)
+    vw = G.to_np(G.R.pose_forward(t32(v), t32(pose)))
+    assert np.allclose(vw, oracle.pose_apply(v, pose), rtol=1e-5, atol=2e-6)
+    gw = rng.normal(size=(N, 3)).astype(np.float32)
+    gv = torch.zeros(N * 3, device="cuda")
+    gp = torch.zeros(6, device="cuda")
+    G.R.pose_backward(t32(v), t32(pose), t32(gw), gv, gp)
+    rv, rp = oracle.pose_vjp(v, pose, gw)
+    assert np.allclose(G.to_np(gv).reshape(N, 3), rv, rtol=1e-5, atol=2e-6)
+    ok, l2, el = G.grad_tol_ok(G.to_np(gp), rp)
+    assert l2 < 1e-5, (l2, el)
+
+
+def test_vertex_normals(oracle_lib):
+    import oracle
+    for sc in (scenes.patch_scene(), scenes.face_render_scene(W=8, H=8)):
+        m, ds = G.gpu_setup(sc)
+        n = G.to_np(m.normals())
+        ref = oracle.vertex_normals(sc)
+        assert np.abs(n - ref).max() < 2e-6
+
+
+def test_adam_matches_oracle(oracle_lib):
+    import oracle
+    rng = np.random.default_rng(4)
+    n = 1000
+    th = rng.normal(size=n).astype(np.float32)
+    lr = rng.choice([1e-3, 1e-2, 2e-2, 5e-3], size=n).astype(np.float32)
+    p, m, v = t32(th), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    tr, mr, vr = th.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t in range(1, 151):
+        g = rng.normal(size=n).astype(np.float32)
+        G.R.adam_step(p, t32(g), m, v, t32(lr), t)
+        tr, mr, vr = oracle.adam(tr, g, mr, vr, t, lr.astype(np.float64))
+    # FP32 state over 150 steps: parameters move by ~lr per step
+    assert np.abs(G.to_np(p) - tr).max() < 2e-5
