@@ -119,7 +119,7 @@ typedef struct {
   int32_t brdf_variant;    /* FR_BRDF_* */
   int32_t components;      /* bit 0 diffuse, bit 1 specular (3 = full BRDF) */
   int32_t edge_samples;    /* boundary-term samples in the backward; 0 = off, -1 = W*H */
-  int32_t reserved;
+  int32_t light_chunk;     /* lights per work item (0 = library default per pass) */
   /* Debug dump of the decisions (device, nullable):
    *   dbg_hit [W*H*spp] int32 closest-hit triangle id per sample (-1 = miss);
    *   dbg_pflag [W*H*spp] uint8 nonzero when that decision is near ambiguous;
@@ -129,7 +129,8 @@ typedef struct {
    * In fr_render_backward the dump covers the boundary term instead (dbg_vis
    * must be NULL): dbg_hit [n_edge_samples*4] receives per edge sample the
    * edge id, the pixel id (-1 outside the image) and the hit triangle of the
-   * minus and plus side rays; dbg_pflag [n_edge_samples] its ambiguity flag. */
+   * minus and plus side rays; dbg_pflag [n_edge_samples] its ambiguity flag,
+   * OR-accumulated (the caller zeroes it). */
   int32_t* dbg_hit;
   uint8_t* dbg_pflag;
   uint8_t* dbg_vis;
@@ -206,6 +207,137 @@ int fr_pose_backward(const float* d_v, int32_t n_verts, const float* d_pose, con
  * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
 int fr_adam_step(float* d_param, const float* d_grad, float* d_m, float* d_v, const float* d_lr, int32_t n,
                  int32_t t, float beta1, float beta2, float eps, fr_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched reconstructions.  A model holds what every reconstruction of a face
+ * shares: the mesh topology and the morphable model of Sec. 3.1 / 3.2 (device
+ * pointers, caller-owned, kept alive while the model is used).  A job is one
+ * reconstruction: its parameters [alpha, delta | beta | pose(6) | radiance
+ * (3L)] are optimised with Adam (Sec. 5) against its target image, with its
+ * own image size, samples per pixel and lights.  fr_batch_step advances every
+ * job of a batch by one or more optimisation steps (blend, pose, normals +
+ * refit, render, loss, backward with edge sampling, adjoints, Adam), with one
+ * launch per stage covering all jobs; with use_graph the launch sequence is
+ * captured into a hipGraph once per job set and replayed.
+ * ------------------------------------------------------------------------- */
+typedef struct fr_model fr_model;
+typedef struct fr_batch fr_batch;
+
+typedef struct {
+  int32_t width, height, spp, n_lights;
+  int32_t edge_samples;    /* boundary-term samples per step: -1 = W*H, 0 = off */
+  int32_t smooth;          /* 1: 3x3 Gaussian smoothing before the loss */
+  int32_t brdf_variant;    /* FR_BRDF_* */
+  int32_t hist_cap;        /* per-step losses kept on the device */
+  uint64_t seed;           /* Philox key of this job's renders */
+  float fov_y;             /* host value, radians */
+  int32_t pad_;
+  /* host or device memory, copied at fr_batch_add (free to reuse afterwards): */
+  const float* cam;        /* [12] camera R (row-major), T */
+  const float* light_p0;   /* [L*3] */
+  const float* light_e1;   /* [L*3] */
+  const float* light_e2;   /* [L*3] */
+  const int32_t* light_shape; /* [L] */
+  const float* target;     /* [H*W*3] target image p^R */
+  const float* params;     /* [n_param] initial parameters */
+  const float* lr;         /* [n_param] per-parameter learning rates */
+} fr_job_desc;
+
+int fr_model_create(fr_ctx* ctx, int32_t n_verts, int32_t n_tris, const int32_t* h_tris, const float* d_mean_geo,
+                    const float* d_basis_geo, int32_t K_geo, const float* d_mean_alb, const float* d_basis_alb,
+                    int32_t K_alb, const float* d_specular, const float* d_roughness, fr_model** out);
+int fr_model_destroy(fr_model* model);
+/* Parameters of a job with n_lights lights: K_geo + K_alb + 6 + 3 n_lights. */
+int32_t fr_model_n_param(const fr_model* model, int32_t n_lights);
+/* Device bytes one job of this description occupies (its mesh, BVH and
+ * buffers); the serving loop admits jobs against an HBM budget with it. */
+size_t fr_job_bytes(const fr_model* model, const fr_job_desc* desc);
+
+int fr_batch_create(fr_model* model, fr_batch** out);
+int fr_batch_destroy(fr_batch* batch);
+/* Allocate a job, copy its inputs, build its BVH (synchronises). */
+int fr_batch_add(fr_batch* batch, const fr_job_desc* desc, int32_t* job_id, fr_stream stream);
+/* Free a job (synchronises the device first). */
+int fr_batch_remove(fr_batch* batch, int32_t job_id);
+int32_t fr_batch_size(const fr_batch* batch);
+int fr_batch_step(fr_batch* batch, int32_t n_steps, int32_t use_graph, fr_stream stream);
+/* Copy a job's state to host buffers (each nullable): parameters [n_param],
+ * gradient of the last step [n_param], per-step losses [hist_cap] (loss of the
+ * image rendered at step k in entry k - 1), last rendered image [H*W*3],
+ * completed steps.  Synchronises the stream. */
+int fr_batch_read(fr_batch* batch, int32_t job_id, float* h_params, float* h_grad, float* h_loss_hist,
+                  float* h_image, int32_t* h_t, fr_stream stream);
+
+/* Size of a job and its completed steps. */
+int fr_batch_job_info(const fr_batch* batch, int32_t job_id, int32_t* n_param, int32_t* hist_cap,
+                      int32_t* steps_done);
+/* Latest loss of every job (at most cap, in job-id order) into h_ids / h_losses;
+ * returns the count, or -FR_ERR_* on failure.  Synchronises the stream. */
+int32_t fr_batch_losses(fr_batch* batch, int32_t cap, int32_t* h_ids, float* h_losses, fr_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving.  A server owns a worker thread, a HIP stream and a batch on the
+ * model's device, and runs submitted reconstructions with continuous
+ * batching: between optimisation steps it admits queued requests in arrival
+ * order while a slot is free and the request's device bytes (fr_job_bytes)
+ * fit the HBM budget, steps all admitted requests together, fails a request
+ * whose loss turns non-finite (FR_ERR_NONFINITE), and retires the ones that
+ * reached their step count.  A request is never split or preempted; a request
+ * that does not fit the remaining budget blocks those behind it (strict FIFO).
+ * All calls are thread-safe and return at once except fr_server_wait.
+ * ------------------------------------------------------------------------- */
+typedef struct fr_server fr_server;
+
+typedef struct {
+  size_t hbm_budget;     /* device bytes the admitted requests may hold together */
+  int32_t max_slots;     /* requests stepped together at most */
+  int32_t quantum;       /* steps per scheduling round at most (bounds admission delay) */
+  int32_t use_graph;     /* 1: replay each round's step from a hipGraph */
+  int32_t pad_;
+} fr_server_opts;
+
+typedef struct {
+  fr_job_desc job;       /* pointers: HOST memory, copied at submit */
+  int32_t n_steps;       /* Adam steps to run */
+  int32_t pad_;
+} fr_request;
+
+enum { FR_REQ_QUEUED = 0, FR_REQ_RUNNING = 1, FR_REQ_DONE = 2, FR_REQ_FAILED = 3, FR_REQ_CANCELLED = 4 };
+
+typedef struct {
+  int32_t state;         /* FR_REQ_* */
+  int32_t status;        /* FR_OK, or why the request failed */
+  int32_t steps_done, n_steps, n_losses;
+  float final_loss;      /* loss of the image rendered at the last step run */
+  double t_submit, t_admit, t_done;   /* seconds on the server clock */
+} fr_result;
+
+typedef struct {
+  int64_t submitted, completed, failed, cancelled, rejected;
+  int32_t queued, active, peak_active, pad_;
+  size_t bytes_in_use, peak_bytes;
+  double p50_s, p99_s, mean_s;   /* arrival-to-done latency of completed requests (nearest rank) */
+  double recons_per_s;           /* completed / (last completion - first arrival) */
+  double busy_s;                 /* time spent in batched steps */
+  int64_t steps, ticks;          /* batched steps run, scheduling rounds */
+} fr_stats;
+
+int fr_server_create(fr_model* model, const fr_server_opts* opts, fr_server** out);
+/* Stops the worker; requests still queued or running are dropped. */
+int fr_server_destroy(fr_server* server);
+/* FR_ERR_BUDGET if the request alone exceeds the budget. */
+int fr_server_submit(fr_server* server, const fr_request* req, uint64_t* id);
+/* State of a request; when done (or failed after running) also its final
+ * parameters [n_param] and per-step losses [n_steps] (both nullable). */
+int fr_server_poll(fr_server* server, uint64_t id, fr_result* out, float* h_params, float* h_losses);
+int fr_server_cancel(fr_server* server, uint64_t id);
+/* Drop the record of a finished request. */
+int fr_server_forget(fr_server* server, uint64_t id);
+int fr_server_stats(fr_server* server, fr_stats* out);
+/* Block until nothing is queued or running: FR_OK, or FR_ERR_LIMIT after timeout_s. */
+int fr_server_wait(fr_server* server, double timeout_s);
+/* Seconds since the server was created (the clock of fr_result). */
+double fr_server_clock(fr_server* server);
 
 #ifdef __cplusplus
 }

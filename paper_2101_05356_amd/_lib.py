@@ -30,13 +30,96 @@ class FrScene(ctypes.Structure):
 
 class FrRenderOpts(ctypes.Structure):
     _fields_ = [("brdf_variant", ctypes.c_int32), ("components", ctypes.c_int32),
-                ("edge_samples", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("edge_samples", ctypes.c_int32), ("light_chunk", ctypes.c_int32),
                 ("dbg_hit", P), ("dbg_pflag", P), ("dbg_vis", P), ("dbg_stats", P)]
 
 
 class FrGrads(ctypes.Structure):
     _fields_ = [("verts", P), ("normals", P), ("diffuse", P), ("specular", P), ("roughness", P),
                 ("light_geom", P), ("light_rad", P), ("cam", P)]
+
+
+class FrJobDesc(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("spp", ctypes.c_int32),
+                ("n_lights", ctypes.c_int32), ("edge_samples", ctypes.c_int32), ("smooth", ctypes.c_int32),
+                ("brdf_variant", ctypes.c_int32), ("hist_cap", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("fov_y", ctypes.c_float), ("pad_", ctypes.c_int32),
+                ("cam", P), ("light_p0", P), ("light_e1", P), ("light_e2", P), ("light_shape", P),
+                ("target", P), ("params", P), ("lr", P)]
+
+
+class FrServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("quantum", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class FrRequest(ctypes.Structure):
+    _fields_ = [("job", FrJobDesc), ("n_steps", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class FrResult(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("steps_done", ctypes.c_int32),
+                ("n_steps", ctypes.c_int32), ("n_losses", ctypes.c_int32), ("final_loss", ctypes.c_float),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class FrStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("cancelled", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("queued", ctypes.c_int32), ("active", ctypes.c_int32), ("peak_active", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t),
+                ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double),
+                ("recons_per_s", ctypes.c_double), ("busy_s", ctypes.c_double),
+                ("steps", ctypes.c_int64), ("ticks", ctypes.c_int64)]
+
+
+FR_REQ_QUEUED, FR_REQ_RUNNING, FR_REQ_DONE, FR_REQ_FAILED, FR_REQ_CANCELLED = 0, 1, 2, 3, 4
+
+_i32 = ctypes.c_int32
+# name -> (argument types, result type) of every entry point of include/fr.h
+SIGNATURES = {
+    "fr_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "fr_last_error": ([P], ctypes.c_char_p),
+    "fr_ctx_create": ([ctypes.c_int, P], ctypes.c_int),
+    "fr_ctx_destroy": ([P], ctypes.c_int),
+    "fr_mesh_create": ([P, _i32, _i32, P, P], ctypes.c_int),
+    "fr_mesh_destroy": ([P], ctypes.c_int),
+    "fr_mesh_update": ([P, P, ctypes.c_int, P], ctypes.c_int),
+    "fr_mesh_normals": ([P], P),
+    "fr_mesh_edges": ([P, P, P], _i32),
+    "fr_mesh_bvh_depth": ([P], _i32),
+    "fr_render_forward": ([P, P, P, P, P], ctypes.c_int),
+    "fr_loss": ([P, P, _i32, _i32, _i32, P, P, P], ctypes.c_int),
+    "fr_render_backward": ([P, P, P, P, P, P], ctypes.c_int),
+    "fr_blend": ([P, P, P, _i32, _i32, P, P], ctypes.c_int),
+    "fr_blend_backward": ([P, P, _i32, _i32, P, P], ctypes.c_int),
+    "fr_pose_forward": ([P, _i32, P, P, P], ctypes.c_int),
+    "fr_pose_backward": ([P, _i32, P, P, P, P, P], ctypes.c_int),
+    "fr_adam_step": ([P, P, P, P, P, _i32, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, P],
+                     ctypes.c_int),
+    "fr_model_create": ([P, _i32, _i32, P, P, P, _i32, P, P, _i32, P, P, P], ctypes.c_int),
+    "fr_model_destroy": ([P], ctypes.c_int),
+    "fr_model_n_param": ([P, _i32], _i32),
+    "fr_job_bytes": ([P, P], ctypes.c_size_t),
+    "fr_batch_create": ([P, P], ctypes.c_int),
+    "fr_batch_destroy": ([P], ctypes.c_int),
+    "fr_batch_add": ([P, P, P, P], ctypes.c_int),
+    "fr_batch_remove": ([P, _i32], ctypes.c_int),
+    "fr_batch_size": ([P], _i32),
+    "fr_batch_step": ([P, _i32, _i32, P], ctypes.c_int),
+    "fr_batch_read": ([P, _i32, P, P, P, P, P, P], ctypes.c_int),
+    "fr_batch_job_info": ([P, _i32, P, P, P], ctypes.c_int),
+    "fr_batch_losses": ([P, _i32, P, P, P], _i32),
+    "fr_server_create": ([P, P, P], ctypes.c_int),
+    "fr_server_destroy": ([P], ctypes.c_int),
+    "fr_server_submit": ([P, P, P], ctypes.c_int),
+    "fr_server_poll": ([P, ctypes.c_uint64, P, P, P], ctypes.c_int),
+    "fr_server_cancel": ([P, ctypes.c_uint64], ctypes.c_int),
+    "fr_server_forget": ([P, ctypes.c_uint64], ctypes.c_int),
+    "fr_server_stats": ([P, P], ctypes.c_int),
+    "fr_server_wait": ([P, ctypes.c_double], ctypes.c_int),
+    "fr_server_clock": ([P], ctypes.c_double),
+}
 
 
 class FrError(RuntimeError):
@@ -54,29 +137,7 @@ def lib():
         raise FrError(f"HIP library {LIB_PATH} is not built: run paper_2101_05356_amd/build.py "
                       "(or __graft_entry__.build()) first")
     L = ctypes.CDLL(LIB_PATH)
-    i32, u64 = ctypes.c_int32, ctypes.c_uint64
-    sig = {
-        "fr_status_string": ([ctypes.c_int], ctypes.c_char_p),
-        "fr_last_error": ([P], ctypes.c_char_p),
-        "fr_ctx_create": ([ctypes.c_int, P], ctypes.c_int),
-        "fr_ctx_destroy": ([P], ctypes.c_int),
-        "fr_mesh_create": ([P, i32, i32, P, P], ctypes.c_int),
-        "fr_mesh_destroy": ([P], ctypes.c_int),
-        "fr_mesh_update": ([P, P, ctypes.c_int, P], ctypes.c_int),
-        "fr_mesh_normals": ([P], P),
-        "fr_mesh_edges": ([P, P, P], i32),
-        "fr_mesh_bvh_depth": ([P], i32),
-        "fr_render_forward": ([P, P, P, P, P], ctypes.c_int),
-        "fr_loss": ([P, P, i32, i32, i32, P, P, P], ctypes.c_int),
-        "fr_render_backward": ([P, P, P, P, P, P], ctypes.c_int),
-        "fr_blend": ([P, P, P, i32, i32, P, P], ctypes.c_int),
-        "fr_blend_backward": ([P, P, i32, i32, P, P], ctypes.c_int),
-        "fr_pose_forward": ([P, i32, P, P, P], ctypes.c_int),
-        "fr_pose_backward": ([P, i32, P, P, P, P, P], ctypes.c_int),
-        "fr_adam_step": ([P, P, P, P, P, i32, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, P],
-                         ctypes.c_int),
-    }
-    for name, (args, res) in sig.items():
+    for name, (args, res) in SIGNATURES.items():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = res
@@ -86,10 +147,7 @@ def lib():
 
 def exported_symbols():
     """Names of the functions the binding expects the library to export."""
-    return ["fr_status_string", "fr_last_error", "fr_ctx_create", "fr_ctx_destroy", "fr_mesh_create",
-            "fr_mesh_destroy", "fr_mesh_update", "fr_mesh_normals", "fr_mesh_edges", "fr_mesh_bvh_depth",
-            "fr_render_forward", "fr_loss", "fr_render_backward", "fr_blend", "fr_blend_backward",
-            "fr_pose_forward", "fr_pose_backward", "fr_adam_step"]
+    return list(SIGNATURES)
 
 
 def check(rc: int, ctx=None, what: str = ""):

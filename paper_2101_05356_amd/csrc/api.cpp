@@ -47,7 +47,7 @@ hipError_t dalloc(T** p, size_t n) {
 
 bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
-int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::RenderArgs& a) {
+int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::RenderArgs& a, int default_chunk) {
   fr_ctx* ctx = m->ctx;
   if (!s || !o) return fail(ctx, FR_ERR_INVALID_ARG, "scene and opts are required");
   if (s->width <= 0 || s->height <= 0 || s->n_lights < 0)
@@ -75,6 +75,10 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
   while ((1 << lg) < P) ++lg;
   a.tile_w = 1 << ((lg + 1) / 2);
   a.tile_h = P / a.tile_w;
+  if (o->light_chunk < 0) return fail(ctx, FR_ERR_INVALID_ARG, "light_chunk must be >= 0");
+  a.lc = o->light_chunk > 0 ? o->light_chunk : default_chunk;
+  a.n_lchunks = std::max(1, (s->n_lights + a.lc - 1) / a.lc);
+  a.partial = nullptr;
   a.tiles_x = (a.W + a.tile_w - 1) / a.tile_w;
   a.tiles_y = (a.H + a.tile_h - 1) / a.tile_h;
   a.n_tiles = a.tiles_x * a.tiles_y;
@@ -99,6 +103,80 @@ int ensure_lights(fr_mesh* m, int L) {
   if (dalloc(&m->d.lights, cap) != hipSuccess || dalloc(&m->d.ltmp, (size_t)cap * 12) != hipSuccess)
     return fail(m->ctx, FR_ERR_OOM, "light table allocation failed");
   m->d.light_cap = cap;
+  return FR_OK;
+}
+
+
+// Host-side topology of a mesh: triangles, vertex->face CSR (faces in
+// increasing order), unique edges (lower id first, sorted) and their faces.
+struct HostTopo {
+  int N = 0, F = 0;
+  std::vector<int32_t> tris, off, idx, edges, edge_faces;
+};
+
+int build_topology(fr_ctx* ctx, int32_t n_verts, int32_t n_tris, const int32_t* h_tris, HostTopo& t) {
+  if (n_verts < 3 || n_tris < 1) return fail(ctx, FR_ERR_INVALID_ARG, "need >= 3 vertices and >= 1 triangle");
+  if (n_tris > (1 << 26)) return fail(ctx, FR_ERR_LIMIT, "more than 2^26 triangles");
+  for (int64_t i = 0; i < 3ll * n_tris; ++i)
+    if (h_tris[i] < 0 || h_tris[i] >= n_verts) return fail(ctx, FR_ERR_SHAPE, "triangle index out of range");
+  t.N = n_verts;
+  t.F = n_tris;
+  t.tris.assign(h_tris, h_tris + 3ll * n_tris);
+  t.off.assign(n_verts + 1, 0);
+  t.idx.assign(3 * (size_t)n_tris, 0);
+  for (int64_t i = 0; i < 3ll * n_tris; ++i) t.off[h_tris[i] + 1]++;
+  for (int i = 0; i < n_verts; ++i) t.off[i + 1] += t.off[i];
+  std::vector<int32_t> fill(t.off.begin(), t.off.end() - 1);
+  for (int f = 0; f < n_tris; ++f)
+    for (int k = 0; k < 3; ++k) t.idx[fill[h_tris[3 * f + k]]++] = f;
+  std::map<std::pair<int, int>, std::pair<int, int>> em;
+  for (int f = 0; f < n_tris; ++f)
+    for (int k = 0; k < 3; ++k) {
+      int a = h_tris[3 * f + k], b = h_tris[3 * f + (k + 1) % 3];
+      if (a > b) std::swap(a, b);
+      auto it = em.find({a, b});
+      if (it == em.end()) em[{a, b}] = {f, -1};
+      else if (it->second.second < 0) it->second.second = f;
+    }
+  for (auto& kv : em) {
+    t.edges.push_back(kv.first.first); t.edges.push_back(kv.first.second);
+    t.edge_faces.push_back(kv.second.first); t.edge_faces.push_back(kv.second.second);
+  }
+  return FR_OK;
+}
+
+int mesh_from_topology(fr_ctx* ctx, const HostTopo& t, fr_mesh** out) {
+  FR_HIP(ctx, hipSetDevice(ctx->device));
+  fr_mesh* m = new fr_mesh();
+  m->ctx = ctx;
+  fr::MeshDev& d = m->d;
+  d.N = t.N;
+  d.F = t.F;
+  d.E = (int)(t.edges.size() / 2);
+  m->h_edges = t.edges;
+  m->h_edge_faces = t.edge_faces;
+  const int F = t.F, NI = std::max(F - 1, 1), nb = (F + 1023) / 1024, n_verts = t.N;
+  bool ok = dalloc(&d.tris, 3 * (size_t)F) == hipSuccess && dalloc(&d.vf_off, n_verts + 1) == hipSuccess &&
+            dalloc(&d.vf_idx, 3 * (size_t)F) == hipSuccess && dalloc(&d.normals, 3 * (size_t)n_verts) == hipSuccess &&
+            dalloc(&d.nlen, n_verts) == hipSuccess && dalloc(&d.gnorm, 3 * (size_t)n_verts) == hipSuccess &&
+            dalloc(&d.edges, 2 * (size_t)d.E) == hipSuccess && dalloc(&d.edge_faces, 2 * (size_t)d.E) == hipSuccess &&
+            dalloc(&d.nodes, NI) == hipSuccess && dalloc(&d.recs, F + 1) == hipSuccess &&
+            dalloc(&d.order, F) == hipSuccess && dalloc(&d.node_parent, NI) == hipSuccess &&
+            dalloc(&d.leaf_parent, F) == hipSuccess && dalloc(&d.flags, NI) == hipSuccess &&
+            dalloc(&d.keys[0], F) == hipSuccess && dalloc(&d.keys[1], F) == hipSuccess &&
+            dalloc(&d.vals[0], F) == hipSuccess && dalloc(&d.vals[1], F) == hipSuccess &&
+            dalloc(&d.hist, 256 * (size_t)nb) == hipSuccess && dalloc(&d.partial, 64 * 6) == hipSuccess &&
+            dalloc(&d.scene_box, 6) == hipSuccess && dalloc(&d.depth, 2) == hipSuccess &&
+            dalloc(&d.edge_len, d.E) == hipSuccess && dalloc(&d.edge_cdf, d.E) == hipSuccess &&
+            dalloc(&d.face_front, F) == hipSuccess && dalloc(&d.scan_part, 1024) == hipSuccess;
+  if (!ok) { fr_mesh_destroy(m); return fail(ctx, FR_ERR_OOM, "mesh allocation failed"); }
+  ok = hipMemcpy(d.tris, t.tris.data(), sizeof(int32_t) * 3 * F, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(d.vf_off, t.off.data(), sizeof(int32_t) * (n_verts + 1), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(d.vf_idx, t.idx.data(), sizeof(int32_t) * 3 * F, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(d.edges, t.edges.data(), sizeof(int32_t) * 2 * d.E, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(d.edge_faces, t.edge_faces.data(), sizeof(int32_t) * 2 * d.E, hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) { fr_mesh_destroy(m); return fail(ctx, FR_ERR_DEVICE, "mesh upload failed"); }
+  *out = m;
   return FR_OK;
 }
 
@@ -141,61 +219,10 @@ int fr_ctx_destroy(fr_ctx* ctx) {
 
 int fr_mesh_create(fr_ctx* ctx, int32_t n_verts, int32_t n_tris, const int32_t* h_tris, fr_mesh** out) {
   if (!ctx || !out || !h_tris) return fail(ctx, FR_ERR_INVALID_ARG, "null argument");
-  if (n_verts < 3 || n_tris < 1) return fail(ctx, FR_ERR_INVALID_ARG, "need >= 3 vertices and >= 1 triangle");
-  if (n_tris > (1 << 26)) return fail(ctx, FR_ERR_LIMIT, "more than 2^26 triangles");
-  for (int64_t i = 0; i < 3ll * n_tris; ++i)
-    if (h_tris[i] < 0 || h_tris[i] >= n_verts) return fail(ctx, FR_ERR_SHAPE, "triangle index out of range");
-  FR_HIP(ctx, hipSetDevice(ctx->device));
-  fr_mesh* m = new fr_mesh();
-  m->ctx = ctx;
-  fr::MeshDev& d = m->d;
-  d.N = n_verts;
-  d.F = n_tris;
-  // vertex -> faces CSR (faces in increasing order)
-  std::vector<int32_t> off(n_verts + 1, 0), idx(3 * (size_t)n_tris);
-  for (int64_t i = 0; i < 3ll * n_tris; ++i) off[h_tris[i] + 1]++;
-  for (int i = 0; i < n_verts; ++i) off[i + 1] += off[i];
-  std::vector<int32_t> fill(off.begin(), off.end() - 1);
-  for (int f = 0; f < n_tris; ++f)
-    for (int k = 0; k < 3; ++k) idx[fill[h_tris[3 * f + k]]++] = f;
-  // unique edges (lower vertex id first, sorted) and their faces
-  std::map<std::pair<int, int>, std::pair<int, int>> em;
-  for (int f = 0; f < n_tris; ++f)
-    for (int k = 0; k < 3; ++k) {
-      int a = h_tris[3 * f + k], b = h_tris[3 * f + (k + 1) % 3];
-      if (a > b) std::swap(a, b);
-      auto it = em.find({a, b});
-      if (it == em.end()) em[{a, b}] = {f, -1};
-      else if (it->second.second < 0) it->second.second = f;
-    }
-  d.E = (int)em.size();
-  for (auto& kv : em) {
-    m->h_edges.push_back(kv.first.first); m->h_edges.push_back(kv.first.second);
-    m->h_edge_faces.push_back(kv.second.first); m->h_edge_faces.push_back(kv.second.second);
-  }
-  const int F = n_tris, NI = std::max(F - 1, 1), nb = (F + 1023) / 1024;
-  bool ok = dalloc(&d.tris, 3 * (size_t)F) == hipSuccess && dalloc(&d.vf_off, n_verts + 1) == hipSuccess &&
-            dalloc(&d.vf_idx, 3 * (size_t)F) == hipSuccess && dalloc(&d.normals, 3 * (size_t)n_verts) == hipSuccess &&
-            dalloc(&d.nlen, n_verts) == hipSuccess && dalloc(&d.gnorm, 3 * (size_t)n_verts) == hipSuccess &&
-            dalloc(&d.edges, 2 * (size_t)d.E) == hipSuccess && dalloc(&d.edge_faces, 2 * (size_t)d.E) == hipSuccess &&
-            dalloc(&d.nodes, NI) == hipSuccess && dalloc(&d.recs, F) == hipSuccess && dalloc(&d.order, F) == hipSuccess &&
-            dalloc(&d.node_parent, NI) == hipSuccess && dalloc(&d.leaf_parent, F) == hipSuccess &&
-            dalloc(&d.flags, NI) == hipSuccess && dalloc(&d.keys[0], F) == hipSuccess &&
-            dalloc(&d.keys[1], F) == hipSuccess && dalloc(&d.vals[0], F) == hipSuccess &&
-            dalloc(&d.vals[1], F) == hipSuccess && dalloc(&d.hist, 256 * (size_t)nb) == hipSuccess &&
-            dalloc(&d.partial, 64 * 6) == hipSuccess && dalloc(&d.scene_box, 6) == hipSuccess &&
-            dalloc(&d.depth, 2) == hipSuccess && dalloc(&d.edge_len, d.E) == hipSuccess &&
-            dalloc(&d.edge_cdf, d.E) == hipSuccess && dalloc(&d.face_front, F) == hipSuccess &&
-            dalloc(&d.scan_part, 1024) == hipSuccess;
-  if (!ok) { fr_mesh_destroy(m); return fail(ctx, FR_ERR_OOM, "mesh allocation failed"); }
-  ok = hipMemcpy(d.tris, h_tris, sizeof(int32_t) * 3 * F, hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(d.vf_off, off.data(), sizeof(int32_t) * (n_verts + 1), hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(d.vf_idx, idx.data(), sizeof(int32_t) * 3 * F, hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(d.edges, m->h_edges.data(), sizeof(int32_t) * 2 * d.E, hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(d.edge_faces, m->h_edge_faces.data(), sizeof(int32_t) * 2 * d.E, hipMemcpyHostToDevice) == hipSuccess;
-  if (!ok) { fr_mesh_destroy(m); return fail(ctx, FR_ERR_DEVICE, "mesh upload failed"); }
-  *out = m;
-  return FR_OK;
+  HostTopo topo;
+  int rc = build_topology(ctx, n_verts, n_tris, h_tris, topo);
+  if (rc != FR_OK) return rc;
+  return mesh_from_topology(ctx, topo, out);
 }
 
 int fr_mesh_destroy(fr_mesh* m) {
@@ -204,7 +231,7 @@ int fr_mesh_destroy(fr_mesh* m) {
   void* ptrs[] = {d.tris, d.vf_off, d.vf_idx, d.normals, d.nlen, d.gnorm, d.edges, d.edge_faces, d.nodes, d.recs,
                   d.order, d.node_parent, d.leaf_parent, d.flags, d.keys[0], d.keys[1], d.vals[0], d.vals[1],
                   d.hist, d.partial, d.scene_box, d.depth, d.lights, d.ltmp, d.edge_len, d.edge_cdf, d.face_front,
-                  d.scan_part, m->loss_scratch, m->loss_gtmp};
+                  d.scan_part, d.img_partial, m->loss_scratch, m->loss_gtmp};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -249,13 +276,25 @@ int32_t fr_mesh_bvh_depth(const fr_mesh* m) { return m ? m->d.bvh_depth : -1; }
 int fr_render_forward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, float* d_image, fr_stream stream) {
   if (!m || !d_image) return FR_ERR_INVALID_ARG;
   fr::RenderArgs a;
-  int rc = build_args(m, s, o, a);
+  int rc = build_args(m, s, o, a, fr::kLightChunkFwd);
   if (rc != FR_OK) return rc;
   const bool any_dbg = o->dbg_hit || o->dbg_pflag || o->dbg_vis || o->dbg_stats;
   if (any_dbg && !(o->dbg_hit && o->dbg_pflag && o->dbg_vis))
     return fail(m->ctx, FR_ERR_INVALID_ARG, "the forward dump needs dbg_hit, dbg_pflag and dbg_vis");
   if ((rc = ensure_lights(m, s->n_lights)) != FR_OK) return rc;
   a.lights = m->d.lights;
+  if (a.n_lchunks > 1) {
+    const size_t need = (size_t)a.n_lchunks * 3 * a.W * a.H;
+    if (need > m->d.img_partial_cap) {
+      if (m->d.img_partial) (void)hipFree(m->d.img_partial);
+      m->d.img_partial = nullptr;
+      m->d.img_partial_cap = 0;
+      if (dalloc(&m->d.img_partial, need) != hipSuccess)
+        return fail(m->ctx, FR_ERR_OOM, "partial image allocation failed");
+      m->d.img_partial_cap = need;
+    }
+    a.partial = m->d.img_partial;
+  }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (s->n_lights > 0) fr::launch_light_setup(*s, m->d.lights, st);
   fr::launch_render_forward(a, d_image, st);
@@ -288,7 +327,7 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
                        fr_stream stream) {
   if (!m || !d_dEdp || !g) return FR_ERR_INVALID_ARG;
   fr::RenderArgs a;
-  int rc = build_args(m, s, o, a);
+  int rc = build_args(m, s, o, a, fr::kLightChunkBwd);
   if (rc != FR_OK) return rc;
   if (o->dbg_vis || (!o->dbg_hit) != (!o->dbg_pflag))
     return fail(m->ctx, FR_ERR_INVALID_ARG, "the backward dump takes dbg_hit and dbg_pflag only");
@@ -340,6 +379,330 @@ int fr_adam_step(float* d_param, const float* d_grad, float* d_m, float* d_v, co
   if (!d_param || !d_grad || !d_m || !d_v || !d_lr || n <= 0 || t < 1) return FR_ERR_INVALID_ARG;
   fr::launch_adam(d_param, d_grad, d_m, d_v, d_lr, n, t, beta1, beta2, eps, reinterpret_cast<hipStream_t>(stream));
   return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched reconstruction jobs
+// ===========================================================================
+#include "batch.h"
+
+struct fr_model {
+  fr_ctx* ctx = nullptr;
+  HostTopo topo;
+  const float* mean_geo = nullptr; const float* basis_geo = nullptr; int K_geo = 0;
+  const float* mean_alb = nullptr; const float* basis_alb = nullptr; int K_alb = 0;
+  const float* specular = nullptr; const float* roughness = nullptr;
+};
+
+namespace {
+
+struct JobHost {
+  fr_mesh* mesh = nullptr;
+  char* arena = nullptr;
+  size_t bytes = 0;
+  int n_param = 0, W = 0, H = 0, hist_cap = 0;
+  fr::JobDev dev{};
+};
+
+// Carves typed sub-buffers out of one allocation (256-byte aligned).
+struct Carver {
+  size_t off = 0;
+  char* base = nullptr;
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+    off += sizeof(T) * std::max<size_t>(n, 1);
+    return p;
+  }
+};
+
+// Lays out (base == nullptr: only sizes) the device buffers of one job.
+void layout_job(Carver& c, const fr_model* md, const fr_job_desc* d, fr::JobDev& J, int n_lchunks) {
+  const size_t N3 = 3 * (size_t)md->topo.N, px3 = 3 * (size_t)d->width * d->height;
+  const int L = d->n_lights;
+  const int n_param = md->K_geo + md->K_alb + 6 + 3 * L;
+  J.v_obj = c.take<float>(N3); J.v_w = c.take<float>(N3); J.diffuse = c.take<float>(N3);
+  J.g_verts = c.take<float>(N3); J.g_diffuse = c.take<float>(N3); J.g_vobj = c.take<float>(N3);
+  J.image = c.take<float>(px3); J.dEdp = c.take<float>(px3); J.gsign = c.take<float>(px3);
+  J.target = c.take<float>(px3);
+  J.ra.partial = n_lchunks > 1 ? c.take<float>(px3 * n_lchunks) : nullptr;
+  J.loss_part = c.take<double>(fr::cdiv(d->width * d->height, 256));
+  J.loss = c.take<float>(1);
+  J.loss_hist = c.take<float>(std::max(d->hist_cap, 1));
+  J.lslots = c.take<float>((size_t)fr::kSlots * (12 * L + 12));
+  J.param = c.take<float>(n_param); J.grad = c.take<float>(n_param);
+  J.adam_m = c.take<float>(n_param); J.adam_v = c.take<float>(n_param); J.lr = c.take<float>(n_param);
+  J.lights = c.take<fr::LightRec>(L);
+  J.lp0 = c.take<float>(3 * L); J.le1 = c.take<float>(3 * L); J.le2 = c.take<float>(3 * L);
+  J.lshape = c.take<int32_t>(L);
+  J.ra.cam = c.take<float>(12);
+}
+
+int validate_job(fr_model* md, const fr_job_desc* d) {
+  fr_ctx* ctx = md->ctx;
+  if (!d) return fail(ctx, FR_ERR_INVALID_ARG, "null job description");
+  if (d->width <= 0 || d->height <= 0 || d->n_lights <= 0) return fail(ctx, FR_ERR_INVALID_ARG, "bad job sizes");
+  if (!pow2(d->spp) || d->spp > 1024) return fail(ctx, FR_ERR_LIMIT, "spp must be a power of two in [1, 1024]");
+  if (!d->cam || !d->light_p0 || !d->light_e1 || !d->light_e2 || !d->light_shape || !d->target || !d->params ||
+      !d->lr)
+    return fail(ctx, FR_ERR_INVALID_ARG, "null job pointer");
+  if (!(d->fov_y > 0.0f && d->fov_y < 3.1f)) return fail(ctx, FR_ERR_INVALID_ARG, "fov_y must be in (0, 3.1)");
+  return FR_OK;
+}
+
+}  // namespace
+
+namespace fr {
+int model_device(const fr_model* m) { return m->ctx->device; }
+}  // namespace fr
+
+struct fr_batch {
+  fr_model* model = nullptr;
+  fr::Batch b;
+  std::map<int32_t, JobHost*> jobs;
+  int32_t next_id = 1;
+  bool dirty = false;
+};
+
+extern "C" {
+
+int fr_model_create(fr_ctx* ctx, int32_t n_verts, int32_t n_tris, const int32_t* h_tris, const float* d_mean_geo,
+                    const float* d_basis_geo, int32_t K_geo, const float* d_mean_alb, const float* d_basis_alb,
+                    int32_t K_alb, const float* d_specular, const float* d_roughness, fr_model** out) {
+  if (!ctx || !out || !h_tris || !d_mean_geo || !d_mean_alb || !d_specular || !d_roughness || K_geo < 0 ||
+      K_alb < 0 || (K_geo > 0 && !d_basis_geo) || (K_alb > 0 && !d_basis_alb))
+    return fail(ctx, FR_ERR_INVALID_ARG, "bad model arguments");
+  fr_model* m = new fr_model();
+  m->ctx = ctx;
+  const int rc = build_topology(ctx, n_verts, n_tris, h_tris, m->topo);
+  if (rc != FR_OK) { delete m; return rc; }
+  m->mean_geo = d_mean_geo; m->basis_geo = d_basis_geo; m->K_geo = K_geo;
+  m->mean_alb = d_mean_alb; m->basis_alb = d_basis_alb; m->K_alb = K_alb;
+  m->specular = d_specular; m->roughness = d_roughness;
+  *out = m;
+  return FR_OK;
+}
+
+int fr_model_destroy(fr_model* m) {
+  delete m;
+  return FR_OK;
+}
+
+int32_t fr_model_n_param(const fr_model* m, int32_t n_lights) {
+  return m ? m->K_geo + m->K_alb + 6 + 3 * n_lights : -1;
+}
+
+size_t fr_job_bytes(const fr_model* m, const fr_job_desc* d) {
+  if (!m || !d || d->n_lights <= 0 || d->width <= 0 || d->height <= 0) return 0;
+  fr::JobDev J{};
+  Carver c;
+  layout_job(c, m, d, J, std::max(1, fr::cdiv(d->n_lights, fr::kLightChunkFwd)));
+  const size_t F = m->topo.F, N = m->topo.N, E = m->topo.edges.size() / 2;
+  // mesh: topology, normals, BVH (64-byte nodes, 48-byte records), sort buffers, edge tables
+  const size_t mesh = F * (12 + 12 + 64 + 48 + 4 * 8 + 1) + N * (4 + 4 * 7) + E * (16 + 16);
+  return c.off + mesh;
+}
+
+int fr_batch_create(fr_model* model, fr_batch** out) {
+  if (!model || !out) return FR_ERR_INVALID_ARG;
+  fr_batch* b = new fr_batch();
+  b->model = model;
+  *out = b;
+  return FR_OK;
+}
+
+int fr_batch_destroy(fr_batch* b) {
+  if (!b) return FR_OK;
+  for (auto& kv : b->jobs) {
+    fr_mesh_destroy(kv.second->mesh);
+    if (kv.second->arena) (void)hipFree(kv.second->arena);
+    delete kv.second;
+  }
+  delete b;
+  return FR_OK;
+}
+
+int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream stream) {
+  if (!b || !job_id) return FR_ERR_INVALID_ARG;
+  fr_model* md = b->model;
+  fr_ctx* ctx = md->ctx;
+  int rc = validate_job(md, d);
+  if (rc != FR_OK) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  JobHost* jh = new JobHost();
+  rc = mesh_from_topology(ctx, md->topo, &jh->mesh);
+  if (rc != FR_OK) { delete jh; return rc; }
+  fr::JobDev& J = jh->dev;
+  const int L = d->n_lights;
+  const int nch_f = std::max(1, fr::cdiv(L, fr::kLightChunkFwd));
+  Carver sizing;
+  layout_job(sizing, md, d, J, nch_f);
+  if (hipMalloc(reinterpret_cast<void**>(&jh->arena), sizing.off) != hipSuccess) {
+    fr_mesh_destroy(jh->mesh);
+    delete jh;
+    return fail(ctx, FR_ERR_OOM, "job allocation failed");
+  }
+  jh->bytes = sizing.off;
+  Carver c;
+  c.base = jh->arena;
+  layout_job(c, md, d, J, nch_f);
+  const int n_param = md->K_geo + md->K_alb + 6 + 3 * L;
+  jh->n_param = n_param; jh->W = d->width; jh->H = d->height; jh->hist_cap = std::max(d->hist_cap, 1);
+  const size_t px3 = 3 * (size_t)d->width * d->height;
+  auto cp = [&](const void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(const_cast<void*>(dst), src, bytes, hipMemcpyDefault, st) == hipSuccess;
+  };
+  bool ok = cp(J.param, d->params, 4 * n_param) && cp(J.lr, d->lr, 4 * n_param) && cp(J.target, d->target, 4 * px3) &&
+            cp(J.lp0, d->light_p0, 12 * L) && cp(J.le1, d->light_e1, 12 * L) && cp(J.le2, d->light_e2, 12 * L) &&
+            cp(J.lshape, d->light_shape, 4 * L) && cp(J.ra.cam, d->cam, 48);
+  ok = ok && hipMemsetAsync(J.adam_m, 0, 4 * n_param, st) == hipSuccess &&
+       hipMemsetAsync(J.adam_v, 0, 4 * n_param, st) == hipSuccess &&
+       hipMemsetAsync(J.loss_hist, 0, 4 * jh->hist_cap, st) == hipSuccess;
+  if (!ok) { fr_mesh_destroy(jh->mesh); (void)hipFree(jh->arena); delete jh; return fail(ctx, FR_ERR_DEVICE, "job upload"); }
+  // initial geometry and BVH
+  const int N = md->topo.N, M = 3 * N;
+  fr::launch_blend(md->mean_geo, md->basis_geo, J.param, md->K_geo, M, J.v_obj, st);
+  fr::launch_blend(md->mean_alb, md->basis_alb, J.param + md->K_geo, md->K_alb, M, J.diffuse, st);
+  fr::launch_pose(J.v_obj, N, J.param + md->K_geo + md->K_alb, J.v_w, st);
+  rc = fr_mesh_update(jh->mesh, J.v_w, FR_REBUILD, stream);
+  if (rc != FR_OK) { fr_mesh_destroy(jh->mesh); (void)hipFree(jh->arena); delete jh; return rc; }
+  // render views
+  fr_scene sc{};
+  sc.width = d->width; sc.height = d->height; sc.spp = d->spp; sc.n_lights = L;
+  sc.verts = J.v_w; sc.diffuse = J.diffuse; sc.specular = md->specular; sc.roughness = md->roughness;
+  sc.light_p0 = J.lp0; sc.light_e1 = J.le1; sc.light_e2 = J.le2; sc.light_rad = J.param + n_param - 3 * L;
+  sc.light_shape = J.lshape; sc.cam = J.ra.cam; sc.fov_y = d->fov_y; sc.step = 0; sc.seed = d->seed;
+  fr_render_opts o{};
+  o.brdf_variant = d->brdf_variant;
+  o.components = 3;
+  float* partial = J.ra.partial;
+  const float* cam = J.ra.cam;
+  if ((rc = build_args(jh->mesh, &sc, &o, J.ra, fr::kLightChunkFwd)) != FR_OK ||
+      (rc = build_args(jh->mesh, &sc, &o, J.rb, fr::kLightChunkBwd)) != FR_OK) {
+    fr_mesh_destroy(jh->mesh); (void)hipFree(jh->arena); delete jh; return rc;
+  }
+  J.ra.partial = partial; J.rb.partial = nullptr;
+  J.ra.lights = J.lights; J.rb.lights = J.lights;
+  J.ra.cam = cam; J.rb.cam = cam;
+  const fr::MeshDev& md_ = jh->mesh->d;
+  J.ea.edges = md_.edges; J.ea.cdf = md_.edge_cdf; J.ea.E = md_.E;
+  J.ea.n_samples = d->edge_samples < 0 ? d->width * d->height : d->edge_samples;
+  J.ea.th = std::tan(0.5 * (double)d->fov_y);
+  J.ea.aspect = (double)d->width / (double)d->height;
+  J.ea.dEdp = J.dEdp; J.ea.gverts = J.g_verts; J.ea.gcam = nullptr; J.ea.dbg_rec = nullptr; J.ea.dbg_flag = nullptr;
+  J.mean_geo = md->mean_geo; J.basis_geo = md->basis_geo; J.mean_alb = md->mean_alb; J.basis_alb = md->basis_alb;
+  J.K_geo = md->K_geo; J.K_alb = md->K_alb; J.N = N; J.F = md->topo.F; J.M = M;
+  J.hist_cap = jh->hist_cap;
+  J.gnorm = md_.gnorm;
+  J.zero_stride = fr::cdiv(std::max(n_param, 3 * N), 256) * 256;
+  J.n_param = n_param; J.off_alb = md->K_geo; J.off_pose = md->K_geo + md->K_alb; J.off_rad = n_param - 3 * L;
+  J.tris = md_.tris; J.vf_off = md_.vf_off; J.vf_idx = md_.vf_idx; J.normals = md_.normals; J.nlen = md_.nlen;
+  J.nodes = md_.nodes; J.recs = md_.recs; J.order = md_.order; J.node_parent = md_.node_parent;
+  J.leaf_parent = md_.leaf_parent; J.flags = md_.flags;
+  J.edge_faces = md_.edge_faces; J.face_front = md_.face_front; J.edge_len = md_.edge_len; J.edge_cdf = md_.edge_cdf;
+  J.smooth = d->smooth ? 1 : 0;
+  const double e = 0.60653065971263342, z = (1.0 + 2.0 * e) * (1.0 + 2.0 * e);
+  J.taps = fr::Taps{(float)(1.0 / z), (float)(e / z), (float)(e * e / z)};
+  J.t = 0;
+  J.ra.step = J.rb.step = 1;
+  const int32_t id = b->next_id++;
+  b->jobs[id] = jh;
+  b->b.jobs.push_back(J);
+  b->dirty = true;
+  *job_id = id;
+  return hipStreamSynchronize(st) == hipSuccess ? FR_OK : FR_ERR_DEVICE;
+}
+
+int fr_batch_remove(fr_batch* b, int32_t job_id) {
+  if (!b) return FR_ERR_INVALID_ARG;
+  auto it = b->jobs.find(job_id);
+  if (it == b->jobs.end()) return FR_ERR_NOT_FOUND;
+  JobHost* jh = it->second;
+  // table entries are kept in job-id order, so the position is the rank of the id
+  int pos = 0;
+  for (auto& kv : b->jobs) { if (kv.first == job_id) break; ++pos; }
+  if (hipDeviceSynchronize() != hipSuccess) return FR_ERR_DEVICE;
+  b->b.jobs.erase(b->b.jobs.begin() + pos);
+  b->jobs.erase(it);
+  fr_mesh_destroy(jh->mesh);
+  if (jh->arena) (void)hipFree(jh->arena);
+  delete jh;
+  b->dirty = true;
+  return FR_OK;
+}
+
+int32_t fr_batch_size(const fr_batch* b) { return b ? (int32_t)b->jobs.size() : -1; }
+
+int fr_batch_step(fr_batch* b, int32_t n_steps, int32_t use_graph, fr_stream stream) {
+  if (!b || n_steps < 0) return FR_ERR_INVALID_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (b->dirty) {
+    const int rc = b->b.upload(st);
+    if (rc != FR_OK) return fail(b->model->ctx, rc, "batch table upload failed");
+    b->dirty = false;
+  }
+  const int rc = b->b.step(st, n_steps, use_graph != 0);
+  if (rc != FR_OK) return fail(b->model->ctx, rc, "batch step failed");
+  for (auto& J : b->b.jobs) {   // host mirror of the device step counters
+    J.t += n_steps;
+    J.ra.step = (uint32_t)(J.t + 1);
+    J.rb.step = (uint32_t)(J.t + 1);
+  }
+  return FR_OK;
+}
+
+int fr_batch_job_info(const fr_batch* b, int32_t job_id, int32_t* n_param, int32_t* hist_cap, int32_t* steps_done) {
+  if (!b) return FR_ERR_INVALID_ARG;
+  auto it = b->jobs.find(job_id);
+  if (it == b->jobs.end()) return FR_ERR_NOT_FOUND;
+  int pos = 0;
+  for (auto& kv : b->jobs) { if (kv.first == job_id) break; ++pos; }
+  if (n_param) *n_param = it->second->n_param;
+  if (hist_cap) *hist_cap = it->second->hist_cap;
+  if (steps_done) *steps_done = b->b.jobs[pos].t;
+  return FR_OK;
+}
+
+int32_t fr_batch_losses(fr_batch* b, int32_t cap, int32_t* h_ids, float* h_losses, fr_stream stream) {
+  if (!b || (cap > 0 && (!h_ids || !h_losses))) return -FR_ERR_INVALID_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int32_t n = 0;
+  size_t pos = 0;
+  for (auto& kv : b->jobs) {
+    if (n >= cap) break;
+    h_ids[n] = kv.first;
+    if (hipMemcpyAsync(h_losses + n, b->b.jobs[pos].loss, 4, hipMemcpyDeviceToHost, st) != hipSuccess)
+      return -FR_ERR_DEVICE;
+    ++n;
+    ++pos;
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) return -FR_ERR_DEVICE;
+  return n;
+}
+
+int fr_batch_read(fr_batch* b, int32_t job_id, float* h_params, float* h_grad, float* h_loss_hist, float* h_image,
+                  int32_t* h_t, fr_stream stream) {
+  if (!b) return FR_ERR_INVALID_ARG;
+  auto it = b->jobs.find(job_id);
+  if (it == b->jobs.end()) return FR_ERR_NOT_FOUND;
+  JobHost* jh = it->second;
+  int pos = 0;
+  for (auto& kv : b->jobs) { if (kv.first == job_id) break; ++pos; }
+  const fr::JobDev& J = b->b.jobs[pos];
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  bool ok = true;
+  if (h_params) ok = ok && hipMemcpyAsync(h_params, J.param, 4 * jh->n_param, hipMemcpyDeviceToHost, st) == hipSuccess;
+  if (h_grad) ok = ok && hipMemcpyAsync(h_grad, J.grad, 4 * jh->n_param, hipMemcpyDeviceToHost, st) == hipSuccess;
+  if (h_loss_hist)
+    ok = ok && hipMemcpyAsync(h_loss_hist, J.loss_hist, 4 * jh->hist_cap, hipMemcpyDeviceToHost, st) == hipSuccess;
+  if (h_image)
+    ok = ok && hipMemcpyAsync(h_image, J.image, 12 * (size_t)jh->W * jh->H, hipMemcpyDeviceToHost, st) == hipSuccess;
+  ok = ok && hipStreamSynchronize(st) == hipSuccess;
+  if (h_t) *h_t = J.t;
+  return ok ? FR_OK : FR_ERR_DEVICE;
 }
 
 }  // extern "C"

@@ -14,7 +14,7 @@
 
 namespace fr {
 
-constexpr int kSlots = 1024;
+
 
 __device__ __forceinline__ float wave_sum(float x) {
   for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
@@ -44,14 +44,16 @@ __device__ __forceinline__ void g1_fwd_bwd(float nv, float hv, float r, float& G
   dG1_dr = -dG * a / r;             // da/dr = -a / r
 }
 
-__global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, const float* __restrict__ dEdp, fr_grads g,
-                                                    float* __restrict__ gnorm, float* __restrict__ slots) {
+__device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const float* __restrict__ dEdp, const fr_grads& g,
+                                                 float* __restrict__ gnorm, float* __restrict__ slots, int bid) {
   extern __shared__ float lds[];   // [L*12 + 12]: per light p0 e1 e2 rad, then camera
   const int nl = a.L * 12 + 12;
   for (int i = threadIdx.x; i < nl; i += 256) lds[i] = 0.0f;
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int tile = wave_tile(a);
+  const Item it = wave_item(a, bid);
+  const int tile = it.tile;
+  const int j0 = it.chunk * a.lc, j1 = min(a.L, j0 + a.lc);
   float gcam[12];
   for (int k = 0; k < 12; ++k) gcam[k] = 0.0f;
   if (tile >= 0) {
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, const float* _
       // sample-level adjoint accumulators
       V3 gx = {0, 0, 0}, gns = {0, 0, 0}, gwo = {0, 0, 0}, gc = {0, 0, 0}, gs = {0, 0, 0};
       float gr = 0.0f;
-      for (int j = 0; j < a.L; ++j) {
+      for (int j = j0; j < j1; ++j) {
         const LightRec& Lj = a.lights[j];
         LightSample ls;
         const bool lit = shaded && light_sample(a, ps.pid, s, j, Lj, fr, ls);
@@ -185,7 +187,12 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, const float* _
       // ---- sample-level adjoint: shading frame, intersection, camera
       V3 gv[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, gn[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
       float gb[3] = {0.0f, 0.0f, 0.0f};
-      if (shaded) {
+      // lanes whose chunk of lights left no gradient skip the chain and the scatter
+      const bool has_g = shaded && (gx.x != 0.0f || gx.y != 0.0f || gx.z != 0.0f || gns.x != 0.0f ||
+                                    gns.y != 0.0f || gns.z != 0.0f || gwo.x != 0.0f || gwo.y != 0.0f ||
+                                    gwo.z != 0.0f || gc.x != 0.0f || gc.y != 0.0f || gc.z != 0.0f ||
+                                    gs.x != 0.0f || gs.y != 0.0f || gs.z != 0.0f || gr != 0.0f);
+      if (has_g) {
         const float grr = fr.r_free ? gr : 0.0f;
         const V3 gm = project_out(gns, fr.ns, fr.inv_m);
         V3 vv[3];
@@ -229,11 +236,11 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, const float* _
         gr = grr;
       }
       // ---- per-vertex scatter: one atomic set per distinct triangle in the wave
-      uint64_t todo = ballot(shaded);
+      uint64_t todo = ballot(has_g);
       while (todo) {
         const int leader = (int)__builtin_ctzll(todo);
         const int key = readlane_i(h.id, leader);
-        const bool mine = shaded && h.id == key;
+        const bool mine = has_g && h.id == key;
         todo &= ~ballot(mine);
         const int* tv = a.tris + 3 * key;
         for (int k = 0; k < 3; ++k) {
@@ -259,16 +266,21 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, const float* _
     if (lane == 0 && t != 0.0f) atomicAdd(&lds[12 * a.L + k], t);
   }
   __syncthreads();
-  float* slot = slots + (size_t)(blockIdx.x % kSlots) * nl;
+  float* slot = slots + (size_t)(bid % kSlots) * nl;
   for (int i = threadIdx.x; i < nl; i += 256)
     if (lds[i] != 0.0f) atomicAdd(slot + i, lds[i]);
 }
 
+__global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, const float* __restrict__ dEdp, fr_grads g,
+                                                    float* __restrict__ gnorm, float* __restrict__ slots) {
+  render_bwd_block(a, dEdp, g, gnorm, slots, blockIdx.x);
+}
+
 // Sum the slots into the caller's light and camera gradients.
-__global__ __launch_bounds__(256) void k_slots_reduce(const float* __restrict__ slots, int nl, int L,
-                                                      float* __restrict__ glight, float* __restrict__ grad,
-                                                      float* __restrict__ gcam) {
-  const int i = blockIdx.x;   // one block per value
+__device__ __forceinline__ void slots_reduce_block(const float* __restrict__ slots, int nl, int L,
+                                                   float* __restrict__ glight, float* __restrict__ grad,
+                                                   float* __restrict__ gcam, int bid) {
+  const int i = bid;   // one block per value
   __shared__ float red[256];
   float acc = 0.0f;
   for (int s = threadIdx.x; s < kSlots; s += 256) acc += slots[(size_t)s * nl + i];
@@ -287,6 +299,12 @@ __global__ __launch_bounds__(256) void k_slots_reduce(const float* __restrict__ 
   } else if (gcam) {
     gcam[i - 12 * L] += v;
   }
+}
+
+__global__ __launch_bounds__(256) void k_slots_reduce(const float* __restrict__ slots, int nl, int L,
+                                                      float* __restrict__ glight, float* __restrict__ grad,
+                                                      float* __restrict__ gcam) {
+  slots_reduce_block(slots, nl, L, glight, grad, gcam, blockIdx.x);
 }
 
 __global__ void k_zero_slots(float* p, size_t n) {
@@ -309,7 +327,7 @@ void launch_render_backward(const RenderArgs& a, const float* dEdp, const fr_gra
     g_slots_cap = need;
   }
   hipLaunchKernelGGL(k_zero_slots, dim3((unsigned)((need + 255) / 256)), dim3(256), 0, st, g_slots, need);
-  const int blocks = wave_blocks_strips(a);
+  const int blocks = wave_blocks_items(a);
   hipLaunchKernelGGL(k_render_bwd, dim3(blocks), dim3(256), nl * sizeof(float), st, a, dEdp, g, gnorm, g_slots);
   hipLaunchKernelGGL(k_slots_reduce, dim3(nl), dim3(256), 0, st, g_slots, nl, a.L, g.light_geom, g.light_rad, g.cam);
 }

@@ -202,12 +202,12 @@ __global__ void k_single_leaf(BvhNode* __restrict__ nodes, int32_t* __restrict__
 // ---------------------------------------------------------------------------
 // Refit: leaf records + bottom-up boxes.  flags[] must be zero on entry.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_refit(const float* __restrict__ v, const int32_t* __restrict__ tris,
+__device__ __forceinline__ void refit_block(const float* __restrict__ v, const int32_t* __restrict__ tris,
                                                const int32_t* __restrict__ order, int F, BvhNode* nodes,
                                                const int32_t* __restrict__ node_parent,
                                                const int32_t* __restrict__ leaf_parent, uint32_t* flags,
-                                               TriRec* __restrict__ recs, float pad) {
-  const int slot = blockIdx.x * 256 + threadIdx.x;
+                                               TriRec* __restrict__ recs, float pad, int bid) {
+  const int slot = bid * 256 + threadIdx.x;
   if (slot >= F) return;
   const int f = order[slot];
   const V3 a = ld3(v, tris[3 * f]), b = ld3(v, tris[3 * f + 1]), c = ld3(v, tris[3 * f + 2]);
@@ -243,6 +243,14 @@ __global__ __launch_bounds__(256) void k_refit(const float* __restrict__ v, cons
     child = p;
     p = node_parent[p];
   }
+}
+
+__global__ __launch_bounds__(256) void k_refit(const float* __restrict__ v, const int32_t* __restrict__ tris,
+                                               const int32_t* __restrict__ order, int F, BvhNode* nodes,
+                                               const int32_t* __restrict__ node_parent,
+                                               const int32_t* __restrict__ leaf_parent, uint32_t* flags,
+                                               TriRec* __restrict__ recs, float pad) {
+  refit_block(v, tris, order, F, nodes, node_parent, leaf_parent, flags, recs, pad, blockIdx.x);
 }
 
 // Structural check of a freshly built tree: sorted keys, child and parent
@@ -290,15 +298,18 @@ __global__ __launch_bounds__(256) void k_leaf_depth(const int32_t* __restrict__ 
   atomicMax(max_depth, p == 0 ? d : 1 << 20);
 }
 
-__global__ void k_zero_u32(uint32_t* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void zero_u32_block(uint32_t* p, int n, int bid) {
+  const int i = bid * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
+}
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+  zero_u32_block(p, n, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // Host drivers
 // ---------------------------------------------------------------------------
-static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 void bvh_refit(MeshDev& m, const float* d_verts, hipStream_t st) {
   const int F = m.F;

@@ -18,9 +18,9 @@
 
 namespace fr {
 
-__global__ __launch_bounds__(256) void k_face_front(const float* __restrict__ v, const int32_t* __restrict__ tris, int F,
-                                                    const float* __restrict__ cam, uint8_t* __restrict__ front) {
-  const int f = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void face_front_block(const float* __restrict__ v, const int32_t* __restrict__ tris, int F,
+                                                    const float* __restrict__ cam, uint8_t* __restrict__ front, int bid) {
+  const int f = bid * 256 + threadIdx.x;
   if (f >= F) return;
   const int i0 = tris[3 * f], i1 = tris[3 * f + 1], i2 = tris[3 * f + 2];
   const double v0x = v[3 * i0], v0y = v[3 * i0 + 1], v0z = v[3 * i0 + 2];
@@ -29,6 +29,11 @@ __global__ __launch_bounds__(256) void k_face_front(const float* __restrict__ v,
   const double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
   const double wx = (double)cam[9] - v0x, wy = (double)cam[10] - v0y, wz = (double)cam[11] - v0z;
   front[f] = (nx * wx + ny * wy + nz * wz) > 0.0 ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_face_front(const float* __restrict__ v, const int32_t* __restrict__ tris, int F,
+                                                    const float* __restrict__ cam, uint8_t* __restrict__ front) {
+  face_front_block(v, tris, F, cam, front, blockIdx.x);
 }
 
 struct FilmD { double x, y, z; };
@@ -48,11 +53,11 @@ __device__ __forceinline__ FilmD project_d(const float* __restrict__ cam, double
   return f;
 }
 
-__global__ __launch_bounds__(256) void k_edge_len(const float* __restrict__ v, const int32_t* __restrict__ edges,
+__device__ __forceinline__ void edge_len_block(const float* __restrict__ v, const int32_t* __restrict__ edges,
                                                   const int32_t* __restrict__ edge_faces, int E,
                                                   const uint8_t* __restrict__ front, const float* __restrict__ cam,
-                                                  double th, double aspect, int W, int H, double* __restrict__ len) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
+                                                  double th, double aspect, int W, int H, double* __restrict__ len, int bid) {
+  const int e = bid * 256 + threadIdx.x;
   if (e >= E) return;
   const int f0 = edge_faces[2 * e], f1 = edge_faces[2 * e + 1];
   const bool sil = f1 < 0 || front[f0] != front[f1];
@@ -66,8 +71,15 @@ __global__ __launch_bounds__(256) void k_edge_len(const float* __restrict__ v, c
   len[e] = l;
 }
 
+__global__ __launch_bounds__(256) void k_edge_len(const float* __restrict__ v, const int32_t* __restrict__ edges,
+                                                  const int32_t* __restrict__ edge_faces, int E,
+                                                  const uint8_t* __restrict__ front, const float* __restrict__ cam,
+                                                  double th, double aspect, int W, int H, double* __restrict__ len) {
+  edge_len_block(v, edges, edge_faces, E, front, cam, th, aspect, W, H, len, blockIdx.x);
+}
+
 // Inclusive FP64 scan in fixed order: per-thread serial runs + block scan.
-__global__ __launch_bounds__(1024) void k_edge_scan(const double* __restrict__ len, int E, double* __restrict__ cdf) {
+__device__ __forceinline__ void edge_scan_block(const double* __restrict__ len, int E, double* __restrict__ cdf, int bid) {
   __shared__ double part[1024];
   const int per = (E + 1023) / 1024;
   const int b = threadIdx.x * per;
@@ -84,10 +96,14 @@ __global__ __launch_bounds__(1024) void k_edge_scan(const double* __restrict__ l
   for (int i = 0; i < per; ++i) if (b + i < E) { run += len[b + i]; cdf[b + i] = run; }
 }
 
+__global__ __launch_bounds__(1024) void k_edge_scan(const double* __restrict__ len, int E, double* __restrict__ cdf) {
+  edge_scan_block(len, E, cdf, blockIdx.x);
+}
+
 // Shaded radiance (no 1/S) of the camera ray through film point (fx, fy).
 template <bool DUMP>
-__device__ __forceinline__ void side_radiance(const RenderArgs& a, float fx, float fy, bool active, int k, V3& L,
-                                              int& hit_id, bool& amb) {
+__device__ __forceinline__ void side_radiance(const RenderArgs& a, float fx, float fy, bool active, int k, int j0,
+                                              int j1, V3& L, int& hit_id, bool& amb) {
   Sample sm;
   camera_ray_film(a, fx, fy, sm);
   HitState h;
@@ -100,7 +116,7 @@ __device__ __forceinline__ void side_radiance(const RenderArgs& a, float fx, flo
   const bool shaded = active && h.id >= 0 && shading_frame(a, sm, h, fr);
   if (DUMP && active && h.id >= 0 && fabsf(fr.cos_o) < kFlagCos) amb = true;
   L = {0.0f, 0.0f, 0.0f};
-  for (int j = 0; j < a.L; ++j) {
+  for (int j = j0; j < j1; ++j) {
     const LightRec& Lj = a.lights[j];
     const U4 r = philox((uint32_t)k, 0u, PURPOSE_EDGE + 1u + (uint32_t)j, a.step, a.k0, a.k1);
     LightSample ls;
@@ -125,22 +141,16 @@ __device__ __forceinline__ void side_radiance(const RenderArgs& a, float fx, flo
   }
 }
 
-struct EdgeArgs {
-  const int32_t* edges;
-  const double* cdf;
-  int E, n_samples;
-  double th, aspect;
-  const float* dEdp;
-  float* gverts;
-  float* gcam;
-  int32_t* dbg_rec;     // [n*4]: edge, pixel, hit-, hit+
-  uint8_t* dbg_flag;    // [n]
-};
 
+// One wave = 64 consecutive edge samples x one chunk of lights; the chunks of
+// one sample group are neighbouring waves of a block.
 template <bool DUMP>
-__global__ __launch_bounds__(256) void k_edge_samples(RenderArgs a, EdgeArgs e) {
+__device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const EdgeArgs& e, int bid) {
   const int lane = threadIdx.x & 63;
-  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int w = bid * 4 + (threadIdx.x >> 6);
+  const int group = w / a.n_lchunks, chunk = w - group * a.n_lchunks;
+  const int j0 = chunk * a.lc, j1 = min(a.L, j0 + a.lc);
+  const int k = group * 64 + lane;
   const bool in = k < e.n_samples;
   const double ltot = e.cdf[e.E - 1];
   int eid = 0, pid = -1;
@@ -176,11 +186,13 @@ __global__ __launch_bounds__(256) void k_edge_samples(RenderArgs a, EdgeArgs e) 
   const bool active = pid >= 0;
   V3 Lm, Lp;
   int hm = -1, hp = -1;
-  side_radiance<DUMP>(a, fx - 1e-3f * mx, fy - 1e-3f * my, active, k, Lm, hm, amb);
-  side_radiance<DUMP>(a, fx + 1e-3f * mx, fy + 1e-3f * my, active, k, Lp, hp, amb);
+  side_radiance<DUMP>(a, fx - 1e-3f * mx, fy - 1e-3f * my, active, k, j0, j1, Lm, hm, amb);
+  side_radiance<DUMP>(a, fx + 1e-3f * mx, fy + 1e-3f * my, active, k, j0, j1, Lp, hp, amb);
   if (DUMP && in) {
-    e.dbg_rec[4 * k] = eid; e.dbg_rec[4 * k + 1] = pid; e.dbg_rec[4 * k + 2] = hm; e.dbg_rec[4 * k + 3] = hp;
-    e.dbg_flag[k] = amb ? 1 : 0;
+    if (chunk == 0) {
+      e.dbg_rec[4 * k] = eid; e.dbg_rec[4 * k + 1] = pid; e.dbg_rec[4 * k + 2] = hm; e.dbg_rec[4 * k + 3] = hp;
+    }
+    if (amb) e.dbg_flag[k] = 1;   // OR over chunks: the caller zeroes the flags
   }
   float gcam[12];
   for (int q = 0; q < 12; ++q) gcam[q] = 0.0f;
@@ -227,6 +239,11 @@ __global__ __launch_bounds__(256) void k_edge_samples(RenderArgs a, EdgeArgs e) 
   }
 }
 
+template <bool DUMP>
+__global__ __launch_bounds__(256) void k_edge_samples(RenderArgs a, EdgeArgs e) {
+  edge_samples_block<DUMP>(a, e, blockIdx.x);
+}
+
 void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samples, const fr_grads& g,
                   int32_t* dbg_rec, uint8_t* dbg_flag, double tan_half, hipStream_t st) {
   hipLaunchKernelGGL(k_face_front, dim3((m.F + 255) / 256), dim3(256), 0, st, a.verts, m.tris, m.F, a.cam,
@@ -239,7 +256,8 @@ void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samp
   e.edges = m.edges; e.cdf = m.edge_cdf; e.E = m.E; e.n_samples = n_samples;
   e.th = tan_half; e.aspect = aspect; e.dEdp = dEdp; e.gverts = g.verts; e.gcam = g.cam;
   e.dbg_rec = dbg_rec; e.dbg_flag = dbg_flag;
-  const int blocks = (n_samples + 255) / 256;
+  const int groups = (n_samples + 63) / 64;
+  const int blocks = (groups * a.n_lchunks + 3) / 4;
   if (dbg_rec)
     hipLaunchKernelGGL(k_edge_samples<true>, dim3(blocks), dim3(256), 0, st, a, e);
   else

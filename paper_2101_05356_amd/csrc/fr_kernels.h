@@ -8,6 +8,24 @@
 
 namespace fr {
 
+__host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+__device__ inline int cdiv_d(int a, int b) { return (a + b - 1) / b; }
+
+struct Taps { float c, e, k; };   // smoothing weights: centre, edge, corner
+
+// Arguments of the edge-sampling kernel.
+struct EdgeArgs {
+  const int32_t* edges;
+  const double* cdf;
+  int E, n_samples;
+  double th, aspect;
+  const float* dEdp;
+  float* gverts;
+  float* gcam;
+  int32_t* dbg_rec;     // [n*4]: edge, pixel, hit-, hit+
+  uint8_t* dbg_flag;    // [n]
+};
+
 // Device buffers owned by one mesh (topology fixed at creation).
 struct MeshDev {
   int N = 0, F = 0, E = 0;
@@ -42,6 +60,8 @@ struct MeshDev {
   double* edge_cdf = nullptr;       // [E] inclusive running sum
   uint8_t* face_front = nullptr;    // [F]
   double* scan_part = nullptr;      // [1024]
+  float* img_partial = nullptr;     // per-light-chunk partial images
+  size_t img_partial_cap = 0;
   int bvh_depth = -1;
   int built = 0;
 };
@@ -63,6 +83,8 @@ struct RenderArgs {
   int tile_w, tile_h, tiles_x, tiles_y, n_tiles;   // wave tiles (S <= 64)
   int chunks;             // S / 64 when S > 64, else 1
   int lanes_per_pixel;    // min(S, 64)
+  int lc, n_lchunks;      // lights per work item, light chunks per tile
+  float* partial;         // [n_lchunks][H*W*3] per-chunk pixel sums (n_lchunks > 1)
   float tan_half, aspect;
   uint32_t k0, k1, step;
   int variant, components;
@@ -90,6 +112,13 @@ void launch_zero(float* p, int n, hipStream_t st);
 void launch_axpy(float* dst, const float* src, int n, hipStream_t st);
 // render.hip
 void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st);
+// Default lights per work item: short items balance the forward launch; the
+// backward repeats more per-item work (primary trace, chain, scatter), so it
+// takes longer items.
+constexpr int kLightChunkFwd = 12;
+constexpr int kLightChunkBwd = 24;
+// Partial slots of the backward light/camera gradients (reduced in a fixed order).
+constexpr int kSlots = 1024;
 // loss.hip
 void launch_loss(const float* img, const float* target, int W, int H, int smooth, float* loss, float* dEdp,
                  double* scratch, float* gtmp, hipStream_t st);

@@ -14,24 +14,34 @@ namespace fr {
 // ---------------------------------------------------------------------------
 // Wave -> tile mapping
 // ---------------------------------------------------------------------------
+// Work items are (tile, light chunk): a tile of 64/S pixels x S samples
+// shaded with lights [chunk * lc, chunk * lc + lc).  Splitting the light loop
+// keeps every wave short (a face tile with all lights costs ~100x a background
+// tile), which removes the long tail of the launch.
+//
 // Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8).
 // The image is cut into strips of 4 tile rows; XCD x walks strips x, x+8,
-// x+16, ... in order, a block covering 4 consecutive tiles of its strip.  Each
-// XCD's L2 then holds the BVH nodes around its current strip, while the load
-// stays balanced because every XCD gets strips from the whole image height.
-__device__ __forceinline__ int wave_tile(const RenderArgs& a) {
-  const int per_strip = a.tiles_x;             // blocks per strip: 4 rows * tiles_x / 4 waves
-  const int b = blockIdx.x;
+// x+16, ... in order, a block covering 4 consecutive items (the chunks of one
+// tile share its primary rays in cache).  Each XCD's L2 then holds the BVH
+// around its current strip while every XCD gets work from the whole image.
+struct Item { int tile, chunk; };
+
+__device__ __forceinline__ Item wave_item(const RenderArgs& a, int b) {
+  const int per_strip = a.tiles_x * a.n_lchunks;        // blocks per strip
   const int x = b & 7, k = b >> 3;
   const int si = k / per_strip, bi = k - si * per_strip;
   const int strip = si * 8 + x;
-  const int t = strip * 4 * a.tiles_x + bi * 4 + (threadIdx.x >> 6);
-  return (t / a.tiles_x) < a.tiles_y ? t : -1;
+  const int item = strip * 4 * per_strip + bi * 4 + (threadIdx.x >> 6);
+  Item it;
+  it.tile = item / a.n_lchunks;
+  it.chunk = item - it.tile * a.n_lchunks;
+  if (it.tile / a.tiles_x >= a.tiles_y) it.tile = -1;
+  return it;
 }
 
-inline int wave_blocks_strips(const RenderArgs& a) {
+inline int wave_blocks_items(const RenderArgs& a) {
   const int strips = (a.tiles_y + 3) / 4;
-  return 8 * a.tiles_x * ((strips + 7) / 8);
+  return 8 * a.tiles_x * a.n_lchunks * ((strips + 7) / 8);
 }
 
 struct PixelSample {

@@ -6,13 +6,12 @@
 
 namespace fr {
 
-struct Taps { float c, e, k; };   // centre, edge, corner weights
 
-__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ img, const float* __restrict__ tgt, int W, int H,
+__device__ __forceinline__ void loss_block(const float* __restrict__ img, const float* __restrict__ tgt, int W, int H,
                                               int smooth, Taps w, float* __restrict__ gsign,
-                                              double* __restrict__ partial) {
+                                              double* __restrict__ partial, int bid) {
   __shared__ double red[256];
-  const int pid = blockIdx.x * 256 + threadIdx.x;
+  const int pid = bid * 256 + threadIdx.x;
   double acc = 0.0;
   if (pid < W * H) {
     const int x = pid % W, y = pid / W;
@@ -40,10 +39,16 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ img, con
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) partial[bid] = red[0];
 }
 
-__global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ partial, int n, float* __restrict__ loss) {
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ img, const float* __restrict__ tgt, int W, int H,
+                                              int smooth, Taps w, float* __restrict__ gsign,
+                                              double* __restrict__ partial) {
+  loss_block(img, tgt, W, H, smooth, w, gsign, partial, blockIdx.x);
+}
+
+__device__ __forceinline__ void loss_final_block(const double* __restrict__ partial, int n, float* __restrict__ loss, int bid) {
   __shared__ double red[256];
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) acc += partial[i];
@@ -54,6 +59,10 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
     __syncthreads();
   }
   if (threadIdx.x == 0) loss[0] = (float)red[0];
+}
+
+__global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ partial, int n, float* __restrict__ loss) {
+  loss_final_block(partial, n, loss, blockIdx.x);
 }
 
 // Sources i of a clamp-to-edge tap: clamp(i + o) == q, o in {-1, 0, 1}.
@@ -67,9 +76,9 @@ __device__ __forceinline__ int tap_sources(int q, int o, int n, int src[2]) {
   return k;
 }
 
-__global__ __launch_bounds__(256) void k_smooth_adjoint(const float* __restrict__ g, int W, int H, Taps w,
-                                                        float* __restrict__ out) {
-  const int pid = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void smooth_adjoint_block(const float* __restrict__ g, int W, int H, Taps w,
+                                                        float* __restrict__ out, int bid) {
+  const int pid = bid * 256 + threadIdx.x;
   if (pid >= W * H) return;
   const int qx = pid % W, qy = pid / W;
   float acc[3] = {0.0f, 0.0f, 0.0f};
@@ -92,6 +101,11 @@ __global__ __launch_bounds__(256) void k_smooth_adjoint(const float* __restrict_
   out[3 * pid] = acc[0];
   out[3 * pid + 1] = acc[1];
   out[3 * pid + 2] = acc[2];
+}
+
+__global__ __launch_bounds__(256) void k_smooth_adjoint(const float* __restrict__ g, int W, int H, Taps w,
+                                                        float* __restrict__ out) {
+  smooth_adjoint_block(g, W, H, w, out, blockIdx.x);
 }
 
 void launch_loss(const float* img, const float* target, int W, int H, int smooth, float* loss, float* dEdp,

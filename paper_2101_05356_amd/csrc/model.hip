@@ -4,7 +4,6 @@
 
 namespace fr {
 
-static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 // ---------------------------------------------------------------------------
 // Vertex normals: n_i = N_i / |N_i|, N_i = sum over incident faces of
@@ -24,10 +23,10 @@ __device__ __forceinline__ D3 crossd(D3 a, D3 b) {
   return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 
-__global__ __launch_bounds__(256) void k_normals(const float* __restrict__ v, const int32_t* __restrict__ tris,
+__device__ __forceinline__ void normals_block(const float* __restrict__ v, const int32_t* __restrict__ tris,
                                                  const int32_t* __restrict__ off, const int32_t* __restrict__ idx, int N,
-                                                 float* __restrict__ n, float* __restrict__ nlen) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+                                                 float* __restrict__ n, float* __restrict__ nlen, int bid) {
+  const int i = bid * 256 + threadIdx.x;
   if (i >= N) return;
   D3 acc = {0.0, 0.0, 0.0};
   for (int k = off[i]; k < off[i + 1]; ++k) {
@@ -40,14 +39,20 @@ __global__ __launch_bounds__(256) void k_normals(const float* __restrict__ v, co
   nlen[i] = (float)len;
 }
 
+__global__ __launch_bounds__(256) void k_normals(const float* __restrict__ v, const int32_t* __restrict__ tris,
+                                                 const int32_t* __restrict__ off, const int32_t* __restrict__ idx, int N,
+                                                 float* __restrict__ n, float* __restrict__ nlen) {
+  normals_block(v, tris, off, idx, N, n, nlen, blockIdx.x);
+}
+
 // g_N_i = (I - n n^T) g_n_i / |N_i|, written in place over g_n.  n and |N| are
 // recomputed in FP64 from the vertices.
-__global__ __launch_bounds__(256) void k_normals_bwd_project(const float* __restrict__ v,
+__device__ __forceinline__ void normals_bwd_project_block(const float* __restrict__ v,
                                                              const int32_t* __restrict__ tris,
                                                              const int32_t* __restrict__ off,
                                                              const int32_t* __restrict__ idx, int N,
-                                                             float* __restrict__ g) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+                                                             float* __restrict__ g, int bid) {
+  const int i = bid * 256 + threadIdx.x;
   if (i >= N) return;
   D3 acc = {0.0, 0.0, 0.0};
   for (int k = off[i]; k < off[i + 1]; ++k) {
@@ -64,14 +69,22 @@ __global__ __launch_bounds__(256) void k_normals_bwd_project(const float* __rest
   g[3 * i + 2] = (float)((gg.z - nn.z * d) / len);
 }
 
+__global__ __launch_bounds__(256) void k_normals_bwd_project(const float* __restrict__ v,
+                                                             const int32_t* __restrict__ tris,
+                                                             const int32_t* __restrict__ off,
+                                                             const int32_t* __restrict__ idx, int N,
+                                                             float* __restrict__ g) {
+  normals_bwd_project_block(v, tris, off, idx, N, g, blockIdx.x);
+}
+
 // For face f with N_f = a x b (a = v1 - v0, b = v2 - v0) and gN = sum of the
 // projected gradients of its three vertices: g_a = b x gN, g_b = gN x a;
 // vertex 1 gets g_a, vertex 2 gets g_b, vertex 0 gets -(g_a + g_b).
-__global__ __launch_bounds__(256) void k_normals_bwd_gather(const float* __restrict__ v, const int32_t* __restrict__ tris,
+__device__ __forceinline__ void normals_bwd_gather_block(const float* __restrict__ v, const int32_t* __restrict__ tris,
                                                             const int32_t* __restrict__ off,
                                                             const int32_t* __restrict__ idx, int N,
-                                                            const float* __restrict__ gN, float* __restrict__ gv) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+                                                            const float* __restrict__ gN, float* __restrict__ gv, int bid) {
+  const int i = bid * 256 + threadIdx.x;
   if (i >= N) return;
   D3 acc = {0.0, 0.0, 0.0};
   for (int k = off[i]; k < off[i + 1]; ++k) {
@@ -86,6 +99,13 @@ __global__ __launch_bounds__(256) void k_normals_bwd_gather(const float* __restr
     else acc = acc + gb;
   }
   gv[3 * i] += (float)acc.x; gv[3 * i + 1] += (float)acc.y; gv[3 * i + 2] += (float)acc.z;
+}
+
+__global__ __launch_bounds__(256) void k_normals_bwd_gather(const float* __restrict__ v, const int32_t* __restrict__ tris,
+                                                            const int32_t* __restrict__ off,
+                                                            const int32_t* __restrict__ idx, int N,
+                                                            const float* __restrict__ gN, float* __restrict__ gv) {
+  normals_bwd_gather_block(v, tris, off, idx, N, gN, gv, blockIdx.x);
 }
 
 void launch_normals(MeshDev& m, const float* d_verts, hipStream_t st) {
@@ -107,21 +127,26 @@ void launch_normals_backward(MeshDev& m, const float* d_verts, const float* d_gn
 // row is streamed with fully coalesced loads; coefficients are wave-uniform
 // scalar loads.  Accumulation order k = 0..K-1.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_blend(const float* __restrict__ mean, const float* __restrict__ basis,
-                                               const float* __restrict__ coef, int K, int M, float* __restrict__ out) {
-  const int m = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void blend_block(const float* __restrict__ mean, const float* __restrict__ basis,
+                                               const float* __restrict__ coef, int K, int M, float* __restrict__ out, int bid) {
+  const int m = bid * 256 + threadIdx.x;
   if (m >= M) return;
   float acc = mean[m];
   for (int k = 0; k < K; ++k) acc = fmaf(coef[k], __builtin_nontemporal_load(basis + (size_t)k * M + m), acc);
   out[m] = acc;
 }
 
+__global__ __launch_bounds__(256) void k_blend(const float* __restrict__ mean, const float* __restrict__ basis,
+                                               const float* __restrict__ coef, int K, int M, float* __restrict__ out) {
+  blend_block(mean, basis, coef, K, M, out, blockIdx.x);
+}
+
 // gcoef[k] += sum_m basis[k][m] gout[m]: one block per component, fixed-order
 // tree reduction (deterministic).
-__global__ __launch_bounds__(1024) void k_blend_bwd(const float* __restrict__ basis, const float* __restrict__ gout,
-                                                    int M, float* __restrict__ gcoef) {
+__device__ __forceinline__ void blend_bwd_block(const float* __restrict__ basis, const float* __restrict__ gout,
+                                                    int M, float* __restrict__ gcoef, int bid) {
   __shared__ float red[1024];
-  const int k = blockIdx.x;
+  const int k = bid;
   const float* row = basis + (size_t)k * M;
   float acc = 0.0f;
   for (int m = threadIdx.x; m < M; m += 1024) acc = fmaf(row[m], gout[m], acc);
@@ -132,6 +157,11 @@ __global__ __launch_bounds__(1024) void k_blend_bwd(const float* __restrict__ ba
     __syncthreads();
   }
   if (threadIdx.x == 0) gcoef[k] += red[0];
+}
+
+__global__ __launch_bounds__(1024) void k_blend_bwd(const float* __restrict__ basis, const float* __restrict__ gout,
+                                                    int M, float* __restrict__ gcoef) {
+  blend_bwd_block(basis, gout, M, gcoef, blockIdx.x);
 }
 
 void launch_blend(const float* mean, const float* basis, const float* coef, int K, int M, float* out, hipStream_t st) {
@@ -183,9 +213,9 @@ __device__ void pose_matrices(const float* p, float R[9], float dR[3][9], bool w
   }
 }
 
-__global__ __launch_bounds__(256) void k_pose(const float* __restrict__ v, int N, const float* __restrict__ pose,
-                                              float* __restrict__ vw) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void pose_block(const float* __restrict__ v, int N, const float* __restrict__ pose,
+                                              float* __restrict__ vw, int bid) {
+  const int i = bid * 256 + threadIdx.x;
   if (i >= N) return;
   float R[9], dR[3][9];
   pose_matrices(pose, R, dR, false);
@@ -195,9 +225,14 @@ __global__ __launch_bounds__(256) void k_pose(const float* __restrict__ v, int N
   vw[3 * i + 2] = R[6] * p.x + R[7] * p.y + R[8] * p.z + pose[5];
 }
 
-__global__ __launch_bounds__(256) void k_pose_bwd_v(int N, const float* __restrict__ pose, const float* __restrict__ gw,
-                                                    float* __restrict__ gv) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_pose(const float* __restrict__ v, int N, const float* __restrict__ pose,
+                                              float* __restrict__ vw) {
+  pose_block(v, N, pose, vw, blockIdx.x);
+}
+
+__device__ __forceinline__ void pose_bwd_v_block(int N, const float* __restrict__ pose, const float* __restrict__ gw,
+                                                    float* __restrict__ gv, int bid) {
+  const int i = bid * 256 + threadIdx.x;
   if (i >= N) return;
   float R[9], dR[3][9];
   pose_matrices(pose, R, dR, false);
@@ -207,10 +242,15 @@ __global__ __launch_bounds__(256) void k_pose_bwd_v(int N, const float* __restri
   gv[3 * i + 2] += R[2] * g.x + R[5] * g.y + R[8] * g.z;
 }
 
+__global__ __launch_bounds__(256) void k_pose_bwd_v(int N, const float* __restrict__ pose, const float* __restrict__ gw,
+                                                    float* __restrict__ gv) {
+  pose_bwd_v_block(N, pose, gw, gv, blockIdx.x);
+}
+
 // One block: gR = sum_i gw_i v_i^T, gt = sum_i gw_i, then the chain rule
 // through the Euler angles.
-__global__ __launch_bounds__(1024) void k_pose_bwd_p(const float* __restrict__ v, int N, const float* __restrict__ pose,
-                                                     const float* __restrict__ gw, float* __restrict__ gpose) {
+__device__ __forceinline__ void pose_bwd_p_block(const float* __restrict__ v, int N, const float* __restrict__ pose,
+                                                     const float* __restrict__ gw, float* __restrict__ gpose, int bid) {
   __shared__ float red[12][1024];
   float acc[12];
   for (int k = 0; k < 12; ++k) acc[k] = 0.0f;
@@ -240,6 +280,11 @@ __global__ __launch_bounds__(1024) void k_pose_bwd_p(const float* __restrict__ v
   }
 }
 
+__global__ __launch_bounds__(1024) void k_pose_bwd_p(const float* __restrict__ v, int N, const float* __restrict__ pose,
+                                                     const float* __restrict__ gw, float* __restrict__ gpose) {
+  pose_bwd_p_block(v, N, pose, gw, gpose, blockIdx.x);
+}
+
 void launch_pose(const float* v, int N, const float* pose, float* vw, hipStream_t st) {
   hipLaunchKernelGGL(k_pose, dim3(cdiv(N, 256)), dim3(256), 0, st, v, N, pose, vw);
 }
@@ -253,10 +298,10 @@ void launch_pose_backward(const float* v, int N, const float* pose, const float*
 // ---------------------------------------------------------------------------
 // Adam
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+__device__ __forceinline__ void adam_block(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                                               float* __restrict__ v, const float* __restrict__ lr, int n, float b1,
-                                              float b2, float eps, float c1, float c2) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+                                              float b2, float eps, float c1, float c2, int bid) {
+  const int i = bid * 256 + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
   const float mi = b1 * m[i] + (1.0f - b1) * gi;
@@ -264,6 +309,12 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
   m[i] = mi;
   v[i] = vi;
   p[i] -= lr[i] * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, const float* __restrict__ lr, int n, float b1,
+                                              float b2, float eps, float c1, float c2) {
+  adam_block(p, g, m, v, lr, n, b1, b2, eps, c1, c2, blockIdx.x);
 }
 
 void launch_adam(float* p, const float* g, float* m, float* v, const float* lr, int n, int t, float b1, float b2,
@@ -276,10 +327,10 @@ void launch_adam(float* p, const float* g, float* m, float* v, const float* lr, 
 // ---------------------------------------------------------------------------
 // Light records: na = -kappa (e1 x e2), kappa = 1 or 1/2.
 // ---------------------------------------------------------------------------
-__global__ void k_light_setup(const float* __restrict__ p0, const float* __restrict__ e1, const float* __restrict__ e2,
+__device__ __forceinline__ void light_setup_block(const float* __restrict__ p0, const float* __restrict__ e1, const float* __restrict__ e2,
                               const float* __restrict__ rad, const int32_t* __restrict__ shape, int L,
-                              LightRec* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+                              LightRec* __restrict__ out, int bid) {
+  const int j = bid * blockDim.x + threadIdx.x;
   if (j >= L) return;
   LightRec r;
   const V3 a = ld3(e1, j), b = ld3(e2, j);
@@ -291,19 +342,33 @@ __global__ void k_light_setup(const float* __restrict__ p0, const float* __restr
   out[j] = r;
 }
 
+__global__ void k_light_setup(const float* __restrict__ p0, const float* __restrict__ e1, const float* __restrict__ e2,
+                              const float* __restrict__ rad, const int32_t* __restrict__ shape, int L,
+                              LightRec* __restrict__ out) {
+  light_setup_block(p0, e1, e2, rad, shape, L, out, blockIdx.x);
+}
+
 void launch_light_setup(const fr_scene& sc, LightRec* out, hipStream_t st) {
   hipLaunchKernelGGL(k_light_setup, dim3(cdiv(sc.n_lights, 64)), dim3(64), 0, st, sc.light_p0, sc.light_e1,
                      sc.light_e2, sc.light_rad, sc.light_shape, sc.n_lights, out);
 }
 
-__global__ void k_zero_f32(float* __restrict__ p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void zero_f32_block(float* __restrict__ p, int n, int bid) {
+  const int i = bid * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0f;
 }
 
-__global__ void k_axpy(float* __restrict__ dst, const float* __restrict__ src, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_zero_f32(float* __restrict__ p, int n) {
+  zero_f32_block(p, n, blockIdx.x);
+}
+
+__device__ __forceinline__ void axpy_block(float* __restrict__ dst, const float* __restrict__ src, int n, int bid) {
+  const int i = bid * blockDim.x + threadIdx.x;
   if (i < n) dst[i] += src[i];
+}
+
+__global__ void k_axpy(float* __restrict__ dst, const float* __restrict__ src, int n) {
+  axpy_block(dst, src, n, blockIdx.x);
 }
 
 void launch_zero(float* p, int n, hipStream_t st) {

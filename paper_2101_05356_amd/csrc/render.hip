@@ -11,10 +11,12 @@
 namespace fr {
 
 template <bool DUMP>
-__global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, float* __restrict__ image) {
+__device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __restrict__ image, int bid) {
   const int lane = threadIdx.x & 63;
-  const int tile = wave_tile(a);
-  if (tile < 0) return;
+  const Item it = wave_item(a, bid);
+  if (it.tile < 0) return;
+  const int tile = it.tile;
+  const int j0 = it.chunk * a.lc, j1 = min(a.L, j0 + a.lc);
   PixelSample ps = pixel_sample(a, tile, lane);
   float acc[3] = {0.0f, 0.0f, 0.0f};
   TravStats st = {0, 0, 0, 0, 0};
@@ -26,16 +28,16 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, float* __restr
     HitState h;
     h.t = 3.4e38f; h.id = -1; h.tamb = 3.4e38f;
     bool dummy = false;
-    trace<false, DUMP>(a.nodes, a.recs, a.F, sm.ray, ps.valid, -1, h, dummy, &st);
+    trace<false, DUMP>(a.nodes, a.recs, a.F, sm.ray, ps.valid, -1, h, dummy, it.chunk == 0 ? &st : nullptr);
     const size_t rs = (size_t)ps.pid * a.S + s;
     Frame fr;
     const bool shaded = ps.valid && h.id >= 0 && shading_frame(a, sm, h, fr);
-    if (DUMP && ps.valid) {
+    if (DUMP && ps.valid && it.chunk == 0) {
       a.dbg_hit[rs] = h.id;
       const bool pf = hit_ambiguous(h) || (h.id >= 0 && fabsf(fr.cos_o) < kFlagCos);
       a.dbg_pflag[rs] = pf ? 1 : 0;
     }
-    for (int j = 0; j < a.L; ++j) {
+    for (int j = j0; j < j1; ++j) {
       const LightRec& Lj = a.lights[j];
       LightSample ls;
       const bool lit = shaded && light_sample(a, ps.pid, s, j, Lj, fr, ls);
@@ -77,18 +79,43 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, float* __restr
   for (int k = 0; k < 3; ++k) acc[k] = group_sum(acc[k], a.lanes_per_pixel);
   if (ps.valid && ps.s0 == 0) {
     const float inv = 1.0f / (float)a.S;
-    image[3 * ps.pid] = acc[0] * inv;
-    image[3 * ps.pid + 1] = acc[1] * inv;
-    image[3 * ps.pid + 2] = acc[2] * inv;
+    float* out = a.n_lchunks > 1 ? a.partial + (size_t)it.chunk * 3 * a.W * a.H : image;
+    out[3 * ps.pid] = acc[0] * inv;
+    out[3 * ps.pid + 1] = acc[1] * inv;
+    out[3 * ps.pid + 2] = acc[2] * inv;
   }
 }
 
+template <bool DUMP>
+__global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, float* __restrict__ image) {
+  render_fwd_block<DUMP>(a, image, blockIdx.x);
+}
+
+// image = sum over light chunks of the partial images, in chunk order.
+__device__ __forceinline__ void sum_chunks_block(const float* __restrict__ partial, int n, int nch,
+                                                 float* __restrict__ image, int bid) {
+  const int i = bid * 256 + threadIdx.x;
+  if (i >= n) return;
+  float acc = partial[i];
+  for (int c = 1; c < nch; ++c) acc += partial[(size_t)c * n + i];
+  image[i] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_sum_chunks(const float* __restrict__ partial, int n, int nch,
+                                                    float* __restrict__ image) {
+  sum_chunks_block(partial, n, nch, image, blockIdx.x);
+}
+
 void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st) {
-  const int blocks = wave_blocks_strips(a);
+  const int blocks = wave_blocks_items(a);
   if (a.dbg_hit)
     hipLaunchKernelGGL(k_render_fwd<true>, dim3(blocks), dim3(256), 0, st, a, image);
   else
     hipLaunchKernelGGL(k_render_fwd<false>, dim3(blocks), dim3(256), 0, st, a, image);
+  if (a.n_lchunks > 1) {
+    const int n = 3 * a.W * a.H;
+    hipLaunchKernelGGL(k_sum_chunks, dim3((n + 255) / 256), dim3(256), 0, st, a.partial, n, a.n_lchunks, image);
+  }
 }
 
 }  // namespace fr

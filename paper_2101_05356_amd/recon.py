@@ -1,0 +1,304 @@
+"""Face reconstruction by analysis-by-synthesis (Sec. 4 "Optimization
+strategy", Sec. 5): the parameters [alpha, delta | beta | pose | light
+radiance] of a morphable face are fitted to a target image with Adam.
+
+Two ways to run the same optimisation step, both entirely in libfr:
+
+* `Reconstruction` composes the step from the single-job entry points
+  (blend, pose, mesh update, render, loss, backward + boundary term, pose and
+  blend adjoints, Adam), one launch sequence per job;
+* `Batch` steps many jobs at once (fr_batch_*): one launch per stage for all
+  jobs, replayed from a hipGraph.
+
+Both follow the same step convention: step k (1-based) renders with Philox
+counter word 4 = k and applies Adam with bias correction at t = k.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _lib
+from . import render as R
+from . import scenes
+from ._lib import FrJobDesc, check, lib
+
+
+def _dev(a, device, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dtype).contiguous()
+
+
+@dataclasses.dataclass
+class ModelTensors:
+    """Device copy of a morphable model (Sec. 3.1 / 3.2)."""
+    mean_geo: torch.Tensor     # [3N]
+    basis_geo: torch.Tensor    # [K_s + K_e, 3N] identity then expression
+    mean_alb: torch.Tensor     # [3N]
+    basis_alb: torch.Tensor    # [K_r, 3N]
+    specular: torch.Tensor     # [N,3]
+    roughness: torch.Tensor    # [N]
+    tris: np.ndarray           # [F,3] int32 (host)
+    K_id: int
+
+    @property
+    def N(self):
+        return self.mean_geo.numel() // 3
+
+    @property
+    def K_geo(self):
+        return self.basis_geo.shape[0]
+
+    @property
+    def K_alb(self):
+        return self.basis_alb.shape[0]
+
+    @staticmethod
+    def from_model(m: scenes.MorphModel, device="cuda") -> "ModelTensors":
+        return ModelTensors(
+            mean_geo=_dev(m.mean_shape, device), basis_geo=_dev(np.concatenate([m.basis_id, m.basis_exp]), device),
+            mean_alb=_dev(m.mean_albedo, device), basis_alb=_dev(m.basis_alb, device),
+            specular=_dev(m.specular, device), roughness=_dev(m.roughness, device),
+            tris=np.ascontiguousarray(m.tris, np.int32), K_id=int(m.basis_id.shape[0]))
+
+
+def param_slices(K_geo, K_alb, L):
+    o_alb, o_pose, o_rad = K_geo, K_geo + K_alb, K_geo + K_alb + 6
+    return dict(geo=slice(0, o_alb), alb=slice(o_alb, o_pose), pose=slice(o_pose, o_rad),
+                rad=slice(o_rad, o_rad + 3 * L))
+
+
+def learning_rates(mt: ModelTensors, L: int) -> np.ndarray:
+    """Per-parameter Adam step sizes of Sec. 5: identity 1e-2, expression
+    1e-3, albedo 2e-2, pose 1e-3, light radiance 1e-3."""
+    sl = param_slices(mt.K_geo, mt.K_alb, L)
+    lr = np.zeros(sl["rad"].stop, np.float32)
+    lr[0:mt.K_id] = 1e-2
+    lr[mt.K_id:mt.K_geo] = 1e-3
+    lr[sl["alb"]] = 2e-2
+    lr[sl["pose"]] = 1e-3
+    lr[sl["rad"]] = 1e-3
+    return lr
+
+
+@dataclasses.dataclass
+class JobSpec:
+    """One reconstruction: image size, samples, lights, camera, target,
+    initial parameters and learning rates (device tensors)."""
+    W: int
+    H: int
+    spp: int
+    lights: scenes.Lights
+    camera: scenes.Camera
+    target: torch.Tensor       # [H,W,3]
+    params: torch.Tensor       # [n_param]
+    lr: torch.Tensor           # [n_param]
+    seed: int = 4
+    edge_samples: int = -1     # -1: W*H, 0: off
+    smooth: bool = True
+    brdf_variant: int = 0
+    hist_cap: int = 1024
+
+    @property
+    def L(self):
+        return self.lights.count
+
+
+class Reconstruction:
+    """Single-job optimisation step composed from the per-call entry points."""
+
+    def __init__(self, ctx: R.Context, mt: ModelTensors, job: JobSpec):
+        self.ctx, self.mt, self.job = ctx, mt, job
+        dev = mt.mean_geo.device
+        L = job.L
+        self.sl = param_slices(mt.K_geo, mt.K_alb, L)
+        cam = job.camera
+        sc = scenes.Scene(verts=np.zeros((mt.N, 3), np.float32), tris=mt.tris,
+                          diffuse=np.zeros((mt.N, 3), np.float32), specular=np.zeros((mt.N, 3), np.float32),
+                          roughness=np.zeros(mt.N, np.float32), lights=job.lights, camera=cam, spp=job.spp,
+                          seed=job.seed, step=0)
+        self.ds = R.DeviceScene.from_scene(sc, dev)
+        self.ds.specular, self.ds.roughness = mt.specular.view(-1, 3), mt.roughness
+        self.mesh = R.Mesh(ctx, mt.N, mt.tris)
+        self.param = job.params.clone()
+        self.lr = job.lr
+        self.m = torch.zeros_like(self.param)
+        self.v = torch.zeros_like(self.param)
+        self.grad = torch.zeros_like(self.param)
+        self.t = 0
+        N = mt.N
+        self.v_obj = torch.empty(3 * N, dtype=torch.float32, device=dev)
+        self.v_w = torch.empty(3 * N, dtype=torch.float32, device=dev)
+        self.diffuse = torch.empty(3 * N, dtype=torch.float32, device=dev)
+        self.g_vobj = torch.zeros(3 * N, dtype=torch.float32, device=dev)
+        self.losses = []
+        self.geometry(rebuild=True)
+
+    def scene(self):
+        return dataclasses.replace(self.ds, verts=self.v_w.view(-1, 3), diffuse=self.diffuse.view(-1, 3),
+                                   light_rad=self.param[self.sl["rad"]].view(-1, 3), step=self.t)
+
+    def geometry(self, rebuild=False):
+        mt = self.mt
+        R.blend(mt.mean_geo, mt.basis_geo, self.param[self.sl["geo"]], out=self.v_obj)
+        R.blend(mt.mean_alb, mt.basis_alb, self.param[self.sl["alb"]], out=self.diffuse)
+        R.pose_forward(self.v_obj, self.param[self.sl["pose"]], out=self.v_w)
+        self.mesh.update(self.v_w, rebuild=rebuild)
+
+    def render(self):
+        return R.render_forward(self.mesh, self.scene(), self.job.brdf_variant, verts=self.v_w)
+
+    def step(self, events=None):
+        """One optimisation step; `events` (dict of start/end pairs) times the render calls.
+        Returns the loss (device tensor [1]) of the image rendered at this step."""
+        job, mt, sl = self.job, self.mt, self.sl
+        self.t += 1
+        self.geometry(rebuild=False)
+        sc = self.scene()
+        if events is not None:
+            events["fwd"][0].record()
+        img = R.render_forward(self.mesh, sc, job.brdf_variant, verts=self.v_w)
+        if events is not None:
+            events["fwd"][1].record()
+        E, dEdp = R.loss(img, job.target, smooth=job.smooth)
+        self.grad.zero_()
+        self.g_vobj.zero_()
+        if events is not None:
+            events["bwd"][0].record()
+        g = R.render_backward(self.mesh, sc, dEdp, job.brdf_variant, edge_samples=job.edge_samples,
+                              groups=("verts", "diffuse", "light_rad"), verts=self.v_w)
+        if events is not None:
+            events["bwd"][1].record()
+        R.pose_backward(self.v_obj, self.param[sl["pose"]], g["verts"], self.g_vobj, self.grad[sl["pose"]])
+        R.blend_backward(mt.basis_geo, self.g_vobj, self.grad[sl["geo"]])
+        R.blend_backward(mt.basis_alb, g["diffuse"], self.grad[sl["alb"]])
+        self.grad[sl["rad"]] += g["light_rad"].view(-1)
+        R.adam_step(self.param, self.grad, self.m, self.v, self.lr, self.t)
+        self.last_image = img
+        return E
+
+
+def render_params(ctx, mt: ModelTensors, job: JobSpec, params: torch.Tensor) -> torch.Tensor:
+    """Image of the face with the given parameters (e.g. a synthetic target)."""
+    rc = Reconstruction(ctx, mt, dataclasses.replace(job, params=params))
+    return rc.render()
+
+
+def face_job(mt: ModelTensors, rng: np.random.Generator, ctx, W=256, spp=16, n_lights=72, seed=4,
+             edge_samples=-1, hist_cap=1024, device="cuda") -> tuple[JobSpec, torch.Tensor]:
+    """A synthetic reconstruction: ground-truth parameters drawn from `rng`,
+    target rendered from them (on the device); the start point has zero
+    coefficients, a perturbed pose and 0.8x the light radiance.
+    Returns (job, true parameters)."""
+    lights = scenes.face_lights(n_lights)
+    cam = scenes.face_camera(W, W)
+    L = lights.count
+    sl = param_slices(mt.K_geo, mt.K_alb, L)
+    K_e = mt.K_geo - mt.K_id
+    p_true = np.concatenate([rng.standard_normal(mt.K_id), rng.standard_normal(K_e), rng.standard_normal(mt.K_alb),
+                             np.radians(rng.uniform(-10.0, 10.0, 3)), rng.normal(0.0, 0.05, 3),
+                             np.asarray(lights.rad, np.float64).reshape(-1)]).astype(np.float32)
+    lr = _dev(learning_rates(mt, L), device)
+    job = JobSpec(W=W, H=W, spp=spp, lights=lights, camera=cam, target=None, params=_dev(p_true, device), lr=lr,
+                  seed=seed, edge_samples=edge_samples, hist_cap=hist_cap)
+    target = render_params(ctx, mt, job, job.params).contiguous()
+    p0 = p_true.copy()
+    p0[:mt.K_geo + mt.K_alb] = 0.0
+    p0[sl["pose"]] += np.array([0.05, -0.05, 0.03, 0.02, -0.02, 0.01], np.float32)
+    p0[sl["rad"]] *= 0.8
+    return dataclasses.replace(job, target=target, params=_dev(p0, device)), _dev(p_true, device)
+
+
+class Model:
+    """fr_model: topology and morphable model shared by the jobs of a batch."""
+
+    def __init__(self, ctx: R.Context, mt: ModelTensors):
+        self.ctx, self.mt = ctx, mt
+        h = ctypes.c_void_p()
+        tris = np.ascontiguousarray(mt.tris, np.int32)
+        check(lib().fr_model_create(ctx.h, mt.N, tris.shape[0], tris.ctypes.data_as(ctypes.c_void_p),
+                                    R._p(mt.mean_geo), R._p(mt.basis_geo), mt.K_geo, R._p(mt.mean_alb),
+                                    R._p(mt.basis_alb), mt.K_alb, R._p(mt.specular), R._p(mt.roughness),
+                                    ctypes.byref(h)), ctx.h, "fr_model_create")
+        self.h = h
+
+    def n_param(self, n_lights):
+        return int(lib().fr_model_n_param(self.h, n_lights))
+
+    def job_bytes(self, job: JobSpec) -> int:
+        d, _keep = _desc(job)
+        return int(lib().fr_job_bytes(self.h, ctypes.byref(d)))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None and _lib._lib is not None:
+            _lib._lib.fr_model_destroy(self.h)
+            self.h = None
+
+
+def _desc(job: JobSpec):
+    """fr_job_desc of a job, plus the tensors it points to (keep them alive)."""
+    dev = job.params.device
+    lt = job.lights
+    keep = dict(p0=_dev(lt.p0, dev), e1=_dev(lt.e1, dev), e2=_dev(lt.e2, dev),
+                shape=_dev(lt.shape, dev, torch.int32),
+                cam=_dev(np.concatenate([np.asarray(job.camera.R, np.float32).reshape(9),
+                                         np.asarray(job.camera.T, np.float32)]), dev),
+                target=job.target.contiguous(), params=job.params.contiguous(), lr=job.lr.contiguous())
+    d = FrJobDesc()
+    d.width, d.height, d.spp, d.n_lights = job.W, job.H, job.spp, job.L
+    d.edge_samples, d.smooth, d.brdf_variant, d.hist_cap = job.edge_samples, int(job.smooth), job.brdf_variant, \
+        job.hist_cap
+    d.seed, d.fov_y = job.seed, float(job.camera.fov_y)
+    d.cam, d.light_p0, d.light_e1, d.light_e2 = (keep[k].data_ptr() for k in ("cam", "p0", "e1", "e2"))
+    d.light_shape, d.target, d.params, d.lr = (keep[k].data_ptr() for k in ("shape", "target", "params", "lr"))
+    return d, keep
+
+
+class Batch:
+    """fr_batch: jobs stepped together, one launch per stage for all of them."""
+
+    def __init__(self, model: Model):
+        self.model = model
+        h = ctypes.c_void_p()
+        check(lib().fr_batch_create(model.h, ctypes.byref(h)), model.ctx.h, "fr_batch_create")
+        self.h = h
+        self.jobs = {}
+
+    def add(self, job: JobSpec) -> int:
+        d, keep = _desc(job)
+        jid = ctypes.c_int32()
+        check(lib().fr_batch_add(self.h, ctypes.byref(d), ctypes.byref(jid), R._stream()), self.model.ctx.h,
+              "fr_batch_add")
+        torch.cuda.current_stream().synchronize()   # the inputs were copied; `keep` may go
+        self.jobs[jid.value] = job
+        return jid.value
+
+    def remove(self, jid: int):
+        check(lib().fr_batch_remove(self.h, jid), self.model.ctx.h, "fr_batch_remove")
+        del self.jobs[jid]
+
+    def __len__(self):
+        return int(lib().fr_batch_size(self.h))
+
+    def step(self, n=1, graph=True):
+        check(lib().fr_batch_step(self.h, n, 1 if graph else 0, R._stream()), self.model.ctx.h, "fr_batch_step")
+
+    def read(self, jid: int, image=False):
+        """dict(params, grad [n_param], losses [steps done], t, image [H,W,3] or None), host arrays."""
+        job = self.jobs[jid]
+        n = self.model.n_param(job.L)
+        params, grad = np.zeros(n, np.float32), np.zeros(n, np.float32)
+        hist = np.zeros(max(job.hist_cap, 1), np.float32)
+        img = np.zeros((job.H, job.W, 3), np.float32) if image else None
+        t = ctypes.c_int32()
+        c = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+        check(lib().fr_batch_read(self.h, jid, c(params), c(grad), c(hist), c(img), ctypes.byref(t), R._stream()),
+              self.model.ctx.h, "fr_batch_read")
+        return dict(params=params, grad=grad, losses=hist[:min(t.value, hist.size)], t=t.value, image=img)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None and _lib._lib is not None:
+            _lib._lib.fr_batch_destroy(self.h)
+            self.h = None

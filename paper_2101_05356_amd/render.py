@@ -145,9 +145,10 @@ class DeviceScene:
         return s
 
 
-def _opts(brdf_variant=0, components=3, edge_samples=0, dbg=None) -> FrRenderOpts:
+def _opts(brdf_variant=0, components=3, edge_samples=0, dbg=None, light_chunk=0) -> FrRenderOpts:
     o = FrRenderOpts()
     o.brdf_variant, o.components, o.edge_samples = int(brdf_variant), int(components), int(edge_samples)
+    o.light_chunk = int(light_chunk)
     if dbg is not None:
         o.dbg_hit = dbg[0].data_ptr() if dbg[0] is not None else None
         o.dbg_pflag = dbg[1].data_ptr() if dbg[1] is not None else None
@@ -155,7 +156,8 @@ def _opts(brdf_variant=0, components=3, edge_samples=0, dbg=None) -> FrRenderOpt
     return o
 
 
-def render_forward(mesh: Mesh, sc: DeviceScene, brdf_variant=0, components=3, dump=False, verts=None, stats=None):
+def render_forward(mesh: Mesh, sc: DeviceScene, brdf_variant=0, components=3, dump=False, verts=None, stats=None,
+                   light_chunk=0):
     """Image [H,W,3]; with dump=True also (hit [H*W,S], pflag [H*W,S], vis [H*W,S,L]).
     `stats` (a uint64-sized int64 tensor [10], dump only) accumulates traversal counts."""
     dev = sc.verts.device
@@ -166,7 +168,7 @@ def render_forward(mesh: Mesh, sc: DeviceScene, brdf_variant=0, components=3, du
         dbg = (torch.full((n,), -7, dtype=torch.int32, device=dev), torch.zeros(n, dtype=torch.uint8, device=dev),
                torch.full((n * max(sc.n_lights, 1),), 0xEE, dtype=torch.uint8, device=dev))
     s = sc.struct(verts)
-    o = _opts(brdf_variant, components, 0, dbg)
+    o = _opts(brdf_variant, components, 0, dbg, light_chunk)
     if stats is not None:
         assert dump and stats.dtype == torch.int64 and stats.numel() == 10
         o.dbg_stats = stats.data_ptr()
@@ -192,7 +194,7 @@ GRAD_GROUPS = ("verts", "normals", "diffuse", "specular", "roughness", "light_ge
 
 
 def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_variant=0, components=3,
-                    edge_samples=0, groups=GRAD_GROUPS, verts=None, edge_dump=False):
+                    edge_samples=0, groups=GRAD_GROUPS, verts=None, edge_dump=False, light_chunk=0):
     """Gradients (dict of new tensors) of sum dEdp . image."""
     dev = sc.verts.device
     N, L = mesh.n_verts, sc.n_lights
@@ -208,7 +210,7 @@ def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_varian
         dbg = (torch.full((ns * 4,), -7, dtype=torch.int32, device=dev), torch.zeros(ns, dtype=torch.uint8, device=dev),
                None)
     s = sc.struct(verts)
-    o = _opts(brdf_variant, components, edge_samples, dbg)
+    o = _opts(brdf_variant, components, edge_samples, dbg, light_chunk)
     check(lib().fr_render_backward(mesh.h, ctypes.byref(s), ctypes.byref(o), _p(dEdp.contiguous()), ctypes.byref(g),
                                    _stream()), mesh.ctx.h, "fr_render_backward")
     if edge_dump and dbg is not None:

@@ -1,0 +1,97 @@
+"""The reconstruction server on the GPU (fr_server_*): requests of different
+image sizes, samples and light counts are served with continuous batching;
+each result equals the same job run alone (loss within 1e-4 relative,
+parameters within 5% of one Adam step, see test_gpu_batch), with the budget
+forcing one-at-a-time service or not."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2101_05356_amd import scenes
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def env():
+    from paper_2101_05356_amd import recon, serve
+    from paper_2101_05356_amd import render as R
+    ctx = R.Context(0)
+    model = scenes.synthetic_morph_model(seed=31, n_lon=40, n_ring=26, K_s=6, K_e=4, K_r=6)
+    mt = recon.ModelTensors.from_model(model)
+    m = recon.Model(ctx, mt)
+    specs = [(24, 2, 5), (40, 4, 3), (16, 8, 7), (32, 1, 4)]
+    jobs = []
+    for i, (W, spp, L) in enumerate(specs):
+        job, _ = recon.face_job(mt, np.random.default_rng(100 + i), ctx, W=W, spp=spp, n_lights=L, seed=50 + i,
+                                hist_cap=16)
+        jobs.append(job)
+    return recon, serve, ctx, mt, m, jobs
+
+
+def alone(env, job, n):
+    recon, _, ctx, mt, m, _ = env
+    b = recon.Batch(m)
+    jid = b.add(job)
+    b.step(n)
+    torch.cuda.synchronize()
+    return b.read(jid)
+
+
+def check_same(res, ref, job):
+    lr = job.lr.cpu().numpy()
+    assert res["state_name"] == "done" and res["status"] == 0
+    assert res["steps_done"] == ref["t"] and res["n_losses"] == ref["t"]
+    assert np.all(np.abs(res["losses"] - ref["losses"]) <= 1e-4 * np.abs(ref["losses"]))
+    assert np.all(np.abs(res["params"] - ref["params"]) <= 2e-6 + 1e-5 * np.abs(ref["params"]) + 0.05 * lr)
+
+
+@pytest.mark.parametrize("one_at_a_time", [False, True])
+def test_served_results_equal_jobs_run_alone(env, one_at_a_time):
+    recon, serve, ctx, mt, m, jobs = env
+    n_steps = [5, 7, 3, 6]
+    budget = max(m.job_bytes(j) for j in jobs) if one_at_a_time else 8 << 30
+    srv = serve.Server(m, hbm_budget=budget, max_slots=8, quantum=2)
+    try:
+        ids = [srv.submit(j, n) for j, n in zip(jobs, n_steps)]
+        assert srv.wait(300.0)
+        st = srv.stats()
+        assert st["completed"] == 4 and st["failed"] == 0 and st["active"] == 0 and st["queued"] == 0
+        sizes = sorted(m.job_bytes(j) for j in jobs)
+        if one_at_a_time and sizes[0] + sizes[1] > budget:
+            assert st["peak_active"] == 1
+        elif not one_at_a_time:
+            assert st["peak_active"] >= 2
+        assert st["p99_s"] >= st["p50_s"] > 0 and st["recons_per_s"] > 0
+        for rid, job, n in zip(ids, jobs, n_steps):
+            check_same(srv.poll(rid), alone(env, job, n), job)
+    finally:
+        srv.close()
+
+
+def test_budget_rejection_and_cancel(env):
+    recon, serve, ctx, mt, m, jobs = env
+    # the server keeps max(hist_cap, n_steps) losses per request
+    budget = m.job_bytes(dataclasses.replace(jobs[0], hist_cap=200))
+    srv = serve.Server(m, hbm_budget=budget, max_slots=1, quantum=1)
+    try:
+        big = max(jobs, key=m.job_bytes)
+        assert m.job_bytes(big) > budget
+        with pytest.raises(Exception, match="budget"):
+            srv.submit(big, 3)
+        a = srv.submit(jobs[0], 200)
+        b = srv.submit(jobs[0], 3)
+        srv.cancel(b)          # still queued behind a
+        srv.cancel(a)
+        assert srv.wait(300.0)
+        ra, rb = srv.poll(a), srv.poll(b)
+        assert rb["state_name"] == "cancelled" and rb["steps_done"] == 0
+        assert ra["state_name"] == "cancelled" and ra["steps_done"] < 200
+        assert srv.stats()["bytes_in_use"] == 0
+        srv.forget(b)
+        with pytest.raises(Exception):
+            srv.poll(b)
+    finally:
+        srv.close()
