@@ -8,7 +8,11 @@ edge-sampling boundary term, pose and blend adjoints, Adam.  Inputs are
 synthetic and resident in HBM before the timed region.
 
 Prints one JSON line (see the "metric" field).  The headline value is nominal
-forward rays per second of whole steps: W*H*spp*(1 + L) / step time.
+forward rays per second of whole steps: W*H*spp*(1 + L) / step time.  The
+same line carries the roofline of the dominant kernel, traversal statistics,
+the batched step over 32 faces of mixed sizes ("batch"), the serving run
+(Poisson arrivals, continuous batching vs one at a time: recons/s, p50/p99
+latency; "serving") and the FP64 oracle's rate on the host ("cpu_baseline").
 """
 from __future__ import annotations
 
@@ -51,126 +55,15 @@ def parse():
     ap.add_argument("--edge-samples", type=int, default=-1, help="-1 = W*H")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--profile-only", action="store_true", help="skip stats and CPU baseline (for profilers)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the timed single-face steps (for profilers)")
+    ap.add_argument("--batch-jobs", type=int, default=32, help="faces in the batched-step measurement (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--serve-requests", type=int, default=8, help="requests in the serving measurement (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-steps", type=int, default=150, help="Adam steps per request")
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     return ap.parse_args()
-
-
-class Step:
-    """Device state and launch sequence of one optimisation step."""
-
-    def __init__(self, width, spp, n_lights, edge_samples):
-        import torch
-        from paper_2101_05356_amd import render as R
-        from paper_2101_05356_amd import scenes
-        self.torch, self.R = torch, R
-        dev = "cuda"
-        model = scenes.synthetic_morph_model(seed=11)
-        rng = np.random.default_rng(12)
-        truth = scenes.random_face_params(rng, model)
-        self.W = self.H = width
-        self.spp, self.L = spp, n_lights
-        self.edge_samples = edge_samples
-        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(dev)
-        self.mean_geo = f(model.mean_shape)
-        self.basis_geo = f(np.concatenate([model.basis_id, model.basis_exp]))
-        self.mean_alb = f(model.mean_albedo)
-        self.basis_alb = f(model.basis_alb)
-        self.K_geo, self.K_alb = self.basis_geo.shape[0], self.basis_alb.shape[0]
-        N = model.n_verts
-        self.N = N
-        lights = scenes.face_lights(n_lights)
-        cam = scenes.face_camera(width, width)
-        base = scenes.Scene(verts=model.mean_shape.reshape(-1, 3), tris=model.tris,
-                            diffuse=model.mean_albedo.reshape(-1, 3), specular=model.specular,
-                            roughness=model.roughness, lights=lights, camera=cam, spp=spp, seed=4, step=0)
-        self.ds = R.DeviceScene.from_scene(base, dev)
-        self.ctx = R.Context(0)
-        self.mesh = R.Mesh(self.ctx, N, model.tris)
-        # parameter vector: [alpha, delta | beta | pose | light radiance]
-        nrad = 3 * n_lights
-        self.n_param = self.K_geo + self.K_alb + 6 + nrad
-        self.param = torch.zeros(self.n_param, dtype=torch.float32, device=dev)
-        self.sl_geo = slice(0, self.K_geo)
-        self.sl_alb = slice(self.K_geo, self.K_geo + self.K_alb)
-        self.sl_pose = slice(self.K_geo + self.K_alb, self.K_geo + self.K_alb + 6)
-        self.sl_rad = slice(self.K_geo + self.K_alb + 6, self.n_param)
-        # learning rates of Sec. 5: identity 1e-2, blendshapes 1e-3, albedo 2e-2, pose 1e-3, lights 1e-3
-        lr = np.zeros(self.n_param, np.float32)
-        lr[0:model.basis_id.shape[0]] = 1e-2
-        lr[model.basis_id.shape[0]:self.K_geo] = 1e-3
-        lr[self.sl_alb] = 2e-2
-        lr[self.sl_pose] = 1e-3
-        lr[self.sl_rad] = 1e-3
-        self.lr = f(lr)
-        self.m = torch.zeros_like(self.param)
-        self.v = torch.zeros_like(self.param)
-        self.grad = torch.zeros_like(self.param)
-        self.t = 0
-        # buffers
-        self.v_obj = torch.empty(3 * N, dtype=torch.float32, device=dev)
-        self.v_w = torch.empty(3 * N, dtype=torch.float32, device=dev)
-        self.diffuse = torch.empty(3 * N, dtype=torch.float32, device=dev)
-        self.g_vobj = torch.zeros(3 * N, dtype=torch.float32, device=dev)
-        # target: render of the ground-truth parameters (GPU), before timing
-        p_true = np.concatenate([truth.alpha, truth.delta, truth.beta, truth.pose,
-                                 np.asarray(lights.rad, np.float32).reshape(-1)]).astype(np.float32)
-        self.param.copy_(f(p_true))
-        self._geometry(rebuild=True)
-        self.target = R.render_forward(self.mesh, self._scene(), verts=self.v_w).clone()
-        # start: zero coefficients, perturbed pose, radiance x 0.8
-        p0 = p_true.copy()
-        p0[:self.K_geo + self.K_alb] = 0.0
-        p0[self.sl_pose] += np.array([0.05, -0.05, 0.03, 0.02, -0.02, 0.01], np.float32)
-        p0[self.sl_rad] *= 0.8
-        self.param.copy_(f(p0))
-        self._geometry(rebuild=True)
-        torch.cuda.synchronize()
-
-    def _scene(self):
-        import dataclasses
-        return dataclasses.replace(self.ds, verts=self.v_w.view(-1, 3), diffuse=self.diffuse.view(-1, 3),
-                                   light_rad=self.param[self.sl_rad].view(-1, 3), step=self.t)
-
-    def _geometry(self, rebuild=False):
-        R = self.R
-        R.blend(self.mean_geo, self.basis_geo, self.param[self.sl_geo], out=self.v_obj)
-        R.blend(self.mean_alb, self.basis_alb, self.param[self.sl_alb], out=self.diffuse)
-        R.pose_forward(self.v_obj, self.param[self.sl_pose], out=self.v_w)
-        self.mesh.update(self.v_w, rebuild=rebuild)
-
-    def run(self, events=None):
-        """One optimisation step; `events` (dict of start/end pairs) times the render calls."""
-        R, torch = self.R, self.torch
-        self.t += 1
-        self._geometry(rebuild=False)
-        sc = self._scene()
-        if events is not None:
-            events["fwd"][0].record()
-        img = R.render_forward(self.mesh, sc, verts=self.v_w)
-        if events is not None:
-            events["fwd"][1].record()
-        E, dEdp = R.loss(img, self.target, smooth=True)
-        self.grad.zero_()
-        self.g_vobj.zero_()
-        if events is not None:
-            events["bwd"][0].record()
-        g = R.render_backward(self.mesh, sc, dEdp, edge_samples=self.edge_samples,
-                              groups=("verts", "diffuse", "light_rad"), verts=self.v_w)
-        if events is not None:
-            events["bwd"][1].record()
-        R.pose_backward(self.v_obj, self.param[self.sl_pose], g["verts"], self.g_vobj, self.grad[self.sl_pose])
-        R.blend_backward(self.basis_geo, self.g_vobj, self.grad[self.sl_geo])
-        R.blend_backward(self.basis_alb, g["diffuse"], self.grad[self.sl_alb])
-        self.grad[self.sl_rad] += g["light_rad"].view(-1)
-        R.adam_step(self.param, self.grad, self.m, self.v, self.lr, self.t)
-        return E
-
-    def traversal_stats(self):
-        torch = self.torch
-        st = torch.zeros(10, dtype=torch.int64, device="cuda")
-        self.R.render_forward(self.mesh, self._scene(), verts=self.v_w, dump=True, stats=st)
-        torch.cuda.synchronize()
-        return st.cpu().numpy().astype(np.float64)
 
 
 def algorithmic_ops(stats, W, H, S, L, backward=False):
@@ -211,6 +104,102 @@ def cpu_baseline(seconds, spp, n_lights, width):
                       f"brute-force forward decisions + shading + dual-number interior gradient, {dt:.1f} s"}
 
 
+def make_c2(ctx, width, spp, n_lights, edge_samples):
+    """The 256x256 face reconstruction: morphable model seed 11, truth seed 12."""
+    from paper_2101_05356_amd import recon, scenes
+    mt = recon.ModelTensors.from_model(scenes.synthetic_morph_model(seed=11))
+    job, _ = recon.face_job(mt, np.random.default_rng(12), ctx, W=width, spp=spp, n_lights=n_lights, seed=4,
+                            edge_samples=edge_samples)
+    return mt, recon.Reconstruction(ctx, mt, job)
+
+
+def traversal_stats(rc):
+    import torch
+    from paper_2101_05356_amd import render as R
+    st = torch.zeros(10, dtype=torch.int64, device="cuda")
+    R.render_forward(rc.mesh, rc.scene(), verts=rc.v_w, dump=True, stats=st)
+    torch.cuda.synchronize()
+    return st.cpu().numpy().astype(np.float64)
+
+
+def batch_bench(ctx, mt, n_jobs, steps, warmup, seed=31):
+    """32-face batch: resolutions from {128..512}^2, spp from {4, 8, 16}, a
+    seeded subset of 36..72 lights of the 72-light stage per face; one
+    graph-replayed batched step for all faces."""
+    import torch
+    from paper_2101_05356_amd import recon
+    rng = np.random.default_rng(seed)
+    jobs, nominal = [], 0
+    for i in range(n_jobs):
+        W = int(rng.choice([128, 192, 256, 384, 512]))
+        spp = int(rng.choice([4, 8, 16]))
+        L = int(rng.integers(36, 73))
+        idx = rng.choice(72, size=L, replace=False)
+        job, _ = recon.face_job(mt, np.random.default_rng(1000 + i), ctx, W=W, spp=spp, light_idx=idx,
+                                seed=2000 + i, hist_cap=steps + warmup)
+        jobs.append(job)
+        nominal += W * W * spp * (1 + L)
+    b = recon.Batch(recon.Model(ctx, mt))
+    for j in jobs:
+        b.add(j)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"jobs": n_jobs, "steps": steps, "ms_per_step": 1e3 * dt / steps, "nominal_rays_per_step": nominal,
+            "rays_per_s": nominal * steps / dt,
+            "workload": f"{n_jobs} faces, W from {{128..512}}, spp from {{4,8,16}}, 36..72 of 72 lights"}
+
+
+def serve_bench(ctx, mt, n_req, rate, n_steps, budget, seed=41):
+    """Poisson arrivals of reconstruction requests (resolution from
+    {128..512}^2, spp from {4, 8, 16, 32}, 72 lights, target rendered at 32
+    spp with its own seed), served with continuous batching and, as the
+    baseline, one at a time (one slot) with the same arrival times."""
+    from paper_2101_05356_amd import recon, serve
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n_req):
+        W = int(rng.choice([128, 192, 256, 384, 512]))
+        spp = int(rng.choice([4, 8, 16, 32]))
+        job, _ = recon.face_job(mt, np.random.default_rng(3000 + i), ctx, W=W, spp=spp, n_lights=72,
+                                seed=4000 + i, target_spp=32, target_seed=5000 + i, hist_cap=n_steps)
+        reqs.append(job)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    arrivals -= arrivals[0]
+    model = recon.Model(ctx, mt)
+
+    def run(max_slots):
+        srv = serve.Server(model, hbm_budget=budget, max_slots=max_slots, quantum=10)
+        try:
+            t0 = time.perf_counter()
+            ids = []
+            for a, job in zip(arrivals, reqs):
+                wait = t0 + a - time.perf_counter()
+                if wait > 0:
+                    time.sleep(wait)
+                ids.append(srv.submit(job, n_steps))
+            if not srv.wait(1800.0):
+                raise RuntimeError("serving did not finish")
+            st = srv.stats()
+            res = [srv.poll(i, want_params=False) for i in ids]
+        finally:
+            srv.close()
+        return st, res
+
+    st_b, res_b = run(max_slots=64)
+    st_s, res_s = run(max_slots=1)
+    rel = max(abs(a["final_loss"] - b["final_loss"]) / abs(b["final_loss"]) for a, b in zip(res_b, res_s))
+    pick = lambda st: {k: st[k] for k in ("recons_per_s", "p50_s", "p99_s", "mean_s", "peak_active", "completed",
+                                           "failed", "busy_s")}
+    return {"requests": n_req, "rate_per_s": rate, "steps_per_request": n_steps, "hbm_budget_gb": budget / 2**30,
+            "batched": pick(st_b), "serial": pick(st_s), "final_loss_max_rel_diff_vs_serial": rel,
+            "offered_load_over_serial_capacity": rate / max(st_s["recons_per_s"], 1e-9),
+            "workload": "C2 faces, W from {128..512}, spp from {4,8,16,32}, 72 lights, Adam with the Sec. 5 rates"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -218,18 +207,20 @@ def main():
                                    "design is described but not built)"}))
         sys.exit(2)
     import torch
+    from paper_2101_05356_amd import render as R
     W = H = args.width
     S, L = args.spp, args.lights
     ns = W * H if args.edge_samples < 0 else args.edge_samples
-    st = Step(W, S, L, args.edge_samples)
+    ctx = R.Context(0)
+    mt, rc = make_c2(ctx, W, S, L, args.edge_samples)
     for _ in range(args.warmup):
-        st.run()
+        rc.step()
     torch.cuda.synchronize()
     ev = {k: [] for k in ("fwd", "bwd")}
     t0 = time.perf_counter()
     for _ in range(args.steps):
         pair = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in ev}
-        E = st.run(pair)
+        E = rc.step(pair)
         for k in ev:
             ev[k].append(pair[k])
     torch.cuda.synchronize()
@@ -245,15 +236,17 @@ def main():
            "config": {"workload": f"{W}x{H} face: 28,002-vertex / 56,000-triangle morphable mesh, {S} spp, {L} "
                                   f"area lights, blend+pose+refit+render+loss+backward with {ns} edge samples+Adam",
                       "global_batch": 1, "seq_len": W * H, "parallelism": "single GPU"},
-           "fwd_ms": fwd_ms, "bwd_ms": bwd_ms, "loss": float(E.item())}
+           "render_fwd_kernel_ms": fwd_ms, "render_bwd_kernel_ms": bwd_ms, "loss": float(E.item())}
     if not args.profile_only:
-        stats = st.traversal_stats()
+        stats = traversal_stats(rc)
         ops_f = algorithmic_ops(stats, W, H, S, L)
         ops_b = algorithmic_ops(stats, W, H, S, L, backward=True)
-        dom, ops, ms = ("render_bwd", ops_b, bwd_ms) if bwd_ms >= fwd_ms else ("render_fwd", ops_f, fwd_ms)
+        dom, ops, ms = ("k_render_bwd", ops_b, bwd_ms) if bwd_ms >= fwd_ms else ("k_render_fwd", ops_f, fwd_ms)
         ach = ops / (ms * 1e-3)
         out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": ach / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                           "unit": "Tlane-op/s", "frac": ach / PEAK_LANE_OPS, "traffic": None}
+                           "unit": "Tlane-op/s", "frac": ach / PEAK_LANE_OPS, "traffic": None,
+                           "other": {"k_render_fwd": {"ms": fwd_ms, "achieved": ops_f / (fwd_ms * 1e-3) / 1e12,
+                                                      "frac": ops_f / (fwd_ms * 1e-3) / PEAK_LANE_OPS}}}
         cam_rays, sh_rays = stats[2], stats[5]
         out["traversal"] = {
             "camera_rays": cam_rays, "shadow_rays_traced": sh_rays,
@@ -263,6 +256,14 @@ def main():
             "simd_efficiency": (stats[0] + stats[1] + stats[3] + stats[4]) /
                                max(64.0 * (stats[6] + stats[7] + stats[8] + stats[9]), 1.0)}
         out["rays_cast_per_s"] = (W * H * S + sh_rays) * args.steps / dt
+        del rc
+        if args.batch_jobs > 0:
+            out["batch"] = batch_bench(ctx, mt, args.batch_jobs, args.batch_steps, 2)
+            print(json.dumps({"progress": "batch", **out["batch"]}), file=sys.stderr, flush=True)
+        if args.serve_requests > 0:
+            out["serving"] = serve_bench(ctx, mt, args.serve_requests, args.serve_rate, args.serve_steps,
+                                         int(args.serve_budget_gb * 2**30))
+            print(json.dumps({"progress": "serving"}), file=sys.stderr, flush=True)
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, S, L, W)
     print(json.dumps(out), flush=True)

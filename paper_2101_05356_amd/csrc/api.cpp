@@ -168,7 +168,8 @@ int mesh_from_topology(fr_ctx* ctx, const HostTopo& t, fr_mesh** out) {
             dalloc(&d.hist, 256 * (size_t)nb) == hipSuccess && dalloc(&d.partial, 64 * 6) == hipSuccess &&
             dalloc(&d.scene_box, 6) == hipSuccess && dalloc(&d.depth, 2) == hipSuccess &&
             dalloc(&d.edge_len, d.E) == hipSuccess && dalloc(&d.edge_cdf, d.E) == hipSuccess &&
-            dalloc(&d.face_front, F) == hipSuccess && dalloc(&d.scan_part, 1024) == hipSuccess;
+            dalloc(&d.face_front, F) == hipSuccess && dalloc(&d.scan_part, 1024) == hipSuccess &&
+            dalloc(&d.acc, 13 * (size_t)n_verts + 12) == hipSuccess;
   if (!ok) { fr_mesh_destroy(m); return fail(ctx, FR_ERR_OOM, "mesh allocation failed"); }
   ok = hipMemcpy(d.tris, t.tris.data(), sizeof(int32_t) * 3 * F, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(d.vf_off, t.off.data(), sizeof(int32_t) * (n_verts + 1), hipMemcpyHostToDevice) == hipSuccess &&
@@ -231,7 +232,7 @@ int fr_mesh_destroy(fr_mesh* m) {
   void* ptrs[] = {d.tris, d.vf_off, d.vf_idx, d.normals, d.nlen, d.gnorm, d.edges, d.edge_faces, d.nodes, d.recs,
                   d.order, d.node_parent, d.leaf_parent, d.flags, d.keys[0], d.keys[1], d.vals[0], d.vals[1],
                   d.hist, d.partial, d.scene_box, d.depth, d.lights, d.ltmp, d.edge_len, d.edge_cdf, d.face_front,
-                  d.scan_part, d.img_partial, m->loss_scratch, m->loss_gtmp};
+                  d.scan_part, d.img_partial, d.acc, d.slots, m->loss_scratch, m->loss_gtmp};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -297,7 +298,8 @@ int fr_render_forward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fl
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (s->n_lights > 0) fr::launch_light_setup(*s, m->d.lights, st);
-  fr::launch_render_forward(a, d_image, st);
+  fr::launch_render_forward(a, d_image, st, static_cast<hipEvent_t>(o->ev_kernel_begin),
+                            static_cast<hipEvent_t>(o->ev_kernel_end));
   FR_HIP(m->ctx, hipGetLastError());
   return FR_OK;
 }
@@ -335,14 +337,41 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
   if ((rc = ensure_lights(m, s->n_lights)) != FR_OK) return rc;
   a.lights = m->d.lights;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (s->n_lights > 0) fr::launch_light_setup(*s, m->d.lights, st);
-  fr::launch_zero(m->d.gnorm, 3 * m->d.N, st);
-  fr::launch_render_backward(a, d_dEdp, *g, m->d.gnorm, st);
-  if (g->normals) fr::launch_axpy(g->normals, m->d.gnorm, 3 * m->d.N, st);   // before the in-place projection
-  if (g->verts) fr::launch_normals_backward(m->d, s->verts, m->d.gnorm, g->verts, st);
+  fr::MeshDev& d = m->d;
+  const size_t need = (size_t)fr::kSlots * (12 * (size_t)s->n_lights + 12);
+  if (need > d.slots_cap) {
+    if (d.slots) (void)hipFree(d.slots);
+    d.slots = nullptr;
+    d.slots_cap = 0;
+    FR_HIP(m->ctx, dalloc(&d.slots, need));
+    d.slots_cap = need;
+  }
+  // fixed-point accumulators: verts, normals, diffuse, specular (3N each), roughness (N), camera (12)
+  const size_t N = d.N;
+  fr::fix_t* acc_v = d.acc;
+  fr::fix_t* acc_n = d.acc + 3 * N;
+  fr::fix_t* acc_c = d.acc + 6 * N;
+  fr::fix_t* acc_s = d.acc + 9 * N;
+  fr::fix_t* acc_r = d.acc + 12 * N;
+  fr::fix_t* acc_cam = d.acc + 13 * N;
+  fr::launch_zero_fix(d.acc, 13 * N + 12, st);
+  if (s->n_lights > 0) fr::launch_light_setup(*s, d.lights, st);
+  const bool want_n = g->normals || g->verts;
+  const fr::FixGrads fg = {g->verts ? acc_v : nullptr, want_n ? acc_n : nullptr, g->diffuse ? acc_c : nullptr,
+                           g->specular ? acc_s : nullptr, g->roughness ? acc_r : nullptr};
+  fr::launch_render_backward(a, d_dEdp, fg, d.slots, *g, st, static_cast<hipEvent_t>(o->ev_kernel_begin),
+                             static_cast<hipEvent_t>(o->ev_kernel_end));
+  if (g->normals) fr::launch_fix_to_float(acc_n, g->normals, 3 * d.N, st);
+  if (g->verts) fr::launch_normals_backward(d, s->verts, acc_n, d.gnorm, acc_v, st);
   const int ns = o->edge_samples < 0 ? s->width * s->height : o->edge_samples;
   if (ns > 0 && (g->verts || g->cam || o->dbg_hit))
-    fr::launch_edges(m->d, a, d_dEdp, ns, *g, o->dbg_hit, o->dbg_pflag, std::tan(0.5 * (double)s->fov_y), st);
+    fr::launch_edges(d, a, d_dEdp, ns, g->verts ? acc_v : nullptr, g->cam ? acc_cam : nullptr, o->dbg_hit,
+                     o->dbg_pflag, std::tan(0.5 * (double)s->fov_y), st);
+  if (g->verts) fr::launch_fix_to_float(acc_v, g->verts, 3 * d.N, st);
+  if (g->diffuse) fr::launch_fix_to_float(acc_c, g->diffuse, 3 * d.N, st);
+  if (g->specular) fr::launch_fix_to_float(acc_s, g->specular, 3 * d.N, st);
+  if (g->roughness) fr::launch_fix_to_float(acc_r, g->roughness, d.N, st);
+  if (g->cam) fr::launch_fix_to_float(acc_cam, g->cam, 12, st);
   FR_HIP(m->ctx, hipGetLastError());
   return FR_OK;
 }
@@ -432,7 +461,7 @@ void layout_job(Carver& c, const fr_model* md, const fr_job_desc* d, fr::JobDev&
   J.loss_part = c.take<double>(fr::cdiv(d->width * d->height, 256));
   J.loss = c.take<float>(1);
   J.loss_hist = c.take<float>(std::max(d->hist_cap, 1));
-  J.lslots = c.take<float>((size_t)fr::kSlots * (12 * L + 12));
+  J.lslots = c.take<fr::fix_t>((size_t)fr::kSlots * (12 * L + 12));
   J.param = c.take<float>(n_param); J.grad = c.take<float>(n_param);
   J.adam_m = c.take<float>(n_param); J.adam_v = c.take<float>(n_param); J.lr = c.take<float>(n_param);
   J.lights = c.take<fr::LightRec>(L);
@@ -592,11 +621,12 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   J.ea.n_samples = d->edge_samples < 0 ? d->width * d->height : d->edge_samples;
   J.ea.th = std::tan(0.5 * (double)d->fov_y);
   J.ea.aspect = (double)d->width / (double)d->height;
-  J.ea.dEdp = J.dEdp; J.ea.gverts = J.g_verts; J.ea.gcam = nullptr; J.ea.dbg_rec = nullptr; J.ea.dbg_flag = nullptr;
+  J.ea.dEdp = J.dEdp; J.ea.gverts = md_.acc; J.ea.gcam = nullptr; J.ea.dbg_rec = nullptr; J.ea.dbg_flag = nullptr;
   J.mean_geo = md->mean_geo; J.basis_geo = md->basis_geo; J.mean_alb = md->mean_alb; J.basis_alb = md->basis_alb;
   J.K_geo = md->K_geo; J.K_alb = md->K_alb; J.N = N; J.F = md->topo.F; J.M = M;
   J.hist_cap = jh->hist_cap;
   J.gnorm = md_.gnorm;
+  J.acc = md_.acc;
   J.zero_stride = fr::cdiv(std::max(n_param, 3 * N), 256) * 256;
   J.n_param = n_param; J.off_alb = md->K_geo; J.off_pose = md->K_geo + md->K_alb; J.off_rad = n_param - 3 * L;
   J.tris = md_.tris; J.vf_off = md_.vf_off; J.vf_idx = md_.vf_idx; J.normals = md_.normals; J.nlen = md_.nlen;

@@ -6,10 +6,12 @@
 // intersection, into
 //   - per-vertex positions, normals, diffuse, specular, roughness: per-wave
 //     match-reduce over lanes that hit the same triangle, then one set of
-//     atomics per distinct triangle;
-//   - per-light geometry and radiance, and the camera: wave reduction, LDS
-//     accumulation per block, then atomics into one of kSlots partial slots,
-//     summed by a final kernel.
+//     fixed-point atomics per distinct triangle;
+//   - per-light geometry and radiance, and the camera: wave reduction,
+//     fixed-point LDS accumulation per block, then fixed-point atomics into
+//     one of kSlots partial slots, summed by a final kernel.
+// All cross-wave sums are exact 64-bit integer sums (see fix_t), so the
+// gradients do not depend on scheduling.
 #include "fr_shade.h"
 
 namespace fr {
@@ -44,11 +46,11 @@ __device__ __forceinline__ void g1_fwd_bwd(float nv, float hv, float r, float& G
   dG1_dr = -dG * a / r;             // da/dr = -a / r
 }
 
-__device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const float* __restrict__ dEdp, const fr_grads& g,
-                                                 float* __restrict__ gnorm, float* __restrict__ slots, int bid) {
-  extern __shared__ float lds[];   // [L*12 + 12]: per light p0 e1 e2 rad, then camera
+__device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const float* __restrict__ dEdp,
+                                                 const FixGrads& g, fix_t* __restrict__ slots, int bid) {
+  extern __shared__ fix_t lds[];   // [L*12 + 12]: per light p0 e1 e2 rad, then camera
   const int nl = a.L * 12 + 12;
-  for (int i = threadIdx.x; i < nl; i += 256) lds[i] = 0.0f;
+  for (int i = threadIdx.x; i < nl; i += 256) lds[i] = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const Item it = wave_item(a, bid);
@@ -180,7 +182,7 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
         if (ballot(vis)) {
           for (int k = 0; k < 12; ++k) {
             const float t = wave_sum(gl12[k]);
-            if (lane == 0 && t != 0.0f) atomicAdd(&lds[12 * j + k], t);
+            if (lane == 0 && t != 0.0f) atomicAdd(&lds[12 * j + k], to_fix(t));
           }
         }
       }
@@ -250,11 +252,11 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
                             gs.x * bk, gs.y * bk, gs.z * bk, gr * bk};
           for (int q = 0; q < 13; ++q) vals[q] = wave_sum(mine ? vals[q] : 0.0f);
           if (lane == leader) {
-            if (g.verts) { atomicAdd(g.verts + 3 * vi, vals[0]); atomicAdd(g.verts + 3 * vi + 1, vals[1]); atomicAdd(g.verts + 3 * vi + 2, vals[2]); }
-            atomicAdd(gnorm + 3 * vi, vals[3]); atomicAdd(gnorm + 3 * vi + 1, vals[4]); atomicAdd(gnorm + 3 * vi + 2, vals[5]);
-            if (g.diffuse) { atomicAdd(g.diffuse + 3 * vi, vals[6]); atomicAdd(g.diffuse + 3 * vi + 1, vals[7]); atomicAdd(g.diffuse + 3 * vi + 2, vals[8]); }
-            if (g.specular) { atomicAdd(g.specular + 3 * vi, vals[9]); atomicAdd(g.specular + 3 * vi + 1, vals[10]); atomicAdd(g.specular + 3 * vi + 2, vals[11]); }
-            if (g.roughness) atomicAdd(g.roughness + vi, vals[12]);
+            if (g.verts) { fix_add(g.verts + 3 * vi, vals[0]); fix_add(g.verts + 3 * vi + 1, vals[1]); fix_add(g.verts + 3 * vi + 2, vals[2]); }
+            if (g.normals) { fix_add(g.normals + 3 * vi, vals[3]); fix_add(g.normals + 3 * vi + 1, vals[4]); fix_add(g.normals + 3 * vi + 2, vals[5]); }
+            if (g.diffuse) { fix_add(g.diffuse + 3 * vi, vals[6]); fix_add(g.diffuse + 3 * vi + 1, vals[7]); fix_add(g.diffuse + 3 * vi + 2, vals[8]); }
+            if (g.specular) { fix_add(g.specular + 3 * vi, vals[9]); fix_add(g.specular + 3 * vi + 1, vals[10]); fix_add(g.specular + 3 * vi + 2, vals[11]); }
+            if (g.roughness) fix_add(g.roughness + vi, vals[12]);
           }
         }
       }
@@ -263,26 +265,26 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
   // camera: wave reduction into LDS
   for (int k = 0; k < 12; ++k) {
     const float t = wave_sum(gcam[k]);
-    if (lane == 0 && t != 0.0f) atomicAdd(&lds[12 * a.L + k], t);
+    if (lane == 0 && t != 0.0f) atomicAdd(&lds[12 * a.L + k], to_fix(t));
   }
   __syncthreads();
-  float* slot = slots + (size_t)(bid % kSlots) * nl;
+  fix_t* slot = slots + (size_t)(bid % kSlots) * nl;
   for (int i = threadIdx.x; i < nl; i += 256)
-    if (lds[i] != 0.0f) atomicAdd(slot + i, lds[i]);
+    if (lds[i] != 0) atomicAdd(slot + i, lds[i]);
 }
 
-__global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, const float* __restrict__ dEdp, fr_grads g,
-                                                    float* __restrict__ gnorm, float* __restrict__ slots) {
-  render_bwd_block(a, dEdp, g, gnorm, slots, blockIdx.x);
+__global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, const float* __restrict__ dEdp, FixGrads g,
+                                                    fix_t* __restrict__ slots) {
+  render_bwd_block(a, dEdp, g, slots, blockIdx.x);
 }
 
-// Sum the slots into the caller's light and camera gradients.
-__device__ __forceinline__ void slots_reduce_block(const float* __restrict__ slots, int nl, int L,
+// Sum the slots (exact integer sums) into the caller's light and camera gradients.
+__device__ __forceinline__ void slots_reduce_block(const fix_t* __restrict__ slots, int nl, int L,
                                                    float* __restrict__ glight, float* __restrict__ grad,
                                                    float* __restrict__ gcam, int bid) {
   const int i = bid;   // one block per value
-  __shared__ float red[256];
-  float acc = 0.0f;
+  __shared__ fix_t red[256];
+  fix_t acc = 0;
   for (int s = threadIdx.x; s < kSlots; s += 256) acc += slots[(size_t)s * nl + i];
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -291,7 +293,7 @@ __device__ __forceinline__ void slots_reduce_block(const float* __restrict__ slo
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
-  const float v = red[0];
+  const float v = (float)from_fix(red[0]);
   if (i < 12 * L) {
     const int j = i / 12, k = i % 12;
     if (k < 9) { if (glight) glight[9 * j + k] += v; }
@@ -301,35 +303,22 @@ __device__ __forceinline__ void slots_reduce_block(const float* __restrict__ slo
   }
 }
 
-__global__ __launch_bounds__(256) void k_slots_reduce(const float* __restrict__ slots, int nl, int L,
+__global__ __launch_bounds__(256) void k_slots_reduce(const fix_t* __restrict__ slots, int nl, int L,
                                                       float* __restrict__ glight, float* __restrict__ grad,
                                                       float* __restrict__ gcam) {
   slots_reduce_block(slots, nl, L, glight, grad, gcam, blockIdx.x);
 }
 
-__global__ void k_zero_slots(float* p, size_t n) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.0f;
-}
-
-// Slot storage: kSlots * (12 L + 12) floats, grown on demand.
-static float* g_slots = nullptr;
-static size_t g_slots_cap = 0;
-
-void launch_render_backward(const RenderArgs& a, const float* dEdp, const fr_grads& g, float* gnorm, hipStream_t st) {
+// `slots` holds kSlots * (12 L + 12) accumulators (the caller sizes and owns it).
+void launch_render_backward(const RenderArgs& a, const float* dEdp, const FixGrads& fg, fix_t* slots,
+                            const fr_grads& g, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const int nl = a.L * 12 + 12;
-  const size_t need = (size_t)kSlots * nl;
-  if (need > g_slots_cap) {
-    if (g_slots) (void)hipFree(g_slots);
-    g_slots = nullptr;
-    g_slots_cap = 0;
-    if (hipMalloc(&g_slots, need * sizeof(float)) != hipSuccess) return;
-    g_slots_cap = need;
-  }
-  hipLaunchKernelGGL(k_zero_slots, dim3((unsigned)((need + 255) / 256)), dim3(256), 0, st, g_slots, need);
+  launch_zero_fix(slots, (size_t)kSlots * nl, st);
   const int blocks = wave_blocks_items(a);
-  hipLaunchKernelGGL(k_render_bwd, dim3(blocks), dim3(256), nl * sizeof(float), st, a, dEdp, g, gnorm, g_slots);
-  hipLaunchKernelGGL(k_slots_reduce, dim3(nl), dim3(256), 0, st, g_slots, nl, a.L, g.light_geom, g.light_rad, g.cam);
+  if (e0) (void)hipEventRecord(e0, st);
+  hipLaunchKernelGGL(k_render_bwd, dim3(blocks), dim3(256), nl * sizeof(fix_t), st, a, dEdp, fg, slots);
+  if (e1) (void)hipEventRecord(e1, st);
+  hipLaunchKernelGGL(k_slots_reduce, dim3(nl), dim3(256), 0, st, slots, nl, a.L, g.light_geom, g.light_rad, g.cam);
 }
 
 }  // namespace fr

@@ -18,7 +18,8 @@ struct JobDev {
   float* v_obj; float* v_w; float* diffuse;
   float* image; const float* target; float* dEdp; float* gsign; double* loss_part; float* loss;
   float* loss_hist; int hist_cap;
-  float* g_verts; float* g_diffuse; float* g_vobj; float* gnorm; float* lslots; int zero_stride;
+  float* g_verts; float* g_diffuse; float* g_vobj; float* gnorm; fix_t* lslots; int zero_stride;
+  fix_t* acc;               // fixed-point accumulators: verts [3N], normals [3N], diffuse [3N]
   float* param; float* grad; float* adam_m; float* adam_v; const float* lr;
   int n_param, off_alb, off_pose, off_rad;
   const int32_t* tris; const int32_t* vf_off; const int32_t* vf_idx; float* normals; float* nlen;

@@ -72,29 +72,38 @@ FR_BATCH_KERNEL(kb_loss_final, 256) {
 FR_BATCH_KERNEL(kb_smooth_adjoint, 256) {
   FR_JOB_PROLOGUE if (J.smooth) smooth_adjoint_block(J.gsign, J.ra.W, J.ra.H, J.taps, J.dEdp, lb);
 }
-// zero the gradient buffers: grad, g_verts, g_diffuse, g_vobj, gnorm, light slots
+// zero the gradient buffers: grad, g_vobj, the fixed-point accumulators, light slots
 FR_BATCH_KERNEL(kb_zero_grads, 256) {
   FR_JOB_PROLOGUE
   const int i = lb * 256 + threadIdx.x;
-  const int n3 = 3 * J.N;
+  const int n9 = 9 * J.N;
   const int nslot = kSlots * (12 * J.ra.L + 12);
   if (i < J.n_param) J.grad[i] = 0.0f;
-  if (i < n3) { J.g_verts[i] = 0.0f; J.g_diffuse[i] = 0.0f; J.g_vobj[i] = 0.0f; J.gnorm[i] = 0.0f; }
-  for (int k = i; k < nslot; k += J.zero_stride) J.lslots[k] = 0.0f;
+  if (i < 3 * J.N) J.g_vobj[i] = 0.0f;
+  for (int k = i; k < n9; k += J.zero_stride) J.acc[k] = 0;
+  for (int k = i; k < nslot; k += J.zero_stride) J.lslots[k] = 0;
 }
-FR_BATCH_KERNEL(kb_render_bwd, 256) {
+__attribute__((amdgpu_waves_per_eu(3))) FR_BATCH_KERNEL(kb_render_bwd, 256) {
   FR_JOB_PROLOGUE
-  fr_grads g = {J.g_verts, nullptr, J.g_diffuse, nullptr, nullptr, nullptr, nullptr, nullptr};
-  render_bwd_block(J.rb, J.dEdp, g, J.gnorm, J.lslots, lb);
+  const FixGrads g = {J.acc, J.acc + 3 * J.N, J.acc + 6 * J.N, nullptr, nullptr};
+  render_bwd_block(J.rb, J.dEdp, g, J.lslots, lb);
+}
+// fixed-point vertex and diffuse gradients -> float
+FR_BATCH_KERNEL(kb_fix_finalize, 256) {
+  FR_JOB_PROLOGUE
+  const int i = lb * 256 + threadIdx.x;
+  if (i >= 3 * J.N) return;
+  J.g_verts[i] = (float)from_fix(J.acc[i]);
+  J.g_diffuse[i] = (float)from_fix(J.acc[6 * J.N + i]);
 }
 FR_BATCH_KERNEL(kb_slots_reduce, 256) {
   FR_JOB_PROLOGUE slots_reduce_block(J.lslots, 12 * J.ra.L + 12, J.ra.L, nullptr, J.grad + J.off_rad, nullptr, lb);
 }
 FR_BATCH_KERNEL(kb_normals_bwd_project, 256) {
-  FR_JOB_PROLOGUE normals_bwd_project_block(J.v_w, J.tris, J.vf_off, J.vf_idx, J.N, J.gnorm, lb);
+  FR_JOB_PROLOGUE normals_bwd_project_block(J.v_w, J.tris, J.vf_off, J.vf_idx, J.N, J.acc + 3 * J.N, J.gnorm, lb);
 }
 FR_BATCH_KERNEL(kb_normals_bwd_gather, 256) {
-  FR_JOB_PROLOGUE normals_bwd_gather_block(J.v_w, J.tris, J.vf_off, J.vf_idx, J.N, J.gnorm, J.g_verts, lb);
+  FR_JOB_PROLOGUE normals_bwd_gather_block(J.v_w, J.tris, J.vf_off, J.vf_idx, J.N, J.gnorm, J.acc, lb);
 }
 FR_BATCH_KERNEL(kb_face_front, 256) { FR_JOB_PROLOGUE face_front_block(J.v_w, J.tris, J.F, J.ra.cam, J.face_front, lb); }
 FR_BATCH_KERNEL(kb_edge_len, 256) {
@@ -114,7 +123,7 @@ FR_BATCH_KERNEL(kb_blend_bwd_alb, 1024) {
 FR_BATCH_KERNEL(kb_adam, 256) {
   FR_JOB_PROLOGUE
   const int t = J.t + 1;
-  const float c1 = 1.0f - powf(0.9f, (float)t), c2 = 1.0f - powf(0.999f, (float)t);
+  const float c1 = adam_bias(0.9f, t), c2 = adam_bias(0.999f, t);
   adam_block(J.param, J.grad, J.adam_m, J.adam_v, J.lr, J.n_param, 0.9f, 0.999f, 1e-8f, c1, c2, lb);
 }
 // Advance the step counters of every job.  Step k (1-based) renders with
@@ -134,7 +143,7 @@ __global__ void kb_advance(JobDev* jobs, int njobs) {
 enum Stage {
   S_BLEND_GEO, S_BLEND_ALB, S_POSE, S_NORMALS, S_ZERO_FLAGS, S_REFIT, S_LIGHTS, S_FWD, S_SUM, S_LOSS, S_LOSS_FINAL,
   S_SMOOTH_ADJ, S_ZERO_GRADS, S_BWD, S_SLOTS, S_NBWD_P, S_NBWD_G, S_FACE_FRONT, S_EDGE_LEN, S_EDGE_SCAN,
-  S_EDGE_SAMPLES, S_POSE_BWD_V, S_POSE_BWD_P, S_BLEND_BWD_GEO, S_BLEND_BWD_ALB, S_ADAM, S_COUNT
+  S_EDGE_SAMPLES, S_FIX_FINALIZE, S_POSE_BWD_V, S_POSE_BWD_P, S_BLEND_BWD_GEO, S_BLEND_BWD_ALB, S_ADAM, S_COUNT
 };
 
 static int stage_blocks(const JobDev& J, int s) {
@@ -142,6 +151,7 @@ static int stage_blocks(const JobDev& J, int s) {
   switch (s) {
     case S_BLEND_GEO: case S_BLEND_ALB: return cdiv(J.M, 256);
     case S_POSE: case S_NORMALS: case S_NBWD_P: case S_NBWD_G: case S_POSE_BWD_V: return cdiv(N, 256);
+    case S_FIX_FINALIZE: return cdiv(3 * N, 256);
     case S_ZERO_FLAGS: return cdiv(F > 1 ? F - 1 : 1, 256);
     case S_REFIT: case S_FACE_FRONT: return cdiv(F, 256);
     case S_LIGHTS: return cdiv(J.ra.L, 256);
@@ -226,7 +236,7 @@ void Batch::launch_step(hipStream_t st) {
   FR_LAUNCH(kb_loss_final, S_LOSS_FINAL, 256, 0);
   FR_LAUNCH(kb_smooth_adjoint, S_SMOOTH_ADJ, 256, 0);
   FR_LAUNCH(kb_zero_grads, S_ZERO_GRADS, 256, 0);
-  FR_LAUNCH(kb_render_bwd, S_BWD, 256, max_nl * sizeof(float));
+  FR_LAUNCH(kb_render_bwd, S_BWD, 256, max_nl * sizeof(fix_t));
   FR_LAUNCH(kb_slots_reduce, S_SLOTS, 256, 0);
   FR_LAUNCH(kb_normals_bwd_project, S_NBWD_P, 256, 0);
   FR_LAUNCH(kb_normals_bwd_gather, S_NBWD_G, 256, 0);
@@ -234,6 +244,7 @@ void Batch::launch_step(hipStream_t st) {
   FR_LAUNCH(kb_edge_len, S_EDGE_LEN, 256, 0);
   FR_LAUNCH(kb_edge_scan, S_EDGE_SCAN, 1024, 0);
   FR_LAUNCH(kb_edge_samples, S_EDGE_SAMPLES, 256, 0);
+  FR_LAUNCH(kb_fix_finalize, S_FIX_FINALIZE, 256, 0);
   FR_LAUNCH(kb_pose_bwd_v, S_POSE_BWD_V, 256, 0);
   FR_LAUNCH(kb_pose_bwd_p, S_POSE_BWD_P, 1024, 0);
   FR_LAUNCH(kb_blend_bwd_geo, S_BLEND_BWD_GEO, 1024, 0);

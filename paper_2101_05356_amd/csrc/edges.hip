@@ -218,10 +218,10 @@ __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const Ed
                      R[6] * gpc.x + R[7] * gpc.y + R[8] * gpc.z};
       const float sa = wgt * (1.0f - w), sb = wgt * w;
       if (e.gverts) {
-        atomicAdd(e.gverts + 3 * va, gX.x * sa); atomicAdd(e.gverts + 3 * va + 1, gX.y * sa);
-        atomicAdd(e.gverts + 3 * va + 2, gX.z * sa);
-        atomicAdd(e.gverts + 3 * vb, gX.x * sb); atomicAdd(e.gverts + 3 * vb + 1, gX.y * sb);
-        atomicAdd(e.gverts + 3 * vb + 2, gX.z * sb);
+        fix_add(e.gverts + 3 * va, gX.x * sa); fix_add(e.gverts + 3 * va + 1, gX.y * sa);
+        fix_add(e.gverts + 3 * va + 2, gX.z * sa);
+        fix_add(e.gverts + 3 * vb, gX.x * sb); fix_add(e.gverts + 3 * vb + 1, gX.y * sb);
+        fix_add(e.gverts + 3 * vb + 2, gX.z * sb);
       }
       // pc_i = sum_k R[k][i] (X - T)_k  ->  dR[k][i] = (X - T)_k gpc_i ; dT = -R gpc
       const float gp[3] = {gpc.x, gpc.y, gpc.z}, dd[3] = {dX.x, dX.y, dX.z};
@@ -234,7 +234,7 @@ __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const Ed
     for (int q = 0; q < 12; ++q) {
       float t = gcam[q];
       for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
-      if (lane == 0 && t != 0.0f) atomicAdd(e.gcam + q, t);
+      if (lane == 0 && t != 0.0f) fix_add(e.gcam + q, t);
     }
   }
 }
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_edge_samples(RenderArgs a, EdgeArgs e) 
   edge_samples_block<DUMP>(a, e, blockIdx.x);
 }
 
-void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samples, const fr_grads& g,
+void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samples, fix_t* gverts, fix_t* gcam,
                   int32_t* dbg_rec, uint8_t* dbg_flag, double tan_half, hipStream_t st) {
   hipLaunchKernelGGL(k_face_front, dim3((m.F + 255) / 256), dim3(256), 0, st, a.verts, m.tris, m.F, a.cam,
                      m.face_front);
@@ -254,7 +254,7 @@ void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samp
   hipLaunchKernelGGL(k_edge_scan, dim3(1), dim3(1024), 0, st, m.edge_len, m.E, m.edge_cdf);
   EdgeArgs e;
   e.edges = m.edges; e.cdf = m.edge_cdf; e.E = m.E; e.n_samples = n_samples;
-  e.th = tan_half; e.aspect = aspect; e.dEdp = dEdp; e.gverts = g.verts; e.gcam = g.cam;
+  e.th = tan_half; e.aspect = aspect; e.dEdp = dEdp; e.gverts = gverts; e.gcam = gcam;
   e.dbg_rec = dbg_rec; e.dbg_flag = dbg_flag;
   const int groups = (n_samples + 63) / 64;
   const int blocks = (groups * a.n_lchunks + 3) / 4;

@@ -13,6 +13,40 @@ __device__ inline int cdiv_d(int a, int b) { return (a + b - 1) / b; }
 
 struct Taps { float c, e, k; };   // smoothing weights: centre, edge, corner
 
+// Adam's bias correction 1 - b^t, computed identically on host and device
+// (square-and-multiply in double, one rounding to float at the end).
+__host__ __device__ inline float adam_bias(float b, int t) {
+  double r = 1.0, x = (double)b;
+  for (unsigned e = (unsigned)t; e; e >>= 1) {
+    if (e & 1u) r *= x;
+    x *= x;
+  }
+  return (float)(1.0 - r);
+}
+
+// Fixed-point gradient accumulation.  Every contribution is rounded once to a
+// multiple of 2^-32 and summed in 64-bit two's-complement integers, so a sum
+// does not depend on the order in which waves and blocks add to it: gradients
+// are identical from run to run and whatever else shares the launch.
+// Range: |sum| < 2^31; resolution 2^-32.
+typedef unsigned long long fix_t;
+constexpr double kFixOne = 4294967296.0;   // 2^32
+__device__ __forceinline__ fix_t to_fix(float v) { return (fix_t)__float2ll_rn(v * 4294967296.0f); }
+__device__ __forceinline__ fix_t to_fix_d(double v) { return (fix_t)__double2ll_rn(v * kFixOne); }
+__device__ __forceinline__ void fix_add(fix_t* p, float v) {
+  if (v != 0.0f) atomicAdd(p, to_fix(v));
+}
+__host__ __device__ __forceinline__ double from_fix(fix_t a) { return (double)(long long)a * (1.0 / kFixOne); }
+
+// Fixed-point accumulators of the per-vertex gradients (each nullable).
+struct FixGrads {
+  fix_t* verts;       // [N*3]
+  fix_t* normals;     // [N*3] dE/dn before the normalisation adjoint
+  fix_t* diffuse;     // [N*3]
+  fix_t* specular;    // [N*3]
+  fix_t* roughness;   // [N]
+};
+
 // Arguments of the edge-sampling kernel.
 struct EdgeArgs {
   const int32_t* edges;
@@ -20,8 +54,8 @@ struct EdgeArgs {
   int E, n_samples;
   double th, aspect;
   const float* dEdp;
-  float* gverts;
-  float* gcam;
+  fix_t* gverts;        // [N*3] fixed-point
+  fix_t* gcam;          // [12] fixed-point
   int32_t* dbg_rec;     // [n*4]: edge, pixel, hit-, hit+
   uint8_t* dbg_flag;    // [n]
 };
@@ -35,7 +69,12 @@ struct MeshDev {
   int32_t* vf_idx = nullptr;        // [3F]
   float* normals = nullptr;         // [N*3]
   float* nlen = nullptr;            // [N] length of the unnormalised normal sum
-  float* gnorm = nullptr;           // [N*3] backward scratch: dE/dn
+  float* gnorm = nullptr;           // [N*3] backward scratch: projected dE/dn
+  // fixed-point backward accumulators [13N + 12]: verts, normals, diffuse,
+  // specular (3N each), roughness (N), camera (12)
+  fix_t* acc = nullptr;
+  fix_t* slots = nullptr;           // [kSlots * (12 L + 12)] light/camera partial slots
+  size_t slots_cap = 0;
   // unique edges and their faces, for the boundary term
   int32_t* edges = nullptr;         // [E*2]
   int32_t* edge_faces = nullptr;    // [E*2]
@@ -99,7 +138,10 @@ int bvh_build(MeshDev& m, const float* d_verts, hipStream_t st, int* depth_out);
 void bvh_refit(MeshDev& m, const float* d_verts, hipStream_t st);
 // model.hip
 void launch_normals(MeshDev& m, const float* d_verts, hipStream_t st);
-void launch_normals_backward(MeshDev& m, const float* d_verts, const float* d_gn, float* d_gv, hipStream_t st);
+void launch_normals_backward(MeshDev& m, const float* d_verts, const fix_t* acc_n, float* gn_tmp, fix_t* acc_v,
+                             hipStream_t st);
+void launch_fix_to_float(const fix_t* acc, float* out, int n, hipStream_t st);   // out += acc
+void launch_zero_fix(fix_t* p, size_t n, hipStream_t st);
 void launch_blend(const float* mean, const float* basis, const float* coef, int K, int M, float* out, hipStream_t st);
 void launch_blend_backward(const float* basis, const float* gout, int K, int M, float* gcoef, hipStream_t st);
 void launch_pose(const float* v, int N, const float* pose, float* vw, hipStream_t st);
@@ -111,7 +153,8 @@ void launch_light_setup(const fr_scene& sc, LightRec* out, hipStream_t st);
 void launch_zero(float* p, int n, hipStream_t st);
 void launch_axpy(float* dst, const float* src, int n, hipStream_t st);
 // render.hip
-void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st);
+void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr);
 // Default lights per work item: short items balance the forward launch; the
 // backward repeats more per-item work (primary trace, chain, scatter), so it
 // takes longer items.
@@ -123,9 +166,12 @@ constexpr int kSlots = 1024;
 void launch_loss(const float* img, const float* target, int W, int H, int smooth, float* loss, float* dEdp,
                  double* scratch, float* gtmp, hipStream_t st);
 // backward.hip
-void launch_render_backward(const RenderArgs& a, const float* dEdp, const fr_grads& g, float* gnorm, hipStream_t st);
+// Interior adjoint: per-vertex gradients into `fg`, light and camera
+// gradients into the slots and then added to g.light_geom, g.light_rad, g.cam.
+void launch_render_backward(const RenderArgs& a, const float* dEdp, const FixGrads& fg, fix_t* slots,
+                            const fr_grads& g, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // edges.hip
-void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samples, const fr_grads& g,
+void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samples, fix_t* gverts, fix_t* gcam,
                   int32_t* dbg_rec, uint8_t* dbg_flag, double tan_half, hipStream_t st);
 
 }  // namespace fr

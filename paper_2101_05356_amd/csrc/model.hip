@@ -51,6 +51,7 @@ __device__ __forceinline__ void normals_bwd_project_block(const float* __restric
                                                              const int32_t* __restrict__ tris,
                                                              const int32_t* __restrict__ off,
                                                              const int32_t* __restrict__ idx, int N,
+                                                             const fix_t* __restrict__ gacc,
                                                              float* __restrict__ g, int bid) {
   const int i = bid * 256 + threadIdx.x;
   if (i >= N) return;
@@ -62,7 +63,7 @@ __device__ __forceinline__ void normals_bwd_project_block(const float* __restric
   }
   const double len = sqrt(acc.x * acc.x + acc.y * acc.y + acc.z * acc.z);
   const D3 nn = {acc.x / len, acc.y / len, acc.z / len};
-  const D3 gg = d3(g, i);
+  const D3 gg = {from_fix(gacc[3 * i]), from_fix(gacc[3 * i + 1]), from_fix(gacc[3 * i + 2])};
   const double d = nn.x * gg.x + nn.y * gg.y + nn.z * gg.z;
   g[3 * i] = (float)((gg.x - nn.x * d) / len);
   g[3 * i + 1] = (float)((gg.y - nn.y * d) / len);
@@ -73,8 +74,9 @@ __global__ __launch_bounds__(256) void k_normals_bwd_project(const float* __rest
                                                              const int32_t* __restrict__ tris,
                                                              const int32_t* __restrict__ off,
                                                              const int32_t* __restrict__ idx, int N,
+                                                             const fix_t* __restrict__ gacc,
                                                              float* __restrict__ g) {
-  normals_bwd_project_block(v, tris, off, idx, N, g, blockIdx.x);
+  normals_bwd_project_block(v, tris, off, idx, N, gacc, g, blockIdx.x);
 }
 
 // For face f with N_f = a x b (a = v1 - v0, b = v2 - v0) and gN = sum of the
@@ -83,7 +85,8 @@ __global__ __launch_bounds__(256) void k_normals_bwd_project(const float* __rest
 __device__ __forceinline__ void normals_bwd_gather_block(const float* __restrict__ v, const int32_t* __restrict__ tris,
                                                             const int32_t* __restrict__ off,
                                                             const int32_t* __restrict__ idx, int N,
-                                                            const float* __restrict__ gN, float* __restrict__ gv, int bid) {
+                                                            const float* __restrict__ gN, fix_t* __restrict__ gv,
+                                                            int bid) {
   const int i = bid * 256 + threadIdx.x;
   if (i >= N) return;
   D3 acc = {0.0, 0.0, 0.0};
@@ -98,13 +101,14 @@ __device__ __forceinline__ void normals_bwd_gather_block(const float* __restrict
     else if (i == i1) acc = acc + ga;
     else acc = acc + gb;
   }
-  gv[3 * i] += (float)acc.x; gv[3 * i + 1] += (float)acc.y; gv[3 * i + 2] += (float)acc.z;
+  // one thread owns vertex i: a plain read-modify-write of its accumulator
+  gv[3 * i] += to_fix_d(acc.x); gv[3 * i + 1] += to_fix_d(acc.y); gv[3 * i + 2] += to_fix_d(acc.z);
 }
 
 __global__ __launch_bounds__(256) void k_normals_bwd_gather(const float* __restrict__ v, const int32_t* __restrict__ tris,
                                                             const int32_t* __restrict__ off,
                                                             const int32_t* __restrict__ idx, int N,
-                                                            const float* __restrict__ gN, float* __restrict__ gv) {
+                                                            const float* __restrict__ gN, fix_t* __restrict__ gv) {
   normals_bwd_gather_block(v, tris, off, idx, N, gN, gv, blockIdx.x);
 }
 
@@ -113,12 +117,35 @@ void launch_normals(MeshDev& m, const float* d_verts, hipStream_t st) {
                      m.normals, m.nlen);
 }
 
-void launch_normals_backward(MeshDev& m, const float* d_verts, const float* d_gn, float* d_gv, hipStream_t st) {
-  // d_gn is the mesh's own scratch (m.gnorm) and is projected in place
+void launch_normals_backward(MeshDev& m, const float* d_verts, const fix_t* acc_n, float* gn_tmp, fix_t* acc_v,
+                             hipStream_t st) {
   hipLaunchKernelGGL(k_normals_bwd_project, dim3(cdiv(m.N, 256)), dim3(256), 0, st, d_verts, m.tris, m.vf_off,
-                     m.vf_idx, m.N, const_cast<float*>(d_gn));
+                     m.vf_idx, m.N, acc_n, gn_tmp);
   hipLaunchKernelGGL(k_normals_bwd_gather, dim3(cdiv(m.N, 256)), dim3(256), 0, st, d_verts, m.tris, m.vf_off,
-                     m.vf_idx, m.N, d_gn, d_gv);
+                     m.vf_idx, m.N, gn_tmp, acc_v);
+}
+
+__device__ __forceinline__ void fix_to_float_block(const fix_t* __restrict__ acc, float* __restrict__ out, int n,
+                                                   int bid) {
+  const int i = bid * 256 + threadIdx.x;
+  if (i < n) out[i] += (float)from_fix(acc[i]);
+}
+
+__global__ __launch_bounds__(256) void k_fix_to_float(const fix_t* __restrict__ acc, float* __restrict__ out, int n) {
+  fix_to_float_block(acc, out, n, blockIdx.x);
+}
+
+void launch_fix_to_float(const fix_t* acc, float* out, int n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_fix_to_float, dim3(cdiv(n, 256)), dim3(256), 0, st, acc, out, n);
+}
+
+__global__ __launch_bounds__(256) void k_zero_fix(fix_t* p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+void launch_zero_fix(fix_t* p, size_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_zero_fix, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -319,8 +346,7 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
 
 void launch_adam(float* p, const float* g, float* m, float* v, const float* lr, int n, int t, float b1, float b2,
                  float eps, hipStream_t st) {
-  const float c1 = (float)(1.0 - std::pow((double)b1, (double)t));
-  const float c2 = (float)(1.0 - std::pow((double)b2, (double)t));
+  const float c1 = adam_bias(b1, t), c2 = adam_bias(b2, t);
   hipLaunchKernelGGL(k_adam, dim3(cdiv(n, 256)), dim3(256), 0, st, p, g, m, v, lr, n, b1, b2, eps, c1, c2);
 }
 

@@ -106,12 +106,14 @@ __global__ __launch_bounds__(256) void k_sum_chunks(const float* __restrict__ pa
   sum_chunks_block(partial, n, nch, image, blockIdx.x);
 }
 
-void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st) {
+void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const int blocks = wave_blocks_items(a);
+  if (e0) (void)hipEventRecord(e0, st);
   if (a.dbg_hit)
     hipLaunchKernelGGL(k_render_fwd<true>, dim3(blocks), dim3(256), 0, st, a, image);
   else
     hipLaunchKernelGGL(k_render_fwd<false>, dim3(blocks), dim3(256), 0, st, a, image);
+  if (e1) (void)hipEventRecord(e1, st);
   if (a.n_lchunks > 1) {
     const int n = 3 * a.W * a.H;
     hipLaunchKernelGGL(k_sum_chunks, dim3((n + 255) / 256), dim3(256), 0, st, a.partial, n, a.n_lchunks, image);

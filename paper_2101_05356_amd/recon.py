@@ -151,26 +151,20 @@ class Reconstruction:
         return R.render_forward(self.mesh, self.scene(), self.job.brdf_variant, verts=self.v_w)
 
     def step(self, events=None):
-        """One optimisation step; `events` (dict of start/end pairs) times the render calls.
+        """One optimisation step; `events` ({"fwd"|"bwd": (start, end)} torch
+        events) times the forward render kernel and the interior adjoint kernel.
         Returns the loss (device tensor [1]) of the image rendered at this step."""
         job, mt, sl = self.job, self.mt, self.sl
         self.t += 1
         self.geometry(rebuild=False)
         sc = self.scene()
-        if events is not None:
-            events["fwd"][0].record()
-        img = R.render_forward(self.mesh, sc, job.brdf_variant, verts=self.v_w)
-        if events is not None:
-            events["fwd"][1].record()
+        ev = events or {}
+        img = R.render_forward(self.mesh, sc, job.brdf_variant, verts=self.v_w, events=ev.get("fwd"))
         E, dEdp = R.loss(img, job.target, smooth=job.smooth)
         self.grad.zero_()
         self.g_vobj.zero_()
-        if events is not None:
-            events["bwd"][0].record()
         g = R.render_backward(self.mesh, sc, dEdp, job.brdf_variant, edge_samples=job.edge_samples,
-                              groups=("verts", "diffuse", "light_rad"), verts=self.v_w)
-        if events is not None:
-            events["bwd"][1].record()
+                              groups=("verts", "diffuse", "light_rad"), verts=self.v_w, events=ev.get("bwd"))
         R.pose_backward(self.v_obj, self.param[sl["pose"]], g["verts"], self.g_vobj, self.grad[sl["pose"]])
         R.blend_backward(mt.basis_geo, self.g_vobj, self.grad[sl["geo"]])
         R.blend_backward(mt.basis_alb, g["diffuse"], self.grad[sl["alb"]])
@@ -187,12 +181,18 @@ def render_params(ctx, mt: ModelTensors, job: JobSpec, params: torch.Tensor) -> 
 
 
 def face_job(mt: ModelTensors, rng: np.random.Generator, ctx, W=256, spp=16, n_lights=72, seed=4,
-             edge_samples=-1, hist_cap=1024, device="cuda") -> tuple[JobSpec, torch.Tensor]:
+             edge_samples=-1, hist_cap=1024, device="cuda", light_idx=None, target_spp=None,
+             target_seed=None) -> tuple[JobSpec, torch.Tensor]:
     """A synthetic reconstruction: ground-truth parameters drawn from `rng`,
-    target rendered from them (on the device); the start point has zero
-    coefficients, a perturbed pose and 0.8x the light radiance.
-    Returns (job, true parameters)."""
-    lights = scenes.face_lights(n_lights)
+    target rendered from them on the device (with `target_spp` samples and
+    Philox key `target_seed` when given); the start point has zero
+    coefficients, a perturbed pose and 0.8x the light radiance.  Lights: a
+    Fibonacci stage of `n_lights`, or the subset `light_idx` of the 72-light
+    stage.  Returns (job, true parameters)."""
+    if light_idx is None:
+        lights = scenes.face_lights(n_lights)
+    else:
+        lights = scenes.face_lights(72).subset(np.sort(np.asarray(light_idx)))
     cam = scenes.face_camera(W, W)
     L = lights.count
     sl = param_slices(mt.K_geo, mt.K_alb, L)
@@ -203,7 +203,8 @@ def face_job(mt: ModelTensors, rng: np.random.Generator, ctx, W=256, spp=16, n_l
     lr = _dev(learning_rates(mt, L), device)
     job = JobSpec(W=W, H=W, spp=spp, lights=lights, camera=cam, target=None, params=_dev(p_true, device), lr=lr,
                   seed=seed, edge_samples=edge_samples, hist_cap=hist_cap)
-    target = render_params(ctx, mt, job, job.params).contiguous()
+    tjob = dataclasses.replace(job, spp=target_spp or spp, seed=seed if target_seed is None else target_seed)
+    target = render_params(ctx, mt, tjob, job.params).contiguous()
     p0 = p_true.copy()
     p0[:mt.K_geo + mt.K_alb] = 0.0
     p0[sl["pose"]] += np.array([0.05, -0.05, 0.03, 0.02, -0.02, 0.01], np.float32)

@@ -145,10 +145,19 @@ class DeviceScene:
         return s
 
 
-def _opts(brdf_variant=0, components=3, edge_samples=0, dbg=None, light_chunk=0) -> FrRenderOpts:
+def _event_handle(ev):
+    """Raw hipEvent_t of a torch.cuda.Event (torch creates it at the first record)."""
+    if ev.cuda_event == 0:
+        ev.record()
+    return ev.cuda_event
+
+
+def _opts(brdf_variant=0, components=3, edge_samples=0, dbg=None, light_chunk=0, events=None) -> FrRenderOpts:
     o = FrRenderOpts()
     o.brdf_variant, o.components, o.edge_samples = int(brdf_variant), int(components), int(edge_samples)
     o.light_chunk = int(light_chunk)
+    if events is not None:
+        o.ev_kernel_begin, o.ev_kernel_end = _event_handle(events[0]), _event_handle(events[1])
     if dbg is not None:
         o.dbg_hit = dbg[0].data_ptr() if dbg[0] is not None else None
         o.dbg_pflag = dbg[1].data_ptr() if dbg[1] is not None else None
@@ -157,9 +166,10 @@ def _opts(brdf_variant=0, components=3, edge_samples=0, dbg=None, light_chunk=0)
 
 
 def render_forward(mesh: Mesh, sc: DeviceScene, brdf_variant=0, components=3, dump=False, verts=None, stats=None,
-                   light_chunk=0):
+                   light_chunk=0, events=None):
     """Image [H,W,3]; with dump=True also (hit [H*W,S], pflag [H*W,S], vis [H*W,S,L]).
-    `stats` (a uint64-sized int64 tensor [10], dump only) accumulates traversal counts."""
+    `stats` (a uint64-sized int64 tensor [10], dump only) accumulates traversal counts.
+    `events` (two torch.cuda.Event with timing) bracket the render kernel itself."""
     dev = sc.verts.device
     img = torch.empty((sc.H, sc.W, 3), dtype=torch.float32, device=dev)
     dbg = None
@@ -168,7 +178,7 @@ def render_forward(mesh: Mesh, sc: DeviceScene, brdf_variant=0, components=3, du
         dbg = (torch.full((n,), -7, dtype=torch.int32, device=dev), torch.zeros(n, dtype=torch.uint8, device=dev),
                torch.full((n * max(sc.n_lights, 1),), 0xEE, dtype=torch.uint8, device=dev))
     s = sc.struct(verts)
-    o = _opts(brdf_variant, components, 0, dbg, light_chunk)
+    o = _opts(brdf_variant, components, 0, dbg, light_chunk, events)
     if stats is not None:
         assert dump and stats.dtype == torch.int64 and stats.numel() == 10
         o.dbg_stats = stats.data_ptr()
@@ -194,8 +204,9 @@ GRAD_GROUPS = ("verts", "normals", "diffuse", "specular", "roughness", "light_ge
 
 
 def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_variant=0, components=3,
-                    edge_samples=0, groups=GRAD_GROUPS, verts=None, edge_dump=False, light_chunk=0):
-    """Gradients (dict of new tensors) of sum dEdp . image."""
+                    edge_samples=0, groups=GRAD_GROUPS, verts=None, edge_dump=False, light_chunk=0, events=None):
+    """Gradients (dict of new tensors) of sum dEdp . image.  `events` (two
+    torch.cuda.Event with timing) bracket the interior adjoint kernel."""
     dev = sc.verts.device
     N, L = mesh.n_verts, sc.n_lights
     shapes = dict(verts=(N, 3), normals=(N, 3), diffuse=(N, 3), specular=(N, 3), roughness=(N,),
@@ -210,7 +221,7 @@ def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_varian
         dbg = (torch.full((ns * 4,), -7, dtype=torch.int32, device=dev), torch.zeros(ns, dtype=torch.uint8, device=dev),
                None)
     s = sc.struct(verts)
-    o = _opts(brdf_variant, components, edge_samples, dbg, light_chunk)
+    o = _opts(brdf_variant, components, edge_samples, dbg, light_chunk, events)
     check(lib().fr_render_backward(mesh.h, ctypes.byref(s), ctypes.byref(o), _p(dEdp.contiguous()), ctypes.byref(g),
                                    _stream()), mesh.ctx.h, "fr_render_backward")
     if edge_dump and dbg is not None:
