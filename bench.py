@@ -56,7 +56,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-only", action="store_true",
-                    help="only the timed single-face steps (for profilers)")
+                    help="skip the traversal statistics and the CPU baseline (for profilers)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run 5 plain device-to-device copies of BYTES (counter calibration)")
     ap.add_argument("--batch-jobs", type=int, default=32, help="faces in the batched-step measurement (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--serve-requests", type=int, default=8, help="requests in the serving measurement (0 = skip)")
@@ -102,6 +104,35 @@ def cpu_baseline(seconds, spp, n_lights, width):
     return {"value": rays / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} random pixels of the {width}x{width} face (spp {spp}, {n_lights} lights): FP64 "
                       f"brute-force forward decisions + shading + dual-number interior gradient, {dt:.1f} s"}
+
+
+KERNEL_SOURCES = {
+    "k_render_bwd": ["paper_2101_05356_amd/csrc/backward.hip", "paper_2101_05356_amd/csrc/fr_shade.h",
+                     "paper_2101_05356_amd/csrc/fr_device.h", "paper_2101_05356_amd/csrc/fr_kernels.h",
+                     "include/fr.h"],
+    "k_render_fwd": ["paper_2101_05356_amd/csrc/render.hip", "paper_2101_05356_amd/csrc/fr_shade.h",
+                     "paper_2101_05356_amd/csrc/fr_device.h", "paper_2101_05356_amd/csrc/fr_kernels.h",
+                     "include/fr.h"],
+}
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_render_face256.md")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter record, or None when
+    the kernel's sources changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_RECORD).read()
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])[kernel]
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != rec["sources_sha256_16"]:
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 def make_c2(ctx, width, spp, n_lights, edge_samples):
@@ -207,6 +238,15 @@ def main():
                                    "design is described but not built)"}))
         sys.exit(2)
     import torch
+    if args.copy_probe > 0:
+        n = args.copy_probe // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n, "copies": 5}), flush=True)
+        return
     from paper_2101_05356_amd import render as R
     W = H = args.width
     S, L = args.spp, args.lights
@@ -244,7 +284,7 @@ def main():
         dom, ops, ms = ("k_render_bwd", ops_b, bwd_ms) if bwd_ms >= fwd_ms else ("k_render_fwd", ops_f, fwd_ms)
         ach = ops / (ms * 1e-3)
         out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": ach / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                           "unit": "Tlane-op/s", "frac": ach / PEAK_LANE_OPS, "traffic": None,
+                           "unit": "Tlane-op/s", "frac": ach / PEAK_LANE_OPS, "traffic": measured_traffic(dom),
                            "other": {"k_render_fwd": {"ms": fwd_ms, "achieved": ops_f / (fwd_ms * 1e-3) / 1e12,
                                                       "frac": ops_f / (fwd_ms * 1e-3) / PEAK_LANE_OPS}}}
         cam_rays, sh_rays = stats[2], stats[5]
@@ -256,16 +296,16 @@ def main():
             "simd_efficiency": (stats[0] + stats[1] + stats[3] + stats[4]) /
                                max(64.0 * (stats[6] + stats[7] + stats[8] + stats[9]), 1.0)}
         out["rays_cast_per_s"] = (W * H * S + sh_rays) * args.steps / dt
-        del rc
-        if args.batch_jobs > 0:
-            out["batch"] = batch_bench(ctx, mt, args.batch_jobs, args.batch_steps, 2)
-            print(json.dumps({"progress": "batch", **out["batch"]}), file=sys.stderr, flush=True)
-        if args.serve_requests > 0:
-            out["serving"] = serve_bench(ctx, mt, args.serve_requests, args.serve_rate, args.serve_steps,
-                                         int(args.serve_budget_gb * 2**30))
-            print(json.dumps({"progress": "serving"}), file=sys.stderr, flush=True)
-        if not args.no_cpu_baseline:
-            out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, S, L, W)
+    del rc
+    if args.batch_jobs > 0:
+        out["batch"] = batch_bench(ctx, mt, args.batch_jobs, args.batch_steps, 2)
+        print(json.dumps({"progress": "batch", **out["batch"]}), file=sys.stderr, flush=True)
+    if args.serve_requests > 0:
+        out["serving"] = serve_bench(ctx, mt, args.serve_requests, args.serve_rate, args.serve_steps,
+                                     int(args.serve_budget_gb * 2**30))
+        print(json.dumps({"progress": "serving"}), file=sys.stderr, flush=True)
+    if not args.profile_only and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, S, L, W)
     print(json.dumps(out), flush=True)
 
 
