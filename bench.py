@@ -38,7 +38,7 @@ C_FRAME = 45      # hit point, interpolated normal + normalise, attributes, cos_
 C_LIGHT = 35      # light point, direction, distance, two cosines, geometry term
 C_SETUP = 15      # shadow-ray setup (reciprocal direction, shear)
 C_BRDF = 60       # half vector, D, two G1, Fresnel, combination
-C_NODE = 30       # two slab tests (6 fma + 6 min/max + 2 min3/max3 + 1 cmp each)
+C_BOX = 15        # one slab test (6 fma + 6 min/max + min3/max3 + 1 cmp)
 C_LEAF = 34       # watertight ray/triangle test
 ADJ_FACTOR = 3.0  # reverse-mode shading costs ~3x the forward shading
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock (packed FP32 disabled)
@@ -72,9 +72,9 @@ def algorithmic_ops(stats, W, H, S, L, backward=False):
     """Lane-operations the algorithm needs for one render (forward) or one
     adjoint pass (backward: same traversals + ~3x shading), from the counted
     per-ray visits of the tree."""
-    cam_int, cam_leaf, cam_rays, sh_int, sh_leaf, sh_rays = stats[:6]
+    cam_box, cam_leaf, cam_rays, sh_box, sh_leaf, sh_rays = stats[:6]
     samples = W * H * S
-    trav = (cam_int + sh_int) * C_NODE + (cam_leaf + sh_leaf) * C_LEAF
+    trav = (cam_box + sh_box) * C_BOX + (cam_leaf + sh_leaf) * C_LEAF
     shade = samples * (C_RNG + C_CAM) + cam_rays * C_FRAME + cam_rays * L * (C_RNG + C_LIGHT)
     shade += sh_rays * (C_SETUP + C_BRDF)
     if backward:
@@ -289,12 +289,15 @@ def main():
                                                       "frac": ops_f / (fwd_ms * 1e-3) / PEAK_LANE_OPS}}}
         cam_rays, sh_rays = stats[2], stats[5]
         out["traversal"] = {
+            "tree": "4-wide (collapsed LBVH), one triangle per leaf",
             "camera_rays": cam_rays, "shadow_rays_traced": sh_rays,
-            "visits_per_camera_ray": (stats[0] + stats[1]) / max(cam_rays, 1),
-            "visits_per_shadow_ray": (stats[3] + stats[4]) / max(sh_rays, 1),
-            # node visits single-ray traversals would make / lane-visits the packets executed
+            "box_tests_per_camera_ray": stats[0] / max(cam_rays, 1),
+            "tri_tests_per_camera_ray": stats[1] / max(cam_rays, 1),
+            "box_tests_per_shadow_ray": stats[3] / max(sh_rays, 1),
+            "tri_tests_per_shadow_ray": stats[4] / max(sh_rays, 1),
+            # box and triangle tests single-ray traversals would make / lane tests the packets executed
             "simd_efficiency": (stats[0] + stats[1] + stats[3] + stats[4]) /
-                               max(64.0 * (stats[6] + stats[7] + stats[8] + stats[9]), 1.0)}
+                               max(64.0 * (4 * (stats[6] + stats[8]) + stats[7] + stats[9]), 1.0)}
         out["rays_cast_per_s"] = (W * H * S + sh_rays) * args.steps / dt
     del rc
     if args.batch_jobs > 0:

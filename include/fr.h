@@ -135,10 +135,11 @@ typedef struct {
   uint8_t* dbg_pflag;
   uint8_t* dbg_vis;
   /* Traversal statistics of the forward dump (device, nullable, accumulated):
-   * [10] uint64: camera rays' child-box entries into internal nodes, into
-   * leaves, camera rays traced; the same three for shadow rays; node visits
-   * and leaf visits executed by the wave packets for camera rays, then for
-   * shadow rays. */
+   * [10] uint64: for camera rays, the child boxes a single-ray traversal of
+   * each ray tests (the children of every 4-wide node its ray enters), its
+   * triangle tests, and the rays traced; the same three for shadow rays;
+   * then the node visits and leaf visits executed by the wave packets for
+   * camera rays, then for shadow rays. */
   uint64_t* dbg_stats;
   /* Timing (nullable): two hipEvent_t recorded on the stream immediately
    * before and after the main render kernel of the call (the forward render

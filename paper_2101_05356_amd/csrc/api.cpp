@@ -63,7 +63,7 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
     return fail(ctx, FR_ERR_INVALID_ARG, "bad brdf_variant");
   if (m->d.built == 0) return fail(ctx, FR_ERR_INVALID_ARG, "fr_mesh_update(FR_REBUILD) must run first");
   const fr::MeshDev& d = m->d;
-  a.nodes = d.nodes; a.recs = d.recs; a.tris = d.tris; a.verts = s->verts; a.normals = d.normals;
+  a.nodes = d.nodes4; a.recs = d.recs; a.tris = d.tris; a.verts = s->verts; a.normals = d.normals;
   a.diffuse = s->diffuse; a.specular = s->specular; a.roughness = s->roughness;
   a.lights = d.lights; a.cam = s->cam;
   a.N = d.N; a.F = d.F; a.L = s->n_lights;
@@ -232,7 +232,7 @@ int fr_mesh_destroy(fr_mesh* m) {
   void* ptrs[] = {d.tris, d.vf_off, d.vf_idx, d.normals, d.nlen, d.gnorm, d.edges, d.edge_faces, d.nodes, d.recs,
                   d.order, d.node_parent, d.leaf_parent, d.flags, d.keys[0], d.keys[1], d.vals[0], d.vals[1],
                   d.hist, d.partial, d.scene_box, d.depth, d.lights, d.ltmp, d.edge_len, d.edge_cdf, d.face_front,
-                  d.scan_part, d.img_partial, d.acc, d.slots, m->loss_scratch, m->loss_gtmp};
+                  d.scan_part, d.img_partial, d.acc, d.slots, d.nodes4, d.n4_src, m->loss_scratch, m->loss_gtmp};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -251,9 +251,11 @@ int fr_mesh_update(fr_mesh* m, const float* d_verts, int mode, fr_stream stream)
     const int rc = fr::bvh_build(m->d, d_verts, st, &depth);
     if (rc != FR_OK) { m->d.built = 0; return fail(ctx, rc, "BVH build failed (device error or invalid topology)"); }
     m->d.bvh_depth = depth;
-    if (depth > fr::kStackDepth) {
+    // the 4-wide traversal pushes at most three entries per level
+    if (depth > fr::kStackDepth || 3 * m->d.depth4 > fr::kStackDepth) {
       m->d.built = 0;
-      return fail(ctx, FR_ERR_LIMIT, "BVH depth " + std::to_string(depth) + " exceeds the traversal stack");
+      return fail(ctx, FR_ERR_LIMIT, "BVH depth " + std::to_string(depth) + " (4-wide " +
+                                         std::to_string(m->d.depth4) + ") exceeds the traversal stack");
     }
     m->d.built = 1;
   } else {
@@ -530,8 +532,9 @@ size_t fr_job_bytes(const fr_model* m, const fr_job_desc* d) {
   Carver c;
   layout_job(c, m, d, J, std::max(1, fr::cdiv(d->n_lights, fr::kLightChunkFwd)));
   const size_t F = m->topo.F, N = m->topo.N, E = m->topo.edges.size() / 2;
-  // mesh: topology, normals, BVH (64-byte nodes, 48-byte records), sort buffers, edge tables
-  const size_t mesh = F * (12 + 12 + 64 + 48 + 4 * 8 + 1) + N * (4 + 4 * 7) + E * (16 + 16);
+  // mesh: topology, normals, BVH (64-byte binary nodes, 4-wide nodes for about
+  // half of them, 48-byte records), sort buffers, edge tables, accumulators
+  const size_t mesh = F * (12 + 12 + 64 + 80 + 48 + 4 * 8 + 1) + N * (4 + 4 * 7 + 13 * 8) + E * (16 + 16);
   return c.off + mesh;
 }
 
@@ -630,7 +633,7 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   J.zero_stride = fr::cdiv(std::max(n_param, 3 * N), 256) * 256;
   J.n_param = n_param; J.off_alb = md->K_geo; J.off_pose = md->K_geo + md->K_alb; J.off_rad = n_param - 3 * L;
   J.tris = md_.tris; J.vf_off = md_.vf_off; J.vf_idx = md_.vf_idx; J.normals = md_.normals; J.nlen = md_.nlen;
-  J.nodes = md_.nodes; J.recs = md_.recs; J.order = md_.order; J.node_parent = md_.node_parent;
+  J.nodes = md_.nodes; J.nodes4 = md_.nodes4; J.n4_src = md_.n4_src; J.n4 = md_.n4; J.recs = md_.recs; J.order = md_.order; J.node_parent = md_.node_parent;
   J.leaf_parent = md_.leaf_parent; J.flags = md_.flags;
   J.edge_faces = md_.edge_faces; J.face_front = md_.face_front; J.edge_len = md_.edge_len; J.edge_cdf = md_.edge_cdf;
   J.smooth = d->smooth ? 1 : 0;

@@ -80,7 +80,7 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
       V3 gx = {0, 0, 0}, gns = {0, 0, 0}, gwo = {0, 0, 0}, gc = {0, 0, 0}, gs = {0, 0, 0};
       float gr = 0.0f;
       for (int j = j0; j < j1; ++j) {
-        const LightRec& Lj = a.lights[j];
+        const LightRec Lj = load_const(a.lights, j);
         LightSample ls;
         const bool lit = shaded && light_sample(a, ps.pid, s, j, Lj, fr, ls);
         Ray sr;
@@ -273,7 +273,7 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
     if (lds[i] != 0) atomicAdd(slot + i, lds[i]);
 }
 
-__global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, const float* __restrict__ dEdp, FixGrads g,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_render_bwd(RenderArgs a, const float* __restrict__ dEdp, FixGrads g,
                                                     fix_t* __restrict__ slots) {
   render_bwd_block(a, dEdp, g, slots, blockIdx.x);
 }

@@ -23,7 +23,7 @@ struct JobDev {
   float* param; float* grad; float* adam_m; float* adam_v; const float* lr;
   int n_param, off_alb, off_pose, off_rad;
   const int32_t* tris; const int32_t* vf_off; const int32_t* vf_idx; float* normals; float* nlen;
-  BvhNode* nodes; TriRec* recs; const int32_t* order; const int32_t* node_parent; const int32_t* leaf_parent;
+  BvhNode* nodes; Bvh4Node* nodes4; const int32_t* n4_src; int n4; TriRec* recs; const int32_t* order; const int32_t* node_parent; const int32_t* leaf_parent;
   uint32_t* flags;
   const int32_t* edge_faces; uint8_t* face_front; double* edge_len; double* edge_cdf;
   const float* lp0; const float* le1; const float* le2; const int32_t* lshape; LightRec* lights;

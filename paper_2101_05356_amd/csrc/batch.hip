@@ -51,6 +51,7 @@ FR_BATCH_KERNEL(kb_refit, 256) {
   FR_JOB_PROLOGUE refit_block(J.v_w, J.tris, J.order, J.F, J.nodes, J.node_parent, J.leaf_parent, J.flags, J.recs,
                               kBoxPad, lb);
 }
+FR_BATCH_KERNEL(kb_gather4, 256) { FR_JOB_PROLOGUE gather4_block(J.nodes, J.n4_src, J.n4, J.nodes4, lb); }
 FR_BATCH_KERNEL(kb_light_setup, 256) {
   FR_JOB_PROLOGUE light_setup_block(J.lp0, J.le1, J.le2, J.param + J.off_rad, J.lshape, J.ra.L, J.lights, lb);
 }
@@ -141,7 +142,7 @@ __global__ void kb_advance(JobDev* jobs, int njobs) {
 // Host side
 // ---------------------------------------------------------------------------
 enum Stage {
-  S_BLEND_GEO, S_BLEND_ALB, S_POSE, S_NORMALS, S_ZERO_FLAGS, S_REFIT, S_LIGHTS, S_FWD, S_SUM, S_LOSS, S_LOSS_FINAL,
+  S_BLEND_GEO, S_BLEND_ALB, S_POSE, S_NORMALS, S_ZERO_FLAGS, S_REFIT, S_GATHER4, S_LIGHTS, S_FWD, S_SUM, S_LOSS, S_LOSS_FINAL,
   S_SMOOTH_ADJ, S_ZERO_GRADS, S_BWD, S_SLOTS, S_NBWD_P, S_NBWD_G, S_FACE_FRONT, S_EDGE_LEN, S_EDGE_SCAN,
   S_EDGE_SAMPLES, S_FIX_FINALIZE, S_POSE_BWD_V, S_POSE_BWD_P, S_BLEND_BWD_GEO, S_BLEND_BWD_ALB, S_ADAM, S_COUNT
 };
@@ -154,6 +155,7 @@ static int stage_blocks(const JobDev& J, int s) {
     case S_FIX_FINALIZE: return cdiv(3 * N, 256);
     case S_ZERO_FLAGS: return cdiv(F > 1 ? F - 1 : 1, 256);
     case S_REFIT: case S_FACE_FRONT: return cdiv(F, 256);
+    case S_GATHER4: return cdiv(4 * J.n4, 256);
     case S_LIGHTS: return cdiv(J.ra.L, 256);
     case S_FWD: return wave_blocks_items(J.ra);
     case S_SUM: return J.ra.n_lchunks > 1 ? cdiv(3 * px, 256) : 0;
@@ -229,6 +231,7 @@ void Batch::launch_step(hipStream_t st) {
   FR_LAUNCH(kb_normals, S_NORMALS, 256, 0);
   FR_LAUNCH(kb_zero_flags, S_ZERO_FLAGS, 256, 0);
   FR_LAUNCH(kb_refit, S_REFIT, 256, 0);
+  FR_LAUNCH(kb_gather4, S_GATHER4, 256, 0);
   FR_LAUNCH(kb_light_setup, S_LIGHTS, 256, 0);
   FR_LAUNCH(kb_render_fwd, S_FWD, 256, 0);
   FR_LAUNCH(kb_sum_chunks, S_SUM, 256, 0);

@@ -8,6 +8,9 @@
 //
 // A boundary-to-root walk per leaf gives the depth; the traversal stack is 64
 // entries, so trees deeper than that are rejected by the host.
+#include <cstring>
+#include <vector>
+
 #include "fr_kernels.h"
 
 namespace fr {
@@ -298,6 +301,30 @@ __global__ __launch_bounds__(256) void k_leaf_depth(const int32_t* __restrict__ 
   atomicMax(max_depth, p == 0 ? d : 1 << 20);
 }
 
+// Child boxes of the 4-wide nodes, copied from the binary tree after a refit:
+// one thread per (node, slot).
+__device__ __forceinline__ void gather4_block(const BvhNode* __restrict__ nodes, const int32_t* __restrict__ src,
+                                              int n4, Bvh4Node* __restrict__ out, int bid) {
+  const int t = bid * 256 + threadIdx.x;
+  if (t >= 4 * n4) return;
+  const int i = t >> 2, k = t & 3;
+  const int sref = src[t];
+  float b[6] = {3.4e38f, 3.4e38f, 3.4e38f, -3.4e38f, -3.4e38f, -3.4e38f};
+  if (sref >= 0) {
+    const float* bb = (sref & 1) ? nodes[sref >> 1].b1 : nodes[sref >> 1].b0;
+    for (int q = 0; q < 6; ++q) b[q] = bb[q];
+  }
+  for (int a = 0; a < 3; ++a) {
+    out[i].lo[a][k] = b[a];
+    out[i].hi[a][k] = b[3 + a];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gather4(const BvhNode* __restrict__ nodes, const int32_t* __restrict__ src,
+                                                 int n4, Bvh4Node* __restrict__ out) {
+  gather4_block(nodes, src, n4, out, blockIdx.x);
+}
+
 __device__ __forceinline__ void zero_u32_block(uint32_t* p, int n, int bid) {
   const int i = bid * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -317,6 +344,79 @@ void bvh_refit(MeshDev& m, const float* d_verts, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u32, dim3(cdiv(nflags, 256)), dim3(256), 0, st, m.flags, nflags);
   hipLaunchKernelGGL(k_refit, dim3(cdiv(F, 256)), dim3(256), 0, st, d_verts, m.tris, m.order, F, m.nodes,
                      m.node_parent, m.leaf_parent, m.flags, m.recs, kBoxPad);
+  if (m.n4 > 0)
+    hipLaunchKernelGGL(k_gather4, dim3(cdiv(4 * m.n4, 256)), dim3(256), 0, st, m.nodes, m.n4_src, m.n4, m.nodes4);
+}
+
+// Collapse the binary tree into the 4-wide traversal tree (host side, once
+// per build): every 4-wide node takes the grandchildren of a binary node
+// (a leaf child takes its slot directly), nodes numbered in depth-first
+// order.  Boxes are filled by k_gather4 at every refit.
+static int bvh_collapse(MeshDev& m, hipStream_t st) {
+  const int F = m.F;
+  m.n4 = 0;
+  m.depth4 = 0;
+  if (F <= 1) return FR_OK;
+  std::vector<BvhNode> bn((size_t)F - 1);
+  if (hipMemcpyAsync(bn.data(), m.nodes, sizeof(BvhNode) * (F - 1), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return FR_ERR_DEVICE;
+  auto child = [&](int b, int s) { return s ? bn[b].c1 : bn[b].c0; };
+  // slots of the 4-wide node made from binary node b: (binary ref, box source)
+  auto slots = [&](int b, int ref[4], int src[4]) {
+    int n = 0;
+    for (int s = 0; s < 2; ++s) {
+      const int c = child(b, s);
+      if (c < 0) { ref[n] = c; src[n] = 2 * b + s; ++n; continue; }
+      for (int t = 0; t < 2; ++t) { ref[n] = child(c, t); src[n] = 2 * c + t; ++n; }
+    }
+    for (int k = n; k < 4; ++k) { ref[k] = kEmpty; src[k] = -1; }
+    return n;
+  };
+  // depth-first numbering
+  std::vector<int> id((size_t)F - 1, -1), order, depth;
+  std::vector<int> todo = {0}, tdepth = {1};
+  while (!todo.empty()) {
+    const int b = todo.back(), d = tdepth.back();
+    todo.pop_back(); tdepth.pop_back();
+    id[b] = (int)order.size();
+    order.push_back(b);
+    m.depth4 = std::max(m.depth4, d);
+    int ref[4], src[4];
+    const int n = slots(b, ref, src);
+    for (int k = n - 1; k >= 0; --k)
+      if (ref[k] >= 0) { todo.push_back(ref[k]); tdepth.push_back(d + 1); }
+  }
+  const int n4 = (int)order.size();
+  std::vector<Bvh4Node> h4((size_t)n4);
+  std::vector<int32_t> hsrc((size_t)4 * n4);
+  for (int i = 0; i < n4; ++i) {
+    int ref[4], src[4];
+    slots(order[i], ref, src);
+    Bvh4Node& nd = h4[i];
+    std::memset(&nd, 0, sizeof(nd));
+    for (int k = 0; k < 4; ++k) {
+      nd.c[k] = ref[k] >= 0 ? id[ref[k]] : ref[k];
+      int sub = 0;
+      if (ref[k] >= 0) { int r2[4], s2[4]; sub = slots(ref[k], r2, s2); }
+      nd.nsub[k] = sub;
+      hsrc[(size_t)4 * i + k] = src[k];
+    }
+  }
+  if (n4 > m.n4_cap) {
+    if (m.nodes4) (void)hipFree(m.nodes4);
+    if (m.n4_src) (void)hipFree(m.n4_src);
+    m.nodes4 = nullptr; m.n4_src = nullptr; m.n4_cap = 0;
+    if (hipMalloc(&m.nodes4, sizeof(Bvh4Node) * n4) != hipSuccess) return FR_ERR_OOM;
+    if (hipMalloc(&m.n4_src, sizeof(int32_t) * 4 * n4) != hipSuccess) return FR_ERR_OOM;
+    m.n4_cap = n4;
+  }
+  if (hipMemcpyAsync(m.nodes4, h4.data(), sizeof(Bvh4Node) * n4, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(m.n4_src, hsrc.data(), sizeof(int32_t) * 4 * n4, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return FR_ERR_DEVICE;
+  m.n4 = n4;
+  return FR_OK;
 }
 
 int bvh_build(MeshDev& m, const float* d_verts, hipStream_t st, int* depth_out) {
@@ -352,6 +452,8 @@ int bvh_build(MeshDev& m, const float* d_verts, hipStream_t st, int* depth_out) 
   if (hipMemcpyAsync(chk, m.depth, sizeof(chk), hipMemcpyDeviceToHost, st) != hipSuccess) return FR_ERR_DEVICE;
   if (hipStreamSynchronize(st) != hipSuccess) return FR_ERR_DEVICE;
   if (chk[1] != 0) return FR_ERR_LIMIT;
+  const int rc = bvh_collapse(m, st);
+  if (rc != FR_OK) return rc;
   bvh_refit(m, d_verts, st);
   hipLaunchKernelGGL(k_leaf_depth, dim3(cdiv(F, 256)), dim3(256), 0, st, m.node_parent, m.leaf_parent, F, m.depth);
   int32_t depth = 0;

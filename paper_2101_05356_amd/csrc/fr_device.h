@@ -1,9 +1,11 @@
 // Device building blocks of the MI355X face renderer (gfx950, wave64).
 //
 //  * Philox4x32-10 counter-based generator (Salmon et al., SC'11).
-//  * BVH layout: binary radix tree, one 64-byte node per internal node
-//    holding both children's boxes (one scalar 16-dword load per visit), and
-//    a leaf-ordered 48-byte triangle record array.
+//  * BVH layout: a binary radix tree (built and refitted; one 64-byte node
+//    per internal node holding both children's boxes) collapsed into a 4-wide
+//    tree for traversal (128-byte nodes: four child boxes in SoA form, two
+//    scalar 16-dword loads per visit), and a leaf-ordered 48-byte triangle
+//    record array.
 //  * Watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013).
 //  * Wave-packet traversal: the 64 lanes of a wave trace their own rays
 //    through ONE shared, wave-uniform traversal order.  Node and triangle
@@ -52,6 +54,19 @@ struct alignas(16) BvhNode {
   int32_t pad0, pad1;
 };
 static_assert(sizeof(BvhNode) == 64, "node must be one 64-byte line");
+
+// 4-wide traversal node: the boxes of up to four children (lo/hi per axis,
+// child k in column k), their references (>= 0 a node, kEmpty an unused slot,
+// otherwise ~leaf slot) and, per child, the number of children of that child
+// node (statistics of the debug dump).
+constexpr int32_t kEmpty = INT32_MIN;
+struct alignas(64) Bvh4Node {
+  float lo[3][4];
+  float hi[3][4];
+  int32_t c[4];
+  int32_t nsub[4];
+};
+static_assert(sizeof(Bvh4Node) == 128, "4-wide node is two 64-byte lines");
 
 struct alignas(16) TriRec {
   float v[9];      // v0, v1, v2
@@ -164,15 +179,27 @@ __device__ __forceinline__ void ray_setup(Ray& r) {
 // Slab test of one (wave-uniform) box against this lane's ray; returns the
 // entry distance in tnear.  Branch-free.  Boxes are padded by kBoxPad at refit,
 // which covers the rounding of the plane distances (conservative traversal).
-__device__ __forceinline__ bool slab(const Ray& r, const float* b, float tmax, float& tnear) {
+__device__ __forceinline__ void slab(const Ray& r, const float* b, float tmax, float& tnear, float& tfar) {
   const float tx0 = fmaf(b[0], r.inv.x, r.oinv.x), tx1 = fmaf(b[3], r.inv.x, r.oinv.x);
   const float ty0 = fmaf(b[1], r.inv.y, r.oinv.y), ty1 = fmaf(b[4], r.inv.y, r.oinv.y);
   const float tz0 = fmaf(b[2], r.inv.z, r.oinv.z), tz1 = fmaf(b[5], r.inv.z, r.oinv.z);
-  const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), r.tmin));
-  const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax));
-  tnear = tn;
-  return tn <= tf;
+  tnear = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), r.tmin));
+  tfar = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax));
 }
+
+// Slab test of child k of a 4-wide node.
+__device__ __forceinline__ void slab4(const Ray& r, const Bvh4Node& n, int k, float tmax, float& tnear,
+                                      float& tfar) {
+  const float tx0 = fmaf(n.lo[0][k], r.inv.x, r.oinv.x), tx1 = fmaf(n.hi[0][k], r.inv.x, r.oinv.x);
+  const float ty0 = fmaf(n.lo[1][k], r.inv.y, r.oinv.y), ty1 = fmaf(n.hi[1][k], r.inv.y, r.oinv.y);
+  const float tz0 = fmaf(n.lo[2][k], r.inv.z, r.oinv.z), tz1 = fmaf(n.hi[2][k], r.inv.z, r.oinv.z);
+  tnear = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), r.tmin));
+  tfar = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax));
+}
+
+// Lane mask of a <= b over the executing lanes (the compare's own mask, no
+// round trip through a VGPR).
+__device__ __forceinline__ uint64_t mask_le(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, 5 /* OLE */); }
 
 __device__ __forceinline__ float shear(const V3& M, float c, float x, float y, float z) {
   return fmaf(x, M.x, fmaf(y, M.y, fmaf(z, M.z, c)));
@@ -245,66 +272,124 @@ __device__ __forceinline__ bool hit_ambiguous(const HitState& h) {
 // ray enters (internal nodes / leaves), i.e. the visits a single-ray
 // traversal of the same tree would make.  Wave counts: node and leaf visits
 // the packet executes.
+// Read-only views in the constant address space: the tree, the triangle
+// records and the light records are not written while a render kernel runs,
+// so wave-uniform reads of them become scalar loads (s_load, scalar cache)
+// even in kernels that also write global memory (the backward's atomics
+// would otherwise force vector loads of every node).
+template <class T>
+__device__ __forceinline__ T load_const(const T* p, int i) {
+  static_assert(sizeof(T) % 16 == 0, "records are whole 16-byte vectors");
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const __attribute__((address_space(4))) v4u* q = (const __attribute__((address_space(4))) v4u*)(p + i);
+  T out;
+  v4u* o = reinterpret_cast<v4u*>(&out);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 16); ++k) o[k] = q[k];
+  return out;
+}
+
 struct TravStats {
-  uint32_t lane_int, lane_leaf, wave_int, wave_leaf, rays;
+  // lane_box: child boxes tested by a single-ray traversal of this lane's ray
+  // (the children of every node its ray enters); lane_leaf: its triangle
+  // tests; wave_int / wave_leaf: node / leaf visits the packet executed
+  uint32_t lane_box, lane_leaf, wave_int, wave_leaf, rays;
 };
 
-// Wave-packet traversal.  Every lane of the wave must call it (uniform control
-// flow).  ANY = true: shadow/any-hit query over (tmin, tmax), `occluded` is set
-// on the first accepted triangle and the lane drops out.  ANY = false:
-// closest hit, ties in t resolved to the lowest triangle id.
+// Sorting-network step on (key, child, mask) triples: a <= b afterwards.
+__device__ __forceinline__ void order2(float& ka, int& ca, uint64_t& ma, float& kb, int& cb, uint64_t& mb) {
+  if (kb < ka) {
+    const float k = ka; ka = kb; kb = k;
+    const int c = ca; ca = cb; cb = c;
+    const uint64_t m = ma; ma = mb; mb = m;
+  }
+}
+
+// Wave-packet traversal of the 4-wide tree.  Every lane of the wave must call
+// it (uniform control flow).  ANY = true: shadow/any-hit query over
+// (tmin, tmax), `occluded` is set on the first accepted triangle and the lane
+// drops out.  ANY = false: closest hit, ties in t resolved to the lowest
+// triangle id.
 template <bool ANY, bool DUMP>
-__device__ __forceinline__ void trace(const BvhNode* __restrict__ nodes, const TriRec* __restrict__ tris, int n_tris,
+__device__ __forceinline__ void trace(const Bvh4Node* __restrict__ nodes, const TriRec* __restrict__ tris, int n_tris,
                                       const Ray& r, bool active, int exclude, HitState& h, bool& occluded,
                                       TravStats* st = nullptr) {
   uint64_t live = ballot(active);
   if (live == 0) return;
-  if (DUMP && st && active) { st->rays += 1; st->lane_int += n_tris > 1 ? 1 : 0; st->lane_leaf += n_tris > 1 ? 0 : 1; }
   const int lane = lane_id();
+  if (DUMP && st && active) {
+    st->rays += 1;
+    if (n_tris > 1) {
+      for (int k = 0; k < 4; ++k) st->lane_box += load_const(nodes, 0).c[k] != kEmpty ? 1 : 0;
+    } else {
+      st->lane_leaf += 1;
+    }
+  }
   int stack = 0;
   int sp = 0;
   int node = n_tris > 1 ? 0 : ~0;
   const float tpad = DUMP ? kFlagT : 0.0f;
-  // A tree visits each of its 2F - 1 nodes at most once; the cap only guards
-  // against a corrupted structure.
+  // A tree visits each of its nodes and leaves at most once; the cap only
+  // guards against a corrupted structure.
   int budget = 2 * n_tris + 64;
+  bool clean = false;   // dump builds, any hit: an unambiguous occluder was found
   while (--budget > 0) {
     if (node >= 0) {
-      const BvhNode nd = nodes[node];               // one 64-byte scalar load
+      const Bvh4Node nd = load_const(nodes, node);  // two 64-byte scalar loads
       const float tcur = (ANY ? r.tmax : h.t) + tpad;
-      float tn0, tn1;
-      const bool h0 = slab(r, nd.b0, tcur, tn0) & active;
-      const bool h1 = slab(r, nd.b1, tcur, tn1) & active;
-      const uint64_t m0 = ballot(h0), m1 = ballot(h1);
+      float tn0, tn1, tn2, tn3, tf;
+      slab4(r, nd, 0, tcur, tn0, tf);
+      uint64_t m0 = nd.c[0] != kEmpty ? (mask_le(tn0, tf) & live) : 0ull;
+      slab4(r, nd, 1, tcur, tn1, tf);
+      uint64_t m1 = nd.c[1] != kEmpty ? (mask_le(tn1, tf) & live) : 0ull;
+      slab4(r, nd, 2, tcur, tn2, tf);
+      uint64_t m2 = nd.c[2] != kEmpty ? (mask_le(tn2, tf) & live) : 0ull;
+      slab4(r, nd, 3, tcur, tn3, tf);
+      uint64_t m3 = nd.c[3] != kEmpty ? (mask_le(tn3, tf) & live) : 0ull;
       if (DUMP && st) {
         st->wave_int += 1;
-        st->lane_int += (h0 && nd.c0 >= 0 ? 1 : 0) + (h1 && nd.c1 >= 0 ? 1 : 0);
-        st->lane_leaf += (h0 && nd.c0 < 0 ? 1 : 0) + (h1 && nd.c1 < 0 ? 1 : 0);
+        const uint64_t mm[4] = {m0, m1, m2, m3};
+        for (int k = 0; k < 4; ++k)
+          if ((mm[k] >> lane) & 1) {
+            if (nd.c[k] >= 0) st->lane_box += nd.nsub[k];
+            else st->lane_leaf += 1;
+          }
       }
-      if (m0 && m1) {
-        const uint64_t both = m0 & m1;
-        const int ref = both ? (int)__builtin_ctzll(both) : (int)__builtin_ctzll(m0);
-        const bool near0 = readlane_i(tn0 <= tn1 ? 1 : 0, ref) != 0;
-        const int nearc = near0 ? nd.c0 : nd.c1, farc = near0 ? nd.c1 : nd.c0;
-        if (sp < kStackDepth) {                 // depth <= 64 is checked at build
-          stack = (lane == sp) ? farc : stack;  // entry sp lives in lane sp
-          ++sp;
-        }
-        node = nearc;
-        continue;
+      int c0 = nd.c[0], c1 = nd.c[1], c2 = nd.c[2], c3 = nd.c[3];
+      if (!ANY && (m0 | m1 | m2 | m3)) {
+        // nearest child first, as seen by one lane that enters a child
+        const int ref = (int)__builtin_ctzll(m0 | m1 | m2 | m3);
+        float k0 = m0 ? readlane_f(tn0, ref) : 3.4e38f, k1 = m1 ? readlane_f(tn1, ref) : 3.4e38f;
+        float k2 = m2 ? readlane_f(tn2, ref) : 3.4e38f, k3 = m3 ? readlane_f(tn3, ref) : 3.4e38f;
+        order2(k0, c0, m0, k1, c1, m1);
+        order2(k2, c2, m2, k3, c3, m3);
+        order2(k0, c0, m0, k2, c2, m2);
+        order2(k1, c1, m1, k3, c3, m3);
+        order2(k1, c1, m1, k2, c2, m2);
       }
-      if (m0) { node = nd.c0; continue; }
-      if (m1) { node = nd.c1; continue; }
+      // go to the first child entered, push the others (last first)
+      int next = kEmpty;
+      if (m3) next = c3;
+      if (m2) { if (next != kEmpty) { stack = (lane == sp) ? next : stack; ++sp; } next = c2; }
+      if (m1) { if (next != kEmpty) { stack = (lane == sp) ? next : stack; ++sp; } next = c1; }
+      if (m0) { if (next != kEmpty) { stack = (lane == sp) ? next : stack; ++sp; } next = c0; }
+      if (next != kEmpty) { node = next; continue; }
     } else {
-      const TriRec tr = tris[~node];                // 48-byte scalar load
+      const TriRec tr = load_const(tris, ~node);    // 48-byte scalar load
       if (DUMP && st) st->wave_leaf += 1;
       float t = 0.0f;
       const float tmax = ANY ? r.tmax : h.t;
-      const bool hit = tri_test<DUMP>(r, tr.v, tmax, t, h.tamb) & active & (tr.id != exclude);
+      float amb = 3.4e38f;
+      const bool hit = tri_test<DUMP>(r, tr.v, tmax, t, amb) & active & (tr.id != exclude);
+      if (DUMP && active && tr.id != exclude) h.tamb = fminf(h.tamb, amb);
       if (DUMP && !ANY && hit && h.id >= 0 && fabsf(t - h.t) < kFlagT) h.tamb = fminf(h.tamb, t);
       if (ANY) {
         occluded = occluded | hit;
-        active = active & !hit;
+        // dump builds keep a lane whose hits so far are all near ambiguous:
+        // one unambiguous occluder settles the decision, whatever was seen
+        const bool settled = DUMP ? (hit && !(amb < 3.0e38f)) : hit;
+        if (DUMP && settled) clean = true;
+        active = active & !settled;
         live = ballot(active);
         if (live == 0) break;
       } else if (hit && (t < h.t || (t == h.t && tr.id < h.id))) {
@@ -316,6 +401,7 @@ __device__ __forceinline__ void trace(const BvhNode* __restrict__ nodes, const T
     --sp;
     node = readlane_i(stack, sp);
   }
+  if (DUMP && ANY && clean) h.tamb = 3.4e38f;   // the decision cannot flip
 }
 
 }  // namespace fr

@@ -78,8 +78,11 @@ struct MeshDev {
   // unique edges and their faces, for the boundary term
   int32_t* edges = nullptr;         // [E*2]
   int32_t* edge_faces = nullptr;    // [E*2]
-  // BVH
+  // BVH: binary tree (build + refit) and its 4-wide collapse (traversal)
   BvhNode* nodes = nullptr;         // [max(F-1,1)]
+  Bvh4Node* nodes4 = nullptr;       // [n4]
+  int32_t* n4_src = nullptr;        // [n4*4]: binary parent * 2 + side holding each child box, -1 unused
+  int n4 = 0, n4_cap = 0, depth4 = 0;
   TriRec* recs = nullptr;           // [F]
   int32_t* order = nullptr;         // [F] sorted slot -> triangle id
   int32_t* node_parent = nullptr;   // [max(F-1,1)]
@@ -107,7 +110,7 @@ struct MeshDev {
 
 // Per-render constants shared by the forward, backward and edge kernels.
 struct RenderArgs {
-  const BvhNode* nodes;
+  const Bvh4Node* nodes;
   const TriRec* recs;
   const int32_t* tris;
   const float* verts;

@@ -38,7 +38,7 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
       a.dbg_pflag[rs] = pf ? 1 : 0;
     }
     for (int j = j0; j < j1; ++j) {
-      const LightRec& Lj = a.lights[j];
+      const LightRec Lj = load_const(a.lights, j);
       LightSample ls;
       const bool lit = shaded && light_sample(a, ps.pid, s, j, Lj, fr, ls);
       Ray sr;
@@ -66,7 +66,7 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
   }
   if (DUMP && a.dbg_stats) {
     // lane counts summed over the wave; wave counts taken once per wave
-    const uint32_t v[10] = {st.lane_int, st.lane_leaf, st.rays, st2.lane_int, st2.lane_leaf, st2.rays,
+    const uint32_t v[10] = {st.lane_box, st.lane_leaf, st.rays, st2.lane_box, st2.lane_leaf, st2.rays,
                             st.wave_int, st.wave_leaf, st2.wave_int, st2.wave_leaf};
     for (int k = 0; k < 10; ++k) {
       uint32_t x = v[k];
