@@ -81,6 +81,7 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
       float gr = 0.0f;
       for (int j = j0; j < j1; ++j) {
         const LightRec Lj = load_const(a.lights, j);
+        if (!ballot(shaded && light_may_contribute(Lj, fr))) continue;   // culled for the whole wave
         LightSample ls;
         const bool lit = shaded && light_sample(a, ps.pid, s, j, Lj, fr, ls);
         Ray sr;

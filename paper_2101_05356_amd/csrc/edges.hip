@@ -118,6 +118,7 @@ __device__ __forceinline__ void side_radiance(const RenderArgs& a, float fx, flo
   L = {0.0f, 0.0f, 0.0f};
   for (int j = j0; j < j1; ++j) {
     const LightRec Lj = load_const(a.lights, j);
+    if (!ballot(shaded && light_may_contribute(Lj, fr))) continue;   // culled for the whole wave
     const U4 r = philox((uint32_t)k, 0u, PURPOSE_EDGE + 1u + (uint32_t)j, a.step, a.k0, a.k1);
     LightSample ls;
     const bool lit = shaded && light_point(Lj, unit24(r.x), unit24(r.y), fr, ls);

@@ -202,6 +202,26 @@ __device__ __forceinline__ bool light_point(const LightRec& Lj, float u0, float 
   return ls.cos_s > 0.0f && ls.cos_a > 0.0f;
 }
 
+// Conservative cull of a whole light for this shading point: false only when
+// EVERY point q of the light fails one of light_point's two tests by a
+// margin far above the rounding of those tests: n_s . (q - x) < 0 at all
+// corners (the light lies below the tangent plane), or the point lies behind
+// the light's emitting plane.  A wave whose lanes all return false skips the
+// light (no random numbers, no shadow ray): the exact tests would have
+// culled every lane anyway, without ambiguity.
+__device__ __forceinline__ bool light_may_contribute(const LightRec& Lj, const Frame& f) {
+  const V3 d0 = {Lj.p0[0] - f.x.x, Lj.p0[1] - f.x.y, Lj.p0[2] - f.x.z};
+  const float a = dot(f.ns, d0);
+  const float b = f.ns.x * Lj.e1[0] + f.ns.y * Lj.e1[1] + f.ns.z * Lj.e1[2];
+  const float c = f.ns.x * Lj.e2[0] + f.ns.y * Lj.e2[1] + f.ns.z * Lj.e2[2];
+  float top = fmaxf(a, fmaxf(a + b, a + c));
+  if (Lj.shape != FR_LIGHT_TRIANGLE) top = fmaxf(top, a + b + c);
+  // na . (q - x) equals na . (p0 - x) for every q of the (planar) light
+  const float side = Lj.na[0] * d0.x + Lj.na[1] * d0.y + Lj.na[2] * d0.z;
+  const float alen = fabsf(Lj.na[0]) + fabsf(Lj.na[1]) + fabsf(Lj.na[2]);
+  return !(top < -1e-4f) && !(side < -1e-3f * alen);
+}
+
 __device__ __forceinline__ bool light_sample(const RenderArgs& a, int pid, int s, int j, const LightRec& Lj,
                                              const Frame& f, LightSample& ls) {
   const U4 r = philox((uint32_t)pid, (uint32_t)s, 1u + (uint32_t)j, a.step, a.k0, a.k1);

@@ -39,6 +39,10 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
     }
     for (int j = j0; j < j1; ++j) {
       const LightRec Lj = load_const(a.lights, j);
+      if (!ballot(shaded && light_may_contribute(Lj, fr))) {   // culled for the whole wave
+        if (DUMP && ps.valid) a.dbg_vis[rs * a.L + j] = shaded ? VIS_CULLED : VIS_NONE;
+        continue;
+      }
       LightSample ls;
       const bool lit = shaded && light_sample(a, ps.pid, s, j, Lj, fr, ls);
       Ray sr;
