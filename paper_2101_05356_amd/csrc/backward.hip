@@ -274,7 +274,7 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
     if (lds[i] != 0) atomicAdd(slot + i, lds[i]);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_render_bwd(RenderArgs a, const float* __restrict__ dEdp, FixGrads g,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_render_bwd(RenderArgs a, const float* __restrict__ dEdp, FixGrads g,
                                                     fix_t* __restrict__ slots) {
   render_bwd_block(a, dEdp, g, slots, blockIdx.x);
 }

@@ -55,7 +55,7 @@ FR_BATCH_KERNEL(kb_gather4, 256) { FR_JOB_PROLOGUE gather4_block(J.nodes, J.n4_s
 FR_BATCH_KERNEL(kb_light_setup, 256) {
   FR_JOB_PROLOGUE light_setup_block(J.lp0, J.le1, J.le2, J.param + J.off_rad, J.lshape, J.ra.L, J.lights, lb);
 }
-FR_BATCH_KERNEL(kb_render_fwd, 256) {
+__attribute__((amdgpu_waves_per_eu(8))) FR_BATCH_KERNEL(kb_render_fwd, 256) {
   FR_JOB_PROLOGUE render_fwd_block<false>(J.ra, J.ra.n_lchunks > 1 ? nullptr : J.image, lb);
 }
 FR_BATCH_KERNEL(kb_sum_chunks, 256) {
@@ -84,7 +84,7 @@ FR_BATCH_KERNEL(kb_zero_grads, 256) {
   for (int k = i; k < n9; k += J.zero_stride) J.acc[k] = 0;
   for (int k = i; k < nslot; k += J.zero_stride) J.lslots[k] = 0;
 }
-__attribute__((amdgpu_waves_per_eu(3))) FR_BATCH_KERNEL(kb_render_bwd, 256) {
+__attribute__((amdgpu_waves_per_eu(6))) FR_BATCH_KERNEL(kb_render_bwd, 256) {
   FR_JOB_PROLOGUE
   const FixGrads g = {J.acc, J.acc + 3 * J.N, J.acc + 6 * J.N, nullptr, nullptr};
   render_bwd_block(J.rb, J.dEdp, g, J.lslots, lb);

@@ -91,7 +91,7 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
 }
 
 template <bool DUMP>
-__global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, float* __restrict__ image) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_render_fwd(RenderArgs a, float* __restrict__ image) {
   render_fwd_block<DUMP>(a, image, blockIdx.x);
 }
 
