@@ -112,7 +112,7 @@ FR_BATCH_KERNEL(kb_edge_len, 256) {
                                  J.ea.aspect, J.ra.W, J.ra.H, J.edge_len, lb);
 }
 FR_BATCH_KERNEL(kb_edge_scan, 1024) { FR_JOB_PROLOGUE edge_scan_block(J.edge_len, J.ea.E, J.edge_cdf, lb); }
-FR_BATCH_KERNEL(kb_edge_samples, 256) { FR_JOB_PROLOGUE edge_samples_block<false>(J.rb, J.ea, lb); }
+__attribute__((amdgpu_waves_per_eu(6))) FR_BATCH_KERNEL(kb_edge_samples, 256) { FR_JOB_PROLOGUE edge_samples_block<false>(J.rb, J.ea, lb); }
 FR_BATCH_KERNEL(kb_pose_bwd_v, 256) { FR_JOB_PROLOGUE pose_bwd_v_block(J.N, J.param + J.off_pose, J.g_verts, J.g_vobj, lb); }
 FR_BATCH_KERNEL(kb_pose_bwd_p, 1024) {
   FR_JOB_PROLOGUE pose_bwd_p_block(J.v_obj, J.N, J.param + J.off_pose, J.g_verts, J.grad + J.off_pose, lb);
@@ -166,7 +166,7 @@ static int stage_blocks(const JobDev& J, int s) {
     case S_SLOTS: return 12 * J.ra.L + 12;
     case S_EDGE_LEN: return J.ea.n_samples > 0 ? cdiv(J.ea.E, 256) : 0;
     case S_EDGE_SCAN: return J.ea.n_samples > 0 ? 1 : 0;
-    case S_EDGE_SAMPLES: return J.ea.n_samples > 0 ? cdiv(cdiv(J.ea.n_samples, 64) * J.rb.n_lchunks, 4) : 0;
+    case S_EDGE_SAMPLES: return J.ea.n_samples > 0 ? cdiv(cdiv(J.ea.n_samples, 64) * J.ea.n_lchunks, 4) : 0;
     case S_POSE_BWD_P: return 1;
     case S_BLEND_BWD_GEO: return J.K_geo;
     case S_BLEND_BWD_ALB: return J.K_alb;

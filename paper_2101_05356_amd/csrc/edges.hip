@@ -149,8 +149,8 @@ template <bool DUMP>
 __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const EdgeArgs& e, int bid) {
   const int lane = threadIdx.x & 63;
   const int w = bid * 4 + (threadIdx.x >> 6);
-  const int group = w / a.n_lchunks, chunk = w - group * a.n_lchunks;
-  const int j0 = chunk * a.lc, j1 = min(a.L, j0 + a.lc);
+  const int group = w / e.n_lchunks, chunk = w - group * e.n_lchunks;
+  const int j0 = chunk * e.lc, j1 = min(a.L, j0 + e.lc);
   const int k = group * 64 + lane;
   const bool in = k < e.n_samples;
   const double ltot = e.cdf[e.E - 1];
@@ -241,7 +241,7 @@ __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const Ed
 }
 
 template <bool DUMP>
-__global__ __launch_bounds__(256) void k_edge_samples(RenderArgs a, EdgeArgs e) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_edge_samples(RenderArgs a, EdgeArgs e) {
   edge_samples_block<DUMP>(a, e, blockIdx.x);
 }
 
@@ -257,8 +257,10 @@ void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samp
   e.edges = m.edges; e.cdf = m.edge_cdf; e.E = m.E; e.n_samples = n_samples;
   e.th = tan_half; e.aspect = aspect; e.dEdp = dEdp; e.gverts = gverts; e.gcam = gcam;
   e.dbg_rec = dbg_rec; e.dbg_flag = dbg_flag;
+  e.lc = std::max(1, std::min(kLightChunkEdge, a.L));
+  e.n_lchunks = std::max(1, cdiv(a.L, e.lc));
   const int groups = (n_samples + 63) / 64;
-  const int blocks = (groups * a.n_lchunks + 3) / 4;
+  const int blocks = (groups * e.n_lchunks + 3) / 4;
   if (dbg_rec)
     hipLaunchKernelGGL(k_edge_samples<true>, dim3(blocks), dim3(256), 0, st, a, e);
   else

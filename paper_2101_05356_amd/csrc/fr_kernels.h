@@ -58,6 +58,7 @@ struct EdgeArgs {
   fix_t* gcam;          // [12] fixed-point
   int32_t* dbg_rec;     // [n*4]: edge, pixel, hit-, hit+
   uint8_t* dbg_flag;    // [n]
+  int lc, n_lchunks;    // lights per work item, light chunks per sample group
 };
 
 // Device buffers owned by one mesh (topology fixed at creation).
@@ -163,6 +164,9 @@ void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st, hi
 // takes longer items.
 constexpr int kLightChunkFwd = 12;
 constexpr int kLightChunkBwd = 24;
+// The boundary term has one wave per 64 edge samples and light chunk: short
+// chunks give the launch enough waves to fill the chip.
+constexpr int kLightChunkEdge = 12;
 // Partial slots of the backward light/camera gradients (reduced in a fixed order).
 constexpr int kSlots = 1024;
 // loss.hip
