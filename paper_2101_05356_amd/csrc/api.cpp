@@ -168,7 +168,7 @@ int mesh_from_topology(fr_ctx* ctx, const HostTopo& t, fr_mesh** out) {
             dalloc(&d.hist, 256 * (size_t)nb) == hipSuccess && dalloc(&d.partial, 64 * 6) == hipSuccess &&
             dalloc(&d.scene_box, 6) == hipSuccess && dalloc(&d.depth, 2) == hipSuccess &&
             dalloc(&d.edge_len, d.E) == hipSuccess && dalloc(&d.edge_cdf, d.E) == hipSuccess &&
-            dalloc(&d.face_front, F) == hipSuccess && dalloc(&d.scan_part, 1024) == hipSuccess &&
+            dalloc(&d.face_front, F) == hipSuccess && dalloc(&d.scan_part, (size_t)std::max(1, (d.E + 1023) / 1024)) == hipSuccess &&
             dalloc(&d.acc, 13 * (size_t)n_verts + 12) == hipSuccess;
   if (!ok) { fr_mesh_destroy(m); return fail(ctx, FR_ERR_OOM, "mesh allocation failed"); }
   ok = hipMemcpy(d.tris, t.tris.data(), sizeof(int32_t) * 3 * F, hipMemcpyHostToDevice) == hipSuccess &&
@@ -232,7 +232,7 @@ int fr_mesh_destroy(fr_mesh* m) {
   void* ptrs[] = {d.tris, d.vf_off, d.vf_idx, d.normals, d.nlen, d.gnorm, d.edges, d.edge_faces, d.nodes, d.recs,
                   d.order, d.node_parent, d.leaf_parent, d.flags, d.keys[0], d.keys[1], d.vals[0], d.vals[1],
                   d.hist, d.partial, d.scene_box, d.depth, d.lights, d.ltmp, d.edge_len, d.edge_cdf, d.face_front,
-                  d.scan_part, d.img_partial, d.acc, d.slots, d.nodes4, d.n4_src, m->loss_scratch, m->loss_gtmp};
+                  d.scan_part, d.img_partial, d.acc, d.slots, d.nodes4, d.n4_src, d.top_nodes, d.top_level_off, m->loss_scratch, m->loss_gtmp};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -635,9 +635,11 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   J.zero_stride = fr::cdiv(std::max(n_param, 3 * N), 256) * 256;
   J.n_param = n_param; J.off_alb = md->K_geo; J.off_pose = md->K_geo + md->K_alb; J.off_rad = n_param - 3 * L;
   J.tris = md_.tris; J.vf_off = md_.vf_off; J.vf_idx = md_.vf_idx; J.normals = md_.normals; J.nlen = md_.nlen;
+  J.top_nodes = md_.top_nodes; J.top_level_off = md_.top_level_off; J.n_top_levels = md_.n_top_levels;
   J.nodes = md_.nodes; J.nodes4 = md_.nodes4; J.n4_src = md_.n4_src; J.n4 = md_.n4; J.recs = md_.recs; J.order = md_.order; J.node_parent = md_.node_parent;
   J.leaf_parent = md_.leaf_parent; J.flags = md_.flags;
   J.edge_faces = md_.edge_faces; J.face_front = md_.face_front; J.edge_len = md_.edge_len; J.edge_cdf = md_.edge_cdf;
+  J.scan_part = md_.scan_part;
   J.smooth = d->smooth ? 1 : 0;
   const double e = 0.60653065971263342, z = (1.0 + 2.0 * e) * (1.0 + 2.0 * e);
   J.taps = fr::Taps{(float)(1.0 / z), (float)(e / z), (float)(e * e / z)};

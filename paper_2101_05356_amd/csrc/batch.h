@@ -25,7 +25,8 @@ struct JobDev {
   const int32_t* tris; const int32_t* vf_off; const int32_t* vf_idx; float* normals; float* nlen;
   BvhNode* nodes; Bvh4Node* nodes4; const int32_t* n4_src; int n4; TriRec* recs; const int32_t* order; const int32_t* node_parent; const int32_t* leaf_parent;
   uint32_t* flags;
-  const int32_t* edge_faces; uint8_t* face_front; double* edge_len; double* edge_cdf;
+  const int32_t* top_nodes; const int32_t* top_level_off; int n_top_levels;
+  const int32_t* edge_faces; uint8_t* face_front; double* edge_len; double* edge_cdf; double* scan_part;
   const float* lp0; const float* le1; const float* le2; const int32_t* lshape; LightRec* lights;
   int smooth; Taps taps;
   int t;                    // completed steps; step t + 1 renders with counter word 4 = t + 1

@@ -46,10 +46,12 @@ FR_BATCH_KERNEL(kb_pose, 256) { FR_JOB_PROLOGUE pose_block(J.v_obj, J.N, J.param
 FR_BATCH_KERNEL(kb_normals, 256) {
   FR_JOB_PROLOGUE normals_block(J.v_w, J.tris, J.vf_off, J.vf_idx, J.N, J.normals, J.nlen, lb);
 }
-FR_BATCH_KERNEL(kb_zero_flags, 256) { FR_JOB_PROLOGUE zero_u32_block(J.flags, J.F > 1 ? J.F - 1 : 1, lb); }
-FR_BATCH_KERNEL(kb_refit, 256) {
-  FR_JOB_PROLOGUE refit_block(J.v_w, J.tris, J.order, J.F, J.nodes, J.node_parent, J.leaf_parent, J.flags, J.recs,
-                              kBoxPad, lb);
+FR_BATCH_KERNEL(kb_refit, kRefitTile) {
+  FR_JOB_PROLOGUE refit_local_block(J.v_w, J.tris, J.order, J.F, J.nodes, J.node_parent, J.leaf_parent, J.recs,
+                                    kBoxPad, lb);
+}
+FR_BATCH_KERNEL(kb_refit_top, 1024) {
+  FR_JOB_PROLOGUE refit_top_block(J.nodes, J.node_parent, J.top_nodes, J.top_level_off, J.n_top_levels);
 }
 FR_BATCH_KERNEL(kb_gather4, 256) { FR_JOB_PROLOGUE gather4_block(J.nodes, J.n4_src, J.n4, J.nodes4, lb); }
 FR_BATCH_KERNEL(kb_light_setup, 256) {
@@ -111,7 +113,8 @@ FR_BATCH_KERNEL(kb_edge_len, 256) {
   FR_JOB_PROLOGUE edge_len_block(J.v_w, J.ea.edges, J.edge_faces, J.ea.E, J.face_front, J.ra.cam, J.ea.th,
                                  J.ea.aspect, J.ra.W, J.ra.H, J.edge_len, lb);
 }
-FR_BATCH_KERNEL(kb_edge_scan, 1024) { FR_JOB_PROLOGUE edge_scan_block(J.edge_len, J.ea.E, J.edge_cdf, lb); }
+FR_BATCH_KERNEL(kb_edge_scan, 256) { FR_JOB_PROLOGUE edge_scan_local_block(J.edge_len, J.ea.E, J.edge_cdf, J.scan_part, lb); }
+FR_BATCH_KERNEL(kb_edge_scan_add, 256) { FR_JOB_PROLOGUE edge_scan_add_block(J.edge_cdf, J.ea.E, J.scan_part, lb); }
 __attribute__((amdgpu_waves_per_eu(6))) FR_BATCH_KERNEL(kb_edge_samples, 256) { FR_JOB_PROLOGUE edge_samples_block<false>(J.rb, J.ea, lb); }
 FR_BATCH_KERNEL(kb_pose_bwd_v, 256) { FR_JOB_PROLOGUE pose_bwd_v_block(J.N, J.param + J.off_pose, J.g_verts, J.g_vobj, lb); }
 FR_BATCH_KERNEL(kb_pose_bwd_p, 1024) {
@@ -142,8 +145,8 @@ __global__ void kb_advance(JobDev* jobs, int njobs) {
 // Host side
 // ---------------------------------------------------------------------------
 enum Stage {
-  S_BLEND_GEO, S_BLEND_ALB, S_POSE, S_NORMALS, S_ZERO_FLAGS, S_REFIT, S_GATHER4, S_LIGHTS, S_FWD, S_SUM, S_LOSS, S_LOSS_FINAL,
-  S_SMOOTH_ADJ, S_ZERO_GRADS, S_BWD, S_SLOTS, S_NBWD_P, S_NBWD_G, S_FACE_FRONT, S_EDGE_LEN, S_EDGE_SCAN,
+  S_BLEND_GEO, S_BLEND_ALB, S_POSE, S_NORMALS, S_REFIT, S_REFIT_TOP, S_GATHER4, S_LIGHTS, S_FWD, S_SUM, S_LOSS, S_LOSS_FINAL,
+  S_SMOOTH_ADJ, S_ZERO_GRADS, S_BWD, S_SLOTS, S_NBWD_P, S_NBWD_G, S_FACE_FRONT, S_EDGE_LEN, S_EDGE_SCAN, S_EDGE_SCAN_ADD,
   S_EDGE_SAMPLES, S_FIX_FINALIZE, S_POSE_BWD_V, S_POSE_BWD_P, S_BLEND_BWD_GEO, S_BLEND_BWD_ALB, S_ADAM, S_COUNT
 };
 
@@ -153,8 +156,9 @@ static int stage_blocks(const JobDev& J, int s) {
     case S_BLEND_GEO: case S_BLEND_ALB: return cdiv(J.M, 256);
     case S_POSE: case S_NORMALS: case S_NBWD_P: case S_NBWD_G: case S_POSE_BWD_V: return cdiv(N, 256);
     case S_FIX_FINALIZE: return cdiv(3 * N, 256);
-    case S_ZERO_FLAGS: return cdiv(F > 1 ? F - 1 : 1, 256);
-    case S_REFIT: case S_FACE_FRONT: return cdiv(F, 256);
+    case S_REFIT: return cdiv(F, kRefitTile);
+    case S_REFIT_TOP: return J.n_top_levels > 0 ? 1 : 0;
+    case S_FACE_FRONT: return cdiv(F, 256);
     case S_GATHER4: return cdiv(4 * J.n4, 256);
     case S_LIGHTS: return cdiv(J.ra.L, 256);
     case S_FWD: return wave_blocks_items(J.ra);
@@ -165,7 +169,7 @@ static int stage_blocks(const JobDev& J, int s) {
     case S_BWD: return wave_blocks_items(J.rb);
     case S_SLOTS: return 12 * J.ra.L + 12;
     case S_EDGE_LEN: return J.ea.n_samples > 0 ? cdiv(J.ea.E, 256) : 0;
-    case S_EDGE_SCAN: return J.ea.n_samples > 0 ? 1 : 0;
+    case S_EDGE_SCAN: case S_EDGE_SCAN_ADD: return J.ea.n_samples > 0 ? cdiv(J.ea.E, kScanTile) : 0;
     case S_EDGE_SAMPLES: return J.ea.n_samples > 0 ? cdiv(cdiv(J.ea.n_samples, 64) * J.ea.n_lchunks, 4) : 0;
     case S_POSE_BWD_P: return 1;
     case S_BLEND_BWD_GEO: return J.K_geo;
@@ -229,8 +233,8 @@ void Batch::launch_step(hipStream_t st) {
   FR_LAUNCH(kb_blend_alb, S_BLEND_ALB, 256, 0);
   FR_LAUNCH(kb_pose, S_POSE, 256, 0);
   FR_LAUNCH(kb_normals, S_NORMALS, 256, 0);
-  FR_LAUNCH(kb_zero_flags, S_ZERO_FLAGS, 256, 0);
-  FR_LAUNCH(kb_refit, S_REFIT, 256, 0);
+  FR_LAUNCH(kb_refit, S_REFIT, kRefitTile, 0);
+  FR_LAUNCH(kb_refit_top, S_REFIT_TOP, 1024, 0);
   FR_LAUNCH(kb_gather4, S_GATHER4, 256, 0);
   FR_LAUNCH(kb_light_setup, S_LIGHTS, 256, 0);
   FR_LAUNCH(kb_render_fwd, S_FWD, 256, 0);
@@ -245,7 +249,8 @@ void Batch::launch_step(hipStream_t st) {
   FR_LAUNCH(kb_normals_bwd_gather, S_NBWD_G, 256, 0);
   FR_LAUNCH(kb_face_front, S_FACE_FRONT, 256, 0);
   FR_LAUNCH(kb_edge_len, S_EDGE_LEN, 256, 0);
-  FR_LAUNCH(kb_edge_scan, S_EDGE_SCAN, 1024, 0);
+  FR_LAUNCH(kb_edge_scan, S_EDGE_SCAN, 256, 0);
+  FR_LAUNCH(kb_edge_scan_add, S_EDGE_SCAN_ADD, 256, 0);
   FR_LAUNCH(kb_edge_samples, S_EDGE_SAMPLES, 256, 0);
   FR_LAUNCH(kb_fix_finalize, S_FIX_FINALIZE, 256, 0);
   FR_LAUNCH(kb_pose_bwd_v, S_POSE_BWD_V, 256, 0);

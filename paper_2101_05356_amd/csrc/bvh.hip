@@ -189,6 +189,8 @@ __global__ __launch_bounds__(256) void k_karras(const uint32_t* __restrict__ k, 
   const int c1 = (hi == split + 1) ? ~(split + 1) : split + 1;
   nodes[i].c0 = c0;
   nodes[i].c1 = c1;
+  nodes[i].lo = lo;       // sorted leaf range of the node (tile-local refit)
+  nodes[i].hi = hi;
   if (c0 < 0) leaf_parent[~c0] = i; else node_parent[c0] = i;
   if (c1 < 0) leaf_parent[~c1] = i; else node_parent[c1] = i;
   if (i == 0) node_parent[0] = -1;
@@ -198,19 +200,41 @@ __global__ __launch_bounds__(256) void k_karras(const uint32_t* __restrict__ k, 
 __global__ void k_single_leaf(BvhNode* __restrict__ nodes, int32_t* __restrict__ leaf_parent) {
   nodes[0].c0 = ~0;
   nodes[0].c1 = ~0;
+  nodes[0].lo = 0;
+  nodes[0].hi = 0;
   for (int k = 0; k < 3; ++k) { nodes[0].b1[k] = 3.4e38f; nodes[0].b1[3 + k] = -3.4e38f; }
   leaf_parent[0] = 0;
 }
 
 // ---------------------------------------------------------------------------
-// Refit: leaf records + bottom-up boxes.  flags[] must be zero on entry.
+// Refit: leaf records + bottom-up boxes, in two phases over the fixed
+// topology.  (1) One workgroup per tile of kRefitTile consecutive sorted
+// leaves: every leaf's thread climbs while the parent's leaf range lies in the
+// tile; the second child to arrive at a node (LDS counter) merges both child
+// boxes (kept in LDS) and climbs on.  A climb that reaches a node spanning
+// several tiles stores its box in that node and stops.  (2) One workgroup
+// finishes the spanning ("top") nodes level by level, children before
+// parents (the order is computed on the host at build time).  No device-scope
+// synchronisation.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void refit_block(const float* __restrict__ v, const int32_t* __restrict__ tris,
-                                               const int32_t* __restrict__ order, int F, BvhNode* nodes,
-                                               const int32_t* __restrict__ node_parent,
-                                               const int32_t* __restrict__ leaf_parent, uint32_t* flags,
-                                               TriRec* __restrict__ recs, float pad, int bid) {
-  const int slot = bid * 256 + threadIdx.x;
+constexpr int kRefitTile = 256;
+
+__device__ __forceinline__ void store_child_box(BvhNode* nodes, int p, int child, const float box[6]) {
+  float* dst = nodes[p].c0 == child ? nodes[p].b0 : nodes[p].b1;
+  for (int k = 0; k < 6; ++k) dst[k] = box[k];
+}
+
+__device__ __forceinline__ void refit_local_block(const float* __restrict__ v, const int32_t* __restrict__ tris,
+                                                  const int32_t* __restrict__ order, int F, BvhNode* nodes,
+                                                  const int32_t* __restrict__ node_parent,
+                                                  const int32_t* __restrict__ leaf_parent, TriRec* __restrict__ recs,
+                                                  float pad, int bid) {
+  __shared__ uint32_t flag[kRefitTile];
+  __shared__ float sbox[kRefitTile][2][6];
+  flag[threadIdx.x] = 0u;
+  __syncthreads();
+  const int t0 = bid * kRefitTile, t1 = min(F, t0 + kRefitTile) - 1;
+  const int slot = t0 + threadIdx.x;
   if (slot >= F) return;
   const int f = order[slot];
   const V3 a = ld3(v, tris[3 * f]), b = ld3(v, tris[3 * f + 1]), c = ld3(v, tris[3 * f + 2]);
@@ -222,38 +246,62 @@ __device__ __forceinline__ void refit_block(const float* __restrict__ v, const i
   float box[6] = {fminf(a.x, fminf(b.x, c.x)) - pad, fminf(a.y, fminf(b.y, c.y)) - pad,
                   fminf(a.z, fminf(b.z, c.z)) - pad, fmaxf(a.x, fmaxf(b.x, c.x)) + pad,
                   fmaxf(a.y, fmaxf(b.y, c.y)) + pad, fmaxf(a.z, fmaxf(b.z, c.z)) + pad};
-  // Child boxes live in the parent node.  The second child to arrive at a
-  // node (atomic counter) merges both; box traffic goes through device-scope
-  // atomic loads/stores so no stale cached line is read.
   int child = ~slot;
   int p = leaf_parent[slot];
   while (p >= 0) {
-    BvhNode* pn = nodes + p;
-    float* dst = (pn->c0 == child) ? pn->b0 : pn->b1;
-    for (int k = 0; k < 6; ++k) __hip_atomic_store(dst + k, box[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (F == 1) break;
-    __threadfence();
-    if (atomicAdd(&flags[p], 1u) == 0u) return;    // the sibling finishes this node
-    __threadfence();
+    store_child_box(nodes, p, child, box);
+    if (F == 1) return;
+    const int lo = nodes[p].lo, hi = nodes[p].hi;
+    if (lo < t0 || hi > t1) return;          // spanning node: finished by the top pass
+    const int q = p - t0;                    // a node's index is one end of its range
+    const int side = nodes[p].c0 == child ? 0 : 1;
+    for (int k = 0; k < 6; ++k) sbox[q][side][k] = box[k];
+    __threadfence_block();
+    if (atomicAdd(&flag[q], 1u) == 0u) return;   // the sibling finishes this node
+    __threadfence_block();
     for (int k = 0; k < 3; ++k) {
-      const float a0 = __hip_atomic_load(pn->b0 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const float a1 = __hip_atomic_load(pn->b1 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const float c0 = __hip_atomic_load(pn->b0 + 3 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const float c1 = __hip_atomic_load(pn->b1 + 3 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      box[k] = fminf(a0, a1);
-      box[3 + k] = fmaxf(c0, c1);
+      box[k] = fminf(sbox[q][0][k], sbox[q][1][k]);
+      box[3 + k] = fmaxf(sbox[q][0][3 + k], sbox[q][1][3 + k]);
     }
     child = p;
     p = node_parent[p];
   }
 }
 
-__global__ __launch_bounds__(256) void k_refit(const float* __restrict__ v, const int32_t* __restrict__ tris,
-                                               const int32_t* __restrict__ order, int F, BvhNode* nodes,
-                                               const int32_t* __restrict__ node_parent,
-                                               const int32_t* __restrict__ leaf_parent, uint32_t* flags,
-                                               TriRec* __restrict__ recs, float pad) {
-  refit_block(v, tris, order, F, nodes, node_parent, leaf_parent, flags, recs, pad, blockIdx.x);
+__global__ __launch_bounds__(kRefitTile) void k_refit_local(const float* __restrict__ v,
+                                                            const int32_t* __restrict__ tris,
+                                                            const int32_t* __restrict__ order, int F, BvhNode* nodes,
+                                                            const int32_t* __restrict__ node_parent,
+                                                            const int32_t* __restrict__ leaf_parent,
+                                                            TriRec* __restrict__ recs, float pad) {
+  refit_local_block(v, tris, order, F, nodes, node_parent, leaf_parent, recs, pad, blockIdx.x);
+}
+
+// top[]: spanning nodes, children before parents; level_off[l]..level_off[l+1]
+// is level l (nodes of a level are independent).
+__device__ __forceinline__ void refit_top_block(BvhNode* nodes, const int32_t* __restrict__ node_parent,
+                                                const int32_t* __restrict__ top, const int32_t* __restrict__ level_off,
+                                                int n_levels) {
+  for (int l = 0; l < n_levels; ++l) {
+    for (int i = level_off[l] + threadIdx.x; i < level_off[l + 1]; i += blockDim.x) {
+      const int p = top[i];
+      const int g = node_parent[p];
+      if (g < 0) continue;
+      float box[6];
+      for (int k = 0; k < 3; ++k) {
+        box[k] = fminf(nodes[p].b0[k], nodes[p].b1[k]);
+        box[3 + k] = fmaxf(nodes[p].b0[3 + k], nodes[p].b1[3 + k]);
+      }
+      store_child_box(nodes, g, p, box);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_refit_top(BvhNode* nodes, const int32_t* __restrict__ node_parent,
+                                                    const int32_t* __restrict__ top,
+                                                    const int32_t* __restrict__ level_off, int n_levels) {
+  refit_top_block(nodes, node_parent, top, level_off, n_levels);
 }
 
 // Structural check of a freshly built tree: sorted keys, child and parent
@@ -340,10 +388,11 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 
 void bvh_refit(MeshDev& m, const float* d_verts, hipStream_t st) {
   const int F = m.F;
-  const int nflags = F > 1 ? F - 1 : 1;
-  hipLaunchKernelGGL(k_zero_u32, dim3(cdiv(nflags, 256)), dim3(256), 0, st, m.flags, nflags);
-  hipLaunchKernelGGL(k_refit, dim3(cdiv(F, 256)), dim3(256), 0, st, d_verts, m.tris, m.order, F, m.nodes,
-                     m.node_parent, m.leaf_parent, m.flags, m.recs, kBoxPad);
+  hipLaunchKernelGGL(k_refit_local, dim3(cdiv(F, kRefitTile)), dim3(kRefitTile), 0, st, d_verts, m.tris, m.order, F,
+                     m.nodes, m.node_parent, m.leaf_parent, m.recs, kBoxPad);
+  if (m.n_top_levels > 0)
+    hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(1024), 0, st, m.nodes, m.node_parent, m.top_nodes,
+                       m.top_level_off, m.n_top_levels);
   if (m.n4 > 0)
     hipLaunchKernelGGL(k_gather4, dim3(cdiv(4 * m.n4, 256)), dim3(256), 0, st, m.nodes, m.n4_src, m.n4, m.nodes4);
 }
@@ -386,6 +435,57 @@ static int bvh_collapse(MeshDev& m, hipStream_t st) {
     const int n = slots(b, ref, src);
     for (int k = n - 1; k >= 0; --k)
       if (ref[k] >= 0) { todo.push_back(ref[k]); tdepth.push_back(d + 1); }
+  }
+  // spanning nodes of the tile-local refit, by height (children first)
+  {
+    std::vector<int> height((size_t)F - 1, 0);   // longest path to a leaf, by a post-order walk
+    std::vector<int> post;
+    post.reserve((size_t)F - 1);
+    std::vector<std::pair<int, int>> st2 = {{0, 0}};
+    while (!st2.empty()) {
+      auto& top = st2.back();
+      const int b = top.first;
+      if (top.second < 2) {
+        const int c = child(b, top.second++);
+        if (c >= 0) st2.push_back({c, 0});
+      } else {
+        int h = 0;
+        for (int q = 0; q < 2; ++q) { const int c = child(b, q); if (c >= 0) h = std::max(h, height[c] + 1); }
+        height[b] = h;
+        post.push_back(b);
+        st2.pop_back();
+      }
+    }
+    std::vector<std::vector<int>> levels;
+    for (int b : post) {
+      if (bn[b].lo / kRefitTile == bn[b].hi / kRefitTile) continue;   // tile-local
+      const int h = height[b];   // a spanning child has a smaller height: an earlier level
+      if ((int)levels.size() <= h) levels.resize(h + 1);
+      levels[h].push_back(b);
+    }
+    std::vector<int32_t> top, off = {0};
+    for (auto& lv : levels) {
+      if (lv.empty()) continue;
+      top.insert(top.end(), lv.begin(), lv.end());
+      off.push_back((int32_t)top.size());
+    }
+    const int nt = (int)top.size();
+    if (nt > m.top_cap) {
+      if (m.top_nodes) (void)hipFree(m.top_nodes);
+      if (m.top_level_off) (void)hipFree(m.top_level_off);
+      m.top_nodes = nullptr; m.top_level_off = nullptr; m.top_cap = 0;
+      if (hipMalloc(&m.top_nodes, sizeof(int32_t) * std::max(nt, 1)) != hipSuccess) return FR_ERR_OOM;
+      if (hipMalloc(&m.top_level_off, sizeof(int32_t) * (std::max(nt, 1) + 1)) != hipSuccess) return FR_ERR_OOM;
+      m.top_cap = nt;
+    }
+    if (nt > 0 &&
+        (hipMemcpyAsync(m.top_nodes, top.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice, st) != hipSuccess ||
+         hipMemcpyAsync(m.top_level_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, st) !=
+             hipSuccess ||
+         hipStreamSynchronize(st) != hipSuccess))
+      return FR_ERR_DEVICE;
+    m.n_top = nt;
+    m.n_top_levels = (int)off.size() - 1;
   }
   const int n4 = (int)order.size();
   std::vector<Bvh4Node> h4((size_t)n4);

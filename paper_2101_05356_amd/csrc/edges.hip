@@ -79,25 +79,67 @@ __global__ __launch_bounds__(256) void k_edge_len(const float* __restrict__ v, c
 }
 
 // Inclusive FP64 scan in fixed order: per-thread serial runs + block scan.
-__device__ __forceinline__ void edge_scan_block(const double* __restrict__ len, int E, double* __restrict__ cdf, int bid) {
-  __shared__ double part[1024];
-  const int per = (E + 1023) / 1024;
-  const int b = threadIdx.x * per;
-  double s = 0.0;
-  for (int i = 0; i < per; ++i) if (b + i < E) s += len[b + i];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double run = 0.0;
-    for (int i = 0; i < 1024; ++i) { const double x = part[i]; part[i] = run; run += x; }
+// Inclusive running sum of the edge lengths (the sampling CDF) in two
+// passes over tiles of 1024 edges: (1) each tile scans its edges (4 per
+// thread, then a wave scan and the wave totals) and stores its total;
+// (2) each tile adds the sum of the totals before it.  Fixed summation order.
+constexpr int kScanTile = 1024;
+
+__device__ __forceinline__ double wave_scan_incl(double x, int lane) {
+  for (int off = 1; off < 64; off <<= 1) {
+    const double y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
   }
-  __syncthreads();
-  double run = part[threadIdx.x];
-  for (int i = 0; i < per; ++i) if (b + i < E) { run += len[b + i]; cdf[b + i] = run; }
+  return x;
 }
 
-__global__ __launch_bounds__(1024) void k_edge_scan(const double* __restrict__ len, int E, double* __restrict__ cdf) {
-  edge_scan_block(len, E, cdf, blockIdx.x);
+__device__ __forceinline__ void edge_scan_local_block(const double* __restrict__ len, int E, double* __restrict__ cdf,
+                                                      double* __restrict__ part, int bid) {
+  __shared__ double wsum[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int base = bid * kScanTile + 4 * threadIdx.x;
+  double v[4], run = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    run += base + k < E ? len[base + k] : 0.0;
+    v[k] = run;
+  }
+  const double incl = wave_scan_incl(run, lane);
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  double pre = 0.0;
+  for (int w = 0; w < wave; ++w) pre += wsum[w];
+  const double excl = pre + (incl - run);
+  for (int k = 0; k < 4; ++k)
+    if (base + k < E) cdf[base + k] = excl + v[k];
+  if (threadIdx.x == 255) part[bid] = pre + incl;
+}
+
+__device__ __forceinline__ void edge_scan_add_block(double* __restrict__ cdf, int E, const double* __restrict__ part,
+                                                    int bid) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < bid; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double off = red[0];
+  if (bid == 0) return;
+  const int base = bid * kScanTile + 4 * threadIdx.x;
+  for (int k = 0; k < 4; ++k)
+    if (base + k < E) cdf[base + k] += off;
+}
+
+__global__ __launch_bounds__(256) void k_edge_scan_local(const double* __restrict__ len, int E,
+                                                         double* __restrict__ cdf, double* __restrict__ part) {
+  edge_scan_local_block(len, E, cdf, part, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_edge_scan_add(double* __restrict__ cdf, int E,
+                                                       const double* __restrict__ part) {
+  edge_scan_add_block(cdf, E, part, blockIdx.x);
 }
 
 // Shaded radiance (no 1/S) of the camera ray through film point (fx, fy).
@@ -252,7 +294,9 @@ void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samp
   const double aspect = (double)a.W / (double)a.H;
   hipLaunchKernelGGL(k_edge_len, dim3((m.E + 255) / 256), dim3(256), 0, st, a.verts, m.edges, m.edge_faces, m.E,
                      m.face_front, a.cam, tan_half, aspect, a.W, a.H, m.edge_len);
-  hipLaunchKernelGGL(k_edge_scan, dim3(1), dim3(1024), 0, st, m.edge_len, m.E, m.edge_cdf);
+  const int tiles = cdiv(m.E, kScanTile);
+  hipLaunchKernelGGL(k_edge_scan_local, dim3(tiles), dim3(256), 0, st, m.edge_len, m.E, m.edge_cdf, m.scan_part);
+  hipLaunchKernelGGL(k_edge_scan_add, dim3(tiles), dim3(256), 0, st, m.edge_cdf, m.E, m.scan_part);
   EdgeArgs e;
   e.edges = m.edges; e.cdf = m.edge_cdf; e.E = m.E; e.n_samples = n_samples;
   e.th = tan_half; e.aspect = aspect; e.dEdp = dEdp; e.gverts = gverts; e.gcam = gcam;

@@ -51,7 +51,7 @@ struct alignas(16) BvhNode {
   float b0[6];     // child 0 box: min xyz, max xyz
   float b1[6];     // child 1 box
   int32_t c0, c1;  // >= 0: internal node index; < 0: ~leaf slot
-  int32_t pad0, pad1;
+  int32_t lo, hi;  // range of sorted leaf slots below the node
 };
 static_assert(sizeof(BvhNode) == 64, "node must be one 64-byte line");
 

@@ -84,6 +84,10 @@ struct MeshDev {
   Bvh4Node* nodes4 = nullptr;       // [n4]
   int32_t* n4_src = nullptr;        // [n4*4]: binary parent * 2 + side holding each child box, -1 unused
   int n4 = 0, n4_cap = 0, depth4 = 0;
+  // refit: nodes spanning several leaf tiles, by level (children first)
+  int32_t* top_nodes = nullptr;     // [n_top]
+  int32_t* top_level_off = nullptr; // [n_top_levels + 1]
+  int n_top = 0, n_top_levels = 0, top_cap = 0;
   TriRec* recs = nullptr;           // [F]
   int32_t* order = nullptr;         // [F] sorted slot -> triangle id
   int32_t* node_parent = nullptr;   // [max(F-1,1)]
@@ -102,7 +106,7 @@ struct MeshDev {
   double* edge_len = nullptr;       // [E] film length of silhouette edges (0 otherwise)
   double* edge_cdf = nullptr;       // [E] inclusive running sum
   uint8_t* face_front = nullptr;    // [F]
-  double* scan_part = nullptr;      // [1024]
+  double* scan_part = nullptr;      // [ceil(E/1024)] tile totals of the edge CDF scan
   float* img_partial = nullptr;     // per-light-chunk partial images
   size_t img_partial_cap = 0;
   int bvh_depth = -1;
