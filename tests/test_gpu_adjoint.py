@@ -1,0 +1,125 @@
+"""Adjoint of the whole batched optimisation step against the FP64 oracle, on
+a face: the gradient the batch computes for the step's loss (morphable blend,
+pose, normals, render, smoothing, L1 loss; interior term) equals
+
+  (1) the oracle's own gradient (forward-mode dual numbers through its render,
+      composed with its pose and blend adjoints) to 1e-4 relative, on every
+      parameter, and
+  (2) central finite differences of the oracle's loss (h = 1e-3, decisions
+      frozen at the oracle's base render) on 64 random parameters, to the
+      accuracy such differences have here.
+
+The target is a constant far above every pixel, so the L1 loss is the linear
+function sum(100 - smooth(p)), free of kinks; the GPU's own hit and
+visibility decisions are first checked equal to the oracle's on every sample.
+
+Accuracy of (2): the oracle takes FP32 scene arrays, so each evaluation rounds
+the blended vertices, albedos and radiances to FP32; that noise, divided by
+h, is bounded from the oracle's own input gradients and added to the
+tolerance, with 2e-3 relative for the O(h^2) truncation.  A difference whose
+value at h and h/2 disagree beyond that tolerance has not converged (a
+frozen camera ray near a triangle edge leaves its triangle and is shaded with
+extrapolated barycentrics) and is reported and skipped; at most 4 of the 64
+may be.
+"""
+import numpy as np
+import pytest
+
+from paper_2101_05356_amd import scenes
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+W, SPP, L, H_FD, SEED = 24, 2, 6, 1e-3, 77
+
+
+def oracle_scene(model, params, K_geo, K_alb, lights, cam, seed, step):
+    import oracle
+    sl = np.cumsum([0, K_geo, K_alb, 6])
+    basis_geo = np.concatenate([model.basis_id, model.basis_exp]).astype(np.float64)
+    v_obj = oracle.blend(model.mean_shape, basis_geo, params[sl[0]:sl[1]]).reshape(-1, 3)
+    v_w = oracle.pose_apply(v_obj, params[sl[2]:sl[3]])
+    diffuse = oracle.blend(model.mean_albedo, model.basis_alb, params[sl[1]:sl[2]]).reshape(-1, 3)
+    lt = scenes.Lights(lights.p0, lights.e1, lights.e2, params[sl[3]:].reshape(-1, 3), lights.shape)
+    return scenes.Scene(verts=v_w, tris=model.tris, diffuse=diffuse, specular=model.specular,
+                        roughness=model.roughness, lights=lt, camera=cam, spp=SPP, seed=seed, step=step)
+
+
+def test_batched_step_gradient_matches_oracle_gradient_and_differences(oracle_lib):
+    import oracle
+    from paper_2101_05356_amd import recon
+    from paper_2101_05356_amd import render as R
+    ctx = R.Context(0)
+    model = scenes.synthetic_morph_model(seed=5, n_lon=24, n_ring=16, K_s=16, K_e=12, K_r=16)
+    mt = recon.ModelTensors.from_model(model)
+    job, _ = recon.face_job(mt, np.random.default_rng(SEED), ctx, W=W, spp=SPP, n_lights=L, seed=SEED,
+                            edge_samples=0, hist_cap=4)
+    job.target = torch.full((W, W, 3), 100.0, dtype=torch.float32, device="cuda")
+    p0 = job.params.cpu().numpy().astype(np.float64)
+    K_geo, K_alb = mt.K_geo, mt.K_alb
+
+    # GPU: one batched step (its Philox step counter is 1)
+    b = recon.Batch(recon.Model(ctx, mt))
+    jid = b.add(job)
+    b.step(1, graph=True)
+    torch.cuda.synchronize()
+    g_gpu = b.read(jid)["grad"].astype(np.float64)
+
+    # the GPU's decisions at the same parameters and counters
+    rc = recon.Reconstruction(ctx, mt, job)
+    rc.t = 1
+    _, hit_g, _, vis_g = R.render_forward(rc.mesh, rc.scene(), verts=rc.v_w, dump=True)
+    hit_g = hit_g.cpu().numpy()
+    vis_g = (vis_g.cpu().numpy() & 0x7F)
+
+    # oracle: base decisions, then frozen-decision central differences
+    base = oracle.render(oracle_scene(model, p0, K_geo, K_alb, job.lights, job.camera, SEED, 1))
+    assert np.array_equal(base["hit"], hit_g), "camera-ray decisions differ from the oracle's"
+    assert np.array_equal(base["vis"], vis_g), "shadow decisions differ from the oracle's"
+
+    sl = recon.param_slices(K_geo, K_alb, L)
+    sc0 = oracle_scene(model, p0, K_geo, K_alb, job.lights, job.camera, SEED, 1)
+
+    # (1) the oracle's analytic gradient of -sum(smooth(p)), composed to the parameters
+    dEdp = oracle.smooth_adjoint(-np.ones((W, W, 3))).reshape(-1, 3)
+    g = oracle.grad(sc0, base["hit"], base["vis"], dEdp)
+    basis_geo = np.concatenate([model.basis_id, model.basis_exp]).astype(np.float64)
+    v_obj = oracle.blend(model.mean_shape, basis_geo, p0[sl["geo"]]).reshape(-1, 3)
+    gv_obj, gpose = oracle.pose_vjp(v_obj, p0[sl["pose"]], g["verts"])
+    ga = np.zeros_like(p0)
+    ga[sl["geo"]] = oracle.blend_vjp(basis_geo, gv_obj.reshape(-1))
+    ga[sl["alb"]] = oracle.blend_vjp(model.basis_alb.astype(np.float64), g["diffuse"].reshape(-1))
+    ga[sl["pose"]] = gpose
+    ga[sl["rad"]] = g["rad"].reshape(-1)
+    rel_l2 = np.linalg.norm(g_gpu - ga) / np.linalg.norm(ga)
+    worst = np.max(np.abs(g_gpu - ga) / (np.abs(ga) + 1e-3 * np.abs(ga).max()))
+    assert rel_l2 < 1e-4 and worst < 1e-3, (rel_l2, worst)
+
+    # (2) finite differences of the oracle's loss
+    def loss(p):
+        r = oracle.render(oracle_scene(model, p, K_geo, K_alb, job.lights, job.camera, SEED, 1),
+                          force_hit=base["hit"], force_vis=base["vis"])
+        return -float(np.sum(oracle.smooth(r["rgb"].reshape(W, W, 3))))   # loss minus its constant
+
+    def fd(i, h):
+        e = np.zeros_like(p0)
+        e[i] = h
+        return (loss(p0 + e) - loss(p0 - e)) / (2.0 * h)
+
+    # FP32 rounding of the oracle's inputs: |dE| <= sum |dE/dx| ulp(x) / 2 per evaluation
+    sp = lambda x: np.spacing(np.abs(np.asarray(x, np.float32))).astype(np.float64)
+    noise = (np.sum(np.abs(g["verts"]) * sp(sc0.verts)) + np.sum(np.abs(g["diffuse"]) * sp(sc0.diffuse)) +
+             np.sum(np.abs(g["rad"]) * sp(sc0.lights.rad)))
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(p0.size, size=min(64, p0.size), replace=False))
+    skipped, bad = [], []
+    for i in idx:
+        tol = lambda h: noise / h + 2e-3 * abs(ga[i]) + 1e-4 * np.abs(ga).max()
+        f1, f2 = fd(i, H_FD), fd(i, H_FD / 2)
+        if abs(f1 - f2) > tol(H_FD / 2):
+            skipped.append((int(i), f1, f2))
+            continue
+        if abs(f1 - ga[i]) > tol(H_FD):
+            bad.append((int(i), f1, float(ga[i]), tol(H_FD)))
+    assert len(skipped) <= 4, skipped
+    assert not bad, bad
