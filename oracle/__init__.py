@@ -56,6 +56,8 @@ class OrScene(ctypes.Structure):
         ("fov_y", ctypes.c_float), ("brdf_variant", ctypes.c_int32), ("components", ctypes.c_int32),
         ("pad_", ctypes.c_int32), ("seed", ctypes.c_uint64), ("step", ctypes.c_uint32),
         ("pad2_", ctypes.c_uint32),
+        ("uv", ctypes.c_void_p), ("tex_c", ctypes.c_void_p), ("tex_s", ctypes.c_void_p), ("tex_r", ctypes.c_void_p),
+        ("tex_size", ctypes.c_int32), ("pad3_", ctypes.c_int32),
     ]
 
 
@@ -73,7 +75,7 @@ def lib():
         L.oracle_vertex_normals.argtypes = [P, P]
         L.oracle_normals_vjp.argtypes = [P, P, P]
         L.oracle_render.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, ctypes.c_int32]
-        L.oracle_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int32]
+        L.oracle_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int32]
         L.oracle_edge_grad.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_int32]
         L.oracle_edge_count.argtypes = [P]
         L.oracle_edge_count.restype = ctypes.c_int32
@@ -116,6 +118,14 @@ class _Bound:
         s.fov_y = scene.camera.fov_y
         s.brdf_variant, s.components = int(brdf_variant), int(components)
         s.seed, s.step = int(scene.seed), int(scene.step)
+        if getattr(scene, "tex_diffuse", None) is not None:
+            M = int(scene.tex_diffuse.shape[0])
+            tex = [f32(scene.uv).reshape(-1), f32(scene.tex_diffuse).reshape(-1), f32(scene.tex_specular).reshape(-1),
+                   f32(scene.tex_roughness).reshape(-1)]
+            assert tex[0].size == 6 * scene.n_tris and tex[1].size == 3 * M * M and tex[3].size == M * M
+            self.keep += tex
+            s.uv, s.tex_c, s.tex_s, s.tex_r = [a.ctypes.data for a in tex]
+            s.tex_size = M
         self.s = s
 
     @property
@@ -186,7 +196,8 @@ def grad(scene, hit, vis, dEdp, pixels=None, brdf_variant=0, components=3, nthre
     Returns dict of FP64 arrays: verts [N,3] (total, including the path through
     the vertex normals unless include_normals_path is False), normals [N,3],
     diffuse [N,3], specular [N,3], rough [N], light [L,9] (p0,e1,e2), rad [L,3],
-    cam [12] (R row-major, T)."""
+    cam [12] (R row-major, T); with reflectance maps also tex_diffuse [M,M,3],
+    tex_specular [M,M,3], tex_rough [M,M] (and zero per-vertex reflectance)."""
     b = _Bound(scene, brdf_variant, components)
     N, L = scene.n_verts, scene.lights.count
     pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int32)
@@ -195,11 +206,15 @@ def grad(scene, hit, vis, dEdp, pixels=None, brdf_variant=0, components=3, nthre
     out = dict(verts=np.zeros((N, 3)), normals=np.zeros((N, 3)), diffuse=np.zeros((N, 3)),
                specular=np.zeros((N, 3)), rough=np.zeros(N), light=np.zeros((L, 9)),
                rad=np.zeros((L, 3)), cam=np.zeros(12))
+    M = b.s.tex_size
+    if M > 0:
+        out.update(tex_diffuse=np.zeros((M, M, 3)), tex_specular=np.zeros((M, M, 3)), tex_rough=np.zeros((M, M)))
     h = np.ascontiguousarray(hit, dtype=np.int32)
     v = np.ascontiguousarray(vis, dtype=np.uint8)
     lib().oracle_grad(b.ref, n, _ptr(pix), _ptr(h), _ptr(v), _ptr(g), _ptr(out["verts"]),
                       _ptr(out["normals"]), _ptr(out["diffuse"]), _ptr(out["specular"]), _ptr(out["rough"]),
-                      _ptr(out["light"]), _ptr(out["rad"]), _ptr(out["cam"]), nthreads or default_threads())
+                      _ptr(out["light"]), _ptr(out["rad"]), _ptr(out["cam"]), _ptr(out.get("tex_diffuse")),
+                      _ptr(out.get("tex_specular")), _ptr(out.get("tex_rough")), nthreads or default_threads())
     if include_normals_path:
         out["verts"] = out["verts"] + normals_vjp(scene, out["normals"])
     return out

@@ -59,6 +59,14 @@ struct OrScene {
   uint64_t seed;
   uint32_t step;
   uint32_t pad2_;
+  // reflectance maps (tex_size > 0): per-corner texture coordinates and
+  // M x M maps, read at the interpolated coordinates of the shading point
+  const float* uv;         // [F*3*2] (u, v) of each triangle corner
+  const float* tex_c;      // [M*M*3] diffuse
+  const float* tex_s;      // [M*M*3] specular
+  const float* tex_r;      // [M*M] roughness
+  int32_t tex_size;        // M (0: per-vertex reflectance)
+  int32_t pad3_;
 };
 
 }  // extern "C"
@@ -347,7 +355,34 @@ struct SampleParams {     // what one camera sample depends on
   S r[3];
   S R[9];
   Vec3<S> T;
+  // reflectance maps (M > 0): corner coordinates, the maps, and offsets added
+  // to the looked-up values (zero; seeded to differentiate w.r.t. the texels)
+  double uv[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  const float* tc = nullptr;
+  const float* ts = nullptr;
+  const float* tr = nullptr;
+  int M = 0;
+  Vec3<S> dc{S(0.0), S(0.0), S(0.0)}, ds{S(0.0), S(0.0), S(0.0)};
+  S dr = S(0.0);
 };
+
+// Bilinear footprint of texture coordinates (u, v) on an M x M map: texel
+// (i, j) is centred at ((i + 1/2) / M, (j + 1/2) / M) and stored at j M + i;
+// addressing clamps to the border texels.  Returns the four texel indices and
+// weights (a weight may repeat a clamped index).
+template <class S>
+void tex_footprint(const S& u, const S& v, int M, int idx[4], S w[4]) {
+  const S x = u * double(M) - 0.5, y = v * double(M) - 0.5;
+  const double x0 = std::floor(val(x)), y0 = std::floor(val(y));
+  const S fx = x - x0, fy = y - y0;
+  auto cl = [M](double t) { return (int)std::min(std::max(t, 0.0), (double)(M - 1)); };
+  const int i0 = cl(x0), i1 = cl(x0 + 1.0), j0 = cl(y0), j1 = cl(y0 + 1.0);
+  idx[0] = j0 * M + i0; idx[1] = j0 * M + i1; idx[2] = j1 * M + i0; idx[3] = j1 * M + i1;
+  w[0] = (S(1.0) - fx) * (S(1.0) - fy);
+  w[1] = fx * (S(1.0) - fy);
+  w[2] = (S(1.0) - fx) * fy;
+  w[3] = fx * fy;
+}
 
 template <class S>
 struct LightParams { Vec3<S> p0, e1, e2, rad; int shape; };
@@ -376,13 +411,45 @@ Frame<S> shading_frame(const SampleParams<S>& p, const CamConst& cc, double fx, 
   f.x = p.v[0] * b0 + p.v[1] * b1 + p.v[2] * b2;
   f.ns = normalize(p.n[0] * b0 + p.n[1] * b1 + p.n[2] * b2);
   f.wo = Vec3<S>(-d.x, -d.y, -d.z);
-  f.c = p.c[0] * b0 + p.c[1] * b1 + p.c[2] * b2;
-  f.s = p.s[0] * b0 + p.s[1] * b1 + p.s[2] * b2;
-  S r = p.r[0] * b0 + p.r[1] * b1 + p.r[2] * b2;
+  S r;
+  if (p.M > 0) {
+    // reflectance maps read at the interpolated corner coordinates
+    const S u = b0 * p.uv[0][0] + b1 * p.uv[1][0] + b2 * p.uv[2][0];
+    const S v = b0 * p.uv[0][1] + b1 * p.uv[1][1] + b2 * p.uv[2][1];
+    int idx[4];
+    S w[4];
+    tex_footprint(u, v, p.M, idx, w);
+    f.c = p.dc;
+    f.s = p.ds;
+    r = p.dr;
+    for (int q = 0; q < 4; ++q) {
+      const int t = idx[q];
+      f.c = f.c + Vec3<S>(w[q] * (double)p.tc[3 * t], w[q] * (double)p.tc[3 * t + 1], w[q] * (double)p.tc[3 * t + 2]);
+      f.s = f.s + Vec3<S>(w[q] * (double)p.ts[3 * t], w[q] * (double)p.ts[3 * t + 1], w[q] * (double)p.ts[3 * t + 2]);
+      r = r + w[q] * (double)p.tr[t];
+    }
+  } else {
+    f.c = p.c[0] * b0 + p.c[1] * b1 + p.c[2] * b2;
+    f.s = p.s[0] * b0 + p.s[1] * b1 + p.s[2] * b2;
+    r = p.r[0] * b0 + p.r[1] * b1 + p.r[2] * b2;
+  }
   if (val(r) < kRoughMin) r = S(kRoughMin);      // clamp: the gradient passes only inside
   if (val(r) > kRoughMax) r = S(kRoughMax);
   f.r = r;
   return f;
+}
+
+// Barycentrics of the camera sample through (fx, fy) on the triangle of `p`
+// (the same solve as in shading_frame, values only).
+void bary_of(const SampleParams<double>& p, const CamConst& cc, double fx, double fy, double b[3]) {
+  const V3 d = normalize(mul3(p.R, film_dir(cc, fx, fy)));
+  const V3 e1 = p.v[1] - p.v[0], e2 = p.v[2] - p.v[0];
+  const V3 pv = cross(d, e2);
+  const double det = dot(e1, pv);
+  const V3 sv = p.T - p.v[0];
+  b[1] = dot(sv, pv) / det;
+  b[2] = dot(d, cross(sv, e1)) / det;
+  b[0] = 1.0 - b[1] - b[2];
 }
 
 // Walter et al.'s rational approximation of the Smith G1 for a Beckmann-like
@@ -484,6 +551,11 @@ SampleParams<double> sample_params_d(const Prepared& P, int tri) {
   }
   for (int i = 0; i < 9; ++i) sp.R[i] = P.R[i];
   sp.T = P.T;
+  if (sc.tex_size > 0) {
+    for (int k = 0; k < 3; ++k)
+      for (int a = 0; a < 2; ++a) sp.uv[k][a] = sc.uv[6 * tri + 2 * k + a];
+    sp.tc = sc.tex_c; sp.ts = sc.tex_s; sp.tr = sc.tex_r; sp.M = sc.tex_size;
+  }
   return sp;
 }
 
@@ -645,16 +717,19 @@ int oracle_render(const OrScene* sc, int32_t n_pix, const int32_t* pix, const in
 //   g_cam [12] (R row-major, then T).
 int oracle_grad(const OrScene* sc, int32_t n_pix, const int32_t* pix, const int32_t* hit, const uint8_t* vis,
                 const double* dEdp, double* g_verts, double* g_normals, double* g_diffuse, double* g_specular,
-                double* g_rough, double* g_light, double* g_rad, double* g_cam, int32_t nthreads) {
+                double* g_rough, double* g_light, double* g_rad, double* g_cam, double* g_tex_c, double* g_tex_s,
+                double* g_tex_r, int32_t nthreads) {
   const Prepared P = prepare(sc);
   const int S = sc->spp, L = sc->n_lights, W = sc->width, N = sc->n_verts;
   if (!pix) n_pix = sc->width * sc->height;
   nthreads = std::max(1, std::min<int>(nthreads, n_pix));
-  struct Acc { std::vector<double> v, n, c, s, r, l, rad, cam; };
+  const int M = sc->tex_size, MM = M > 0 ? M * M : 0;
+  struct Acc { std::vector<double> v, n, c, s, r, l, rad, cam, tc, ts, tr; };
   std::vector<Acc> accs(nthreads);
   for (auto& a : accs) {
     a.v.assign(3 * N, 0); a.n.assign(3 * N, 0); a.c.assign(3 * N, 0); a.s.assign(3 * N, 0);
     a.r.assign(N, 0); a.l.assign(9 * L, 0); a.rad.assign(3 * L, 0); a.cam.assign(12, 0);
+    a.tc.assign(3 * (size_t)MM, 0); a.ts.assign(3 * (size_t)MM, 0); a.tr.assign(MM, 0);
   }
   parallel_for(n_pix, nthreads, [&](int ip, int tid) {
     Acc& A = accs[tid];
@@ -679,6 +754,23 @@ int oracle_grad(const OrScene* sc, int32_t n_pix, const int32_t* pix, const int3
       }
       for (int i = 0; i < 9; ++i) sp.R[i] = D63::seed(P.R[i], SLOT_CR + i);
       sp.T = seed3(P.T, SLOT_CT);
+      int tidx[4] = {0, 0, 0, 0};
+      double tw[4] = {0, 0, 0, 0};
+      if (M > 0) {
+        // with maps, the reflectance slots hold the offsets of the looked-up values
+        for (int k = 0; k < 3; ++k)
+          for (int a = 0; a < 2; ++a) sp.uv[k][a] = spd.uv[k][a];
+        sp.tc = spd.tc; sp.ts = spd.ts; sp.tr = spd.tr; sp.M = M;
+        sp.dc = seed3(V3(0.0, 0.0, 0.0), SLOT_C);
+        sp.ds = seed3(V3(0.0, 0.0, 0.0), SLOT_S);
+        sp.dr = D63::seed(0.0, SLOT_R);
+        // footprint at the (value of the) shading point, for the texel scatter
+        double b[3];
+        bary_of(spd, P.cc, fx, fy, b);
+        const double u = b[0] * spd.uv[0][0] + b[1] * spd.uv[1][0] + b[2] * spd.uv[2][0];
+        const double v = b[0] * spd.uv[0][1] + b[1] * spd.uv[1][1] + b[2] * spd.uv[2][1];
+        tex_footprint(u, v, M, tidx, tw);
+      }
       const Frame<D63> fr = shading_frame(sp, P.cc, fx, fy);
       int vid[3];
       for (int k = 0; k < 3; ++k) vid[k] = sc->tris[3 * tri + k];
@@ -698,10 +790,24 @@ int oracle_grad(const OrScene* sc, int32_t n_pix, const int32_t* pix, const int3
           for (int a = 0; a < 3; ++a) {
             A.v[3 * vid[k] + a] += gs[SLOT_V + 3 * k + a];
             A.n[3 * vid[k] + a] += gs[SLOT_N + 3 * k + a];
-            A.c[3 * vid[k] + a] += gs[SLOT_C + 3 * k + a];
-            A.s[3 * vid[k] + a] += gs[SLOT_S + 3 * k + a];
           }
-        for (int k = 0; k < 3; ++k) A.r[vid[k]] += gs[SLOT_R + k];
+        if (M > 0) {
+          for (int q = 0; q < 4; ++q) {
+            const size_t t = (size_t)tidx[q];
+            for (int a = 0; a < 3; ++a) {
+              A.tc[3 * t + a] += tw[q] * gs[SLOT_C + a];
+              A.ts[3 * t + a] += tw[q] * gs[SLOT_S + a];
+            }
+            A.tr[t] += tw[q] * gs[SLOT_R];
+          }
+        } else {
+          for (int k = 0; k < 3; ++k)
+            for (int a = 0; a < 3; ++a) {
+              A.c[3 * vid[k] + a] += gs[SLOT_C + 3 * k + a];
+              A.s[3 * vid[k] + a] += gs[SLOT_S + 3 * k + a];
+            }
+          for (int k = 0; k < 3; ++k) A.r[vid[k]] += gs[SLOT_R + k];
+        }
         for (int a = 0; a < 9; ++a) A.l[9 * j + a] += gs[SLOT_LP0 + a];
         for (int a = 0; a < 3; ++a) A.rad[3 * j + a] += gs[SLOT_LRAD + a];
         for (int a = 0; a < 12; ++a) A.cam[a] += gs[SLOT_CR + a];
@@ -712,6 +818,7 @@ int oracle_grad(const OrScene* sc, int32_t n_pix, const int32_t* pix, const int3
   for (const Acc& a : accs) {
     add(g_verts, a.v); add(g_normals, a.n); add(g_diffuse, a.c); add(g_specular, a.s);
     add(g_rough, a.r); add(g_light, a.l); add(g_rad, a.rad); add(g_cam, a.cam);
+    add(g_tex_c, a.tc); add(g_tex_s, a.ts); add(g_tex_r, a.tr);
   }
   return 0;
 }

@@ -65,6 +65,15 @@ class Scene:
     seed: int               # 64-bit key of the counter-based generator
     step: int = 0
     target: np.ndarray | None = None  # [H,W,3]
+    # reflectance maps (replace the per-vertex reflectance when given)
+    uv: np.ndarray | None = None            # [F,3,2] texture coordinates of each triangle corner
+    tex_diffuse: np.ndarray | None = None   # [M,M,3]
+    tex_specular: np.ndarray | None = None  # [M,M,3]
+    tex_roughness: np.ndarray | None = None # [M,M]
+
+    @property
+    def tex_size(self) -> int:
+        return 0 if self.tex_diffuse is None else int(self.tex_diffuse.shape[0])
 
     @property
     def n_verts(self) -> int:
@@ -305,6 +314,62 @@ def patch_scene(W: int = 64, H: int = 64, spp: int = 4, n_lights: int = 8,
     return Scene(verts=verts, tris=tris, diffuse=diffuse, specular=specular,
                  roughness=rough, lights=lights, camera=cam, spp=spp,
                  seed=render_seed, step=step)
+
+
+def smooth_random_map(rng: np.random.Generator, M: int, channels: int, lo: float, hi: float) -> np.ndarray:
+    """An M x M map of smooth random fields in [lo, hi] (sum of random
+    cosines per channel), texel (i, j) at ((i + 1/2)/M, (j + 1/2)/M)."""
+    c = (np.arange(M) + 0.5) / M
+    V, U = np.meshgrid(c, c, indexing="ij")          # [j, i]
+    out = np.zeros((M, M, channels))
+    for ch in range(channels):
+        acc = np.zeros((M, M))
+        for _ in range(5):
+            fu, fv = rng.uniform(0.5, 6.0, 2)
+            ph = rng.uniform(0, 2 * math.pi)
+            acc += np.cos(2 * math.pi * (fu * U + fv * V) + ph)
+        acc = (acc - acc.min()) / max(acc.max() - acc.min(), 1e-12)
+        out[:, :, ch] = lo + (hi - lo) * acc
+    return _f32(out if channels > 1 else out[:, :, 0])
+
+
+def with_maps(scene: Scene, uv_corner: np.ndarray, M: int, seed: int = 9) -> Scene:
+    """Copy of a scene whose reflectance comes from M x M maps (diffuse
+    U(0.3, 0.8), specular U(0.1, 0.5), roughness U(0.2, 0.6) ranges, smooth
+    random fields) read at the interpolated per-corner coordinates."""
+    rng = np.random.default_rng(seed)
+    return dataclasses.replace(scene, uv=_f32(uv_corner), tex_diffuse=smooth_random_map(rng, M, 3, 0.3, 0.8),
+                               tex_specular=smooth_random_map(rng, M, 3, 0.1, 0.5),
+                               tex_roughness=smooth_random_map(rng, M, 1, 0.2, 0.6))
+
+
+def patch_corner_uv(scene: Scene) -> np.ndarray:
+    """Per-corner texture coordinates of the height-field patch: (x, y) + 1/2."""
+    return _f32(scene.verts[scene.tris][:, :, :2] + 0.5)
+
+
+def latlong_corner_uv(n_lon: int, n_ring: int, tris: np.ndarray) -> np.ndarray:
+    """Per-corner (phi / 2pi, theta / pi) of a lat-long mesh: corners across the
+    phi = 0 seam take u + 1, pole corners the mean u of the other two."""
+    N = n_ring * n_lon + 2
+    k = np.zeros(N)
+    th = np.zeros(N)
+    ids = np.arange(n_ring * n_lon)
+    k[ids] = ids % n_lon
+    th[ids] = (ids // n_lon + 1) / (n_ring + 1)
+    top, bot = n_ring * n_lon, n_ring * n_lon + 1
+    th[top], th[bot] = 0.0, 1.0
+    pole = (tris == top) | (tris == bot)
+    kk = k[tris]
+    # unwrap the seam: lift the low longitudes of a triangle that spans it
+    lo_side = np.where(pole, np.inf, kk).min(axis=1)
+    hi_side = np.where(pole, -np.inf, kk).max(axis=1)
+    wrap = (hi_side - lo_side) > n_lon / 2
+    kk = np.where(wrap[:, None] & (kk < n_lon / 2) & ~pole, kk + n_lon, kk)
+    u = kk / n_lon
+    mean_u = np.where(pole, 0.0, u).sum(axis=1) / np.maximum((~pole).sum(axis=1), 1)
+    u = np.where(pole, mean_u[:, None], u)
+    return _f32(np.stack([u, th[tris]], axis=-1))
 
 
 def perturbed_patch(scene: Scene, sigma: float = 0.05, seed: int = 3) -> Scene:
