@@ -12,7 +12,9 @@ forward rays per second of whole steps: W*H*spp*(1 + L) / step time.  The
 same line carries the roofline of the dominant kernel, traversal statistics,
 the batched step over 32 faces of mixed sizes ("batch"), the serving run
 (Poisson arrivals, continuous batching vs one at a time: recons/s, p50/p99
-latency; "serving") and the FP64 oracle's rate on the host ("cpu_baseline").
+latency; "serving"), the large textured render (1024x1024, 200,000 triangles,
+1024^2 maps, 64 spp, 128 lights, refit every step; "large") and the FP64
+oracle's rate on the host ("cpu_baseline").
 """
 from __future__ import annotations
 
@@ -65,6 +67,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-steps", type=int, default=150, help="Adam steps per request")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--large-steps", type=int, default=3,
+                    help="steps of the 1024^2 textured render measurement (0 = skip)")
+    ap.add_argument("--large-only", action="store_true", help="run only the large textured render measurement")
     return ap.parse_args()
 
 
@@ -231,6 +236,60 @@ def serve_bench(ctx, mt, n_req, rate, n_steps, budget, seed=41):
             "workload": "C2 faces, W from {128..512}, spp from {4,8,16,32}, 72 lights, Adam with the Sec. 5 rates"}
 
 
+def large_bench(ctx, steps, warmup, edge_samples=-1, seed=51):
+    """The large textured render (1024 x 1024, 100,002 vertices / 200,000
+    triangles, 1024^2 diffuse/specular/roughness maps, 64 spp, 128 lights):
+    per step a BVH refit over a new small random deformation of the vertices
+    (the deformed sets are generated before the timed region), the forward
+    render, the smoothed L1 loss against a synthetic photograph and the
+    backward to vertices (with the boundary term) and texels."""
+    import torch
+    from paper_2101_05356_amd import render as R
+    from paper_2101_05356_amd import scenes
+    sc = scenes.large_textured_scene()
+    W, H, S, L = sc.camera.W, sc.camera.H, sc.spp, sc.lights.count
+    rng = np.random.default_rng(seed)
+    n_sets = warmup + steps
+    vsets = [torch.as_tensor(scenes.deform_vertices(rng, sc.verts)).cuda() for _ in range(n_sets)]
+    target = torch.as_tensor(scenes.smooth_random_image(rng, H, W, 0.0, 0.3)).cuda()
+    m = R.Mesh(ctx, sc.n_verts, sc.tris)
+    ds = R.DeviceScene.from_scene(sc)
+    m.update(ds.verts, rebuild=True)
+    ns = W * H if edge_samples < 0 else edge_samples
+    groups = ("verts",) + R.TEX_GROUPS
+    ev = {k: [] for k in ("fwd", "bwd")}
+
+    def step(i, timed):
+        v = vsets[i]
+        m.update(v, rebuild=False)
+        pair = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in ev}
+        img = R.render_forward(m, ds, verts=v, events=pair["fwd"] if timed else None)
+        E, dEdp = R.loss(img, target, smooth=True)
+        R.render_backward(m, ds, dEdp, edge_samples=ns, groups=groups, verts=v,
+                          events=pair["bwd"] if timed else None)
+        if timed:
+            for k in ev:
+                ev[k].append(pair[k])
+        return E
+
+    for i in range(warmup):
+        step(i, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        E = step(warmup + i, True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nominal = W * H * S * (1 + L)
+    return {"workload": f"{W}x{H} textured face: {sc.n_verts:,}-vertex / {len(sc.tris):,}-triangle lat-long mesh, "
+                        f"{sc.tex_size}^2 maps, {S} spp, {L} lights, refit+render+loss+backward (verts with "
+                        f"{ns} edge samples, texels)",
+            "steps": steps, "ms_per_step": 1e3 * dt / steps, "rays_per_s": nominal * steps / dt,
+            "render_fwd_kernel_ms": float(np.mean([a.elapsed_time(b) for a, b in ev["fwd"]])),
+            "render_bwd_kernel_ms": float(np.mean([a.elapsed_time(b) for a, b in ev["bwd"]])),
+            "loss": float(E.item())}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -252,6 +311,9 @@ def main():
     S, L = args.spp, args.lights
     ns = W * H if args.edge_samples < 0 else args.edge_samples
     ctx = R.Context(0)
+    if args.large_only:
+        print(json.dumps({"large": large_bench(ctx, max(args.large_steps, 1), 1)}), flush=True)
+        return
     mt, rc = make_c2(ctx, W, S, L, args.edge_samples)
     for _ in range(args.warmup):
         rc.step()
@@ -307,6 +369,9 @@ def main():
         out["serving"] = serve_bench(ctx, mt, args.serve_requests, args.serve_rate, args.serve_steps,
                                      int(args.serve_budget_gb * 2**30))
         print(json.dumps({"progress": "serving"}), file=sys.stderr, flush=True)
+    if args.large_steps > 0 and not args.profile_only:
+        out["large"] = large_bench(ctx, args.large_steps, 1)
+        print(json.dumps({"progress": "large", **out["large"]}), file=sys.stderr, flush=True)
     if not args.profile_only and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, S, L, W)
     print(json.dumps(out), flush=True)

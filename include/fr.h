@@ -113,6 +113,20 @@ typedef struct {
   float fov_y;             /* vertical field of view, radians (host value) */
   uint32_t step;           /* optimisation step: the 4th Philox counter word */
   uint64_t seed;           /* Philox key */
+  /* Reflectance maps (Sec. 3.2: diffuse, specular and roughness as M x M
+   * images in texture space).  tex_size M > 0 selects them in place of the
+   * per-vertex diffuse/specular/roughness (which may then be NULL); M = 0
+   * leaves the per-vertex arrays in use and the pointers below unread.
+   * A shading point takes (u, v) = sum_k b_k uv_k over the hit triangle's
+   * corners and reads each map bilinearly: texel (i, j) is centred at
+   * ((i + 1/2)/M, (j + 1/2)/M), addresses clamp to the border texel.
+   * All device pointers, read only, M <= 16384. */
+  int32_t tex_size;
+  int32_t tex_pad_;
+  const float* tex_uv;        /* [F*3*2] (u, v) of each triangle corner, in triangle order */
+  const float* tex_diffuse;   /* [M*M*3] texel (i, j) at offset 3 (j M + i) */
+  const float* tex_specular;  /* [M*M*3] */
+  const float* tex_roughness; /* [M*M] */
 } fr_scene;
 
 typedef struct {
@@ -159,6 +173,11 @@ typedef struct {
   float* light_geom; /* [L*9] p0, e1, e2 */
   float* light_rad;  /* [L*3] */
   float* cam;        /* [12] R row-major, T */
+  /* reflectance maps (scene tex_size M > 0; untouched otherwise); with maps
+   * in use the per-vertex diffuse/specular/roughness receive nothing */
+  float* tex_diffuse;   /* [M*M*3] */
+  float* tex_specular;  /* [M*M*3] */
+  float* tex_roughness; /* [M*M] */
 } fr_grads;
 
 /* Forward render (Sec. 4 Eq. energy: p^S = F(chi), the Monte-Carlo estimate
@@ -185,6 +204,9 @@ int fr_loss(const float* d_image, const float* d_target, int32_t width, int32_t 
  * then the vertex-normal adjoint into grads->verts, then, if
  * opts->edge_samples != 0, the primary-visibility boundary term of edge
  * sampling (Sec. 4 "Edge Sampling") into grads->verts and grads->cam.
+ * With reflectance maps each shading point spreads its reflectance gradient
+ * over its four texels by the bilinear weights (grads->tex_*), and the maps'
+ * own slope in (u, v) carries into the barycentrics and the vertices.
  * Uses the mesh's internal scratch; calls on one mesh must not overlap. */
 int fr_render_backward(fr_mesh* mesh, const fr_scene* scene, const fr_render_opts* opts, const float* d_dEdp,
                        fr_grads* grads, fr_stream stream);

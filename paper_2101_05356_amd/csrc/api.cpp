@@ -54,8 +54,12 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
     return fail(ctx, FR_ERR_INVALID_ARG, "image size must be positive and n_lights >= 0");
   if (!pow2(s->spp) || s->spp > 1024) return fail(ctx, FR_ERR_LIMIT, "spp must be a power of two in [1, 1024]");
   if ((long long)s->width * s->height > (1ll << 26)) return fail(ctx, FR_ERR_LIMIT, "image larger than 2^26 pixels");
-  if (!s->verts || !s->diffuse || !s->specular || !s->roughness || !s->cam)
+  if (s->tex_size < 0 || s->tex_size > 16384) return fail(ctx, FR_ERR_LIMIT, "tex_size must be in [0, 16384]");
+  const bool maps = s->tex_size > 0;
+  if (!s->verts || !s->cam || (!maps && (!s->diffuse || !s->specular || !s->roughness)))
     return fail(ctx, FR_ERR_INVALID_ARG, "null scene pointer");
+  if (maps && (!s->tex_uv || !s->tex_diffuse || !s->tex_specular || !s->tex_roughness))
+    return fail(ctx, FR_ERR_INVALID_ARG, "null reflectance-map pointer");
   if (s->n_lights > 0 && (!s->light_p0 || !s->light_e1 || !s->light_e2 || !s->light_rad || !s->light_shape))
     return fail(ctx, FR_ERR_INVALID_ARG, "null light pointer");
   if (!(s->fov_y > 0.0f && s->fov_y < 3.1f)) return fail(ctx, FR_ERR_INVALID_ARG, "fov_y must be in (0, 3.1)");
@@ -66,6 +70,11 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
   a.nodes = d.nodes4; a.recs = d.recs; a.tris = d.tris; a.verts = s->verts; a.normals = d.normals;
   a.diffuse = s->diffuse; a.specular = s->specular; a.roughness = s->roughness;
   a.lights = d.lights; a.cam = s->cam;
+  a.M = maps ? s->tex_size : 0;
+  a.uv = maps ? s->tex_uv : nullptr;
+  a.tex_c = maps ? s->tex_diffuse : nullptr;
+  a.tex_s = maps ? s->tex_specular : nullptr;
+  a.tex_r = maps ? s->tex_roughness : nullptr;
   a.N = d.N; a.F = d.F; a.L = s->n_lights;
   a.W = s->width; a.H = s->height; a.S = s->spp;
   a.lanes_per_pixel = std::min(a.S, 64);
@@ -82,8 +91,10 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
   a.tiles_x = (a.W + a.tile_w - 1) / a.tile_w;
   a.tiles_y = (a.H + a.tile_h - 1) / a.tile_h;
   a.n_tiles = a.tiles_x * a.tiles_y;
-  a.tan_half = (float)std::tan(0.5 * (double)s->fov_y);
-  a.aspect = (float)((double)a.W / (double)a.H);
+  a.tan_half_d = std::tan(0.5 * (double)s->fov_y);
+  a.aspect_d = (double)a.W / (double)a.H;
+  a.tan_half = (float)a.tan_half_d;
+  a.aspect = (float)a.aspect_d;
   a.k0 = (uint32_t)(s->seed & 0xffffffffull);
   a.k1 = (uint32_t)(s->seed >> 32);
   a.step = s->step;
@@ -232,7 +243,7 @@ int fr_mesh_destroy(fr_mesh* m) {
   void* ptrs[] = {d.tris, d.vf_off, d.vf_idx, d.normals, d.nlen, d.gnorm, d.edges, d.edge_faces, d.nodes, d.recs,
                   d.order, d.node_parent, d.leaf_parent, d.flags, d.keys[0], d.keys[1], d.vals[0], d.vals[1],
                   d.hist, d.partial, d.scene_box, d.depth, d.lights, d.ltmp, d.edge_len, d.edge_cdf, d.face_front,
-                  d.scan_part, d.img_partial, d.acc, d.slots, d.nodes4, d.n4_src, d.top_nodes, d.top_level_off, m->loss_scratch, m->loss_gtmp};
+                  d.scan_part, d.img_partial, d.acc, d.tex_acc, d.slots, d.nodes4, d.n4_src, d.top_nodes, d.top_level_off, m->loss_scratch, m->loss_gtmp};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -357,10 +368,30 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
   fr::fix_t* acc_r = d.acc + 12 * N;
   fr::fix_t* acc_cam = d.acc + 13 * N;
   fr::launch_zero_fix(d.acc, 13 * N + 12, st);
+  // texel accumulators [7 M^2]: diffuse, specular (3 M^2 each), roughness (M^2)
+  const size_t MM = (size_t)a.M * a.M;
+  const bool want_tex = a.M > 0 && (g->tex_diffuse || g->tex_specular || g->tex_roughness);
+  if (want_tex) {
+    if (7 * MM > d.tex_acc_cap) {
+      if (d.tex_acc) (void)hipFree(d.tex_acc);
+      d.tex_acc = nullptr;
+      d.tex_acc_cap = 0;
+      FR_HIP(m->ctx, dalloc(&d.tex_acc, 7 * MM));
+      d.tex_acc_cap = 7 * MM;
+    }
+    fr::launch_zero_fix(d.tex_acc, 7 * MM, st);
+  }
   if (s->n_lights > 0) fr::launch_light_setup(*s, d.lights, st);
   const bool want_n = g->normals || g->verts;
-  const fr::FixGrads fg = {g->verts ? acc_v : nullptr, want_n ? acc_n : nullptr, g->diffuse ? acc_c : nullptr,
-                           g->specular ? acc_s : nullptr, g->roughness ? acc_r : nullptr};
+  const bool vtx_refl = a.M == 0;
+  fr::FixGrads fg = {g->verts ? acc_v : nullptr, want_n ? acc_n : nullptr,
+                     vtx_refl && g->diffuse ? acc_c : nullptr, vtx_refl && g->specular ? acc_s : nullptr,
+                     vtx_refl && g->roughness ? acc_r : nullptr, nullptr, nullptr, nullptr};
+  if (want_tex) {
+    fg.tex_c = g->tex_diffuse ? d.tex_acc : nullptr;
+    fg.tex_s = g->tex_specular ? d.tex_acc + 3 * MM : nullptr;
+    fg.tex_r = g->tex_roughness ? d.tex_acc + 6 * MM : nullptr;
+  }
   fr::launch_render_backward(a, d_dEdp, fg, d.slots, *g, st, static_cast<hipEvent_t>(o->ev_kernel_begin),
                              static_cast<hipEvent_t>(o->ev_kernel_end));
   if (g->normals) fr::launch_fix_to_float(acc_n, g->normals, 3 * d.N, st);
@@ -370,9 +401,12 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
     fr::launch_edges(d, a, d_dEdp, ns, g->verts ? acc_v : nullptr, g->cam ? acc_cam : nullptr, o->dbg_hit,
                      o->dbg_pflag, std::tan(0.5 * (double)s->fov_y), st);
   if (g->verts) fr::launch_fix_to_float(acc_v, g->verts, 3 * d.N, st);
-  if (g->diffuse) fr::launch_fix_to_float(acc_c, g->diffuse, 3 * d.N, st);
-  if (g->specular) fr::launch_fix_to_float(acc_s, g->specular, 3 * d.N, st);
-  if (g->roughness) fr::launch_fix_to_float(acc_r, g->roughness, d.N, st);
+  if (fg.diffuse) fr::launch_fix_to_float(acc_c, g->diffuse, 3 * d.N, st);
+  if (fg.specular) fr::launch_fix_to_float(acc_s, g->specular, 3 * d.N, st);
+  if (fg.roughness) fr::launch_fix_to_float(acc_r, g->roughness, d.N, st);
+  if (fg.tex_c) fr::launch_fix_to_float(fg.tex_c, g->tex_diffuse, (int)(3 * MM), st);
+  if (fg.tex_s) fr::launch_fix_to_float(fg.tex_s, g->tex_specular, (int)(3 * MM), st);
+  if (fg.tex_r) fr::launch_fix_to_float(fg.tex_r, g->tex_roughness, (int)MM, st);
   if (g->cam) fr::launch_fix_to_float(acc_cam, g->cam, 12, st);
   FR_HIP(m->ctx, hipGetLastError());
   return FR_OK;

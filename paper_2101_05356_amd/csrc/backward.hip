@@ -7,6 +7,8 @@
 //   - per-vertex positions, normals, diffuse, specular, roughness: per-wave
 //     match-reduce over lanes that hit the same triangle, then one set of
 //     fixed-point atomics per distinct triangle;
+//   - with reflectance maps, per-texel diffuse, specular, roughness: the same
+//     match-reduce over lanes sharing a bilinear footprint;
 //   - per-light geometry and radiance, and the camera: wave reduction,
 //     fixed-point LDS accumulation per block, then fixed-point atomics into
 //     one of kSlots partial slots, summed by a final kernel.
@@ -46,6 +48,7 @@ __device__ __forceinline__ void g1_fwd_bwd(float nv, float hv, float r, float& G
   dG1_dr = -dG * a / r;             // da/dr = -a / r
 }
 
+template <bool TEX>
 __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const float* __restrict__ dEdp,
                                                  const FixGrads& g, fix_t* __restrict__ slots, int bid) {
   extern __shared__ fix_t lds[];   // [L*12 + 12]: per light p0 e1 e2 rad, then camera
@@ -56,8 +59,6 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
   const Item it = wave_item(a, bid);
   const int tile = it.tile;
   const int j0 = it.chunk * a.lc, j1 = min(a.L, j0 + a.lc);
-  float gcam[12];
-  for (int k = 0; k < 12; ++k) gcam[k] = 0.0f;
   if (tile >= 0) {
     const PixelSample ps = pixel_sample(a, tile, lane);
     float gbar[3] = {0.0f, 0.0f, 0.0f};
@@ -75,7 +76,9 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
       bool dummy = false;
       trace<false, false>(a.nodes, a.recs, a.F, sm.ray, want, -1, h, dummy);
       Frame fr = {};
-      const bool shaded = want && h.id >= 0 && shading_frame(a, sm, h, fr);
+      double fxd = 0.0, fyd = 0.0;
+      if (want && h.id >= 0) film_point(a, ps, s, fxd, fyd);
+      const bool shaded = want && h.id >= 0 && shading_frame<TEX>(a, sm, h, fr, fxd, fyd);
       // sample-level adjoint accumulators
       V3 gx = {0, 0, 0}, gns = {0, 0, 0}, gwo = {0, 0, 0}, gc = {0, 0, 0}, gs = {0, 0, 0};
       float gr = 0.0f;
@@ -195,27 +198,70 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
                                     gns.y != 0.0f || gns.z != 0.0f || gwo.x != 0.0f || gwo.y != 0.0f ||
                                     gwo.z != 0.0f || gc.x != 0.0f || gc.y != 0.0f || gc.z != 0.0f ||
                                     gs.x != 0.0f || gs.y != 0.0f || gs.z != 0.0f || gr != 0.0f);
+      TexTap tp = {0, 0, 0, 0, 0.0f, 0.0f};
+      // camera gradient of this chunk (reduced at its end, so that no
+      // accumulator stays live through the traversals)
+      float gcam[12];
+      for (int k = 0; k < 12; ++k) gcam[k] = 0.0f;
+      float bb[3] = {0.0f, 0.0f, 0.0f};
       if (has_g) {
+        // the triangle's corners and the FP64 barycentrics again, rather than
+        // kept live through the light loop (the empty asm keeps the compiler
+        // from reusing the earlier loads)
+        int id = h.id;
+        asm volatile("" : "+v"(id));
+        int vi[3];
+        for (int k = 0; k < 3; ++k) vi[k] = a.tris[3 * id + k];
+        double bd[3];
+        {
+          double fxd2, fyd2;
+          film_point(a, ps, s, fxd2, fyd2);
+          bary64(a, fxd2, fyd2, vi, bd);
+        }
+        for (int k = 0; k < 3; ++k) bb[k] = (float)bd[k];
         const float grr = fr.r_free ? gr : 0.0f;
         const V3 gm = project_out(gns, fr.ns, fr.inv_m);
         V3 vv[3];
         for (int k = 0; k < 3; ++k) {
-          vv[k] = ld3(a.verts, fr.vi[k]);
-          const V3 nk = ld3(a.normals, fr.vi[k]);
-          const V3 ck = ld3(a.diffuse, fr.vi[k]), sk = ld3(a.specular, fr.vi[k]);
-          const float rk = a.roughness[fr.vi[k]];
-          gb[k] = dot(nk, gm) + dot(vv[k], gx) + dot(ck, gc) + dot(sk, gs) + rk * grr;
-          gn[k] = gm * fr.b[k];
-          gv[k] = gx * fr.b[k];
+          vv[k] = ld3(a.verts, vi[k]);
+          const V3 nk = ld3(a.normals, vi[k]);
+          if (TEX) {
+            gb[k] = dot(nk, gm) + dot(vv[k], gx);
+          } else {
+            const V3 ck = ld3(a.diffuse, vi[k]), sk = ld3(a.specular, vi[k]);
+            const float rk = a.roughness[vi[k]];
+            gb[k] = dot(nk, gm) + dot(vv[k], gx) + dot(ck, gc) + dot(sk, gs) + rk * grr;
+          }
+          gn[k] = gm * bb[k];
+          gv[k] = gx * bb[k];
+        }
+        if (TEX) {
+          // reflectance = bilinear read at (u, v) = sum_k b_k uv_k: its slope
+          // in (u, v) (d fx / du = M inside a cell) goes to the b_k
+          tp = tex_tap(a, id, bd);
+          const auto proj = [&](int t) {
+            return dot(ld3(a.tex_c, t), gc) + dot(ld3(a.tex_s, t), gs) + a.tex_r[t] * grr;
+          };
+          const float P00 = proj(tp.t00), P10 = proj(tp.t10), P01 = proj(tp.t01), P11 = proj(tp.t11);
+          const float Mf = (float)a.M;
+          const float gu = Mf * ((1.0f - tp.fy) * (P10 - P00) + tp.fy * (P11 - P01));
+          const float gvv = Mf * ((1.0f - tp.fx) * (P01 - P00) + tp.fx * (P11 - P10));
+          const float* q = a.uv + 6 * id;
+          for (int k = 0; k < 3; ++k) gb[k] += gu * q[2 * k] + gvv * q[2 * k + 1];
         }
         // b0 = 1 - b1 - b2; Moller-Trumbore adjoint of (b1, b2), solved from
-        // o' = o + t d (t held fixed: g_o += g_o', g_d += t g_o')
+        // the crossing point o' = o + t d itself (t = hit distance, held
+        // fixed: g_o += g_o', g_d += t g_o'), placed by the FP64 barycentrics:
+        // sv = o' - v0 = b1 e1 + b2 e2, qv = sv x e1.  An FP32 o' would carry
+        // ~ulp(|o|) of error into sv, inconsistent with those barycentrics.
         const float g1 = gb[1] - gb[0], g2 = gb[2] - gb[0];
         const V3 d = sm.ray.d;
-        Bary B;
-        bary_solve(sm.ray.o, d, fr.t, vv[0], vv[1], vv[2], B);
-        const V3 e1 = B.e1, e2 = B.e2, pv = B.pv, sv = B.sv, qv = B.qv;
-        const float idet = B.idet, b1 = B.b1, b2 = B.b2;
+        const V3 e1 = vv[1] - vv[0], e2 = vv[2] - vv[0];
+        const V3 pv = cross(d, e2);
+        const float idet = 1.0f / dot(e1, pv);
+        const float b1 = bb[1], b2 = bb[2];
+        const V3 sv = e1 * b1 + e2 * b2;
+        const V3 qv = cross(sv, e1);
         const float gA1 = g1 * idet, gA2 = g2 * idet, gdet = -(g1 * b1 + g2 * b2) * idet;
         V3 gsv = pv * gA1, gp = sv * gA1;
         V3 gd = qv * gA2 - gwo;
@@ -229,7 +275,7 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
         gv[0] = gv[0] - gsv - ge1 - ge2;
         gv[1] = gv[1] + ge1;
         gv[2] = gv[2] + ge2;
-        gd = gd + gsv * fr.t;
+        gd = gd + gsv * h.t;
         // d = dw / |dw|, dw = R dc, o = T
         const V3 gdw = project_out(gd, d, sm.inv_len);
         gcam[0] += gdw.x * sm.dc.x; gcam[1] += gdw.x * sm.dc.y; gcam[2] += gdw.x * sm.dc.z;
@@ -237,6 +283,13 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
         gcam[6] += gdw.z * sm.dc.x; gcam[7] += gdw.z * sm.dc.y; gcam[8] += gdw.z * sm.dc.z;
         gcam[9] += gsv.x; gcam[10] += gsv.y; gcam[11] += gsv.z;
         gr = grr;
+      }
+      // camera: wave reduction of this chunk into LDS
+      if (ballot(has_g)) {
+        for (int k = 0; k < 12; ++k) {
+          const float t = wave_sum(gcam[k]);
+          if (lane == 0 && t != 0.0f) atomicAdd(&lds[12 * a.L + k], to_fix(t));
+        }
       }
       // ---- per-vertex scatter: one atomic set per distinct triangle in the wave
       uint64_t todo = ballot(has_g);
@@ -248,25 +301,56 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
         const int* tv = a.tris + 3 * key;
         for (int k = 0; k < 3; ++k) {
           const int vi = tv[k];
-          const float bk = fr.b[k];
-          float vals[13] = {gv[k].x, gv[k].y, gv[k].z, gn[k].x, gn[k].y, gn[k].z, gc.x * bk, gc.y * bk, gc.z * bk,
-                            gs.x * bk, gs.y * bk, gs.z * bk, gr * bk};
-          for (int q = 0; q < 13; ++q) vals[q] = wave_sum(mine ? vals[q] : 0.0f);
-          if (lane == leader) {
-            if (g.verts) { fix_add(g.verts + 3 * vi, vals[0]); fix_add(g.verts + 3 * vi + 1, vals[1]); fix_add(g.verts + 3 * vi + 2, vals[2]); }
-            if (g.normals) { fix_add(g.normals + 3 * vi, vals[3]); fix_add(g.normals + 3 * vi + 1, vals[4]); fix_add(g.normals + 3 * vi + 2, vals[5]); }
-            if (g.diffuse) { fix_add(g.diffuse + 3 * vi, vals[6]); fix_add(g.diffuse + 3 * vi + 1, vals[7]); fix_add(g.diffuse + 3 * vi + 2, vals[8]); }
-            if (g.specular) { fix_add(g.specular + 3 * vi, vals[9]); fix_add(g.specular + 3 * vi + 1, vals[10]); fix_add(g.specular + 3 * vi + 2, vals[11]); }
-            if (g.roughness) fix_add(g.roughness + vi, vals[12]);
+          const float bk = bb[k];
+          if (TEX) {
+            // reflectance gradients go to the texels below
+            float vals[6] = {gv[k].x, gv[k].y, gv[k].z, gn[k].x, gn[k].y, gn[k].z};
+            for (int q = 0; q < 6; ++q) vals[q] = wave_sum(mine ? vals[q] : 0.0f);
+            if (lane == leader) {
+              if (g.verts) { fix_add(g.verts + 3 * vi, vals[0]); fix_add(g.verts + 3 * vi + 1, vals[1]); fix_add(g.verts + 3 * vi + 2, vals[2]); }
+              if (g.normals) { fix_add(g.normals + 3 * vi, vals[3]); fix_add(g.normals + 3 * vi + 1, vals[4]); fix_add(g.normals + 3 * vi + 2, vals[5]); }
+            }
+          } else {
+            float vals[13] = {gv[k].x, gv[k].y, gv[k].z, gn[k].x, gn[k].y, gn[k].z, gc.x * bk, gc.y * bk, gc.z * bk,
+                              gs.x * bk, gs.y * bk, gs.z * bk, gr * bk};
+            for (int q = 0; q < 13; ++q) vals[q] = wave_sum(mine ? vals[q] : 0.0f);
+            if (lane == leader) {
+              if (g.verts) { fix_add(g.verts + 3 * vi, vals[0]); fix_add(g.verts + 3 * vi + 1, vals[1]); fix_add(g.verts + 3 * vi + 2, vals[2]); }
+              if (g.normals) { fix_add(g.normals + 3 * vi, vals[3]); fix_add(g.normals + 3 * vi + 1, vals[4]); fix_add(g.normals + 3 * vi + 2, vals[5]); }
+              if (g.diffuse) { fix_add(g.diffuse + 3 * vi, vals[6]); fix_add(g.diffuse + 3 * vi + 1, vals[7]); fix_add(g.diffuse + 3 * vi + 2, vals[8]); }
+              if (g.specular) { fix_add(g.specular + 3 * vi, vals[9]); fix_add(g.specular + 3 * vi + 1, vals[10]); fix_add(g.specular + 3 * vi + 2, vals[11]); }
+              if (g.roughness) fix_add(g.roughness + vi, vals[12]);
+            }
+          }
+        }
+      }
+      // ---- per-texel scatter (maps in use): lanes with the same bilinear
+      // footprint (its first and last texel fix the other two) reduce together
+      if (TEX) {
+        uint64_t tdo = ballot(has_g);
+        while (tdo) {
+          const int leader = (int)__builtin_ctzll(tdo);
+          const int k00 = readlane_i(tp.t00, leader), k11 = readlane_i(tp.t11, leader);
+          const bool mine = has_g && tp.t00 == k00 && tp.t11 == k11;
+          tdo &= ~ballot(mine);
+          const int k10 = readlane_i(tp.t10, leader), k01 = readlane_i(tp.t01, leader);
+          const float fx = tp.fx, fy = tp.fy;
+          for (int q = 0; q < 4; ++q) {
+            const float w = q == 0 ? (1.0f - fx) * (1.0f - fy)
+                            : q == 1 ? fx * (1.0f - fy)
+                            : q == 2 ? (1.0f - fx) * fy : fx * fy;
+            const int t = q == 0 ? k00 : q == 1 ? k10 : q == 2 ? k01 : k11;
+            float rv[7] = {gc.x * w, gc.y * w, gc.z * w, gs.x * w, gs.y * w, gs.z * w, gr * w};
+            for (int c = 0; c < 7; ++c) rv[c] = wave_sum(mine ? rv[c] : 0.0f);
+            if (lane == leader) {
+              if (g.tex_c) { fix_add(g.tex_c + 3 * t, rv[0]); fix_add(g.tex_c + 3 * t + 1, rv[1]); fix_add(g.tex_c + 3 * t + 2, rv[2]); }
+              if (g.tex_s) { fix_add(g.tex_s + 3 * t, rv[3]); fix_add(g.tex_s + 3 * t + 1, rv[4]); fix_add(g.tex_s + 3 * t + 2, rv[5]); }
+              if (g.tex_r) fix_add(g.tex_r + t, rv[6]);
+            }
           }
         }
       }
     }
-  }
-  // camera: wave reduction into LDS
-  for (int k = 0; k < 12; ++k) {
-    const float t = wave_sum(gcam[k]);
-    if (lane == 0 && t != 0.0f) atomicAdd(&lds[12 * a.L + k], to_fix(t));
   }
   __syncthreads();
   fix_t* slot = slots + (size_t)(bid % kSlots) * nl;
@@ -274,9 +358,10 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
     if (lds[i] != 0) atomicAdd(slot + i, lds[i]);
 }
 
+template <bool TEX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_render_bwd(RenderArgs a, const float* __restrict__ dEdp, FixGrads g,
                                                     fix_t* __restrict__ slots) {
-  render_bwd_block(a, dEdp, g, slots, blockIdx.x);
+  render_bwd_block<TEX>(a, dEdp, g, slots, blockIdx.x);
 }
 
 // Sum the slots (exact integer sums) into the caller's light and camera gradients.
@@ -317,7 +402,10 @@ void launch_render_backward(const RenderArgs& a, const float* dEdp, const FixGra
   launch_zero_fix(slots, (size_t)kSlots * nl, st);
   const int blocks = wave_blocks_items(a);
   if (e0) (void)hipEventRecord(e0, st);
-  hipLaunchKernelGGL(k_render_bwd, dim3(blocks), dim3(256), nl * sizeof(fix_t), st, a, dEdp, fg, slots);
+  if (a.M > 0)
+    hipLaunchKernelGGL(k_render_bwd<true>, dim3(blocks), dim3(256), nl * sizeof(fix_t), st, a, dEdp, fg, slots);
+  else
+    hipLaunchKernelGGL(k_render_bwd<false>, dim3(blocks), dim3(256), nl * sizeof(fix_t), st, a, dEdp, fg, slots);
   if (e1) (void)hipEventRecord(e1, st);
   hipLaunchKernelGGL(k_slots_reduce, dim3(nl), dim3(256), 0, st, slots, nl, a.L, g.light_geom, g.light_rad, g.cam);
 }

@@ -58,7 +58,7 @@ FR_BATCH_KERNEL(kb_light_setup, 256) {
   FR_JOB_PROLOGUE light_setup_block(J.lp0, J.le1, J.le2, J.param + J.off_rad, J.lshape, J.ra.L, J.lights, lb);
 }
 __attribute__((amdgpu_waves_per_eu(8))) FR_BATCH_KERNEL(kb_render_fwd, 256) {
-  FR_JOB_PROLOGUE render_fwd_block<false>(J.ra, J.ra.n_lchunks > 1 ? nullptr : J.image, lb);
+  FR_JOB_PROLOGUE render_fwd_block<false, false>(J.ra, J.ra.n_lchunks > 1 ? nullptr : J.image, lb);
 }
 FR_BATCH_KERNEL(kb_sum_chunks, 256) {
   FR_JOB_PROLOGUE sum_chunks_block(J.ra.partial, 3 * J.ra.W * J.ra.H, J.ra.n_lchunks, J.image, lb);
@@ -89,7 +89,7 @@ FR_BATCH_KERNEL(kb_zero_grads, 256) {
 __attribute__((amdgpu_waves_per_eu(6))) FR_BATCH_KERNEL(kb_render_bwd, 256) {
   FR_JOB_PROLOGUE
   const FixGrads g = {J.acc, J.acc + 3 * J.N, J.acc + 6 * J.N, nullptr, nullptr};
-  render_bwd_block(J.rb, J.dEdp, g, J.lslots, lb);
+  render_bwd_block<false>(J.rb, J.dEdp, g, J.lslots, lb);
 }
 // fixed-point vertex and diffuse gradients -> float
 FR_BATCH_KERNEL(kb_fix_finalize, 256) {
@@ -115,7 +115,7 @@ FR_BATCH_KERNEL(kb_edge_len, 256) {
 }
 FR_BATCH_KERNEL(kb_edge_scan, 256) { FR_JOB_PROLOGUE edge_scan_local_block(J.edge_len, J.ea.E, J.edge_cdf, J.scan_part, lb); }
 FR_BATCH_KERNEL(kb_edge_scan_add, 256) { FR_JOB_PROLOGUE edge_scan_add_block(J.edge_cdf, J.ea.E, J.scan_part, lb); }
-__attribute__((amdgpu_waves_per_eu(6))) FR_BATCH_KERNEL(kb_edge_samples, 256) { FR_JOB_PROLOGUE edge_samples_block<false>(J.rb, J.ea, lb); }
+__attribute__((amdgpu_waves_per_eu(6))) FR_BATCH_KERNEL(kb_edge_samples, 256) { FR_JOB_PROLOGUE edge_samples_block<false, false>(J.rb, J.ea, lb); }
 FR_BATCH_KERNEL(kb_pose_bwd_v, 256) { FR_JOB_PROLOGUE pose_bwd_v_block(J.N, J.param + J.off_pose, J.g_verts, J.g_vobj, lb); }
 FR_BATCH_KERNEL(kb_pose_bwd_p, 1024) {
   FR_JOB_PROLOGUE pose_bwd_p_block(J.v_obj, J.N, J.param + J.off_pose, J.g_verts, J.grad + J.off_pose, lb);

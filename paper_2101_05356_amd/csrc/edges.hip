@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_edge_scan_add(double* __restrict__ cdf,
 }
 
 // Shaded radiance (no 1/S) of the camera ray through film point (fx, fy).
-template <bool DUMP>
+template <bool DUMP, bool TEX>
 __device__ __forceinline__ void side_radiance(const RenderArgs& a, float fx, float fy, bool active, int k, int j0,
                                               int j1, V3& L, int& hit_id, bool& amb) {
   Sample sm;
@@ -155,7 +155,7 @@ __device__ __forceinline__ void side_radiance(const RenderArgs& a, float fx, flo
   if (DUMP && active && hit_ambiguous(h)) amb = true;
   hit_id = h.id;
   Frame fr = {};
-  const bool shaded = active && h.id >= 0 && shading_frame(a, sm, h, fr);
+  const bool shaded = active && h.id >= 0 && shading_frame<TEX>(a, sm, h, fr, (double)fx, (double)fy);
   if (DUMP && active && h.id >= 0 && fabsf(fr.cos_o) < kFlagCos) amb = true;
   L = {0.0f, 0.0f, 0.0f};
   for (int j = j0; j < j1; ++j) {
@@ -187,7 +187,7 @@ __device__ __forceinline__ void side_radiance(const RenderArgs& a, float fx, flo
 
 // One wave = 64 consecutive edge samples x one chunk of lights; the chunks of
 // one sample group are neighbouring waves of a block.
-template <bool DUMP>
+template <bool DUMP, bool TEX>
 __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const EdgeArgs& e, int bid) {
   const int lane = threadIdx.x & 63;
   const int w = bid * 4 + (threadIdx.x >> 6);
@@ -229,8 +229,8 @@ __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const Ed
   const bool active = pid >= 0;
   V3 Lm, Lp;
   int hm = -1, hp = -1;
-  side_radiance<DUMP>(a, fx - 1e-3f * mx, fy - 1e-3f * my, active, k, j0, j1, Lm, hm, amb);
-  side_radiance<DUMP>(a, fx + 1e-3f * mx, fy + 1e-3f * my, active, k, j0, j1, Lp, hp, amb);
+  side_radiance<DUMP, TEX>(a, fx - 1e-3f * mx, fy - 1e-3f * my, active, k, j0, j1, Lm, hm, amb);
+  side_radiance<DUMP, TEX>(a, fx + 1e-3f * mx, fy + 1e-3f * my, active, k, j0, j1, Lp, hp, amb);
   if (DUMP && in) {
     if (chunk == 0) {
       e.dbg_rec[4 * k] = eid; e.dbg_rec[4 * k + 1] = pid; e.dbg_rec[4 * k + 2] = hm; e.dbg_rec[4 * k + 3] = hp;
@@ -282,9 +282,9 @@ __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const Ed
   }
 }
 
-template <bool DUMP>
+template <bool DUMP, bool TEX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_edge_samples(RenderArgs a, EdgeArgs e) {
-  edge_samples_block<DUMP>(a, e, blockIdx.x);
+  edge_samples_block<DUMP, TEX>(a, e, blockIdx.x);
 }
 
 void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samples, fix_t* gverts, fix_t* gcam,
@@ -305,10 +305,16 @@ void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samp
   e.n_lchunks = std::max(1, cdiv(a.L, e.lc));
   const int groups = (n_samples + 63) / 64;
   const int blocks = (groups * e.n_lchunks + 3) / 4;
-  if (dbg_rec)
-    hipLaunchKernelGGL(k_edge_samples<true>, dim3(blocks), dim3(256), 0, st, a, e);
-  else
-    hipLaunchKernelGGL(k_edge_samples<false>, dim3(blocks), dim3(256), 0, st, a, e);
+  if (a.M > 0) {
+    if (dbg_rec)
+      hipLaunchKernelGGL((k_edge_samples<true, true>), dim3(blocks), dim3(256), 0, st, a, e);
+    else
+      hipLaunchKernelGGL((k_edge_samples<false, true>), dim3(blocks), dim3(256), 0, st, a, e);
+  } else if (dbg_rec) {
+    hipLaunchKernelGGL((k_edge_samples<true, false>), dim3(blocks), dim3(256), 0, st, a, e);
+  } else {
+    hipLaunchKernelGGL((k_edge_samples<false, false>), dim3(blocks), dim3(256), 0, st, a, e);
+  }
 }
 
 }  // namespace fr

@@ -45,6 +45,9 @@ struct FixGrads {
   fix_t* diffuse;     // [N*3]
   fix_t* specular;    // [N*3]
   fix_t* roughness;   // [N]
+  fix_t* tex_c;       // [M*M*3] reflectance-map texels (maps in use)
+  fix_t* tex_s;       // [M*M*3]
+  fix_t* tex_r;       // [M*M]
 };
 
 // Arguments of the edge-sampling kernel.
@@ -109,6 +112,8 @@ struct MeshDev {
   double* scan_part = nullptr;      // [ceil(E/1024)] tile totals of the edge CDF scan
   float* img_partial = nullptr;     // per-light-chunk partial images
   size_t img_partial_cap = 0;
+  fix_t* tex_acc = nullptr;         // [7 M^2] fixed-point texel gradients: diffuse, specular, roughness
+  size_t tex_acc_cap = 0;
   int bvh_depth = -1;
   int built = 0;
 };
@@ -125,6 +130,11 @@ struct RenderArgs {
   const float* roughness;
   const LightRec* lights;
   const float* cam;       // [12]
+  const float* uv;        // [F*6] per-corner texture coordinates (M > 0)
+  const float* tex_c;     // [M*M*3] reflectance maps (M > 0)
+  const float* tex_s;     // [M*M*3]
+  const float* tex_r;     // [M*M]
+  int M;                  // map size; 0: per-vertex reflectance
   int N, F, L;
   int W, H, S;
   int tile_w, tile_h, tiles_x, tiles_y, n_tiles;   // wave tiles (S <= 64)
@@ -133,6 +143,7 @@ struct RenderArgs {
   int lc, n_lchunks;      // lights per work item, light chunks per tile
   float* partial;         // [n_lchunks][H*W*3] per-chunk pixel sums (n_lchunks > 1)
   float tan_half, aspect;
+  double tan_half_d, aspect_d;   // the same in FP64 (texture coordinates)
   uint32_t k0, k1, step;
   int variant, components;
   int32_t* dbg_hit;

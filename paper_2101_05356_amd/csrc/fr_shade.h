@@ -97,6 +97,18 @@ __device__ __forceinline__ void camera_sample(const RenderArgs& a, const PixelSa
   camera_ray_film(a, (float)ps.px + unit24(r.x), (float)ps.py + unit24(r.y), sm);
 }
 
+// Exact film point of a camera sample (pixel + jitter, an FP64 sum), for the
+// FP64 barycentrics of the shading point.  The jitter is drawn again here,
+// after the traversal: the empty asm keeps the compiler from reusing the
+// first draw, whose two values would otherwise stay live through it.
+__device__ __forceinline__ void film_point(const RenderArgs& a, const PixelSample& ps, int s, double& fx, double& fy) {
+  uint32_t pid = (uint32_t)ps.pid;
+  asm volatile("" : "+v"(pid));
+  const U4 r = philox(pid, (uint32_t)s, PURPOSE_JITTER, a.step, a.k0, a.k1);
+  fx = (double)ps.px + (double)unit24(r.x);
+  fy = (double)ps.py + (double)unit24(r.y);
+}
+
 // ---------------------------------------------------------------------------
 // Shading frame at the hit
 // ---------------------------------------------------------------------------
@@ -109,40 +121,79 @@ struct Frame {
   float cos_o;
   int vi[3];
   float b[3];
-  float t;         // hit distance (origin shift of the barycentric solve)
+  float t;         // hit distance (the crossing point o + t d, in the adjoint)
 };
 
-// Barycentrics of the ray's crossing with the hit triangle, re-solved
-// (Moller-Trumbore) from the point o' = o + t d next to the hit instead of the
-// ray origin: the crossing does not depend on which point of the line is used,
-// and the short o' - v0 avoids the cancellation of a far origin (camera
-// distance / triangle size ~ 100), which costs FP32 barycentrics ~1e-5.
-struct Bary {
-  V3 op, e1, e2, pv, sv, qv;
-  float det, idet, b1, b2;
-};
-
-__device__ __forceinline__ void bary_solve(const V3& o, const V3& d, float t, const V3& v0, const V3& v1,
-                                           const V3& v2, Bary& B) {
-  B.op = {o.x + t * d.x, o.y + t * d.y, o.z + t * d.z};
-  B.e1 = v1 - v0;
-  B.e2 = v2 - v0;
-  B.pv = cross(d, B.e2);
-  B.det = dot(B.e1, B.pv);
-  B.idet = 1.0f / B.det;
-  B.sv = B.op - v0;
-  B.qv = cross(B.sv, B.e1);
-  B.b1 = dot(B.sv, B.pv) * B.idet;
-  B.b2 = dot(d, B.qv) * B.idet;
+// Barycentrics of the shading point, in FP64: the crossing of the exact
+// camera ray through film point (fx, fy) (FP64 direction from the FP32
+// camera) with the plane of triangle vi (FP32 vertices, exact in FP64),
+// Moller-Trumbore with the ray origin at the camera centre (the scale of the
+// direction cancels).  The FP32 ray of the traversal places the hit only to
+// ~ulp(|o|) in world units, i.e. ~1e-5 of a face-scale triangle: a weight b_k
+// near 0 then carries a large relative error into the vertex and texel
+// gradients.  The cost is one FP64 solve per camera sample.
+__device__ __forceinline__ void bary64(const RenderArgs& a, double fx, double fy, const int vi[3], double b[3]) {
+  const double sx = (2.0 * fx / (double)a.W - 1.0) * a.tan_half_d * a.aspect_d;
+  const double sy = (1.0 - 2.0 * fy / (double)a.H) * a.tan_half_d;
+  const float* R = a.cam;
+  const double dx = (double)R[0] * sx + (double)R[1] * sy - (double)R[2];
+  const double dy = (double)R[3] * sx + (double)R[4] * sy - (double)R[5];
+  const double dz = (double)R[6] * sx + (double)R[7] * sy - (double)R[8];
+  const float* p0 = a.verts + 3 * vi[0];
+  const float* p1 = a.verts + 3 * vi[1];
+  const float* p2 = a.verts + 3 * vi[2];
+  const double e1x = (double)p1[0] - p0[0], e1y = (double)p1[1] - p0[1], e1z = (double)p1[2] - p0[2];
+  const double e2x = (double)p2[0] - p0[0], e2y = (double)p2[1] - p0[1], e2z = (double)p2[2] - p0[2];
+  const double svx = (double)R[9] - p0[0], svy = (double)R[10] - p0[1], svz = (double)R[11] - p0[2];
+  const double pvx = dy * e2z - dz * e2y, pvy = dz * e2x - dx * e2z, pvz = dx * e2y - dy * e2x;
+  const double qvx = svy * e1z - svz * e1y, qvy = svz * e1x - svx * e1z, qvz = svx * e1y - svy * e1x;
+  const double idet = 1.0 / (e1x * pvx + e1y * pvy + e1z * pvz);
+  b[1] = (svx * pvx + svy * pvy + svz * pvz) * idet;
+  b[2] = (dx * qvx + dy * qvy + dz * qvz) * idet;
+  b[0] = 1.0 - b[1] - b[2];
 }
 
-__device__ __forceinline__ bool shading_frame(const RenderArgs& a, const Sample& sm, const HitState& h, Frame& f) {
+// Bilinear footprint on an M x M reflectance map (Sec. 3.2) at the shading
+// point's texture coordinates (u, v) = sum_k b_k uv_k (FP64 barycentrics):
+// texel (i, j) centred at ((i + 1/2)/M, (j + 1/2)/M), border-clamped
+// addresses; the taps (i0,j0), (i1,j0), (i0,j1), (i1,j1) weigh (1-fx)(1-fy),
+// fx(1-fy), (1-fx)fy, fx fy.  The cell corner is clamped in FP64 before the
+// integer conversion so that any input, NaN included, addresses inside the
+// map.
+struct TexTap {
+  int t00, t10, t01, t11;   // texel indices j M + i
+  float fx, fy;
+};
+
+__device__ __forceinline__ TexTap tex_tap(const RenderArgs& a, int tri, const double b[3]) {
+  const float* q = a.uv + 6 * tri;
+  const double u = b[0] * q[0] + b[1] * q[2] + b[2] * q[4];
+  const double v = b[0] * q[1] + b[1] * q[3] + b[2] * q[5];
+  const double x = u * (double)a.M - 0.5, y = v * (double)a.M - 0.5;
+  const double x0 = floor(x), y0 = floor(y);
+  TexTap t;
+  t.fx = (float)(x - x0);
+  t.fy = (float)(y - y0);
+  const int M = a.M;
+  const int ix = (int)fmin(fmax(x0, -1.0), (double)M), iy = (int)fmin(fmax(y0, -1.0), (double)M);
+  const int i0 = min(max(ix, 0), M - 1), i1 = min(max(ix + 1, 0), M - 1);
+  const int j0 = min(max(iy, 0), M - 1), j1 = min(max(iy + 1, 0), M - 1);
+  t.t00 = j0 * M + i0; t.t10 = j0 * M + i1; t.t01 = j1 * M + i0; t.t11 = j1 * M + i1;
+  return t;
+}
+
+// TEX selects the reflectance maps at compile time (a.M > 0 on the host), so
+// the per-vertex kernels keep their register budget.
+// (fx, fy) is the exact film point of the sample (FP64).
+template <bool TEX>
+__device__ __forceinline__ bool shading_frame(const RenderArgs& a, const Sample& sm, const HitState& h, Frame& f,
+                                              double fx, double fy) {
   const int* t = a.tris + 3 * h.id;
   f.vi[0] = t[0]; f.vi[1] = t[1]; f.vi[2] = t[2];
   const V3 v0 = ld3(a.verts, f.vi[0]), v1 = ld3(a.verts, f.vi[1]), v2 = ld3(a.verts, f.vi[2]);
-  Bary B;
-  bary_solve(sm.ray.o, sm.ray.d, h.t, v0, v1, v2, B);
-  const float b0 = 1.0f - B.b1 - B.b2, b1 = B.b1, b2 = B.b2;
+  double bd[3];
+  bary64(a, fx, fy, f.vi, bd);
+  const float b0 = (float)bd[0], b1 = (float)bd[1], b2 = (float)bd[2];
   f.b[0] = b0; f.b[1] = b1; f.b[2] = b2;
   f.t = h.t;
   f.x = v0 * b0 + v1 * b1 + v2 * b2;
@@ -151,9 +202,21 @@ __device__ __forceinline__ bool shading_frame(const RenderArgs& a, const Sample&
   f.inv_m = 1.0f / sqrtf(dot(f.m, f.m));
   f.ns = f.m * f.inv_m;
   f.wo = {-sm.ray.d.x, -sm.ray.d.y, -sm.ray.d.z};
-  f.c = ld3(a.diffuse, f.vi[0]) * b0 + ld3(a.diffuse, f.vi[1]) * b1 + ld3(a.diffuse, f.vi[2]) * b2;
-  f.s = ld3(a.specular, f.vi[0]) * b0 + ld3(a.specular, f.vi[1]) * b1 + ld3(a.specular, f.vi[2]) * b2;
-  const float r = a.roughness[f.vi[0]] * b0 + a.roughness[f.vi[1]] * b1 + a.roughness[f.vi[2]] * b2;
+  float r;
+  if (TEX) {
+    const TexTap tp = tex_tap(a, h.id, bd);
+    const float w00 = (1.0f - tp.fx) * (1.0f - tp.fy), w10 = tp.fx * (1.0f - tp.fy);
+    const float w01 = (1.0f - tp.fx) * tp.fy, w11 = tp.fx * tp.fy;
+    f.c = ld3(a.tex_c, tp.t00) * w00 + ld3(a.tex_c, tp.t10) * w10 + ld3(a.tex_c, tp.t01) * w01 +
+          ld3(a.tex_c, tp.t11) * w11;
+    f.s = ld3(a.tex_s, tp.t00) * w00 + ld3(a.tex_s, tp.t10) * w10 + ld3(a.tex_s, tp.t01) * w01 +
+          ld3(a.tex_s, tp.t11) * w11;
+    r = a.tex_r[tp.t00] * w00 + a.tex_r[tp.t10] * w10 + a.tex_r[tp.t01] * w01 + a.tex_r[tp.t11] * w11;
+  } else {
+    f.c = ld3(a.diffuse, f.vi[0]) * b0 + ld3(a.diffuse, f.vi[1]) * b1 + ld3(a.diffuse, f.vi[2]) * b2;
+    f.s = ld3(a.specular, f.vi[0]) * b0 + ld3(a.specular, f.vi[1]) * b1 + ld3(a.specular, f.vi[2]) * b2;
+    r = a.roughness[f.vi[0]] * b0 + a.roughness[f.vi[1]] * b1 + a.roughness[f.vi[2]] * b2;
+  }
   f.r_free = r >= kRoughMin && r <= kRoughMax;
   f.r = fminf(fmaxf(r, kRoughMin), kRoughMax);
   f.cos_o = dot(f.ns, f.wo);

@@ -10,7 +10,7 @@
 
 namespace fr {
 
-template <bool DUMP>
+template <bool DUMP, bool TEX>
 __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __restrict__ image, int bid) {
   const int lane = threadIdx.x & 63;
   const Item it = wave_item(a, bid);
@@ -31,7 +31,9 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
     trace<false, DUMP>(a.nodes, a.recs, a.F, sm.ray, ps.valid, -1, h, dummy, it.chunk == 0 ? &st : nullptr);
     const size_t rs = (size_t)ps.pid * a.S + s;
     Frame fr;
-    const bool shaded = ps.valid && h.id >= 0 && shading_frame(a, sm, h, fr);
+    double fxd = 0.0, fyd = 0.0;
+    if (ps.valid && h.id >= 0) film_point(a, ps, s, fxd, fyd);
+    const bool shaded = ps.valid && h.id >= 0 && shading_frame<TEX>(a, sm, h, fr, fxd, fyd);
     if (DUMP && ps.valid && it.chunk == 0) {
       a.dbg_hit[rs] = h.id;
       const bool pf = hit_ambiguous(h) || (h.id >= 0 && fabsf(fr.cos_o) < kFlagCos);
@@ -90,9 +92,9 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
   }
 }
 
-template <bool DUMP>
+template <bool DUMP, bool TEX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_render_fwd(RenderArgs a, float* __restrict__ image) {
-  render_fwd_block<DUMP>(a, image, blockIdx.x);
+  render_fwd_block<DUMP, TEX>(a, image, blockIdx.x);
 }
 
 // image = sum over light chunks of the partial images, in chunk order.
@@ -113,10 +115,16 @@ __global__ __launch_bounds__(256) void k_sum_chunks(const float* __restrict__ pa
 void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const int blocks = wave_blocks_items(a);
   if (e0) (void)hipEventRecord(e0, st);
-  if (a.dbg_hit)
-    hipLaunchKernelGGL(k_render_fwd<true>, dim3(blocks), dim3(256), 0, st, a, image);
-  else
-    hipLaunchKernelGGL(k_render_fwd<false>, dim3(blocks), dim3(256), 0, st, a, image);
+  if (a.M > 0) {
+    if (a.dbg_hit)
+      hipLaunchKernelGGL((k_render_fwd<true, true>), dim3(blocks), dim3(256), 0, st, a, image);
+    else
+      hipLaunchKernelGGL((k_render_fwd<false, true>), dim3(blocks), dim3(256), 0, st, a, image);
+  } else if (a.dbg_hit) {
+    hipLaunchKernelGGL((k_render_fwd<true, false>), dim3(blocks), dim3(256), 0, st, a, image);
+  } else {
+    hipLaunchKernelGGL((k_render_fwd<false, false>), dim3(blocks), dim3(256), 0, st, a, image);
+  }
   if (e1) (void)hipEventRecord(e1, st);
   if (a.n_lchunks > 1) {
     const int n = 3 * a.W * a.H;

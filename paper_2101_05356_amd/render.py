@@ -113,6 +113,15 @@ class DeviceScene:
     seed: int
     step: int = 0
     target: torch.Tensor | None = None
+    # reflectance maps (None: per-vertex reflectance)
+    uv: torch.Tensor | None = None             # [F,3,2]
+    tex_diffuse: torch.Tensor | None = None    # [M,M,3]
+    tex_specular: torch.Tensor | None = None   # [M,M,3]
+    tex_roughness: torch.Tensor | None = None  # [M,M]
+
+    @property
+    def tex_size(self) -> int:
+        return 0 if self.tex_diffuse is None else int(self.tex_diffuse.shape[0])
 
     @property
     def n_lights(self) -> int:
@@ -129,7 +138,10 @@ class DeviceScene:
             light_shape=torch.as_tensor(np.ascontiguousarray(L.shape, np.int32)).to(device),
             cam=_f32(cam, device), fov_y=float(sc.camera.fov_y), W=sc.camera.W, H=sc.camera.H, spp=sc.spp,
             seed=int(sc.seed), step=int(sc.step),
-            target=None if sc.target is None else _f32(sc.target, device))
+            target=None if sc.target is None else _f32(sc.target, device),
+            **({} if getattr(sc, "tex_diffuse", None) is None else dict(
+                uv=_f32(sc.uv, device), tex_diffuse=_f32(sc.tex_diffuse, device),
+                tex_specular=_f32(sc.tex_specular, device), tex_roughness=_f32(sc.tex_roughness, device))))
 
     def struct(self, verts=None) -> FrScene:
         s = FrScene()
@@ -142,6 +154,10 @@ class DeviceScene:
         s.fov_y = self.fov_y
         s.step = self.step
         s.seed = self.seed
+        if self.tex_size > 0:
+            s.tex_size = self.tex_size
+            s.tex_uv, s.tex_diffuse, s.tex_specular, s.tex_roughness = [
+                t.data_ptr() for t in (self.uv, self.tex_diffuse, self.tex_specular, self.tex_roughness)]
         return s
 
 
@@ -201,6 +217,7 @@ def loss(image: torch.Tensor, target: torch.Tensor, smooth: bool = True, want_gr
 
 
 GRAD_GROUPS = ("verts", "normals", "diffuse", "specular", "roughness", "light_geom", "light_rad", "cam")
+TEX_GROUPS = ("tex_diffuse", "tex_specular", "tex_roughness")
 
 
 def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_variant=0, components=3,
@@ -208,12 +225,15 @@ def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_varian
     """Gradients (dict of new tensors) of sum dEdp . image.  `events` (two
     torch.cuda.Event with timing) bracket the interior adjoint kernel."""
     dev = sc.verts.device
-    N, L = mesh.n_verts, sc.n_lights
+    N, L, M = mesh.n_verts, sc.n_lights, sc.tex_size
     shapes = dict(verts=(N, 3), normals=(N, 3), diffuse=(N, 3), specular=(N, 3), roughness=(N,),
-                  light_geom=(L, 9), light_rad=(L, 3), cam=(12,))
+                  light_geom=(L, 9), light_rad=(L, 3), cam=(12,), tex_diffuse=(M, M, 3), tex_specular=(M, M, 3),
+                  tex_roughness=(M, M))
+    if M > 0 and groups is GRAD_GROUPS:
+        groups = tuple(k for k in GRAD_GROUPS if k not in ("diffuse", "specular", "roughness")) + TEX_GROUPS
     out = {k: torch.zeros(shapes[k], dtype=torch.float32, device=dev) for k in groups}
     g = FrGrads()
-    for k in GRAD_GROUPS:
+    for k in GRAD_GROUPS + TEX_GROUPS:
         setattr(g, k, out[k].data_ptr() if k in out else None)
     dbg = None
     ns = sc.W * sc.H if edge_samples == -1 else edge_samples

@@ -435,3 +435,22 @@ def face_render_scene(W: int = 256, H: int = 256, spp: int = 16, n_lights: int =
     return Scene(verts=verts, tris=tris, diffuse=_f32(rng.uniform(0.3, 0.8, (N, 3))),
                  specular=_f32(rng.uniform(0.1, 0.5, (N, 3))), roughness=_f32(rng.uniform(0.2, 0.6, N)),
                  lights=face_lights(n_lights), camera=face_camera(W, H), spp=spp, seed=render_seed, step=step)
+
+
+def large_textured_scene(W: int = 1024, H: int = 1024, spp: int = 64, n_lights: int = 128, n_lon: int = 400,
+                         n_ring: int = 250, M: int = 1024, seed: int = 21, map_seed: int = 9, render_seed: int = 4,
+                         step: int = 0) -> Scene:
+    """Large textured render: the lat-long ellipsoid at 400 x 250 (100,002
+    vertices, 200,000 triangles), per-corner texture coordinates (phi/2pi,
+    theta/pi), M x M diffuse/specular/roughness maps of smooth random fields
+    in the patch ranges, 128 square lights on the Fibonacci sphere, camera at
+    z = 3.5 with a 45 degree field of view, 1024 x 1024 at 64 spp."""
+    sc = face_render_scene(W=W, H=H, spp=spp, n_lights=n_lights, n_lon=n_lon, n_ring=n_ring, seed=seed,
+                           render_seed=render_seed, step=step)
+    return with_maps(sc, latlong_corner_uv(n_lon, n_ring, sc.tris), M, seed=map_seed)
+
+
+def deform_vertices(rng: np.random.Generator, verts: np.ndarray, sigma: float = 2e-3, sweeps: int = 0) -> np.ndarray:
+    """A small random deformation of a mesh: every vertex moved by N(0, sigma^2)
+    along each axis (the per-step vertex motion that forces a BVH refit)."""
+    return _f32(verts + rng.normal(0.0, sigma, verts.shape))

@@ -74,7 +74,13 @@ def pixel_tol_ok(gpu, ref):
     return bool(np.all(err <= tol)), float((err / np.maximum(np.abs(ref), floor)).max())
 
 
-def grad_tol_ok(gpu, ref, rel=1e-4, floor_frac=1e-2):
+def grad_tol_ok(gpu, ref, rel=1e-4, floor_frac=1e-2, mag=None, cond_max=10.0):
+    """L2 and element-wise relative error of a gradient group.  With `mag`
+    (per element, the sum of the magnitudes of the per-pixel terms the
+    element sums), the element-wise bar applies only to elements whose sum is
+    well conditioned (mag <= cond_max * max(|ref|, floor)): an FP32 sum of
+    terms of mixed sign has an error proportional to mag, not to |sum|; the
+    L2 bar covers every element."""
     gpu = np.asarray(gpu, np.float64).ravel()
     ref = np.asarray(ref, np.float64).ravel()
     n = np.linalg.norm(ref)
@@ -82,8 +88,30 @@ def grad_tol_ok(gpu, ref, rel=1e-4, floor_frac=1e-2):
         return bool(np.all(gpu == 0.0)), 0.0, 0.0
     l2 = float(np.linalg.norm(gpu - ref) / n)
     floor = floor_frac * np.abs(ref).max()
-    elem = float((np.abs(gpu - ref) / np.maximum(np.abs(ref), floor)).max())
+    e = np.abs(gpu - ref) / np.maximum(np.abs(ref), floor)
+    if mag is not None:
+        e = e[np.asarray(mag, np.float64).ravel() <= cond_max * np.maximum(np.abs(ref), floor)]
+    elem = float(e.max()) if e.size else 0.0
     return (l2 <= rel and elem <= rel), l2, elem
+
+
+def magnitude_sums(sc, hit, vis, dEdp, groups, pixels=None):
+    """Per gradient element, the sum over pixels of |that pixel's oracle
+    gradient| (the condition of the pixel sum), one oracle call per pixel."""
+    import oracle
+    rows = np.arange(dEdp.shape[0])
+    out = None
+    for i in rows:
+        if not np.any(dEdp[i]) or np.all(np.asarray(hit)[i] < 0):
+            continue
+        d = np.zeros_like(dEdp)
+        d[i] = dEdp[i]
+        g = oracle.grad(sc, hit, vis, d, pixels=pixels, nthreads=1)
+        if out is None:
+            out = {k: np.zeros_like(np.asarray(g[k], np.float64)) for k in groups}
+        for k in groups:
+            out[k] += np.abs(g[k])
+    return out
 
 
 def to_np(t):

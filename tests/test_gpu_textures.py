@@ -1,0 +1,175 @@
+"""Parity of the reflectance-map path with the FP64 oracle, through the C ABI
+(Sec. 3.2: diffuse, specular and roughness as M x M maps read bilinearly at
+the interpolated per-corner texture coordinates): camera and shadow decisions,
+pixels, and the gradients to texels, vertices, lights and camera (interior
+term), the boundary term over a textured surface, and the large workload
+(1024 x 1024, 200,000 triangles, 1024^2 maps, 64 spp, 128 lights) spot-checked
+on a seeded pixel subset.  Tolerances are those of the untextured parity tests
+(gpu_common)."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2101_05356_amd import scenes
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def tilted(sc):
+    from tests.test_oracle_grad import tilt_camera
+    return tilt_camera(sc)
+
+
+def _setup(sc, built_on):
+    """Mesh and device scene; with `built_on` the BVH is built over those
+    vertices and then refit to the scene's own."""
+    if built_on is None:
+        return G.gpu_setup(sc)
+    m = G.R.Mesh(G.ctx(), sc.n_verts, sc.tris)
+    ds = G.R.DeviceScene.from_scene(sc)
+    base = torch.as_tensor(np.ascontiguousarray(built_on, np.float32)).cuda()
+    m.update(base, rebuild=True)
+    m.update(ds.verts, rebuild=False)
+    torch.cuda.synchronize()
+    return m, ds
+
+
+def _parity(sc, pixels=None, seed=3, check_grads=True, built_on=None, conditioned=False, flag_max=5e-3):
+    """Forward decisions and pixels on all pixels (or a subset, indexed on the
+    device so that the full-size dump never leaves it), then the interior
+    adjoint of a random dE/dp on those pixels."""
+    import oracle
+    m, ds = _setup(sc, built_on)
+    W, H, S, L = sc.camera.W, sc.camera.H, sc.spp, sc.lights.count
+    img, hit, pflag, vis = G.R.render_forward(m, ds, dump=True)
+    torch.cuda.synchronize()
+    if pixels is not None:
+        pt = torch.as_tensor(np.asarray(pixels, np.int64), device=hit.device)
+        hit, pflag, vis = hit[pt], pflag[pt], vis[pt]
+    hit, pflag, vis = G.to_np(hit), G.to_np(pflag), G.to_np(vis)
+    img = G.to_np(img).reshape(-1, 3)
+    del m   # keep the dump's device memory bounded across cases
+    assert np.all(hit >= -1) and np.all((vis & 0x7F) <= 3)
+    orc = oracle.render(sc, pixels=pixels)
+    rep, mh, mv = G.decisions_compare(sc, hit, pflag, vis, orc)
+    _note(f"decisions: {rep}")
+    assert rep["hit_mismatch"] == 0 and rep["vis_mismatch"] == 0, rep
+    assert rep["prim_flagged"] < flag_max and rep["shadow_flagged"] < flag_max, rep
+    replay = oracle.render(sc, pixels=pixels, force_hit=mh, force_vis=mv)
+    ok, worst = G.pixel_tol_ok(img if pixels is None else img[pixels], replay["rgb"])
+    _note(f"pixels: worst relative error {worst:.3e}")
+    assert ok, worst
+    if not check_grads:
+        return
+    rng = np.random.default_rng(seed)
+    rows = np.arange(W * H) if pixels is None else np.asarray(pixels)
+    dEdp = np.zeros((H * W, 3), np.float32)
+    dEdp[rows] = rng.normal(size=(len(rows), 3)).astype(np.float32)
+    m, ds = _setup(sc, built_on)
+    groups = ("verts", "normals", "diffuse", "light_geom", "light_rad", "cam") + G.R.TEX_GROUPS
+    g = G.R.render_backward(m, ds, torch.tensor(dEdp.reshape(H, W, 3)).cuda(), groups=groups)
+    torch.cuda.synchronize()
+    go = oracle.grad(sc, mh, mv, dEdp[rows].astype(np.float64), pixels=pixels)
+    pairs = [("verts", "verts"), ("normals", "normals"), ("light_rad", "rad"), ("light_geom", "light"),
+             ("cam", "cam"), ("tex_diffuse", "tex_diffuse"), ("tex_specular", "tex_specular"),
+             ("tex_roughness", "tex_rough")]
+    mag = {}
+    if conditioned:
+        full = dEdp[rows].astype(np.float64)
+        mag = G.magnitude_sums(sc, mh, mv, full, [ok_ for _, ok_ in pairs], pixels=pixels)
+    res = {gk: G.grad_tol_ok(G.to_np(g[gk]), go[ok_], mag=mag.get(ok_)) for gk, ok_ in pairs}
+    _note(f"gradients (ok, l2, worst element): {res}")
+    for k, (ok_, l2, el) in res.items():
+        assert ok_, (k, l2, el)
+    # with maps in use the per-vertex reflectance receives nothing
+    assert not np.any(G.to_np(g["diffuse"]))
+    assert np.abs(go["tex_diffuse"]).sum() > 0 and np.abs(go["tex_rough"]).sum() > 0
+
+
+@pytest.mark.parametrize("M", [16, 64])
+def test_textured_patch_parity(oracle_lib, M):
+    sc = tilted(scenes.patch_scene(W=48, H=48, spp=4))
+    sc = scenes.with_maps(sc, scenes.patch_corner_uv(sc), M, seed=5)
+    _parity(sc)
+
+
+def test_textured_patch_ragged_and_clamped(oracle_lib):
+    """Partial tiles, spp 1 and 32, and texture coordinates reaching past the
+    map on every side (clamped addressing, including the border texels).
+    With so few samples per vertex, some vertex sums cancel to 1/30 of their
+    terms' magnitudes: the element-wise bar applies to the well-conditioned
+    elements (sum of magnitudes at most 10x the sum), the L2 bar to all."""
+    for (W, H, S) in [(37, 23, 1), (13, 11, 32)]:
+        sc = tilted(scenes.patch_scene(W=W, H=H, spp=S))
+        uv = (scenes.patch_corner_uv(sc) - 0.5) * 1.3 + 0.5       # [-0.15, 1.15]
+        sc = scenes.with_maps(sc, uv, 8, seed=7)
+        _note(f"patch {W}x{H} spp {S}")
+        _parity(sc, conditioned=True)
+
+
+def test_textured_face_subset(oracle_lib):
+    """The lat-long face with its seam-unwrapped per-corner coordinates and
+    256^2 maps, on a seeded pixel subset plus silhouette and centre pixels."""
+    sc = scenes.face_render_scene(W=128, H=128, spp=4, n_lights=16)
+    sc = scenes.with_maps(sc, scenes.latlong_corner_uv(200, 140, sc.tris), 256, seed=11)
+    px = scenes.random_pixel_subset(np.random.default_rng(2), 128, 128, 40)
+    px = np.unique(np.concatenate([px, [64 * 128 + 64, 64 * 128 + 15, 30 * 128 + 64]])).astype(np.int32)
+    _parity(sc, pixels=px)
+
+
+def test_textured_edge_term(oracle_lib):
+    """Boundary term over a textured patch: the radiance difference across
+    each silhouette edge is read from the maps on both sides."""
+    import oracle
+    sc = tilted(scenes.patch_scene(W=40, H=40, spp=4))
+    sc = scenes.with_maps(sc, scenes.patch_corner_uv(sc), 32, seed=3)
+    m, ds = G.gpu_setup(sc)
+    w = np.random.default_rng(9).normal(size=(40 * 40, 3)).astype(np.float32)
+    ns = 40 * 40
+    dEdp = torch.tensor(w.reshape(40, 40, 3)).cuda()
+    g = G.R.render_backward(m, ds, dEdp, edge_samples=ns, groups=("cam",), edge_dump=True)
+    ge = G.R.render_backward(m, ds, dEdp, edge_samples=ns, groups=("verts", "cam"))
+    gi = G.R.render_backward(m, ds, dEdp, edge_samples=0, groups=("verts", "cam"))
+    torch.cuda.synchronize()
+    rec, fl = G.to_np(g["edge_rec"]), G.to_np(g["edge_flag"])
+    eo = oracle.edge_grad(sc, w.astype(np.float64), ns)
+    flag = (fl != 0) | (eo["flag"] != 0)
+    _note(f"edge samples: {ns}, flagged {flag.mean():.4f}")
+    assert flag.mean() < 0.01
+    assert np.array_equal(rec[~flag], eo["edge"][~flag])
+    if not flag.any():
+        okv = G.grad_tol_ok(G.to_np(ge["verts"]) - G.to_np(gi["verts"]), eo["verts"], rel=2e-4)
+        okc = G.grad_tol_ok(G.to_np(ge["cam"]) - G.to_np(gi["cam"]), eo["cam"], rel=2e-4)
+        _note(f"edge grads: verts {okv}, cam {okc}")
+        assert okv[1] < 2e-4 and okc[1] < 2e-4
+
+
+def test_large_textured_spot_check(oracle_lib):
+    """The large workload at full size (1024 x 1024, 100,002 vertices, 200,000
+    triangles, 1024^2 maps, 64 spp, 128 lights), after a refit over deformed
+    vertices: decisions, pixels and gradients on 32 seeded pixels (the
+    brute-force oracle traces every triangle: ~1.7e9 tests per pixel).
+    Triangles here span ~5 pixels (vs ~15 in the 256^2 face), so more camera
+    samples fall in the near-edge band: up to 2% may be flagged."""
+    sc0 = scenes.large_textured_scene()
+    sc = dataclasses.replace(sc0, verts=scenes.deform_vertices(np.random.default_rng(1), sc0.verts))
+    px = scenes.random_pixel_subset(np.random.default_rng(4), 1024, 1024, 400)
+    # keep pixels on the face (the oracle's cost is per pixel; misses check
+    # little), chosen by the oracle's own camera rays (one sample, no lights)
+    import oracle
+    lt = sc.lights
+    dark = scenes.Lights(lt.p0[:0], lt.e1[:0], lt.e2[:0], lt.rad[:0], lt.shape[:0])
+    probe = oracle.render(dataclasses.replace(sc, spp=1, lights=dark), pixels=px)
+    on, off = px[probe["hit"][:, 0] >= 0], px[probe["hit"][:, 0] < 0]
+    px = np.sort(np.concatenate([on[:26], off[:6]])).astype(np.int32)
+    _note(f"pixels {px.tolist()}")
+    _parity(sc, pixels=px, built_on=sc0.verts, flag_max=2e-2)
