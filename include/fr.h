@@ -133,7 +133,7 @@ typedef struct {
   int32_t brdf_variant;    /* FR_BRDF_* */
   int32_t components;      /* bit 0 diffuse, bit 1 specular (3 = full BRDF) */
   int32_t edge_samples;    /* boundary-term samples in the backward; 0 = off, -1 = W*H */
-  int32_t light_chunk;     /* lights per work item (0 = library default per pass) */
+  int32_t light_chunk;     /* lights per work item, 0..32 (0 = library default per pass) */
   /* Debug dump of the decisions (device, nullable):
    *   dbg_hit [W*H*spp] int32 closest-hit triangle id per sample (-1 = miss);
    *   dbg_pflag [W*H*spp] uint8 nonzero when that decision is near ambiguous;

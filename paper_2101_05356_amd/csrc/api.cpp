@@ -84,7 +84,8 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
   while ((1 << lg) < P) ++lg;
   a.tile_w = 1 << ((lg + 1) / 2);
   a.tile_h = P / a.tile_w;
-  if (o->light_chunk < 0) return fail(ctx, FR_ERR_INVALID_ARG, "light_chunk must be >= 0");
+  if (o->light_chunk < 0 || o->light_chunk > 32)
+    return fail(ctx, FR_ERR_INVALID_ARG, "light_chunk must be in [0, 32]");
   a.lc = o->light_chunk > 0 ? o->light_chunk : default_chunk;
   a.n_lchunks = std::max(1, (s->n_lights + a.lc - 1) / a.lc);
   a.partial = nullptr;

@@ -20,11 +20,6 @@ namespace fr {
 
 
 
-__device__ __forceinline__ float wave_sum(float x) {
-  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
-}
-
 __device__ __forceinline__ V3 project_out(V3 g, V3 u, float inv_len) {
   // adjoint of u = w / |w|: (g - u (u . g)) / |w|
   const float d = dot(u, g);
@@ -82,19 +77,18 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
       // sample-level adjoint accumulators
       V3 gx = {0, 0, 0}, gns = {0, 0, 0}, gwo = {0, 0, 0}, gc = {0, 0, 0}, gs = {0, 0, 0};
       float gr = 0.0f;
+      // shadow decisions of every light of the chunk, then the adjoint of the visible ones
+      const auto draw = [&](int j) { return philox((uint32_t)ps.pid, (uint32_t)s, 1u + (uint32_t)j, a.step, a.k0, a.k1); };
+      const auto none = [](int, bool, bool, const LightSample&, const HitState&) {};
+      const auto skip = [](int) {};
+      const uint32_t vmask = shadow_mask<false>(a, j0, j1, shaded, fr, h.id, draw, none, skip, nullptr);
       for (int j = j0; j < j1; ++j) {
+        const bool vis = (vmask >> (j - j0)) & 1u;
+        if (!ballot(vis)) continue;
         const LightRec Lj = load_const(a.lights, j);
-        if (!ballot(shaded && light_may_contribute(Lj, fr))) continue;   // culled for the whole wave
+        const U4 r = draw(j);
         LightSample ls;
-        const bool lit = shaded && light_sample(a, ps.pid, s, j, Lj, fr, ls);
-        Ray sr;
-        sr.o = fr.x; sr.d = ls.l; sr.tmin = kShadowTmin; sr.tmax = ls.dist;
-        ray_setup(sr);
-        HitState sh;
-        sh.tamb = 3.4e38f;
-        bool occ = false;
-        trace<true, false>(a.nodes, a.recs, a.F, sr, lit, h.id, sh, occ);
-        const bool vis = lit && !occ;
+        light_point(Lj, unit24(r.x), unit24(r.y), fr, ls);
         float gl12[12];
         for (int k = 0; k < 12; ++k) gl12[k] = 0.0f;
         if (vis) {
@@ -183,11 +177,9 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
           gl12[3] = gdq.x * ls.w1 + ge1n.x; gl12[4] = gdq.y * ls.w1 + ge1n.y; gl12[5] = gdq.z * ls.w1 + ge1n.z;
           gl12[6] = gdq.x * ls.w2 + ge2n.x; gl12[7] = gdq.y * ls.w2 + ge2n.y; gl12[8] = gdq.z * ls.w2 + ge2n.z;
         }
-        if (ballot(vis)) {
-          for (int k = 0; k < 12; ++k) {
-            const float t = wave_sum(gl12[k]);
-            if (lane == 0 && t != 0.0f) atomicAdd(&lds[12 * j + k], to_fix(t));
-          }
+        for (int k = 0; k < 12; ++k) {
+          const float t = wave_sum(gl12[k]);
+          if (lane == 0 && t != 0.0f) atomicAdd(&lds[12 * j + k], to_fix(t));
         }
       }
       // ---- sample-level adjoint: shading frame, intersection, camera

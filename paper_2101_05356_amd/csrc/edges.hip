@@ -158,22 +158,22 @@ __device__ __forceinline__ void side_radiance(const RenderArgs& a, float fx, flo
   const bool shaded = active && h.id >= 0 && shading_frame<TEX>(a, sm, h, fr, (double)fx, (double)fy);
   if (DUMP && active && h.id >= 0 && fabsf(fr.cos_o) < kFlagCos) amb = true;
   L = {0.0f, 0.0f, 0.0f};
+  // shadow decisions of every light of the chunk, then the shading of the visible ones
+  const auto draw = [&](int j) { return philox((uint32_t)k, 0u, PURPOSE_EDGE + 1u + (uint32_t)j, a.step, a.k0, a.k1); };
+  const auto note = [&](int, bool lit, bool, const LightSample& ls, const HitState& sh) {
+    if (shaded && ls.amb) amb = true;
+    if (lit && sh.tamb < 3.0e38f) amb = true;
+  };
+  const auto skip = [](int) {};
+  const uint32_t vmask = shadow_mask<DUMP>(a, j0, j1, shaded, fr, h.id, draw, note, skip, nullptr);
   for (int j = j0; j < j1; ++j) {
+    const bool vis = (vmask >> (j - j0)) & 1u;
+    if (!ballot(vis)) continue;
     const LightRec Lj = load_const(a.lights, j);
-    if (!ballot(shaded && light_may_contribute(Lj, fr))) continue;   // culled for the whole wave
-    const U4 r = philox((uint32_t)k, 0u, PURPOSE_EDGE + 1u + (uint32_t)j, a.step, a.k0, a.k1);
+    const U4 r = draw(j);
     LightSample ls;
-    const bool lit = shaded && light_point(Lj, unit24(r.x), unit24(r.y), fr, ls);
-    if (DUMP && shaded && ls.amb) amb = true;
-    Ray sr;
-    sr.o = fr.x; sr.d = ls.l; sr.tmin = kShadowTmin; sr.tmax = ls.dist;
-    ray_setup(sr);
-    HitState sh;
-    sh.tamb = 3.4e38f;
-    bool occ = false;
-    trace<true, DUMP>(a.nodes, a.recs, a.F, sr, lit, h.id, sh, occ);
-    if (DUMP && lit && sh.tamb < 3.0e38f) amb = true;
-    if (lit && !occ) {
+    light_point(Lj, unit24(r.x), unit24(r.y), fr, ls);
+    if (vis) {
       float f[3], g1f = 0.0f;
       brdf_eval<DUMP>(a.variant, a.components, fr, ls, f, g1f);
       if (DUMP && g1f != 0.0f) amb = true;
@@ -275,8 +275,7 @@ __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const Ed
   }
   if (e.gcam) {
     for (int q = 0; q < 12; ++q) {
-      float t = gcam[q];
-      for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+      const float t = wave_sum(gcam[q]);
       if (lane == 0 && t != 0.0f) fix_add(e.gcam + q, t);
     }
   }

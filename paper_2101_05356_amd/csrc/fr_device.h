@@ -131,6 +131,26 @@ __device__ __forceinline__ float readlane_f(float v, int l) {
 }
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Sum over the 64 lanes of a wave, returned wave-uniform.  Cross-lane moves
+// by DPP (VALU only, no LDS round trip): quad swaps, half-row and row
+// mirrors (every lane of a row then holds the row's sum), then lane 15's
+// row sum added into rows 1 and 3 and lane 31's into rows 2 and 3; lane 63
+// ends with the total.  The order of the additions is fixed (deterministic).
+// All 64 lanes must be active: DPP does not read lanes that EXEC disables.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float x) {
+  return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
+}
+__device__ __forceinline__ float wave_sum(float x) {
+  x = dpp_add<0xb1, 0xf>(x);    // quad_perm [1,0,3,2]
+  x = dpp_add<0x4e, 0xf>(x);    // quad_perm [2,3,0,1]
+  x = dpp_add<0x141, 0xf>(x);   // row_half_mirror
+  x = dpp_add<0x140, 0xf>(x);   // row_mirror
+  x = dpp_add<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+  x = dpp_add<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+  return readlane_f(x, 63);
+}
+
 // ---------------------------------------------------------------------------
 // Rays
 // ---------------------------------------------------------------------------

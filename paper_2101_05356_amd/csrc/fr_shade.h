@@ -285,10 +285,38 @@ __device__ __forceinline__ bool light_may_contribute(const LightRec& Lj, const F
   return !(top < -1e-4f) && !(side < -1e-3f * alen);
 }
 
-__device__ __forceinline__ bool light_sample(const RenderArgs& a, int pid, int s, int j, const LightRec& Lj,
-                                             const Frame& f, LightSample& ls) {
-  const U4 r = philox((uint32_t)pid, (uint32_t)s, 1u + (uint32_t)j, a.step, a.k0, a.k1);
-  return light_point(Lj, unit24(r.x), unit24(r.y), f, ls);
+// Shadow decisions of one shading point for lights [j0, j1) (at most 32
+// lights): bit j - j0 of the result is set when the point drawn on light j
+// (uniforms from draw(j)) passes both cosine tests and no triangle but
+// `self` blocks the segment to it.  The shading that follows draws the same
+// point again from the same counters (bit-identical), so only these bits
+// cross from the traversals to the shading: the two never hold their
+// registers at the same time.  note(j, lit, occ, ls, sh) sees every light a
+// wave traces (debug dumps); skip(j) every light the wave culls as a whole.
+template <bool DUMP, class Draw, class Note, class Skip>
+__device__ __forceinline__ uint32_t shadow_mask(const RenderArgs& a, int j0, int j1, bool shaded, const Frame& fr,
+                                                int self, Draw draw, Note note, Skip skip, TravStats* st) {
+  uint32_t mask = 0;
+  for (int j = j0; j < j1; ++j) {
+    const LightRec Lj = load_const(a.lights, j);
+    if (!ballot(shaded && light_may_contribute(Lj, fr))) {   // culled for the whole wave
+      skip(j);
+      continue;
+    }
+    const U4 r = draw(j);
+    LightSample ls;
+    const bool lit = shaded && light_point(Lj, unit24(r.x), unit24(r.y), fr, ls);
+    Ray sr;
+    sr.o = fr.x; sr.d = ls.l; sr.tmin = kShadowTmin; sr.tmax = ls.dist;
+    ray_setup(sr);
+    HitState sh;
+    sh.tamb = 3.4e38f;
+    bool occ = false;
+    trace<true, DUMP>(a.nodes, a.recs, a.F, sr, lit, self, sh, occ, st);
+    if (lit && !occ) mask |= 1u << (j - j0);
+    if (DUMP) note(j, lit, occ, ls, sh);
+  }
+  return mask;
 }
 
 // ---------------------------------------------------------------------------

@@ -39,34 +39,34 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
       const bool pf = hit_ambiguous(h) || (h.id >= 0 && fabsf(fr.cos_o) < kFlagCos);
       a.dbg_pflag[rs] = pf ? 1 : 0;
     }
-    for (int j = j0; j < j1; ++j) {
-      const LightRec Lj = load_const(a.lights, j);
-      if (!ballot(shaded && light_may_contribute(Lj, fr))) {   // culled for the whole wave
-        if (DUMP && ps.valid) a.dbg_vis[rs * a.L + j] = shaded ? VIS_CULLED : VIS_NONE;
-        continue;
+    // shadow decisions of every light of the chunk, then the shading of the visible ones
+    const auto draw = [&](int j) { return philox((uint32_t)ps.pid, (uint32_t)s, 1u + (uint32_t)j, a.step, a.k0, a.k1); };
+    const auto note = [&](int j, bool lit, bool occ, const LightSample& ls, const HitState& sh) {
+      if (ps.valid) {
+        const uint8_t code = !shaded ? VIS_NONE : (!lit ? VIS_CULLED : (occ ? VIS_OCCLUDED : VIS_VISIBLE));
+        const bool amb = (shaded && ls.amb) || sh.tamb < 3.0e38f;
+        a.dbg_vis[rs * a.L + j] = code | (amb ? VIS_FLAG : 0);
       }
+    };
+    const auto skip = [&](int j) {
+      if (DUMP && ps.valid) a.dbg_vis[rs * a.L + j] = shaded ? VIS_CULLED : VIS_NONE;
+    };
+    const uint32_t vmask = shadow_mask<DUMP>(a, j0, j1, shaded, fr, h.id, draw, note, skip, &st2);
+    for (int j = j0; j < j1; ++j) {
+      const bool vis = (vmask >> (j - j0)) & 1u;
+      if (!ballot(vis)) continue;
+      const LightRec Lj = load_const(a.lights, j);
+      const U4 r = draw(j);
       LightSample ls;
-      const bool lit = shaded && light_sample(a, ps.pid, s, j, Lj, fr, ls);
-      Ray sr;
-      sr.o = fr.x; sr.d = ls.l; sr.tmin = kShadowTmin; sr.tmax = ls.dist;
-      ray_setup(sr);
-      HitState sh;
-      sh.tamb = 3.4e38f;
-      bool occ = false;
-      trace<true, DUMP>(a.nodes, a.recs, a.F, sr, lit, h.id, sh, occ, &st2);
-      float g1flag = 0.0f;
-      if (lit && !occ) {
-        float f[3];
+      light_point(Lj, unit24(r.x), unit24(r.y), fr, ls);
+      if (vis) {
+        float f[3], g1flag = 0.0f;
         brdf_eval<DUMP>(a.variant, a.components, fr, ls, f, g1flag);
         const float w = ls.geom;
         acc[0] += Lj.rad[0] * f[0] * w;
         acc[1] += Lj.rad[1] * f[1] * w;
         acc[2] += Lj.rad[2] * f[2] * w;
-      }
-      if (DUMP && ps.valid) {
-        uint8_t code = !shaded ? VIS_NONE : (!lit ? VIS_CULLED : (occ ? VIS_OCCLUDED : VIS_VISIBLE));
-        const bool amb = (shaded && ls.amb) || sh.tamb < 3.0e38f || g1flag != 0.0f;
-        a.dbg_vis[rs * a.L + j] = code | (amb ? VIS_FLAG : 0);
+        if (DUMP && g1flag != 0.0f) a.dbg_vis[rs * a.L + j] |= VIS_FLAG;
       }
     }
   }
