@@ -397,33 +397,122 @@ void bvh_refit(MeshDev& m, const float* d_verts, hipStream_t st) {
     hipLaunchKernelGGL(k_gather4, dim3(cdiv(4 * m.n4, 256)), dim3(256), 0, st, m.nodes, m.n4_src, m.n4, m.nodes4);
 }
 
-// Collapse the binary tree into the 4-wide traversal tree (host side, once
-// per build): every 4-wide node takes the grandchildren of a binary node
-// (a leaf child takes its slot directly), nodes numbered in depth-first
-// order.  Boxes are filled by k_gather4 at every refit.
-static int bvh_collapse(MeshDev& m, hipStream_t st) {
-  const int F = m.F;
-  m.n4 = 0;
-  m.depth4 = 0;
-  if (F <= 1) return FR_OK;
-  std::vector<BvhNode> bn((size_t)F - 1);
-  if (hipMemcpyAsync(bn.data(), m.nodes, sizeof(BvhNode) * (F - 1), hipMemcpyDeviceToHost, st) != hipSuccess ||
+static int download_nodes(const MeshDev& m, std::vector<BvhNode>& bn, hipStream_t st) {
+  bn.resize((size_t)m.F - 1);
+  if (hipMemcpyAsync(bn.data(), m.nodes, sizeof(BvhNode) * (m.F - 1), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return FR_ERR_DEVICE;
+  return FR_OK;
+}
+
+// Refit schedule of a binary tree (host side, once per build): the nodes
+// whose leaf range spans several refit tiles, grouped by height (children
+// first), for the one-workgroup top pass.
+static int bvh_refit_schedule(MeshDev& m, const std::vector<BvhNode>& bn, hipStream_t st) {
+  const int F = m.F;
   auto child = [&](int b, int s) { return s ? bn[b].c1 : bn[b].c0; };
-  // slots of the 4-wide node made from binary node b: (binary ref, box source)
-  auto slots = [&](int b, int ref[4], int src[4]) {
-    int n = 0;
-    for (int s = 0; s < 2; ++s) {
-      const int c = child(b, s);
-      if (c < 0) { ref[n] = c; src[n] = 2 * b + s; ++n; continue; }
-      for (int t = 0; t < 2; ++t) { ref[n] = child(c, t); src[n] = 2 * c + t; ++n; }
+  std::vector<int> height((size_t)F - 1, 0);   // longest path to a leaf, by a post-order walk
+  std::vector<int> post;
+  post.reserve((size_t)F - 1);
+  std::vector<std::pair<int, int>> st2 = {{0, 0}};
+  while (!st2.empty()) {
+    auto& top = st2.back();
+    const int b = top.first;
+    if (top.second < 2) {
+      const int c = child(b, top.second++);
+      if (c >= 0) st2.push_back({c, 0});
+    } else {
+      int h = 0;
+      for (int q = 0; q < 2; ++q) { const int c = child(b, q); if (c >= 0) h = std::max(h, height[c] + 1); }
+      height[b] = h;
+      post.push_back(b);
+      st2.pop_back();
     }
-    for (int k = n; k < 4; ++k) { ref[k] = kEmpty; src[k] = -1; }
+  }
+  std::vector<std::vector<int>> levels;
+  for (int b : post) {
+    if (bn[b].lo / kRefitTile == bn[b].hi / kRefitTile) continue;   // tile-local
+    const int h = height[b];   // a spanning child has a smaller height: an earlier level
+    if ((int)levels.size() <= h) levels.resize(h + 1);
+    levels[h].push_back(b);
+  }
+  std::vector<int32_t> top, off = {0};
+  for (auto& lv : levels) {
+    if (lv.empty()) continue;
+    top.insert(top.end(), lv.begin(), lv.end());
+    off.push_back((int32_t)top.size());
+  }
+  const int nt = (int)top.size();
+  if (nt > m.top_cap) {
+    if (m.top_nodes) (void)hipFree(m.top_nodes);
+    if (m.top_level_off) (void)hipFree(m.top_level_off);
+    m.top_nodes = nullptr; m.top_level_off = nullptr; m.top_cap = 0;
+    if (hipMalloc(&m.top_nodes, sizeof(int32_t) * std::max(nt, 1)) != hipSuccess) return FR_ERR_OOM;
+    if (hipMalloc(&m.top_level_off, sizeof(int32_t) * (std::max(nt, 1) + 1)) != hipSuccess) return FR_ERR_OOM;
+    m.top_cap = nt;
+  }
+  if (nt > 0 &&
+      (hipMemcpyAsync(m.top_nodes, top.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice, st) != hipSuccess ||
+       hipMemcpyAsync(m.top_level_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, st) !=
+           hipSuccess ||
+       hipStreamSynchronize(st) != hipSuccess))
+    return FR_ERR_DEVICE;
+  m.n_top = nt;
+  m.n_top_levels = (int)off.size() - 1;
+  return FR_OK;
+}
+
+// Collapse the binary tree (with its boxes from a first refit) into the
+// 4-wide traversal tree, host side, once per build.  Each 4-wide node starts
+// from the two children of a binary node and repeatedly opens the internal
+// child of largest surface area (the one a random ray is likeliest to enter)
+// until it holds four children or only leaves; nodes are numbered in
+// depth-first order.  Boxes are filled by k_gather4 at every refit, each
+// slot from the binary box it was made of (parent node, side).
+static int bvh_collapse(MeshDev& m, const std::vector<BvhNode>& bn, hipStream_t st) {
+  const int F = m.F;
+  auto child = [&](int b, int s) { return s ? bn[b].c1 : bn[b].c0; };
+  // parent and side of every internal node and leaf
+  std::vector<int> par_i((size_t)F - 1, -1), par_l((size_t)F, -1);
+  for (int b = 0; b < F - 1; ++b)
+    for (int sd = 0; sd < 2; ++sd) {
+      const int c = child(b, sd);
+      if (c >= 0) par_i[c] = 2 * b + sd;
+      else par_l[~c] = 2 * b + sd;
+    }
+  auto src_of = [&](int ref) { return ref >= 0 ? par_i[ref] : par_l[~ref]; };
+  auto area_of = [&](int ref) {
+    const int ps = src_of(ref);
+    const float* b = (ps & 1) ? bn[ps >> 1].b1 : bn[ps >> 1].b0;
+    const float dx = std::max(b[3] - b[0], 0.0f), dy = std::max(b[4] - b[1], 0.0f), dz = std::max(b[5] - b[2], 0.0f);
+    return dx * dy + dy * dz + dz * dx;
+  };
+  // children of the 4-wide node made from binary node b
+  auto slots = [&](int b, int ref[4]) {
+    int n = 2;
+    ref[0] = child(b, 0);
+    ref[1] = child(b, 1);
+    while (n < 4) {
+      int best = -1;
+      float ba = -1.0f;
+      for (int k = 0; k < n; ++k)
+        if (ref[k] >= 0) {
+          const float a = area_of(ref[k]);
+          if (a > ba) { ba = a; best = k; }
+        }
+      if (best < 0) break;
+      const int c = ref[best];
+      for (int k = n; k > best + 1; --k) ref[k] = ref[k - 1];
+      ref[best] = child(c, 0);
+      ref[best + 1] = child(c, 1);
+      ++n;
+    }
+    for (int k = n; k < 4; ++k) ref[k] = kEmpty;
     return n;
   };
   // depth-first numbering
-  std::vector<int> id((size_t)F - 1, -1), order, depth;
+  m.depth4 = 0;
+  std::vector<int> id((size_t)F - 1, -1), order;
   std::vector<int> todo = {0}, tdepth = {1};
   while (!todo.empty()) {
     const int b = todo.back(), d = tdepth.back();
@@ -431,76 +520,25 @@ static int bvh_collapse(MeshDev& m, hipStream_t st) {
     id[b] = (int)order.size();
     order.push_back(b);
     m.depth4 = std::max(m.depth4, d);
-    int ref[4], src[4];
-    const int n = slots(b, ref, src);
+    int ref[4];
+    const int n = slots(b, ref);
     for (int k = n - 1; k >= 0; --k)
       if (ref[k] >= 0) { todo.push_back(ref[k]); tdepth.push_back(d + 1); }
-  }
-  // spanning nodes of the tile-local refit, by height (children first)
-  {
-    std::vector<int> height((size_t)F - 1, 0);   // longest path to a leaf, by a post-order walk
-    std::vector<int> post;
-    post.reserve((size_t)F - 1);
-    std::vector<std::pair<int, int>> st2 = {{0, 0}};
-    while (!st2.empty()) {
-      auto& top = st2.back();
-      const int b = top.first;
-      if (top.second < 2) {
-        const int c = child(b, top.second++);
-        if (c >= 0) st2.push_back({c, 0});
-      } else {
-        int h = 0;
-        for (int q = 0; q < 2; ++q) { const int c = child(b, q); if (c >= 0) h = std::max(h, height[c] + 1); }
-        height[b] = h;
-        post.push_back(b);
-        st2.pop_back();
-      }
-    }
-    std::vector<std::vector<int>> levels;
-    for (int b : post) {
-      if (bn[b].lo / kRefitTile == bn[b].hi / kRefitTile) continue;   // tile-local
-      const int h = height[b];   // a spanning child has a smaller height: an earlier level
-      if ((int)levels.size() <= h) levels.resize(h + 1);
-      levels[h].push_back(b);
-    }
-    std::vector<int32_t> top, off = {0};
-    for (auto& lv : levels) {
-      if (lv.empty()) continue;
-      top.insert(top.end(), lv.begin(), lv.end());
-      off.push_back((int32_t)top.size());
-    }
-    const int nt = (int)top.size();
-    if (nt > m.top_cap) {
-      if (m.top_nodes) (void)hipFree(m.top_nodes);
-      if (m.top_level_off) (void)hipFree(m.top_level_off);
-      m.top_nodes = nullptr; m.top_level_off = nullptr; m.top_cap = 0;
-      if (hipMalloc(&m.top_nodes, sizeof(int32_t) * std::max(nt, 1)) != hipSuccess) return FR_ERR_OOM;
-      if (hipMalloc(&m.top_level_off, sizeof(int32_t) * (std::max(nt, 1) + 1)) != hipSuccess) return FR_ERR_OOM;
-      m.top_cap = nt;
-    }
-    if (nt > 0 &&
-        (hipMemcpyAsync(m.top_nodes, top.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice, st) != hipSuccess ||
-         hipMemcpyAsync(m.top_level_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, st) !=
-             hipSuccess ||
-         hipStreamSynchronize(st) != hipSuccess))
-      return FR_ERR_DEVICE;
-    m.n_top = nt;
-    m.n_top_levels = (int)off.size() - 1;
   }
   const int n4 = (int)order.size();
   std::vector<Bvh4Node> h4((size_t)n4);
   std::vector<int32_t> hsrc((size_t)4 * n4);
   for (int i = 0; i < n4; ++i) {
-    int ref[4], src[4];
-    slots(order[i], ref, src);
+    int ref[4];
+    slots(order[i], ref);
     Bvh4Node& nd = h4[i];
     std::memset(&nd, 0, sizeof(nd));
     for (int k = 0; k < 4; ++k) {
-      nd.c[k] = ref[k] >= 0 ? id[ref[k]] : ref[k];
+      nd.c[k] = ref[k] == kEmpty ? kEmpty : (ref[k] >= 0 ? id[ref[k]] : ref[k]);
       int sub = 0;
-      if (ref[k] >= 0) { int r2[4], s2[4]; sub = slots(ref[k], r2, s2); }
+      if (ref[k] >= 0 && ref[k] != kEmpty) { int r2[4]; sub = slots(ref[k], r2); }
       nd.nsub[k] = sub;
-      hsrc[(size_t)4 * i + k] = src[k];
+      hsrc[(size_t)4 * i + k] = ref[k] == kEmpty ? -1 : src_of(ref[k]);
     }
   }
   if (n4 > m.n4_cap) {
@@ -552,8 +590,19 @@ int bvh_build(MeshDev& m, const float* d_verts, hipStream_t st, int* depth_out) 
   if (hipMemcpyAsync(chk, m.depth, sizeof(chk), hipMemcpyDeviceToHost, st) != hipSuccess) return FR_ERR_DEVICE;
   if (hipStreamSynchronize(st) != hipSuccess) return FR_ERR_DEVICE;
   if (chk[1] != 0) return FR_ERR_LIMIT;
-  const int rc = bvh_collapse(m, st);
-  if (rc != FR_OK) return rc;
+  m.n4 = 0;
+  m.depth4 = 0;
+  m.n_top = 0;
+  m.n_top_levels = 0;
+  if (F > 1) {
+    // topology -> refit schedule -> binary boxes -> 4-wide collapse -> 4-wide boxes
+    std::vector<BvhNode> bn;
+    int rc = download_nodes(m, bn, st);
+    if (rc == FR_OK) rc = bvh_refit_schedule(m, bn, st);
+    if (rc != FR_OK) return rc;
+    bvh_refit(m, d_verts, st);
+    if ((rc = download_nodes(m, bn, st)) != FR_OK || (rc = bvh_collapse(m, bn, st)) != FR_OK) return rc;
+  }
   bvh_refit(m, d_verts, st);
   hipLaunchKernelGGL(k_leaf_depth, dim3(cdiv(F, 256)), dim3(256), 0, st, m.node_parent, m.leaf_parent, F, m.depth);
   int32_t depth = 0;
