@@ -44,7 +44,7 @@ enum {
 };
 
 /* Mesh update modes of fr_mesh_update. */
-enum { FR_REFIT = 0, FR_REBUILD = 1 };
+enum { FR_REFIT = 0, FR_REBUILD = 1, FR_REBUILD_SAH = 2 };
 
 /* Light shapes. */
 enum { FR_LIGHT_PARALLELOGRAM = 0, FR_LIGHT_TRIANGLE = 1 };
@@ -75,11 +75,15 @@ int fr_mesh_destroy(fr_mesh* mesh);
 
 /* Per-step geometry pass over world-space positions d_verts [N*3]:
  * area-weighted vertex normals (the normal at each vertex, Sec. 3.2), then
- * the BVH: FR_REBUILD builds it (Morton codes, radix sort, binary radix tree,
- * bottom-up boxes) and SYNCHRONISES once to check its depth; FR_REFIT keeps
- * the last built topology and recomputes boxes only (no synchronisation).
- * The first update of a mesh must be FR_REBUILD.  d_verts must stay unchanged
- * until the renders that use this update have run. */
+ * the BVH.  FR_REBUILD builds it on the GPU (Morton codes, radix sort, binary
+ * radix tree, bottom-up boxes); FR_REBUILD_SAH builds it on the host with a
+ * binned surface-area heuristic (copies the vertices and triangles to the
+ * host; a slower build, a tree that traversal visits less); both then
+ * collapse it to the 4-wide traversal tree and SYNCHRONISE to check its
+ * depth.  FR_REFIT keeps the last built topology and recomputes boxes only
+ * (no synchronisation).  The first update of a mesh must be a rebuild.
+ * d_verts must stay unchanged until the renders that use this update have
+ * run. */
 int fr_mesh_update(fr_mesh* mesh, const float* d_verts, int mode, fr_stream stream);
 
 /* Device pointer to the mesh's current vertex normals [N*3] (valid after an

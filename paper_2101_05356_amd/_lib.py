@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libfr.so")
 
 FR_OK, FR_ERR_INVALID_ARG, FR_ERR_SHAPE, FR_ERR_OOM, FR_ERR_BUDGET = 0, 1, 2, 3, 4
 FR_ERR_DEVICE, FR_ERR_NONFINITE, FR_ERR_LIMIT, FR_ERR_NOT_FOUND = 5, 6, 7, 8
-FR_REFIT, FR_REBUILD = 0, 1
+FR_REFIT, FR_REBUILD, FR_REBUILD_SAH = 0, 1, 2
 FR_BRDF_PRINTED, FR_BRDF_NORMALIZED = 0, 1
 
 P = ctypes.c_void_p

@@ -254,13 +254,14 @@ int fr_mesh_destroy(fr_mesh* m) {
 int fr_mesh_update(fr_mesh* m, const float* d_verts, int mode, fr_stream stream) {
   if (!m || !d_verts) return FR_ERR_INVALID_ARG;
   fr_ctx* ctx = m->ctx;
-  if (mode != FR_REFIT && mode != FR_REBUILD) return fail(ctx, FR_ERR_INVALID_ARG, "bad mode");
+  if (mode != FR_REFIT && mode != FR_REBUILD && mode != FR_REBUILD_SAH)
+    return fail(ctx, FR_ERR_INVALID_ARG, "bad mode");
   if (mode == FR_REFIT && !m->d.built) return fail(ctx, FR_ERR_INVALID_ARG, "refit before the first build");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   fr::launch_normals(m->d, d_verts, st);
-  if (mode == FR_REBUILD) {
+  if (mode != FR_REFIT) {
     int depth = 0;
-    const int rc = fr::bvh_build(m->d, d_verts, st, &depth);
+    const int rc = fr::bvh_build(m->d, d_verts, st, mode == FR_REBUILD_SAH, &depth);
     if (rc != FR_OK) { m->d.built = 0; return fail(ctx, rc, "BVH build failed (device error or invalid topology)"); }
     m->d.bvh_depth = depth;
     // the 4-wide traversal pushes at most three entries per level
@@ -634,7 +635,7 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   fr::launch_blend(md->mean_geo, md->basis_geo, J.param, md->K_geo, M, J.v_obj, st);
   fr::launch_blend(md->mean_alb, md->basis_alb, J.param + md->K_geo, md->K_alb, M, J.diffuse, st);
   fr::launch_pose(J.v_obj, N, J.param + md->K_geo + md->K_alb, J.v_w, st);
-  rc = fr_mesh_update(jh->mesh, J.v_w, FR_REBUILD, stream);
+  rc = fr_mesh_update(jh->mesh, J.v_w, FR_REBUILD_SAH, stream);
   if (rc != FR_OK) { fr_mesh_destroy(jh->mesh); (void)hipFree(jh->arena); delete jh; return rc; }
   // render views
   fr_scene sc{};

@@ -5,9 +5,13 @@
 // order) -> binary radix tree over the sorted codes (Karras, HPG 2012, with
 // the index as tie-break for equal codes) -> bottom-up boxes.
 // Refit: the bottom-up box pass alone, over the last built topology.
+// Alternative build (FR_REBUILD_SAH): a binned surface-area-heuristic tree
+// built on the host, numbered like a binary radix tree so that the same
+// refit, collapse and traversal apply.
 //
 // A boundary-to-root walk per leaf gives the depth; the traversal stack is 64
 // entries, so trees deeper than that are rejected by the host.
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -557,8 +561,139 @@ static int bvh_collapse(MeshDev& m, const std::vector<BvhNode>& bn, hipStream_t 
   return FR_OK;
 }
 
-int bvh_build(MeshDev& m, const float* d_verts, hipStream_t st, int* depth_out) {
+// Binned SAH build on the host (Wald, "On fast construction of SAH-based
+// bounding volume hierarchies", 2007): at each node, 32 centroid bins per
+// axis, the split between bins that minimises A(left) N(left) + A(right)
+// N(right) (A the box surface area), a median split by index when all
+// centroids coincide.  Each node covers a contiguous range [lo, hi] of the
+// leaf order; numbering as in a binary radix tree: the root is 0, the child
+// ranges [lo, s] and [s + 1, hi] of a split after slot s get the indices s
+// and s + 1 (a one-leaf range is the leaf ~slot).  Every internal index is
+// then one end of its node's range and the F - 1 internal nodes take the
+// indices 0 .. F - 2 exactly once, which the refit relies on.
+static int bvh_build_sah_host(MeshDev& m, const float* d_verts, hipStream_t st) {
+  const int F = m.F, N = m.N;
+  std::vector<float> v((size_t)3 * N);
+  std::vector<int32_t> t((size_t)3 * F);
+  if (hipMemcpyAsync(v.data(), d_verts, sizeof(float) * 3 * N, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(t.data(), m.tris, sizeof(int32_t) * 3 * F, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return FR_ERR_DEVICE;
+  std::vector<float> pb((size_t)6 * F), pc((size_t)3 * F);
+  for (int f = 0; f < F; ++f) {
+    for (int a = 0; a < 3; ++a) {
+      const float x0 = v[3 * t[3 * f] + a], x1 = v[3 * t[3 * f + 1] + a], x2 = v[3 * t[3 * f + 2] + a];
+      pb[6 * f + a] = std::min(x0, std::min(x1, x2));
+      pb[6 * f + 3 + a] = std::max(x0, std::max(x1, x2));
+      pc[3 * f + a] = (x0 + x1 + x2) * (1.0f / 3.0f);
+    }
+  }
+  std::vector<int32_t> idx((size_t)F), npar((size_t)F - 1, -1), lpar((size_t)F, -1);
+  for (int f = 0; f < F; ++f) idx[f] = f;
+  std::vector<BvhNode> nodes((size_t)F - 1);
+  std::memset(nodes.data(), 0, sizeof(BvhNode) * nodes.size());
+  constexpr int B = 32;
+  struct Task { int lo, hi, id, parent; };
+  std::vector<Task> todo = {{0, F - 1, 0, -1}};
+  auto area = [](const float* b) {
+    const float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
+    return dx * dy + dy * dz + dz * dx;
+  };
+  auto grow = [](float* b, const float* c) {
+    for (int a = 0; a < 3; ++a) { b[a] = std::min(b[a], c[a]); b[3 + a] = std::max(b[3 + a], c[3 + a]); }
+  };
+  while (!todo.empty()) {
+    const Task tk = todo.back();
+    todo.pop_back();
+    const int lo = tk.lo, hi = tk.hi, n = hi - lo + 1;
+    float cmin[3] = {3.4e38f, 3.4e38f, 3.4e38f}, cmax[3] = {-3.4e38f, -3.4e38f, -3.4e38f};
+    for (int i = lo; i <= hi; ++i)
+      for (int a = 0; a < 3; ++a) {
+        cmin[a] = std::min(cmin[a], pc[3 * idx[i] + a]);
+        cmax[a] = std::max(cmax[a], pc[3 * idx[i] + a]);
+      }
+    double best = 1e300;
+    int bax = -1, bbin = -1;
+    for (int a = 0; a < 3; ++a) {
+      const float ext = cmax[a] - cmin[a];
+      if (!(ext > 0.0f)) continue;
+      const float sc = (float)B / ext;
+      int cnt[B] = {};
+      float bb[B][6];
+      for (int k = 0; k < B; ++k) { bb[k][0] = bb[k][1] = bb[k][2] = 3.4e38f; bb[k][3] = bb[k][4] = bb[k][5] = -3.4e38f; }
+      for (int i = lo; i <= hi; ++i) {
+        const int f = idx[i];
+        const int k = std::min(B - 1, (int)((pc[3 * f + a] - cmin[a]) * sc));
+        ++cnt[k];
+        grow(bb[k], &pb[6 * f]);
+      }
+      double la[B], ra[B];
+      int ln[B], rn[B];
+      float acc[6] = {3.4e38f, 3.4e38f, 3.4e38f, -3.4e38f, -3.4e38f, -3.4e38f};
+      int c = 0;
+      for (int k = 0; k < B - 1; ++k) {
+        if (cnt[k]) grow(acc, bb[k]);
+        c += cnt[k];
+        ln[k] = c;
+        la[k] = c ? area(acc) : 0.0;
+      }
+      float acc2[6] = {3.4e38f, 3.4e38f, 3.4e38f, -3.4e38f, -3.4e38f, -3.4e38f};
+      c = 0;
+      for (int k = B - 1; k > 0; --k) {
+        if (cnt[k]) grow(acc2, bb[k]);
+        c += cnt[k];
+        rn[k - 1] = c;
+        ra[k - 1] = c ? area(acc2) : 0.0;
+      }
+      for (int k = 0; k < B - 1; ++k) {
+        if (ln[k] == 0 || rn[k] == 0) continue;
+        const double cost = la[k] * ln[k] + ra[k] * rn[k];
+        if (cost < best) { best = cost; bax = a; bbin = k; }
+      }
+    }
+    int mid;   // left = [lo, mid], right = [mid + 1, hi]
+    if (bax < 0) {
+      mid = lo + n / 2 - 1;
+    } else {
+      const float sc = (float)B / (cmax[bax] - cmin[bax]);
+      const float c0 = cmin[bax];
+      auto it = std::partition(idx.begin() + lo, idx.begin() + hi + 1, [&](int f) {
+        return std::min(B - 1, (int)((pc[3 * f + bax] - c0) * sc)) <= bbin;
+      });
+      mid = (int)(it - idx.begin()) - 1;
+    }
+    BvhNode& nd = nodes[tk.id];
+    nd.lo = lo;
+    nd.hi = hi;
+    nd.c0 = mid == lo ? ~lo : mid;
+    nd.c1 = mid + 1 == hi ? ~hi : mid + 1;
+    npar[tk.id] = tk.parent;
+    if (nd.c0 < 0) lpar[lo] = tk.id; else todo.push_back({lo, mid, mid, tk.id});
+    if (nd.c1 < 0) lpar[hi] = tk.id; else todo.push_back({mid + 1, hi, mid + 1, tk.id});
+  }
+  // structural check: every internal index and leaf slot has exactly one parent
+  for (int i = 1; i < F - 1; ++i)
+    if (npar[i] < 0) return FR_ERR_LIMIT;
+  for (int i = 0; i < F; ++i)
+    if (lpar[i] < 0) return FR_ERR_LIMIT;
+  if (hipMemcpyAsync(m.nodes, nodes.data(), sizeof(BvhNode) * (F - 1), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(m.order, idx.data(), sizeof(int32_t) * F, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(m.node_parent, npar.data(), sizeof(int32_t) * (F - 1), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(m.leaf_parent, lpar.data(), sizeof(int32_t) * F, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return FR_ERR_DEVICE;
+  return FR_OK;
+}
+
+static int bvh_finish(MeshDev& m, const float* d_verts, hipStream_t st, int* depth_out);
+
+int bvh_build(MeshDev& m, const float* d_verts, hipStream_t st, bool sah, int* depth_out) {
   const int F = m.F;
+  if (sah && F > 1) {
+    const int rc = bvh_build_sah_host(m, d_verts, st);
+    if (rc != FR_OK) return rc;
+    return bvh_finish(m, d_verts, st, depth_out);
+  }
   const int nparts = 64;
   hipLaunchKernelGGL(k_centroid_bounds, dim3(nparts), dim3(256), 0, st, d_verts, m.tris, F, m.partial);
   hipLaunchKernelGGL(k_morton, dim3(cdiv(F, 256)), dim3(256), 0, st, d_verts, m.tris, F, m.partial, nparts,
@@ -590,6 +725,13 @@ int bvh_build(MeshDev& m, const float* d_verts, hipStream_t st, int* depth_out) 
   if (hipMemcpyAsync(chk, m.depth, sizeof(chk), hipMemcpyDeviceToHost, st) != hipSuccess) return FR_ERR_DEVICE;
   if (hipStreamSynchronize(st) != hipSuccess) return FR_ERR_DEVICE;
   if (chk[1] != 0) return FR_ERR_LIMIT;
+  return bvh_finish(m, d_verts, st, depth_out);
+}
+
+// After either build: refit schedule, binary boxes, 4-wide collapse, 4-wide
+// boxes, depth.
+static int bvh_finish(MeshDev& m, const float* d_verts, hipStream_t st, int* depth_out) {
+  const int F = m.F;
   m.n4 = 0;
   m.depth4 = 0;
   m.n_top = 0;
@@ -604,6 +746,7 @@ int bvh_build(MeshDev& m, const float* d_verts, hipStream_t st, int* depth_out) 
     if ((rc = download_nodes(m, bn, st)) != FR_OK || (rc = bvh_collapse(m, bn, st)) != FR_OK) return rc;
   }
   bvh_refit(m, d_verts, st);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t*>(m.depth), 1);
   hipLaunchKernelGGL(k_leaf_depth, dim3(cdiv(F, 256)), dim3(256), 0, st, m.node_parent, m.leaf_parent, F, m.depth);
   int32_t depth = 0;
   if (hipMemcpyAsync(&depth, m.depth, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess) return FR_ERR_DEVICE;

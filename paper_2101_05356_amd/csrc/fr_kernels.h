@@ -153,7 +153,7 @@ struct RenderArgs {
 };
 
 // bvh.hip
-int bvh_build(MeshDev& m, const float* d_verts, hipStream_t st, int* depth_out);
+int bvh_build(MeshDev& m, const float* d_verts, hipStream_t st, bool sah, int* depth_out);
 void bvh_refit(MeshDev& m, const float* d_verts, hipStream_t st);
 // model.hip
 void launch_normals(MeshDev& m, const float* d_verts, hipStream_t st);

@@ -70,11 +70,13 @@ class Mesh:
             _lib._lib.fr_mesh_destroy(self.h)
             self.h = None
 
-    def update(self, verts: torch.Tensor, rebuild: bool = False):
-        """Normals + BVH over world positions verts [N,3] (kept alive by the mesh)."""
+    def update(self, verts: torch.Tensor, rebuild: bool = False, builder: str = "sah"):
+        """Normals + BVH over world positions verts [N,3] (kept alive by the mesh).
+        A rebuild uses the host SAH builder ("sah") or the GPU LBVH ("lbvh")."""
         assert verts.dtype == torch.float32 and verts.is_contiguous() and verts.numel() == 3 * self.n_verts
+        assert builder in ("sah", "lbvh")
         self._verts = verts
-        mode = _lib.FR_REBUILD if rebuild else _lib.FR_REFIT
+        mode = (_lib.FR_REBUILD_SAH if builder == "sah" else _lib.FR_REBUILD) if rebuild else _lib.FR_REFIT
         check(lib().fr_mesh_update(self.h, _p(verts), mode, _stream()), self.ctx.h, "fr_mesh_update")
 
     def normals(self) -> torch.Tensor:

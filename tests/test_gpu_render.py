@@ -136,6 +136,35 @@ def test_refit_matches_rebuild(oracle_lib):
     assert 0 < m.bvh_depth <= 64
 
 
+def test_tree_builders_agree_bit_for_bit(oracle_lib):
+    """Traversal results do not depend on the tree: the GPU LBVH and the host
+    SAH tree (each also refit over moved vertices) give bit-identical images,
+    decision dumps and gradients on the face."""
+    sc = scenes.face_render_scene(W=64, H=64, spp=4, n_lights=12)
+    rng = np.random.default_rng(3)
+    moved = (sc.verts + rng.normal(0, 2e-3, sc.verts.shape)).astype(np.float32)
+    dEdp = torch.tensor(rng.normal(size=(64, 64, 3)).astype(np.float32)).cuda()
+    outs = []
+    for builder in ("lbvh", "sah"):
+        for refit in (False, True):
+            m = G.R.Mesh(G.ctx(), sc.n_verts, sc.tris)
+            ds = G.R.DeviceScene.from_scene(sc)
+            v = torch.tensor(moved).cuda()
+            if refit:
+                m.update(ds.verts, rebuild=True, builder=builder)
+                m.update(v, rebuild=False)
+            else:
+                m.update(v, rebuild=True, builder=builder)
+            img, hit, pflag, vis = G.R.render_forward(m, ds, verts=v, dump=True)
+            g = G.R.render_backward(m, ds, dEdp, verts=v, edge_samples=-1)
+            torch.cuda.synchronize()
+            assert 0 < m.bvh_depth <= 64
+            outs.append([G.to_np(x) for x in (img, hit, pflag, vis)] + [G.to_np(g[k]) for k in sorted(g)])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
 def test_edge_term_parity_patch(oracle_lib):
     import oracle
     sc = scenes.patch_scene(W=48, H=48, spp=4)
