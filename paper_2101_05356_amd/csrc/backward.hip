@@ -351,7 +351,7 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
 }
 
 template <bool TEX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_render_bwd(RenderArgs a, const float* __restrict__ dEdp, FixGrads g,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_render_bwd(RenderArgs a, const float* __restrict__ dEdp, FixGrads g,
                                                     fix_t* __restrict__ slots) {
   render_bwd_block<TEX>(a, dEdp, g, slots, blockIdx.x);
 }
