@@ -89,6 +89,7 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
   a.lc = o->light_chunk > 0 ? o->light_chunk : default_chunk;
   a.n_lchunks = std::max(1, (s->n_lights + a.lc - 1) / a.lc);
   a.partial = nullptr;
+  a.prim = nullptr;   // set by the caller (ensure_prim, or a job's own buffer)
   a.tiles_x = (a.W + a.tile_w - 1) / a.tile_w;
   a.tiles_y = (a.H + a.tile_h - 1) / a.tile_h;
   a.n_tiles = a.tiles_x * a.tiles_y;
@@ -244,7 +245,7 @@ int fr_mesh_destroy(fr_mesh* m) {
   void* ptrs[] = {d.tris, d.vf_off, d.vf_idx, d.normals, d.nlen, d.gnorm, d.edges, d.edge_faces, d.nodes, d.recs,
                   d.order, d.node_parent, d.leaf_parent, d.flags, d.keys[0], d.keys[1], d.vals[0], d.vals[1],
                   d.hist, d.partial, d.scene_box, d.depth, d.lights, d.ltmp, d.edge_len, d.edge_cdf, d.face_front,
-                  d.scan_part, d.img_partial, d.acc, d.tex_acc, d.slots, d.nodes4, d.n4_src, d.top_nodes, d.top_level_off, m->loss_scratch, m->loss_gtmp};
+                  d.scan_part, d.img_partial, d.prim, d.acc, d.tex_acc, d.slots, d.nodes4, d.n4_src, d.top_nodes, d.top_level_off, m->loss_scratch, m->loss_gtmp};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -289,6 +290,20 @@ int32_t fr_mesh_edges(const fr_mesh* m, int32_t* h_edges, int32_t* h_faces) {
 
 int32_t fr_mesh_bvh_depth(const fr_mesh* m) { return m ? m->d.bvh_depth : -1; }
 
+// The mesh's primary-hit buffer, grown to the call's W*H*S samples.
+int ensure_prim(fr_mesh* m, fr::RenderArgs& a) {
+  const size_t need = (size_t)a.W * a.H * a.S;
+  if (need > m->d.prim_cap) {
+    if (m->d.prim) (void)hipFree(m->d.prim);
+    m->d.prim = nullptr;
+    m->d.prim_cap = 0;
+    if (dalloc(&m->d.prim, need) != hipSuccess) return fail(m->ctx, FR_ERR_OOM, "primary-hit buffer allocation failed");
+    m->d.prim_cap = need;
+  }
+  a.prim = m->d.prim;
+  return FR_OK;
+}
+
 int fr_render_forward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, float* d_image, fr_stream stream) {
   if (!m || !d_image) return FR_ERR_INVALID_ARG;
   fr::RenderArgs a;
@@ -298,6 +313,7 @@ int fr_render_forward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fl
   if (any_dbg && !(o->dbg_hit && o->dbg_pflag && o->dbg_vis))
     return fail(m->ctx, FR_ERR_INVALID_ARG, "the forward dump needs dbg_hit, dbg_pflag and dbg_vis");
   if ((rc = ensure_lights(m, s->n_lights)) != FR_OK) return rc;
+  if ((rc = ensure_prim(m, a)) != FR_OK) return rc;
   a.lights = m->d.lights;
   if (a.n_lchunks > 1) {
     const size_t need = (size_t)a.n_lchunks * 3 * a.W * a.H;
@@ -350,6 +366,7 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
     return fail(m->ctx, FR_ERR_INVALID_ARG, "the backward dump takes dbg_hit and dbg_pflag only");
   a.dbg_hit = nullptr; a.dbg_pflag = nullptr; a.dbg_vis = nullptr; a.dbg_stats = nullptr;
   if ((rc = ensure_lights(m, s->n_lights)) != FR_OK) return rc;
+  if ((rc = ensure_prim(m, a)) != FR_OK) return rc;
   a.lights = m->d.lights;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   fr::MeshDev& d = m->d;
@@ -496,6 +513,7 @@ void layout_job(Carver& c, const fr_model* md, const fr_job_desc* d, fr::JobDev&
   J.image = c.take<float>(px3); J.dEdp = c.take<float>(px3); J.gsign = c.take<float>(px3);
   J.target = c.take<float>(px3);
   J.ra.partial = n_lchunks > 1 ? c.take<float>(px3 * n_lchunks) : nullptr;
+  J.ra.prim = c.take<fr::PrimHit>((size_t)d->width * d->height * d->spp);
   J.loss_part = c.take<double>(fr::cdiv(d->width * d->height, 256));
   J.loss = c.take<float>(1);
   J.loss_hist = c.take<float>(std::max(d->hist_cap, 1));
@@ -647,12 +665,14 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   o.brdf_variant = d->brdf_variant;
   o.components = 3;
   float* partial = J.ra.partial;
+  fr::PrimHit* prim = J.ra.prim;
   const float* cam = J.ra.cam;
   if ((rc = build_args(jh->mesh, &sc, &o, J.ra, fr::kLightChunkFwd)) != FR_OK ||
       (rc = build_args(jh->mesh, &sc, &o, J.rb, fr::kLightChunkBwd)) != FR_OK) {
     fr_mesh_destroy(jh->mesh); (void)hipFree(jh->arena); delete jh; return rc;
   }
   J.ra.partial = partial; J.rb.partial = nullptr;
+  J.ra.prim = prim; J.rb.prim = prim;
   J.ra.lights = J.lights; J.rb.lights = J.lights;
   J.ra.cam = cam; J.rb.cam = cam;
   const fr::MeshDev& md_ = jh->mesh->d;

@@ -66,14 +66,14 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
       const int s = ps.s0 + chunk * 64;
       Sample sm;
       camera_sample(a, ps, s, sm);
+      const size_t rs = (size_t)ps.pid * a.S + s;
+      double bd0[3] = {1.0, 0.0, 0.0};
+      PrimHit ph = {-1, 0.0f, 0.0, 0.0};
+      if (want) ph = load_prim(a, rs, bd0);
       HitState h;
-      h.t = 3.4e38f; h.id = -1; h.tamb = 3.4e38f;
-      bool dummy = false;
-      trace<false, false>(a.nodes, a.recs, a.F, sm.ray, want, -1, h, dummy);
+      h.id = ph.id;
       Frame fr = {};
-      double fxd = 0.0, fyd = 0.0;
-      if (want && h.id >= 0) film_point(a, ps, s, fxd, fyd);
-      const bool shaded = want && h.id >= 0 && shading_frame<TEX>(a, sm, h, fr, fxd, fyd);
+      const bool shaded = want && h.id >= 0 && shading_frame<TEX>(a, sm, ph.id, ph.t, bd0, fr);
       // sample-level adjoint accumulators
       V3 gx = {0, 0, 0}, gns = {0, 0, 0}, gwo = {0, 0, 0}, gc = {0, 0, 0}, gs = {0, 0, 0};
       float gr = 0.0f;
@@ -197,19 +197,16 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
       for (int k = 0; k < 12; ++k) gcam[k] = 0.0f;
       float bb[3] = {0.0f, 0.0f, 0.0f};
       if (has_g) {
-        // the triangle's corners and the FP64 barycentrics again, rather than
-        // kept live through the light loop (the empty asm keeps the compiler
-        // from reusing the earlier loads)
-        int id = h.id;
-        asm volatile("" : "+v"(id));
+        // the primary hit and the triangle's corners again, rather than kept
+        // live through the light loop (the empty asm keeps the compiler from
+        // reusing the earlier loads)
+        size_t rs2 = rs;
+        asm volatile("" : "+v"(rs2));
+        double bd[3];
+        const PrimHit ph2 = load_prim(a, rs2, bd);
+        const int id = ph2.id;
         int vi[3];
         for (int k = 0; k < 3; ++k) vi[k] = a.tris[3 * id + k];
-        double bd[3];
-        {
-          double fxd2, fyd2;
-          film_point(a, ps, s, fxd2, fyd2);
-          bary64(a, fxd2, fyd2, vi, bd);
-        }
         for (int k = 0; k < 3; ++k) bb[k] = (float)bd[k];
         const float grr = fr.r_free ? gr : 0.0f;
         const V3 gm = project_out(gns, fr.ns, fr.inv_m);
@@ -267,7 +264,7 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
         gv[0] = gv[0] - gsv - ge1 - ge2;
         gv[1] = gv[1] + ge1;
         gv[2] = gv[2] + ge2;
-        gd = gd + gsv * h.t;
+        gd = gd + gsv * ph2.t;
         // d = dw / |dw|, dw = R dc, o = T
         const V3 gdw = project_out(gd, d, sm.inv_len);
         gcam[0] += gdw.x * sm.dc.x; gcam[1] += gdw.x * sm.dc.y; gcam[2] += gdw.x * sm.dc.z;
@@ -394,6 +391,7 @@ void launch_render_backward(const RenderArgs& a, const float* dEdp, const FixGra
   launch_zero_fix(slots, (size_t)kSlots * nl, st);
   const int blocks = wave_blocks_items(a);
   if (e0) (void)hipEventRecord(e0, st);
+  launch_primary(a, st);
   if (a.M > 0)
     hipLaunchKernelGGL(k_render_bwd<true>, dim3(blocks), dim3(256), nl * sizeof(fix_t), st, a, dEdp, fg, slots);
   else

@@ -57,6 +57,7 @@ FR_BATCH_KERNEL(kb_gather4, 256) { FR_JOB_PROLOGUE gather4_block(J.nodes, J.n4_s
 FR_BATCH_KERNEL(kb_light_setup, 256) {
   FR_JOB_PROLOGUE light_setup_block(J.lp0, J.le1, J.le2, J.param + J.off_rad, J.lshape, J.ra.L, J.lights, lb);
 }
+FR_BATCH_KERNEL(kb_primary, 256) { FR_JOB_PROLOGUE primary_block<false>(J.ra, lb); }
 __attribute__((amdgpu_waves_per_eu(8))) FR_BATCH_KERNEL(kb_render_fwd, 256) {
   FR_JOB_PROLOGUE render_fwd_block<false, false>(J.ra, J.ra.n_lchunks > 1 ? nullptr : J.image, lb);
 }
@@ -86,7 +87,7 @@ FR_BATCH_KERNEL(kb_zero_grads, 256) {
   for (int k = i; k < n9; k += J.zero_stride) J.acc[k] = 0;
   for (int k = i; k < nslot; k += J.zero_stride) J.lslots[k] = 0;
 }
-__attribute__((amdgpu_waves_per_eu(6))) FR_BATCH_KERNEL(kb_render_bwd, 256) {
+__attribute__((amdgpu_waves_per_eu(5))) FR_BATCH_KERNEL(kb_render_bwd, 256) {
   FR_JOB_PROLOGUE
   const FixGrads g = {J.acc, J.acc + 3 * J.N, J.acc + 6 * J.N, nullptr, nullptr};
   render_bwd_block<false>(J.rb, J.dEdp, g, J.lslots, lb);
@@ -145,8 +146,8 @@ __global__ void kb_advance(JobDev* jobs, int njobs) {
 // Host side
 // ---------------------------------------------------------------------------
 enum Stage {
-  S_BLEND_GEO, S_BLEND_ALB, S_POSE, S_NORMALS, S_REFIT, S_REFIT_TOP, S_GATHER4, S_LIGHTS, S_FWD, S_SUM, S_LOSS, S_LOSS_FINAL,
-  S_SMOOTH_ADJ, S_ZERO_GRADS, S_BWD, S_SLOTS, S_NBWD_P, S_NBWD_G, S_FACE_FRONT, S_EDGE_LEN, S_EDGE_SCAN, S_EDGE_SCAN_ADD,
+  S_BLEND_GEO, S_BLEND_ALB, S_POSE, S_NORMALS, S_REFIT, S_REFIT_TOP, S_GATHER4, S_LIGHTS, S_PRIM, S_FWD, S_SUM, S_LOSS,
+  S_LOSS_FINAL, S_SMOOTH_ADJ, S_ZERO_GRADS, S_BWD, S_SLOTS, S_NBWD_P, S_NBWD_G, S_FACE_FRONT, S_EDGE_LEN, S_EDGE_SCAN, S_EDGE_SCAN_ADD,
   S_EDGE_SAMPLES, S_FIX_FINALIZE, S_POSE_BWD_V, S_POSE_BWD_P, S_BLEND_BWD_GEO, S_BLEND_BWD_ALB, S_ADAM, S_COUNT
 };
 
@@ -161,6 +162,7 @@ static int stage_blocks(const JobDev& J, int s) {
     case S_FACE_FRONT: return cdiv(F, 256);
     case S_GATHER4: return cdiv(4 * J.n4, 256);
     case S_LIGHTS: return cdiv(J.ra.L, 256);
+    case S_PRIM: return wave_blocks_items(J.ra, 1);
     case S_FWD: return wave_blocks_items(J.ra);
     case S_SUM: return J.ra.n_lchunks > 1 ? cdiv(3 * px, 256) : 0;
     case S_LOSS: case S_SMOOTH_ADJ: return cdiv(px, 256);
@@ -207,7 +209,7 @@ int Batch::upload(hipStream_t st) {
       prefix[(size_t)s * (nj + 1) + j] = acc;
       // keep each job's first block on XCD 0 so the render's XCD-aware mapping holds per job
       const int b = stage_blocks(jobs[j], s);
-      acc += (s == S_FWD || s == S_BWD) ? cdiv(b, 8) * 8 : b;
+      acc += (s == S_PRIM || s == S_FWD || s == S_BWD) ? cdiv(b, 8) * 8 : b;
     }
     prefix[(size_t)s * (nj + 1) + nj] = acc;
     total[s] = acc;
@@ -237,12 +239,14 @@ void Batch::launch_step(hipStream_t st) {
   FR_LAUNCH(kb_refit_top, S_REFIT_TOP, 1024, 0);
   FR_LAUNCH(kb_gather4, S_GATHER4, 256, 0);
   FR_LAUNCH(kb_light_setup, S_LIGHTS, 256, 0);
+  FR_LAUNCH(kb_primary, S_PRIM, 256, 0);
   FR_LAUNCH(kb_render_fwd, S_FWD, 256, 0);
   FR_LAUNCH(kb_sum_chunks, S_SUM, 256, 0);
   FR_LAUNCH(kb_loss, S_LOSS, 256, 0);
   FR_LAUNCH(kb_loss_final, S_LOSS_FINAL, 256, 0);
   FR_LAUNCH(kb_smooth_adjoint, S_SMOOTH_ADJ, 256, 0);
   FR_LAUNCH(kb_zero_grads, S_ZERO_GRADS, 256, 0);
+  FR_LAUNCH(kb_primary, S_PRIM, 256, 0);   // the backward traces its own primary hits
   FR_LAUNCH(kb_render_bwd, S_BWD, 256, max_nl * sizeof(fix_t));
   FR_LAUNCH(kb_slots_reduce, S_SLOTS, 256, 0);
   FR_LAUNCH(kb_normals_bwd_project, S_NBWD_P, 256, 0);

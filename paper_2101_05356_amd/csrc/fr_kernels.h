@@ -64,6 +64,17 @@ struct EdgeArgs {
   int lc, n_lchunks;    // lights per work item, light chunks per sample group
 };
 
+// Primary hit of one camera sample: the closest-hit triangle (-1: miss), its
+// distance, and the FP64 barycentrics b1, b2 of the crossing (b0 = 1 - b1 -
+// b2).  Written once per render call by the primary pass and read by every
+// light-chunk work item of the same sample.
+struct PrimHit {
+  int32_t id;
+  float t;
+  double b1, b2;
+};
+static_assert(sizeof(PrimHit) == 24, "primary hit is 24 bytes");
+
 // Device buffers owned by one mesh (topology fixed at creation).
 struct MeshDev {
   int N = 0, F = 0, E = 0;
@@ -110,6 +121,8 @@ struct MeshDev {
   double* edge_cdf = nullptr;       // [E] inclusive running sum
   uint8_t* face_front = nullptr;    // [F]
   double* scan_part = nullptr;      // [ceil(E/1024)] tile totals of the edge CDF scan
+  PrimHit* prim = nullptr;          // [W*H*S] primary hits of the current render call
+  size_t prim_cap = 0;
   float* img_partial = nullptr;     // per-light-chunk partial images
   size_t img_partial_cap = 0;
   fix_t* tex_acc = nullptr;         // [7 M^2] fixed-point texel gradients: diffuse, specular, roughness
@@ -142,6 +155,7 @@ struct RenderArgs {
   int lanes_per_pixel;    // min(S, 64)
   int lc, n_lchunks;      // lights per work item, light chunks per tile
   float* partial;         // [n_lchunks][H*W*3] per-chunk pixel sums (n_lchunks > 1)
+  PrimHit* prim;          // [H*W*S] primary hits, sample index (y*W + x)*S + s
   float tan_half, aspect;
   double tan_half_d, aspect_d;   // the same in FP64 (texture coordinates)
   uint32_t k0, k1, step;
@@ -172,6 +186,8 @@ void launch_light_setup(const fr_scene& sc, LightRec* out, hipStream_t st);
 void launch_zero(float* p, int n, hipStream_t st);
 void launch_axpy(float* dst, const float* src, int n, hipStream_t st);
 // render.hip
+// The primary pass (camera-ray hits into a.prim); the render launchers run it first.
+void launch_primary(const RenderArgs& a, hipStream_t st);
 void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st, hipEvent_t e0 = nullptr,
                            hipEvent_t e1 = nullptr);
 // Default lights per work item: short items balance the forward launch; the

@@ -26,23 +26,26 @@ namespace fr {
 // around its current strip while every XCD gets work from the whole image.
 struct Item { int tile, chunk; };
 
-__device__ __forceinline__ Item wave_item(const RenderArgs& a, int b) {
-  const int per_strip = a.tiles_x * a.n_lchunks;        // blocks per strip
+// nl = light chunks per tile (1 for the primary pass, which has one item per tile).
+__device__ __forceinline__ Item wave_item(const RenderArgs& a, int b, int nl) {
+  const int per_strip = a.tiles_x * nl;                 // blocks per strip
   const int x = b & 7, k = b >> 3;
   const int si = k / per_strip, bi = k - si * per_strip;
   const int strip = si * 8 + x;
   const int item = strip * 4 * per_strip + bi * 4 + (threadIdx.x >> 6);
   Item it;
-  it.tile = item / a.n_lchunks;
-  it.chunk = item - it.tile * a.n_lchunks;
+  it.tile = item / nl;
+  it.chunk = item - it.tile * nl;
   if (it.tile / a.tiles_x >= a.tiles_y) it.tile = -1;
   return it;
 }
+__device__ __forceinline__ Item wave_item(const RenderArgs& a, int b) { return wave_item(a, b, a.n_lchunks); }
 
-inline int wave_blocks_items(const RenderArgs& a) {
+inline int wave_blocks_items(const RenderArgs& a, int nl) {
   const int strips = (a.tiles_y + 3) / 4;
-  return 8 * a.tiles_x * a.n_lchunks * ((strips + 7) / 8);
+  return 8 * a.tiles_x * nl * ((strips + 7) / 8);
 }
+inline int wave_blocks_items(const RenderArgs& a) { return wave_blocks_items(a, a.n_lchunks); }
 
 struct PixelSample {
   int px, py, pid, s0;
@@ -184,18 +187,17 @@ __device__ __forceinline__ TexTap tex_tap(const RenderArgs& a, int tri, const do
 
 // TEX selects the reflectance maps at compile time (a.M > 0 on the host), so
 // the per-vertex kernels keep their register budget.
-// (fx, fy) is the exact film point of the sample (FP64).
+// Frame at the crossing of the sample's ray with triangle `id` at distance t,
+// with FP64 barycentrics bd (as bary64 gives them).
 template <bool TEX>
-__device__ __forceinline__ bool shading_frame(const RenderArgs& a, const Sample& sm, const HitState& h, Frame& f,
-                                              double fx, double fy) {
-  const int* t = a.tris + 3 * h.id;
+__device__ __forceinline__ bool shading_frame(const RenderArgs& a, const Sample& sm, int id, float t_hit,
+                                              const double bd[3], Frame& f) {
+  const int* t = a.tris + 3 * id;
   f.vi[0] = t[0]; f.vi[1] = t[1]; f.vi[2] = t[2];
   const V3 v0 = ld3(a.verts, f.vi[0]), v1 = ld3(a.verts, f.vi[1]), v2 = ld3(a.verts, f.vi[2]);
-  double bd[3];
-  bary64(a, fx, fy, f.vi, bd);
   const float b0 = (float)bd[0], b1 = (float)bd[1], b2 = (float)bd[2];
   f.b[0] = b0; f.b[1] = b1; f.b[2] = b2;
-  f.t = h.t;
+  f.t = t_hit;
   f.x = v0 * b0 + v1 * b1 + v2 * b2;
   const V3 n0 = ld3(a.normals, f.vi[0]), n1 = ld3(a.normals, f.vi[1]), n2 = ld3(a.normals, f.vi[2]);
   f.m = n0 * b0 + n1 * b1 + n2 * b2;
@@ -204,7 +206,7 @@ __device__ __forceinline__ bool shading_frame(const RenderArgs& a, const Sample&
   f.wo = {-sm.ray.d.x, -sm.ray.d.y, -sm.ray.d.z};
   float r;
   if (TEX) {
-    const TexTap tp = tex_tap(a, h.id, bd);
+    const TexTap tp = tex_tap(a, id, bd);
     const float w00 = (1.0f - tp.fx) * (1.0f - tp.fy), w10 = tp.fx * (1.0f - tp.fy);
     const float w01 = (1.0f - tp.fx) * tp.fy, w11 = tp.fx * tp.fy;
     f.c = ld3(a.tex_c, tp.t00) * w00 + ld3(a.tex_c, tp.t10) * w10 + ld3(a.tex_c, tp.t01) * w01 +
@@ -221,6 +223,26 @@ __device__ __forceinline__ bool shading_frame(const RenderArgs& a, const Sample&
   f.r = fminf(fmaxf(r, kRoughMin), kRoughMax);
   f.cos_o = dot(f.ns, f.wo);
   return f.cos_o > 0.0f;
+}
+
+// Frame of a traced hit h of the ray through the exact film point (fx, fy).
+template <bool TEX>
+__device__ __forceinline__ bool shading_frame(const RenderArgs& a, const Sample& sm, const HitState& h, Frame& f,
+                                              double fx, double fy) {
+  const int* t = a.tris + 3 * h.id;
+  const int vi[3] = {t[0], t[1], t[2]};
+  double bd[3];
+  bary64(a, fx, fy, vi, bd);
+  return shading_frame<TEX>(a, sm, h.id, h.t, bd, f);
+}
+
+// The stored primary hit of sample rs (pixel-major) as (id, t, FP64 barycentrics).
+__device__ __forceinline__ PrimHit load_prim(const RenderArgs& a, size_t rs, double bd[3]) {
+  const PrimHit p = a.prim[rs];
+  bd[1] = p.b1;
+  bd[2] = p.b2;
+  bd[0] = 1.0 - p.b1 - p.b2;
+  return p;
 }
 
 // ---------------------------------------------------------------------------

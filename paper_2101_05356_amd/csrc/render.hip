@@ -6,9 +6,84 @@
 // the same light j at the same time, which keeps the wave-packet traversal
 // coherent.  The per-pixel mean is a fixed-order butterfly over the S lanes of
 // the pixel (deterministic).  Waves are mapped to tiles XCD-aware (wave_tile).
+//
+// Primary pass: the camera ray of every sample is traced once per render call
+// (k_primary) and its hit stored; the (tile, light chunk) work items of the
+// forward and backward read it instead of tracing the camera ray again.
 #include "fr_shade.h"
 
 namespace fr {
+
+// Normal-direction cosine n_s . o of a stored hit (the forward dump's flag).
+__device__ __forceinline__ float prim_cos_o(const RenderArgs& a, const Sample& sm, int id, const double bd[3]) {
+  const int* t = a.tris + 3 * id;
+  const float b0 = (float)bd[0], b1 = (float)bd[1], b2 = (float)bd[2];
+  const V3 m = ld3(a.normals, t[0]) * b0 + ld3(a.normals, t[1]) * b1 + ld3(a.normals, t[2]) * b2;
+  const V3 ns = m * (1.0f / sqrtf(dot(m, m)));
+  return -dot(ns, sm.ray.d);
+}
+
+// One wave per tile: trace every sample's camera ray, store its hit (and,
+// in dump builds, the decision, its ambiguity flag and the camera-ray
+// statistics).
+template <bool DUMP>
+__device__ __forceinline__ void primary_block(const RenderArgs& a, int bid) {
+  const int lane = threadIdx.x & 63;
+  const Item it = wave_item(a, bid, 1);
+  if (it.tile < 0) return;
+  const PixelSample ps = pixel_sample(a, it.tile, lane);
+  TravStats st = {0, 0, 0, 0, 0};
+  for (int chunk = 0; chunk < a.chunks; ++chunk) {
+    const int s = ps.s0 + chunk * 64;
+    Sample sm;
+    camera_sample(a, ps, s, sm);
+    HitState h;
+    h.t = 3.4e38f; h.id = -1; h.tamb = 3.4e38f;
+    bool dummy = false;
+    trace<false, DUMP>(a.nodes, a.recs, a.F, sm.ray, ps.valid, -1, h, dummy, &st);
+    PrimHit ph = {h.id, h.t, 0.0, 0.0};
+    double bd[3] = {1.0, 0.0, 0.0};
+    if (ps.valid && h.id >= 0) {
+      double fxd, fyd;
+      film_point(a, ps, s, fxd, fyd);
+      const int* t = a.tris + 3 * h.id;
+      const int vi[3] = {t[0], t[1], t[2]};
+      bary64(a, fxd, fyd, vi, bd);
+      ph.b1 = bd[1];
+      ph.b2 = bd[2];
+    }
+    const size_t rs = (size_t)ps.pid * a.S + s;
+    if (ps.valid) a.prim[rs] = ph;
+    if (DUMP && ps.valid) {
+      a.dbg_hit[rs] = h.id;
+      const bool pf = hit_ambiguous(h) || (h.id >= 0 && fabsf(prim_cos_o(a, sm, h.id, bd)) < kFlagCos);
+      a.dbg_pflag[rs] = pf ? 1 : 0;
+    }
+  }
+  if (DUMP && a.dbg_stats) {
+    const uint32_t v[5] = {st.lane_box, st.lane_leaf, st.rays, st.wave_int, st.wave_leaf};
+    const int slot[5] = {0, 1, 2, 6, 7};
+    for (int k = 0; k < 5; ++k) {
+      uint32_t x = v[k];
+      if (k < 3)
+        for (int off = 32; off >= 1; off >>= 1) x += (uint32_t)__shfl_xor((int)x, off, 64);
+      if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(a.dbg_stats) + slot[k], (unsigned long long)x);
+    }
+  }
+}
+
+template <bool DUMP>
+__global__ __launch_bounds__(256) void k_primary(RenderArgs a) {
+  primary_block<DUMP>(a, blockIdx.x);
+}
+
+void launch_primary(const RenderArgs& a, hipStream_t st) {
+  const int blocks = wave_blocks_items(a, 1);
+  if (a.dbg_hit)
+    hipLaunchKernelGGL(k_primary<true>, dim3(blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_primary<false>, dim3(blocks), dim3(256), 0, st, a);
+}
 
 template <bool DUMP, bool TEX>
 __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __restrict__ image, int bid) {
@@ -19,26 +94,19 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
   const int j0 = it.chunk * a.lc, j1 = min(a.L, j0 + a.lc);
   PixelSample ps = pixel_sample(a, tile, lane);
   float acc[3] = {0.0f, 0.0f, 0.0f};
-  TravStats st = {0, 0, 0, 0, 0};
   TravStats st2 = {0, 0, 0, 0, 0};
   for (int chunk = 0; chunk < a.chunks; ++chunk) {
     const int s = ps.s0 + chunk * 64;
     Sample sm;
     camera_sample(a, ps, s, sm);
-    HitState h;
-    h.t = 3.4e38f; h.id = -1; h.tamb = 3.4e38f;
-    bool dummy = false;
-    trace<false, DUMP>(a.nodes, a.recs, a.F, sm.ray, ps.valid, -1, h, dummy, it.chunk == 0 ? &st : nullptr);
     const size_t rs = (size_t)ps.pid * a.S + s;
+    double bd[3] = {1.0, 0.0, 0.0};
+    PrimHit ph = {-1, 0.0f, 0.0, 0.0};
+    if (ps.valid) ph = load_prim(a, rs, bd);
+    HitState h;
+    h.id = ph.id;
     Frame fr;
-    double fxd = 0.0, fyd = 0.0;
-    if (ps.valid && h.id >= 0) film_point(a, ps, s, fxd, fyd);
-    const bool shaded = ps.valid && h.id >= 0 && shading_frame<TEX>(a, sm, h, fr, fxd, fyd);
-    if (DUMP && ps.valid && it.chunk == 0) {
-      a.dbg_hit[rs] = h.id;
-      const bool pf = hit_ambiguous(h) || (h.id >= 0 && fabsf(fr.cos_o) < kFlagCos);
-      a.dbg_pflag[rs] = pf ? 1 : 0;
-    }
+    const bool shaded = ps.valid && h.id >= 0 && shading_frame<TEX>(a, sm, ph.id, ph.t, bd, fr);
     // shadow decisions of every light of the chunk, then the shading of the visible ones
     const auto draw = [&](int j) { return philox((uint32_t)ps.pid, (uint32_t)s, 1u + (uint32_t)j, a.step, a.k0, a.k1); };
     const auto note = [&](int j, bool lit, bool occ, const LightSample& ls, const HitState& sh) {
@@ -71,14 +139,15 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
     }
   }
   if (DUMP && a.dbg_stats) {
-    // lane counts summed over the wave; wave counts taken once per wave
-    const uint32_t v[10] = {st.lane_box, st.lane_leaf, st.rays, st2.lane_box, st2.lane_leaf, st2.rays,
-                            st.wave_int, st.wave_leaf, st2.wave_int, st2.wave_leaf};
-    for (int k = 0; k < 10; ++k) {
+    // shadow-ray counts (the primary pass adds the camera rays'): lane counts
+    // summed over the wave, wave counts taken once per wave
+    const uint32_t v[5] = {st2.lane_box, st2.lane_leaf, st2.rays, st2.wave_int, st2.wave_leaf};
+    const int slot[5] = {3, 4, 5, 8, 9};
+    for (int k = 0; k < 5; ++k) {
       uint32_t x = v[k];
-      if (k < 6)
+      if (k < 3)
         for (int off = 32; off >= 1; off >>= 1) x += (uint32_t)__shfl_xor((int)x, off, 64);
-      if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(a.dbg_stats) + k, (unsigned long long)x);
+      if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(a.dbg_stats) + slot[k], (unsigned long long)x);
     }
   }
   // per-pixel mean over the S samples
@@ -115,6 +184,7 @@ __global__ __launch_bounds__(256) void k_sum_chunks(const float* __restrict__ pa
 void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const int blocks = wave_blocks_items(a);
   if (e0) (void)hipEventRecord(e0, st);
+  launch_primary(a, st);
   if (a.M > 0) {
     if (a.dbg_hit)
       hipLaunchKernelGGL((k_render_fwd<true, true>), dim3(blocks), dim3(256), 0, st, a, image);
