@@ -137,7 +137,8 @@ typedef struct {
   int32_t brdf_variant;    /* FR_BRDF_* */
   int32_t components;      /* bit 0 diffuse, bit 1 specular (3 = full BRDF) */
   int32_t edge_samples;    /* boundary-term samples in the backward; 0 = off, -1 = W*H */
-  int32_t light_chunk;     /* lights per work item, 0..32 (0 = library default per pass) */
+  int32_t light_chunk;     /* lights per work item, 0..32 (0 = library default per pass; the
+                            * backward takes at least ceil(n_lights / 4)) */
   /* Debug dump of the decisions (device, nullable):
    *   dbg_hit [W*H*spp] int32 closest-hit triangle id per sample (-1 = miss);
    *   dbg_pflag [W*H*spp] uint8 nonzero when that decision is near ambiguous;
@@ -211,6 +212,7 @@ int fr_loss(const float* d_image, const float* d_target, int32_t width, int32_t 
  * With reflectance maps each shading point spreads its reflectance gradient
  * over its four texels by the bilinear weights (grads->tex_*), and the maps'
  * own slope in (u, v) carries into the barycentrics and the vertices.
+ * At most 128 lights (FR_ERR_LIMIT otherwise).
  * Uses the mesh's internal scratch; calls on one mesh must not overlap. */
 int fr_render_backward(fr_mesh* mesh, const fr_scene* scene, const fr_render_opts* opts, const float* d_dEdp,
                        fr_grads* grads, fr_stream stream);

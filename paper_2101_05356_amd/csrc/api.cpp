@@ -290,6 +290,16 @@ int32_t fr_mesh_edges(const fr_mesh* m, int32_t* h_edges, int32_t* h_faces) {
 
 int32_t fr_mesh_bvh_depth(const fr_mesh* m) { return m ? m->d.bvh_depth : -1; }
 
+// The backward's light chunks: the four waves of a block take a tile's
+// chunks, so lc >= ceil(L / 4) (at most 32 lights per chunk).
+int bwd_chunks(fr_mesh* m, fr::RenderArgs& a) {
+  if (a.L > fr::kBwdMaxLights) return fail(m->ctx, FR_ERR_LIMIT, "the backward takes at most 128 lights");
+  a.lc = std::max(a.lc, std::max(1, fr::cdiv(a.L, 4)));
+  if (a.lc > 32) return fail(m->ctx, FR_ERR_LIMIT, "light_chunk must be <= 32");
+  a.n_lchunks = std::max(1, fr::cdiv(a.L, a.lc));
+  return FR_OK;
+}
+
 // The mesh's primary-hit buffer, grown to the call's W*H*S samples.
 int ensure_prim(fr_mesh* m, fr::RenderArgs& a) {
   const size_t need = (size_t)a.W * a.H * a.S;
@@ -360,10 +370,11 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
                        fr_stream stream) {
   if (!m || !d_dEdp || !g) return FR_ERR_INVALID_ARG;
   fr::RenderArgs a;
-  int rc = build_args(m, s, o, a, fr::kLightChunkBwd);
+  int rc = build_args(m, s, o, a, 1);
   if (rc != FR_OK) return rc;
   if (o->dbg_vis || (!o->dbg_hit) != (!o->dbg_pflag))
     return fail(m->ctx, FR_ERR_INVALID_ARG, "the backward dump takes dbg_hit and dbg_pflag only");
+  if ((rc = bwd_chunks(m, a)) != FR_OK) return rc;
   a.dbg_hit = nullptr; a.dbg_pflag = nullptr; a.dbg_vis = nullptr; a.dbg_stats = nullptr;
   if ((rc = ensure_lights(m, s->n_lights)) != FR_OK) return rc;
   if ((rc = ensure_prim(m, a)) != FR_OK) return rc;
@@ -530,6 +541,7 @@ int validate_job(fr_model* md, const fr_job_desc* d) {
   fr_ctx* ctx = md->ctx;
   if (!d) return fail(ctx, FR_ERR_INVALID_ARG, "null job description");
   if (d->width <= 0 || d->height <= 0 || d->n_lights <= 0) return fail(ctx, FR_ERR_INVALID_ARG, "bad job sizes");
+  if (d->n_lights > fr::kBwdMaxLights) return fail(ctx, FR_ERR_LIMIT, "a job takes at most 128 lights");
   if (!pow2(d->spp) || d->spp > 1024) return fail(ctx, FR_ERR_LIMIT, "spp must be a power of two in [1, 1024]");
   if (!d->cam || !d->light_p0 || !d->light_e1 || !d->light_e2 || !d->light_shape || !d->target || !d->params ||
       !d->lr)
@@ -668,7 +680,7 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   fr::PrimHit* prim = J.ra.prim;
   const float* cam = J.ra.cam;
   if ((rc = build_args(jh->mesh, &sc, &o, J.ra, fr::kLightChunkFwd)) != FR_OK ||
-      (rc = build_args(jh->mesh, &sc, &o, J.rb, fr::kLightChunkBwd)) != FR_OK) {
+      (rc = build_args(jh->mesh, &sc, &o, J.rb, 1)) != FR_OK || (rc = bwd_chunks(jh->mesh, J.rb)) != FR_OK) {
     fr_mesh_destroy(jh->mesh); (void)hipFree(jh->arena); delete jh; return rc;
   }
   J.ra.partial = partial; J.rb.partial = nullptr;

@@ -46,14 +46,21 @@ __device__ __forceinline__ void g1_fwd_bwd(float nv, float hv, float r, float& G
 template <bool TEX>
 __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const float* __restrict__ dEdp,
                                                  const FixGrads& g, fix_t* __restrict__ slots, int bid) {
-  extern __shared__ fix_t lds[];   // [L*12 + 12]: per light p0 e1 e2 rad, then camera
+  // LDS: [L*12 + 12] fixed-point sums (per light p0 e1 e2 rad, then camera),
+  // then the per-lane sample adjoints of the block's four waves [4][64][16]
+  extern __shared__ fix_t lds[];
   const int nl = a.L * 12 + 12;
+  float* part = reinterpret_cast<float*>(lds + nl);
+  int* arrived = reinterpret_cast<int*>(part + 4 * 64 * 16);
   for (int i = threadIdx.x; i < nl; i += 256) lds[i] = 0;
+  if (threadIdx.x == 0) *arrived = 0;
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const Item it = wave_item(a, bid);
-  const int tile = it.tile;
-  const int j0 = it.chunk * a.lc, j1 = min(a.L, j0 + a.lc);
+  // one block = one tile; wave wv takes the tile's light chunk wv (at most
+  // four chunks: the host sets lc >= L/4), so the sample-level work below
+  // runs once per sample instead of once per chunk
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tile = block_tile(a, bid);
+  const int j0 = wv * a.lc, j1 = min(a.L, j0 + a.lc);
   if (tile >= 0) {
     const PixelSample ps = pixel_sample(a, tile, lane);
     float gbar[3] = {0.0f, 0.0f, 0.0f};
@@ -182,169 +189,208 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
           if (lane == 0 && t != 0.0f) atomicAdd(&lds[12 * j + k], to_fix(t));
         }
       }
-      // ---- sample-level adjoint: shading frame, intersection, camera
-      V3 gv[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, gn[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-      float gb[3] = {0.0f, 0.0f, 0.0f};
-      // lanes whose chunk of lights left no gradient skip the chain and the scatter
-      const bool has_g = shaded && (gx.x != 0.0f || gx.y != 0.0f || gx.z != 0.0f || gns.x != 0.0f ||
-                                    gns.y != 0.0f || gns.z != 0.0f || gwo.x != 0.0f || gwo.y != 0.0f ||
-                                    gwo.z != 0.0f || gc.x != 0.0f || gc.y != 0.0f || gc.z != 0.0f ||
-                                    gs.x != 0.0f || gs.y != 0.0f || gs.z != 0.0f || gr != 0.0f);
-      TexTap tp = {0, 0, 0, 0, 0.0f, 0.0f};
-      // camera gradient of this chunk (reduced at its end, so that no
-      // accumulator stays live through the traversals)
-      float gcam[12];
-      for (int k = 0; k < 12; ++k) gcam[k] = 0.0f;
-      float bb[3] = {0.0f, 0.0f, 0.0f};
-      if (has_g) {
-        // the primary hit and the triangle's corners again, rather than kept
-        // live through the light loop (the empty asm keeps the compiler from
-        // reusing the earlier loads)
-        size_t rs2 = rs;
-        asm volatile("" : "+v"(rs2));
-        double bd[3];
-        const PrimHit ph2 = load_prim(a, rs2, bd);
-        const int id = ph2.id;
-        int vi[3];
-        for (int k = 0; k < 3; ++k) vi[k] = a.tris[3 * id + k];
-        for (int k = 0; k < 3; ++k) bb[k] = (float)bd[k];
-        const float grr = fr.r_free ? gr : 0.0f;
-        const V3 gm = project_out(gns, fr.ns, fr.inv_m);
-        V3 vv[3];
-        for (int k = 0; k < 3; ++k) {
-          vv[k] = ld3(a.verts, vi[k]);
-          const V3 nk = ld3(a.normals, vi[k]);
-          if (TEX) {
-            gb[k] = dot(nk, gm) + dot(vv[k], gx);
-          } else {
-            const V3 ck = ld3(a.diffuse, vi[k]), sk = ld3(a.specular, vi[k]);
-            const float rk = a.roughness[vi[k]];
-            gb[k] = dot(nk, gm) + dot(vv[k], gx) + dot(ck, gc) + dot(sk, gs) + rk * grr;
-          }
-          gn[k] = gm * bb[k];
-          gv[k] = gx * bb[k];
+      // The chunks' sample adjoints meet in LDS; one wave sums them in chunk
+      // order and runs the sample-level chain and scatters once per sample:
+      // with one sample round per tile, the last wave to arrive (no block
+      // barrier: the others leave at once); otherwise wave 0 after a barrier.
+      {
+        float* p = part + (size_t)(wv * 64 + lane) * 16;
+        p[0] = gx.x; p[1] = gx.y; p[2] = gx.z; p[3] = gns.x; p[4] = gns.y; p[5] = gns.z;
+        p[6] = gwo.x; p[7] = gwo.y; p[8] = gwo.z; p[9] = gc.x; p[10] = gc.y; p[11] = gc.z;
+        p[12] = gs.x; p[13] = gs.y; p[14] = gs.z; p[15] = gr;
+      }
+      bool run;
+      if (a.chunks == 1) {
+        __threadfence_block();   // this wave's partials and LDS sums before its arrival
+        int n = 0;
+        if (lane == 0) n = atomicAdd(arrived, 1);
+        run = __builtin_amdgcn_readlane(n, 0) == 3;
+        __threadfence_block();
+      } else {
+        __syncthreads();
+        run = wv == 0;
+      }
+      if (run) {
+        gx = gns = gwo = gc = gs = V3{0.0f, 0.0f, 0.0f};
+        gr = 0.0f;
+        for (int k = 0; k < a.n_lchunks; ++k) {
+          const float* p = part + (size_t)(k * 64 + lane) * 16;
+          gx = gx + V3{p[0], p[1], p[2]}; gns = gns + V3{p[3], p[4], p[5]}; gwo = gwo + V3{p[6], p[7], p[8]};
+          gc = gc + V3{p[9], p[10], p[11]}; gs = gs + V3{p[12], p[13], p[14]}; gr += p[15];
         }
+        // ---- sample-level adjoint: shading frame, intersection, camera
+        V3 gv[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, gn[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        float gb[3] = {0.0f, 0.0f, 0.0f};
+        // lanes whose chunk of lights left no gradient skip the chain and the scatter
+        const bool has_g = shaded && (gx.x != 0.0f || gx.y != 0.0f || gx.z != 0.0f || gns.x != 0.0f ||
+                                      gns.y != 0.0f || gns.z != 0.0f || gwo.x != 0.0f || gwo.y != 0.0f ||
+                                      gwo.z != 0.0f || gc.x != 0.0f || gc.y != 0.0f || gc.z != 0.0f ||
+                                      gs.x != 0.0f || gs.y != 0.0f || gs.z != 0.0f || gr != 0.0f);
+        TexTap tp = {0, 0, 0, 0, 0.0f, 0.0f};
+        // camera gradient of this chunk (reduced at its end, so that no
+        // accumulator stays live through the traversals)
+        float gcam[12];
+        for (int k = 0; k < 12; ++k) gcam[k] = 0.0f;
+        float bb[3] = {0.0f, 0.0f, 0.0f};
+        if (has_g) {
+          // the primary hit and the triangle's corners again, rather than kept
+          // live through the light loop (the empty asm keeps the compiler from
+          // reusing the earlier loads)
+          size_t rs2 = rs;
+          asm volatile("" : "+v"(rs2));
+          double bd[3];
+          const PrimHit ph2 = load_prim(a, rs2, bd);
+          const int id = ph2.id;
+          int vi[3];
+          for (int k = 0; k < 3; ++k) vi[k] = a.tris[3 * id + k];
+          for (int k = 0; k < 3; ++k) bb[k] = (float)bd[k];
+          const float grr = fr.r_free ? gr : 0.0f;
+          const V3 gm = project_out(gns, fr.ns, fr.inv_m);
+          V3 vv[3];
+          for (int k = 0; k < 3; ++k) {
+            vv[k] = ld3(a.verts, vi[k]);
+            const V3 nk = ld3(a.normals, vi[k]);
+            if (TEX) {
+              gb[k] = dot(nk, gm) + dot(vv[k], gx);
+            } else {
+              const V3 ck = ld3(a.diffuse, vi[k]), sk = ld3(a.specular, vi[k]);
+              const float rk = a.roughness[vi[k]];
+              gb[k] = dot(nk, gm) + dot(vv[k], gx) + dot(ck, gc) + dot(sk, gs) + rk * grr;
+            }
+            gn[k] = gm * bb[k];
+            gv[k] = gx * bb[k];
+          }
+          if (TEX) {
+            // reflectance = bilinear read at (u, v) = sum_k b_k uv_k: its slope
+            // in (u, v) (d fx / du = M inside a cell) goes to the b_k
+            tp = tex_tap(a, id, bd);
+            const auto proj = [&](int t) {
+              return dot(ld3(a.tex_c, t), gc) + dot(ld3(a.tex_s, t), gs) + a.tex_r[t] * grr;
+            };
+            const float P00 = proj(tp.t00), P10 = proj(tp.t10), P01 = proj(tp.t01), P11 = proj(tp.t11);
+            const float Mf = (float)a.M;
+            const float gu = Mf * ((1.0f - tp.fy) * (P10 - P00) + tp.fy * (P11 - P01));
+            const float gvv = Mf * ((1.0f - tp.fx) * (P01 - P00) + tp.fx * (P11 - P10));
+            const float* q = a.uv + 6 * id;
+            for (int k = 0; k < 3; ++k) gb[k] += gu * q[2 * k] + gvv * q[2 * k + 1];
+          }
+          // b0 = 1 - b1 - b2; Moller-Trumbore adjoint of (b1, b2), solved from
+          // the crossing point o' = o + t d itself (t = hit distance, held
+          // fixed: g_o += g_o', g_d += t g_o'), placed by the FP64 barycentrics:
+          // sv = o' - v0 = b1 e1 + b2 e2, qv = sv x e1.  An FP32 o' would carry
+          // ~ulp(|o|) of error into sv, inconsistent with those barycentrics.
+          const float g1 = gb[1] - gb[0], g2 = gb[2] - gb[0];
+          const V3 d = sm.ray.d;
+          const V3 e1 = vv[1] - vv[0], e2 = vv[2] - vv[0];
+          const V3 pv = cross(d, e2);
+          const float idet = 1.0f / dot(e1, pv);
+          const float b1 = bb[1], b2 = bb[2];
+          const V3 sv = e1 * b1 + e2 * b2;
+          const V3 qv = cross(sv, e1);
+          const float gA1 = g1 * idet, gA2 = g2 * idet, gdet = -(g1 * b1 + g2 * b2) * idet;
+          V3 gsv = pv * gA1, gp = sv * gA1;
+          V3 gd = qv * gA2 - gwo;
+          const V3 gq = d * gA2;
+          V3 ge1 = pv * gdet;
+          gp = gp + e1 * gdet;
+          gsv = gsv + cross(e1, gq);
+          ge1 = ge1 + cross(gq, sv);
+          gd = gd + cross(e2, gp);
+          const V3 ge2 = cross(gp, d);
+          gv[0] = gv[0] - gsv - ge1 - ge2;
+          gv[1] = gv[1] + ge1;
+          gv[2] = gv[2] + ge2;
+          gd = gd + gsv * ph2.t;
+          // d = dw / |dw|, dw = R dc, o = T
+          const V3 gdw = project_out(gd, d, sm.inv_len);
+          gcam[0] += gdw.x * sm.dc.x; gcam[1] += gdw.x * sm.dc.y; gcam[2] += gdw.x * sm.dc.z;
+          gcam[3] += gdw.y * sm.dc.x; gcam[4] += gdw.y * sm.dc.y; gcam[5] += gdw.y * sm.dc.z;
+          gcam[6] += gdw.z * sm.dc.x; gcam[7] += gdw.z * sm.dc.y; gcam[8] += gdw.z * sm.dc.z;
+          gcam[9] += gsv.x; gcam[10] += gsv.y; gcam[11] += gsv.z;
+          gr = grr;
+        }
+        // camera: wave reduction of this chunk into LDS
+        if (ballot(has_g)) {
+          for (int k = 0; k < 12; ++k) {
+            const float t = wave_sum(gcam[k]);
+            if (lane == 0 && t != 0.0f) atomicAdd(&lds[12 * a.L + k], to_fix(t));
+          }
+        }
+        // ---- per-vertex scatter: one atomic set per distinct triangle in the wave
+        uint64_t todo = ballot(has_g);
+        while (todo) {
+          const int leader = (int)__builtin_ctzll(todo);
+          const int key = readlane_i(h.id, leader);
+          const bool mine = has_g && h.id == key;
+          todo &= ~ballot(mine);
+          const int* tv = a.tris + 3 * key;
+          for (int k = 0; k < 3; ++k) {
+            const int vi = tv[k];
+            const float bk = bb[k];
+            if (TEX) {
+              // reflectance gradients go to the texels below
+              float vals[6] = {gv[k].x, gv[k].y, gv[k].z, gn[k].x, gn[k].y, gn[k].z};
+              for (int q = 0; q < 6; ++q) vals[q] = wave_sum(mine ? vals[q] : 0.0f);
+              if (lane == leader) {
+                if (g.verts) { fix_add(g.verts + 3 * vi, vals[0]); fix_add(g.verts + 3 * vi + 1, vals[1]); fix_add(g.verts + 3 * vi + 2, vals[2]); }
+                if (g.normals) { fix_add(g.normals + 3 * vi, vals[3]); fix_add(g.normals + 3 * vi + 1, vals[4]); fix_add(g.normals + 3 * vi + 2, vals[5]); }
+              }
+            } else {
+              float vals[13] = {gv[k].x, gv[k].y, gv[k].z, gn[k].x, gn[k].y, gn[k].z, gc.x * bk, gc.y * bk, gc.z * bk,
+                                gs.x * bk, gs.y * bk, gs.z * bk, gr * bk};
+              for (int q = 0; q < 13; ++q) vals[q] = wave_sum(mine ? vals[q] : 0.0f);
+              if (lane == leader) {
+                if (g.verts) { fix_add(g.verts + 3 * vi, vals[0]); fix_add(g.verts + 3 * vi + 1, vals[1]); fix_add(g.verts + 3 * vi + 2, vals[2]); }
+                if (g.normals) { fix_add(g.normals + 3 * vi, vals[3]); fix_add(g.normals + 3 * vi + 1, vals[4]); fix_add(g.normals + 3 * vi + 2, vals[5]); }
+                if (g.diffuse) { fix_add(g.diffuse + 3 * vi, vals[6]); fix_add(g.diffuse + 3 * vi + 1, vals[7]); fix_add(g.diffuse + 3 * vi + 2, vals[8]); }
+                if (g.specular) { fix_add(g.specular + 3 * vi, vals[9]); fix_add(g.specular + 3 * vi + 1, vals[10]); fix_add(g.specular + 3 * vi + 2, vals[11]); }
+                if (g.roughness) fix_add(g.roughness + vi, vals[12]);
+              }
+            }
+          }
+        }
+        // ---- per-texel scatter (maps in use): lanes with the same bilinear
+        // footprint (its first and last texel fix the other two) reduce together
         if (TEX) {
-          // reflectance = bilinear read at (u, v) = sum_k b_k uv_k: its slope
-          // in (u, v) (d fx / du = M inside a cell) goes to the b_k
-          tp = tex_tap(a, id, bd);
-          const auto proj = [&](int t) {
-            return dot(ld3(a.tex_c, t), gc) + dot(ld3(a.tex_s, t), gs) + a.tex_r[t] * grr;
-          };
-          const float P00 = proj(tp.t00), P10 = proj(tp.t10), P01 = proj(tp.t01), P11 = proj(tp.t11);
-          const float Mf = (float)a.M;
-          const float gu = Mf * ((1.0f - tp.fy) * (P10 - P00) + tp.fy * (P11 - P01));
-          const float gvv = Mf * ((1.0f - tp.fx) * (P01 - P00) + tp.fx * (P11 - P10));
-          const float* q = a.uv + 6 * id;
-          for (int k = 0; k < 3; ++k) gb[k] += gu * q[2 * k] + gvv * q[2 * k + 1];
-        }
-        // b0 = 1 - b1 - b2; Moller-Trumbore adjoint of (b1, b2), solved from
-        // the crossing point o' = o + t d itself (t = hit distance, held
-        // fixed: g_o += g_o', g_d += t g_o'), placed by the FP64 barycentrics:
-        // sv = o' - v0 = b1 e1 + b2 e2, qv = sv x e1.  An FP32 o' would carry
-        // ~ulp(|o|) of error into sv, inconsistent with those barycentrics.
-        const float g1 = gb[1] - gb[0], g2 = gb[2] - gb[0];
-        const V3 d = sm.ray.d;
-        const V3 e1 = vv[1] - vv[0], e2 = vv[2] - vv[0];
-        const V3 pv = cross(d, e2);
-        const float idet = 1.0f / dot(e1, pv);
-        const float b1 = bb[1], b2 = bb[2];
-        const V3 sv = e1 * b1 + e2 * b2;
-        const V3 qv = cross(sv, e1);
-        const float gA1 = g1 * idet, gA2 = g2 * idet, gdet = -(g1 * b1 + g2 * b2) * idet;
-        V3 gsv = pv * gA1, gp = sv * gA1;
-        V3 gd = qv * gA2 - gwo;
-        const V3 gq = d * gA2;
-        V3 ge1 = pv * gdet;
-        gp = gp + e1 * gdet;
-        gsv = gsv + cross(e1, gq);
-        ge1 = ge1 + cross(gq, sv);
-        gd = gd + cross(e2, gp);
-        const V3 ge2 = cross(gp, d);
-        gv[0] = gv[0] - gsv - ge1 - ge2;
-        gv[1] = gv[1] + ge1;
-        gv[2] = gv[2] + ge2;
-        gd = gd + gsv * ph2.t;
-        // d = dw / |dw|, dw = R dc, o = T
-        const V3 gdw = project_out(gd, d, sm.inv_len);
-        gcam[0] += gdw.x * sm.dc.x; gcam[1] += gdw.x * sm.dc.y; gcam[2] += gdw.x * sm.dc.z;
-        gcam[3] += gdw.y * sm.dc.x; gcam[4] += gdw.y * sm.dc.y; gcam[5] += gdw.y * sm.dc.z;
-        gcam[6] += gdw.z * sm.dc.x; gcam[7] += gdw.z * sm.dc.y; gcam[8] += gdw.z * sm.dc.z;
-        gcam[9] += gsv.x; gcam[10] += gsv.y; gcam[11] += gsv.z;
-        gr = grr;
-      }
-      // camera: wave reduction of this chunk into LDS
-      if (ballot(has_g)) {
-        for (int k = 0; k < 12; ++k) {
-          const float t = wave_sum(gcam[k]);
-          if (lane == 0 && t != 0.0f) atomicAdd(&lds[12 * a.L + k], to_fix(t));
-        }
-      }
-      // ---- per-vertex scatter: one atomic set per distinct triangle in the wave
-      uint64_t todo = ballot(has_g);
-      while (todo) {
-        const int leader = (int)__builtin_ctzll(todo);
-        const int key = readlane_i(h.id, leader);
-        const bool mine = has_g && h.id == key;
-        todo &= ~ballot(mine);
-        const int* tv = a.tris + 3 * key;
-        for (int k = 0; k < 3; ++k) {
-          const int vi = tv[k];
-          const float bk = bb[k];
-          if (TEX) {
-            // reflectance gradients go to the texels below
-            float vals[6] = {gv[k].x, gv[k].y, gv[k].z, gn[k].x, gn[k].y, gn[k].z};
-            for (int q = 0; q < 6; ++q) vals[q] = wave_sum(mine ? vals[q] : 0.0f);
-            if (lane == leader) {
-              if (g.verts) { fix_add(g.verts + 3 * vi, vals[0]); fix_add(g.verts + 3 * vi + 1, vals[1]); fix_add(g.verts + 3 * vi + 2, vals[2]); }
-              if (g.normals) { fix_add(g.normals + 3 * vi, vals[3]); fix_add(g.normals + 3 * vi + 1, vals[4]); fix_add(g.normals + 3 * vi + 2, vals[5]); }
-            }
-          } else {
-            float vals[13] = {gv[k].x, gv[k].y, gv[k].z, gn[k].x, gn[k].y, gn[k].z, gc.x * bk, gc.y * bk, gc.z * bk,
-                              gs.x * bk, gs.y * bk, gs.z * bk, gr * bk};
-            for (int q = 0; q < 13; ++q) vals[q] = wave_sum(mine ? vals[q] : 0.0f);
-            if (lane == leader) {
-              if (g.verts) { fix_add(g.verts + 3 * vi, vals[0]); fix_add(g.verts + 3 * vi + 1, vals[1]); fix_add(g.verts + 3 * vi + 2, vals[2]); }
-              if (g.normals) { fix_add(g.normals + 3 * vi, vals[3]); fix_add(g.normals + 3 * vi + 1, vals[4]); fix_add(g.normals + 3 * vi + 2, vals[5]); }
-              if (g.diffuse) { fix_add(g.diffuse + 3 * vi, vals[6]); fix_add(g.diffuse + 3 * vi + 1, vals[7]); fix_add(g.diffuse + 3 * vi + 2, vals[8]); }
-              if (g.specular) { fix_add(g.specular + 3 * vi, vals[9]); fix_add(g.specular + 3 * vi + 1, vals[10]); fix_add(g.specular + 3 * vi + 2, vals[11]); }
-              if (g.roughness) fix_add(g.roughness + vi, vals[12]);
+          uint64_t tdo = ballot(has_g);
+          while (tdo) {
+            const int leader = (int)__builtin_ctzll(tdo);
+            const int k00 = readlane_i(tp.t00, leader), k11 = readlane_i(tp.t11, leader);
+            const bool mine = has_g && tp.t00 == k00 && tp.t11 == k11;
+            tdo &= ~ballot(mine);
+            const int k10 = readlane_i(tp.t10, leader), k01 = readlane_i(tp.t01, leader);
+            const float fx = tp.fx, fy = tp.fy;
+            for (int q = 0; q < 4; ++q) {
+              const float w = q == 0 ? (1.0f - fx) * (1.0f - fy)
+                              : q == 1 ? fx * (1.0f - fy)
+                              : q == 2 ? (1.0f - fx) * fy : fx * fy;
+              const int t = q == 0 ? k00 : q == 1 ? k10 : q == 2 ? k01 : k11;
+              float rv[7] = {gc.x * w, gc.y * w, gc.z * w, gs.x * w, gs.y * w, gs.z * w, gr * w};
+              for (int c = 0; c < 7; ++c) rv[c] = wave_sum(mine ? rv[c] : 0.0f);
+              if (lane == leader) {
+                if (g.tex_c) { fix_add(g.tex_c + 3 * t, rv[0]); fix_add(g.tex_c + 3 * t + 1, rv[1]); fix_add(g.tex_c + 3 * t + 2, rv[2]); }
+                if (g.tex_s) { fix_add(g.tex_s + 3 * t, rv[3]); fix_add(g.tex_s + 3 * t + 1, rv[4]); fix_add(g.tex_s + 3 * t + 2, rv[5]); }
+                if (g.tex_r) fix_add(g.tex_r + t, rv[6]);
+              }
             }
           }
         }
       }
-      // ---- per-texel scatter (maps in use): lanes with the same bilinear
-      // footprint (its first and last texel fix the other two) reduce together
-      if (TEX) {
-        uint64_t tdo = ballot(has_g);
-        while (tdo) {
-          const int leader = (int)__builtin_ctzll(tdo);
-          const int k00 = readlane_i(tp.t00, leader), k11 = readlane_i(tp.t11, leader);
-          const bool mine = has_g && tp.t00 == k00 && tp.t11 == k11;
-          tdo &= ~ballot(mine);
-          const int k10 = readlane_i(tp.t10, leader), k01 = readlane_i(tp.t01, leader);
-          const float fx = tp.fx, fy = tp.fy;
-          for (int q = 0; q < 4; ++q) {
-            const float w = q == 0 ? (1.0f - fx) * (1.0f - fy)
-                            : q == 1 ? fx * (1.0f - fy)
-                            : q == 2 ? (1.0f - fx) * fy : fx * fy;
-            const int t = q == 0 ? k00 : q == 1 ? k10 : q == 2 ? k01 : k11;
-            float rv[7] = {gc.x * w, gc.y * w, gc.z * w, gs.x * w, gs.y * w, gs.z * w, gr * w};
-            for (int c = 0; c < 7; ++c) rv[c] = wave_sum(mine ? rv[c] : 0.0f);
-            if (lane == leader) {
-              if (g.tex_c) { fix_add(g.tex_c + 3 * t, rv[0]); fix_add(g.tex_c + 3 * t + 1, rv[1]); fix_add(g.tex_c + 3 * t + 2, rv[2]); }
-              if (g.tex_s) { fix_add(g.tex_s + 3 * t, rv[3]); fix_add(g.tex_s + 3 * t + 1, rv[4]); fix_add(g.tex_s + 3 * t + 2, rv[5]); }
-              if (g.tex_r) fix_add(g.tex_r + t, rv[6]);
-            }
-          }
-        }
+      if (a.chunks > 1) __syncthreads();
+      if (a.chunks == 1 && run) {
+        // every other wave has arrived: their LDS sums are complete
+        fix_t* slot = slots + (size_t)(bid % kSlots) * nl;
+        for (int i = lane; i < nl; i += 64)
+          if (lds[i] != 0) atomicAdd(slot + i, lds[i]);
       }
     }
   }
-  __syncthreads();
-  fix_t* slot = slots + (size_t)(bid % kSlots) * nl;
-  for (int i = threadIdx.x; i < nl; i += 256)
-    if (lds[i] != 0) atomicAdd(slot + i, lds[i]);
+  if (a.chunks > 1) {
+    __syncthreads();
+    fix_t* slot = slots + (size_t)(bid % kSlots) * nl;
+    for (int i = threadIdx.x; i < nl; i += 256)
+      if (lds[i] != 0) atomicAdd(slot + i, lds[i]);
+  }
 }
 
 template <bool TEX>
@@ -389,13 +435,14 @@ void launch_render_backward(const RenderArgs& a, const float* dEdp, const FixGra
                             const fr_grads& g, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const int nl = a.L * 12 + 12;
   launch_zero_fix(slots, (size_t)kSlots * nl, st);
-  const int blocks = wave_blocks_items(a);
+  const int blocks = tile_blocks(a);
+  const size_t lds = nl * sizeof(fix_t) + kBwdPartBytes;
   if (e0) (void)hipEventRecord(e0, st);
   launch_primary(a, st);
   if (a.M > 0)
-    hipLaunchKernelGGL(k_render_bwd<true>, dim3(blocks), dim3(256), nl * sizeof(fix_t), st, a, dEdp, fg, slots);
+    hipLaunchKernelGGL(k_render_bwd<true>, dim3(blocks), dim3(256), lds, st, a, dEdp, fg, slots);
   else
-    hipLaunchKernelGGL(k_render_bwd<false>, dim3(blocks), dim3(256), nl * sizeof(fix_t), st, a, dEdp, fg, slots);
+    hipLaunchKernelGGL(k_render_bwd<false>, dim3(blocks), dim3(256), lds, st, a, dEdp, fg, slots);
   if (e1) (void)hipEventRecord(e1, st);
   hipLaunchKernelGGL(k_slots_reduce, dim3(nl), dim3(256), 0, st, slots, nl, a.L, g.light_geom, g.light_rad, g.cam);
 }

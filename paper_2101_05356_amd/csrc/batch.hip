@@ -168,7 +168,7 @@ static int stage_blocks(const JobDev& J, int s) {
     case S_LOSS: case S_SMOOTH_ADJ: return cdiv(px, 256);
     case S_LOSS_FINAL: return 1;
     case S_ZERO_GRADS: return cdiv(std::max(J.n_param, 3 * N), 256);
-    case S_BWD: return wave_blocks_items(J.rb);
+    case S_BWD: return tile_blocks(J.rb);
     case S_SLOTS: return 12 * J.ra.L + 12;
     case S_EDGE_LEN: return J.ea.n_samples > 0 ? cdiv(J.ea.E, 256) : 0;
     case S_EDGE_SCAN: case S_EDGE_SCAN_ADD: return J.ea.n_samples > 0 ? cdiv(J.ea.E, kScanTile) : 0;
@@ -247,7 +247,7 @@ void Batch::launch_step(hipStream_t st) {
   FR_LAUNCH(kb_smooth_adjoint, S_SMOOTH_ADJ, 256, 0);
   FR_LAUNCH(kb_zero_grads, S_ZERO_GRADS, 256, 0);
   FR_LAUNCH(kb_primary, S_PRIM, 256, 0);   // the backward traces its own primary hits
-  FR_LAUNCH(kb_render_bwd, S_BWD, 256, max_nl * sizeof(fix_t));
+  FR_LAUNCH(kb_render_bwd, S_BWD, 256, max_nl * sizeof(fix_t) + kBwdPartBytes);
   FR_LAUNCH(kb_slots_reduce, S_SLOTS, 256, 0);
   FR_LAUNCH(kb_normals_bwd_project, S_NBWD_P, 256, 0);
   FR_LAUNCH(kb_normals_bwd_gather, S_NBWD_G, 256, 0);

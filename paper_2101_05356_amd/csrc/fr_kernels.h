@@ -194,7 +194,8 @@ void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st, hi
 // backward repeats more per-item work (primary trace, chain, scatter), so it
 // takes longer items.
 constexpr int kLightChunkFwd = 12;
-constexpr int kLightChunkBwd = 24;
+constexpr int kBwdMaxLights = 128;   // four chunks of at most 32 lights
+constexpr size_t kBwdPartBytes = 4 * 64 * 16 * sizeof(float) + 16;   // backward LDS: sample adjoints of 4 waves, arrivals
 // The boundary term has one wave per 64 edge samples and light chunk: short
 // chunks give the launch enough waves to fill the chip.
 constexpr int kLightChunkEdge = 12;

@@ -47,6 +47,20 @@ inline int wave_blocks_items(const RenderArgs& a, int nl) {
 }
 inline int wave_blocks_items(const RenderArgs& a) { return wave_blocks_items(a, a.n_lchunks); }
 
+// One tile per block (the backward, whose four waves are the tile's light
+// chunks): the same XCD-aware strip order as wave_item.
+__device__ __forceinline__ int block_tile(const RenderArgs& a, int b) {
+  const int per_strip = a.tiles_x * 4;                 // tiles per strip of 4 tile rows
+  const int x = b & 7, k = b >> 3;
+  const int si = k / per_strip, bi = k - si * per_strip;
+  const int tile = (si * 8 + x) * per_strip + bi;
+  return tile / a.tiles_x < a.tiles_y ? tile : -1;
+}
+inline int tile_blocks(const RenderArgs& a) {
+  const int strips = (a.tiles_y + 3) / 4;
+  return 8 * a.tiles_x * 4 * ((strips + 7) / 8);
+}
+
 struct PixelSample {
   int px, py, pid, s0;
   bool valid;
