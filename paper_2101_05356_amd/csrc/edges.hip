@@ -142,10 +142,10 @@ __global__ __launch_bounds__(256) void k_edge_scan_add(double* __restrict__ cdf,
   edge_scan_add_block(cdf, E, part, blockIdx.x);
 }
 
-// Shaded radiance (no 1/S) of the camera ray through film point (fx, fy).
-template <bool DUMP, bool TEX>
-__device__ __forceinline__ void side_radiance(const RenderArgs& a, float fx, float fy, bool active, int k, int j0,
-                                              int j1, V3& L, int& hit_id, bool& amb) {
+// Side ray through film point (fx, fy): its closest hit with the FP64
+// barycentrics of the crossing (traced once per edge sample and side).
+template <bool DUMP>
+__device__ __forceinline__ PrimHit side_trace(const RenderArgs& a, float fx, float fy, bool active, bool& amb) {
   Sample sm;
   camera_ray_film(a, fx, fy, sm);
   HitState h;
@@ -153,11 +153,30 @@ __device__ __forceinline__ void side_radiance(const RenderArgs& a, float fx, flo
   bool dummy = false;
   trace<false, DUMP>(a.nodes, a.recs, a.F, sm.ray, active, -1, h, dummy);
   if (DUMP && active && hit_ambiguous(h)) amb = true;
-  hit_id = h.id;
+  PrimHit ph = {active ? h.id : -1, h.t, 0.0, 0.0};
+  if (ph.id >= 0) {
+    const int* t = a.tris + 3 * h.id;
+    const int vi[3] = {t[0], t[1], t[2]};
+    double bd[3];
+    bary64(a, (double)fx, (double)fy, vi, bd);
+    ph.b1 = bd[1];
+    ph.b2 = bd[2];
+  }
+  return ph;
+}
+
+// Shaded radiance (no 1/S) of the side ray through (fx, fy) with hit ph, over
+// lights [j0, j1).
+template <bool DUMP, bool TEX>
+__device__ __forceinline__ V3 side_shade(const RenderArgs& a, float fx, float fy, const PrimHit& ph, int k, int j0,
+                                         int j1, bool& amb) {
+  Sample sm;
+  camera_ray_film(a, fx, fy, sm);
+  const double bd[3] = {1.0 - ph.b1 - ph.b2, ph.b1, ph.b2};
   Frame fr = {};
-  const bool shaded = active && h.id >= 0 && shading_frame<TEX>(a, sm, h, fr, (double)fx, (double)fy);
-  if (DUMP && active && h.id >= 0 && fabsf(fr.cos_o) < kFlagCos) amb = true;
-  L = {0.0f, 0.0f, 0.0f};
+  const bool shaded = ph.id >= 0 && shading_frame<TEX>(a, sm, ph.id, ph.t, bd, fr);
+  if (DUMP && ph.id >= 0 && fabsf(fr.cos_o) < kFlagCos) amb = true;
+  V3 L = {0.0f, 0.0f, 0.0f};
   // shadow decisions of every light of the chunk, then the shading of the visible ones
   const auto draw = [&](int j) { return philox((uint32_t)k, 0u, PURPOSE_EDGE + 1u + (uint32_t)j, a.step, a.k0, a.k1); };
   const auto note = [&](int, bool lit, bool, const LightSample& ls, const HitState& sh) {
@@ -165,7 +184,7 @@ __device__ __forceinline__ void side_radiance(const RenderArgs& a, float fx, flo
     if (lit && sh.tamb < 3.0e38f) amb = true;
   };
   const auto skip = [](int) {};
-  const uint32_t vmask = shadow_mask<DUMP>(a, j0, j1, shaded, fr, h.id, draw, note, skip, nullptr);
+  const uint32_t vmask = shadow_mask<DUMP>(a, j0, j1, shaded, fr, ph.id, draw, note, skip, nullptr);
   for (int j = j0; j < j1; ++j) {
     const bool vis = (vmask >> (j - j0)) & 1u;
     if (!ballot(vis)) continue;
@@ -182,18 +201,23 @@ __device__ __forceinline__ void side_radiance(const RenderArgs& a, float fx, flo
       L.z += Lj.rad[2] * f[2] * ls.geom;
     }
   }
+  return L;
 }
 
-
-// One wave = 64 consecutive edge samples x one chunk of lights; the chunks of
-// one sample group are neighbouring waves of a block.
+// One block = 64 consecutive edge samples (lane = sample); its four waves are
+// the light chunks (lc >= L/4).  Waves 0 and 1 trace the minus and plus side
+// rays into LDS; every wave shades both sides with its lights; the last wave
+// to arrive sums the chunks in order and scatters the gradient once.
 template <bool DUMP, bool TEX>
 __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const EdgeArgs& e, int bid) {
-  const int lane = threadIdx.x & 63;
-  const int w = bid * 4 + (threadIdx.x >> 6);
-  const int group = w / e.n_lchunks, chunk = w - group * e.n_lchunks;
-  const int j0 = chunk * e.lc, j1 = min(a.L, j0 + e.lc);
+  __shared__ PrimHit side_hit[2][64];
+  __shared__ float side_L[4][64][6];
+  __shared__ int arrived;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int group = bid;
+  const int j0 = wv * e.lc, j1 = min(a.L, j0 + e.lc);
   const int k = group * 64 + lane;
+  if (threadIdx.x == 0) arrived = 0;
   const bool in = k < e.n_samples;
   const double ltot = e.cdf[e.E - 1];
   int eid = 0, pid = -1;
@@ -227,21 +251,38 @@ __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const Ed
     pax = pa.x; pay = pa.y; paz = pa.z; pbz = pb.z;
   }
   const bool active = pid >= 0;
-  V3 Lm, Lp;
-  int hm = -1, hp = -1;
-  side_radiance<DUMP, TEX>(a, fx - 1e-3f * mx, fy - 1e-3f * my, active, k, j0, j1, Lm, hm, amb);
-  side_radiance<DUMP, TEX>(a, fx + 1e-3f * mx, fy + 1e-3f * my, active, k, j0, j1, Lp, hp, amb);
+  const float fxm = fx - 1e-3f * mx, fym = fy - 1e-3f * my, fxp = fx + 1e-3f * mx, fyp = fy + 1e-3f * my;
+  if (wv < 2) side_hit[wv][lane] = side_trace<DUMP>(a, wv ? fxp : fxm, wv ? fyp : fym, active, amb);
+  __syncthreads();
+  const PrimHit hm = side_hit[0][lane], hp = side_hit[1][lane];
+  const V3 Lm = side_shade<DUMP, TEX>(a, fxm, fym, hm, k, j0, j1, amb);
+  const V3 Lp = side_shade<DUMP, TEX>(a, fxp, fyp, hp, k, j0, j1, amb);
   if (DUMP && in) {
-    if (chunk == 0) {
-      e.dbg_rec[4 * k] = eid; e.dbg_rec[4 * k + 1] = pid; e.dbg_rec[4 * k + 2] = hm; e.dbg_rec[4 * k + 3] = hp;
+    if (wv == 0) {
+      e.dbg_rec[4 * k] = eid; e.dbg_rec[4 * k + 1] = pid; e.dbg_rec[4 * k + 2] = hm.id; e.dbg_rec[4 * k + 3] = hp.id;
     }
-    if (amb) e.dbg_flag[k] = 1;   // OR over chunks: the caller zeroes the flags
+    if (amb) e.dbg_flag[k] = 1;   // OR over the waves: the caller zeroes the flags
+  }
+  {
+    float* q = side_L[wv][lane];
+    q[0] = Lm.x; q[1] = Lm.y; q[2] = Lm.z; q[3] = Lp.x; q[4] = Lp.y; q[5] = Lp.z;
+  }
+  __threadfence_block();
+  int n_arr = 0;
+  if (lane == 0) n_arr = atomicAdd(&arrived, 1);
+  if (__builtin_amdgcn_readlane(n_arr, 0) != 3) return;   // another wave finishes this group
+  __threadfence_block();
+  V3 Sm = {0.0f, 0.0f, 0.0f}, Sp = {0.0f, 0.0f, 0.0f};
+  for (int c = 0; c < e.n_lchunks; ++c) {
+    const float* q = side_L[c][lane];
+    Sm = Sm + V3{q[0], q[1], q[2]};
+    Sp = Sp + V3{q[3], q[4], q[5]};
   }
   float gcam[12];
   for (int q = 0; q < 12; ++q) gcam[q] = 0.0f;
   if (active) {
-    const float dl = (Lm.x - Lp.x) * e.dEdp[3 * pid] + (Lm.y - Lp.y) * e.dEdp[3 * pid + 1] +
-                     (Lm.z - Lp.z) * e.dEdp[3 * pid + 2];
+    const float dl = (Sm.x - Sp.x) * e.dEdp[3 * pid] + (Sm.y - Sp.y) * e.dEdp[3 * pid + 1] +
+                     (Sm.z - Sp.z) * e.dEdp[3 * pid + 2];
     const float wgt = (float)(ltot / (double)e.n_samples) * dl;
     if (wgt != 0.0f) {
       // film velocity of X(w) = (1 - w) A + w B, w perspective-correct
@@ -300,10 +341,9 @@ void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samp
   e.edges = m.edges; e.cdf = m.edge_cdf; e.E = m.E; e.n_samples = n_samples;
   e.th = tan_half; e.aspect = aspect; e.dEdp = dEdp; e.gverts = gverts; e.gcam = gcam;
   e.dbg_rec = dbg_rec; e.dbg_flag = dbg_flag;
-  e.lc = std::max(1, std::min(kLightChunkEdge, a.L));
+  e.lc = std::max(1, cdiv(a.L, 4));   // the four waves of a block
   e.n_lchunks = std::max(1, cdiv(a.L, e.lc));
-  const int groups = (n_samples + 63) / 64;
-  const int blocks = (groups * e.n_lchunks + 3) / 4;
+  const int blocks = (n_samples + 63) / 64;
   if (a.M > 0) {
     if (dbg_rec)
       hipLaunchKernelGGL((k_edge_samples<true, true>), dim3(blocks), dim3(256), 0, st, a, e);

@@ -198,7 +198,6 @@ constexpr int kBwdMaxLights = 128;   // four chunks of at most 32 lights
 constexpr size_t kBwdPartBytes = 4 * 64 * 16 * sizeof(float) + 16;   // backward LDS: sample adjoints of 4 waves, arrivals
 // The boundary term has one wave per 64 edge samples and light chunk: short
 // chunks give the launch enough waves to fill the chip.
-constexpr int kLightChunkEdge = 12;
 // Partial slots of the backward light/camera gradients (reduced in a fixed order).
 constexpr int kSlots = 1024;
 // loss.hip
