@@ -351,7 +351,7 @@ def main():
                                                       "frac": ops_f / (fwd_ms * 1e-3) / PEAK_LANE_OPS}}}
         cam_rays, sh_rays = stats[2], stats[5]
         out["traversal"] = {
-            "tree": "4-wide (collapsed LBVH), one triangle per leaf",
+            "tree": "binned-SAH binary tree collapsed to 4-wide, one triangle per leaf",
             "camera_rays": cam_rays, "shadow_rays_traced": sh_rays,
             "box_tests_per_camera_ray": stats[0] / max(cam_rays, 1),
             "tri_tests_per_camera_ray": stats[1] / max(cam_rays, 1),

@@ -161,8 +161,9 @@ typedef struct {
    * camera rays, then for shadow rays. */
   uint64_t* dbg_stats;
   /* Timing (nullable): two hipEvent_t recorded on the stream immediately
-   * before and after the main render kernel of the call (the forward render
-   * kernel, or the interior adjoint kernel of fr_render_backward). */
+   * before the primary pass (the camera rays of every sample) and after the
+   * main render kernel of the call (the forward render kernel, or the
+   * interior adjoint kernel of fr_render_backward). */
   void* ev_kernel_begin;
   void* ev_kernel_end;
 } fr_render_opts;
