@@ -79,9 +79,16 @@ __device__ __forceinline__ PixelSample pixel_sample(const RenderArgs& a, int til
   return p;
 }
 
-// Fixed-order butterfly sum over aligned groups of n lanes (n a power of 2).
+// Sum over aligned groups of n lanes (n a power of 2, wave-uniform), every
+// lane of a group receiving its group's sum, in a fixed order: DPP within a
+// row of 16 lanes (quad swaps, half-row and row mirrors), LDS permutes
+// beyond.  All 64 lanes must be active.
 __device__ __forceinline__ float group_sum(float x, int n) {
-  for (int off = n >> 1; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  if (n >= 2) x = dpp_add<0xb1, 0xf>(x);    // quad_perm [1,0,3,2]
+  if (n >= 4) x = dpp_add<0x4e, 0xf>(x);    // quad_perm [2,3,0,1]
+  if (n >= 8) x = dpp_add<0x141, 0xf>(x);   // row_half_mirror
+  if (n >= 16) x = dpp_add<0x140, 0xf>(x);  // row_mirror
+  for (int off = 16; off < n; off <<= 1) x += __shfl_xor(x, off, 64);
   return x;
 }
 
