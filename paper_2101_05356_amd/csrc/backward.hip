@@ -77,10 +77,8 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
       double bd0[3] = {1.0, 0.0, 0.0};
       PrimHit ph = {-1, 0.0f, 0.0, 0.0};
       if (want) ph = load_prim(a, rs, bd0);
-      HitState h;
-      h.id = ph.id;
       Frame fr = {};
-      const bool shaded = want && h.id >= 0 && shading_frame<TEX>(a, sm, ph.id, ph.t, bd0, fr);
+      const bool shaded = want && ph.id >= 0 && shading_frame<TEX>(a, sm, ph.id, ph.t, bd0, fr);
       // sample-level adjoint accumulators
       V3 gx = {0, 0, 0}, gns = {0, 0, 0}, gwo = {0, 0, 0}, gc = {0, 0, 0}, gs = {0, 0, 0};
       float gr = 0.0f;
@@ -88,7 +86,7 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
       const auto draw = [&](int j) { return philox((uint32_t)ps.pid, (uint32_t)s, 1u + (uint32_t)j, a.step, a.k0, a.k1); };
       const auto none = [](int, bool, bool, const LightSample&, const HitState&) {};
       const auto skip = [](int) {};
-      const uint32_t vmask = shadow_mask<false>(a, j0, j1, shaded, fr, h.id, draw, none, skip, nullptr);
+      const uint32_t vmask = shadow_mask<false>(a, j0, j1, shaded, fr, ph.id, draw, none, skip, nullptr);
       for (int j = j0; j < j1; ++j) {
         const bool vis = (vmask >> (j - j0)) & 1u;
         if (!ballot(vis)) continue;
@@ -320,8 +318,8 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
         uint64_t todo = ballot(has_g);
         while (todo) {
           const int leader = (int)__builtin_ctzll(todo);
-          const int key = readlane_i(h.id, leader);
-          const bool mine = has_g && h.id == key;
+          const int key = readlane_i(ph.id, leader);
+          const bool mine = has_g && ph.id == key;
           todo &= ~ballot(mine);
           const int* tv = a.tris + 3 * key;
           for (int k = 0; k < 3; ++k) {

@@ -103,10 +103,8 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
     double bd[3] = {1.0, 0.0, 0.0};
     PrimHit ph = {-1, 0.0f, 0.0, 0.0};
     if (ps.valid) ph = load_prim(a, rs, bd);
-    HitState h;
-    h.id = ph.id;
     Frame fr;
-    const bool shaded = ps.valid && h.id >= 0 && shading_frame<TEX>(a, sm, ph.id, ph.t, bd, fr);
+    const bool shaded = ps.valid && ph.id >= 0 && shading_frame<TEX>(a, sm, ph.id, ph.t, bd, fr);
     // shadow decisions of every light of the chunk, then the shading of the visible ones
     const auto draw = [&](int j) { return philox((uint32_t)ps.pid, (uint32_t)s, 1u + (uint32_t)j, a.step, a.k0, a.k1); };
     const auto note = [&](int j, bool lit, bool occ, const LightSample& ls, const HitState& sh) {
@@ -119,7 +117,7 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
     const auto skip = [&](int j) {
       if (DUMP && ps.valid) a.dbg_vis[rs * a.L + j] = shaded ? VIS_CULLED : VIS_NONE;
     };
-    const uint32_t vmask = shadow_mask<DUMP>(a, j0, j1, shaded, fr, h.id, draw, note, skip, &st2);
+    const uint32_t vmask = shadow_mask<DUMP>(a, j0, j1, shaded, fr, ph.id, draw, note, skip, &st2);
     for (int j = j0; j < j1; ++j) {
       const bool vis = (vmask >> (j - j0)) & 1u;
       if (!ballot(vis)) continue;
