@@ -26,10 +26,12 @@ __device__ __forceinline__ D3 crossd(D3 a, D3 b) {
 __device__ __forceinline__ void normals_block(const float* __restrict__ v, const int32_t* __restrict__ tris,
                                                  const int32_t* __restrict__ off, const int32_t* __restrict__ idx, int N,
                                                  float* __restrict__ n, float* __restrict__ nlen, int bid) {
-  const int i = bid * 256 + threadIdx.x;
+  const int i = bid * (int)blockDim.x + threadIdx.x;
   if (i >= N) return;
   D3 acc = {0.0, 0.0, 0.0};
-  for (int k = off[i]; k < off[i + 1]; ++k) {
+  const int k0 = off[i], k1 = off[i + 1];
+#pragma unroll 4
+  for (int k = k0; k < k1; ++k) {
     const int f = idx[k];
     const D3 a = d3(v, tris[3 * f]);
     acc = acc + crossd(d3(v, tris[3 * f + 1]) - a, d3(v, tris[3 * f + 2]) - a);
@@ -53,10 +55,12 @@ __device__ __forceinline__ void normals_bwd_project_block(const float* __restric
                                                              const int32_t* __restrict__ idx, int N,
                                                              const fix_t* __restrict__ gacc,
                                                              float* __restrict__ g, int bid) {
-  const int i = bid * 256 + threadIdx.x;
+  const int i = bid * (int)blockDim.x + threadIdx.x;
   if (i >= N) return;
   D3 acc = {0.0, 0.0, 0.0};
-  for (int k = off[i]; k < off[i + 1]; ++k) {
+  const int k0 = off[i], k1 = off[i + 1];
+#pragma unroll 4
+  for (int k = k0; k < k1; ++k) {
     const int f = idx[k];
     const D3 a = d3(v, tris[3 * f]);
     acc = acc + crossd(d3(v, tris[3 * f + 1]) - a, d3(v, tris[3 * f + 2]) - a);
@@ -87,10 +91,12 @@ __device__ __forceinline__ void normals_bwd_gather_block(const float* __restrict
                                                             const int32_t* __restrict__ idx, int N,
                                                             const float* __restrict__ gN, fix_t* __restrict__ gv,
                                                             int bid) {
-  const int i = bid * 256 + threadIdx.x;
+  const int i = bid * (int)blockDim.x + threadIdx.x;
   if (i >= N) return;
   D3 acc = {0.0, 0.0, 0.0};
-  for (int k = off[i]; k < off[i + 1]; ++k) {
+  const int k0 = off[i], k1 = off[i + 1];
+#pragma unroll 4
+  for (int k = k0; k < k1; ++k) {
     const int f = idx[k];
     const int i0 = tris[3 * f], i1 = tris[3 * f + 1], i2 = tris[3 * f + 2];
     const D3 g = d3(gN, i0) + d3(gN, i1) + d3(gN, i2);
@@ -112,16 +118,19 @@ __global__ __launch_bounds__(256) void k_normals_bwd_gather(const float* __restr
   normals_bwd_gather_block(v, tris, off, idx, N, gN, gv, blockIdx.x);
 }
 
+// One-wave blocks: a face-scale mesh gives a few hundred of them, spread over
+// all CUs (256-thread blocks would leave most CUs idle on these latency-bound
+// adjacency loops).
 void launch_normals(MeshDev& m, const float* d_verts, hipStream_t st) {
-  hipLaunchKernelGGL(k_normals, dim3(cdiv(m.N, 256)), dim3(256), 0, st, d_verts, m.tris, m.vf_off, m.vf_idx, m.N,
+  hipLaunchKernelGGL(k_normals, dim3(cdiv(m.N, 64)), dim3(64), 0, st, d_verts, m.tris, m.vf_off, m.vf_idx, m.N,
                      m.normals, m.nlen);
 }
 
 void launch_normals_backward(MeshDev& m, const float* d_verts, const fix_t* acc_n, float* gn_tmp, fix_t* acc_v,
                              hipStream_t st) {
-  hipLaunchKernelGGL(k_normals_bwd_project, dim3(cdiv(m.N, 256)), dim3(256), 0, st, d_verts, m.tris, m.vf_off,
+  hipLaunchKernelGGL(k_normals_bwd_project, dim3(cdiv(m.N, 64)), dim3(64), 0, st, d_verts, m.tris, m.vf_off,
                      m.vf_idx, m.N, acc_n, gn_tmp);
-  hipLaunchKernelGGL(k_normals_bwd_gather, dim3(cdiv(m.N, 256)), dim3(256), 0, st, d_verts, m.tris, m.vf_off,
+  hipLaunchKernelGGL(k_normals_bwd_gather, dim3(cdiv(m.N, 64)), dim3(64), 0, st, d_verts, m.tris, m.vf_off,
                      m.vf_idx, m.N, gn_tmp, acc_v);
 }
 
@@ -159,6 +168,8 @@ __device__ __forceinline__ void blend_block(const float* __restrict__ mean, cons
   const int m = bid * 256 + threadIdx.x;
   if (m >= M) return;
   float acc = mean[m];
+  // loads issued 16 components ahead of the (ordered) accumulation
+#pragma unroll 16
   for (int k = 0; k < K; ++k) acc = fmaf(coef[k], __builtin_nontemporal_load(basis + (size_t)k * M + m), acc);
   out[m] = acc;
 }
