@@ -155,7 +155,8 @@ static int stage_blocks(const JobDev& J, int s) {
   const int N = J.N, F = J.F, px = J.ra.W * J.ra.H;
   switch (s) {
     case S_BLEND_GEO: case S_BLEND_ALB: return cdiv(J.M, 256);
-    case S_POSE: case S_NORMALS: case S_NBWD_P: case S_NBWD_G: case S_POSE_BWD_V: return cdiv(N, 256);
+    case S_POSE: case S_POSE_BWD_V: return cdiv(N, 256);
+    case S_NORMALS: case S_NBWD_P: case S_NBWD_G: return normals_blocks(N);
     case S_FIX_FINALIZE: return cdiv(3 * N, 256);
     case S_REFIT: return cdiv(F, kRefitTile);
     case S_REFIT_TOP: return J.n_top_levels > 0 ? 1 : 0;

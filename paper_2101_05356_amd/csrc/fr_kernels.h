@@ -170,6 +170,8 @@ struct RenderArgs {
 int bvh_build(MeshDev& m, const float* d_verts, hipStream_t st, bool sah, int* depth_out);
 void bvh_refit(MeshDev& m, const float* d_verts, hipStream_t st);
 // model.hip
+// Blocks of 256 threads for the vertex-normal kernels over N vertices.
+int normals_blocks(int N);
 void launch_normals(MeshDev& m, const float* d_verts, hipStream_t st);
 void launch_normals_backward(MeshDev& m, const float* d_verts, const fix_t* acc_n, float* gn_tmp, fix_t* acc_v,
                              hipStream_t st);

@@ -8,11 +8,18 @@ namespace fr {
 // ---------------------------------------------------------------------------
 // Vertex normals: n_i = N_i / |N_i|, N_i = sum over incident faces of
 // (v1 - v0) x (v2 - v0), gathered per vertex through the vertex->face CSR
-// (no atomics, fixed order).  FP64: the edge vectors of a fine mesh are short
-// differences of O(1) coordinates, and the normal adjoint sums one-ring terms
-// that largely cancel, so FP32 would lose ~1e-5 relative there.  These
-// kernels are a negligible part of a step.
+// (no atomics).  FP64: the edge vectors of a fine mesh are short differences
+// of O(1) coordinates, and the normal adjoint sums one-ring terms that largely
+// cancel, so FP32 would lose ~1e-5 relative there.
+//
+// Eight lanes per vertex: lane s of the group takes the incident faces
+// s, s + 8, ... (all of them for valence <= 8, so one round of the dependent
+// CSR -> face -> vertex loads), and the group sums its partials with a fixed
+// xor butterfly, which leaves the same bits in all eight lanes.  A face-scale
+// mesh then fills the chip instead of giving each SIMD less than one wave.
 // ---------------------------------------------------------------------------
+constexpr int kVtxLanes = 8;
+
 struct D3 { double x, y, z; };
 __device__ __forceinline__ D3 d3(const float* __restrict__ p, int i) {
   return {(double)p[3 * i], (double)p[3 * i + 1], (double)p[3 * i + 2]};
@@ -22,20 +29,41 @@ __device__ __forceinline__ D3 operator-(D3 a, D3 b) { return {a.x - b.x, a.y - b
 __device__ __forceinline__ D3 crossd(D3 a, D3 b) {
   return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
-
-__device__ __forceinline__ void normals_block(const float* __restrict__ v, const int32_t* __restrict__ tris,
-                                                 const int32_t* __restrict__ off, const int32_t* __restrict__ idx, int N,
-                                                 float* __restrict__ n, float* __restrict__ nlen, int bid) {
-  const int i = bid * (int)blockDim.x + threadIdx.x;
-  if (i >= N) return;
+// Sum over the eight lanes of a group; every lane of the wave must call it.
+__device__ __forceinline__ D3 group8_sum(D3 a) {
+#pragma unroll
+  for (int m = 1; m < kVtxLanes; m <<= 1)
+    a = a + D3{__shfl_xor(a.x, m, kVtxLanes), __shfl_xor(a.y, m, kVtxLanes), __shfl_xor(a.z, m, kVtxLanes)};
+  return a;
+}
+// Vertex of this lane's group, and the lane's index in the group.
+__device__ __forceinline__ int group_vertex(int bid, int& sub) {
+  const int t = bid * (int)blockDim.x + (int)threadIdx.x;
+  sub = t & (kVtxLanes - 1);
+  return t / kVtxLanes;
+}
+// This lane's share of N_i (zero for lanes past the last vertex).
+__device__ __forceinline__ D3 face_normal_part(const float* __restrict__ v, const int32_t* __restrict__ tris,
+                                               const int32_t* __restrict__ off, const int32_t* __restrict__ idx,
+                                               int N, int i, int sub) {
   D3 acc = {0.0, 0.0, 0.0};
-  const int k0 = off[i], k1 = off[i + 1];
-#pragma unroll 4
-  for (int k = k0; k < k1; ++k) {
+  if (i >= N) return acc;
+  const int k1 = off[i + 1];
+  for (int k = off[i] + sub; k < k1; k += kVtxLanes) {
     const int f = idx[k];
     const D3 a = d3(v, tris[3 * f]);
     acc = acc + crossd(d3(v, tris[3 * f + 1]) - a, d3(v, tris[3 * f + 2]) - a);
   }
+  return acc;
+}
+
+__device__ __forceinline__ void normals_block(const float* __restrict__ v, const int32_t* __restrict__ tris,
+                                                 const int32_t* __restrict__ off, const int32_t* __restrict__ idx, int N,
+                                                 float* __restrict__ n, float* __restrict__ nlen, int bid) {
+  int sub;
+  const int i = group_vertex(bid, sub);
+  const D3 acc = group8_sum(face_normal_part(v, tris, off, idx, N, i, sub));
+  if (i >= N || sub != 0) return;
   const double len = sqrt(acc.x * acc.x + acc.y * acc.y + acc.z * acc.z);
   n[3 * i] = (float)(acc.x / len); n[3 * i + 1] = (float)(acc.y / len); n[3 * i + 2] = (float)(acc.z / len);
   nlen[i] = (float)len;
@@ -48,23 +76,17 @@ __global__ __launch_bounds__(256) void k_normals(const float* __restrict__ v, co
 }
 
 // g_N_i = (I - n n^T) g_n_i / |N_i|, written in place over g_n.  n and |N| are
-// recomputed in FP64 from the vertices.
+// recomputed in FP64 from the vertices, by the same group sum as above.
 __device__ __forceinline__ void normals_bwd_project_block(const float* __restrict__ v,
                                                              const int32_t* __restrict__ tris,
                                                              const int32_t* __restrict__ off,
                                                              const int32_t* __restrict__ idx, int N,
                                                              const fix_t* __restrict__ gacc,
                                                              float* __restrict__ g, int bid) {
-  const int i = bid * (int)blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  D3 acc = {0.0, 0.0, 0.0};
-  const int k0 = off[i], k1 = off[i + 1];
-#pragma unroll 4
-  for (int k = k0; k < k1; ++k) {
-    const int f = idx[k];
-    const D3 a = d3(v, tris[3 * f]);
-    acc = acc + crossd(d3(v, tris[3 * f + 1]) - a, d3(v, tris[3 * f + 2]) - a);
-  }
+  int sub;
+  const int i = group_vertex(bid, sub);
+  const D3 acc = group8_sum(face_normal_part(v, tris, off, idx, N, i, sub));
+  if (i >= N || sub != 0) return;
   const double len = sqrt(acc.x * acc.x + acc.y * acc.y + acc.z * acc.z);
   const D3 nn = {acc.x / len, acc.y / len, acc.z / len};
   const D3 gg = {from_fix(gacc[3 * i]), from_fix(gacc[3 * i + 1]), from_fix(gacc[3 * i + 2])};
@@ -91,23 +113,26 @@ __device__ __forceinline__ void normals_bwd_gather_block(const float* __restrict
                                                             const int32_t* __restrict__ idx, int N,
                                                             const float* __restrict__ gN, fix_t* __restrict__ gv,
                                                             int bid) {
-  const int i = bid * (int)blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  int sub;
+  const int i = group_vertex(bid, sub);
   D3 acc = {0.0, 0.0, 0.0};
-  const int k0 = off[i], k1 = off[i + 1];
-#pragma unroll 4
-  for (int k = k0; k < k1; ++k) {
-    const int f = idx[k];
-    const int i0 = tris[3 * f], i1 = tris[3 * f + 1], i2 = tris[3 * f + 2];
-    const D3 g = d3(gN, i0) + d3(gN, i1) + d3(gN, i2);
-    const D3 p0 = d3(v, i0);
-    const D3 a = d3(v, i1) - p0, b = d3(v, i2) - p0;
-    const D3 ga = crossd(b, g), gb = crossd(g, a);
-    if (i == i0) acc = acc - (ga + gb);
-    else if (i == i1) acc = acc + ga;
-    else acc = acc + gb;
+  if (i < N) {
+    const int k1 = off[i + 1];
+    for (int k = off[i] + sub; k < k1; k += kVtxLanes) {
+      const int f = idx[k];
+      const int i0 = tris[3 * f], i1 = tris[3 * f + 1], i2 = tris[3 * f + 2];
+      const D3 g = d3(gN, i0) + d3(gN, i1) + d3(gN, i2);
+      const D3 p0 = d3(v, i0);
+      const D3 a = d3(v, i1) - p0, b = d3(v, i2) - p0;
+      const D3 ga = crossd(b, g), gb = crossd(g, a);
+      if (i == i0) acc = acc - (ga + gb);
+      else if (i == i1) acc = acc + ga;
+      else acc = acc + gb;
+    }
   }
-  // one thread owns vertex i: a plain read-modify-write of its accumulator
+  acc = group8_sum(acc);
+  if (i >= N || sub != 0) return;
+  // one lane owns vertex i: a plain read-modify-write of its accumulator
   gv[3 * i] += to_fix_d(acc.x); gv[3 * i + 1] += to_fix_d(acc.y); gv[3 * i + 2] += to_fix_d(acc.z);
 }
 
@@ -118,19 +143,18 @@ __global__ __launch_bounds__(256) void k_normals_bwd_gather(const float* __restr
   normals_bwd_gather_block(v, tris, off, idx, N, gN, gv, blockIdx.x);
 }
 
-// One-wave blocks: a face-scale mesh gives a few hundred of them, spread over
-// all CUs (256-thread blocks would leave most CUs idle on these latency-bound
-// adjacency loops).
+int normals_blocks(int N) { return cdiv(N, 256 / kVtxLanes); }
+
 void launch_normals(MeshDev& m, const float* d_verts, hipStream_t st) {
-  hipLaunchKernelGGL(k_normals, dim3(cdiv(m.N, 64)), dim3(64), 0, st, d_verts, m.tris, m.vf_off, m.vf_idx, m.N,
-                     m.normals, m.nlen);
+  hipLaunchKernelGGL(k_normals, dim3(normals_blocks(m.N)), dim3(256), 0, st, d_verts, m.tris, m.vf_off, m.vf_idx,
+                     m.N, m.normals, m.nlen);
 }
 
 void launch_normals_backward(MeshDev& m, const float* d_verts, const fix_t* acc_n, float* gn_tmp, fix_t* acc_v,
                              hipStream_t st) {
-  hipLaunchKernelGGL(k_normals_bwd_project, dim3(cdiv(m.N, 64)), dim3(64), 0, st, d_verts, m.tris, m.vf_off,
+  hipLaunchKernelGGL(k_normals_bwd_project, dim3(normals_blocks(m.N)), dim3(256), 0, st, d_verts, m.tris, m.vf_off,
                      m.vf_idx, m.N, acc_n, gn_tmp);
-  hipLaunchKernelGGL(k_normals_bwd_gather, dim3(cdiv(m.N, 64)), dim3(64), 0, st, d_verts, m.tris, m.vf_off,
+  hipLaunchKernelGGL(k_normals_bwd_gather, dim3(normals_blocks(m.N)), dim3(256), 0, st, d_verts, m.tris, m.vf_off,
                      m.vf_idx, m.N, gn_tmp, acc_v);
 }
 
@@ -187,6 +211,7 @@ __device__ __forceinline__ void blend_bwd_block(const float* __restrict__ basis,
   const int k = bid;
   const float* row = basis + (size_t)k * M;
   float acc = 0.0f;
+#pragma unroll 8
   for (int m = threadIdx.x; m < M; m += 1024) acc = fmaf(row[m], gout[m], acc);
   red[threadIdx.x] = acc;
   __syncthreads();
