@@ -161,11 +161,23 @@ typedef struct {
    * camera rays, then for shadow rays. */
   uint64_t* dbg_stats;
   /* Timing (nullable): two hipEvent_t recorded on the stream immediately
-   * before the primary pass (the camera rays of every sample) and after the
+   * before the primary pass (the camera rays of every sample; the main
+   * kernel, when the backward reuses the forward's hits) and after the
    * main render kernel of the call (the forward render kernel, or the
    * interior adjoint kernel of fr_render_backward). */
   void* ev_kernel_begin;
   void* ev_kernel_end;
+  /* fr_render_backward only: nonzero takes the camera-ray hits of every
+   * sample from the last render call on this mesh instead of tracing them
+   * again, when that call matches this one: same width, height, spp, seed,
+   * step, fov_y, vertex buffer, camera buffer, and no fr_mesh_update since.
+   * The caller vouches that the contents of the vertex and camera buffers
+   * are unchanged since then (the library compares pointers, not contents).
+   * On any mismatch the backward traces the hits itself.  Forward and
+   * backward with the same counters trace identical hits, so the gradients
+   * are bit-identical either way. */
+  int32_t reuse_primary;
+  int32_t opts_pad_;
 } fr_render_opts;
 
 /* Gradients of a backward pass; every pointer is nullable ("not requested")

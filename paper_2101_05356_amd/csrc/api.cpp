@@ -17,9 +17,30 @@ struct fr_ctx {
   std::string last_error;
 };
 
+// What the mesh's primary-hit buffer currently holds: the camera-ray hits of
+// the render call with these inputs (valid = false: nothing usable).
+struct PrimKey {
+  bool valid = false;
+  int32_t W = 0, H = 0, S = 0;
+  uint64_t seed = 0;
+  uint32_t step = 0;
+  float fov = 0.0f;
+  const float* verts = nullptr;
+  const float* cam = nullptr;
+  const void* buf = nullptr;
+  uint64_t version = 0;
+  bool operator==(const PrimKey& o) const {
+    return valid && o.valid && W == o.W && H == o.H && S == o.S && seed == o.seed && step == o.step &&
+           std::memcmp(&fov, &o.fov, sizeof(float)) == 0 && verts == o.verts && cam == o.cam && buf == o.buf &&
+           version == o.version;
+  }
+};
+
 struct fr_mesh {
   fr_ctx* ctx = nullptr;
   fr::MeshDev d;
+  uint64_t version = 0;   // bumped by every fr_mesh_update
+  PrimKey prim_key;
   std::vector<int32_t> h_edges, h_edge_faces;
   double* loss_scratch = nullptr;   // per-block loss partials
   float* loss_gtmp = nullptr;       // sign image before the adjoint smoothing
@@ -258,6 +279,7 @@ int fr_mesh_update(fr_mesh* m, const float* d_verts, int mode, fr_stream stream)
   if (mode != FR_REFIT && mode != FR_REBUILD && mode != FR_REBUILD_SAH)
     return fail(ctx, FR_ERR_INVALID_ARG, "bad mode");
   if (mode == FR_REFIT && !m->d.built) return fail(ctx, FR_ERR_INVALID_ARG, "refit before the first build");
+  ++m->version;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   fr::launch_normals(m->d, d_verts, st);
   if (mode != FR_REFIT) {
@@ -300,6 +322,17 @@ int bwd_chunks(fr_mesh* m, fr::RenderArgs& a) {
   return FR_OK;
 }
 
+PrimKey prim_key_of(const fr_mesh* m, const fr_scene* s) {
+  PrimKey k;
+  k.valid = true;
+  k.W = s->width; k.H = s->height; k.S = s->spp;
+  k.seed = s->seed; k.step = s->step; k.fov = s->fov_y;
+  k.verts = s->verts; k.cam = s->cam;
+  k.buf = m->d.prim;
+  k.version = m->version;
+  return k;
+}
+
 // The mesh's primary-hit buffer, grown to the call's W*H*S samples.
 int ensure_prim(fr_mesh* m, fr::RenderArgs& a) {
   const size_t need = (size_t)a.W * a.H * a.S;
@@ -339,9 +372,11 @@ int fr_render_forward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fl
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (s->n_lights > 0) fr::launch_light_setup(*s, m->d.lights, st);
+  m->prim_key.valid = false;
   fr::launch_render_forward(a, d_image, st, static_cast<hipEvent_t>(o->ev_kernel_begin),
                             static_cast<hipEvent_t>(o->ev_kernel_end));
   FR_HIP(m->ctx, hipGetLastError());
+  m->prim_key = prim_key_of(m, s);
   return FR_OK;
 }
 
@@ -422,8 +457,13 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
     fg.tex_s = g->tex_specular ? d.tex_acc + 3 * MM : nullptr;
     fg.tex_r = g->tex_roughness ? d.tex_acc + 6 * MM : nullptr;
   }
+  const PrimKey key = prim_key_of(m, s);
+  const bool trace = !(o->reuse_primary && m->prim_key == key);
+  m->prim_key.valid = false;
   fr::launch_render_backward(a, d_dEdp, fg, d.slots, *g, st, static_cast<hipEvent_t>(o->ev_kernel_begin),
-                             static_cast<hipEvent_t>(o->ev_kernel_end));
+                             static_cast<hipEvent_t>(o->ev_kernel_end), trace);
+  FR_HIP(m->ctx, hipGetLastError());
+  m->prim_key = key;
   if (g->normals) fr::launch_fix_to_float(acc_n, g->normals, 3 * d.N, st);
   if (g->verts) fr::launch_normals_backward(d, s->verts, acc_n, d.gnorm, acc_v, st);
   const int ns = o->edge_samples < 0 ? s->width * s->height : o->edge_samples;

@@ -430,13 +430,13 @@ __global__ __launch_bounds__(256) void k_slots_reduce(const fix_t* __restrict__ 
 
 // `slots` holds kSlots * (12 L + 12) accumulators (the caller sizes and owns it).
 void launch_render_backward(const RenderArgs& a, const float* dEdp, const FixGrads& fg, fix_t* slots,
-                            const fr_grads& g, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+                            const fr_grads& g, hipStream_t st, hipEvent_t e0, hipEvent_t e1, bool trace_primary) {
   const int nl = a.L * 12 + 12;
   launch_zero_fix(slots, (size_t)kSlots * nl, st);
   const int blocks = tile_blocks(a);
   const size_t lds = nl * sizeof(fix_t) + kBwdPartBytes;
   if (e0) (void)hipEventRecord(e0, st);
-  launch_primary(a, st);
+  if (trace_primary) launch_primary(a, st);
   if (a.M > 0)
     hipLaunchKernelGGL(k_render_bwd<true>, dim3(blocks), dim3(256), lds, st, a, dEdp, fg, slots);
   else

@@ -240,6 +240,8 @@ void Batch::launch_step(hipStream_t st) {
   FR_LAUNCH(kb_refit_top, S_REFIT_TOP, 1024, 0);
   FR_LAUNCH(kb_gather4, S_GATHER4, 256, 0);
   FR_LAUNCH(kb_light_setup, S_LIGHTS, 256, 0);
+  // camera-ray hits of every sample, read by the forward and again by the
+  // adjoint (nothing between them moves the geometry or the counters)
   FR_LAUNCH(kb_primary, S_PRIM, 256, 0);
   FR_LAUNCH(kb_render_fwd, S_FWD, 256, 0);
   FR_LAUNCH(kb_sum_chunks, S_SUM, 256, 0);
@@ -247,7 +249,6 @@ void Batch::launch_step(hipStream_t st) {
   FR_LAUNCH(kb_loss_final, S_LOSS_FINAL, 256, 0);
   FR_LAUNCH(kb_smooth_adjoint, S_SMOOTH_ADJ, 256, 0);
   FR_LAUNCH(kb_zero_grads, S_ZERO_GRADS, 256, 0);
-  FR_LAUNCH(kb_primary, S_PRIM, 256, 0);   // the backward traces its own primary hits
   FR_LAUNCH(kb_render_bwd, S_BWD, 256, max_nl * sizeof(fix_t) + kBwdPartBytes);
   FR_LAUNCH(kb_slots_reduce, S_SLOTS, 256, 0);
   FR_LAUNCH(kb_normals_bwd_project, S_NBWD_P, 256, 0);

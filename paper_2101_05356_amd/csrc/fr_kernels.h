@@ -208,8 +208,10 @@ void launch_loss(const float* img, const float* target, int W, int H, int smooth
 // backward.hip
 // Interior adjoint: per-vertex gradients into `fg`, light and camera
 // gradients into the slots and then added to g.light_geom, g.light_rad, g.cam.
+// With trace_primary false, a.prim already holds this call's camera-ray hits.
 void launch_render_backward(const RenderArgs& a, const float* dEdp, const FixGrads& fg, fix_t* slots,
-                            const fr_grads& g, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                            const fr_grads& g, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+                            bool trace_primary = true);
 // edges.hip
 void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samples, fix_t* gverts, fix_t* gcam,
                   int32_t* dbg_rec, uint8_t* dbg_flag, double tan_half, hipStream_t st);

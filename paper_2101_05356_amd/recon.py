@@ -164,7 +164,8 @@ class Reconstruction:
         self.grad.zero_()
         self.g_vobj.zero_()
         g = R.render_backward(self.mesh, sc, dEdp, job.brdf_variant, edge_samples=job.edge_samples,
-                              groups=("verts", "diffuse", "light_rad"), verts=self.v_w, events=ev.get("bwd"))
+                              groups=("verts", "diffuse", "light_rad"), verts=self.v_w, events=ev.get("bwd"),
+                              reuse_primary=True)
         R.pose_backward(self.v_obj, self.param[sl["pose"]], g["verts"], self.g_vobj, self.grad[sl["pose"]])
         R.blend_backward(mt.basis_geo, self.g_vobj, self.grad[sl["geo"]])
         R.blend_backward(mt.basis_alb, g["diffuse"], self.grad[sl["alb"]])

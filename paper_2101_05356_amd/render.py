@@ -223,9 +223,13 @@ TEX_GROUPS = ("tex_diffuse", "tex_specular", "tex_roughness")
 
 
 def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_variant=0, components=3,
-                    edge_samples=0, groups=GRAD_GROUPS, verts=None, edge_dump=False, light_chunk=0, events=None):
+                    edge_samples=0, groups=GRAD_GROUPS, verts=None, edge_dump=False, light_chunk=0, events=None,
+                    reuse_primary=False):
     """Gradients (dict of new tensors) of sum dEdp . image.  `events` (two
-    torch.cuda.Event with timing) bracket the interior adjoint kernel."""
+    torch.cuda.Event with timing) bracket the interior adjoint kernel.
+    `reuse_primary`: take the camera-ray hits of the last render of this mesh
+    when it had the same size, samples, counters, vertex and camera buffers
+    (their contents unchanged since; the library checks the rest)."""
     dev = sc.verts.device
     N, L, M = mesh.n_verts, sc.n_lights, sc.tex_size
     shapes = dict(verts=(N, 3), normals=(N, 3), diffuse=(N, 3), specular=(N, 3), roughness=(N,),
@@ -244,6 +248,7 @@ def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_varian
                None)
     s = sc.struct(verts)
     o = _opts(brdf_variant, components, edge_samples, dbg, light_chunk, events)
+    o.reuse_primary = int(bool(reuse_primary))
     check(lib().fr_render_backward(mesh.h, ctypes.byref(s), ctypes.byref(o), _p(dEdp.contiguous()), ctypes.byref(g),
                                    _stream()), mesh.ctx.h, "fr_render_backward")
     if edge_dump and dbg is not None:
@@ -316,7 +321,8 @@ class RenderFn(torch.autograd.Function):
         o = ctx.opts
         g = render_backward(ctx.mesh, ctx.sc, seed, o.get("brdf_variant", 0), o.get("components", 3),
                             o.get("edge_samples", 0),
-                            groups=("verts", "diffuse", "specular", "roughness", "light_geom", "light_rad", "cam"))
+                            groups=("verts", "diffuse", "specular", "roughness", "light_geom", "light_rad", "cam"),
+                            reuse_primary=True)
         lg = g["light_geom"]
         return (g["verts"], g["diffuse"], g["specular"], g["roughness"], lg[:, 0:3].contiguous(),
                 lg[:, 3:6].contiguous(), lg[:, 6:9].contiguous(), g["light_rad"], g["cam"], None, None, None, None)

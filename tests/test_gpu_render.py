@@ -194,3 +194,43 @@ def test_edge_term_parity_patch(oracle_lib):
         okc = G.grad_tol_ok(gc, eo["cam"], rel=2e-4)
         _note(f"edge grads: verts {okv}, cam {okc}")
         assert okv[1] < 2e-4 and okc[1] < 2e-4
+
+
+def test_backward_reusing_the_forward_hits_is_bit_identical(oracle_lib):
+    """fr_render_opts.reuse_primary: the adjoint takes the camera-ray hits the
+    forward stored when the calls match, and traces them itself otherwise
+    (other step counter, a mesh update in between, another size rendered in
+    between); every gradient equals that of a backward that traces its own."""
+    sc = scenes.face_render_scene(W=64, H=64, spp=4, n_lights=12)
+    rng = np.random.default_rng(8)
+    dEdp = torch.tensor(rng.normal(size=(64, 64, 3)).astype(np.float32)).cuda()
+    m, ds = G.gpu_setup(sc)
+    groups = ("verts", "diffuse", "light_geom", "light_rad", "cam")
+
+    def bwd(scene, reuse):
+        g = G.R.render_backward(m, scene, dEdp, edge_samples=-1, groups=groups, reuse_primary=reuse)
+        torch.cuda.synchronize()
+        return [G.to_np(g[k]) for k in groups]
+
+    def same(a, b):
+        return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+    s1, s2 = dataclasses.replace(ds, step=1), dataclasses.replace(ds, step=2)
+    want1, want2 = bwd(s1, False), bwd(s2, False)
+    assert not same(want1, want2)
+    G.R.render_forward(m, s1)
+    assert same(bwd(s1, True), want1)                    # matching forward: its hits
+    G.R.render_forward(m, s1)
+    assert same(bwd(s2, True), want2)                    # other counter: traced
+    G.R.render_forward(m, s2)
+    m.update(ds.verts, rebuild=False)
+    assert same(bwd(s2, True), want2)                    # mesh updated in between: traced
+    G.R.render_forward(m, s1)
+    big = scenes.face_render_scene(W=96, H=96, spp=8, n_lights=12)
+    mb = G.R.Mesh(G.ctx(), big.n_verts, big.tris)       # another mesh leaves this one's hits alone
+    db = G.R.DeviceScene.from_scene(big)
+    mb.update(db.verts, rebuild=True)
+    G.R.render_forward(mb, db)
+    assert same(bwd(s1, True), want1)
+    G.R.render_forward(m, dataclasses.replace(s1, spp=8))    # larger buffer on this mesh
+    assert same(bwd(s1, True), want1)
