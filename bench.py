@@ -75,14 +75,12 @@ def parse():
 
 def algorithmic_ops(stats, W, H, S, L, backward=False):
     """Lane-operations the algorithm needs for one render (forward: camera and
-    shadow traversals + shading) or one adjoint pass (backward: the shadow
-    traversals + ~3x shading; the camera-ray hits are the forward's, reused),
-    from the counted per-ray visits of the tree."""
+    shadow traversals + shading) or one adjoint pass (backward: ~3x shading;
+    the camera-ray hits and shadow decisions are the forward's, reused), from
+    the counted per-ray visits of the tree."""
     cam_box, cam_leaf, cam_rays, sh_box, sh_leaf, sh_rays = stats[:6]
     samples = W * H * S
-    trav = sh_box * C_BOX + sh_leaf * C_LEAF
-    if not backward:
-        trav += cam_box * C_BOX + cam_leaf * C_LEAF
+    trav = 0 if backward else (cam_box + sh_box) * C_BOX + (cam_leaf + sh_leaf) * C_LEAF
     shade = samples * (C_RNG + C_CAM) + cam_rays * C_FRAME + cam_rays * L * (C_RNG + C_LIGHT)
     shade += sh_rays * (C_SETUP + C_BRDF)
     if backward:
@@ -266,10 +264,10 @@ def large_bench(ctx, steps, warmup, edge_samples=-1, seed=51):
         v = vsets[i]
         m.update(v, rebuild=False)
         pair = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in ev}
-        img = R.render_forward(m, ds, verts=v, events=pair["fwd"] if timed else None)
+        img = R.render_forward(m, ds, verts=v, events=pair["fwd"] if timed else None, keep_shadows=True)
         E, dEdp = R.loss(img, target, smooth=True)
         R.render_backward(m, ds, dEdp, edge_samples=ns, groups=groups, verts=v,
-                          events=pair["bwd"] if timed else None, reuse_primary=True)
+                          events=pair["bwd"] if timed else None, reuse_forward=True)
         if timed:
             for k in ev:
                 ev[k].append(pair[k])

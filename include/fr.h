@@ -170,14 +170,20 @@ typedef struct {
   /* fr_render_backward only: nonzero takes the camera-ray hits of every
    * sample from the last render call on this mesh instead of tracing them
    * again, when that call matches this one: same width, height, spp, seed,
-   * step, fov_y, vertex buffer, camera buffer, and no fr_mesh_update since.
-   * The caller vouches that the contents of the vertex and camera buffers
-   * are unchanged since then (the library compares pointers, not contents).
-   * On any mismatch the backward traces the hits itself.  Forward and
-   * backward with the same counters trace identical hits, so the gradients
-   * are bit-identical either way. */
-  int32_t reuse_primary;
-  int32_t opts_pad_;
+   * step, fov_y, vertex buffer, camera buffer, and no fr_mesh_update since;
+   * and, when that call was a forward with keep_shadows set and the light
+   * buffers (light_p0, light_e1, light_e2, light_shape) and n_lights match
+   * too, its shadow decisions instead of tracing the shadow rays.  The
+   * caller vouches that the contents of those buffers are unchanged since
+   * then (the library compares pointers, not contents).  On any mismatch the
+   * backward traces what it cannot take.  Forward and backward with the same
+   * counters make identical decisions, so the gradients are bit-identical
+   * either way. */
+  int32_t reuse_forward;
+  /* fr_render_forward only: nonzero also keeps the shadow decision of every
+   * sample and light (one bit each, held by the mesh: 4 bytes per sample and
+   * chunk of light_chunk lights) for a backward with reuse_forward. */
+  int32_t keep_shadows;
 } fr_render_opts;
 
 /* Gradients of a backward pass; every pointer is nullable ("not requested")
@@ -218,7 +224,8 @@ int fr_loss(const float* d_image, const float* d_target, int32_t width, int32_t 
 
 /* Backward pass: the adjoint of fr_render_forward for a given dE/dp
  * d_dEdp [H*W*3], recomputing every intersection and shadow decision from the
- * same counters (no stored paths) and holding them fixed (interior term),
+ * same counters (or taking the forward's, opts->reuse_forward) and holding
+ * them fixed (interior term),
  * then the vertex-normal adjoint into grads->verts, then, if
  * opts->edge_samples != 0, the primary-visibility boundary term of edge
  * sampling (Sec. 4 "Edge Sampling") into grads->verts and grads->cam.

@@ -35,7 +35,7 @@ class FrRenderOpts(ctypes.Structure):
                 ("edge_samples", ctypes.c_int32), ("light_chunk", ctypes.c_int32),
                 ("dbg_hit", P), ("dbg_pflag", P), ("dbg_vis", P), ("dbg_stats", P),
                 ("ev_kernel_begin", P), ("ev_kernel_end", P),
-                ("reuse_primary", ctypes.c_int32), ("opts_pad_", ctypes.c_int32)]
+                ("reuse_forward", ctypes.c_int32), ("keep_shadows", ctypes.c_int32)]
 
 
 class FrGrads(ctypes.Structure):

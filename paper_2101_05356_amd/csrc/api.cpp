@@ -18,7 +18,19 @@ struct fr_ctx {
 };
 
 // What the mesh's primary-hit buffer currently holds: the camera-ray hits of
-// the render call with these inputs (valid = false: nothing usable).
+// the render call with these inputs (valid = false: nothing usable); and
+// whether its shadow-mask buffer holds that call's decisions for the lights
+// below (kept by a forward asked to keep them).
+struct LightKey {
+  bool valid = false;
+  int32_t L = 0, lc = 0;
+  const float* p0 = nullptr;
+  const float* e1 = nullptr;
+  const float* e2 = nullptr;
+  const int32_t* shape = nullptr;
+  const void* buf = nullptr;
+};
+
 struct PrimKey {
   bool valid = false;
   int32_t W = 0, H = 0, S = 0;
@@ -41,6 +53,7 @@ struct fr_mesh {
   fr::MeshDev d;
   uint64_t version = 0;   // bumped by every fr_mesh_update
   PrimKey prim_key;
+  LightKey vis_key;
   std::vector<int32_t> h_edges, h_edge_faces;
   double* loss_scratch = nullptr;   // per-block loss partials
   float* loss_gtmp = nullptr;       // sign image before the adjoint smoothing
@@ -111,6 +124,7 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
   a.n_lchunks = std::max(1, (s->n_lights + a.lc - 1) / a.lc);
   a.partial = nullptr;
   a.prim = nullptr;   // set by the caller (ensure_prim, or a job's own buffer)
+  a.vis_out = nullptr; a.vis_in = nullptr; a.vis_lc = 0;
   a.tiles_x = (a.W + a.tile_w - 1) / a.tile_w;
   a.tiles_y = (a.H + a.tile_h - 1) / a.tile_h;
   a.n_tiles = a.tiles_x * a.tiles_y;
@@ -266,7 +280,7 @@ int fr_mesh_destroy(fr_mesh* m) {
   void* ptrs[] = {d.tris, d.vf_off, d.vf_idx, d.normals, d.nlen, d.gnorm, d.edges, d.edge_faces, d.nodes, d.recs,
                   d.order, d.node_parent, d.leaf_parent, d.flags, d.keys[0], d.keys[1], d.vals[0], d.vals[1],
                   d.hist, d.partial, d.scene_box, d.depth, d.lights, d.ltmp, d.edge_len, d.edge_cdf, d.face_front,
-                  d.scan_part, d.img_partial, d.prim, d.acc, d.tex_acc, d.slots, d.nodes4, d.n4_src, d.top_nodes, d.top_level_off, m->loss_scratch, m->loss_gtmp};
+                  d.scan_part, d.img_partial, d.prim, d.vis, d.acc, d.tex_acc, d.slots, d.nodes4, d.n4_src, d.top_nodes, d.top_level_off, m->loss_scratch, m->loss_gtmp};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -333,6 +347,20 @@ PrimKey prim_key_of(const fr_mesh* m, const fr_scene* s) {
   return k;
 }
 
+LightKey light_key_of(const fr_mesh* m, const fr_scene* s, int lc) {
+  LightKey k;
+  k.valid = true;
+  k.L = s->n_lights; k.lc = lc;
+  k.p0 = s->light_p0; k.e1 = s->light_e1; k.e2 = s->light_e2; k.shape = s->light_shape;
+  k.buf = m->d.vis;
+  return k;
+}
+
+bool same_lights(const LightKey& a, const LightKey& b) {
+  return a.valid && b.valid && a.L == b.L && a.p0 == b.p0 && a.e1 == b.e1 && a.e2 == b.e2 && a.shape == b.shape &&
+         a.buf == b.buf;
+}
+
 // The mesh's primary-hit buffer, grown to the call's W*H*S samples.
 int ensure_prim(fr_mesh* m, fr::RenderArgs& a) {
   const size_t need = (size_t)a.W * a.H * a.S;
@@ -372,11 +400,25 @@ int fr_render_forward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fl
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (s->n_lights > 0) fr::launch_light_setup(*s, m->d.lights, st);
+  if (o->keep_shadows && s->n_lights > 0) {
+    const size_t need = (size_t)a.n_lchunks * a.W * a.H * a.S;
+    if (need > m->d.vis_cap) {
+      if (m->d.vis) (void)hipFree(m->d.vis);
+      m->d.vis = nullptr;
+      m->d.vis_cap = 0;
+      if (dalloc(&m->d.vis, need) != hipSuccess) return fail(m->ctx, FR_ERR_OOM, "shadow-mask allocation failed");
+      m->d.vis_cap = need;
+    }
+    a.vis_out = m->d.vis;
+    a.vis_lc = a.lc;
+  }
   m->prim_key.valid = false;
+  m->vis_key.valid = false;
   fr::launch_render_forward(a, d_image, st, static_cast<hipEvent_t>(o->ev_kernel_begin),
                             static_cast<hipEvent_t>(o->ev_kernel_end));
   FR_HIP(m->ctx, hipGetLastError());
   m->prim_key = prim_key_of(m, s);
+  if (a.vis_out) m->vis_key = light_key_of(m, s, a.lc);
   return FR_OK;
 }
 
@@ -458,12 +500,19 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
     fg.tex_r = g->tex_roughness ? d.tex_acc + 6 * MM : nullptr;
   }
   const PrimKey key = prim_key_of(m, s);
-  const bool trace = !(o->reuse_primary && m->prim_key == key);
+  const bool reuse = o->reuse_forward && m->prim_key == key;
+  if (reuse && s->n_lights > 0 && same_lights(m->vis_key, light_key_of(m, s, m->vis_key.lc))) {
+    a.vis_in = m->d.vis;
+    a.vis_lc = m->vis_key.lc;
+  }
+  const LightKey vkeep = a.vis_in ? m->vis_key : LightKey{};
   m->prim_key.valid = false;
+  m->vis_key.valid = false;
   fr::launch_render_backward(a, d_dEdp, fg, d.slots, *g, st, static_cast<hipEvent_t>(o->ev_kernel_begin),
-                             static_cast<hipEvent_t>(o->ev_kernel_end), trace);
+                             static_cast<hipEvent_t>(o->ev_kernel_end), !reuse);
   FR_HIP(m->ctx, hipGetLastError());
   m->prim_key = key;
+  m->vis_key = vkeep;
   if (g->normals) fr::launch_fix_to_float(acc_n, g->normals, 3 * d.N, st);
   if (g->verts) fr::launch_normals_backward(d, s->verts, acc_n, d.gnorm, acc_v, st);
   const int ns = o->edge_samples < 0 ? s->width * s->height : o->edge_samples;
@@ -565,6 +614,7 @@ void layout_job(Carver& c, const fr_model* md, const fr_job_desc* d, fr::JobDev&
   J.target = c.take<float>(px3);
   J.ra.partial = n_lchunks > 1 ? c.take<float>(px3 * n_lchunks) : nullptr;
   J.ra.prim = c.take<fr::PrimHit>((size_t)d->width * d->height * d->spp);
+  J.ra.vis_out = L > 0 ? c.take<uint32_t>((size_t)n_lchunks * d->width * d->height * d->spp) : nullptr;
   J.loss_part = c.take<double>(fr::cdiv(d->width * d->height, 256));
   J.loss = c.take<float>(1);
   J.loss_hist = c.take<float>(std::max(d->hist_cap, 1));
@@ -718,6 +768,7 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   o.components = 3;
   float* partial = J.ra.partial;
   fr::PrimHit* prim = J.ra.prim;
+  uint32_t* vis = J.ra.vis_out;
   const float* cam = J.ra.cam;
   if ((rc = build_args(jh->mesh, &sc, &o, J.ra, fr::kLightChunkFwd)) != FR_OK ||
       (rc = build_args(jh->mesh, &sc, &o, J.rb, 1)) != FR_OK || (rc = bwd_chunks(jh->mesh, J.rb)) != FR_OK) {
@@ -725,6 +776,9 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   }
   J.ra.partial = partial; J.rb.partial = nullptr;
   J.ra.prim = prim; J.rb.prim = prim;
+  // the adjoint reads the forward's shadow decisions (same step, geometry and lights)
+  J.ra.vis_out = vis; J.ra.vis_lc = J.ra.lc;
+  J.rb.vis_in = vis; J.rb.vis_lc = J.ra.lc;
   J.ra.lights = J.lights; J.rb.lights = J.lights;
   J.ra.cam = cam; J.rb.cam = cam;
   const fr::MeshDev& md_ = jh->mesh->d;

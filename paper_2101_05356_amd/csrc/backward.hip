@@ -43,6 +43,23 @@ __device__ __forceinline__ void g1_fwd_bwd(float nv, float hv, float r, float& G
   dG1_dr = -dG * a / r;             // da/dr = -a / r
 }
 
+// The shadow decisions of lights [j0, j1) for sample rs, read from the masks
+// the forward kept (its chunks of vis_lc lights need not align with these):
+// the same bits shadow_mask returns, since a lane's bit depends on its own
+// shading point, light draw and ray only.  Zero where the adjoint does not
+// shade the sample.
+__device__ __forceinline__ uint32_t kept_mask(const RenderArgs& a, int j0, int j1, size_t rs, bool shaded) {
+  if (!shaded || j1 <= j0) return 0u;
+  const size_t ns = (size_t)a.W * a.H * a.S;
+  uint32_t m = 0u;
+  for (int c = j0 / a.vis_lc; c * a.vis_lc < j1; ++c) {
+    const uint32_t w = a.vis_in[(size_t)c * ns + rs];
+    const int sh = c * a.vis_lc - j0;          // in (-vis_lc, j1 - j0): |sh| <= 31
+    m |= sh >= 0 ? (w << sh) : (w >> -sh);
+  }
+  return j1 - j0 >= 32 ? m : (m & ((1u << (j1 - j0)) - 1u));
+}
+
 template <bool TEX>
 __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const float* __restrict__ dEdp,
                                                  const FixGrads& g, fix_t* __restrict__ slots, int bid) {
@@ -86,7 +103,8 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
       const auto draw = [&](int j) { return philox((uint32_t)ps.pid, (uint32_t)s, 1u + (uint32_t)j, a.step, a.k0, a.k1); };
       const auto none = [](int, bool, bool, const LightSample&, const HitState&) {};
       const auto skip = [](int) {};
-      const uint32_t vmask = shadow_mask<false>(a, j0, j1, shaded, fr, ph.id, draw, none, skip, nullptr);
+      const uint32_t vmask = a.vis_in ? kept_mask(a, j0, j1, rs, shaded)
+                                      : shadow_mask<false>(a, j0, j1, shaded, fr, ph.id, draw, none, skip, nullptr);
       for (int j = j0; j < j1; ++j) {
         const bool vis = (vmask >> (j - j0)) & 1u;
         if (!ballot(vis)) continue;

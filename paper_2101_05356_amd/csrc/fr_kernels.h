@@ -123,6 +123,8 @@ struct MeshDev {
   double* scan_part = nullptr;      // [ceil(E/1024)] tile totals of the edge CDF scan
   PrimHit* prim = nullptr;          // [W*H*S] primary hits of the current render call
   size_t prim_cap = 0;
+  uint32_t* vis = nullptr;          // [n_lchunks][W*H*S] shadow masks a forward kept for its adjoint
+  size_t vis_cap = 0;
   float* img_partial = nullptr;     // per-light-chunk partial images
   size_t img_partial_cap = 0;
   fix_t* tex_acc = nullptr;         // [7 M^2] fixed-point texel gradients: diffuse, specular, roughness
@@ -156,6 +158,12 @@ struct RenderArgs {
   int lc, n_lchunks;      // lights per work item, light chunks per tile
   float* partial;         // [n_lchunks][H*W*3] per-chunk pixel sums (n_lchunks > 1)
   PrimHit* prim;          // [H*W*S] primary hits, sample index (y*W + x)*S + s
+  // Shadow masks, word (c, sample) at c*W*H*S + sample: bit b is light
+  // c*vis_lc + b.  The forward writes them (vis_out, with vis_lc = lc) when
+  // asked; the adjoint then reads them (vis_in) in place of its shadow rays.
+  uint32_t* vis_out;
+  const uint32_t* vis_in;
+  int vis_lc;
   float tan_half, aspect;
   double tan_half_d, aspect_d;   // the same in FP64 (texture coordinates)
   uint32_t k0, k1, step;

@@ -118,6 +118,7 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
       if (DUMP && ps.valid) a.dbg_vis[rs * a.L + j] = shaded ? VIS_CULLED : VIS_NONE;
     };
     const uint32_t vmask = shadow_mask<DUMP>(a, j0, j1, shaded, fr, ph.id, draw, note, skip, &st2);
+    if (a.vis_out && ps.valid) a.vis_out[(size_t)it.chunk * ((size_t)a.W * a.H * a.S) + rs] = vmask;
     for (int j = j0; j < j1; ++j) {
       const bool vis = (vmask >> (j - j0)) & 1u;
       if (!ballot(vis)) continue;

@@ -159,13 +159,14 @@ class Reconstruction:
         self.geometry(rebuild=False)
         sc = self.scene()
         ev = events or {}
-        img = R.render_forward(self.mesh, sc, job.brdf_variant, verts=self.v_w, events=ev.get("fwd"))
+        img = R.render_forward(self.mesh, sc, job.brdf_variant, verts=self.v_w, events=ev.get("fwd"),
+                               keep_shadows=True)
         E, dEdp = R.loss(img, job.target, smooth=job.smooth)
         self.grad.zero_()
         self.g_vobj.zero_()
         g = R.render_backward(self.mesh, sc, dEdp, job.brdf_variant, edge_samples=job.edge_samples,
                               groups=("verts", "diffuse", "light_rad"), verts=self.v_w, events=ev.get("bwd"),
-                              reuse_primary=True)
+                              reuse_forward=True)
         R.pose_backward(self.v_obj, self.param[sl["pose"]], g["verts"], self.g_vobj, self.grad[sl["pose"]])
         R.blend_backward(mt.basis_geo, self.g_vobj, self.grad[sl["geo"]])
         R.blend_backward(mt.basis_alb, g["diffuse"], self.grad[sl["alb"]])

@@ -184,10 +184,12 @@ def _opts(brdf_variant=0, components=3, edge_samples=0, dbg=None, light_chunk=0,
 
 
 def render_forward(mesh: Mesh, sc: DeviceScene, brdf_variant=0, components=3, dump=False, verts=None, stats=None,
-                   light_chunk=0, events=None):
+                   light_chunk=0, events=None, keep_shadows=False):
     """Image [H,W,3]; with dump=True also (hit [H*W,S], pflag [H*W,S], vis [H*W,S,L]).
     `stats` (a uint64-sized int64 tensor [10], dump only) accumulates traversal counts.
-    `events` (two torch.cuda.Event with timing) bracket the render kernel itself."""
+    `events` (two torch.cuda.Event with timing) bracket the render kernel itself.
+    `keep_shadows`: the mesh keeps the shadow decisions for a backward with
+    reuse_forward."""
     dev = sc.verts.device
     img = torch.empty((sc.H, sc.W, 3), dtype=torch.float32, device=dev)
     dbg = None
@@ -197,6 +199,7 @@ def render_forward(mesh: Mesh, sc: DeviceScene, brdf_variant=0, components=3, du
                torch.full((n * max(sc.n_lights, 1),), 0xEE, dtype=torch.uint8, device=dev))
     s = sc.struct(verts)
     o = _opts(brdf_variant, components, 0, dbg, light_chunk, events)
+    o.keep_shadows = int(bool(keep_shadows))
     if stats is not None:
         assert dump and stats.dtype == torch.int64 and stats.numel() == 10
         o.dbg_stats = stats.data_ptr()
@@ -224,11 +227,12 @@ TEX_GROUPS = ("tex_diffuse", "tex_specular", "tex_roughness")
 
 def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_variant=0, components=3,
                     edge_samples=0, groups=GRAD_GROUPS, verts=None, edge_dump=False, light_chunk=0, events=None,
-                    reuse_primary=False):
+                    reuse_forward=False):
     """Gradients (dict of new tensors) of sum dEdp . image.  `events` (two
     torch.cuda.Event with timing) bracket the interior adjoint kernel.
-    `reuse_primary`: take the camera-ray hits of the last render of this mesh
-    when it had the same size, samples, counters, vertex and camera buffers
+    `reuse_forward`: take the camera-ray hits of the last render of this mesh
+    when it had the same size, samples, counters, vertex and camera buffers,
+    and its shadow decisions when it kept them for the same light buffers
     (their contents unchanged since; the library checks the rest)."""
     dev = sc.verts.device
     N, L, M = mesh.n_verts, sc.n_lights, sc.tex_size
@@ -248,7 +252,7 @@ def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_varian
                None)
     s = sc.struct(verts)
     o = _opts(brdf_variant, components, edge_samples, dbg, light_chunk, events)
-    o.reuse_primary = int(bool(reuse_primary))
+    o.reuse_forward = int(bool(reuse_forward))
     check(lib().fr_render_backward(mesh.h, ctypes.byref(s), ctypes.byref(o), _p(dEdp.contiguous()), ctypes.byref(g),
                                    _stream()), mesh.ctx.h, "fr_render_backward")
     if edge_dump and dbg is not None:
@@ -305,7 +309,7 @@ class RenderFn(torch.autograd.Function):
                                  light_p0=light_p0.contiguous(), light_e1=light_e1.contiguous(),
                                  light_e2=light_e2.contiguous(), light_rad=light_rad.contiguous(), cam=cam.contiguous())
         mesh.update(sc.verts, rebuild=opts.get("rebuild", False))
-        img = render_forward(mesh, sc, opts.get("brdf_variant", 0), opts.get("components", 3))
+        img = render_forward(mesh, sc, opts.get("brdf_variant", 0), opts.get("components", 3), keep_shadows=True)
         E, dEdp = loss(img, target, opts.get("smooth", True))
         ctx.mesh, ctx.sc, ctx.opts = mesh, sc, opts
         ctx.save_for_backward(dEdp)
@@ -322,7 +326,7 @@ class RenderFn(torch.autograd.Function):
         g = render_backward(ctx.mesh, ctx.sc, seed, o.get("brdf_variant", 0), o.get("components", 3),
                             o.get("edge_samples", 0),
                             groups=("verts", "diffuse", "specular", "roughness", "light_geom", "light_rad", "cam"),
-                            reuse_primary=True)
+                            reuse_forward=True)
         lg = g["light_geom"]
         return (g["verts"], g["diffuse"], g["specular"], g["roughness"], lg[:, 0:3].contiguous(),
                 lg[:, 3:6].contiguous(), lg[:, 6:9].contiguous(), g["light_rad"], g["cam"], None, None, None, None)

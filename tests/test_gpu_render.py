@@ -196,41 +196,56 @@ def test_edge_term_parity_patch(oracle_lib):
         assert okv[1] < 2e-4 and okc[1] < 2e-4
 
 
-def test_backward_reusing_the_forward_hits_is_bit_identical(oracle_lib):
-    """fr_render_opts.reuse_primary: the adjoint takes the camera-ray hits the
-    forward stored when the calls match, and traces them itself otherwise
-    (other step counter, a mesh update in between, another size rendered in
-    between); every gradient equals that of a backward that traces its own."""
+def test_backward_reusing_the_forward_decisions_is_bit_identical(oracle_lib):
+    """fr_render_opts.reuse_forward / keep_shadows: the adjoint takes the
+    camera-ray hits the forward stored, and the shadow masks it kept, when the
+    calls match, and traces what it cannot take otherwise (other step
+    counter, a mesh update in between, other light buffers, another size
+    rendered in between).  The forward's light chunks (5 lights) straddle the
+    32-bit words and differ from the adjoint's (3 or 8 lights, the latter
+    leaving two of the four waves without lights).  Every gradient equals
+    that of a backward that traces its own."""
     sc = scenes.face_render_scene(W=64, H=64, spp=4, n_lights=12)
     rng = np.random.default_rng(8)
     dEdp = torch.tensor(rng.normal(size=(64, 64, 3)).astype(np.float32)).cuda()
     m, ds = G.gpu_setup(sc)
     groups = ("verts", "diffuse", "light_geom", "light_rad", "cam")
 
-    def bwd(scene, reuse):
-        g = G.R.render_backward(m, scene, dEdp, edge_samples=-1, groups=groups, reuse_primary=reuse)
+    def bwd(scene, reuse, lc=0):
+        g = G.R.render_backward(m, scene, dEdp, edge_samples=-1, groups=groups, reuse_forward=reuse, light_chunk=lc)
         torch.cuda.synchronize()
         return [G.to_np(g[k]) for k in groups]
+
+    def fwd(scene, keep, mesh=None):
+        G.R.render_forward(mesh or m, scene, keep_shadows=keep, light_chunk=5)
 
     def same(a, b):
         return all(np.array_equal(x, y) for x, y in zip(a, b))
 
     s1, s2 = dataclasses.replace(ds, step=1), dataclasses.replace(ds, step=2)
-    want1, want2 = bwd(s1, False), bwd(s2, False)
+    want1, want2, want1_8 = bwd(s1, False), bwd(s2, False), bwd(s1, False, 8)
     assert not same(want1, want2)
-    G.R.render_forward(m, s1)
-    assert same(bwd(s1, True), want1)                    # matching forward: its hits
-    G.R.render_forward(m, s1)
-    assert same(bwd(s2, True), want2)                    # other counter: traced
-    G.R.render_forward(m, s2)
-    m.update(ds.verts, rebuild=False)
-    assert same(bwd(s2, True), want2)                    # mesh updated in between: traced
-    G.R.render_forward(m, s1)
+    for keep in (False, True):
+        fwd(s1, keep)
+        assert same(bwd(s1, True), want1)                # matching forward: its decisions
+        assert same(bwd(s1, True), want1)                # a second adjoint of the same forward
+        fwd(s1, keep)
+        assert same(bwd(s1, True, 8), want1_8)
+        fwd(s1, keep)
+        assert same(bwd(s2, True), want2)                # other counter: traced
+        fwd(s2, keep)
+        m.update(ds.verts, rebuild=False)
+        assert same(bwd(s2, True), want2)                # mesh updated in between: traced
+    other = dataclasses.replace(s1, light_p0=s1.light_p0.clone(), light_e1=s1.light_e1.clone(),
+                                light_e2=s1.light_e2.clone(), light_shape=s1.light_shape.clone())
+    fwd(other, True)
+    assert same(bwd(s1, True), want1)                    # other light buffers: hits taken, shadows traced
+    fwd(s1, True)
     big = scenes.face_render_scene(W=96, H=96, spp=8, n_lights=12)
-    mb = G.R.Mesh(G.ctx(), big.n_verts, big.tris)       # another mesh leaves this one's hits alone
+    mb = G.R.Mesh(G.ctx(), big.n_verts, big.tris)       # another mesh leaves this one's decisions alone
     db = G.R.DeviceScene.from_scene(big)
     mb.update(db.verts, rebuild=True)
-    G.R.render_forward(mb, db)
+    fwd(db, True, mb)
     assert same(bwd(s1, True), want1)
-    G.R.render_forward(m, dataclasses.replace(s1, spp=8))    # larger buffer on this mesh
+    fwd(dataclasses.replace(s1, spp=8), True)            # larger buffers on this mesh
     assert same(bwd(s1, True), want1)
