@@ -60,7 +60,9 @@ __device__ __forceinline__ uint32_t kept_mask(const RenderArgs& a, int j0, int j
   return j1 - j0 >= 32 ? m : (m & ((1u << (j1 - j0)) - 1u));
 }
 
-template <bool TEX>
+// KEPT: the shadow decisions come from the forward's masks (a.vis_in), and
+// the kernel holds no traversal code at all.
+template <bool TEX, bool KEPT>
 __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const float* __restrict__ dEdp,
                                                  const FixGrads& g, fix_t* __restrict__ slots, int bid) {
   // LDS: [L*12 + 12] fixed-point sums (per light p0 e1 e2 rad, then camera),
@@ -103,8 +105,9 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
       const auto draw = [&](int j) { return philox((uint32_t)ps.pid, (uint32_t)s, 1u + (uint32_t)j, a.step, a.k0, a.k1); };
       const auto none = [](int, bool, bool, const LightSample&, const HitState&) {};
       const auto skip = [](int) {};
-      const uint32_t vmask = a.vis_in ? kept_mask(a, j0, j1, rs, shaded)
-                                      : shadow_mask<false>(a, j0, j1, shaded, fr, ph.id, draw, none, skip, nullptr);
+      uint32_t vmask;
+      if (KEPT) vmask = kept_mask(a, j0, j1, rs, shaded);
+      else vmask = shadow_mask<false>(a, j0, j1, shaded, fr, ph.id, draw, none, skip, nullptr);
       for (int j = j0; j < j1; ++j) {
         const bool vis = (vmask >> (j - j0)) & 1u;
         if (!ballot(vis)) continue;
@@ -409,10 +412,19 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
   }
 }
 
+// Occupancy: the traced kernel's shadow traversals and the adjoint shading
+// fit five waves per SIMD without spilling; the kept-mask kernel runs at the
+// occupancy that measured fastest.
 template <bool TEX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_render_bwd(RenderArgs a, const float* __restrict__ dEdp, FixGrads g,
                                                     fix_t* __restrict__ slots) {
-  render_bwd_block<TEX>(a, dEdp, g, slots, blockIdx.x);
+  render_bwd_block<TEX, false>(a, dEdp, g, slots, blockIdx.x);
+}
+
+template <bool TEX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_render_bwd_kept(RenderArgs a, const float* __restrict__ dEdp, FixGrads g,
+                                                    fix_t* __restrict__ slots) {
+  render_bwd_block<TEX, true>(a, dEdp, g, slots, blockIdx.x);
 }
 
 // Sum the slots (exact integer sums) into the caller's light and camera gradients.
@@ -455,10 +467,17 @@ void launch_render_backward(const RenderArgs& a, const float* dEdp, const FixGra
   const size_t lds = nl * sizeof(fix_t) + kBwdPartBytes;
   if (e0) (void)hipEventRecord(e0, st);
   if (trace_primary) launch_primary(a, st);
-  if (a.M > 0)
-    hipLaunchKernelGGL(k_render_bwd<true>, dim3(blocks), dim3(256), lds, st, a, dEdp, fg, slots);
-  else
-    hipLaunchKernelGGL(k_render_bwd<false>, dim3(blocks), dim3(256), lds, st, a, dEdp, fg, slots);
+  if (a.vis_in) {
+    if (a.M > 0)
+      hipLaunchKernelGGL(k_render_bwd_kept<true>, dim3(blocks), dim3(256), lds, st, a, dEdp, fg, slots);
+    else
+      hipLaunchKernelGGL(k_render_bwd_kept<false>, dim3(blocks), dim3(256), lds, st, a, dEdp, fg, slots);
+  } else {
+    if (a.M > 0)
+      hipLaunchKernelGGL(k_render_bwd<true>, dim3(blocks), dim3(256), lds, st, a, dEdp, fg, slots);
+    else
+      hipLaunchKernelGGL(k_render_bwd<false>, dim3(blocks), dim3(256), lds, st, a, dEdp, fg, slots);
+  }
   if (e1) (void)hipEventRecord(e1, st);
   hipLaunchKernelGGL(k_slots_reduce, dim3(nl), dim3(256), 0, st, slots, nl, a.L, g.light_geom, g.light_rad, g.cam);
 }

@@ -87,10 +87,11 @@ FR_BATCH_KERNEL(kb_zero_grads, 256) {
   for (int k = i; k < n9; k += J.zero_stride) J.acc[k] = 0;
   for (int k = i; k < nslot; k += J.zero_stride) J.lslots[k] = 0;
 }
-__attribute__((amdgpu_waves_per_eu(5))) FR_BATCH_KERNEL(kb_render_bwd, 256) {
+// The adjoint takes the forward's shadow masks (J.rb.vis_in).
+__attribute__((amdgpu_waves_per_eu(4))) FR_BATCH_KERNEL(kb_render_bwd, 256) {
   FR_JOB_PROLOGUE
   const FixGrads g = {J.acc, J.acc + 3 * J.N, J.acc + 6 * J.N, nullptr, nullptr};
-  render_bwd_block<false>(J.rb, J.dEdp, g, J.lslots, lb);
+  render_bwd_block<false, true>(J.rb, J.dEdp, g, J.lslots, lb);
 }
 // fixed-point vertex and diffuse gradients -> float
 FR_BATCH_KERNEL(kb_fix_finalize, 256) {
