@@ -113,7 +113,7 @@ def cpu_baseline(seconds, spp, n_lights, width):
 
 
 KERNEL_SOURCES = {
-    "k_render_bwd": ["paper_2101_05356_amd/csrc/backward.hip", "paper_2101_05356_amd/csrc/fr_shade.h",
+    "k_render_bwd_kept": ["paper_2101_05356_amd/csrc/backward.hip", "paper_2101_05356_amd/csrc/fr_shade.h",
                      "paper_2101_05356_amd/csrc/fr_device.h", "paper_2101_05356_amd/csrc/fr_kernels.h",
                      "include/fr.h"],
     "k_render_fwd": ["paper_2101_05356_amd/csrc/render.hip", "paper_2101_05356_amd/csrc/fr_shade.h",
@@ -344,12 +344,13 @@ def main():
         stats = traversal_stats(rc)
         ops_f = algorithmic_ops(stats, W, H, S, L)
         ops_b = algorithmic_ops(stats, W, H, S, L, backward=True)
-        dom, ops, ms = ("k_render_bwd", ops_b, bwd_ms) if bwd_ms >= fwd_ms else ("k_render_fwd", ops_f, fwd_ms)
+        dom, ops, ms = ("k_render_bwd_kept", ops_b, bwd_ms) if bwd_ms >= fwd_ms else ("k_render_fwd", ops_f, fwd_ms)
         ach = ops / (ms * 1e-3)
         out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": ach / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                            "unit": "Tlane-op/s", "frac": ach / PEAK_LANE_OPS, "traffic": measured_traffic(dom),
-                           "other": {"k_render_fwd": {"ms": fwd_ms, "achieved": ops_f / (fwd_ms * 1e-3) / 1e12,
-                                                      "frac": ops_f / (fwd_ms * 1e-3) / PEAK_LANE_OPS}}}
+                           "other": {k: {"ms": t, "achieved": o / (t * 1e-3) / 1e12, "frac": o / (t * 1e-3) / PEAK_LANE_OPS}
+                                     for k, o, t in (("k_render_fwd", ops_f, fwd_ms), ("k_render_bwd_kept", ops_b, bwd_ms))
+                                     if k != dom}}
         cam_rays, sh_rays = stats[2], stats[5]
         out["traversal"] = {
             "tree": "binned-SAH binary tree collapsed to 4-wide, one triangle per leaf",
