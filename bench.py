@@ -49,8 +49,9 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock (packed FP3
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=50,
+                    help="untimed steps first (~0.2 s: the GPU clocks settle after the host-side setup)")
     ap.add_argument("--width", type=int, default=256)
     ap.add_argument("--spp", type=int, default=16)
     ap.add_argument("--lights", type=int, default=72)
