@@ -49,7 +49,7 @@ struct OrScene {
   const float* light_e1;   // [L*3]
   const float* light_e2;   // [L*3]
   const float* light_rad;  // [L*3]
-  const int32_t* light_shape;  // [L] 0 parallelogram, 1 triangle
+  const int32_t* light_shape;  // [L] 0 parallelogram, 1 triangle, 2 at infinity (direction p0)
   const float* cam_R;      // [9] camera-to-world, row-major
   const float* cam_T;      // [3]
   float fov_y;
@@ -340,6 +340,7 @@ V3 film_dir(const CamConst& cc, double fx, double fy) {
 
 // Point on light j from two uniforms: parallelogram p0 + u0 e1 + u1 e2;
 // triangle p0 + sqrt(u0)(1-u1) e1 + sqrt(u0) u1 e2 (uniform area density).
+// A light at infinity (shape 2) has no point: the weights go unused.
 inline void light_weights(int shape, double u0, double u1, double* w1, double* w2) {
   if (shape == 1) { const double su = std::sqrt(u0); *w1 = su * (1.0 - u1); *w2 = su * u1; }
   else { *w1 = u0; *w2 = u1; }
@@ -498,10 +499,21 @@ Vec3<S> brdf(const Frame<S>& f, const Vec3<S>& l, const S& cos_o, const S& cos_l
 // weight): V L_j * f_r * (n_s . l) * (-n_j . l) A_j / |q - x|^2.
 // With A_j (-n_j . l) = -kappa (e1 x e2) . l, kappa = 1 (parallelogram) or
 // 1/2 (triangle).  `vis` is the frozen decision; culled pairs give zero.
+// A light at infinity (the environment-map pixels of Sec. 6, "Environment
+// Map vs. Light Stage") shines along l = p0 / |p0| with L_j the irradiance
+// it delivers to a surface facing it (radiance times the pixel's solid
+// angle): V L_j * f_r * (n_s . l).
 template <class S>
 Vec3<S> light_contribution(const Frame<S>& f, const LightParams<S>& L, double w1, double w2, uint8_t vis,
                            int variant, int components, uint8_t* flags) {
   if (vis != VIS_VISIBLE) return Vec3<S>(S(0.0), S(0.0), S(0.0));
+  if (L.shape == 2) {
+    const Vec3<S> l = normalize(L.p0);
+    const S cos_s = dot(f.ns, l);
+    const S cos_o = dot(f.ns, f.wo);
+    const Vec3<S> fr = brdf(f, l, cos_o, cos_s, variant, components, flags);
+    return Vec3<S>(L.rad.x * fr.x * cos_s, L.rad.y * fr.y * cos_s, L.rad.z * fr.z * cos_s);
+  }
   const Vec3<S> q = L.p0 + L.e1 * S(w1) + L.e2 * S(w2);
   const Vec3<S> dq = q - f.x;
   const S dist2 = dot(dq, dq);
@@ -566,11 +578,19 @@ LightParams<double> light_params_d(const OrScene& sc, int j) {
 
 // Decision pass of one light for a shading frame (FP64): cull tests, then the
 // shadow ray from x towards q over t in (1e-4, |q - x|), excluding the hit
-// triangle.
+// triangle.  A light at infinity: the one cosine test, then the ray along
+// p0 / |p0| over t in (1e-4, 1e4) (the scene lies well within 1e4).
 uint8_t light_decision(const Prepared& P, const Frame<double>& f, int j, double w1, double w2, int hit,
                        uint8_t* flags) {
   const OrScene& sc = *P.sc;
   const LightParams<double> L = light_params_d(sc, j);
+  if (L.shape == 2) {
+    const V3 l = normalize(L.p0);
+    const double cs = dot(f.ns, l);
+    if (std::fabs(cs) < kFlagEps) *flags |= FLAG_COSL;
+    if (cs <= 0.0) return VIS_CULLED;
+    return occluded(P.tg, f.x, l, kShadowTmin, kMissFar, hit, flags) ? VIS_OCCLUDED : VIS_VISIBLE;
+  }
   const V3 q = L.p0 + L.e1 * w1 + L.e2 * w2;
   const V3 dq = q - f.x;
   const double dist = norm(dq);

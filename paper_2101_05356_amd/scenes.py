@@ -22,6 +22,7 @@ import numpy as np
 
 LIGHT_PARALLELOGRAM = 0
 LIGHT_TRIANGLE = 1
+LIGHT_DIRECTIONAL = 2   # at infinity: p0 = direction towards the light, e1 = e2 = 0
 
 
 @dataclasses.dataclass
@@ -396,6 +397,27 @@ def face_lights(n_lights: int = 72, radius: float = 3.0, side: float = 0.2, seed
     rng = np.random.default_rng(seed)
     centres = fibonacci_light_centres(n_lights, radius)
     return square_lights(centres, side, rng.uniform(0.0, 5.0, (n_lights, 3)))
+
+
+def environment_lights(res: int = 32, seed: int = 13, lo: float = 0.0, hi: float = 0.6) -> Lights:
+    """The environment-map lighting of the paper's ablation (Sec. 6,
+    "Environment Map vs. Light Stage"): a res x res latitude-longitude map,
+    each pixel a light at infinity.  Pixel (i, k) looks along polar angle
+    theta_i = (i + 1/2) pi / res from +y and azimuth phi_k = (k + 1/2) 2 pi /
+    res; its RGB intensity is a smooth random field in [lo, hi] and its
+    `rad` that intensity times the pixel's solid angle
+    sin(theta) (pi / res) (2 pi / res), i.e. the irradiance it delivers to a
+    surface facing it."""
+    rng = np.random.default_rng(seed)
+    inten = smooth_random_map(rng, res, 3, lo, hi).reshape(res, res, 3)   # [theta][phi][rgb]
+    th = (np.arange(res) + 0.5) * math.pi / res
+    ph = (np.arange(res) + 0.5) * 2.0 * math.pi / res
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    d = np.stack([np.sin(T) * np.cos(P), np.cos(T), np.sin(T) * np.sin(P)], -1).reshape(-1, 3)
+    omega = (np.sin(T) * (math.pi / res) * (2.0 * math.pi / res)).reshape(-1, 1)
+    L = res * res
+    return Lights(p0=_f32(d), e1=_f32(np.zeros((L, 3))), e2=_f32(np.zeros((L, 3))),
+                  rad=_f32(inten.reshape(-1, 3) * omega), shape=_i32(np.full(L, LIGHT_DIRECTIONAL)))
 
 
 def face_camera(W: int = 256, H: int = 256) -> Camera:

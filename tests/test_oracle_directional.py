@@ -1,0 +1,107 @@
+"""Pins of the oracle's lights at infinity (the environment-map lighting of
+Sec. 6, "Environment Map vs. Light Stage": each map pixel a light at
+infinity): the closed form on a flat Lambertian patch, the limit of a far
+square area light of matching irradiance (ties the new branch to the area
+light's pinned code, occlusion included), and frozen-decision central
+differences of the direction, the irradiance and the vertices."""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+from paper_2101_05356_amd import scenes
+
+pytestmark = pytest.mark.usefixtures("oracle_lib")
+
+
+def one_directional(d, rad):
+    d = np.asarray(d, np.float64)
+    return scenes.Lights(p0=np.asarray([d], np.float32), e1=np.zeros((1, 3), np.float32),
+                         e2=np.zeros((1, 3), np.float32), rad=np.asarray([rad], np.float32),
+                         shape=np.asarray([scenes.LIGHT_DIRECTIONAL], np.int32))
+
+
+def test_flat_lambertian_patch_closed_form(oracle_lib):
+    """Flat patch at z = 0 (normal +z), uniform diffuse albedo c, diffuse
+    term only: every sample that hits reads c / pi * E * (n . l)."""
+    o = oracle_lib
+    sc = scenes.patch_scene(W=16, H=16, spp=2)
+    v, t = scenes.heightfield_patch(24, bump_h=0.0)
+    c = np.array([0.6, 0.45, 0.3], np.float32)
+    E = np.array([1.5, 2.0, 0.7], np.float32)
+    d = np.array([0.3, -0.2, 0.9])
+    sc = dataclasses.replace(sc, verts=v, tris=t, diffuse=np.tile(c, (v.shape[0], 1)),
+                             lights=one_directional(d, E))
+    r = o.render(sc, components=1)
+    hit_all = np.all(r["hit"] >= 0, axis=1)
+    assert hit_all.sum() > 40 and np.all(r["vis"][r["hit"] >= 0] == 1)
+    d32 = d.astype(np.float32).astype(np.float64)          # the direction as the render reads it
+    want = c.astype(np.float64) / math.pi * E.astype(np.float64) * (d32[2] / np.linalg.norm(d32))
+    assert np.allclose(r["rgb"][hit_all], want, rtol=1e-12, atol=0)
+    # a light below the surface is culled for every sample
+    r2 = o.render(dataclasses.replace(sc, lights=one_directional(-d, E)), components=1)
+    assert np.all(r2["vis"][r2["hit"] >= 0] == 2) and not np.any(r2["rgb"])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_far_square_light_tends_to_the_light_at_infinity(oracle_lib, seed):
+    """A square light of side a at distance D along l, facing the scene, with
+    radiance E D^2 / a^2, delivers E (n . l) (1 + O(size / D)) to every
+    point: at D = 1e5 the two renders agree to 1e-4 and their shadow
+    decisions coincide (the face's nose shadows part of the cheek for these
+    grazing directions)."""
+    o = oracle_lib
+    rng = np.random.default_rng(seed)
+    sc = scenes.face_render_scene(W=24, H=24, spp=1, n_lights=1, n_lon=40, n_ring=28)
+    th = rng.uniform(1.1, 1.35)
+    ph = rng.uniform(0.0, 2 * math.pi)
+    l = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+    E = rng.uniform(0.5, 2.0, 3)
+    D, a = 1e5, 1.0
+    p0, e1, e2 = scenes._square_facing_origin(D * l, a)
+    far = scenes.Lights(p0=np.asarray([p0], np.float32), e1=np.asarray([e1], np.float32),
+                        e2=np.asarray([e2], np.float32), rad=np.asarray([E * D * D / (a * a)], np.float32),
+                        shape=np.asarray([scenes.LIGHT_PARALLELOGRAM], np.int32))
+    ra = o.render(dataclasses.replace(sc, lights=far))
+    rd = o.render(dataclasses.replace(sc, lights=one_directional(l, E)))
+    assert np.array_equal(ra["hit"], rd["hit"])
+    lit = rd["hit"] >= 0
+    assert np.array_equal(ra["vis"][lit], rd["vis"][lit])
+    assert (rd["vis"][lit] == 0).sum() > 0 and (rd["vis"][lit] == 1).sum() > 0
+    scale = np.abs(rd["rgb"]).max()
+    assert np.allclose(ra["rgb"], rd["rgb"], rtol=1e-4, atol=1e-4 * scale)
+
+
+@pytest.mark.parametrize("group", ["light", "rad", "verts"])
+def test_directional_gradients_match_frozen_central_differences(oracle_lib, group):
+    """Three lights at infinity on the tilted bump patch; quantised inputs
+    and steps keep every perturbed value exact in FP32.  The direction
+    gradient lands in the p0 slots of the light group (e1, e2 get none)."""
+    from tests.test_oracle_grad import functional, perturbed, tilt_camera
+    o = oracle_lib
+    sc = tilt_camera(scenes.patch_scene(W=16, H=16, spp=2))
+    q = lambda x: (np.round(np.asarray(x, np.float64) * 2.0 ** 22) / 2.0 ** 22).astype(np.float32)
+    dirs = np.array([[0.3, -0.2, 0.9], [-0.5, 0.4, 0.6], [0.1, 0.7, 0.5]])
+    lights = scenes.Lights(p0=q(dirs), e1=np.zeros((3, 3), np.float32), e2=np.zeros((3, 3), np.float32),
+                           rad=q([[1.5, 2.0, 0.7], [0.4, 0.3, 1.1], [0.9, 0.9, 0.2]]),
+                           shape=np.full(3, scenes.LIGHT_DIRECTIONAL, np.int32))
+    sc = dataclasses.replace(sc, verts=q(sc.verts), diffuse=q(sc.diffuse), specular=q(sc.specular),
+                             roughness=q(sc.roughness), lights=lights)
+    dec = o.render(sc)
+    assert (dec["vis"] == 0).sum() > 0 and (dec["vis"] == 1).sum() > 0   # the bump shadows the patch
+    rng = np.random.default_rng(["light", "rad", "verts"].index(group))
+    w = rng.normal(size=dec["rgb"].shape)
+    g = o.grad(sc, dec["hit"], dec["vis"], w)
+    shape = {"light": (3, 9), "rad": (3, 3), "verts": sc.verts.shape}[group]
+    d = rng.integers(-2, 3, size=shape).astype(np.float64)
+    if group == "light":
+        d[:, 3:] = 0.0
+        assert not np.any(g["light"].reshape(3, 9)[:, 3:])
+
+    def cd(h):
+        return (functional(o, perturbed(sc, group, d, h), w, dec) - functional(o, perturbed(sc, group, d, -h), w, dec)) / (2 * h)
+
+    fd = cd(2.0 ** -20)
+    an = float((g[group] * d).sum())
+    assert math.isclose(fd, an, rel_tol=2e-5, abs_tol=1e-8 * np.abs(g[group]).sum()), (fd, an)
