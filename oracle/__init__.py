@@ -75,7 +75,8 @@ def lib():
         L.oracle_vertex_normals.argtypes = [P, P]
         L.oracle_normals_vjp.argtypes = [P, P, P]
         L.oracle_render.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, ctypes.c_int32]
-        L.oracle_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int32]
+        L.oracle_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int32,
+                                  ctypes.c_int32]
         L.oracle_edge_grad.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_int32]
         L.oracle_edge_count.argtypes = [P]
         L.oracle_edge_count.restype = ctypes.c_int32
@@ -189,7 +190,7 @@ def render(scene, pixels=None, force_hit=None, force_vis=None, brdf_variant=0, c
 
 
 def grad(scene, hit, vis, dEdp, pixels=None, brdf_variant=0, components=3, nthreads=None,
-         include_normals_path=True):
+         include_normals_path=True, abs_terms=False):
     """Interior gradient of sum_p dEdp[p] . rgb[p] with decisions (hit, vis) fixed.
 
     dEdp is [n,3] for the pixel subset (or [H*W,3] / [H,W,3] for all pixels).
@@ -197,7 +198,10 @@ def grad(scene, hit, vis, dEdp, pixels=None, brdf_variant=0, components=3, nthre
     the vertex normals unless include_normals_path is False), normals [N,3],
     diffuse [N,3], specular [N,3], rough [N], light [L,9] (p0,e1,e2), rad [L,3],
     cam [12] (R row-major, T); with reflectance maps also tex_diffuse [M,M,3],
-    tex_specular [M,M,3], tex_rough [M,M] (and zero per-vertex reflectance)."""
+    tex_specular [M,M,3], tex_rough [M,M] (and zero per-vertex reflectance).
+    abs_terms=True returns instead, per element, the sum of the magnitudes of
+    its (sample, light) terms (verts: the direct path only), the condition
+    measure that test tolerances use."""
     b = _Bound(scene, brdf_variant, components)
     N, L = scene.n_verts, scene.lights.count
     pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int32)
@@ -214,8 +218,9 @@ def grad(scene, hit, vis, dEdp, pixels=None, brdf_variant=0, components=3, nthre
     lib().oracle_grad(b.ref, n, _ptr(pix), _ptr(h), _ptr(v), _ptr(g), _ptr(out["verts"]),
                       _ptr(out["normals"]), _ptr(out["diffuse"]), _ptr(out["specular"]), _ptr(out["rough"]),
                       _ptr(out["light"]), _ptr(out["rad"]), _ptr(out["cam"]), _ptr(out.get("tex_diffuse")),
-                      _ptr(out.get("tex_specular")), _ptr(out.get("tex_rough")), nthreads or default_threads())
-    if include_normals_path:
+                      _ptr(out.get("tex_specular")), _ptr(out.get("tex_rough")), nthreads or default_threads(),
+                      int(bool(abs_terms)))
+    if include_normals_path and not abs_terms:
         out["verts"] = out["verts"] + normals_vjp(scene, out["normals"])
     return out
 

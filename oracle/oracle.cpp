@@ -735,10 +735,13 @@ int oracle_render(const OrScene* sc, int32_t n_pix, const int32_t* pix, const in
 //   g_verts [N*3] (direct path only), g_normals [N*3], g_diffuse [N*3],
 //   g_specular [N*3], g_rough [N], g_light [L*9] (p0, e1, e2), g_rad [L*3],
 //   g_cam [12] (R row-major, then T).
+// abs_terms != 0 accumulates the magnitude of every (sample, light) term
+// instead of the term: the condition measure of each sum (test tolerance
+// only; not a gradient).
 int oracle_grad(const OrScene* sc, int32_t n_pix, const int32_t* pix, const int32_t* hit, const uint8_t* vis,
                 const double* dEdp, double* g_verts, double* g_normals, double* g_diffuse, double* g_specular,
                 double* g_rough, double* g_light, double* g_rad, double* g_cam, double* g_tex_c, double* g_tex_s,
-                double* g_tex_r, int32_t nthreads) {
+                double* g_tex_r, int32_t nthreads, int32_t abs_terms) {
   const Prepared P = prepare(sc);
   const int S = sc->spp, L = sc->n_lights, W = sc->width, N = sc->n_verts;
   if (!pix) n_pix = sc->width * sc->height;
@@ -806,6 +809,8 @@ int oracle_grad(const OrScene* sc, int32_t n_pix, const int32_t* pix, const int3
         const Vec3<D63> c = light_contribution(fr, lp, w1, w2, vs, sc->brdf_variant, sc->components, nullptr);
         double gs[NSLOT];
         for (int k = 0; k < NSLOT; ++k) gs[k] = g[0] * c.x.d[k] + g[1] * c.y.d[k] + g[2] * c.z.d[k];
+        if (abs_terms)
+          for (int k = 0; k < NSLOT; ++k) gs[k] = std::fabs(gs[k]);
         for (int k = 0; k < 3; ++k)
           for (int a = 0; a < 3; ++a) {
             A.v[3 * vid[k] + a] += gs[SLOT_V + 3 * k + a];

@@ -105,3 +105,22 @@ def test_directional_gradients_match_frozen_central_differences(oracle_lib, grou
     fd = cd(2.0 ** -20)
     an = float((g[group] * d).sum())
     assert math.isclose(fd, an, rel_tol=2e-5, abs_tol=1e-8 * np.abs(g[group]).sum()), (fd, an)
+
+
+def test_term_magnitudes_bound_the_gradient(oracle_lib):
+    """abs_terms (the condition measure of the parity tolerances) bounds
+    every element of the gradient it measures, and equals it for the
+    radiance of a single light, whose terms all share one sign when the
+    weights are positive."""
+    o = oracle_lib
+    sc = scenes.patch_scene(W=12, H=12, spp=2)
+    dec = o.render(sc)
+    w = np.random.default_rng(2).normal(size=dec["rgb"].shape)
+    g = o.grad(sc, dec["hit"], dec["vis"], w, include_normals_path=False)
+    m = o.grad(sc, dec["hit"], dec["vis"], w, abs_terms=True)
+    for k in ("verts", "normals", "diffuse", "specular", "rough", "light", "rad", "cam"):
+        assert np.all(np.abs(g[k]) <= m[k] * (1 + 1e-12) + 1e-300), k
+    assert m["normals"].sum() > np.abs(g["normals"]).sum()
+    gp = o.grad(sc, dec["hit"], dec["vis"], np.abs(w))
+    mp = o.grad(sc, dec["hit"], dec["vis"], np.abs(w), abs_terms=True)
+    assert np.allclose(mp["rad"], np.abs(gp["rad"]), rtol=1e-12, atol=0)
