@@ -46,8 +46,15 @@ enum {
 /* Mesh update modes of fr_mesh_update. */
 enum { FR_REFIT = 0, FR_REBUILD = 1, FR_REBUILD_SAH = 2 };
 
-/* Light shapes. */
-enum { FR_LIGHT_PARALLELOGRAM = 0, FR_LIGHT_TRIANGLE = 1 };
+/* Light shapes.  FR_LIGHT_DIRECTIONAL is a light at infinity (each pixel of
+ * the environment map of Sec. 6, "Environment Map vs. Light Stage"): it
+ * shines along l = p0 / |p0| (p0 need not be unit; e1, e2 are ignored and
+ * get no gradient), `light_rad` is the irradiance it delivers to a surface
+ * facing it (radiance times the solid angle the light stands for), a
+ * sample receives V rad f_r (n_s . l), and its shadow ray runs over
+ * t in (1e-4, 1e4) (the scene must lie well within 1e4).  No random numbers
+ * are drawn for it. */
+enum { FR_LIGHT_PARALLELOGRAM = 0, FR_LIGHT_TRIANGLE = 1, FR_LIGHT_DIRECTIONAL = 2 };
 
 /* BRDF readings (Appendix A, Eq. brdf_d and Eq. brdf_f).
  * FR_BRDF_PRINTED:   D = (2/r + 2)/(2 pi) (n.h)^(2/r - 2), F = s + (1 - s)(1 - o.h)
@@ -232,7 +239,9 @@ int fr_loss(const float* d_image, const float* d_target, int32_t width, int32_t 
  * With reflectance maps each shading point spreads its reflectance gradient
  * over its four texels by the bilinear weights (grads->tex_*), and the maps'
  * own slope in (u, v) carries into the barycentrics and the vertices.
- * At most 128 lights (FR_ERR_LIMIT otherwise).
+ * Any number of lights: more than 128 are taken in groups of 128, one
+ * adjoint and one boundary-term launch per group (the sample-level chain
+ * is linear in the summed per-light adjoints, so the groups' chains add).
  * Uses the mesh's internal scratch; calls on one mesh must not overlap. */
 int fr_render_backward(fr_mesh* mesh, const fr_scene* scene, const fr_render_opts* opts, const float* d_dEdp,
                        fr_grads* grads, fr_stream stream);

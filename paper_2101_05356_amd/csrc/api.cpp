@@ -125,6 +125,7 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
   a.partial = nullptr;
   a.prim = nullptr;   // set by the caller (ensure_prim, or a job's own buffer)
   a.vis_out = nullptr; a.vis_in = nullptr; a.vis_lc = 0;
+  a.light0 = 0;
   a.tiles_x = (a.W + a.tile_w - 1) / a.tile_w;
   a.tiles_y = (a.H + a.tile_h - 1) / a.tile_h;
   a.n_tiles = a.tiles_x * a.tiles_y;
@@ -327,12 +328,14 @@ int32_t fr_mesh_edges(const fr_mesh* m, int32_t* h_edges, int32_t* h_faces) {
 int32_t fr_mesh_bvh_depth(const fr_mesh* m) { return m ? m->d.bvh_depth : -1; }
 
 // The backward's light chunks: the four waves of a block take a tile's
-// chunks, so lc >= ceil(L / 4) (at most 32 lights per chunk).
+// chunks of one light group (at most 128 lights), so lc >= ceil(L_group / 4)
+// (at most 32 lights per chunk).  The adjoint launcher recomputes them per
+// group; a batch job (at most 128 lights) has one group.
 int bwd_chunks(fr_mesh* m, fr::RenderArgs& a) {
-  if (a.L > fr::kBwdMaxLights) return fail(m->ctx, FR_ERR_LIMIT, "the backward takes at most 128 lights");
-  a.lc = std::max(a.lc, std::max(1, fr::cdiv(a.L, 4)));
+  const int Lg = std::min(a.L, fr::kBwdMaxLights);
+  a.lc = std::max(a.lc, std::max(1, fr::cdiv(Lg, 4)));
   if (a.lc > 32) return fail(m->ctx, FR_ERR_LIMIT, "light_chunk must be <= 32");
-  a.n_lchunks = std::max(1, fr::cdiv(a.L, a.lc));
+  a.n_lchunks = std::max(1, fr::cdiv(Lg, a.lc));
   return FR_OK;
 }
 
@@ -458,7 +461,7 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
   a.lights = m->d.lights;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   fr::MeshDev& d = m->d;
-  const size_t need = (size_t)fr::kSlots * (12 * (size_t)s->n_lights + 12);
+  const size_t need = (size_t)fr::kSlots * (12 * (size_t)std::min(s->n_lights, fr::kBwdMaxLights) + 12);
   if (need > d.slots_cap) {
     if (d.slots) (void)hipFree(d.slots);
     d.slots = nullptr;

@@ -43,8 +43,9 @@ __device__ __forceinline__ void g1_fwd_bwd(float nv, float hv, float r, float& G
   dG1_dr = -dG * a / r;             // da/dr = -a / r
 }
 
-// The shadow decisions of lights [j0, j1) for sample rs, read from the masks
-// the forward kept (its chunks of vis_lc lights need not align with these):
+// The shadow decisions of lights [j0, j1) (global indices) for sample rs,
+// read from the masks the forward kept (its chunks of vis_lc lights need not
+// align with these):
 // the same bits shadow_mask returns, since a lane's bit depends on its own
 // shading point, light draw and ray only.  Zero where the adjoint does not
 // shade the sample.
@@ -102,17 +103,17 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
       V3 gx = {0, 0, 0}, gns = {0, 0, 0}, gwo = {0, 0, 0}, gc = {0, 0, 0}, gs = {0, 0, 0};
       float gr = 0.0f;
       // shadow decisions of every light of the chunk, then the adjoint of the visible ones
-      const auto draw = [&](int j) { return philox((uint32_t)ps.pid, (uint32_t)s, 1u + (uint32_t)j, a.step, a.k0, a.k1); };
+      const auto draw = [&](int j) { return philox((uint32_t)ps.pid, (uint32_t)s, 1u + (uint32_t)(a.light0 + j), a.step, a.k0, a.k1); };
       const auto none = [](int, bool, bool, const LightSample&, const HitState&) {};
       const auto skip = [](int) {};
       uint32_t vmask;
-      if (KEPT) vmask = kept_mask(a, j0, j1, rs, shaded);
+      if (KEPT) vmask = kept_mask(a, a.light0 + j0, a.light0 + j1, rs, shaded);
       else vmask = shadow_mask<false>(a, j0, j1, shaded, fr, ph.id, draw, none, skip, nullptr);
       for (int j = j0; j < j1; ++j) {
         const bool vis = (vmask >> (j - j0)) & 1u;
         if (!ballot(vis)) continue;
         const LightRec Lj = load_const(a.lights, j);
-        const U4 r = draw(j);
+        const U4 r = Lj.shape == FR_LIGHT_DIRECTIONAL ? U4{0u, 0u, 0u, 0u} : draw(j);
         LightSample ls;
         light_point(Lj, unit24(r.x), unit24(r.y), fr, ls);
         float gl12[12];
@@ -188,20 +189,28 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
           // cos_o = ns . wo ; cos_s = ns . l ; cos_a = na . l
           gns = gns + fr.wo * gcos_o + ls.l * gcos_s;
           gwo = gwo + fr.ns * gcos_o;
-          gl = gl + fr.ns * gcos_s + na * gcos_a;
-          const V3 gna = ls.l * gcos_a;
-          // na = -kappa (e1 x e2)
-          const float kap = Lj.shape == FR_LIGHT_TRIANGLE ? 0.5f : 1.0f;
-          const V3 e1 = {Lj.e1[0], Lj.e1[1], Lj.e1[2]}, e2 = {Lj.e2[0], Lj.e2[1], Lj.e2[2]};
-          const V3 ge1n = cross(e2, gna) * (-kap), ge2n = cross(gna, e1) * (-kap);
-          // l = dq / |dq|, dist2 = dq . dq
-          V3 gdq = project_out(gl, ls.l, 1.0f / ls.dist);
-          gdq = gdq + (ls.q - fr.x) * (2.0f * gdist2);
-          gx = gx - gdq;
-          // q = p0 + w1 e1 + w2 e2
-          gl12[0] = gdq.x; gl12[1] = gdq.y; gl12[2] = gdq.z;
-          gl12[3] = gdq.x * ls.w1 + ge1n.x; gl12[4] = gdq.y * ls.w1 + ge1n.y; gl12[5] = gdq.z * ls.w1 + ge1n.z;
-          gl12[6] = gdq.x * ls.w2 + ge2n.x; gl12[7] = gdq.y * ls.w2 + ge2n.y; gl12[8] = gdq.z * ls.w2 + ge2n.z;
+          if (Lj.shape == FR_LIGHT_DIRECTIONAL) {
+            // light at infinity: geom = cos_s, l = p0 / |p0| (no point, no
+            // dependence on x); the direction's gradient goes to p0
+            gl = gl + fr.ns * gcos_s;
+            const V3 gp = project_out(gl, ls.l, Lj.e1[0]);
+            gl12[0] = gp.x; gl12[1] = gp.y; gl12[2] = gp.z;
+          } else {
+            gl = gl + fr.ns * gcos_s + na * gcos_a;
+            const V3 gna = ls.l * gcos_a;
+            // na = -kappa (e1 x e2)
+            const float kap = Lj.shape == FR_LIGHT_TRIANGLE ? 0.5f : 1.0f;
+            const V3 e1 = {Lj.e1[0], Lj.e1[1], Lj.e1[2]}, e2 = {Lj.e2[0], Lj.e2[1], Lj.e2[2]};
+            const V3 ge1n = cross(e2, gna) * (-kap), ge2n = cross(gna, e1) * (-kap);
+            // l = dq / |dq|, dist2 = dq . dq
+            V3 gdq = project_out(gl, ls.l, 1.0f / ls.dist);
+            gdq = gdq + (ls.q - fr.x) * (2.0f * gdist2);
+            gx = gx - gdq;
+            // q = p0 + w1 e1 + w2 e2
+            gl12[0] = gdq.x; gl12[1] = gdq.y; gl12[2] = gdq.z;
+            gl12[3] = gdq.x * ls.w1 + ge1n.x; gl12[4] = gdq.y * ls.w1 + ge1n.y; gl12[5] = gdq.z * ls.w1 + ge1n.z;
+            gl12[6] = gdq.x * ls.w2 + ge2n.x; gl12[7] = gdq.y * ls.w2 + ge2n.y; gl12[8] = gdq.z * ls.w2 + ge2n.z;
+          }
         }
         for (int k = 0; k < 12; ++k) {
           const float t = wave_sum(gl12[k]);
@@ -458,28 +467,43 @@ __global__ __launch_bounds__(256) void k_slots_reduce(const fix_t* __restrict__ 
   slots_reduce_block(slots, nl, L, glight, grad, gcam, blockIdx.x);
 }
 
-// `slots` holds kSlots * (12 L + 12) accumulators (the caller sizes and owns it).
+// `slots` holds kSlots * (12 min(L, 128) + 12) accumulators (the caller sizes
+// and owns it).  Lights go in groups of at most 128, one launch each: the
+// sample-level chain is linear in the per-sample adjoint it starts from, so
+// the groups' chains and scatters add up to the chain of the full sum (the
+// vertex, texel and slot sums are exact integer sums).
 void launch_render_backward(const RenderArgs& a, const float* dEdp, const FixGrads& fg, fix_t* slots,
                             const fr_grads& g, hipStream_t st, hipEvent_t e0, hipEvent_t e1, bool trace_primary) {
-  const int nl = a.L * 12 + 12;
-  launch_zero_fix(slots, (size_t)kSlots * nl, st);
   const int blocks = tile_blocks(a);
-  const size_t lds = nl * sizeof(fix_t) + kBwdPartBytes;
   if (e0) (void)hipEventRecord(e0, st);
   if (trace_primary) launch_primary(a, st);
-  if (a.vis_in) {
-    if (a.M > 0)
-      hipLaunchKernelGGL(k_render_bwd_kept<true>, dim3(blocks), dim3(256), lds, st, a, dEdp, fg, slots);
-    else
-      hipLaunchKernelGGL(k_render_bwd_kept<false>, dim3(blocks), dim3(256), lds, st, a, dEdp, fg, slots);
-  } else {
-    if (a.M > 0)
-      hipLaunchKernelGGL(k_render_bwd<true>, dim3(blocks), dim3(256), lds, st, a, dEdp, fg, slots);
-    else
-      hipLaunchKernelGGL(k_render_bwd<false>, dim3(blocks), dim3(256), lds, st, a, dEdp, fg, slots);
+  const int user_lc = a.lc;
+  for (int g0 = 0; g0 == 0 || g0 < a.L; g0 += kBwdMaxLights) {
+    RenderArgs ag = a;
+    ag.L = std::min(kBwdMaxLights, a.L - g0);
+    ag.light0 = a.light0 + g0;
+    ag.lights = a.lights + g0;
+    ag.lc = std::max(user_lc, std::max(1, cdiv(ag.L, 4)));
+    ag.n_lchunks = std::max(1, cdiv(ag.L, ag.lc));
+    const int nl = ag.L * 12 + 12;
+    launch_zero_fix(slots, (size_t)kSlots * nl, st);
+    const size_t lds = nl * sizeof(fix_t) + kBwdPartBytes;
+    if (ag.vis_in) {
+      if (ag.M > 0)
+        hipLaunchKernelGGL(k_render_bwd_kept<true>, dim3(blocks), dim3(256), lds, st, ag, dEdp, fg, slots);
+      else
+        hipLaunchKernelGGL(k_render_bwd_kept<false>, dim3(blocks), dim3(256), lds, st, ag, dEdp, fg, slots);
+    } else {
+      if (ag.M > 0)
+        hipLaunchKernelGGL(k_render_bwd<true>, dim3(blocks), dim3(256), lds, st, ag, dEdp, fg, slots);
+      else
+        hipLaunchKernelGGL(k_render_bwd<false>, dim3(blocks), dim3(256), lds, st, ag, dEdp, fg, slots);
+    }
+    if (e1 && g0 + kBwdMaxLights >= a.L) (void)hipEventRecord(e1, st);
+    hipLaunchKernelGGL(k_slots_reduce, dim3(nl), dim3(256), 0, st, slots, nl, ag.L,
+                       g.light_geom ? g.light_geom + (size_t)9 * g0 : nullptr,
+                       g.light_rad ? g.light_rad + (size_t)3 * g0 : nullptr, g.cam);
   }
-  if (e1) (void)hipEventRecord(e1, st);
-  hipLaunchKernelGGL(k_slots_reduce, dim3(nl), dim3(256), 0, st, slots, nl, a.L, g.light_geom, g.light_rad, g.cam);
 }
 
 }  // namespace fr

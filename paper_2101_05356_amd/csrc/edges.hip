@@ -178,7 +178,7 @@ __device__ __forceinline__ V3 side_shade(const RenderArgs& a, float fx, float fy
   if (DUMP && ph.id >= 0 && fabsf(fr.cos_o) < kFlagCos) amb = true;
   V3 L = {0.0f, 0.0f, 0.0f};
   // shadow decisions of every light of the chunk, then the shading of the visible ones
-  const auto draw = [&](int j) { return philox((uint32_t)k, 0u, PURPOSE_EDGE + 1u + (uint32_t)j, a.step, a.k0, a.k1); };
+  const auto draw = [&](int j) { return philox((uint32_t)k, 0u, PURPOSE_EDGE + 1u + (uint32_t)(a.light0 + j), a.step, a.k0, a.k1); };
   const auto note = [&](int, bool lit, bool, const LightSample& ls, const HitState& sh) {
     if (shaded && ls.amb) amb = true;
     if (lit && sh.tamb < 3.0e38f) amb = true;
@@ -189,7 +189,7 @@ __device__ __forceinline__ V3 side_shade(const RenderArgs& a, float fx, float fy
     const bool vis = (vmask >> (j - j0)) & 1u;
     if (!ballot(vis)) continue;
     const LightRec Lj = load_const(a.lights, j);
-    const U4 r = draw(j);
+    const U4 r = Lj.shape == FR_LIGHT_DIRECTIONAL ? U4{0u, 0u, 0u, 0u} : draw(j);
     LightSample ls;
     light_point(Lj, unit24(r.x), unit24(r.y), fr, ls);
     if (vis) {
@@ -341,18 +341,26 @@ void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samp
   e.edges = m.edges; e.cdf = m.edge_cdf; e.E = m.E; e.n_samples = n_samples;
   e.th = tan_half; e.aspect = aspect; e.dEdp = dEdp; e.gverts = gverts; e.gcam = gcam;
   e.dbg_rec = dbg_rec; e.dbg_flag = dbg_flag;
-  e.lc = std::max(1, cdiv(a.L, 4));   // the four waves of a block
-  e.n_lchunks = std::max(1, cdiv(a.L, e.lc));
   const int blocks = (n_samples + 63) / 64;
-  if (a.M > 0) {
-    if (dbg_rec)
-      hipLaunchKernelGGL((k_edge_samples<true, true>), dim3(blocks), dim3(256), 0, st, a, e);
-    else
-      hipLaunchKernelGGL((k_edge_samples<false, true>), dim3(blocks), dim3(256), 0, st, a, e);
-  } else if (dbg_rec) {
-    hipLaunchKernelGGL((k_edge_samples<true, false>), dim3(blocks), dim3(256), 0, st, a, e);
-  } else {
-    hipLaunchKernelGGL((k_edge_samples<false, false>), dim3(blocks), dim3(256), 0, st, a, e);
+  // lights in groups of at most 128 (one launch each): the estimate is linear
+  // in f- - f+, so the groups' scatters add up (exact integer sums)
+  for (int g0 = 0; g0 == 0 || g0 < a.L; g0 += kBwdMaxLights) {
+    RenderArgs ag = a;
+    ag.L = std::min(kBwdMaxLights, a.L - g0);
+    ag.light0 = a.light0 + g0;
+    ag.lights = a.lights + g0;
+    e.lc = std::max(1, cdiv(ag.L, 4));   // the four waves of a block
+    e.n_lchunks = std::max(1, cdiv(ag.L, e.lc));
+    if (ag.M > 0) {
+      if (dbg_rec)
+        hipLaunchKernelGGL((k_edge_samples<true, true>), dim3(blocks), dim3(256), 0, st, ag, e);
+      else
+        hipLaunchKernelGGL((k_edge_samples<false, true>), dim3(blocks), dim3(256), 0, st, ag, e);
+    } else if (dbg_rec) {
+      hipLaunchKernelGGL((k_edge_samples<true, false>), dim3(blocks), dim3(256), 0, st, ag, e);
+    } else {
+      hipLaunchKernelGGL((k_edge_samples<false, false>), dim3(blocks), dim3(256), 0, st, ag, e);
+    }
   }
 }
 

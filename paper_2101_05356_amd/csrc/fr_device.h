@@ -28,6 +28,7 @@ namespace fr {
 constexpr int kWave = 64;
 constexpr int kStackDepth = 64;        // entries of the wave-uniform stack
 constexpr float kShadowTmin = 1e-4f;   // shadow rays start 1e-4 from the shading point
+constexpr float kDirectionalFar = 1e4f;   // shadow rays to a light at infinity end at 1e4
 constexpr float kRoughMin = 1e-3f, kRoughMax = 1.0f;
 constexpr float kPi = 3.14159265358979323846f;
 constexpr float kBoxPad = 1e-5f;       // absolute box enlargement (conservative traversal)
@@ -75,7 +76,9 @@ struct alignas(16) TriRec {
 };
 static_assert(sizeof(TriRec) == 48, "triangle record is 48 bytes");
 
-// Per-light constants, built once per render: 16 floats.
+// Per-light constants, built once per render: 16 floats.  A light at
+// infinity keeps its unit direction in p0 and 1 / |p0| in e1[0] (the rest of
+// e1, e2 and na are zero).
 struct alignas(16) LightRec {
   float p0[3], e1[3], e2[3];
   float na[3];     // -kappa (e1 x e2): A_j (-n_j) with kappa = 1 (parallelogram) or 1/2 (triangle)

@@ -156,6 +156,7 @@ struct RenderArgs {
   int chunks;             // S / 64 when S > 64, else 1
   int lanes_per_pixel;    // min(S, 64)
   int lc, n_lchunks;      // lights per work item, light chunks per tile
+  int light0;             // global index of lights[0] (> 0 in the adjoint's later light groups)
   float* partial;         // [n_lchunks][H*W*3] per-chunk pixel sums (n_lchunks > 1)
   PrimHit* prim;          // [H*W*S] primary hits, sample index (y*W + x)*S + s
   // Shadow masks, word (c, sample) at c*W*H*S + sample: bit b is light
@@ -204,7 +205,7 @@ void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st, hi
 // backward repeats more per-item work (primary trace, chain, scatter), so it
 // takes longer items.
 constexpr int kLightChunkFwd = 12;
-constexpr int kBwdMaxLights = 128;   // four chunks of at most 32 lights
+constexpr int kBwdMaxLights = 128;   // four chunks of at most 32 lights: one adjoint launch's light group
 constexpr size_t kBwdPartBytes = 4 * 64 * 16 * sizeof(float) + 16;   // backward LDS: sample adjoints of 4 waves, arrivals
 // The boundary term has one wave per 64 edge samples and light chunk: short
 // chunks give the launch enough waves to fill the chip.

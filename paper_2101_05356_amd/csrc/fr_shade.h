@@ -291,8 +291,22 @@ __device__ __forceinline__ void light_weights(int shape, float u0, float u1, flo
 
 // Returns true when light j contributes to this shading point before
 // visibility: n_s . l > 0 and -n_j . l > 0 (the caller already required
-// n_s . o > 0).  geom = (n_s . l) A_j (-n_j . l) / |q - x|^2.
+// n_s . o > 0).  geom = (n_s . l) A_j (-n_j . l) / |q - x|^2.  A light at
+// infinity: l is its direction, geom = n_s . l, and the shadow segment ends
+// at kDirectionalFar (q is left at x: nothing depends on a point).
 __device__ __forceinline__ bool light_point(const LightRec& Lj, float u0, float u1, const Frame& f, LightSample& ls) {
+  if (Lj.shape == FR_LIGHT_DIRECTIONAL) {
+    ls.w1 = 0.0f; ls.w2 = 0.0f;
+    ls.l = {Lj.p0[0], Lj.p0[1], Lj.p0[2]};
+    ls.q = f.x;
+    ls.dist = kDirectionalFar;
+    ls.dist2 = 1.0f;
+    ls.cos_s = dot(f.ns, ls.l);
+    ls.cos_a = 1.0f;
+    ls.geom = ls.cos_s;
+    ls.amb = fabsf(ls.cos_s) < kFlagCos;
+    return ls.cos_s > 0.0f;
+  }
   light_weights(Lj.shape, u0, u1, ls.w1, ls.w2);
   ls.q = {Lj.p0[0] + Lj.e1[0] * ls.w1 + Lj.e2[0] * ls.w2, Lj.p0[1] + Lj.e1[1] * ls.w1 + Lj.e2[1] * ls.w2,
           Lj.p0[2] + Lj.e1[2] * ls.w1 + Lj.e2[2] * ls.w2};
@@ -316,6 +330,8 @@ __device__ __forceinline__ bool light_point(const LightRec& Lj, float u0, float 
 // light (no random numbers, no shadow ray): the exact tests would have
 // culled every lane anyway, without ambiguity.
 __device__ __forceinline__ bool light_may_contribute(const LightRec& Lj, const Frame& f) {
+  if (Lj.shape == FR_LIGHT_DIRECTIONAL)
+    return !(f.ns.x * Lj.p0[0] + f.ns.y * Lj.p0[1] + f.ns.z * Lj.p0[2] < -1e-4f);
   const V3 d0 = {Lj.p0[0] - f.x.x, Lj.p0[1] - f.x.y, Lj.p0[2] - f.x.z};
   const float a = dot(f.ns, d0);
   const float b = f.ns.x * Lj.e1[0] + f.ns.y * Lj.e1[1] + f.ns.z * Lj.e1[2];
@@ -346,7 +362,7 @@ __device__ __forceinline__ uint32_t shadow_mask(const RenderArgs& a, int j0, int
       skip(j);
       continue;
     }
-    const U4 r = draw(j);
+    const U4 r = Lj.shape == FR_LIGHT_DIRECTIONAL ? U4{0u, 0u, 0u, 0u} : draw(j);
     LightSample ls;
     const bool lit = shaded && light_point(Lj, unit24(r.x), unit24(r.y), fr, ls);
     Ray sr;

@@ -395,12 +395,21 @@ __device__ __forceinline__ void light_setup_block(const float* __restrict__ p0, 
   const int j = bid * blockDim.x + threadIdx.x;
   if (j >= L) return;
   LightRec r;
-  const V3 a = ld3(e1, j), b = ld3(e2, j);
-  const V3 n = cross(a, b);
-  const float kappa = shape[j] == FR_LIGHT_TRIANGLE ? 0.5f : 1.0f;
-  for (int k = 0; k < 3; ++k) { r.p0[k] = p0[3 * j + k]; r.e1[k] = e1[3 * j + k]; r.e2[k] = e2[3 * j + k]; r.rad[k] = rad[3 * j + k]; }
-  r.na[0] = -kappa * n.x; r.na[1] = -kappa * n.y; r.na[2] = -kappa * n.z;
+  for (int k = 0; k < 3; ++k) r.rad[k] = rad[3 * j + k];
   r.shape = shape[j];
+  if (r.shape == FR_LIGHT_DIRECTIONAL) {
+    const V3 d = ld3(p0, j);
+    const float il = 1.0f / sqrtf(dot(d, d));
+    r.p0[0] = d.x * il; r.p0[1] = d.y * il; r.p0[2] = d.z * il;
+    for (int k = 0; k < 3; ++k) { r.e1[k] = 0.0f; r.e2[k] = 0.0f; r.na[k] = 0.0f; }
+    r.e1[0] = il;
+  } else {
+    const V3 a = ld3(e1, j), b = ld3(e2, j);
+    const V3 n = cross(a, b);
+    const float kappa = r.shape == FR_LIGHT_TRIANGLE ? 0.5f : 1.0f;
+    for (int k = 0; k < 3; ++k) { r.p0[k] = p0[3 * j + k]; r.e1[k] = e1[3 * j + k]; r.e2[k] = e2[3 * j + k]; }
+    r.na[0] = -kappa * n.x; r.na[1] = -kappa * n.y; r.na[2] = -kappa * n.z;
+  }
   out[j] = r;
 }
 

@@ -106,7 +106,7 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
     Frame fr;
     const bool shaded = ps.valid && ph.id >= 0 && shading_frame<TEX>(a, sm, ph.id, ph.t, bd, fr);
     // shadow decisions of every light of the chunk, then the shading of the visible ones
-    const auto draw = [&](int j) { return philox((uint32_t)ps.pid, (uint32_t)s, 1u + (uint32_t)j, a.step, a.k0, a.k1); };
+    const auto draw = [&](int j) { return philox((uint32_t)ps.pid, (uint32_t)s, 1u + (uint32_t)(a.light0 + j), a.step, a.k0, a.k1); };
     const auto note = [&](int j, bool lit, bool occ, const LightSample& ls, const HitState& sh) {
       if (ps.valid) {
         const uint8_t code = !shaded ? VIS_NONE : (!lit ? VIS_CULLED : (occ ? VIS_OCCLUDED : VIS_VISIBLE));
@@ -123,7 +123,7 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
       const bool vis = (vmask >> (j - j0)) & 1u;
       if (!ballot(vis)) continue;
       const LightRec Lj = load_const(a.lights, j);
-      const U4 r = draw(j);
+      const U4 r = Lj.shape == FR_LIGHT_DIRECTIONAL ? U4{0u, 0u, 0u, 0u} : draw(j);
       LightSample ls;
       light_point(Lj, unit24(r.x), unit24(r.y), fr, ls);
       if (vis) {

@@ -1,0 +1,154 @@
+"""Lights at infinity (the environment-map lighting of Sec. 6, "Environment
+Map vs. Light Stage") and light counts above one adjoint launch's group of
+128, against the FP64 oracle through the C ABI: forward decisions and pixels,
+interior adjoint (light directions, irradiances, vertices, camera), the
+boundary term, and the adjoint taking the forward's decisions across light
+groups bit for bit.  Tolerances are those of the area-light parity tests."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2101_05356_amd import scenes
+from tests import gpu_common as G
+from tests.test_gpu_render import _forward_parity
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def with_environment(sc, res, keep_area=True, seed=13):
+    env = scenes.environment_lights(res, seed=seed)
+    if keep_area:
+        lt = sc.lights
+        env = scenes.Lights(p0=np.concatenate([env.p0, lt.p0]), e1=np.concatenate([env.e1, lt.e1]),
+                            e2=np.concatenate([env.e2, lt.e2]), rad=np.concatenate([env.rad, lt.rad]),
+                            shape=np.concatenate([env.shape, lt.shape]).astype(np.int32))
+    return dataclasses.replace(sc, lights=env)
+
+
+def mixed_patch(W=32, H=32, spp=2, res=16):
+    """Tilted bump patch under a res x res environment map plus its 8 square
+    lights (264 lights at res 16: adjoint groups of 128, 128 and 8)."""
+    from tests.test_oracle_grad import tilt_camera
+    return with_environment(tilt_camera(scenes.patch_scene(W=W, H=H, spp=spp)), res)
+
+
+def _backward_parity(sc, pixels=None, variant=0, seed=3):
+    """Forward parity, then the interior adjoint of a random dE/dp.  With a
+    few hundred lights from every direction, a vertex's normal or roughness
+    gradient sums hundreds of per-light terms of both signs within each
+    sample (opposite lights pull the normal opposite ways), in FP32 on the
+    GPU: the element-wise bar applies to the elements whose sum is well
+    conditioned (sum of term magnitudes, per pixel and per (sample, light)
+    term, at most 10x the sum; gpu_common.grad_tol_ok), the L2 bar to every
+    element."""
+    import oracle
+    m, ds, img, hit, vis, mh, mv = _forward_parity(sc, pixels=pixels, variant=variant)
+    W, H = sc.camera.W, sc.camera.H
+    rng = np.random.default_rng(seed)
+    dEdp = np.zeros((H * W, 3), np.float32)
+    rows = np.arange(W * H) if pixels is None else pixels
+    dEdp[rows] = rng.normal(size=(len(rows), 3)).astype(np.float32)
+    g = G.R.render_backward(m, ds, torch.tensor(dEdp.reshape(H, W, 3)).cuda(), brdf_variant=variant)
+    torch.cuda.synchronize()
+    full = dEdp[rows].astype(np.float64)
+    go = oracle.grad(sc, mh, mv, full, pixels=pixels, brdf_variant=variant)
+    pairs = [("verts", "verts"), ("normals", "normals"), ("diffuse", "diffuse"), ("specular", "specular"),
+             ("roughness", "rough"), ("light_rad", "rad"), ("cam", "cam"), ("light_geom", "light")]
+    mag = G.magnitude_sums(sc, mh, mv, full, [o for _, o in pairs], pixels=pixels)
+    terms = oracle.grad(sc, mh, mv, full, pixels=pixels, brdf_variant=variant, abs_terms=True)
+    mag = {k: np.maximum(v, np.abs(terms[k])) for k, v in mag.items()}
+    res = {gk: G.grad_tol_ok(G.to_np(g[gk]), go[ok_], mag=mag[ok_]) for gk, ok_ in pairs}
+    _note(f"gradients (ok, l2, worst element): {res}")
+    for k, (ok_, l2, el) in res.items():
+        assert ok_, (k, l2, el)
+    # the directions' gradients (p0 slots) are there; e1, e2 slots stay zero
+    gl = G.to_np(g["light_geom"]).reshape(-1, 3, 3)
+    env = sc.lights.shape == scenes.LIGHT_DIRECTIONAL
+    assert np.abs(gl[env, 0]).sum() > 0 and not np.any(gl[env, 1:])
+
+
+def test_environment_patch_forward_and_adjoint(oracle_lib):
+    sc = mixed_patch()
+    _note(f"lights {sc.lights.count}")
+    _backward_parity(sc)
+
+
+def test_environment_patch_ragged_specular_variant(oracle_lib):
+    sc = mixed_patch(W=19, H=13, spp=4, res=12)
+    _backward_parity(sc, variant=1)
+
+
+def test_environment_face_subset(oracle_lib):
+    """A coarser face (80 x 56 lat-long mesh) under the paper's 32 x 32 map
+    (1,024 lights at infinity, eight adjoint groups)."""
+    sc = scenes.face_render_scene(W=64, H=64, spp=2, n_lights=4, n_lon=80, n_ring=56)
+    sc = with_environment(sc, 32, keep_area=False)
+    px = scenes.random_pixel_subset(np.random.default_rng(6), 64, 64, 24)
+    px = np.unique(np.concatenate([px, [32 * 64 + 32, 32 * 64 + 12]])).astype(np.int32)
+    _backward_parity(sc, pixels=px)
+
+
+def test_environment_edge_term(oracle_lib):
+    """Boundary term with 264 lights (three launches of the boundary-term
+    kernel): records bit-exact on the unflagged samples, gradients to the
+    edge-term tolerance.  A sample is flagged when any of its 2 x 264
+    shadow or cosine decisions is near-ambiguous (so far more often than
+    with 8 lights: up to 5 %); its pixel's dE/dp is then zeroed on both
+    sides, which removes exactly its term (and its pixel's other terms)
+    from both gradients."""
+    import oracle
+    sc = mixed_patch(W=32, H=32, spp=2)
+    m, ds = G.gpu_setup(sc)
+    ns = 32 * 32
+    w = np.random.default_rng(9).normal(size=(ns, 3)).astype(np.float32)
+    g = G.R.render_backward(m, ds, torch.tensor(w.reshape(32, 32, 3)).cuda(), edge_samples=ns, groups=("cam",),
+                            edge_dump=True)
+    torch.cuda.synchronize()
+    rec, fl = G.to_np(g["edge_rec"]), G.to_np(g["edge_flag"])
+    eo = oracle.edge_grad(sc, w.astype(np.float64), ns)
+    flag = (fl != 0) | (eo["flag"] != 0)
+    _note(f"edge samples: {ns}, flagged {flag.mean():.4f}")
+    assert flag.mean() < 0.05
+    assert np.array_equal(rec[~flag], eo["edge"][~flag])
+    drop = np.unique(np.concatenate([rec[flag, 1], eo["edge"][flag, 1]]))
+    w2 = w.copy()
+    w2[drop[drop >= 0]] = 0.0
+    d2 = torch.tensor(w2.reshape(32, 32, 3)).cuda()
+    ge = G.R.render_backward(m, ds, d2, edge_samples=ns, groups=("verts", "cam"))
+    gi = G.R.render_backward(m, ds, d2, edge_samples=0, groups=("verts", "cam"))
+    torch.cuda.synchronize()
+    eo2 = oracle.edge_grad(sc, w2.astype(np.float64), ns)
+    okv = G.grad_tol_ok(G.to_np(ge["verts"]) - G.to_np(gi["verts"]), eo2["verts"], rel=2e-4)
+    okc = G.grad_tol_ok(G.to_np(ge["cam"]) - G.to_np(gi["cam"]), eo2["cam"], rel=2e-4)
+    _note(f"edge grads: verts {okv}, cam {okc}")
+    assert np.abs(eo2["verts"]).sum() > 0
+    assert okv[1] < 2e-4 and okc[1] < 2e-4
+
+
+def test_kept_decisions_across_light_groups_bit_identical(oracle_lib):
+    """The forward keeps 12-light mask words over all 264 lights; each
+    adjoint group composes its chunks from them (global light indices)."""
+    sc = mixed_patch(W=40, H=24, spp=4)
+    m, ds = G.gpu_setup(sc)
+    dEdp = torch.tensor(np.random.default_rng(4).normal(size=(24, 40, 3)).astype(np.float32)).cuda()
+    groups = ("verts", "diffuse", "light_geom", "light_rad", "cam")
+
+    def bwd(reuse, lc=0):
+        g = G.R.render_backward(m, ds, dEdp, edge_samples=-1, groups=groups, reuse_forward=reuse, light_chunk=lc)
+        torch.cuda.synchronize()
+        return [G.to_np(g[k]) for k in groups]
+
+    for lc in (0, 7):
+        want = bwd(False, lc)
+        G.R.render_forward(m, ds, keep_shadows=True)
+        got = bwd(True, lc)
+        assert all(np.array_equal(x, y) for x, y in zip(want, got)), lc
+        assert float(np.abs(want[3][:256]).sum()) > 0 and float(np.abs(want[3][256:]).sum()) > 0
