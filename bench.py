@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--large-steps", type=int, default=3,
                     help="steps of the 1024^2 textured render measurement (0 = skip)")
     ap.add_argument("--large-only", action="store_true", help="run only the large textured render measurement")
+    ap.add_argument("--envmap-steps", type=int, default=5,
+                    help="steps of the face under a 32x32 environment map (1,024 lights at infinity; 0 = skip)")
+    ap.add_argument("--envmap-only", action="store_true", help="run only the environment-map measurement")
     return ap.parse_args()
 
 
@@ -245,10 +248,41 @@ def large_bench(ctx, steps, warmup, edge_samples=-1, seed=51):
     (the deformed sets are generated before the timed region), the forward
     render, the smoothed L1 loss against a synthetic photograph and the
     backward to vertices (with the boundary term) and texels."""
-    import torch
     from paper_2101_05356_amd import render as R
     from paper_2101_05356_amd import scenes
     sc = scenes.large_textured_scene()
+    r = render_step_bench(ctx, sc, steps, warmup, ("verts",) + R.TEX_GROUPS, edge_samples, seed)
+    W, H, S, L = sc.camera.W, sc.camera.H, sc.spp, sc.lights.count
+    r["workload"] = (f"{W}x{H} textured face: {sc.n_verts:,}-vertex / {len(sc.tris):,}-triangle lat-long mesh, "
+                     f"{sc.tex_size}^2 maps, {S} spp, {L} lights, refit+render+loss+backward (verts with "
+                     f"{r['edge_samples']} edge samples, texels)")
+    return r
+
+
+def envmap_bench(ctx, steps, warmup, edge_samples=-1, seed=52):
+    """The face workload under the environment-map lighting of the paper's
+    ablation (Sec. 6): the 256 x 256 face (28,002 vertices, 56,000
+    triangles), 16 spp, a 32 x 32 latitude-longitude map whose 1,024 pixels
+    are lights at infinity; per step a refit, the forward, the loss and the
+    backward to vertices (with the boundary term) and the map's irradiances."""
+    from paper_2101_05356_amd import scenes
+    import dataclasses
+    sc = dataclasses.replace(scenes.face_render_scene(W=256, H=256, spp=16, n_lights=1),
+                             lights=scenes.environment_lights(32))
+    r = render_step_bench(ctx, sc, steps, warmup, ("verts", "light_rad"), edge_samples, seed)
+    r["workload"] = (f"256x256 face: {sc.n_verts:,}-vertex / {len(sc.tris):,}-triangle mesh, 16 spp, 32x32 "
+                     f"environment map (1,024 lights at infinity), refit+render+loss+backward (verts with "
+                     f"{r['edge_samples']} edge samples, map irradiances)")
+    return r
+
+
+def render_step_bench(ctx, sc, steps, warmup, groups, edge_samples=-1, seed=51):
+    """Refit + forward (keeping its decisions) + loss + backward (taking them)
+    per step on one scene; the deformed vertex sets and the target are made
+    before the timed region."""
+    import torch
+    from paper_2101_05356_amd import render as R
+    from paper_2101_05356_amd import scenes
     W, H, S, L = sc.camera.W, sc.camera.H, sc.spp, sc.lights.count
     rng = np.random.default_rng(seed)
     n_sets = warmup + steps
@@ -258,7 +292,6 @@ def large_bench(ctx, steps, warmup, edge_samples=-1, seed=51):
     ds = R.DeviceScene.from_scene(sc)
     m.update(ds.verts, rebuild=True)
     ns = W * H if edge_samples < 0 else edge_samples
-    groups = ("verts",) + R.TEX_GROUPS
     ev = {k: [] for k in ("fwd", "bwd")}
 
     def step(i, timed):
@@ -283,10 +316,7 @@ def large_bench(ctx, steps, warmup, edge_samples=-1, seed=51):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     nominal = W * H * S * (1 + L)
-    return {"workload": f"{W}x{H} textured face: {sc.n_verts:,}-vertex / {len(sc.tris):,}-triangle lat-long mesh, "
-                        f"{sc.tex_size}^2 maps, {S} spp, {L} lights, refit+render+loss+backward (verts with "
-                        f"{ns} edge samples, texels)",
-            "steps": steps, "ms_per_step": 1e3 * dt / steps, "rays_per_s": nominal * steps / dt,
+    return {"edge_samples": ns, "steps": steps, "ms_per_step": 1e3 * dt / steps, "rays_per_s": nominal * steps / dt,
             "render_fwd_kernel_ms": float(np.mean([a.elapsed_time(b) for a, b in ev["fwd"]])),
             "render_bwd_kernel_ms": float(np.mean([a.elapsed_time(b) for a, b in ev["bwd"]])),
             "loss": float(E.item())}
@@ -315,6 +345,9 @@ def main():
     ctx = R.Context(0)
     if args.large_only:
         print(json.dumps({"large": large_bench(ctx, max(args.large_steps, 1), 1)}), flush=True)
+        return
+    if args.envmap_only:
+        print(json.dumps({"envmap": envmap_bench(ctx, max(args.envmap_steps, 1), 2)}), flush=True)
         return
     mt, rc = make_c2(ctx, W, S, L, args.edge_samples)
     for _ in range(args.warmup):
@@ -375,6 +408,9 @@ def main():
     if args.large_steps > 0 and not args.profile_only:
         out["large"] = large_bench(ctx, args.large_steps, 1)
         print(json.dumps({"progress": "large", **out["large"]}), file=sys.stderr, flush=True)
+    if args.envmap_steps > 0 and not args.profile_only:
+        out["envmap"] = envmap_bench(ctx, args.envmap_steps, 2)
+        print(json.dumps({"progress": "envmap", **out["envmap"]}), file=sys.stderr, flush=True)
     if not args.profile_only and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, S, L, W)
     print(json.dumps(out), flush=True)

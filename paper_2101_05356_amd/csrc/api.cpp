@@ -787,8 +787,7 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   const fr::MeshDev& md_ = jh->mesh->d;
   J.ea.edges = md_.edges; J.ea.cdf = md_.edge_cdf; J.ea.E = md_.E;
   J.ea.n_samples = d->edge_samples < 0 ? d->width * d->height : d->edge_samples;
-  J.ea.lc = std::max(1, fr::cdiv(L, 4));   // the four waves of a boundary-term block
-  J.ea.n_lchunks = std::max(1, fr::cdiv(L, J.ea.lc));
+  fr::edge_groups(L, J.ea.n_samples, J.ea);
   J.ea.th = std::tan(0.5 * (double)d->fov_y);
   J.ea.aspect = (double)d->width / (double)d->height;
   J.ea.dEdp = J.dEdp; J.ea.gverts = md_.acc; J.ea.gcam = nullptr; J.ea.dbg_rec = nullptr; J.ea.dbg_flag = nullptr;

@@ -174,7 +174,7 @@ static int stage_blocks(const JobDev& J, int s) {
     case S_SLOTS: return 12 * J.ra.L + 12;
     case S_EDGE_LEN: return J.ea.n_samples > 0 ? cdiv(J.ea.E, 256) : 0;
     case S_EDGE_SCAN: case S_EDGE_SCAN_ADD: return J.ea.n_samples > 0 ? cdiv(J.ea.E, kScanTile) : 0;
-    case S_EDGE_SAMPLES: return J.ea.n_samples > 0 ? cdiv(J.ea.n_samples, 64) : 0;
+    case S_EDGE_SAMPLES: return J.ea.n_samples > 0 ? J.ea.bx * J.ea.n_groups : 0;
     case S_POSE_BWD_P: return 1;
     case S_BLEND_BWD_GEO: return J.K_geo;
     case S_BLEND_BWD_ALB: return J.K_alb;

@@ -204,19 +204,25 @@ __device__ __forceinline__ V3 side_shade(const RenderArgs& a, float fx, float fy
   return L;
 }
 
-// One block = 64 consecutive edge samples (lane = sample); its four waves are
-// the light chunks (lc >= L/4).  Waves 0 and 1 trace the minus and plus side
-// rays into LDS; every wave shades both sides with its lights; the last wave
-// to arrive sums the chunks in order and scatters the gradient once.
+// One block = 64 consecutive edge samples (lane = sample) and one group of
+// lights; its four waves are the group's light chunks.  Waves 0 and 1 trace
+// the minus and plus side rays into LDS; every wave shades both sides with
+// its lights; the last wave to arrive sums the chunks in order and scatters
+// the group's part of the estimate (linear in f- - f+, so the groups' parts
+// add up in the integer sums).
 template <bool DUMP, bool TEX>
 __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const EdgeArgs& e, int bid) {
   __shared__ PrimHit side_hit[2][64];
   __shared__ float side_L[4][64][6];
   __shared__ int arrived;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int group = bid;
-  const int j0 = wv * e.lc, j1 = min(a.L, j0 + e.lc);
-  const int k = group * 64 + lane;
+  const int lgroup = bid / e.bx, sblock = bid - lgroup * e.bx;
+  const int light0 = lgroup * e.gsize;
+  const int Lg = max(0, min(e.gsize, a.L - light0));
+  const int lc = max(1, cdiv(Lg, 4));
+  const int nch = max(1, cdiv(Lg, lc));
+  const int j0 = light0 + wv * lc, j1 = min(light0 + Lg, j0 + lc);
+  const int k = sblock * 64 + lane;
   if (threadIdx.x == 0) arrived = 0;
   const bool in = k < e.n_samples;
   const double ltot = e.cdf[e.E - 1];
@@ -258,7 +264,7 @@ __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const Ed
   const V3 Lm = side_shade<DUMP, TEX>(a, fxm, fym, hm, k, j0, j1, amb);
   const V3 Lp = side_shade<DUMP, TEX>(a, fxp, fyp, hp, k, j0, j1, amb);
   if (DUMP && in) {
-    if (wv == 0) {
+    if (wv == 0 && lgroup == 0) {
       e.dbg_rec[4 * k] = eid; e.dbg_rec[4 * k + 1] = pid; e.dbg_rec[4 * k + 2] = hm.id; e.dbg_rec[4 * k + 3] = hp.id;
     }
     if (amb) e.dbg_flag[k] = 1;   // OR over the waves: the caller zeroes the flags
@@ -273,7 +279,7 @@ __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const Ed
   if (__builtin_amdgcn_readlane(n_arr, 0) != 3) return;   // another wave finishes this group
   __threadfence_block();
   V3 Sm = {0.0f, 0.0f, 0.0f}, Sp = {0.0f, 0.0f, 0.0f};
-  for (int c = 0; c < e.n_lchunks; ++c) {
+  for (int c = 0; c < nch; ++c) {
     const float* q = side_L[c][lane];
     Sm = Sm + V3{q[0], q[1], q[2]};
     Sp = Sp + V3{q[3], q[4], q[5]};
@@ -341,27 +347,26 @@ void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samp
   e.edges = m.edges; e.cdf = m.edge_cdf; e.E = m.E; e.n_samples = n_samples;
   e.th = tan_half; e.aspect = aspect; e.dEdp = dEdp; e.gverts = gverts; e.gcam = gcam;
   e.dbg_rec = dbg_rec; e.dbg_flag = dbg_flag;
-  const int blocks = (n_samples + 63) / 64;
-  // lights in groups of at most 128 (one launch each): the estimate is linear
-  // in f- - f+, so the groups' scatters add up (exact integer sums)
-  for (int g0 = 0; g0 == 0 || g0 < a.L; g0 += kBwdMaxLights) {
-    RenderArgs ag = a;
-    ag.L = std::min(kBwdMaxLights, a.L - g0);
-    ag.light0 = a.light0 + g0;
-    ag.lights = a.lights + g0;
-    e.lc = std::max(1, cdiv(ag.L, 4));   // the four waves of a block
-    e.n_lchunks = std::max(1, cdiv(ag.L, e.lc));
-    if (ag.M > 0) {
-      if (dbg_rec)
-        hipLaunchKernelGGL((k_edge_samples<true, true>), dim3(blocks), dim3(256), 0, st, ag, e);
-      else
-        hipLaunchKernelGGL((k_edge_samples<false, true>), dim3(blocks), dim3(256), 0, st, ag, e);
-    } else if (dbg_rec) {
-      hipLaunchKernelGGL((k_edge_samples<true, false>), dim3(blocks), dim3(256), 0, st, ag, e);
-    } else {
-      hipLaunchKernelGGL((k_edge_samples<false, false>), dim3(blocks), dim3(256), 0, st, ag, e);
-    }
+  edge_groups(a.L, n_samples, e);
+  const int blocks = e.bx * e.n_groups;
+  if (a.M > 0) {
+    if (dbg_rec)
+      hipLaunchKernelGGL((k_edge_samples<true, true>), dim3(blocks), dim3(256), 0, st, a, e);
+    else
+      hipLaunchKernelGGL((k_edge_samples<false, true>), dim3(blocks), dim3(256), 0, st, a, e);
+  } else if (dbg_rec) {
+    hipLaunchKernelGGL((k_edge_samples<true, false>), dim3(blocks), dim3(256), 0, st, a, e);
+  } else {
+    hipLaunchKernelGGL((k_edge_samples<false, false>), dim3(blocks), dim3(256), 0, st, a, e);
   }
+}
+
+void edge_groups(int L, int n_samples, EdgeArgs& e) {
+  e.bx = std::max(1, cdiv(n_samples, 64));
+  int ng = std::max(1, std::max(cdiv(L, kBwdMaxLights), cdiv(2048, e.bx)));
+  ng = std::min(ng, std::max(1, cdiv(L, 4)));
+  e.gsize = cdiv(L, ng);
+  e.n_groups = L > 0 ? cdiv(L, e.gsize) : 1;
 }
 
 }  // namespace fr

@@ -61,8 +61,16 @@ struct EdgeArgs {
   fix_t* gcam;          // [12] fixed-point
   int32_t* dbg_rec;     // [n*4]: edge, pixel, hit-, hit+
   uint8_t* dbg_flag;    // [n]
-  int lc, n_lchunks;    // lights per work item, light chunks per sample group
+  // The lights are cut into n_groups groups of gsize (the last may be
+  // shorter); block b takes sample block b % bx of group b / bx, its four
+  // waves the group's four light chunks.
+  int gsize, n_groups, bx;
 };
+
+// Light groups of the boundary term for L lights and n edge samples: at most
+// 128 lights a group, and enough groups that the launch holds at least 2048
+// blocks (a whole chip of waves) while every wave keeps a light.
+void edge_groups(int L, int n_samples, EdgeArgs& e);
 
 // Primary hit of one camera sample: the closest-hit triangle (-1: miss), its
 // distance, and the FP64 barycentrics b1, b2 of the crossing (b0 = 1 - b1 -
