@@ -58,6 +58,7 @@ class OrScene(ctypes.Structure):
         ("pad2_", ctypes.c_uint32),
         ("uv", ctypes.c_void_p), ("tex_c", ctypes.c_void_p), ("tex_s", ctypes.c_void_p), ("tex_r", ctypes.c_void_p),
         ("tex_size", ctypes.c_int32), ("pad3_", ctypes.c_int32),
+        ("sh", ctypes.c_void_p), ("sh_bands", ctypes.c_int32), ("pad4_", ctypes.c_int32),
     ]
 
 
@@ -76,7 +77,7 @@ def lib():
         L.oracle_normals_vjp.argtypes = [P, P, P]
         L.oracle_render.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, ctypes.c_int32]
         L.oracle_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int32,
-                                  ctypes.c_int32]
+                                  ctypes.c_int32, P]
         L.oracle_edge_grad.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_int32]
         L.oracle_edge_count.argtypes = [P]
         L.oracle_edge_count.restype = ctypes.c_int32
@@ -87,6 +88,10 @@ def lib():
         L.oracle_occluded.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, P]
         L.oracle_occluded.restype = ctypes.c_int32
         L.oracle_brdf.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, ctypes.c_double, P, P]
+        L.oracle_sh_basis.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
+        L.oracle_sh_basis.restype = ctypes.c_int32
+        L.oracle_sh_cosine_coeff.argtypes = [ctypes.c_int32]
+        L.oracle_sh_cosine_coeff.restype = ctypes.c_double
         L.oracle_g1_of_a.argtypes = [ctypes.c_double]
         L.oracle_g1_of_a.restype = ctypes.c_double
         _lib = L
@@ -127,6 +132,12 @@ class _Bound:
             self.keep += tex
             s.uv, s.tex_c, s.tex_s, s.tex_r = [a.ctypes.data for a in tex]
             s.tex_size = M
+        if getattr(scene, "sh", None) is not None:
+            shc = f32(scene.sh).reshape(-1)
+            B = int(round((shc.size // 3) ** 0.5))
+            assert shc.size == 3 * B * B and 1 <= B <= 11
+            self.keep.append(shc)
+            s.sh, s.sh_bands = shc.ctypes.data, B
         self.s = s
 
     @property
@@ -213,13 +224,16 @@ def grad(scene, hit, vis, dEdp, pixels=None, brdf_variant=0, components=3, nthre
     M = b.s.tex_size
     if M > 0:
         out.update(tex_diffuse=np.zeros((M, M, 3)), tex_specular=np.zeros((M, M, 3)), tex_rough=np.zeros((M, M)))
+    B = b.s.sh_bands
+    if B > 0:
+        out["sh"] = np.zeros((B * B, 3))
     h = np.ascontiguousarray(hit, dtype=np.int32)
     v = np.ascontiguousarray(vis, dtype=np.uint8)
     lib().oracle_grad(b.ref, n, _ptr(pix), _ptr(h), _ptr(v), _ptr(g), _ptr(out["verts"]),
                       _ptr(out["normals"]), _ptr(out["diffuse"]), _ptr(out["specular"]), _ptr(out["rough"]),
                       _ptr(out["light"]), _ptr(out["rad"]), _ptr(out["cam"]), _ptr(out.get("tex_diffuse")),
                       _ptr(out.get("tex_specular")), _ptr(out.get("tex_rough")), nthreads or default_threads(),
-                      int(bool(abs_terms)))
+                      int(bool(abs_terms)), _ptr(out.get("sh")))
     if include_normals_path and not abs_terms:
         out["verts"] = out["verts"] + normals_vjp(scene, out["normals"])
     return out
@@ -301,6 +315,17 @@ def brdf(n, l, o, c, s, r, variant=0, components=3):
 
 def g1_of_a(a: float) -> float:
     return float(lib().oracle_g1_of_a(float(a)))
+
+
+def sh_basis(bands: int, n) -> np.ndarray:
+    """Real SH Y [B*B] (index l(l+1)+m) at the unit vector n."""
+    out = np.zeros(bands * bands)
+    assert lib().oracle_sh_basis(int(bands), float(n[0]), float(n[1]), float(n[2]), _ptr(out)) == 0
+    return out
+
+
+def sh_cosine_coeff(l: int) -> float:
+    return float(lib().oracle_sh_cosine_coeff(int(l)))
 
 
 # ---------------------------------------------------------------------------

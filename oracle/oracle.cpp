@@ -67,6 +67,11 @@ struct OrScene {
   const float* tex_r;      // [M*M] roughness
   int32_t tex_size;        // M (0: per-vertex reflectance)
   int32_t pad3_;
+  // spherical-harmonics lighting (sh_bands B > 0): coefficients L_lm of the
+  // distant radiance, [B*B][3] (index l(l+1)+m, RGB inner)
+  const float* sh;
+  int32_t sh_bands;
+  int32_t pad4_;
 };
 
 }  // extern "C"
@@ -528,6 +533,89 @@ Vec3<S> light_contribution(const Frame<S>& f, const LightParams<S>& L, double w1
 }
 
 // ---------------------------------------------------------------------------
+// Spherical-harmonics lighting (Sec. 6, "Spherical Harmonics (SH) vs. Light
+// Stage": distant light as a B-band SH expansion, no visibility).  Reading:
+// the SH light reaches the diffuse term only, as the irradiance
+// E(n) = sum_l A_l sum_m L_lm Y_lm(n), with A_l the coefficients of the
+// clamped cosine max(0, n . w) (Ramamoorthi and Hanrahan 2001); a sample
+// receives (c / pi) E(n_s).
+// ---------------------------------------------------------------------------
+constexpr int kMaxShBands = 11;
+
+// Normalisation of the real SH: sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!).
+double sh_norm(int l, int m) {
+  double r = 1.0;
+  for (int k = l - m + 1; k <= l + m; ++k) r /= k;
+  return std::sqrt((2.0 * l + 1.0) / (4.0 * kPi) * r);
+}
+
+// A_l: pi, 2 pi / 3, 0 for odd l > 1, and for even l
+// 2 pi (-1)^(l/2 - 1) / ((l + 2)(l - 1)) * l! / (2^l ((l/2)!)^2).
+double sh_cosine_coeff(int l) {
+  if (l == 0) return kPi;
+  if (l == 1) return 2.0 * kPi / 3.0;
+  if (l % 2) return 0.0;
+  double c = 1.0;                      // l! / (2^l ((l/2)!)^2) = C(l, l/2) / 2^l
+  for (int k = 1; k <= l / 2; ++k) c *= (double)(l / 2 + k) / (double)k;
+  c /= std::ldexp(1.0, l);
+  const double sg = ((l / 2 - 1) % 2) ? -1.0 : 1.0;
+  return 2.0 * kPi * sg / ((l + 2.0) * (l - 1.0)) * c;
+}
+
+// Real SH up to band B-1 at the unit vector n (z the polar axis), Y[l(l+1)+m]:
+// Y_l0 = K_l0 P_l(z); Y_l,+m = sqrt2 K_lm Pbar_lm(z) Re (x + i y)^m;
+// Y_l,-m = sqrt2 K_lm Pbar_lm(z) Im (x + i y)^m, where Pbar_lm is the
+// associated Legendre function (Condon-Shortley phase) divided by
+// (1 - z^2)^(m/2), from its three-term recurrence in l.
+template <class S>
+void sh_basis(int B, const Vec3<S>& n, S* Y) {
+  S cr[kMaxShBands], ci[kMaxShBands];
+  cr[0] = S(1.0); ci[0] = S(0.0);
+  for (int m = 1; m < B; ++m) {
+    cr[m] = n.x * cr[m - 1] - n.y * ci[m - 1];
+    ci[m] = n.x * ci[m - 1] + n.y * cr[m - 1];
+  }
+  for (int m = 0; m < B; ++m) {
+    double pmm = 1.0;                  // (-1)^m (2m - 1)!!
+    for (int k = 1; k <= m; ++k) pmm *= -(2.0 * k - 1.0);
+    auto put = [&](int l, const S& p) {
+      if (m == 0) { Y[l * (l + 1)] = p * sh_norm(l, 0); return; }
+      const double k = std::sqrt(2.0) * sh_norm(l, m);
+      Y[l * (l + 1) + m] = p * cr[m] * k;
+      Y[l * (l + 1) - m] = p * ci[m] * k;
+    };
+    S pa = S(pmm);
+    put(m, pa);
+    if (m + 1 >= B) continue;
+    S pb = n.z * ((2.0 * m + 1.0) * pmm);
+    put(m + 1, pb);
+    for (int l = m + 2; l < B; ++l) {
+      const S pc = (n.z * pb * (2.0 * l - 1.0) - pa * (double)(l + m - 1)) / (double)(l - m);
+      put(l, pc);
+      pa = pb; pb = pc;
+    }
+  }
+}
+
+// The SH light's contribution to a sample: (c / pi) E(n_s), diffuse only.
+template <class S>
+Vec3<S> sh_contribution(const Frame<S>& f, const float* sh, int B, int components) {
+  if (B <= 0 || !(components & 1)) return Vec3<S>(S(0.0), S(0.0), S(0.0));
+  S Y[kMaxShBands * kMaxShBands];
+  sh_basis(B, f.ns, Y);
+  S e[3] = {S(0.0), S(0.0), S(0.0)};
+  for (int l = 0; l < B; ++l) {
+    const double a = sh_cosine_coeff(l);
+    if (a == 0.0) continue;
+    for (int m = -l; m <= l; ++m) {
+      const int i = l * (l + 1) + m;
+      for (int ch = 0; ch < 3; ++ch) e[ch] = e[ch] + Y[i] * (a * (double)sh[3 * i + ch]);
+    }
+  }
+  return Vec3<S>(f.c.x * e[0] * (1.0 / kPi), f.c.y * e[1] * (1.0 / kPi), f.c.z * e[2] * (1.0 / kPi));
+}
+
+// ---------------------------------------------------------------------------
 // Scene access helpers.
 // ---------------------------------------------------------------------------
 struct Prepared {
@@ -723,6 +811,10 @@ int oracle_render(const OrScene* sc, int32_t n_pix, const int32_t* pix, const in
         if (vis_row) vis_row[j] = vis;
         if (sf_row) sf_row[j] = sflag;
       }
+      if (cos_o > 0.0) {
+        const Vec3<double> c = sh_contribution(fr, sc->sh, sc->sh_bands, sc->components);
+        acc[0] += c.x; acc[1] += c.y; acc[2] += c.z;
+      }
     }
     if (out_rgb) for (int k = 0; k < 3; ++k) out_rgb[3 * ip + k] = acc[k] / S;
   });
@@ -737,22 +829,25 @@ int oracle_render(const OrScene* sc, int32_t n_pix, const int32_t* pix, const in
 //   g_cam [12] (R row-major, then T).
 // abs_terms != 0 accumulates the magnitude of every (sample, light) term
 // instead of the term: the condition measure of each sum (test tolerance
-// only; not a gradient).
+// only; not a gradient).  g_sh [B*B*3] (nullable): the SH coefficients'
+// gradient (the SH term is linear in them: (g . c / pi) A_l Y_lm(n_s)).
 int oracle_grad(const OrScene* sc, int32_t n_pix, const int32_t* pix, const int32_t* hit, const uint8_t* vis,
                 const double* dEdp, double* g_verts, double* g_normals, double* g_diffuse, double* g_specular,
                 double* g_rough, double* g_light, double* g_rad, double* g_cam, double* g_tex_c, double* g_tex_s,
-                double* g_tex_r, int32_t nthreads, int32_t abs_terms) {
+                double* g_tex_r, int32_t nthreads, int32_t abs_terms, double* g_sh) {
   const Prepared P = prepare(sc);
   const int S = sc->spp, L = sc->n_lights, W = sc->width, N = sc->n_verts;
   if (!pix) n_pix = sc->width * sc->height;
   nthreads = std::max(1, std::min<int>(nthreads, n_pix));
   const int M = sc->tex_size, MM = M > 0 ? M * M : 0;
-  struct Acc { std::vector<double> v, n, c, s, r, l, rad, cam, tc, ts, tr; };
+  const int B = sc->sh_bands;
+  struct Acc { std::vector<double> v, n, c, s, r, l, rad, cam, tc, ts, tr, sh; };
   std::vector<Acc> accs(nthreads);
   for (auto& a : accs) {
     a.v.assign(3 * N, 0); a.n.assign(3 * N, 0); a.c.assign(3 * N, 0); a.s.assign(3 * N, 0);
     a.r.assign(N, 0); a.l.assign(9 * L, 0); a.rad.assign(3 * L, 0); a.cam.assign(12, 0);
     a.tc.assign(3 * (size_t)MM, 0); a.ts.assign(3 * (size_t)MM, 0); a.tr.assign(MM, 0);
+    a.sh.assign(3 * (size_t)B * B, 0);
   }
   parallel_for(n_pix, nthreads, [&](int ip, int tid) {
     Acc& A = accs[tid];
@@ -797,16 +892,9 @@ int oracle_grad(const OrScene* sc, int32_t n_pix, const int32_t* pix, const int3
       const Frame<D63> fr = shading_frame(sp, P.cc, fx, fy);
       int vid[3];
       for (int k = 0; k < 3; ++k) vid[k] = sc->tris[3 * tri + k];
-      for (int j = 0; j < L; ++j) {
-        const uint8_t vs = vis[rs * L + j];
-        if (vs != VIS_VISIBLE) continue;
-        const Rand4 rl = philox4x32_10((uint32_t)pid, (uint32_t)s, 1u + (uint32_t)j, sc->step, sc->seed);
-        double w1, w2;
-        light_weights(sc->light_shape[j], unit24(rl.x[0]), unit24(rl.x[1]), &w1, &w2);
-        const LightParams<double> ld = light_params_d(*sc, j);
-        LightParams<D63> lp{seed3(ld.p0, SLOT_LP0), seed3(ld.e1, SLOT_LE1), seed3(ld.e2, SLOT_LE2),
-                            seed3(ld.rad, SLOT_LRAD), ld.shape};
-        const Vec3<D63> c = light_contribution(fr, lp, w1, w2, vs, sc->brdf_variant, sc->components, nullptr);
+      // one term (a light's or the SH light's contribution) into the sums;
+      // j < 0: no light slots
+      auto scatter = [&](const Vec3<D63>& c, int j) {
         double gs[NSLOT];
         for (int k = 0; k < NSLOT; ++k) gs[k] = g[0] * c.x.d[k] + g[1] * c.y.d[k] + g[2] * c.z.d[k];
         if (abs_terms)
@@ -833,9 +921,38 @@ int oracle_grad(const OrScene* sc, int32_t n_pix, const int32_t* pix, const int3
             }
           for (int k = 0; k < 3; ++k) A.r[vid[k]] += gs[SLOT_R + k];
         }
-        for (int a = 0; a < 9; ++a) A.l[9 * j + a] += gs[SLOT_LP0 + a];
-        for (int a = 0; a < 3; ++a) A.rad[3 * j + a] += gs[SLOT_LRAD + a];
+        if (j >= 0) {
+          for (int a = 0; a < 9; ++a) A.l[9 * j + a] += gs[SLOT_LP0 + a];
+          for (int a = 0; a < 3; ++a) A.rad[3 * j + a] += gs[SLOT_LRAD + a];
+        }
         for (int a = 0; a < 12; ++a) A.cam[a] += gs[SLOT_CR + a];
+      };
+      for (int j = 0; j < L; ++j) {
+        const uint8_t vs = vis[rs * L + j];
+        if (vs != VIS_VISIBLE) continue;
+        const Rand4 rl = philox4x32_10((uint32_t)pid, (uint32_t)s, 1u + (uint32_t)j, sc->step, sc->seed);
+        double w1, w2;
+        light_weights(sc->light_shape[j], unit24(rl.x[0]), unit24(rl.x[1]), &w1, &w2);
+        const LightParams<double> ld = light_params_d(*sc, j);
+        LightParams<D63> lp{seed3(ld.p0, SLOT_LP0), seed3(ld.e1, SLOT_LE1), seed3(ld.e2, SLOT_LE2),
+                            seed3(ld.rad, SLOT_LRAD), ld.shape};
+        scatter(light_contribution(fr, lp, w1, w2, vs, sc->brdf_variant, sc->components, nullptr), j);
+      }
+      if (B > 0 && (sc->components & 1) && val(dot(fr.ns, fr.wo)) > 0.0) {
+        scatter(sh_contribution(fr, sc->sh, B, sc->components), -1);
+        // the coefficients: (g . c / pi) A_l Y_lm(n_s), in values
+        Vec3<double> ns(val(fr.ns.x), val(fr.ns.y), val(fr.ns.z));
+        double Y[kMaxShBands * kMaxShBands];
+        sh_basis(B, ns, Y);
+        const double w[3] = {g[0] * val(fr.c.x) / kPi, g[1] * val(fr.c.y) / kPi, g[2] * val(fr.c.z) / kPi};
+        for (int l = 0; l < B; ++l)
+          for (int m = -l; m <= l; ++m) {
+            const int i = l * (l + 1) + m;
+            for (int ch = 0; ch < 3; ++ch) {
+              const double t = w[ch] * sh_cosine_coeff(l) * Y[i];
+              A.sh[3 * i + ch] += abs_terms ? std::fabs(t) : t;
+            }
+          }
       }
     }
   });
@@ -843,7 +960,7 @@ int oracle_grad(const OrScene* sc, int32_t n_pix, const int32_t* pix, const int3
   for (const Acc& a : accs) {
     add(g_verts, a.v); add(g_normals, a.n); add(g_diffuse, a.c); add(g_specular, a.s);
     add(g_rough, a.r); add(g_light, a.l); add(g_rad, a.rad); add(g_cam, a.cam);
-    add(g_tex_c, a.tc); add(g_tex_s, a.ts); add(g_tex_r, a.tr);
+    add(g_tex_c, a.tc); add(g_tex_s, a.ts); add(g_tex_r, a.tr); add(g_sh, a.sh);
   }
   return 0;
 }
@@ -985,6 +1102,8 @@ int oracle_edge_grad(const OrScene* sc, int32_t n_samples, int32_t n_sel, const 
                                                     s.components, &flag);
           fpm[side][0] += c.x; fpm[side][1] += c.y; fpm[side][2] += c.z;
         }
+        const Vec3<double> c = sh_contribution(fr, s.sh, s.sh_bands, s.components);
+        fpm[side][0] += c.x; fpm[side][1] += c.y; fpm[side][2] += c.z;
       }
     }
     if (edge_out) { edge_out[4 * is] = e; edge_out[4 * is + 1] = pid; edge_out[4 * is + 2] = hits[0]; edge_out[4 * is + 3] = hits[1]; }
@@ -1097,5 +1216,15 @@ double oracle_g1_of_a(double a) {
   if (a < 1.6) return (3.535 * a + 2.181 * a * a) / (1.0 + 2.276 * a + 2.577 * a * a);
   return 1.0;
 }
+
+// The real SH basis Y [B*B] at the unit vector (x, y, z), and A_l, for the
+// pins of the SH lighting.
+int oracle_sh_basis(int32_t B, double x, double y, double z, double* Y) {
+  if (B < 1 || B > kMaxShBands) return -1;
+  sh_basis(B, Vec3<double>(x, y, z), Y);
+  return 0;
+}
+
+double oracle_sh_cosine_coeff(int32_t l) { return sh_cosine_coeff(l); }
 
 }  // extern "C"

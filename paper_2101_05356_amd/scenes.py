@@ -71,6 +71,13 @@ class Scene:
     tex_diffuse: np.ndarray | None = None   # [M,M,3]
     tex_specular: np.ndarray | None = None  # [M,M,3]
     tex_roughness: np.ndarray | None = None # [M,M]
+    # spherical-harmonics lighting: coefficients of the distant radiance,
+    # [B*B, 3] (index l(l+1)+m, RGB), on top of the lights
+    sh: np.ndarray | None = None
+
+    @property
+    def sh_bands(self) -> int:
+        return 0 if self.sh is None else int(round(math.sqrt(self.sh.shape[0])))
 
     @property
     def tex_size(self) -> int:
@@ -149,8 +156,11 @@ def _square_facing_origin(centre: np.ndarray, side: float):
 
 
 def square_lights(centres: np.ndarray, side: float, rad: np.ndarray) -> Lights:
-    p0, e1, e2 = zip(*(_square_facing_origin(c, side) for c in centres))
     L = len(centres)
+    if L == 0:
+        z = np.zeros((0, 3))
+        return Lights(p0=_f32(z), e1=_f32(z), e2=_f32(z), rad=_f32(z), shape=_i32(np.zeros(0)))
+    p0, e1, e2 = zip(*(_square_facing_origin(c, side) for c in centres))
     return Lights(p0=_f32(p0), e1=_f32(e1), e2=_f32(e2), rad=_f32(rad),
                   shape=_i32(np.full(L, LIGHT_PARALLELOGRAM)))
 
@@ -418,6 +428,18 @@ def environment_lights(res: int = 32, seed: int = 13, lo: float = 0.0, hi: float
     L = res * res
     return Lights(p0=_f32(d), e1=_f32(np.zeros((L, 3))), e2=_f32(np.zeros((L, 3))),
                   rad=_f32(inten.reshape(-1, 3) * omega), shape=_i32(np.full(L, LIGHT_DIRECTIONAL)))
+
+
+def sh_lighting(bands: int, seed: int = 17, scale: float = 0.6, decay: float = 0.6) -> np.ndarray:
+    """SH coefficients [B*B, 3] of a distant light (the SH lighting of the
+    paper's ablation, Sec. 6, with 3 or 7 bands there): a positive constant
+    band 0 and seeded band-l coefficients shrinking as decay^l."""
+    rng = np.random.default_rng(seed)
+    c = np.zeros((bands * bands, 3))
+    c[0] = scale * (1.0 + 0.3 * rng.uniform(-1, 1, 3))
+    for l in range(1, bands):
+        c[l * l:(l + 1) * (l + 1)] = scale * decay ** l * rng.uniform(-1, 1, (2 * l + 1, 3))
+    return _f32(c)
 
 
 def face_camera(W: int = 256, H: int = 256) -> Camera:
