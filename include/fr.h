@@ -138,6 +138,17 @@ typedef struct {
   const float* tex_diffuse;   /* [M*M*3] texel (i, j) at offset 3 (j M + i) */
   const float* tex_specular;  /* [M*M*3] */
   const float* tex_roughness; /* [M*M] */
+  /* Spherical-harmonics lighting (Sec. 6, "Spherical Harmonics (SH) vs.
+   * Light Stage"): a distant light given by the real SH coefficients L_lm
+   * of its radiance, bands l < sh_bands (0 = none, at most 11), z the polar
+   * axis, sh [B*B*3] at index l(l+1)+m with RGB inner (device).  It adds,
+   * on top of the lights and without visibility, (c / pi) E(n_s) to every
+   * shaded sample, E(n) = sum_l A_l sum_m L_lm Y_lm(n) the irradiance of the
+   * clamped cosine (A_0 = pi, A_1 = 2 pi / 3, A_2 = pi / 4, ...), on the
+   * diffuse term only. */
+  const float* sh;
+  int32_t sh_bands;
+  int32_t sh_pad_;
 } fr_scene;
 
 typedef struct {
@@ -209,6 +220,7 @@ typedef struct {
   float* tex_diffuse;   /* [M*M*3] */
   float* tex_specular;  /* [M*M*3] */
   float* tex_roughness; /* [M*M] */
+  float* sh;            /* [B*B*3] SH coefficients (fr_scene.sh_bands > 0) */
 } fr_grads;
 
 /* Forward render (Sec. 4 Eq. energy: p^S = F(chi), the Monte-Carlo estimate

@@ -27,7 +27,8 @@ class FrScene(ctypes.Structure):
                 ("light_p0", P), ("light_e1", P), ("light_e2", P), ("light_rad", P), ("light_shape", P),
                 ("cam", P), ("fov_y", ctypes.c_float), ("step", ctypes.c_uint32), ("seed", ctypes.c_uint64),
                 ("tex_size", ctypes.c_int32), ("tex_pad_", ctypes.c_int32), ("tex_uv", P), ("tex_diffuse", P),
-                ("tex_specular", P), ("tex_roughness", P)]
+                ("tex_specular", P), ("tex_roughness", P), ("sh", P), ("sh_bands", ctypes.c_int32),
+                ("sh_pad_", ctypes.c_int32)]
 
 
 class FrRenderOpts(ctypes.Structure):
@@ -41,7 +42,7 @@ class FrRenderOpts(ctypes.Structure):
 class FrGrads(ctypes.Structure):
     _fields_ = [("verts", P), ("normals", P), ("diffuse", P), ("specular", P), ("roughness", P),
                 ("light_geom", P), ("light_rad", P), ("cam", P), ("tex_diffuse", P), ("tex_specular", P),
-                ("tex_roughness", P)]
+                ("tex_roughness", P), ("sh", P)]
 
 
 class FrJobDesc(ctypes.Structure):

@@ -81,6 +81,31 @@ hipError_t dalloc(T** p, size_t n) {
 
 bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
+// Constants of the SH lighting: A_l, the clamped cosine's SH coefficients
+// (pi, 2 pi / 3, then 0 for odd l and 2 pi (-1)^(l/2+1) C(l, l/2) /
+// (2^l (l + 2)(l - 1)) for even l), and the real-SH normalisation
+// sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!), times sqrt 2 for m > 0.
+void sh_tables(fr::RenderArgs& a) {
+  const double pi = 3.14159265358979323846;
+  for (int l = 0; l < fr::kMaxShBands; ++l) {
+    double A;
+    if (l == 0) A = pi;
+    else if (l == 1) A = 2.0 * pi / 3.0;
+    else if (l & 1) A = 0.0;
+    else {
+      double binom = 1.0;                      // C(l, l/2)
+      for (int k = 1; k <= l / 2; ++k) binom = binom * (l / 2 + k) / k;
+      A = 2.0 * pi * ((l / 2) % 2 ? 1.0 : -1.0) * binom / (std::pow(2.0, l) * (l + 2.0) * (l - 1.0));
+    }
+    a.sh_ash[l] = (float)A;
+    for (int m = 0; m <= l; ++m) {
+      double r = 1.0;                          // (l-m)! / (l+m)!
+      for (int k = l - m + 1; k <= l + m; ++k) r /= k;
+      a.sh_norm[l * (l + 1) / 2 + m] = (float)(std::sqrt((2.0 * l + 1.0) / (4.0 * pi) * r) * (m > 0 ? std::sqrt(2.0) : 1.0));
+    }
+  }
+}
+
 int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::RenderArgs& a, int default_chunk) {
   fr_ctx* ctx = m->ctx;
   if (!s || !o) return fail(ctx, FR_ERR_INVALID_ARG, "scene and opts are required");
@@ -126,6 +151,11 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
   a.prim = nullptr;   // set by the caller (ensure_prim, or a job's own buffer)
   a.vis_out = nullptr; a.vis_in = nullptr; a.vis_lc = 0;
   a.light0 = 0;
+  if (s->sh_bands < 0 || s->sh_bands > fr::kMaxShBands || (s->sh_bands > 0 && !s->sh))
+    return fail(ctx, FR_ERR_INVALID_ARG, "sh_bands must be in [0, 11] with sh given");
+  a.sh = s->sh_bands > 0 ? s->sh : nullptr;
+  a.sh_bands = s->sh_bands;
+  sh_tables(a);
   a.tiles_x = (a.W + a.tile_w - 1) / a.tile_w;
   a.tiles_y = (a.H + a.tile_h - 1) / a.tile_h;
   a.n_tiles = a.tiles_x * a.tiles_y;
@@ -461,7 +491,8 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
   a.lights = m->d.lights;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   fr::MeshDev& d = m->d;
-  const size_t need = (size_t)fr::kSlots * (12 * (size_t)std::min(s->n_lights, fr::kBwdMaxLights) + 12);
+  const size_t need = (size_t)fr::kSlots *
+                      (12 * (size_t)std::min(s->n_lights, fr::kBwdMaxLights) + 12 + 3 * (size_t)a.sh_bands * a.sh_bands);
   if (need > d.slots_cap) {
     if (d.slots) (void)hipFree(d.slots);
     d.slots = nullptr;

@@ -69,7 +69,7 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
   // LDS: [L*12 + 12] fixed-point sums (per light p0 e1 e2 rad, then camera),
   // then the per-lane sample adjoints of the block's four waves [4][64][16]
   extern __shared__ fix_t lds[];
-  const int nl = a.L * 12 + 12;
+  const int nl = a.L * 12 + 12 + 3 * a.sh_bands * a.sh_bands;
   float* part = reinterpret_cast<float*>(lds + nl);
   int* arrived = reinterpret_cast<int*>(part + 4 * 64 * 16);
   for (int i = threadIdx.x; i < nl; i += 256) lds[i] = 0;
@@ -215,6 +215,34 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
         for (int k = 0; k < 12; ++k) {
           const float t = wave_sum(gl12[k]);
           if (lane == 0 && t != 0.0f) atomicAdd(&lds[12 * j + k], to_fix(t));
+        }
+      }
+      // The SH light (first light chunk of the first light group only):
+      // dE/dc = gbar E / pi, dE/dn_s = sum_ch (gbar c / pi)_ch grad E_ch, and
+      // the coefficients' gradient (gbar c / pi) A_l Y_lm into the LDS sums.
+      if (a.sh_bands > 0 && wv == 0 && (a.components & 1)) {
+        const V3 n = shaded ? fr.ns : V3{0.0f, 0.0f, 1.0f};
+        const float w0 = shaded ? gbar[0] * fr.c.x * (1.0f / kPi) : 0.0f;
+        const float w1 = shaded ? gbar[1] * fr.c.y * (1.0f / kPi) : 0.0f;
+        const float w2 = shaded ? gbar[2] * fr.c.z * (1.0f / kPi) : 0.0f;
+        V3 e = {0.0f, 0.0f, 0.0f}, gn = {0.0f, 0.0f, 0.0f};
+        fix_t* lsh = lds + 12 * a.L + 12;
+        sh_stream(a, n, [&](int i, int l, G4 y) {
+          const float A = a.sh_ash[l];
+          const float c0 = a.sh[3 * i], c1 = a.sh[3 * i + 1], c2 = a.sh[3 * i + 2];
+          e.x += A * y.v * c0; e.y += A * y.v * c1; e.z += A * y.v * c2;
+          const float q = A * (w0 * c0 + w1 * c1 + w2 * c2);
+          gn = gn + V3{y.dx, y.dy, y.dz} * q;
+          const float t0 = wave_sum(w0 * A * y.v), t1 = wave_sum(w1 * A * y.v), t2 = wave_sum(w2 * A * y.v);
+          if (lane == 0) {
+            if (t0 != 0.0f) atomicAdd(&lsh[3 * i], to_fix(t0));
+            if (t1 != 0.0f) atomicAdd(&lsh[3 * i + 1], to_fix(t1));
+            if (t2 != 0.0f) atomicAdd(&lsh[3 * i + 2], to_fix(t2));
+          }
+        });
+        if (shaded) {
+          gc = gc + V3{gbar[0] * e.x, gbar[1] * e.y, gbar[2] * e.z} * (1.0f / kPi);
+          gns = gns + gn;
         }
       }
       // The chunks' sample adjoints meet in LDS; one wave sums them in chunk
@@ -437,9 +465,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 // Sum the slots (exact integer sums) into the caller's light and camera gradients.
+// Values 12L .. 12L + 11 are the camera's, the rest (3 B^2) the SH
+// coefficients'.
 __device__ __forceinline__ void slots_reduce_block(const fix_t* __restrict__ slots, int nl, int L,
                                                    float* __restrict__ glight, float* __restrict__ grad,
-                                                   float* __restrict__ gcam, int bid) {
+                                                   float* __restrict__ gcam, float* __restrict__ gsh, int bid) {
   const int i = bid;   // one block per value
   __shared__ fix_t red[256];
   fix_t acc = 0;
@@ -456,15 +486,17 @@ __device__ __forceinline__ void slots_reduce_block(const fix_t* __restrict__ slo
     const int j = i / 12, k = i % 12;
     if (k < 9) { if (glight) glight[9 * j + k] += v; }
     else if (grad) grad[3 * j + (k - 9)] += v;
-  } else if (gcam) {
-    gcam[i - 12 * L] += v;
+  } else if (i < 12 * L + 12) {
+    if (gcam) gcam[i - 12 * L] += v;
+  } else if (gsh) {
+    gsh[i - 12 * L - 12] += v;
   }
 }
 
 __global__ __launch_bounds__(256) void k_slots_reduce(const fix_t* __restrict__ slots, int nl, int L,
                                                       float* __restrict__ glight, float* __restrict__ grad,
-                                                      float* __restrict__ gcam) {
-  slots_reduce_block(slots, nl, L, glight, grad, gcam, blockIdx.x);
+                                                      float* __restrict__ gcam, float* __restrict__ gsh) {
+  slots_reduce_block(slots, nl, L, glight, grad, gcam, gsh, blockIdx.x);
 }
 
 // `slots` holds kSlots * (12 min(L, 128) + 12) accumulators (the caller sizes
@@ -485,7 +517,8 @@ void launch_render_backward(const RenderArgs& a, const float* dEdp, const FixGra
     ag.lights = a.lights + g0;
     ag.lc = std::max(user_lc, std::max(1, cdiv(ag.L, 4)));
     ag.n_lchunks = std::max(1, cdiv(ag.L, ag.lc));
-    const int nl = ag.L * 12 + 12;
+    if (g0 > 0) ag.sh_bands = 0;   // the SH light goes with the first group
+    const int nl = ag.L * 12 + 12 + 3 * ag.sh_bands * ag.sh_bands;
     launch_zero_fix(slots, (size_t)kSlots * nl, st);
     const size_t lds = nl * sizeof(fix_t) + kBwdPartBytes;
     if (ag.vis_in) {
@@ -502,7 +535,7 @@ void launch_render_backward(const RenderArgs& a, const float* dEdp, const FixGra
     if (e1 && g0 + kBwdMaxLights >= a.L) (void)hipEventRecord(e1, st);
     hipLaunchKernelGGL(k_slots_reduce, dim3(nl), dim3(256), 0, st, slots, nl, ag.L,
                        g.light_geom ? g.light_geom + (size_t)9 * g0 : nullptr,
-                       g.light_rad ? g.light_rad + (size_t)3 * g0 : nullptr, g.cam);
+                       g.light_rad ? g.light_rad + (size_t)3 * g0 : nullptr, g.cam, ag.sh_bands > 0 ? g.sh : nullptr);
   }
 }
 

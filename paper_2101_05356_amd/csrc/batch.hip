@@ -102,7 +102,8 @@ FR_BATCH_KERNEL(kb_fix_finalize, 256) {
   J.g_diffuse[i] = (float)from_fix(J.acc[6 * J.N + i]);
 }
 FR_BATCH_KERNEL(kb_slots_reduce, 256) {
-  FR_JOB_PROLOGUE slots_reduce_block(J.lslots, 12 * J.ra.L + 12, J.ra.L, nullptr, J.grad + J.off_rad, nullptr, lb);
+  FR_JOB_PROLOGUE slots_reduce_block(J.lslots, 12 * J.ra.L + 12, J.ra.L, nullptr, J.grad + J.off_rad, nullptr, nullptr,
+                                     lb);
 }
 FR_BATCH_KERNEL(kb_normals_bwd_project, 256) {
   FR_JOB_PROLOGUE normals_bwd_project_block(J.v_w, J.tris, J.vf_off, J.vf_idx, J.N, J.acc + 3 * J.N, J.gnorm, lb);

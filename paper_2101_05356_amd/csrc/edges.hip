@@ -169,7 +169,7 @@ __device__ __forceinline__ PrimHit side_trace(const RenderArgs& a, float fx, flo
 // lights [j0, j1).
 template <bool DUMP, bool TEX>
 __device__ __forceinline__ V3 side_shade(const RenderArgs& a, float fx, float fy, const PrimHit& ph, int k, int j0,
-                                         int j1, bool& amb) {
+                                         int j1, bool with_sh, bool& amb) {
   Sample sm;
   camera_ray_film(a, fx, fy, sm);
   const double bd[3] = {1.0 - ph.b1 - ph.b2, ph.b1, ph.b2};
@@ -200,6 +200,10 @@ __device__ __forceinline__ V3 side_shade(const RenderArgs& a, float fx, float fy
       L.y += Lj.rad[1] * f[1] * ls.geom;
       L.z += Lj.rad[2] * f[2] * ls.geom;
     }
+  }
+  if (with_sh && a.sh_bands > 0 && (a.components & 1)) {
+    const V3 e = sh_irradiance(a, shaded ? fr.ns : V3{0.0f, 0.0f, 1.0f});
+    if (shaded) L = L + V3{fr.c.x * e.x, fr.c.y * e.y, fr.c.z * e.z} * (1.0f / kPi);
   }
   return L;
 }
@@ -261,8 +265,9 @@ __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const Ed
   if (wv < 2) side_hit[wv][lane] = side_trace<DUMP>(a, wv ? fxp : fxm, wv ? fyp : fym, active, amb);
   __syncthreads();
   const PrimHit hm = side_hit[0][lane], hp = side_hit[1][lane];
-  const V3 Lm = side_shade<DUMP, TEX>(a, fxm, fym, hm, k, j0, j1, amb);
-  const V3 Lp = side_shade<DUMP, TEX>(a, fxp, fyp, hp, k, j0, j1, amb);
+  const bool with_sh = wv == 0 && lgroup == 0;   // the SH light once per sample
+  const V3 Lm = side_shade<DUMP, TEX>(a, fxm, fym, hm, k, j0, j1, with_sh, amb);
+  const V3 Lp = side_shade<DUMP, TEX>(a, fxp, fyp, hp, k, j0, j1, with_sh, amb);
   if (DUMP && in) {
     if (wv == 0 && lgroup == 0) {
       e.dbg_rec[4 * k] = eid; e.dbg_rec[4 * k + 1] = pid; e.dbg_rec[4 * k + 2] = hm.id; e.dbg_rec[4 * k + 3] = hp.id;

@@ -142,6 +142,8 @@ struct MeshDev {
 };
 
 // Per-render constants shared by the forward, backward and edge kernels.
+constexpr int kMaxShBands = 11;   // spherical-harmonics lighting: bands 0..10
+
 struct RenderArgs {
   const Bvh4Node* nodes;
   const TriRec* recs;
@@ -165,6 +167,13 @@ struct RenderArgs {
   int lanes_per_pixel;    // min(S, 64)
   int lc, n_lchunks;      // lights per work item, light chunks per tile
   int light0;             // global index of lights[0] (> 0 in the adjoint's later light groups)
+  // spherical-harmonics lighting: coefficients [B*B*3] (B = sh_bands, 0 =
+  // none), A_l, and the basis normalisation per (l, m >= 0) at
+  // l(l+1)/2 + m (sqrt 2 folded in for m > 0)
+  const float* sh;
+  int sh_bands;
+  float sh_ash[kMaxShBands];
+  float sh_norm[kMaxShBands * (kMaxShBands + 1) / 2];
   float* partial;         // [n_lchunks][H*W*3] per-chunk pixel sums (n_lchunks > 1)
   PrimHit* prim;          // [H*W*S] primary hits, sample index (y*W + x)*S + s
   // Shadow masks, word (c, sample) at c*W*H*S + sample: bit b is light

@@ -420,4 +420,71 @@ __device__ __forceinline__ void brdf_eval(int variant, int components, const Fra
   }
 }
 
+// ---------------------------------------------------------------------------
+// Spherical-harmonics lighting (Sec. 6, "Spherical Harmonics (SH) vs. Light
+// Stage"): a distant light as real SH coefficients L_lm, no visibility, on
+// the diffuse term: (c / pi) E(n_s), E(n) = sum_l A_l sum_m L_lm Y_lm(n).
+// ---------------------------------------------------------------------------
+// A value with its gradient in (x, y, z).
+struct G4 { float v, dx, dy, dz; };
+__device__ __forceinline__ G4 operator+(G4 a, G4 b) { return {a.v + b.v, a.dx + b.dx, a.dy + b.dy, a.dz + b.dz}; }
+__device__ __forceinline__ G4 operator-(G4 a, G4 b) { return {a.v - b.v, a.dx - b.dx, a.dy - b.dy, a.dz - b.dz}; }
+__device__ __forceinline__ G4 operator*(G4 a, float s) { return {a.v * s, a.dx * s, a.dy * s, a.dz * s}; }
+__device__ __forceinline__ G4 operator*(G4 a, G4 b) {
+  return {a.v * b.v, a.dx * b.v + a.v * b.dx, a.dy * b.v + a.v * b.dy, a.dz * b.v + a.v * b.dz};
+}
+
+// Calls f(i, l, Y) for every real SH Y_lm of band l < B at the unit vector
+// n (z the polar axis), i = l(l+1) + m, Y with its gradient in n (as a
+// polynomial in x, y, z).  Y_l0 = K_l0 Pbar_l0(z); Y_l,+m / Y_l,-m =
+// sqrt2 K_lm Pbar_lm(z) times Re / Im (x + i y)^m, with Pbar_lm the
+// associated Legendre function (Condon-Shortley phase) over
+// (1 - z^2)^(m/2): Pbar_mm = (-1)^m (2m-1)!!, Pbar_(m+1)m = (2m+1) z Pbar_mm,
+// then (l - m) Pbar_lm = (2l-1) z Pbar_(l-1)m - (l+m-1) Pbar_(l-2)m.
+template <class F>
+__device__ __forceinline__ void sh_stream(const RenderArgs& a, V3 n, F f) {
+  const G4 X = {n.x, 1.0f, 0.0f, 0.0f}, Y = {n.y, 0.0f, 1.0f, 0.0f}, Z = {n.z, 0.0f, 0.0f, 1.0f};
+  G4 cr = {1.0f, 0.0f, 0.0f, 0.0f}, ci = {0.0f, 0.0f, 0.0f, 0.0f};
+  float pmm = 1.0f;
+  for (int m = 0; m < a.sh_bands; ++m) {
+    if (m > 0) {
+      const G4 t = X * cr - Y * ci;
+      ci = X * ci + Y * cr;
+      cr = t;
+      pmm *= -(2.0f * (float)m - 1.0f);
+    }
+    G4 pa = {pmm, 0.0f, 0.0f, 0.0f}, pb = pa;
+    for (int l = m; l < a.sh_bands; ++l) {
+      G4 p;
+      if (l == m) {
+        p = pa;
+      } else if (l == m + 1) {
+        pb = Z * ((2.0f * (float)m + 1.0f) * pmm);
+        p = pb;
+      } else {
+        p = (Z * pb * (2.0f * (float)l - 1.0f) - pa * (float)(l + m - 1)) * (1.0f / (float)(l - m));
+        pa = pb;
+        pb = p;
+      }
+      const float k = a.sh_norm[l * (l + 1) / 2 + m];
+      if (m == 0) {
+        f(l * (l + 1), l, p * k);
+      } else {
+        f(l * (l + 1) + m, l, p * cr * k);
+        f(l * (l + 1) - m, l, p * ci * k);
+      }
+    }
+  }
+}
+
+// E(n) per channel (values only).
+__device__ __forceinline__ V3 sh_irradiance(const RenderArgs& a, V3 n) {
+  V3 e = {0.0f, 0.0f, 0.0f};
+  sh_stream(a, n, [&](int i, int l, G4 y) {
+    const float w = a.sh_ash[l] * y.v;
+    e.x += w * a.sh[3 * i]; e.y += w * a.sh[3 * i + 1]; e.z += w * a.sh[3 * i + 2];
+  });
+  return e;
+}
+
 }  // namespace fr

@@ -136,6 +136,15 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
         if (DUMP && g1flag != 0.0f) a.dbg_vis[rs * a.L + j] |= VIS_FLAG;
       }
     }
+    // the SH light, once per sample (by the tile's first light chunk)
+    if (a.sh_bands > 0 && it.chunk == 0 && (a.components & 1)) {
+      const V3 e = sh_irradiance(a, shaded ? fr.ns : V3{0.0f, 0.0f, 1.0f});
+      if (shaded) {
+        acc[0] += fr.c.x * e.x * (1.0f / kPi);
+        acc[1] += fr.c.y * e.y * (1.0f / kPi);
+        acc[2] += fr.c.z * e.z * (1.0f / kPi);
+      }
+    }
   }
   if (DUMP && a.dbg_stats) {
     // shadow-ray counts (the primary pass adds the camera rays'): lane counts

@@ -120,10 +120,16 @@ class DeviceScene:
     tex_diffuse: torch.Tensor | None = None    # [M,M,3]
     tex_specular: torch.Tensor | None = None   # [M,M,3]
     tex_roughness: torch.Tensor | None = None  # [M,M]
+    # spherical-harmonics lighting (None: none), [B*B, 3]
+    sh: torch.Tensor | None = None
 
     @property
     def tex_size(self) -> int:
         return 0 if self.tex_diffuse is None else int(self.tex_diffuse.shape[0])
+
+    @property
+    def sh_bands(self) -> int:
+        return 0 if self.sh is None else int(round(self.sh.shape[0] ** 0.5))
 
     @property
     def n_lights(self) -> int:
@@ -141,6 +147,7 @@ class DeviceScene:
             cam=_f32(cam, device), fov_y=float(sc.camera.fov_y), W=sc.camera.W, H=sc.camera.H, spp=sc.spp,
             seed=int(sc.seed), step=int(sc.step),
             target=None if sc.target is None else _f32(sc.target, device),
+            sh=None if getattr(sc, "sh", None) is None else _f32(sc.sh, device),
             **({} if getattr(sc, "tex_diffuse", None) is None else dict(
                 uv=_f32(sc.uv, device), tex_diffuse=_f32(sc.tex_diffuse, device),
                 tex_specular=_f32(sc.tex_specular, device), tex_roughness=_f32(sc.tex_roughness, device))))
@@ -160,6 +167,9 @@ class DeviceScene:
             s.tex_size = self.tex_size
             s.tex_uv, s.tex_diffuse, s.tex_specular, s.tex_roughness = [
                 t.data_ptr() for t in (self.uv, self.tex_diffuse, self.tex_specular, self.tex_roughness)]
+        if self.sh_bands > 0:
+            assert self.sh.is_contiguous() and self.sh.shape == (self.sh_bands ** 2, 3)
+            s.sh, s.sh_bands = self.sh.data_ptr(), self.sh_bands
         return s
 
 
@@ -236,14 +246,15 @@ def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_varian
     (their contents unchanged since; the library checks the rest)."""
     dev = sc.verts.device
     N, L, M = mesh.n_verts, sc.n_lights, sc.tex_size
+    B = sc.sh_bands
     shapes = dict(verts=(N, 3), normals=(N, 3), diffuse=(N, 3), specular=(N, 3), roughness=(N,),
                   light_geom=(L, 9), light_rad=(L, 3), cam=(12,), tex_diffuse=(M, M, 3), tex_specular=(M, M, 3),
-                  tex_roughness=(M, M))
+                  tex_roughness=(M, M), sh=(B * B, 3))
     if M > 0 and groups is GRAD_GROUPS:
         groups = tuple(k for k in GRAD_GROUPS if k not in ("diffuse", "specular", "roughness")) + TEX_GROUPS
     out = {k: torch.zeros(shapes[k], dtype=torch.float32, device=dev) for k in groups}
     g = FrGrads()
-    for k in GRAD_GROUPS + TEX_GROUPS:
+    for k in GRAD_GROUPS + TEX_GROUPS + ("sh",):
         setattr(g, k, out[k].data_ptr() if k in out else None)
     dbg = None
     ns = sc.W * sc.H if edge_samples == -1 else edge_samples
