@@ -49,9 +49,10 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock (packed FP3
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=50,
-                    help="untimed steps first (~0.2 s: the GPU clocks settle after the host-side setup)")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3,
+                    help="untimed optimisation steps before the timed ones (after ~0.3 s of renders of the initial "
+                         "state that change nothing, so that the GPU clocks settle after the host-side setup)")
     ap.add_argument("--width", type=int, default=256)
     ap.add_argument("--spp", type=int, default=16)
     ap.add_argument("--lights", type=int, default=72)
@@ -74,6 +75,8 @@ def parse():
     ap.add_argument("--envmap-steps", type=int, default=5,
                     help="steps of the face under a 32x32 environment map (1,024 lights at infinity; 0 = skip)")
     ap.add_argument("--envmap-only", action="store_true", help="run only the environment-map measurement")
+    ap.add_argument("--sh-steps", type=int, default=10, help="steps of the face under 7-band SH lighting (0 = skip)")
+    ap.add_argument("--sh-only", action="store_true", help="run only the SH-lighting measurement")
     return ap.parse_args()
 
 
@@ -152,6 +155,21 @@ def make_c2(ctx, width, spp, n_lights, edge_samples):
     job, _ = recon.face_job(mt, np.random.default_rng(12), ctx, W=width, spp=spp, n_lights=n_lights, seed=4,
                             edge_samples=edge_samples)
     return mt, recon.Reconstruction(ctx, mt, job)
+
+
+def settle_clocks(rc, seconds):
+    """Render and back-propagate the reconstruction's current state (no
+    optimiser update, nothing changes) for about `seconds`."""
+    import torch
+    from paper_2101_05356_amd import render as R
+    sc = rc.scene()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        img = R.render_forward(rc.mesh, sc, verts=rc.v_w, keep_shadows=True)
+        _, dEdp = R.loss(img, rc.job.target, smooth=True)
+        R.render_backward(rc.mesh, sc, dEdp, edge_samples=rc.job.edge_samples, groups=("verts",), verts=rc.v_w,
+                          reuse_forward=True)
+        torch.cuda.synchronize()
 
 
 def traversal_stats(rc):
@@ -276,6 +294,23 @@ def envmap_bench(ctx, steps, warmup, edge_samples=-1, seed=52):
     return r
 
 
+def sh_bench(ctx, steps, warmup, bands=7, edge_samples=-1, seed=53):
+    """The face workload under SH lighting (Sec. 6 ablation: 3 and 7 bands
+    there; no lights, no visibility): the 256 x 256 face, 16 spp, a 7-band
+    SH light; per step a refit, the forward, the loss and the backward to
+    vertices (with the boundary term), albedos and the SH coefficients."""
+    from paper_2101_05356_amd import scenes
+    import dataclasses
+    sc = dataclasses.replace(scenes.face_render_scene(W=256, H=256, spp=16, n_lights=0),
+                             sh=scenes.sh_lighting(bands))
+    r = render_step_bench(ctx, sc, steps, warmup, ("verts", "diffuse", "sh"), edge_samples, seed)
+    r["workload"] = (f"256x256 face: {sc.n_verts:,}-vertex / {len(sc.tris):,}-triangle mesh, 16 spp, {bands}-band SH "
+                     f"light, no lights, refit+render+loss+backward (verts with {r['edge_samples']} edge samples, "
+                     f"albedos, SH coefficients)")
+    r["unit"] = "camera rays/s (rays_per_s counts W*H*S per step: no shadow rays)"
+    return r
+
+
 def render_step_bench(ctx, sc, steps, warmup, groups, edge_samples=-1, seed=51):
     """Refit + forward (keeping its decisions) + loss + backward (taking them)
     per step on one scene; the deformed vertex sets and the target are made
@@ -349,7 +384,11 @@ def main():
     if args.envmap_only:
         print(json.dumps({"envmap": envmap_bench(ctx, max(args.envmap_steps, 1), 2)}), flush=True)
         return
+    if args.sh_only:
+        print(json.dumps({"sh": sh_bench(ctx, max(args.sh_steps, 1), 3)}), flush=True)
+        return
     mt, rc = make_c2(ctx, W, S, L, args.edge_samples)
+    settle_clocks(rc, 0.3)
     for _ in range(args.warmup):
         rc.step()
     torch.cuda.synchronize()
@@ -411,6 +450,9 @@ def main():
     if args.envmap_steps > 0 and not args.profile_only:
         out["envmap"] = envmap_bench(ctx, args.envmap_steps, 2)
         print(json.dumps({"progress": "envmap", **out["envmap"]}), file=sys.stderr, flush=True)
+    if args.sh_steps > 0 and not args.profile_only:
+        out["sh"] = sh_bench(ctx, args.sh_steps, 3)
+        print(json.dumps({"progress": "sh", **out["sh"]}), file=sys.stderr, flush=True)
     if not args.profile_only and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, S, L, W)
     print(json.dumps(out), flush=True)
