@@ -462,3 +462,44 @@ def adam(theta, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mhat = m / (1.0 - beta1 ** t)
     vhat = v / (1.0 - beta2 ** t)
     return theta - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+# ---------------------------------------------------------------------------
+# Virtual light stage (Sec. 3.3, Eq. lightIntensity).  Each light j sits on
+# face j of a convex base shape (the icosahedron) with parameters
+# (d, a, p1, p2, i): the face scaled about the origin so that its centroid
+# lies at distance d (the homothetic face), a light triangle similar to it
+# with a times its area, centred at barycentric position p within it, facing
+# the origin, with radiance I = d^2 / a * i.
+# ---------------------------------------------------------------------------
+def light_stage(faces, params):
+    """(p0, e1, e2, rad) [J, 3] each, triangle lights emitting towards the
+    origin; FP64 (complex inputs give complex outputs, for the derivative)."""
+    V = np.asarray(faces)
+    P = np.asarray(params)
+    d, a, p1, p2, i = P[:, 0], P[:, 1], P[:, 2], P[:, 3], P[:, 4:7]
+    C = V.mean(axis=1)
+    scale = d / np.sqrt((np.real(C) ** 2).sum(axis=1))
+    c = scale[:, None] * (V[:, 0] + p1[:, None] * (V[:, 1] - V[:, 0]) + p2[:, None] * (V[:, 2] - V[:, 0]))
+    q = c[:, None, :] + (np.sqrt(a) * scale)[:, None, None] * (V - C[:, None, :])
+    # vertex order reversed: (q2 - q0) x (q1 - q0) points towards the origin
+    p0, e1, e2 = q[:, 0], q[:, 2] - q[:, 0], q[:, 1] - q[:, 0]
+    rad = (d * d / a)[:, None] * i
+    return p0, e1, e2, rad
+
+
+def light_stage_vjp(faces, params, g_geom, g_rad, h=1e-30):
+    """Gradient [J, 7] of sum(g_geom . (p0, e1, e2)) + sum(g_rad . rad) with
+    respect to the parameters, by complex-step differentiation of
+    light_stage (exact to rounding: no subtraction of nearby values)."""
+    P = np.asarray(params, np.float64)
+    gg = np.asarray(g_geom, np.float64).reshape(-1, 3, 3)
+    gr = np.asarray(g_rad, np.float64).reshape(-1, 3)
+    out = np.zeros_like(P)
+    for k in range(P.shape[1]):
+        Pc = P.astype(np.complex128)
+        Pc[:, k] += 1j * h
+        p0, e1, e2, rad = light_stage(np.asarray(faces, np.float64), Pc)
+        geom = np.stack([p0, e1, e2], axis=1)
+        out[:, k] = (np.imag(geom) / h * gg).sum(axis=(1, 2)) + (np.imag(rad) / h * gr).sum(axis=1)
+    return out

@@ -409,6 +409,40 @@ def face_lights(n_lights: int = 72, radius: float = 3.0, side: float = 0.2, seed
     return square_lights(centres, side, rng.uniform(0.0, 5.0, (n_lights, 3)))
 
 
+def icosahedron_faces() -> np.ndarray:
+    """The 20 faces [20, 3, 3] of the regular icosahedron of unit
+    circumradius centred at the origin (the virtual light stage's layout,
+    Sec. 3.3), each ordered so that (v1 - v0) x (v2 - v0) points outwards."""
+    g = (1.0 + math.sqrt(5.0)) / 2.0
+    v = np.array([[-1, g, 0], [1, g, 0], [-1, -g, 0], [1, -g, 0], [0, -1, g], [0, 1, g], [0, -1, -g], [0, 1, -g],
+                  [g, 0, -1], [g, 0, 1], [-g, 0, -1], [-g, 0, 1]], np.float64)
+    v /= np.linalg.norm(v[0])
+    # the faces are the triples of mutually adjacent vertices (edge length 1.0515...)
+    e = np.linalg.norm(v[0] - v[11])
+    adj = np.abs(np.linalg.norm(v[:, None] - v[None], axis=-1) - e) < 1e-9
+    faces = []
+    for i in range(12):
+        for j in range(i + 1, 12):
+            for k in range(j + 1, 12):
+                if adj[i, j] and adj[j, k] and adj[i, k]:
+                    f = [v[i], v[j], v[k]]
+                    if np.dot(np.cross(f[1] - f[0], f[2] - f[0]), f[0] + f[1] + f[2]) < 0:
+                        f = [f[0], f[2], f[1]]
+                    faces.append(f)
+    return _f32(np.array(faces))
+
+
+def light_stage_params(n_faces: int = 20, d: float = 3.0, a: float = 0.05, seed: int = 19) -> np.ndarray:
+    """Initial virtual-light-stage parameters [J, 7] = (d, a, p1, p2, i_rgb):
+    every light at its face's centre (p = (1/3, 1/3)), distance d, relative
+    area a, and a seeded perceived intensity in [0.2, 1]."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros((n_faces, 7))
+    p[:, 0], p[:, 1], p[:, 2], p[:, 3] = d, a, 1.0 / 3.0, 1.0 / 3.0
+    p[:, 4:] = rng.uniform(0.2, 1.0, (n_faces, 3))
+    return _f32(p)
+
+
 def environment_lights(res: int = 32, seed: int = 13, lo: float = 0.0, hi: float = 0.6) -> Lights:
     """The environment-map lighting of the paper's ablation (Sec. 6,
     "Environment Map vs. Light Stage"): a res x res latitude-longitude map,
