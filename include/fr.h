@@ -276,6 +276,25 @@ int fr_pose_forward(const float* d_v, int32_t n_verts, const float* d_pose, floa
 int fr_pose_backward(const float* d_v, int32_t n_verts, const float* d_pose, const float* d_gw, float* d_gv,
                      float* d_gpose, fr_stream stream);
 
+/* Virtual light stage (Sec. 3.3 "Virtual Light Stage", Eq. lightIntensity):
+ * light j lives on face j of a convex base shape (d_faces [J*9]: its three
+ * vertices; the icosahedron of unit circumradius, 20 faces, in the paper),
+ * with parameters d_params [J*7] = (d, a, p1, p2, i_r, i_g, i_b): the face
+ * scaled about the origin so that its centroid lies at distance d (the
+ * homothetic face); a triangle light similar to it with a times its area,
+ * centred at barycentric position (p1, p2) within it, parallel to it and
+ * emitting towards the origin; radiance I = d^2 / a * i.  Writes the
+ * triangle lights of fr_scene: d_p0, d_e1, d_e2, d_rad [J*3] and
+ * d_shape [J] = FR_LIGHT_TRIANGLE (each nullable).  a > 0 and d > 0 are the
+ * caller's (the paper keeps them there by a soft box constraint). */
+int fr_light_stage(const float* d_faces, const float* d_params, int32_t n_lights, float* d_p0, float* d_e1,
+                   float* d_e2, float* d_rad, int32_t* d_shape, fr_stream stream);
+/* Adjoint: d_gparams [J*7] += the gradient of sum(g_geom . (p0, e1, e2)) +
+ * sum(g_rad . rad), with d_g_geom [J*9] (p0, e1, e2: the light_geom layout
+ * of fr_grads) and d_g_rad [J*3] (each nullable). */
+int fr_light_stage_backward(const float* d_faces, const float* d_params, int32_t n_lights, const float* d_g_geom,
+                            const float* d_g_rad, float* d_gparams, fr_stream stream);
+
 /* Adam (Sec. 5 "Implementation Details": beta1 0.9, beta2 0.999, one learning
  * rate per parameter group), step number t >= 1, per-element learning rate
  * d_lr [n]: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;

@@ -101,6 +101,8 @@ SIGNATURES = {
     "fr_blend_backward": ([P, P, _i32, _i32, P, P], ctypes.c_int),
     "fr_pose_forward": ([P, _i32, P, P, P], ctypes.c_int),
     "fr_pose_backward": ([P, _i32, P, P, P, P, P], ctypes.c_int),
+    "fr_light_stage": ([P, P, _i32, P, P, P, P, P, P], ctypes.c_int),
+    "fr_light_stage_backward": ([P, P, _i32, P, P, P, P], ctypes.c_int),
     "fr_adam_step": ([P, P, P, P, P, _i32, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, P],
                      ctypes.c_int),
     "fr_model_create": ([P, _i32, _i32, P, P, P, _i32, P, P, _i32, P, P, P], ctypes.c_int),

@@ -585,6 +585,22 @@ int fr_pose_forward(const float* d_v, int32_t n, const float* d_pose, float* d_v
   return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
 }
 
+int fr_light_stage(const float* d_faces, const float* d_params, int32_t n, float* d_p0, float* d_e1, float* d_e2,
+                   float* d_rad, int32_t* d_shape, fr_stream stream) {
+  if (!d_faces || !d_params || n < 0) return FR_ERR_INVALID_ARG;
+  if (n > 0) fr::launch_light_stage(d_faces, d_params, n, d_p0, d_e1, d_e2, d_rad, d_shape,
+                                    reinterpret_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
+}
+
+int fr_light_stage_backward(const float* d_faces, const float* d_params, int32_t n, const float* d_g_geom,
+                            const float* d_g_rad, float* d_gparams, fr_stream stream) {
+  if (!d_faces || !d_params || !d_gparams || n < 0) return FR_ERR_INVALID_ARG;
+  if (n > 0) fr::launch_light_stage_backward(d_faces, d_params, n, d_g_geom, d_g_rad, d_gparams,
+                                             reinterpret_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
+}
+
 int fr_pose_backward(const float* d_v, int32_t n, const float* d_pose, const float* d_gw, float* d_gv, float* d_gpose,
                      fr_stream stream) {
   if (!d_v || !d_pose || !d_gw || n <= 0) return FR_ERR_INVALID_ARG;

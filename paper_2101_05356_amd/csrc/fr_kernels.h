@@ -211,6 +211,10 @@ void launch_pose_backward(const float* v, int N, const float* pose, const float*
 void launch_adam(float* p, const float* g, float* m, float* v, const float* lr, int n, int t, float b1, float b2,
                  float eps, hipStream_t st);
 void launch_light_setup(const fr_scene& sc, LightRec* out, hipStream_t st);
+void launch_light_stage(const float* faces, const float* P, int J, float* p0, float* e1, float* e2, float* rad,
+                        int32_t* shape, hipStream_t st);
+void launch_light_stage_backward(const float* faces, const float* P, int J, const float* gg, const float* gr,
+                                 float* gP, hipStream_t st);
 void launch_zero(float* p, int n, hipStream_t st);
 void launch_axpy(float* dst, const float* src, int n, hipStream_t st);
 // render.hip

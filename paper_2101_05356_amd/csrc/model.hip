@@ -450,4 +450,79 @@ void launch_axpy(float* dst, const float* src, int n, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(k_axpy, dim3(cdiv(n, 256)), dim3(256), 0, st, dst, src, n);
 }
 
+// ---------------------------------------------------------------------------
+// Virtual light stage (Sec. 3.3, Eq. lightIntensity): light j on face
+// (V0, V1, V2) with (d, a, p1, p2, i).  With C the face's centroid,
+// scale = d / |C|, B = V0 + p1 (V1 - V0) + p2 (V2 - V0) and
+// s = sqrt(a) scale:  p0 = scale B + s (V0 - C),  e1 = s (V2 - V0),
+// e2 = s (V1 - V0) (vertex order reversed: e1 x e2 points at the origin),
+// rad = d^2 / a * i.  One thread per light.
+// ---------------------------------------------------------------------------
+struct StageFace { V3 V0, V1, V2, C, B; float h; };
+__device__ __forceinline__ StageFace stage_face(const float* __restrict__ faces, const float* __restrict__ P, int j) {
+  StageFace f;
+  f.V0 = ld3(faces, 3 * j); f.V1 = ld3(faces, 3 * j + 1); f.V2 = ld3(faces, 3 * j + 2);
+  f.C = (f.V0 + f.V1 + f.V2) * (1.0f / 3.0f);
+  f.h = sqrtf(dot(f.C, f.C));
+  f.B = f.V0 + (f.V1 - f.V0) * P[7 * j + 2] + (f.V2 - f.V0) * P[7 * j + 3];
+  return f;
+}
+
+__global__ __launch_bounds__(64) void k_light_stage(const float* __restrict__ faces, const float* __restrict__ P, int J,
+                                                    float* __restrict__ p0, float* __restrict__ e1,
+                                                    float* __restrict__ e2, float* __restrict__ rad,
+                                                    int32_t* __restrict__ shape) {
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  if (j >= J) return;
+  const StageFace f = stage_face(faces, P, j);
+  const float d = P[7 * j], a = P[7 * j + 1];
+  const float scale = d / f.h, s = sqrtf(a) * scale;
+  const V3 q0 = f.B * scale + (f.V0 - f.C) * s, u = (f.V2 - f.V0) * s, w = (f.V1 - f.V0) * s;
+  const float I = d * d / a;
+  if (p0) { p0[3 * j] = q0.x; p0[3 * j + 1] = q0.y; p0[3 * j + 2] = q0.z; }
+  if (e1) { e1[3 * j] = u.x; e1[3 * j + 1] = u.y; e1[3 * j + 2] = u.z; }
+  if (e2) { e2[3 * j] = w.x; e2[3 * j + 1] = w.y; e2[3 * j + 2] = w.z; }
+  if (rad) for (int k = 0; k < 3; ++k) rad[3 * j + k] = I * P[7 * j + 4 + k];
+  if (shape) shape[j] = FR_LIGHT_TRIANGLE;
+}
+
+__global__ __launch_bounds__(64) void k_light_stage_bwd(const float* __restrict__ faces, const float* __restrict__ P,
+                                                        int J, const float* __restrict__ gg,
+                                                        const float* __restrict__ gr, float* __restrict__ gP) {
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  if (j >= J) return;
+  const StageFace f = stage_face(faces, P, j);
+  const float d = P[7 * j], a = P[7 * j + 1];
+  const float ra = sqrtf(a), scale = d / f.h;
+  const V3 z = {0.0f, 0.0f, 0.0f};
+  const V3 g0 = gg ? ld3(gg, 3 * j) : z, g1 = gg ? ld3(gg, 3 * j + 1) : z, g2 = gg ? ld3(gg, 3 * j + 2) : z;
+  // the parts that scale with s = sqrt(a) d / h
+  const float gs = dot(g0, f.V0 - f.C) + dot(g1, f.V2 - f.V0) + dot(g2, f.V1 - f.V0);
+  float gd = dot(g0, f.B) / f.h + gs * ra / f.h;
+  float ga = gs * scale * 0.5f / ra;
+  const float gp1 = dot(g0, f.V1 - f.V0) * scale, gp2 = dot(g0, f.V2 - f.V0) * scale;
+  float gi[3] = {0.0f, 0.0f, 0.0f};
+  if (gr) {
+    const float I = d * d / a;
+    for (int k = 0; k < 3; ++k) {
+      const float g = gr[3 * j + k], i = P[7 * j + 4 + k];
+      gd += g * 2.0f * d / a * i;
+      ga -= g * I / a * i;
+      gi[k] = g * I;
+    }
+  }
+  gP[7 * j] += gd; gP[7 * j + 1] += ga; gP[7 * j + 2] += gp1; gP[7 * j + 3] += gp2;
+  for (int k = 0; k < 3; ++k) gP[7 * j + 4 + k] += gi[k];
+}
+
+void launch_light_stage(const float* faces, const float* P, int J, float* p0, float* e1, float* e2, float* rad,
+                        int32_t* shape, hipStream_t st) {
+  hipLaunchKernelGGL(k_light_stage, dim3(cdiv(J, 64)), dim3(64), 0, st, faces, P, J, p0, e1, e2, rad, shape);
+}
+
+void launch_light_stage_backward(const float* faces, const float* P, int J, const float* gg, const float* gr,
+                                 float* gP, hipStream_t st) {
+  hipLaunchKernelGGL(k_light_stage_bwd, dim3(cdiv(J, 64)), dim3(64), 0, st, faces, P, J, gg, gr, gP);
+}
+
 }  // namespace fr

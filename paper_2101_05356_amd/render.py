@@ -292,6 +292,31 @@ def pose_forward(v, pose, out=None):
     return out
 
 
+def light_stage(faces, params):
+    """Virtual light stage -> triangle lights (p0, e1, e2, rad, shape) on
+    the device (faces [J,3,3], params [J,7] = (d, a, p1, p2, i_rgb))."""
+    J = int(params.shape[0])
+    dev = params.device
+    out = [torch.empty((J, 3), dtype=torch.float32, device=dev) for _ in range(4)]
+    shape = torch.empty(J, dtype=torch.int32, device=dev)
+    check(lib().fr_light_stage(_p(faces.contiguous()), _p(params.contiguous()), J, *[_p(t) for t in out], _p(shape),
+                               _stream()), None, "fr_light_stage")
+    return (*out, shape)
+
+
+def light_stage_backward(faces, params, g_geom=None, g_rad=None, gparams=None):
+    """gparams [J,7] += the stage parameters' gradient from the lights' (g_geom
+    [J,9] = p0, e1, e2; g_rad [J,3])."""
+    if gparams is None:
+        gparams = torch.zeros_like(params)
+    J = int(params.shape[0])
+    check(lib().fr_light_stage_backward(_p(faces.contiguous()), _p(params.contiguous()), J,
+                                        _p(None if g_geom is None else g_geom.contiguous()),
+                                        _p(None if g_rad is None else g_rad.contiguous()), _p(gparams), _stream()),
+          None, "fr_light_stage_backward")
+    return gparams
+
+
 def pose_backward(v, pose, gw, gv=None, gpose=None):
     N = v.numel() // 3
     check(lib().fr_pose_backward(_p(v), N, _p(pose), _p(gw), _p(gv), _p(gpose), _stream()), None,

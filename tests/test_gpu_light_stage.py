@@ -1,0 +1,74 @@
+"""The virtual light stage (Sec. 3.3, Eq. lightIntensity) on the GPU through
+the C ABI: the lights it builds and the parameters' gradient against the
+FP64 oracle (its mapping and complex-step derivative), alone and composed
+with a render and its adjoint."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2101_05356_amd import scenes
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _params(seed=0):
+    rng = np.random.default_rng(seed)
+    P = scenes.light_stage_params().astype(np.float64)
+    P[:, 0] *= rng.uniform(0.8, 1.2, 20)
+    P[:, 1] = rng.uniform(0.02, 0.6, 20)
+    P[:, 2:4] = rng.uniform(0.15, 0.45, (20, 2))
+    return P.astype(np.float32)
+
+
+def test_light_stage_forward_and_adjoint(oracle_lib):
+    import oracle
+    f = scenes.icosahedron_faces()
+    P = _params()
+    ft, Pt = torch.tensor(f).cuda(), torch.tensor(P).cuda()
+    p0, e1, e2, rad, shape = G.R.light_stage(ft, Pt)
+    torch.cuda.synchronize()
+    o = oracle.light_stage(f.astype(np.float64), P.astype(np.float64))
+    for got, want in zip((p0, e1, e2, rad), o):
+        assert np.allclose(G.to_np(got), want, rtol=2e-6, atol=2e-6 * np.abs(want).max())
+    assert np.all(G.to_np(shape) == scenes.LIGHT_TRIANGLE)
+    rng = np.random.default_rng(1)
+    gg, gr = rng.normal(size=(20, 9)).astype(np.float32), rng.normal(size=(20, 3)).astype(np.float32)
+    g = G.R.light_stage_backward(ft, Pt, torch.tensor(gg).cuda(), torch.tensor(gr).cuda())
+    torch.cuda.synchronize()
+    want = oracle.light_stage_vjp(f.astype(np.float64), P.astype(np.float64), gg, gr)
+    ok, l2, el = G.grad_tol_ok(G.to_np(g), want, rel=2e-5)
+    assert ok, (l2, el)
+
+
+def test_light_stage_composed_with_render(oracle_lib):
+    """Parameters -> lights -> render of the tilted bump patch -> adjoint ->
+    parameters, against the oracle's gradient of the same render composed
+    with its light-stage derivative."""
+    import oracle
+    from tests.test_oracle_grad import tilt_camera
+    f = scenes.icosahedron_faces()
+    P = _params(2)
+    ft, Pt = torch.tensor(f).cuda(), torch.tensor(P).cuda()
+    p0, e1, e2, rad, shape = G.R.light_stage(ft, Pt)
+    torch.cuda.synchronize()
+    sc = tilt_camera(scenes.patch_scene(W=32, H=32, spp=4))
+    lights = scenes.Lights(p0=G.to_np(p0), e1=G.to_np(e1), e2=G.to_np(e2), rad=G.to_np(rad),
+                           shape=G.to_np(shape).astype(np.int32))
+    sc = dataclasses.replace(sc, lights=lights)
+    m, ds = G.gpu_setup(sc)
+    img, hit, pflag, vis = G.R.render_forward(m, ds, dump=True)
+    torch.cuda.synchronize()
+    orc = oracle.render(sc)
+    rep, mh, mv = G.decisions_compare(sc, G.to_np(hit), G.to_np(pflag), G.to_np(vis), orc)
+    assert rep["hit_mismatch"] == 0 and rep["vis_mismatch"] == 0, rep
+    w = np.random.default_rng(3).normal(size=(32 * 32, 3)).astype(np.float32)
+    g = G.R.render_backward(m, ds, torch.tensor(w.reshape(32, 32, 3)).cuda(), groups=("light_geom", "light_rad"))
+    gP = G.R.light_stage_backward(ft, Pt, g["light_geom"], g["light_rad"])
+    torch.cuda.synchronize()
+    go = oracle.grad(sc, mh, mv, w.astype(np.float64))
+    want = oracle.light_stage_vjp(f.astype(np.float64), P.astype(np.float64), go["light"], go["rad"])
+    ok, l2, el = G.grad_tol_ok(G.to_np(gP), want)
+    assert np.abs(want).sum() > 0 and ok, (l2, el)
