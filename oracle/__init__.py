@@ -503,3 +503,67 @@ def light_stage_vjp(faces, params, g_geom, g_rad, h=1e-30):
         geom = np.stack([p0, e1, e2], axis=1)
         out[:, k] = (np.imag(geom) / h * gg).sum(axis=(1, 2)) + (np.imag(rad) / h * gr).sum(axis=1)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Stage II regularisers of the personalised maps (Sec. 4 "Stage II",
+# Eq. loss3): symmetry E_s, chromaticity consistency E_c, smoothness E_m and
+# the soft box E_b, on M x M maps (texel (i, j) at [j, i]; the horizontal
+# flip maps i to M - 1 - i).  Readings: chromaticity c / (c_r + c_g + c_b +
+# 1e-6); E_m sums, over texels and their in-map 4-neighbours, the squared
+# difference (each pair twice); E_b(x) = min(x, 0)^2 + max(x - 1, 0)^2;
+# sign(0) = 0 in the gradients of the L1 terms.
+# ---------------------------------------------------------------------------
+def _flip(X):
+    return X[:, ::-1]
+
+
+def _chroma(X, eps=1e-6):
+    return X / (X.sum(axis=-1, keepdims=True) + eps)
+
+
+def map_regularizers(Ch, Sh, Rh, C, S, w_sym=0.3, w_chroma=0.3, w_smooth=2e-4, w_box=1.0, eps=1e-6):
+    """E = w_sym (E_s(Ch) + E_s(Sh)) + w_chroma (E_c(Ch, C) + E_c(Sh, S))
+    + w_smooth (E_m(Ch) + E_m(Sh) + E_m(Rh)) + w_box (E_b(Sh) + E_b(Rh)),
+    with its gradient (gCh, gSh, gRh); maps [M, M, 3] (Rh [M, M]), FP64."""
+    Ch, Sh, Rh, C, S = (np.asarray(x, np.float64) for x in (Ch, Sh, Rh, C, S))
+
+    def e_s(X):
+        d = X - _flip(X)
+        return np.abs(d).sum(), 2.0 * np.sign(d)
+
+    def e_c(X, Y):
+        s = np.sign(_chroma(X, eps) - _chroma(Y, eps))
+        tot = X.sum(axis=-1, keepdims=True) + eps
+        g = s / tot - (s * X).sum(axis=-1, keepdims=True) / tot ** 2
+        return np.abs(_chroma(X, eps) - _chroma(Y, eps)).sum(), g
+
+    def e_m(X):
+        # each in-map neighbour pair (k, k+1) along an axis appears twice:
+        # 2 d^2 with d = X[k+1] - X[k]; d/dX[k+1] = 4 d, d/dX[k] = -4 d
+        E, g = 0.0, np.zeros_like(X)
+        for ax in (0, 1):
+            d = np.diff(X, axis=ax)
+            E += 2.0 * (d ** 2).sum()
+            hi = [slice(None)] * X.ndim
+            lo = [slice(None)] * X.ndim
+            hi[ax], lo[ax] = slice(1, None), slice(0, -1)
+            g[tuple(hi)] += 4.0 * d
+            g[tuple(lo)] -= 4.0 * d
+        return E, g
+
+    def e_b(X):
+        lo, hi = np.minimum(X, 0.0), np.maximum(X - 1.0, 0.0)
+        return (lo ** 2 + hi ** 2).sum(), 2.0 * lo + 2.0 * hi
+
+    E = 0.0
+    gC, gS, gR = np.zeros_like(Ch), np.zeros_like(Sh), np.zeros_like(Rh)
+    for X, g in ((Ch, gC), (Sh, gS)):
+        e, d = e_s(X); E += w_sym * e; g += w_sym * d
+    for X, Y, g in ((Ch, C, gC), (Sh, S, gS)):
+        e, d = e_c(X, Y); E += w_chroma * e; g += w_chroma * d
+    for X, g in ((Ch, gC), (Sh, gS), (Rh, gR)):
+        e, d = e_m(X); E += w_smooth * e; g += w_smooth * d
+    for X, g in ((Sh, gS), (Rh, gR)):
+        e, d = e_b(X); E += w_box * e; g += w_box * d
+    return E, (gC, gS, gR)
