@@ -241,6 +241,23 @@ int fr_render_forward(fr_mesh* mesh, const fr_scene* scene, const fr_render_opts
 int fr_loss(const float* d_image, const float* d_target, int32_t width, int32_t height, int32_t smooth,
             float* d_loss, float* d_dEdp, fr_stream stream);
 
+/* Stage II regularisers of the personalised reflectance maps (Sec. 4
+ * "Stage II", Eq. loss3; the paper's weights are w_sym = w_chroma = 0.3,
+ * w_smooth = 0.0002, w_box = 1):
+ *   w_sym (E_s(C) + E_s(S)) + w_chroma (E_c(C, C0) + E_c(S, S0))
+ *   + w_smooth (E_m(C) + E_m(S) + E_m(R)) + w_box (E_b(S) + E_b(R))
+ * over M x M maps (C, S, C0, S0 [M*M*3], R [M*M], texel (i, j) at j M + i,
+ * device): E_s the L1 difference to the horizontally flipped map (i to
+ * M - 1 - i), E_c the L1 difference of chromaticities x / (x_r + x_g + x_b +
+ * 1e-6) to the Stage I maps C0, S0, E_m the squared differences of each
+ * texel to its in-map 4-neighbours, E_b the squared excess outside [0, 1].
+ * d_loss [1] float is overwritten (FP64 sums); the gradients (nullable) are
+ * accumulated (+=). */
+typedef struct { float w_sym, w_chroma, w_smooth, w_box; } fr_map_reg_weights;
+int fr_map_regularizers(const float* d_c, const float* d_s, const float* d_r, const float* d_c0, const float* d_s0,
+                        int32_t M, const fr_map_reg_weights* weights, float* d_loss, float* d_gc, float* d_gs,
+                        float* d_gr, fr_stream stream);
+
 /* Backward pass: the adjoint of fr_render_forward for a given dE/dp
  * d_dEdp [H*W*3], recomputing every intersection and shadow decision from the
  * same counters (or taking the forward's, opts->reuse_forward) and holding

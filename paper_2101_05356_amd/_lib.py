@@ -39,6 +39,11 @@ class FrRenderOpts(ctypes.Structure):
                 ("reuse_forward", ctypes.c_int32), ("keep_shadows", ctypes.c_int32)]
 
 
+class FrMapRegWeights(ctypes.Structure):
+    _fields_ = [("w_sym", ctypes.c_float), ("w_chroma", ctypes.c_float), ("w_smooth", ctypes.c_float),
+                ("w_box", ctypes.c_float)]
+
+
 class FrGrads(ctypes.Structure):
     _fields_ = [("verts", P), ("normals", P), ("diffuse", P), ("specular", P), ("roughness", P),
                 ("light_geom", P), ("light_rad", P), ("cam", P), ("tex_diffuse", P), ("tex_specular", P),
@@ -102,6 +107,7 @@ SIGNATURES = {
     "fr_pose_forward": ([P, _i32, P, P, P], ctypes.c_int),
     "fr_pose_backward": ([P, _i32, P, P, P, P, P], ctypes.c_int),
     "fr_light_stage": ([P, P, _i32, P, P, P, P, P, P], ctypes.c_int),
+    "fr_map_regularizers": ([P, P, P, P, P, _i32, P, P, P, P, P, P], ctypes.c_int),
     "fr_light_stage_backward": ([P, P, _i32, P, P, P, P], ctypes.c_int),
     "fr_adam_step": ([P, P, P, P, P, _i32, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, P],
                      ctypes.c_int),

@@ -476,6 +476,25 @@ int fr_loss(const float* d_image, const float* d_target, int32_t W, int32_t H, i
   return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
 }
 
+int fr_map_regularizers(const float* d_c, const float* d_s, const float* d_r, const float* d_c0, const float* d_s0,
+                        int32_t M, const fr_map_reg_weights* w, float* d_loss, float* d_gc, float* d_gs, float* d_gr,
+                        fr_stream stream) {
+  if (!d_c || !d_s || !d_r || !d_c0 || !d_s0 || !w || !d_loss || M <= 0 || M > 16384) return FR_ERR_INVALID_ARG;
+  static thread_local double* scratch = nullptr;
+  static thread_local size_t cap = 0;
+  const size_t nb = ((size_t)M * M + 255) / 256;
+  if (nb > cap) {
+    if (scratch) (void)hipFree(scratch);
+    scratch = nullptr; cap = 0;
+    if (dalloc(&scratch, nb) != hipSuccess) return FR_ERR_OOM;
+    cap = nb;
+  }
+  const fr::MapRegWeights mw{w->w_sym, w->w_chroma, w->w_smooth, w->w_box};
+  fr::launch_map_regularizers(d_c, d_s, d_r, d_c0, d_s0, M, mw, d_loss, d_gc, d_gs, d_gr, scratch,
+                              reinterpret_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
+}
+
 int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, const float* d_dEdp, fr_grads* g,
                        fr_stream stream) {
   if (!m || !d_dEdp || !g) return FR_ERR_INVALID_ARG;

@@ -233,6 +233,10 @@ constexpr size_t kBwdPartBytes = 4 * 64 * 16 * sizeof(float) + 16;   // backward
 // Partial slots of the backward light/camera gradients (reduced in a fixed order).
 constexpr int kSlots = 1024;
 // loss.hip
+struct MapRegWeights { float w_sym, w_chroma, w_smooth, w_box; };
+void launch_map_regularizers(const float* Cm, const float* Sm, const float* Rm, const float* C0, const float* S0, int M,
+                             const MapRegWeights& w, float* loss, float* gC, float* gS, float* gR, double* scratch,
+                             hipStream_t st);
 void launch_loss(const float* img, const float* target, int W, int H, int smooth, float* loss, float* dEdp,
                  double* scratch, float* gtmp, hipStream_t st);
 // backward.hip

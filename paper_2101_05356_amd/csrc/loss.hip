@@ -108,6 +108,101 @@ __global__ __launch_bounds__(256) void k_smooth_adjoint(const float* __restrict_
   smooth_adjoint_block(g, W, H, w, out, blockIdx.x);
 }
 
+// ---------------------------------------------------------------------------
+// Stage II regularisers of the personalised maps (Sec. 4 "Stage II",
+// Eq. loss3): w_sym (E_s(C) + E_s(S)) + w_chroma (E_c(C, C0) + E_c(S, S0))
+// + w_smooth (E_m(C) + E_m(S) + E_m(R)) + w_box (E_b(S) + E_b(R)).  Texel
+// (i, j) at j M + i; the flip maps i to M - 1 - i; chromaticity
+// x / (x_r + x_g + x_b + 1e-6); E_m sums each texel's squared differences to
+// its in-map 4-neighbours; E_b(x) = min(x, 0)^2 + max(x - 1, 0)^2.  One
+// thread per texel gathers its own gradient (no atomics) and its terms of
+// the sum (FP64, fixed-order block and final sums).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float sgnf(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
+
+// Symmetry, smoothness and (optionally) chromaticity terms of channel-
+// interleaved map X (nc channels) at texel t; adds to g[0..nc) and returns
+// the texel's part of the weighted sum.
+__device__ __forceinline__ double map_terms(const float* __restrict__ X, const float* __restrict__ Y, int nc, int M,
+                                            int i, int j, const MapRegWeights& w, bool sym, float* g) {
+  const int t = j * M + i;
+  double e = 0.0;
+  const int nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
+  for (int c = 0; c < nc; ++c) {
+    const float x = X[nc * t + c];
+    if (sym) {
+      const float d = x - X[nc * (j * M + (M - 1 - i)) + c];
+      e += (double)w.w_sym * fabs((double)d);
+      g[c] += w.w_sym * 2.0f * sgnf(d);
+    }
+    for (int k = 0; k < 4; ++k) {
+      const int ii = nb[k][0], jj = nb[k][1];
+      if (ii < 0 || ii >= M || jj < 0 || jj >= M) continue;
+      const float d = x - X[nc * (jj * M + ii) + c];
+      e += (double)w.w_smooth * (double)d * (double)d;
+      g[c] += w.w_smooth * 4.0f * d;
+    }
+  }
+  if (Y) {   // chromaticity against the reference
+    const float T = X[3 * t] + X[3 * t + 1] + X[3 * t + 2] + 1e-6f;
+    const float U = Y[3 * t] + Y[3 * t + 1] + Y[3 * t + 2] + 1e-6f;
+    float s[3], sx = 0.0f;
+    for (int c = 0; c < 3; ++c) {
+      const float d = X[3 * t + c] / T - Y[3 * t + c] / U;
+      e += (double)w.w_chroma * fabs((double)d);
+      s[c] = sgnf(d);
+      sx += s[c] * X[3 * t + c];
+    }
+    for (int c = 0; c < 3; ++c) g[c] += w.w_chroma * (s[c] / T - sx / (T * T));
+  }
+  return e;
+}
+
+__device__ __forceinline__ double box_term(float x, float wb, float& g) {
+  const float lo = fminf(x, 0.0f), hi = fmaxf(x - 1.0f, 0.0f);
+  g += wb * (2.0f * lo + 2.0f * hi);
+  return (double)wb * ((double)lo * lo + (double)hi * hi);
+}
+
+__global__ __launch_bounds__(256) void k_map_reg(const float* __restrict__ Cm, const float* __restrict__ Sm,
+                                                 const float* __restrict__ Rm, const float* __restrict__ C0,
+                                                 const float* __restrict__ S0, int M, MapRegWeights w,
+                                                 float* __restrict__ gC, float* __restrict__ gS,
+                                                 float* __restrict__ gR, double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  double e = 0.0;
+  if (t < M * M) {
+    const int i = t % M, j = t / M;
+    float g3[3] = {0.0f, 0.0f, 0.0f};
+    e += map_terms(Cm, C0, 3, M, i, j, w, true, g3);
+    if (gC) for (int c = 0; c < 3; ++c) gC[3 * t + c] += g3[c];
+    g3[0] = g3[1] = g3[2] = 0.0f;
+    e += map_terms(Sm, S0, 3, M, i, j, w, true, g3);
+    for (int c = 0; c < 3; ++c) e += box_term(Sm[3 * t + c], w.w_box, g3[c]);
+    if (gS) for (int c = 0; c < 3; ++c) gS[3 * t + c] += g3[c];
+    float g1[1] = {0.0f};
+    e += map_terms(Rm, nullptr, 1, M, i, j, w, false, g1);
+    e += box_term(Rm[t], w.w_box, g1[0]);
+    if (gR) gR[t] += g1[0];
+  }
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+void launch_map_regularizers(const float* Cm, const float* Sm, const float* Rm, const float* C0, const float* S0, int M,
+                             const MapRegWeights& w, float* loss, float* gC, float* gS, float* gR, double* scratch,
+                             hipStream_t st) {
+  const int blocks = cdiv(M * M, 256);
+  hipLaunchKernelGGL(k_map_reg, dim3(blocks), dim3(256), 0, st, Cm, Sm, Rm, C0, S0, M, w, gC, gS, gR, scratch);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, scratch, blocks, loss);
+}
+
 void launch_loss(const float* img, const float* target, int W, int H, int smooth, float* loss, float* dEdp,
                  double* scratch, float* gtmp, hipStream_t st) {
   const double e = 0.60653065971263342;   // exp(-1/2)

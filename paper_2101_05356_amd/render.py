@@ -292,6 +292,21 @@ def pose_forward(v, pose, out=None):
     return out
 
 
+def map_regularizers(C, S, R, C0, S0, w_sym=0.3, w_chroma=0.3, w_smooth=2e-4, w_box=1.0, grads=True):
+    """Stage II regularisers of the maps (C, S, C0, S0 [M,M,3], R [M,M]);
+    returns (loss [1], gC, gS, gR) with new gradient tensors (None when
+    grads is False)."""
+    from ._lib import FrMapRegWeights
+    M = int(C.shape[0])
+    dev = C.device
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    g = [torch.zeros_like(x) for x in (C, S, R)] if grads else [None, None, None]
+    w = FrMapRegWeights(float(w_sym), float(w_chroma), float(w_smooth), float(w_box))
+    check(lib().fr_map_regularizers(*[_p(x.contiguous()) for x in (C, S, R, C0, S0)], M, ctypes.byref(w), _p(loss),
+                                    *[_p(x) for x in g], _stream()), None, "fr_map_regularizers")
+    return (loss, *g)
+
+
 def light_stage(faces, params):
     """Virtual light stage -> triangle lights (p0, e1, e2, rad, shape) on
     the device (faces [J,3,3], params [J,7] = (d, a, p1, p2, i_rgb))."""
