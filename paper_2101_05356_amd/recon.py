@@ -176,6 +176,46 @@ class Reconstruction:
         return E
 
 
+class Stage2:
+    """Stage II of the optimisation (Sec. 4 "Stage II", Eq. loss3): the
+    personalised diffuse, specular and roughness maps, initialised from the
+    Stage I maps (C0, S0) and a uniform roughness, fitted to the photograph
+    by Adam (lr 0.005, Sec. 5) under the map regularisers, with geometry,
+    lights and camera fixed.  Each step: render (keeping the decisions), the
+    smoothed L1 loss, the adjoint to the texels (taking the decisions), the
+    regularisers' value and gradient, one Adam step of each map; all on the
+    GPU through the C ABI."""
+
+    def __init__(self, mesh: R.Mesh, scene: R.DeviceScene, target: torch.Tensor, C0: torch.Tensor, S0: torch.Tensor,
+                 roughness0: float = 0.4, lr: float = 0.005, weights=(0.3, 0.3, 2e-4, 1.0)):
+        self.mesh, self.scene, self.target = mesh, scene, target
+        self.C0, self.S0 = C0.contiguous(), S0.contiguous()
+        self.maps = [self.C0.clone(), self.S0.clone(), torch.full(C0.shape[:2], roughness0, device=C0.device)]
+        self.m = [torch.zeros_like(x) for x in self.maps]
+        self.v = [torch.zeros_like(x) for x in self.maps]
+        self.lr = [torch.full((x.numel(),), lr, device=x.device) for x in self.maps]
+        self.weights = weights
+        self.t = 0
+
+    def step(self):
+        """One Stage II step; returns (photometric loss, regulariser sum) as
+        device tensors [1]."""
+        self.t += 1
+        C, S, Rm = self.maps
+        sc = dataclasses.replace(self.scene, tex_diffuse=C, tex_specular=S, tex_roughness=Rm, step=self.t)
+        img = R.render_forward(self.mesh, sc, keep_shadows=True)
+        E, dEdp = R.loss(img, self.target, smooth=True)
+        g = R.render_backward(self.mesh, sc, dEdp, groups=R.TEX_GROUPS, reuse_forward=True)
+        w = self.weights
+        Er, gC, gS, gR = R.map_regularizers(C, S, Rm, self.C0, self.S0, w_sym=w[0], w_chroma=w[1], w_smooth=w[2],
+                                            w_box=w[3])
+        for x, gr, gt, m, v, lr in zip(self.maps, (gC, gS, gR), (g["tex_diffuse"], g["tex_specular"],
+                                                                 g["tex_roughness"]), self.m, self.v, self.lr):
+            gr += gt
+            R.adam_step(x, gr, m, v, lr, self.t)
+        return E, Er
+
+
 def render_params(ctx, mt: ModelTensors, job: JobSpec, params: torch.Tensor) -> torch.Tensor:
     """Image of the face with the given parameters (e.g. a synthetic target)."""
     rc = Reconstruction(ctx, mt, dataclasses.replace(job, params=params))
