@@ -567,3 +567,31 @@ def map_regularizers(Ch, Sh, Rh, C, S, w_sym=0.3, w_chroma=0.3, w_smooth=2e-4, w
     for X, g in ((Sh, gS), (Rh, gR)):
         e, d = e_b(X); E += w_box * e; g += w_box * d
     return E, (gC, gS, gR)
+
+
+# ---------------------------------------------------------------------------
+# Stage I priors (Sec. 4 "Stage I", Eq. loss1).  Readings: the statistical
+# prior squares each coefficient over its standard deviation (the printed
+# sum of (alpha_k / sigma_k) is unbounded below); the light prior pulls each
+# light's RGB intensity towards its own mean over the channels (a high weight
+# gives monochromatic light, as the text says); the box keeps values in
+# [0, 1] by min(x, 0)^2 + max(x - 1, 0)^2.
+# ---------------------------------------------------------------------------
+PRIOR_STATISTICAL, PRIOR_BOX, PRIOR_LIGHT_CHROMA = 0, 1, 2
+
+
+def prior(x, kind, weight=1.0, sigma=None):
+    """(E, dE/dx) of one prior term, FP64."""
+    x = np.asarray(x, np.float64)
+    if kind == PRIOR_STATISTICAL:
+        s = np.asarray(sigma, np.float64)
+        return weight * float(((x / s) ** 2).sum()), weight * 2.0 * x / s ** 2
+    if kind == PRIOR_BOX:
+        lo, hi = np.minimum(x, 0.0), np.maximum(x - 1.0, 0.0)
+        return weight * float((lo ** 2 + hi ** 2).sum()), weight * (2.0 * lo + 2.0 * hi)
+    if kind == PRIOR_LIGHT_CHROMA:
+        I = x.reshape(-1, 3)
+        d = I - I.mean(axis=1, keepdims=True)
+        # d/dI_c of sum_c' (I_c' - mean)^2 = 2 (d_c - mean(d)) = 2 d_c (mean(d) = 0)
+        return weight * float((d ** 2).sum()), (weight * 2.0 * d).reshape(x.shape)
+    raise ValueError(kind)
