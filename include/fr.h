@@ -254,6 +254,17 @@ int fr_loss(const float* d_image, const float* d_target, int32_t width, int32_t 
  * d_loss [1] float is overwritten (FP64 sums); the gradients (nullable) are
  * accumulated (+=). */
 typedef struct { float w_sym, w_chroma, w_smooth, w_box; } fr_map_reg_weights;
+
+/* Stage I priors (Sec. 4 "Stage I", Eq. loss1; Sec. 5 weights w_i = w_c =
+ * w_s = 0.0025, w_1 = 0.01), over n device floats d_x:
+ *   FR_PRIOR_STATISTICAL  weight sum (x_k / sigma_k)^2 (d_sigma [n]);
+ *   FR_PRIOR_BOX          weight sum (min(x, 0)^2 + max(x - 1, 0)^2);
+ *   FR_PRIOR_LIGHT_CHROMA weight sum_j ||I_j - mean_c I_j||^2 over the n / 3
+ *                         RGB intensities I_j (d_sigma unused).
+ * d_loss [1] float is overwritten (FP64 sums); d_g (nullable) += dE/dx. */
+enum { FR_PRIOR_STATISTICAL = 0, FR_PRIOR_BOX = 1, FR_PRIOR_LIGHT_CHROMA = 2 };
+int fr_prior(const float* d_x, const float* d_sigma, int32_t n, int32_t kind, float weight, float* d_loss, float* d_g,
+             fr_stream stream);
 int fr_map_regularizers(const float* d_c, const float* d_s, const float* d_r, const float* d_c0, const float* d_s0,
                         int32_t M, const fr_map_reg_weights* weights, float* d_loss, float* d_gc, float* d_gs,
                         float* d_gr, fr_stream stream);

@@ -476,6 +476,24 @@ int fr_loss(const float* d_image, const float* d_target, int32_t W, int32_t H, i
   return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
 }
 
+int fr_prior(const float* d_x, const float* d_sigma, int32_t n, int32_t kind, float weight, float* d_loss, float* d_g,
+             fr_stream stream) {
+  if (!d_x || !d_loss || n < 0 || kind < FR_PRIOR_STATISTICAL || kind > FR_PRIOR_LIGHT_CHROMA ||
+      (kind == FR_PRIOR_STATISTICAL && !d_sigma) || (kind == FR_PRIOR_LIGHT_CHROMA && n % 3))
+    return FR_ERR_INVALID_ARG;
+  static thread_local double* scratch = nullptr;
+  static thread_local size_t cap = 0;
+  const size_t nb = std::max<size_t>(1, ((size_t)n + 255) / 256);
+  if (nb > cap) {
+    if (scratch) (void)hipFree(scratch);
+    scratch = nullptr; cap = 0;
+    if (dalloc(&scratch, nb) != hipSuccess) return FR_ERR_OOM;
+    cap = nb;
+  }
+  fr::launch_prior(d_x, d_sigma, n, kind, weight, d_loss, d_g, scratch, reinterpret_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
+}
+
 int fr_map_regularizers(const float* d_c, const float* d_s, const float* d_r, const float* d_c0, const float* d_s0,
                         int32_t M, const fr_map_reg_weights* w, float* d_loss, float* d_gc, float* d_gs, float* d_gr,
                         fr_stream stream) {

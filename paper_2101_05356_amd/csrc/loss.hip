@@ -203,6 +203,54 @@ void launch_map_regularizers(const float* Cm, const float* Sm, const float* Rm, 
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, scratch, blocks, loss);
 }
 
+// ---------------------------------------------------------------------------
+// Stage I priors (Sec. 4 "Stage I", Eq. loss1): statistical w sum (x/sigma)^2,
+// soft box w sum (min(x,0)^2 + max(x-1,0)^2), and the light prior
+// w sum_j ||I_j - mean_c(I_j)||^2 over RGB triples.  One thread per value
+// (per light for the light prior); FP64 block and final sums.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_prior(const float* __restrict__ x, const float* __restrict__ sigma, int n,
+                                               int kind, float w, float* __restrict__ g,
+                                               double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double e = 0.0;
+  if (kind == FR_PRIOR_LIGHT_CHROMA) {
+    if (i < n / 3) {
+      const float m = (x[3 * i] + x[3 * i + 1] + x[3 * i + 2]) * (1.0f / 3.0f);
+      for (int c = 0; c < 3; ++c) {
+        const float d = x[3 * i + c] - m;
+        e += (double)w * (double)d * (double)d;
+        if (g) g[3 * i + c] += w * 2.0f * d;
+      }
+    }
+  } else if (i < n) {
+    if (kind == FR_PRIOR_STATISTICAL) {
+      const float q = x[i] / sigma[i];
+      e = (double)w * (double)q * (double)q;
+      if (g) g[i] += w * 2.0f * q / sigma[i];
+    } else {
+      const float lo = fminf(x[i], 0.0f), hi = fmaxf(x[i] - 1.0f, 0.0f);
+      e = (double)w * ((double)lo * lo + (double)hi * hi);
+      if (g) g[i] += w * (2.0f * lo + 2.0f * hi);
+    }
+  }
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+void launch_prior(const float* x, const float* sigma, int n, int kind, float w, float* loss, float* g, double* scratch,
+                  hipStream_t st) {
+  const int blocks = std::max(1, cdiv(n, 256));
+  hipLaunchKernelGGL(k_prior, dim3(blocks), dim3(256), 0, st, x, sigma, n, kind, w, g, scratch);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, scratch, blocks, loss);
+}
+
 void launch_loss(const float* img, const float* target, int W, int H, int smooth, float* loss, float* dEdp,
                  double* scratch, float* gtmp, hipStream_t st) {
   const double e = 0.60653065971263342;   // exp(-1/2)

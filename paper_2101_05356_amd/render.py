@@ -307,6 +307,20 @@ def map_regularizers(C, S, R, C0, S0, w_sym=0.3, w_chroma=0.3, w_smooth=2e-4, w_
     return (loss, *g)
 
 
+PRIOR_STATISTICAL, PRIOR_BOX, PRIOR_LIGHT_CHROMA = 0, 1, 2
+
+
+def prior(x, kind, weight, sigma=None, g=None):
+    """Stage I prior of x (see fr_prior): returns (loss [1], g) with g += dE/dx
+    (a new tensor when g is None)."""
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    if g is None:
+        g = torch.zeros_like(x)
+    check(lib().fr_prior(_p(x.contiguous()), _p(None if sigma is None else sigma.contiguous()), x.numel(), int(kind),
+                         float(weight), _p(loss), _p(g), _stream()), None, "fr_prior")
+    return loss, g
+
+
 def light_stage(faces, params):
     """Virtual light stage -> triangle lights (p0, e1, e2, rad, shape) on
     the device (faces [J,3,3], params [J,7] = (d, a, p1, p2, i_rgb))."""
