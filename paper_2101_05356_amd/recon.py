@@ -176,6 +176,96 @@ class Reconstruction:
         return E
 
 
+class Stage1:
+    """Stage I of the optimisation (Sec. 4 "Stage I", Eq. loss1) with the
+    virtual light stage (Sec. 3.3): identity and expression coefficients,
+    statistical albedo, pose and the stage parameters (d, a, p, i of one
+    light per icosahedron face) fitted to the photograph under the
+    statistical prior (w_i = w_c = 0.0025 over the model's component
+    standard deviations), the light prior (w_1 = 0.01 on the intensities
+    I_j = d^2 / a i) and the soft box on the expression coefficients; Adam
+    with the Sec. 5 rates (light stage 1e-3).  Each step runs on the GPU
+    through the C ABI: blend, pose, refit, light stage, render (keeping its
+    decisions), loss, adjoint (taking them), the adjoints of the light stage,
+    pose and blend, the priors, Adam.  The model here has no specular basis,
+    so the specular prior of the paper has nothing to act on."""
+
+    def __init__(self, ctx: R.Context, mt: ModelTensors, target: torch.Tensor, camera: scenes.Camera, spp: int,
+                 params0: torch.Tensor, stage0: np.ndarray, sigma_id: np.ndarray, sigma_alb: np.ndarray, seed: int = 4,
+                 edge_samples: int = -1):
+        dev = mt.mean_geo.device
+        self.mt, self.target, self.edge_samples = mt, target, edge_samples
+        self.sl = param_slices(mt.K_geo, mt.K_alb, 0)
+        self.faces = torch.tensor(scenes.icosahedron_faces(), device=dev)
+        self.x = params0[:self.sl["pose"].stop].clone()
+        self.w = torch.tensor(np.asarray(stage0, np.float32), device=dev)
+        lr = learning_rates(mt, 0)[:self.x.numel()]
+        self.lr_x = torch.tensor(lr, device=dev)
+        self.lr_w = torch.full((self.w.numel(),), 1e-3, device=dev)
+        self.m_x, self.v_x = torch.zeros_like(self.x), torch.zeros_like(self.x)
+        self.m_w, self.v_w_ = torch.zeros_like(self.w), torch.zeros_like(self.w)
+        self.sig_id = torch.tensor(np.asarray(sigma_id, np.float32), device=dev)
+        self.sig_alb = torch.tensor(np.asarray(sigma_alb, np.float32), device=dev)
+        N, J = mt.N, self.w.shape[0]
+        self.v_obj = torch.empty(3 * N, device=dev)
+        self.v_w = torch.empty(3 * N, device=dev)
+        self.diffuse = torch.empty(3 * N, device=dev)
+        self.mesh = R.Mesh(ctx, N, mt.tris)
+        empty = scenes.Lights(p0=np.zeros((J, 3), np.float32), e1=np.zeros((J, 3), np.float32),
+                              e2=np.zeros((J, 3), np.float32), rad=np.zeros((J, 3), np.float32),
+                              shape=np.full(J, scenes.LIGHT_TRIANGLE, np.int32))
+        sc = scenes.Scene(verts=np.zeros((N, 3), np.float32), tris=mt.tris, diffuse=np.zeros((N, 3), np.float32),
+                          specular=np.zeros((N, 3), np.float32), roughness=np.zeros(N, np.float32), lights=empty,
+                          camera=camera, spp=spp, seed=seed, step=0)
+        self.ds = R.DeviceScene.from_scene(sc, dev)
+        self.ds.specular, self.ds.roughness = mt.specular.view(-1, 3), mt.roughness
+        self.t = 0
+        self._geometry(rebuild=True)
+
+    def _geometry(self, rebuild=False):
+        mt, sl = self.mt, self.sl
+        R.blend(mt.mean_geo, mt.basis_geo, self.x[sl["geo"]], out=self.v_obj)
+        R.blend(mt.mean_alb, mt.basis_alb, self.x[sl["alb"]], out=self.diffuse)
+        R.pose_forward(self.v_obj, self.x[sl["pose"]], out=self.v_w)
+        self.mesh.update(self.v_w, rebuild=rebuild)
+
+    def scene(self):
+        p0, e1, e2, rad, shape = R.light_stage(self.faces, self.w)
+        return dataclasses.replace(self.ds, verts=self.v_w.view(-1, 3), diffuse=self.diffuse.view(-1, 3),
+                                   light_p0=p0, light_e1=e1, light_e2=e2, light_rad=rad, light_shape=shape,
+                                   step=self.t)
+
+    def gradients(self):
+        """(objective [1], gradient of the model parameters, of the stage
+        parameters) at the current state and step counter."""
+        mt, sl, K_id = self.mt, self.sl, self.mt.K_id
+        sc = self.scene()
+        img = R.render_forward(self.mesh, sc, verts=self.v_w, keep_shadows=True)
+        E, dEdp = R.loss(img, self.target, smooth=True)
+        g = R.render_backward(self.mesh, sc, dEdp, edge_samples=self.edge_samples, verts=self.v_w,
+                              groups=("verts", "diffuse", "light_geom", "light_rad"), reuse_forward=True)
+        gx = torch.zeros_like(self.x)
+        g_vobj = torch.zeros_like(self.v_obj)
+        R.pose_backward(self.v_obj, self.x[sl["pose"]], g["verts"], g_vobj, gx[sl["pose"]])
+        R.blend_backward(mt.basis_geo, g_vobj, gx[sl["geo"]])
+        R.blend_backward(mt.basis_alb, g["diffuse"], gx[sl["alb"]])
+        e_id, _ = R.prior(self.x[0:K_id], R.PRIOR_STATISTICAL, 0.0025, self.sig_id, g=gx[0:K_id])
+        e_alb, _ = R.prior(self.x[sl["alb"]], R.PRIOR_STATISTICAL, 0.0025, self.sig_alb, g=gx[sl["alb"]])
+        e_box, _ = R.prior(self.x[K_id:mt.K_geo], R.PRIOR_BOX, 1.0, g=gx[K_id:mt.K_geo])
+        e_l, _ = R.prior(sc.light_rad, R.PRIOR_LIGHT_CHROMA, 0.01, g=g["light_rad"])
+        gw = R.light_stage_backward(self.faces, self.w, g["light_geom"], g["light_rad"])
+        return E + e_id + e_alb + e_box + e_l, gx, gw
+
+    def step(self):
+        """One Stage I step; returns the objective at the step's parameters."""
+        self.t += 1
+        self._geometry(rebuild=False)
+        E, gx, gw = self.gradients()
+        R.adam_step(self.x, gx, self.m_x, self.v_x, self.lr_x, self.t)
+        R.adam_step(self.w, gw, self.m_w, self.v_w_, self.lr_w, self.t)
+        return E
+
+
 class Stage2:
     """Stage II of the optimisation (Sec. 4 "Stage II", Eq. loss3): the
     personalised diffuse, specular and roughness maps, initialised from the

@@ -1,0 +1,73 @@
+"""Stage I of the optimisation with the virtual light stage (Sec. 4 Eq. loss1,
+Sec. 3.3) on the GPU: the stage parameters' gradient of one step equals the
+oracle's (render adjoint to the lights + light prior, through the light
+stage's derivative), and steps lower the objective."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2101_05356_amd import scenes
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def setup(seed=31, W=32, spp=4):
+    from paper_2101_05356_amd import recon
+    ctx = G.ctx()
+    model = scenes.synthetic_morph_model(seed=seed, n_lon=40, n_ring=26, K_s=6, K_e=4, K_r=6)
+    mt = recon.ModelTensors.from_model(model)
+    cam = scenes.face_camera(W, W)
+    n = mt.K_geo + mt.K_alb + 6
+    return recon, ctx, mt, cam, n
+
+
+def test_stage1_light_stage_gradient_matches_oracle(oracle_lib):
+    import oracle
+    recon, ctx, mt, cam, n = setup()
+    rng = np.random.default_rng(3)
+    params0 = torch.tensor(np.concatenate([rng.normal(0, 0.5, n - 6), [0.05, -0.05, 0.03, 0.02, -0.02, 0.01]])
+                           .astype(np.float32)).cuda()
+    stage0 = scenes.light_stage_params(d=3.0, a=0.05)
+    target = torch.tensor(scenes.smooth_random_image(rng, 32, 32, 0.0, 0.4)).cuda()
+    st = recon.Stage1(ctx, mt, target, cam, 4, params0, stage0, np.ones(mt.K_id), np.ones(mt.K_alb))
+    st.t = 1
+    E, gx, gw = st.gradients()
+    sc = st.scene()
+    img, hit, pflag, vis = G.R.render_forward(st.mesh, sc, verts=st.v_w, dump=True)
+    torch.cuda.synchronize()
+    # the oracle on the very same FP32 inputs
+    osc = scenes.Scene(verts=G.to_np(st.v_w).reshape(-1, 3), tris=mt.tris, diffuse=G.to_np(st.diffuse).reshape(-1, 3),
+                       specular=G.to_np(mt.specular), roughness=G.to_np(mt.roughness),
+                       lights=scenes.Lights(p0=G.to_np(sc.light_p0), e1=G.to_np(sc.light_e1), e2=G.to_np(sc.light_e2),
+                                            rad=G.to_np(sc.light_rad), shape=G.to_np(sc.light_shape)),
+                       camera=cam, spp=4, seed=4, step=1)
+    rep, mh, mv = G.decisions_compare(osc, G.to_np(hit), G.to_np(pflag), G.to_np(vis), oracle.render(osc))
+    assert rep["hit_mismatch"] == 0 and rep["vis_mismatch"] == 0, rep
+    _, dEdp = G.R.loss(img, target, smooth=True)
+    go = oracle.grad(osc, mh, mv, G.to_np(dEdp).reshape(-1, 3).astype(np.float64))
+    _, gp = oracle.prior(osc.lights.rad, oracle.PRIOR_LIGHT_CHROMA, 0.01)
+    want = oracle.light_stage_vjp(scenes.icosahedron_faces().astype(np.float64), stage0.astype(np.float64),
+                                  go["light"], go["rad"] + gp)
+    ok, l2, el = G.grad_tol_ok(G.to_np(gw), want)
+    assert np.abs(want).sum() > 0 and ok, (l2, el)
+
+
+def test_stage1_steps_lower_the_objective(oracle_lib):
+    recon, ctx, mt, cam, n = setup()
+    rng = np.random.default_rng(5)
+    truth = np.concatenate([rng.normal(0, 0.5, n - 6), np.zeros(6)]).astype(np.float32)
+    stage_true = scenes.light_stage_params(d=3.0, a=0.05, seed=23)
+    ref = recon.Stage1(ctx, mt, torch.zeros((32, 32, 3), device="cuda"), cam, 4, torch.tensor(truth).cuda(),
+                       stage_true, np.ones(mt.K_id), np.ones(mt.K_alb))
+    target = G.R.render_forward(ref.mesh, ref.scene(), verts=ref.v_w)
+    start = truth.copy()
+    start[:n - 6] = 0.0
+    start[n - 6:] = [0.05, -0.05, 0.03, 0.02, -0.02, 0.01]
+    stage0 = scenes.light_stage_params(d=3.0, a=0.05, seed=29)
+    st = recon.Stage1(ctx, mt, target, cam, 4, torch.tensor(start).cuda(), stage0, np.ones(mt.K_id), np.ones(mt.K_alb))
+    objs = [float(st.step().item()) for _ in range(40)]
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(objs)) and np.mean(objs[-5:]) < 0.8 * np.mean(objs[:5]), objs
