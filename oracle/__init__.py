@@ -595,3 +595,42 @@ def prior(x, kind, weight=1.0, sigma=None):
         # d/dI_c of sum_c' (I_c' - mean)^2 = 2 (d_c - mean(d)) = 2 d_c (mean(d) = 0)
         return weight * float((d ** 2).sum()), (weight * 2.0 * d).reshape(x.shape)
     raise ValueError(kind)
+
+
+# ---------------------------------------------------------------------------
+# Landmark loss (Sec. 4 Eq. landmark): sum_l || Pi(Gamma(v_l)) - z_l ||^2 with
+# the pinhole of the render (Sec. 3.1): camera frame p = R^T (X - T), film
+# point ((p_x / -p_z) / (tan(fov/2) W/H) + 1) W/2, (1 - (p_y / -p_z) /
+# tan(fov/2)) H/2, in pixels.  Gradient by complex-step differentiation.
+# ---------------------------------------------------------------------------
+def project(X, cam, fov_y, W, H):
+    """Film points [n, 2] of world points X [n, 3]; cam [12] = R (row-major),
+    T; complex inputs allowed."""
+    cam = np.asarray(cam)
+    R, T = cam[:9].reshape(3, 3), cam[9:12]
+    p = (np.asarray(X) - T) @ R                      # R^T (X - T), row-vector form
+    th = np.tan(0.5 * float(fov_y))
+    z = -p[:, 2]
+    return np.stack([(p[:, 0] / z / (th * W / H) + 1.0) * (0.5 * W), (1.0 - p[:, 1] / z / th) * (0.5 * H)], axis=1)
+
+
+def landmark_loss(verts, idx, cam, fov_y, W, H, z, h=1e-30):
+    """(E, dE/dverts [N, 3] (nonzero at the landmark vertices), dE/dcam [12])."""
+    V = np.asarray(verts, np.float64)
+    idx = np.asarray(idx)
+    cam = np.asarray(cam, np.float64)
+    zz = np.asarray(z, np.float64)
+    E = float(((project(V[idx], cam, fov_y, W, H) - zz) ** 2).sum())
+    gV = np.zeros_like(V)
+    for l, i in enumerate(idx):
+        for k in range(3):
+            X = V[[i]].astype(np.complex128)
+            X[0, k] += 1j * h
+            r = project(X, cam, fov_y, W, H)[0] - zz[l]
+            gV[i, k] += float(np.imag((r * r).sum())) / h
+    gc = np.zeros(12)
+    for k in range(12):
+        c = cam.astype(np.complex128)
+        c[k] += 1j * h
+        gc[k] = float(np.imag(((project(V[idx], c, fov_y, W, H) - zz) ** 2).sum())) / h
+    return E, gV, gc
