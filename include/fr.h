@@ -263,6 +263,15 @@ typedef struct { float w_sym, w_chroma, w_smooth, w_box; } fr_map_reg_weights;
  *                         RGB intensities I_j (d_sigma unused).
  * d_loss [1] float is overwritten (FP64 sums); d_g (nullable) += dE/dx. */
 enum { FR_PRIOR_STATISTICAL = 0, FR_PRIOR_BOX = 1, FR_PRIOR_LIGHT_CHROMA = 2 };
+
+/* Landmark loss (Sec. 4 Eq. landmark): sum_l || Pi(v_l) - z_l ||^2 over n
+ * landmarks, v_l = d_verts[d_idx[l]] (world positions, distinct indices),
+ * Pi the render's pinhole (Sec. 3.1; cam [12] as in fr_scene, fov_y and
+ * the W x H image: film points in pixels, y down), z_l = d_z [n*2].
+ * d_loss [1] float overwritten; d_gverts [N*3] and d_gcam [12] (nullable)
+ * accumulate (+=). */
+int fr_landmark_loss(const float* d_verts, const int32_t* d_idx, int32_t n, const float* d_cam, float fov_y, int32_t W,
+                     int32_t H, const float* d_z, float* d_loss, float* d_gverts, float* d_gcam, fr_stream stream);
 int fr_prior(const float* d_x, const float* d_sigma, int32_t n, int32_t kind, float weight, float* d_loss, float* d_g,
              fr_stream stream);
 int fr_map_regularizers(const float* d_c, const float* d_s, const float* d_r, const float* d_c0, const float* d_s0,

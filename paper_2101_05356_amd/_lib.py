@@ -109,6 +109,7 @@ SIGNATURES = {
     "fr_light_stage": ([P, P, _i32, P, P, P, P, P, P], ctypes.c_int),
     "fr_map_regularizers": ([P, P, P, P, P, _i32, P, P, P, P, P, P], ctypes.c_int),
     "fr_prior": ([P, P, _i32, _i32, ctypes.c_float, P, P, P], ctypes.c_int),
+    "fr_landmark_loss": ([P, P, _i32, P, ctypes.c_float, _i32, _i32, P, P, P, P, P], ctypes.c_int),
     "fr_light_stage_backward": ([P, P, _i32, P, P, P, P], ctypes.c_int),
     "fr_adam_step": ([P, P, P, P, P, _i32, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, P],
                      ctypes.c_int),

@@ -476,6 +476,15 @@ int fr_loss(const float* d_image, const float* d_target, int32_t W, int32_t H, i
   return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
 }
 
+int fr_landmark_loss(const float* d_verts, const int32_t* d_idx, int32_t n, const float* d_cam, float fov_y, int32_t W,
+                     int32_t H, const float* d_z, float* d_loss, float* d_gverts, float* d_gcam, fr_stream stream) {
+  if (!d_verts || !d_idx || !d_cam || !d_z || !d_loss || n < 0 || W <= 0 || H <= 0 || !(fov_y > 0.0f && fov_y < 3.1f))
+    return FR_ERR_INVALID_ARG;
+  fr::launch_landmarks(d_verts, d_idx, n, d_cam, std::tan(0.5f * fov_y), W, H, d_z, d_loss, d_gverts, d_gcam,
+                       reinterpret_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
+}
+
 int fr_prior(const float* d_x, const float* d_sigma, int32_t n, int32_t kind, float weight, float* d_loss, float* d_g,
              fr_stream stream) {
   if (!d_x || !d_loss || n < 0 || kind < FR_PRIOR_STATISTICAL || kind > FR_PRIOR_LIGHT_CHROMA ||

@@ -234,6 +234,8 @@ constexpr size_t kBwdPartBytes = 4 * 64 * 16 * sizeof(float) + 16;   // backward
 constexpr int kSlots = 1024;
 // loss.hip
 struct MapRegWeights { float w_sym, w_chroma, w_smooth, w_box; };
+void launch_landmarks(const float* V, const int32_t* idx, int n, const float* cam, float tan_half, int W, int H,
+                      const float* z, float* loss, float* gV, float* gcam, hipStream_t st);
 void launch_prior(const float* x, const float* sigma, int n, int kind, float w, float* loss, float* g, double* scratch,
                   hipStream_t st);
 void launch_map_regularizers(const float* Cm, const float* Sm, const float* Rm, const float* C0, const float* S0, int M,

@@ -251,6 +251,66 @@ void launch_prior(const float* x, const float* sigma, int n, int kind, float w, 
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, scratch, blocks, loss);
 }
 
+// ---------------------------------------------------------------------------
+// Landmark loss (Sec. 4 Eq. landmark): sum_l || Pi(v_l) - z_l ||^2 with the
+// render's pinhole (Sec. 3.1): p = R^T (X - T), z = -p_z,
+// f = ((p_x / z) / (tan_half aspect) + 1) W / 2, (1 - (p_y / z) / tan_half) H / 2.
+// One block; each thread takes landmarks l, l + 256, ...; the vertex
+// gradients go to their vertices (distinct indices: plain adds), the
+// camera's and the loss through fixed-order block sums.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_landmarks(const float* __restrict__ V, const int32_t* __restrict__ idx, int n,
+                                                   const float* __restrict__ cam, float th, int W, int H,
+                                                   const float* __restrict__ zt, float* __restrict__ loss,
+                                                   float* __restrict__ gV, float* __restrict__ gcam) {
+  __shared__ double red[256];
+  __shared__ float redc[12][256];
+  double e = 0.0;
+  float gc[12];
+  for (int k = 0; k < 12; ++k) gc[k] = 0.0f;
+  const float asp = (float)W / (float)H;
+  for (int l = threadIdx.x; l < n; l += 256) {
+    const int i = idx[l];
+    const V3 X = ld3(V, i), T = {cam[9], cam[10], cam[11]};
+    const V3 q = X - T;
+    const V3 p = {cam[0] * q.x + cam[3] * q.y + cam[6] * q.z, cam[1] * q.x + cam[4] * q.y + cam[7] * q.z,
+                  cam[2] * q.x + cam[5] * q.y + cam[8] * q.z};
+    const float z = -p.z;
+    const float ax = 0.5f * (float)W / (th * asp), ay = 0.5f * (float)H / th;
+    const float fx = (p.x / z) * ax + 0.5f * (float)W, fy = 0.5f * (float)H - (p.y / z) * ay;
+    const float rx = fx - zt[2 * l], ry = fy - zt[2 * l + 1];
+    e += (double)rx * rx + (double)ry * ry;
+    // dE/dp through both film coordinates
+    const V3 gp = {2.0f * rx * ax / z, -2.0f * ry * ay / z, 2.0f * rx * ax * p.x / (z * z) - 2.0f * ry * ay * p.y / (z * z)};
+    const V3 gX = {cam[0] * gp.x + cam[1] * gp.y + cam[2] * gp.z, cam[3] * gp.x + cam[4] * gp.y + cam[5] * gp.z,
+                   cam[6] * gp.x + cam[7] * gp.y + cam[8] * gp.z};
+    if (gV) { gV[3 * i] += gX.x; gV[3 * i + 1] += gX.y; gV[3 * i + 2] += gX.z; }
+    const float qq[3] = {q.x, q.y, q.z}, pp[3] = {gp.x, gp.y, gp.z};
+    for (int k = 0; k < 3; ++k)
+      for (int c = 0; c < 3; ++c) gc[3 * k + c] += qq[k] * pp[c];
+    gc[9] -= gX.x; gc[10] -= gX.y; gc[11] -= gX.z;
+  }
+  red[threadIdx.x] = e;
+  for (int k = 0; k < 12; ++k) redc[k][threadIdx.x] = gc[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      red[threadIdx.x] += red[threadIdx.x + s];
+      for (int k = 0; k < 12; ++k) redc[k][threadIdx.x] += redc[k][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    loss[0] = (float)red[0];
+    if (gcam) for (int k = 0; k < 12; ++k) gcam[k] += redc[k][0];
+  }
+}
+
+void launch_landmarks(const float* V, const int32_t* idx, int n, const float* cam, float tan_half, int W, int H,
+                      const float* z, float* loss, float* gV, float* gcam, hipStream_t st) {
+  hipLaunchKernelGGL(k_landmarks, dim3(1), dim3(256), 0, st, V, idx, n, cam, tan_half, W, H, z, loss, gV, gcam);
+}
+
 void launch_loss(const float* img, const float* target, int W, int H, int smooth, float* loss, float* dEdp,
                  double* scratch, float* gtmp, hipStream_t st) {
   const double e = 0.60653065971263342;   // exp(-1/2)

@@ -192,8 +192,14 @@ class Stage1:
 
     def __init__(self, ctx: R.Context, mt: ModelTensors, target: torch.Tensor, camera: scenes.Camera, spp: int,
                  params0: torch.Tensor, stage0: np.ndarray, sigma_id: np.ndarray, sigma_alb: np.ndarray, seed: int = 4,
-                 edge_samples: int = -1):
+                 edge_samples: int = -1, landmarks=None, w_land: float = 1.0):
+        """landmarks: (vertex indices [68], film points [68, 2]) for the
+        landmark term E_land (weight alpha_1 = 1, Sec. 5), or None."""
         dev = mt.mean_geo.device
+        self.land = None if landmarks is None else (torch.as_tensor(np.asarray(landmarks[0], np.int32), device=dev),
+                                                     torch.as_tensor(np.asarray(landmarks[1], np.float32), device=dev))
+        self.w_land = w_land
+        self.camera = camera
         self.mt, self.target, self.edge_samples = mt, target, edge_samples
         self.sl = param_slices(mt.K_geo, mt.K_alb, 0)
         self.faces = torch.tensor(scenes.icosahedron_faces(), device=dev)
@@ -254,7 +260,19 @@ class Stage1:
         e_box, _ = R.prior(self.x[K_id:mt.K_geo], R.PRIOR_BOX, 1.0, g=gx[K_id:mt.K_geo])
         e_l, _ = R.prior(sc.light_rad, R.PRIOR_LIGHT_CHROMA, 0.01, g=g["light_rad"])
         gw = R.light_stage_backward(self.faces, self.w, g["light_geom"], g["light_rad"])
-        return E + e_id + e_alb + e_box + e_l, gx, gw
+        total = E + e_id + e_alb + e_box + e_l
+        if self.land is not None:
+            # E_land on the posed vertices, back through pose and blend
+            g_lv = torch.zeros_like(self.v_w)
+            e_land = R.landmark_loss(self.v_w, self.land[0], self.ds.cam, self.ds.fov_y, self.ds.W, self.ds.H,
+                                     self.land[1], gverts=g_lv)
+            if self.w_land != 1.0:
+                g_lv *= self.w_land
+            g_lobj = torch.zeros_like(self.v_obj)
+            R.pose_backward(self.v_obj, self.x[sl["pose"]], g_lv, g_lobj, gx[sl["pose"]])
+            R.blend_backward(mt.basis_geo, g_lobj, gx[sl["geo"]])
+            total = total + self.w_land * e_land
+        return total, gx, gw
 
     def step(self):
         """One Stage I step; returns the objective at the step's parameters."""

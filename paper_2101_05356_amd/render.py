@@ -307,6 +307,16 @@ def map_regularizers(C, S, R, C0, S0, w_sym=0.3, w_chroma=0.3, w_smooth=2e-4, w_
     return (loss, *g)
 
 
+def landmark_loss(verts, idx, cam, fov_y, W, H, z, gverts=None, gcam=None):
+    """Landmark loss (see fr_landmark_loss): returns loss [1]; gverts / gcam
+    (when given) accumulate the gradients."""
+    loss = torch.empty(1, dtype=torch.float32, device=verts.device)
+    check(lib().fr_landmark_loss(_p(verts.contiguous()), _p(idx.contiguous()), int(idx.numel()), _p(cam.contiguous()),
+                                 float(fov_y), int(W), int(H), _p(z.contiguous()), _p(loss), _p(gverts), _p(gcam),
+                                 _stream()), None, "fr_landmark_loss")
+    return loss
+
+
 PRIOR_STATISTICAL, PRIOR_BOX, PRIOR_LIGHT_CHROMA = 0, 1, 2
 
 

@@ -71,3 +71,35 @@ def test_stage1_steps_lower_the_objective(oracle_lib):
     objs = [float(st.step().item()) for _ in range(40)]
     torch.cuda.synchronize()
     assert np.all(np.isfinite(objs)) and np.mean(objs[-5:]) < 0.8 * np.mean(objs[:5]), objs
+
+
+def test_stage1_with_landmarks(oracle_lib):
+    """With 68 synthetic landmarks (projections of the true face's vertices)
+    the landmark term shrinks as the geometry and pose are fitted."""
+    import oracle
+    recon, ctx, mt, cam, n = setup()
+    rng = np.random.default_rng(7)
+    truth = np.concatenate([rng.normal(0, 0.5, n - 6), [0.08, -0.06, 0.04, 0.03, -0.02, 0.02]]).astype(np.float32)
+    stage = scenes.light_stage_params(d=3.0, a=0.05, seed=23)
+    ref = recon.Stage1(ctx, mt, torch.zeros((32, 32, 3), device="cuda"), cam, 4, torch.tensor(truth).cuda(), stage,
+                       np.ones(mt.K_id), np.ones(mt.K_alb))
+    target = G.R.render_forward(ref.mesh, ref.scene(), verts=ref.v_w)
+    v_true = G.to_np(ref.v_w).reshape(-1, 3)
+    front = np.nonzero(v_true[:, 2] > 0.3)[0]
+    idx = np.sort(rng.choice(front, 68, replace=False)).astype(np.int32)
+    camv = np.concatenate([cam.R.reshape(9), cam.T]).astype(np.float64)
+    z = oracle.project(v_true[idx].astype(np.float64), camv, cam.fov_y, 32, 32)
+    start = np.zeros_like(truth)
+    st = recon.Stage1(ctx, mt, target, cam, 4, torch.tensor(start).cuda(), stage, np.ones(mt.K_id), np.ones(mt.K_alb),
+                      landmarks=(idx, z))
+
+    def land():
+        lv = G.R.landmark_loss(st.v_w, st.land[0], st.ds.cam, cam.fov_y, 32, 32, st.land[1])
+        return float(lv.item())
+
+    l0 = land()
+    for _ in range(40):
+        st.step()
+    st._geometry()
+    torch.cuda.synchronize()
+    assert land() < 0.5 * l0, (l0, land())
