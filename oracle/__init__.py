@@ -79,6 +79,10 @@ def lib():
         L.oracle_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int32,
                                   ctypes.c_int32, P]
         L.oracle_edge_grad.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_int32]
+        L.oracle_shadow_jumps.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                          P, P, P, P, P]
+        L.oracle_shadow_jumps.restype = ctypes.c_int32
+        L.oracle_shadow_edge_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, ctypes.c_int32]
         L.oracle_edge_count.argtypes = [P]
         L.oracle_edge_count.restype = ctypes.c_int32
         L.oracle_camera_ray.argtypes = [P, ctypes.c_double, ctypes.c_double, P]
@@ -261,6 +265,41 @@ def edge_grad(scene, dEdp_full, n_samples, select=None, brdf_variant=0, componen
     lib().oracle_edge_grad(b.ref, int(n_samples), n_sel, _ptr(sel), _ptr(g), _ptr(gv), _ptr(gc), _ptr(edge),
                            _ptr(flag), _ptr(ltot), nthreads or default_threads())
     return dict(verts=gv, cam=gc, edge=edge, flag=flag, ltot=float(ltot[0]))
+
+
+def shadow_edge_grad(scene, dEdp_full, n_samples, brdf_variant=0, components=3, nthreads=None):
+    """Shadow-edge (secondary visibility) boundary term from n_samples line
+    samples (camera sample, light, line w2 = v across the light).  Returns
+    dict: verts [N,3], light [L,9] (p0, e1, e2), cam [12], rec [n,4] (camera
+    sample, light, jumps, edge-key sum), flag [n]."""
+    b = _Bound(scene, brdf_variant, components)
+    N, L = scene.n_verts, scene.lights.count
+    g = np.ascontiguousarray(np.asarray(dEdp_full, dtype=np.float64).reshape(-1, 3))
+    gv = np.zeros((N, 3))
+    gl = np.zeros((max(L, 1), 9))
+    gc = np.zeros(12)
+    rec = np.zeros((n_samples, 4), np.int32)
+    flag = np.zeros(n_samples, np.uint8)
+    lib().oracle_shadow_edge_grad(b.ref, int(n_samples), _ptr(g), _ptr(gv), _ptr(gl), _ptr(gc), _ptr(rec),
+                                  _ptr(flag), nthreads or default_threads())
+    return dict(verts=gv, light=gl[:L], cam=gc, rec=rec, flag=flag)
+
+
+def shadow_jumps(scene, x, self_tri, light, v, cap=64):
+    """Jumps of the visibility along the line w2 = v of `light` seen from
+    point x (triangle self_tri never occludes).  Returns dict: w1 [k], J [k]
+    (V(w1-) - V(w1+)), edge [k,2] (vertex ids), grad [k,18] (dw1 / d(a, b,
+    x, p0, e1, e2)), flags."""
+    b = _Bound(scene)
+    w1 = np.zeros(cap)
+    J = np.zeros(cap, np.int32)
+    edge = np.zeros((cap, 2), np.int32)
+    grad = np.zeros((cap, 18))
+    fl = np.zeros(1, np.uint8)
+    n = lib().oracle_shadow_jumps(b.ref, _ptr(_d3(x)), int(self_tri), int(light), float(v), cap, _ptr(w1), _ptr(J),
+                                  _ptr(edge), _ptr(grad), _ptr(fl))
+    n = min(n, cap)
+    return dict(w1=w1[:n], J=J[:n], edge=edge[:n], grad=grad[:n], flags=int(fl[0]))
 
 
 # ---------------------------------------------------------------------------

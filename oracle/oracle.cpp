@@ -1141,6 +1141,321 @@ int32_t oracle_edge_count(const OrScene* sc) { return (int32_t)build_edges(*sc).
 
 }  // extern "C"
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// Shadow-edge (secondary visibility) boundary term, Sec. 4 "Edge Sampling":
+// the gradient must include the visibility discontinuities, and those of the
+// shadow rays (Sec. 3.3) lie on the lights.  Light j seen from the shading
+// point x contributes I = kappa^-1 int int h(w1, w2) V(x, y) dw1 dw2 over the
+// light's parameter domain (unit square; triangle: w1 + w2 <= 1), y = p0 +
+// w1 e1 + w2 e2, h the render's per-sample value of the light at y (pdf 1/A,
+// A = kappa |e1 x e2|).  On the line w2 = v the visibility V is piecewise
+// constant in w1, so d/dtheta of the inner integral is the interior term plus
+// sum_k h(w1_k) J_k dw1_k/dtheta over the jumps w1_k, J_k = V(w1_k-) -
+// V(w1_k+) (Leibniz).  A jump is where an occluder edge (a, b) crosses the
+// wedge {x + tau (y(w1, v) - x)}, the edge's faces (other than the shading
+// point's own triangle, which never occludes) all lie on one side as seen
+// from x, and no other triangle blocks x -> y(w1_k).  Its position solves
+// D(w1) = det[a - x, b - x, y(w1, v) - x] = 0, linear in w1; implicit
+// differentiation gives dw1/dtheta = -(dD/dtheta) / (dD/dw1).
+// ---------------------------------------------------------------------------
+constexpr uint32_t PURPOSE_SHADOW_EDGE = 0xC0000000u;
+
+// Index in [0, n) from 32 random bits, floor(r n / 2^32), and its exact
+// probability (the number of r mapping to i, over 2^32).
+inline int64_t pick_index(uint32_t r, int64_t n) { return (int64_t)(((uint64_t)r * (uint64_t)n) >> 32); }
+inline double pick_prob(int64_t i, int64_t n) {
+  const auto cdiv = [n](uint64_t x) { return (x + (uint64_t)n - 1) / (uint64_t)n; };
+  return (double)(cdiv((uint64_t)(i + 1) << 32) - cdiv((uint64_t)i << 32)) * (1.0 / 4294967296.0);
+}
+
+// Neighbour of triangle f across its edge k (tris[3f+k], tris[3f+(k+1)%3]), -1 if none.
+std::vector<int> face_neighbours(const OrScene& sc) {
+  const EdgeList E = build_edges(sc);
+  std::map<std::pair<int, int>, int> id;
+  for (size_t e = 0; e < E.a.size(); ++e) id[{E.a[e], E.b[e]}] = (int)e;
+  std::vector<int> nb(3 * (size_t)sc.n_tris, -1);
+  for (int f = 0; f < sc.n_tris; ++f)
+    for (int k = 0; k < 3; ++k) {
+      int i = sc.tris[3 * f + k], j = sc.tris[3 * f + (k + 1) % 3];
+      if (i > j) std::swap(i, j);
+      const int e = id[{i, j}];
+      nb[3 * f + k] = E.f0[e] == f ? E.f1[e] : E.f0[e];
+    }
+  return nb;
+}
+
+// Occlusion of o + t d, t in (tmin, tmax), by any triangle but ex[0..2].
+bool occluded3(const std::vector<TriGeo>& tg, const V3& o, const V3& d, double tmin, double tmax, const int ex[3],
+               uint8_t* flags) {
+  bool occ = false;
+  for (int f = 0; f < (int)tg.size(); ++f) {
+    if (f == ex[0] || f == ex[1] || f == ex[2]) continue;
+    if (!may_touch(o, d, tmin, tmax, tg[f], 1e-5)) continue;
+    const Crossing c = cross_plane(o, d, tg[f]);
+    if (inside(c) && c.t > tmin && c.t < tmax) occ = true;
+    if (near_boundary(o, d, tmin, tmax, tg[f])) *flags |= FLAG_EDGE;
+    if (inside(c) && (std::fabs(c.t - tmin) < kFlagEps || std::fabs(c.t - tmax) < kFlagEps)) *flags |= FLAG_TRANGE;
+  }
+  return occ;
+}
+
+// One jump of V along the line w2 = v of light j, seen from x.
+struct ShadowJump { int a, b, f0, f1; int J; double w1; };
+
+// Jumps of V(x, y(w1, v)), w1 in (0, l), l = 1 (parallelogram) or 1 - v
+// (triangle), with `self` the shading point's triangle (never an occluder),
+// in increasing w1 (ties by edge).  Every near-ambiguous decision sets a bit
+// of *flags.
+std::vector<ShadowJump> shadow_jumps(const OrScene& sc, const std::vector<TriGeo>& tg, const std::vector<int>& nb,
+                                     const V3& x, int self, int j, double v, uint8_t* flags) {
+  std::vector<ShadowJump> out;
+  const LightParams<double> L = light_params_d(sc, j);
+  if (L.shape == 2) return out;
+  const double ell = L.shape == 1 ? 1.0 - v : 1.0;
+  const V3 y0 = L.p0 + L.e2 * v, y1 = y0 + L.e1 * ell;
+  const V3 Nw = cross(y0 - x, y1 - x);
+  const double nN = norm(Nw);
+  if (!(nN > 0.0)) return out;
+  const auto sgn = [&](int vi) { return dot(Nw, load3(sc.verts, vi) - x); };
+  const auto near_plane = [&](double s) { return std::fabs(s) < kFlagEps * nN; };
+  // side (+1: towards larger w1) of face f, whose edge (a, b) crosses the
+  // plane at P: the direction from P to the face's other crossing, seen from x
+  const auto side = [&](int f, int ia, int ib, const V3& P) -> int {
+    int ic = -1;
+    for (int k = 0; k < 3; ++k) {
+      const int t = sc.tris[3 * f + k];
+      if (t != ia && t != ib) ic = t;
+    }
+    const double sa = sgn(ia), sb = sgn(ib), sc_ = sgn(ic);
+    if (near_plane(sc_)) *flags |= FLAG_EDGE;
+    const V3 A = load3(sc.verts, ia), B = load3(sc.verts, ib), C = load3(sc.verts, ic);
+    const bool with_a = (sc_ > 0.0) == (sa > 0.0);        // c on a's side: the other crossing is on (b, c)
+    const V3 Q = with_a ? B + (C - B) * (sb / (sb - sc_)) : A + (C - A) * (sa / (sa - sc_));
+    const double o = dot(cross(P - x, Q - x), Nw);
+    if (std::fabs(o) < kFlagEps * norm(P - x) * norm(Q - P) * nN) *flags |= FLAG_EDGE;
+    return o > 0.0 ? 1 : -1;
+  };
+  for (int f = 0; f < sc.n_tris; ++f)
+    for (int k = 0; k < 3; ++k) {
+      const int g = nb[3 * f + k];
+      if (g >= 0 && g < f) continue;                      // each edge once, from its lower face
+      int ia = sc.tris[3 * f + k], ib = sc.tris[3 * f + (k + 1) % 3];
+      if (ia > ib) std::swap(ia, ib);
+      const double sa = sgn(ia), sb = sgn(ib);
+      // an end on the wedge plane is flagged once the crossing is in range
+      // (below); an edge with no crossing and an end near the plane is
+      // flagged when that end lies inside the wedge's range
+      const V3 A = load3(sc.verts, ia), B = load3(sc.verts, ib);
+      if (near_plane(sa) || near_plane(sb)) {
+        // E - x ~ alpha (y0 - x) + beta (y1 - x) (least squares): in front of
+        // x and within the line's span, with a margin
+        const V3 E = near_plane(sa) ? A : B, u0 = y0 - x, u1 = y1 - x, e = E - x;
+        const double g00 = dot(u0, u0), g01 = dot(u0, u1), g11 = dot(u1, u1);
+        const double r0 = dot(u0, e), r1 = dot(u1, e), det = g00 * g11 - g01 * g01;
+        const double al = (g11 * r0 - g01 * r1) / det, be = (g00 * r1 - g01 * r0) / det;
+        const double tot = al + be;
+        if (tot > 0.0 && be > -0.01 * tot && be < 1.01 * tot && tot < 1.01) *flags |= FLAG_EDGE;
+      }
+      if (!((sa > 0.0 && sb < 0.0) || (sa < 0.0 && sb > 0.0))) continue;
+      const V3 P = A + (B - A) * (sa / (sa - sb));
+      const V3 ax = A - x, bx = B - x, nab = cross(ax, bx);
+      const double D1 = dot(nab, L.e1);
+      if (D1 == 0.0) continue;
+      const double w1 = -dot(nab, y0 - x) / D1;
+      const V3 yk = L.p0 + L.e1 * w1 + L.e2 * v;
+      const V3 dy = yk - x;
+      const double dist = norm(dy);
+      const double tau = dot(P - x, dy) / (dist * dist);
+      if (!(tau > 0.0)) continue;
+      const double dP = tau * dist;
+      const bool in_w = w1 > 0.0 && w1 < ell, in_t = dP > kShadowTmin && tau < 1.0;
+      const bool near_w = std::fabs(w1) < kFlagEps || std::fabs(w1 - ell) < kFlagEps;
+      const bool near_t = std::fabs(dP - kShadowTmin) < kFlagEps || std::fabs(dist - dP) < kFlagEps;
+      if (near_w || near_t) *flags |= FLAG_TRANGE;
+      if (!(in_w && in_t)) continue;
+      int faces[2] = {f, g}, n = 0, right = 0;
+      for (int q = 0; q < 2; ++q) {
+        if (faces[q] < 0 || faces[q] == self) continue;
+        ++n;
+        right += side(faces[q], ia, ib, P) > 0 ? 1 : 0;
+      }
+      if (n == 0 || (right != 0 && right != n)) continue;   // no face, or faces on both sides
+      const int ex[3] = {f, g, self};
+      const V3 l = dy * (1.0 / dist);
+      if (occluded3(tg, x, l, kShadowTmin, dist, ex, flags)) continue;
+      out.push_back({ia, ib, f, g, right == n ? 1 : -1, w1});
+    }
+  std::sort(out.begin(), out.end(), [](const ShadowJump& p, const ShadowJump& q) {
+    return p.w1 < q.w1 || (p.w1 == q.w1 && (p.a < q.a || (p.a == q.a && p.b < q.b)));
+  });
+  return out;
+}
+
+// dw1/dtheta of a jump, theta = (a, b, x, p0, e1, e2) as 18 directional
+// derivatives, from D(w1) = det[a - x, b - x, p0 + w1 e1 + v e2 - x] = 0.
+using D18 = Dual<18>;
+void jump_gradient(const V3& a, const V3& b, const Vec3<D18>& x, const LightParams<double>& L, double v,
+                   D18* w1_out) {
+  const Vec3<D18> A(D18::seed(a.x, 0), D18::seed(a.y, 1), D18::seed(a.z, 2));
+  const Vec3<D18> B(D18::seed(b.x, 3), D18::seed(b.y, 4), D18::seed(b.z, 5));
+  const Vec3<D18> p0(D18::seed(L.p0.x, 9), D18::seed(L.p0.y, 10), D18::seed(L.p0.z, 11));
+  const Vec3<D18> e1(D18::seed(L.e1.x, 12), D18::seed(L.e1.y, 13), D18::seed(L.e1.z, 14));
+  const Vec3<D18> e2(D18::seed(L.e2.x, 15), D18::seed(L.e2.y, 16), D18::seed(L.e2.z, 17));
+  const Vec3<D18> nab = cross(A - x, B - x);
+  *w1_out = -(dot(nab, p0 + e2 * D18(v) - x) / dot(nab, e1));
+}
+
+}  // namespace
+
+extern "C" {
+
+// Jumps of the visibility along the line w2 = v of light j seen from point x
+// (triangle `self` excluded as an occluder): returns their count; up to cap
+// of them are written as w1[k], J[k], edge[2k..2k+1] (vertex ids, lower
+// first) and grad[18k..18k+17] = dw1/d(a, b, x, p0, e1, e2).  *flags gets
+// the ambiguity bits.  A probe for the oracle's own pins.
+int32_t oracle_shadow_jumps(const OrScene* sc, const double* xp, int32_t self, int32_t j, double v, int32_t cap,
+                            double* w1, int32_t* J, int32_t* edge, double* grad, uint8_t* flags) {
+  const std::vector<TriGeo> tg = tri_geometry(*sc);
+  const std::vector<int> nb = face_neighbours(*sc);
+  const V3 x(xp[0], xp[1], xp[2]);
+  uint8_t fl = 0;
+  const std::vector<ShadowJump> js = shadow_jumps(*sc, tg, nb, x, self, j, v, &fl);
+  const LightParams<double> L = light_params_d(*sc, j);
+  const Vec3<D18> X(D18::seed(x.x, 6), D18::seed(x.y, 7), D18::seed(x.z, 8));
+  for (int k = 0; k < (int)js.size() && k < cap; ++k) {
+    w1[k] = js[k].w1;
+    J[k] = js[k].J;
+    edge[2 * k] = js[k].a;
+    edge[2 * k + 1] = js[k].b;
+    if (grad) {
+      D18 w;
+      jump_gradient(load3(sc->verts, js[k].a), load3(sc->verts, js[k].b), X, L, v, &w);
+      for (int q = 0; q < 18; ++q) grad[18 * k + q] = w.d[q];
+    }
+  }
+  if (flags) *flags = fl;
+  return (int32_t)js.size();
+}
+
+// Shadow-edge boundary term of sum_p dEdp[p] . rgb[p] (dEdp [H*W*3]) from
+// n_samples line samples: sample i draws, from Philox counter (i, 0,
+// 0xC0000000, step), a camera sample (pixel y*W + x, sample s) uniformly
+// over the W*H*S of them (word 0), a light uniformly (word 1) and the line
+// w2 = v (word 2, 24 bits), and contributes, per jump,
+//   kappa^-1 (1/S) (dEdp . h(w1_k, v)) J_k dw1_k/dtheta / (n_samples p_ps p_j)
+// with p_ps, p_j the exact probabilities of the two draws.  The shading
+// point x is the camera ray's hit, a function of the hit triangle and the
+// camera (Sec. 3.1), as in the render.  Accumulated (+=): g_verts [N*3],
+// g_light [L*9] (p0, e1, e2), g_cam [12].  rec [n*4] = (camera sample,
+// light, jumps that passed the occlusion test, sum of their lower vertex ids
+// * N + upper ids mod 2^31); flag [n] the ambiguity bits (camera ray, edge
+// tests, occlusion tests, cosines at the jump points).
+int oracle_shadow_edge_grad(const OrScene* sc, int32_t n_samples, const double* dEdp, double* g_verts,
+                            double* g_light, double* g_cam, int32_t* rec, uint8_t* flag_out, int32_t nthreads) {
+  const Prepared P = prepare(sc);
+  const OrScene& s = *sc;
+  const std::vector<int> nb = face_neighbours(s);
+  const int N = s.n_verts, L = s.n_lights, W = s.width, S = s.spp;
+  const int64_t n_cs = (int64_t)W * s.height * S;
+  if (n_samples <= 0) return 0;
+  nthreads = std::max(1, std::min<int>(nthreads, n_samples));
+  std::vector<std::vector<double>> gv(nthreads, std::vector<double>(3 * (size_t)N, 0.0)),
+      gl(nthreads, std::vector<double>(9 * (size_t)std::max(L, 1), 0.0)), gc(nthreads, std::vector<double>(12, 0.0));
+  parallel_for(n_samples, nthreads, [&](int i, int th) {
+    const Rand4 r = philox4x32_10((uint32_t)i, 0u, PURPOSE_SHADOW_EDGE, s.step, s.seed);
+    const int64_t cs = pick_index(r.x[0], n_cs);
+    const int j = L > 0 ? (int)pick_index(r.x[1], L) : -1;
+    const double v = unit24(r.x[2]);
+    int32_t* rr = rec ? rec + 4 * (size_t)i : nullptr;
+    if (rr) { rr[0] = (int32_t)cs; rr[1] = j; rr[2] = 0; rr[3] = 0; }
+    uint8_t fl = 0;
+    const auto done = [&]() { if (flag_out) flag_out[i] = fl; };
+    if (j < 0 || s.light_shape[j] == 2) { done(); return; }
+    const int pid = (int)(cs / S), smp = (int)(cs % S);
+    const int px = pid % W, py = pid / W;
+    const Rand4 rj = philox4x32_10((uint32_t)pid, (uint32_t)smp, PURPOSE_JITTER, s.step, s.seed);
+    const double fx = px + unit24(rj.x[0]), fy = py + unit24(rj.x[1]);
+    const V3 d = normalize(mul3(P.R, film_dir(P.cc, fx, fy)));
+    const HitResult h = closest_hit(P.tg, P.T, d);
+    fl |= h.flags;
+    if (h.id < 0) { done(); return; }
+    const SampleParams<double> sp = sample_params_d(P, h.id);
+    const Frame<double> fr = shading_frame(sp, P.cc, fx, fy);
+    const double cos_o = dot(fr.ns, fr.wo);
+    if (std::fabs(cos_o) < kFlagEps) fl |= FLAG_COSO;
+    if (!(cos_o > 0.0)) { done(); return; }
+    const std::vector<ShadowJump> js = shadow_jumps(s, P.tg, nb, fr.x, h.id, j, v, &fl);
+    if (js.empty()) { done(); return; }
+    // the shading point as a function of the hit triangle and the camera
+    using D36 = Dual<36>;
+    SampleParams<D36> spd;
+    for (int k = 0; k < 3; ++k) {
+      spd.v[k] = Vec3<D36>(D36::seed(sp.v[k].x, 3 * k), D36::seed(sp.v[k].y, 3 * k + 1), D36::seed(sp.v[k].z, 3 * k + 2));
+      spd.n[k] = Vec3<D36>(D36(sp.n[k].x), D36(sp.n[k].y), D36(sp.n[k].z));
+      spd.c[k] = Vec3<D36>(D36(sp.c[k].x), D36(sp.c[k].y), D36(sp.c[k].z));
+      spd.s[k] = Vec3<D36>(D36(sp.s[k].x), D36(sp.s[k].y), D36(sp.s[k].z));
+      spd.r[k] = D36(0.5);
+    }
+    for (int q = 0; q < 9; ++q) spd.R[q] = D36::seed(P.R[q], 9 + q);
+    spd.T = Vec3<D36>(D36::seed(P.T.x, 18), D36::seed(P.T.y, 19), D36::seed(P.T.z, 20));
+    const Vec3<D36> xd = shading_frame(spd, P.cc, fx, fy).x;
+    // x's 18-slot seeds for jump_gradient carry x's own value; its slots 6..8
+    // are chained below through dx/d(triangle, camera)
+    const Vec3<D18> X(D18::seed(xd.x.v, 6), D18::seed(xd.y.v, 7), D18::seed(xd.z.v, 8));
+    const LightParams<double> Lp = light_params_d(s, j);
+    const double kinv = Lp.shape == 1 ? 2.0 : 1.0;
+    const double wgt = 1.0 / ((double)n_samples * pick_prob(cs, n_cs) * pick_prob(j, L));
+    int n_ok = 0;
+    int64_t key = 0;
+    for (const ShadowJump& q : js) {
+      ++n_ok;
+      key = (key + (int64_t)q.a * N + q.b) % 2147483648LL;
+      // h at the jump: the render's value of the light sample there (cosine
+      // culls included), with the ambiguity bits of its tests
+      const V3 yk = Lp.p0 + Lp.e1 * q.w1 + Lp.e2 * v;
+      const V3 dy = yk - fr.x;
+      const V3 l = dy * (1.0 / norm(dy));
+      const double cs_ = dot(fr.ns, l), cl = -dot(normalize(cross(Lp.e1, Lp.e2)), l);
+      if (std::fabs(cs_) < kFlagEps || std::fabs(cl) < kFlagEps) fl |= FLAG_COSL;
+      if (!(cs_ > 0.0 && cl > 0.0)) continue;
+      const Vec3<double> hv = light_contribution(fr, Lp, q.w1, v, VIS_VISIBLE, s.brdf_variant, s.components, &fl);
+      const double* g = dEdp + 3 * (size_t)pid;
+      const double coef = wgt * kinv / S * q.J * (g[0] * hv.x + g[1] * hv.y + g[2] * hv.z);
+      if (coef == 0.0) continue;
+      D18 w;
+      jump_gradient(load3(s.verts, q.a), load3(s.verts, q.b), X, Lp, v, &w);
+      for (int c = 0; c < 3; ++c) {
+        gv[th][3 * (size_t)q.a + c] += coef * w.d[c];
+        gv[th][3 * (size_t)q.b + c] += coef * w.d[3 + c];
+        gl[th][9 * (size_t)j + c] += coef * w.d[9 + c];
+        gl[th][9 * (size_t)j + 3 + c] += coef * w.d[12 + c];
+        gl[th][9 * (size_t)j + 6 + c] += coef * w.d[15 + c];
+      }
+      // chain dw1/dx through x(triangle, camera)
+      const double gx[3] = {coef * w.d[6], coef * w.d[7], coef * w.d[8]};
+      const D36* xc[3] = {&xd.x, &xd.y, &xd.z};
+      for (int c = 0; c < 3; ++c) {
+        for (int k = 0; k < 3; ++k)
+          for (int e = 0; e < 3; ++e) gv[th][3 * (size_t)s.tris[3 * h.id + k] + e] += gx[c] * xc[c]->d[3 * k + e];
+        for (int q2 = 0; q2 < 12; ++q2) gc[th][q2] += gx[c] * xc[c]->d[9 + q2];
+      }
+    }
+    if (rr) { rr[2] = n_ok; rr[3] = (int32_t)key; }
+    done();
+  });
+  for (int t = 0; t < nthreads; ++t) {
+    for (size_t k = 0; k < 3 * (size_t)N; ++k) g_verts[k] += gv[t][k];
+    for (size_t k = 0; k < 9 * (size_t)L; ++k) g_light[k] += gl[t][k];
+    for (int k = 0; k < 12; ++k) g_cam[k] += gc[t][k];
+  }
+  return 0;
+}
+
+}  // extern "C"
+
 // ---------------------------------------------------------------------------
 // Probes of single stages, used by the oracle's own pins.
 // ---------------------------------------------------------------------------
