@@ -295,6 +295,32 @@ int fr_map_regularizers(const float* d_c, const float* d_s, const float* d_r, co
 int fr_render_backward(fr_mesh* mesh, const fr_scene* scene, const fr_render_opts* opts, const float* d_dEdp,
                        fr_grads* grads, fr_stream stream);
 
+/* Shadow-edge (secondary visibility) boundary term of the adjoint (Sec. 4
+ * "Edge Sampling", for the visibility of the shadow rays of Sec. 3.3):
+ * n_samples line samples, accumulated (+=) into grads->verts, ->light_geom
+ * and ->cam (the other fields are ignored; each pointer nullable).  Light j
+ * seen from a shading point x contributes kappa^-1 int int h V dw1 dw2 over
+ * its parameters (y = p0 + w1 e1 + w2 e2; kappa = 1 parallelogram, 1/2
+ * triangle; h the render's per-sample light value).  Sample i draws, from
+ * Philox counter (i, 0, 0xC0000000, step), a camera sample uniformly over the
+ * W*H*spp (word 0: floor(r n / 2^32)), a light uniformly (word 1) and a line
+ * w2 = v (word 2, 24 bits), traces the camera ray, and adds, for each jump
+ * w1_k of V along the line (an occluder edge crossing the wedge from x to the
+ * line, its faces other than x's triangle on one side as seen from x, the
+ * shadow ray to y(w1_k, v) otherwise free), kappa^-1 (1/spp) (dEdp[pixel] .
+ * h) J_k dw1_k/dtheta / (n_samples p), J_k = V(w1_k-) - V(w1_k+), p the
+ * exact probability of the two draws.  Lights at infinity contribute nothing
+ * here (their shadows are hard: a screen-space term, not built).  Manifold
+ * meshes (an edge with more than two faces is not supported).  Call after
+ * fr_render_forward of the same scene (the traversal uses its tree).
+ * d_dEdp [H*W*3] device.  d_rec [n*4] / d_flag [n] (nullable, together):
+ * per sample (camera sample, light, jumps that passed the occlusion test,
+ * sum of their edges' lower vertex id * N + upper id, mod 2^31) and 1 when a
+ * decision was near-ambiguous.  Requires W*H*spp < 2^31 (FR_ERR_LIMIT).
+ * Uses the mesh's internal scratch; calls on one mesh must not overlap. */
+int fr_shadow_edges(fr_mesh* mesh, const fr_scene* scene, const fr_render_opts* opts, const float* d_dEdp,
+                    int32_t n_samples, fr_grads* grads, int32_t* d_rec, uint8_t* d_flag, fr_stream stream);
+
 /* Morphable blend (Sec. 3.1, Sec. 3.2): d_out[m] = d_mean[m] + sum_k
  * d_coef[k] d_basis[k*M + m], m < M, with the basis stored component-major
  * ([K][M]).  Geometry: mean = a_s, basis = [Sigma_s; Sigma_e], coef =

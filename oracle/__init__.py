@@ -82,7 +82,7 @@ def lib():
         L.oracle_shadow_jumps.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                           P, P, P, P, P]
         L.oracle_shadow_jumps.restype = ctypes.c_int32
-        L.oracle_shadow_edge_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, ctypes.c_int32]
+        L.oracle_shadow_edge_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32]
         L.oracle_edge_count.argtypes = [P]
         L.oracle_edge_count.restype = ctypes.c_int32
         L.oracle_camera_ray.argtypes = [P, ctypes.c_double, ctypes.c_double, P]
@@ -267,11 +267,12 @@ def edge_grad(scene, dEdp_full, n_samples, select=None, brdf_variant=0, componen
     return dict(verts=gv, cam=gc, edge=edge, flag=flag, ltot=float(ltot[0]))
 
 
-def shadow_edge_grad(scene, dEdp_full, n_samples, brdf_variant=0, components=3, nthreads=None):
+def shadow_edge_grad(scene, dEdp_full, n_samples, brdf_variant=0, components=3, nthreads=None, abs_terms=False):
     """Shadow-edge (secondary visibility) boundary term from n_samples line
     samples (camera sample, light, line w2 = v across the light).  Returns
     dict: verts [N,3], light [L,9] (p0, e1, e2), cam [12], rec [n,4] (camera
-    sample, light, jumps, edge-key sum), flag [n]."""
+    sample, light, jumps, edge-key sum), flag [n].  abs_terms: the sums of the
+    terms' magnitudes instead (the condition measure of each element)."""
     b = _Bound(scene, brdf_variant, components)
     N, L = scene.n_verts, scene.lights.count
     g = np.ascontiguousarray(np.asarray(dEdp_full, dtype=np.float64).reshape(-1, 3))
@@ -281,7 +282,7 @@ def shadow_edge_grad(scene, dEdp_full, n_samples, brdf_variant=0, components=3, 
     rec = np.zeros((n_samples, 4), np.int32)
     flag = np.zeros(n_samples, np.uint8)
     lib().oracle_shadow_edge_grad(b.ref, int(n_samples), _ptr(g), _ptr(gv), _ptr(gl), _ptr(gc), _ptr(rec),
-                                  _ptr(flag), nthreads or default_threads())
+                                  _ptr(flag), nthreads or default_threads(), int(bool(abs_terms)))
     return dict(verts=gv, light=gl[:L], cam=gc, rec=rec, flag=flag)
 
 

@@ -1354,7 +1354,11 @@ int32_t oracle_shadow_jumps(const OrScene* sc, const double* xp, int32_t self, i
 // * N + upper ids mod 2^31); flag [n] the ambiguity bits (camera ray, edge
 // tests, occlusion tests, cosines at the jump points).
 int oracle_shadow_edge_grad(const OrScene* sc, int32_t n_samples, const double* dEdp, double* g_verts,
-                            double* g_light, double* g_cam, int32_t* rec, uint8_t* flag_out, int32_t nthreads) {
+                            double* g_light, double* g_cam, int32_t* rec, uint8_t* flag_out, int32_t nthreads,
+                            int32_t abs_terms) {
+  // abs_terms != 0: accumulate the magnitude of every term instead (the
+  // condition measure of each element's sum; a test tolerance, not a gradient)
+  const auto T = [abs_terms](double x) { return abs_terms ? std::fabs(x) : x; };
   const Prepared P = prepare(sc);
   const OrScene& s = *sc;
   const std::vector<int> nb = face_neighbours(s);
@@ -1428,19 +1432,19 @@ int oracle_shadow_edge_grad(const OrScene* sc, int32_t n_samples, const double* 
       D18 w;
       jump_gradient(load3(s.verts, q.a), load3(s.verts, q.b), X, Lp, v, &w);
       for (int c = 0; c < 3; ++c) {
-        gv[th][3 * (size_t)q.a + c] += coef * w.d[c];
-        gv[th][3 * (size_t)q.b + c] += coef * w.d[3 + c];
-        gl[th][9 * (size_t)j + c] += coef * w.d[9 + c];
-        gl[th][9 * (size_t)j + 3 + c] += coef * w.d[12 + c];
-        gl[th][9 * (size_t)j + 6 + c] += coef * w.d[15 + c];
+        gv[th][3 * (size_t)q.a + c] += T(coef * w.d[c]);
+        gv[th][3 * (size_t)q.b + c] += T(coef * w.d[3 + c]);
+        gl[th][9 * (size_t)j + c] += T(coef * w.d[9 + c]);
+        gl[th][9 * (size_t)j + 3 + c] += T(coef * w.d[12 + c]);
+        gl[th][9 * (size_t)j + 6 + c] += T(coef * w.d[15 + c]);
       }
       // chain dw1/dx through x(triangle, camera)
       const double gx[3] = {coef * w.d[6], coef * w.d[7], coef * w.d[8]};
       const D36* xc[3] = {&xd.x, &xd.y, &xd.z};
       for (int c = 0; c < 3; ++c) {
         for (int k = 0; k < 3; ++k)
-          for (int e = 0; e < 3; ++e) gv[th][3 * (size_t)s.tris[3 * h.id + k] + e] += gx[c] * xc[c]->d[3 * k + e];
-        for (int q2 = 0; q2 < 12; ++q2) gc[th][q2] += gx[c] * xc[c]->d[9 + q2];
+          for (int e = 0; e < 3; ++e) gv[th][3 * (size_t)s.tris[3 * h.id + k] + e] += T(gx[c] * xc[c]->d[3 * k + e]);
+        for (int q2 = 0; q2 < 12; ++q2) gc[th][q2] += T(gx[c] * xc[c]->d[9 + q2]);
       }
     }
     if (rr) { rr[2] = n_ok; rr[3] = (int32_t)key; }

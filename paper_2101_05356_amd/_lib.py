@@ -102,6 +102,7 @@ SIGNATURES = {
     "fr_render_forward": ([P, P, P, P, P], ctypes.c_int),
     "fr_loss": ([P, P, _i32, _i32, _i32, P, P, P], ctypes.c_int),
     "fr_render_backward": ([P, P, P, P, P, P], ctypes.c_int),
+    "fr_shadow_edges": ([P, P, P, P, ctypes.c_int32, P, P, P, P], ctypes.c_int),
     "fr_blend": ([P, P, P, _i32, _i32, P, P], ctypes.c_int),
     "fr_blend_backward": ([P, P, _i32, _i32, P, P], ctypes.c_int),
     "fr_pose_forward": ([P, _i32, P, P, P], ctypes.c_int),

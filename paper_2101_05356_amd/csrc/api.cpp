@@ -256,6 +256,25 @@ int mesh_from_topology(fr_ctx* ctx, const HostTopo& t, fr_mesh** out) {
        hipMemcpy(d.edges, t.edges.data(), sizeof(int32_t) * 2 * d.E, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(d.edge_faces, t.edge_faces.data(), sizeof(int32_t) * 2 * d.E, hipMemcpyHostToDevice) == hipSuccess;
   if (!ok) { fr_mesh_destroy(m); return fail(ctx, FR_ERR_DEVICE, "mesh upload failed"); }
+  // face across each edge of each face (the shadow-edge term's adjacency)
+  std::vector<int32_t> nbr(3 * (size_t)F, -1);
+  for (size_t e = 0; e < t.edges.size() / 2; ++e) {
+    const int a = t.edges[2 * e], b = t.edges[2 * e + 1];
+    const int fs[2] = {t.edge_faces[2 * e], t.edge_faces[2 * e + 1]};
+    for (int q = 0; q < 2; ++q) {
+      const int f = fs[q];
+      if (f < 0) continue;
+      for (int k = 0; k < 3; ++k) {
+        const int i = t.tris[3 * (size_t)f + k], j = t.tris[3 * (size_t)f + (k + 1) % 3];
+        if ((i == a && j == b) || (i == b && j == a)) nbr[3 * (size_t)f + k] = fs[1 - q];
+      }
+    }
+  }
+  if (dalloc(&d.face_nbr, 3 * (size_t)F) != hipSuccess ||
+      hipMemcpy(d.face_nbr, nbr.data(), sizeof(int32_t) * 3 * F, hipMemcpyHostToDevice) != hipSuccess) {
+    fr_mesh_destroy(m);
+    return fail(ctx, FR_ERR_DEVICE, "mesh upload failed");
+  }
   *out = m;
   return FR_OK;
 }
@@ -308,7 +327,7 @@ int fr_mesh_create(fr_ctx* ctx, int32_t n_verts, int32_t n_tris, const int32_t* 
 int fr_mesh_destroy(fr_mesh* m) {
   if (!m) return FR_OK;
   fr::MeshDev& d = m->d;
-  void* ptrs[] = {d.tris, d.vf_off, d.vf_idx, d.normals, d.nlen, d.gnorm, d.edges, d.edge_faces, d.nodes, d.recs,
+  void* ptrs[] = {d.tris, d.vf_off, d.vf_idx, d.normals, d.nlen, d.gnorm, d.edges, d.edge_faces, d.face_nbr, d.se_acc, d.nodes, d.recs,
                   d.order, d.node_parent, d.leaf_parent, d.flags, d.keys[0], d.keys[1], d.vals[0], d.vals[1],
                   d.hist, d.partial, d.scene_box, d.depth, d.lights, d.ltmp, d.edge_len, d.edge_cdf, d.face_front,
                   d.scan_part, d.img_partial, d.prim, d.vis, d.acc, d.tex_acc, d.slots, d.nodes4, d.n4_src, d.top_nodes, d.top_level_off, m->loss_scratch, m->loss_gtmp};
@@ -607,6 +626,49 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
   if (fg.tex_s) fr::launch_fix_to_float(fg.tex_s, g->tex_specular, (int)(3 * MM), st);
   if (fg.tex_r) fr::launch_fix_to_float(fg.tex_r, g->tex_roughness, (int)MM, st);
   if (g->cam) fr::launch_fix_to_float(acc_cam, g->cam, 12, st);
+  FR_HIP(m->ctx, hipGetLastError());
+  return FR_OK;
+}
+
+int fr_shadow_edges(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, const float* d_dEdp, int32_t n_samples,
+                    fr_grads* g, int32_t* d_rec, uint8_t* d_flag, fr_stream stream) {
+  if (!m || !d_dEdp || !g || n_samples < 0) return FR_ERR_INVALID_ARG;
+  if ((!d_rec) != (!d_flag)) return fail(m->ctx, FR_ERR_INVALID_ARG, "the shadow-edge dump takes d_rec and d_flag together");
+  fr::RenderArgs a;
+  int rc = build_args(m, s, o, a, 1);
+  if (rc != FR_OK) return rc;
+  if ((long long)s->width * s->height * s->spp >= (1ll << 31))
+    return fail(m->ctx, FR_ERR_LIMIT, "the shadow-edge term needs W*H*spp < 2^31");
+  a.dbg_hit = nullptr; a.dbg_pflag = nullptr; a.dbg_vis = nullptr; a.dbg_stats = nullptr;
+  if ((rc = ensure_lights(m, s->n_lights)) != FR_OK) return rc;
+  a.lights = m->d.lights;
+  fr::MeshDev& d = m->d;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const size_t N = d.N, L = s->n_lights, need = 3 * N + 9 * L + 12;
+  if (need > d.se_cap) {
+    if (d.se_acc) (void)hipFree(d.se_acc);
+    d.se_acc = nullptr;
+    d.se_cap = 0;
+    FR_HIP(m->ctx, dalloc(&d.se_acc, need));
+    d.se_cap = need;
+  }
+  if (n_samples == 0 || L == 0) return FR_OK;
+  fr::launch_zero_fix(d.se_acc, need, st);
+  fr::launch_light_setup(*s, d.lights, st);
+  fr::ShadowEdgeArgs e;
+  e.nbr = d.face_nbr;
+  e.n_samples = n_samples;
+  e.dEdp = d_dEdp;
+  e.gverts = g->verts ? d.se_acc : nullptr;
+  e.glight = g->light_geom ? d.se_acc + 3 * N : nullptr;
+  e.gcam = g->cam ? d.se_acc + 3 * N + 9 * L : nullptr;
+  e.dbg_rec = d_rec;
+  e.dbg_flag = d_flag;
+  fr::launch_shadow_edges(a, e, st);
+  FR_HIP(m->ctx, hipGetLastError());
+  if (g->verts) fr::launch_fix_to_float(d.se_acc, g->verts, (int)(3 * N), st);
+  if (g->light_geom) fr::launch_fix_to_float(d.se_acc + 3 * N, g->light_geom, (int)(9 * L), st);
+  if (g->cam) fr::launch_fix_to_float(d.se_acc + 3 * N + 9 * L, g->cam, 12, st);
   FR_HIP(m->ctx, hipGetLastError());
   return FR_OK;
 }

@@ -6,3 +6,4 @@
 #include "loss.hip"
 #include "backward.hip"
 #include "edges.hip"
+#include "shadow_edges.hip"

@@ -335,10 +335,10 @@ __device__ __forceinline__ void order2(float& ka, int& ca, uint64_t& ma, float& 
 // (tmin, tmax), `occluded` is set on the first accepted triangle and the lane
 // drops out.  ANY = false: closest hit, ties in t resolved to the lowest
 // triangle id.
-template <bool ANY, bool DUMP>
+template <bool ANY, bool DUMP, bool EX = false>
 __device__ __forceinline__ void trace(const Bvh4Node* __restrict__ nodes, const TriRec* __restrict__ tris, int n_tris,
                                       const Ray& r, bool active, int exclude, HitState& h, bool& occluded,
-                                      TravStats* st = nullptr) {
+                                      TravStats* st = nullptr, int ex2 = -1, int ex3 = -1) {
   uint64_t live = ballot(active);
   if (live == 0) return;
   const int lane = lane_id();
@@ -405,8 +405,9 @@ __device__ __forceinline__ void trace(const Bvh4Node* __restrict__ nodes, const 
       float t = 0.0f;
       const float tmax = ANY ? r.tmax : h.t;
       float amb = 3.4e38f;
-      const bool hit = tri_test<DUMP>(r, tr.v, tmax, t, amb) & active & (tr.id != exclude);
-      if (DUMP && active && tr.id != exclude) h.tamb = fminf(h.tamb, amb);
+      const bool other = tr.id != exclude && (!EX || (tr.id != ex2 && tr.id != ex3));
+      const bool hit = tri_test<DUMP>(r, tr.v, tmax, t, amb) & active & other;
+      if (DUMP && active && other) h.tamb = fminf(h.tamb, amb);
       if (DUMP && !ANY && hit && h.id >= 0 && fabsf(t - h.t) < kFlagT) h.tamb = fminf(h.tamb, t);
       if (ANY) {
         occluded = occluded | hit;

@@ -50,6 +50,18 @@ struct FixGrads {
   fix_t* tex_r;       // [M*M]
 };
 
+// Arguments of the shadow-edge (secondary visibility) kernel.
+struct ShadowEdgeArgs {
+  const int32_t* nbr;   // [F*3] face across edge k (tris[3f+k], tris[3f+(k+1)%3]) of face f, -1 if none
+  int n_samples;
+  const float* dEdp;    // [H*W*3]
+  fix_t* gverts;        // [N*3] fixed-point (nullable)
+  fix_t* glight;        // [L*9] fixed-point p0, e1, e2 (nullable)
+  fix_t* gcam;          // [12] fixed-point (nullable)
+  int32_t* dbg_rec;     // [n*4]: camera sample, light, jumps, edge-key sum (nullable)
+  uint8_t* dbg_flag;    // [n]
+};
+
 // Arguments of the edge-sampling kernel.
 struct EdgeArgs {
   const int32_t* edges;
@@ -101,6 +113,9 @@ struct MeshDev {
   // unique edges and their faces, for the boundary term
   int32_t* edges = nullptr;         // [E*2]
   int32_t* edge_faces = nullptr;    // [E*2]
+  int32_t* face_nbr = nullptr;      // [F*3] face across each edge of a face (-1: open edge)
+  fix_t* se_acc = nullptr;          // [3N + 9L + 12] shadow-edge accumulators: verts, light geometry, camera
+  size_t se_cap = 0;
   // BVH: binary tree (build + refit) and its 4-wide collapse (traversal)
   BvhNode* nodes = nullptr;         // [max(F-1,1)]
   Bvh4Node* nodes4 = nullptr;       // [n4]
@@ -192,6 +207,8 @@ struct RenderArgs {
   uint64_t* dbg_stats;
 };
 
+// shadow_edges.hip
+void launch_shadow_edges(const RenderArgs& a, const ShadowEdgeArgs& e, hipStream_t st);
 // bvh.hip
 int bvh_build(MeshDev& m, const float* d_verts, hipStream_t st, bool sah, int* depth_out);
 void bvh_refit(MeshDev& m, const float* d_verts, hipStream_t st);

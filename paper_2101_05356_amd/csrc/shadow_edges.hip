@@ -1,0 +1,307 @@
+// Shadow-edge (secondary visibility) boundary term of the adjoint, Sec. 4
+// "Edge Sampling" applied to the shadow rays of Sec. 3.3.
+//
+// Light j seen from a shading point x contributes kappa^-1 int int h V dw1
+// dw2 over the light's parameters (y = p0 + w1 e1 + w2 e2; kappa = 1 for a
+// parallelogram, 1/2 for a triangle), h the render's per-sample value of the
+// light at y.  On a line w2 = v the visibility V is piecewise constant in
+// w1; the derivative of the line integral gains h(w1_k) J_k dw1_k/dtheta at
+// each jump (J_k = V(w1_k-) - V(w1_k+)).  One thread per line sample: it
+// draws a camera sample, a light and v, traces the camera ray, then walks
+// the 4-wide tree with the wedge spanned by x and the line (a box is entered
+// when it straddles the wedge's plane and overlaps the wedge's bounding
+// box).  An edge (a, b) of a visited triangle is a jump when it crosses the
+// plane inside the wedge, its faces other than x's own triangle fold to one
+// side as seen from x, and a shadow ray from x to the jump's light point,
+// excluding those faces, is free.  Each edge is handled once, by its lower
+// face.  The jump solves D(w1) = det[a - x, b - x, y(w1) - x] = 0 (linear in
+// w1), so dw1/dtheta = -(dD/dtheta) / (dD/dw1), scattered to a, b, the light's
+// p0, e1, e2 and, through the camera ray's crossing with x's triangle plane
+// (x = o + t d, t = (v0 - o) . n / d . n), to that triangle and the camera.
+#include "fr_kernels.h"
+#include "fr_shade.h"
+
+namespace fr {
+
+constexpr uint32_t PURPOSE_SHADOW_EDGE = 0xC0000000u;
+constexpr float kSePlane = 1e-5f;   // relative distance of a vertex to the wedge plane
+constexpr float kSeW = 1e-5f;       // jump position at the ends of the line
+constexpr float kSeSide = 1e-5f;    // a face's slice nearly along the ray from x
+
+// Exact probability of floor(r n / 2^32) == i over the 2^32 values of r.
+__device__ __forceinline__ double pick_prob(uint64_t i, uint64_t n) {
+  const uint64_t hi = (((i + 1) << 32) + n - 1) / n, lo = ((i << 32) + n - 1) / n;
+  return (double)(hi - lo) * (1.0 / 4294967296.0);
+}
+
+template <bool DUMP, bool TEX>
+__device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const ShadowEdgeArgs& e, int i) {
+  const int lane = lane_id();
+  const bool valid = i < e.n_samples;
+  const U4 r = philox((uint32_t)i, 0u, PURPOSE_SHADOW_EDGE, a.step, a.k0, a.k1);
+  const uint64_t n_cs = (uint64_t)a.W * a.H * a.S;
+  const uint64_t cs = ((uint64_t)r.x * n_cs) >> 32;
+  const int j = a.L > 0 ? (int)(((uint64_t)r.y * (uint64_t)a.L) >> 32) : -1;
+  const float v = unit24(r.z);
+  const int pid = (int)(cs / a.S), s = (int)(cs % a.S);
+  PixelSample ps;
+  ps.pid = pid; ps.px = pid % a.W; ps.py = pid / a.W; ps.s0 = 0; ps.valid = valid;
+  bool amb = false;
+  // camera ray and its shading frame, as in the render
+  Sample sm;
+  camera_sample(a, ps, s, sm);
+  HitState h;
+  h.t = 3.4e38f; h.id = -1; h.tamb = 3.4e38f;
+  bool dummy = false;
+  trace<false, DUMP>(a.nodes, a.recs, a.F, sm.ray, valid, -1, h, dummy);
+  if (DUMP && valid && hit_ambiguous(h)) amb = true;
+  Frame fr;
+  double fx = 0.0, fy = 0.0;
+  film_point(a, ps, s, fx, fy);
+  bool shaded = valid && h.id >= 0 && shading_frame<TEX>(a, sm, h, fr, fx, fy);
+  if (DUMP && valid && h.id >= 0 && fabsf(fr.cos_o) < kFlagCos) amb = true;
+  LightRec Lj = load_const(a.lights, max(j, 0));
+  shaded = shaded && j >= 0 && Lj.shape != FR_LIGHT_DIRECTIONAL;
+  // the wedge: x and the line y0 -> y1 = y0 + ell e1 on the light
+  const V3 p0 = {Lj.p0[0], Lj.p0[1], Lj.p0[2]}, e1 = {Lj.e1[0], Lj.e1[1], Lj.e1[2]},
+           e2 = {Lj.e2[0], Lj.e2[1], Lj.e2[2]};
+  const float ell = Lj.shape == FR_LIGHT_TRIANGLE ? 1.0f - v : 1.0f;
+  const V3 x = fr.x;
+  const V3 y0 = p0 + e2 * v, y1 = y0 + e1 * ell;
+  const V3 Nw = cross(y0 - x, y1 - x);
+  const float nN = sqrtf(dot(Nw, Nw));
+  shaded = shaded && nN > 0.0f;
+  const float pad = 1e-4f;
+  const V3 blo = {fminf(x.x, fminf(y0.x, y1.x)) - pad, fminf(x.y, fminf(y0.y, y1.y)) - pad,
+                  fminf(x.z, fminf(y0.z, y1.z)) - pad};
+  const V3 bhi = {fmaxf(x.x, fmaxf(y0.x, y1.x)) + pad, fmaxf(x.y, fmaxf(y0.y, y1.y)) + pad,
+                  fmaxf(x.z, fmaxf(y0.z, y1.z)) + pad};
+  const float kinv = Lj.shape == FR_LIGHT_TRIANGLE ? 2.0f : 1.0f;
+  const float wgt = valid && a.L > 0
+                        ? (float)(1.0 / ((double)e.n_samples * pick_prob(cs, n_cs) * pick_prob((uint64_t)max(j, 0), (uint64_t)a.L)))
+                        : 0.0f;
+  const float* g = e.dEdp + 3 * (size_t)pid;
+  const V3 gpix = valid ? V3{g[0], g[1], g[2]} : V3{0.0f, 0.0f, 0.0f};
+  int n_ok = 0;
+  long long key = 0;
+  V3 gx_tot = {0.0f, 0.0f, 0.0f};
+  V3 gy_tot = {0.0f, 0.0f, 0.0f}, ge1_tot = {0.0f, 0.0f, 0.0f}, ge2_tot = {0.0f, 0.0f, 0.0f};
+  const auto near_plane = [&](float sv, V3 E) { return fabsf(sv) < kSePlane * nN * (1.0f + sqrtf(dot(E - x, E - x))); };
+
+  // ---- wave-cooperative walk of the tree with every lane's wedge
+  uint64_t live = ballot(shaded);
+  int stack = 0, sp = 0;
+  int node = a.F > 1 ? 0 : ~0;
+  int budget = 2 * a.F + 64;
+  while (live != 0 && --budget > 0) {
+    if (node >= 0) {
+      const Bvh4Node nd = load_const(a.nodes, node);
+      uint64_t mk[4];
+      for (int k = 0; k < 4; ++k) {
+        const V3 lo = {nd.lo[0][k], nd.lo[1][k], nd.lo[2][k]}, hi = {nd.hi[0][k], nd.hi[1][k], nd.hi[2][k]};
+        const V3 c = (lo + hi) * 0.5f, ex = (hi - lo) * 0.5f;
+        const float dc = dot(Nw, c - x);
+        const float rad = fabsf(Nw.x) * ex.x + fabsf(Nw.y) * ex.y + fabsf(Nw.z) * ex.z;
+        const bool straddle = fabsf(dc) <= rad * 1.0001f + 2.0f * kSePlane * nN * (1.0f + sqrtf(dot(c - x, c - x)) + rad / fmaxf(nN, 1e-30f));
+        const bool overlap = !(hi.x < blo.x || lo.x > bhi.x || hi.y < blo.y || lo.y > bhi.y || hi.z < blo.z ||
+                               lo.z > bhi.z);
+        mk[k] = nd.c[k] != kEmpty ? (ballot(shaded && straddle && overlap) & live) : 0ull;
+      }
+      int next = kEmpty;
+      for (int k = 3; k >= 0; --k) {
+        if (!mk[k]) continue;
+        if (next != kEmpty) { stack = (lane == sp) ? next : stack; ++sp; }
+        next = nd.c[k];
+      }
+      if (next != kEmpty) { node = next; continue; }
+    } else {
+      const TriRec tr = load_const(a.recs, ~node);
+      const int f = tr.id;
+      for (int k = 0; k < 3; ++k) {
+        int ia = a.tris[3 * f + k], ib = a.tris[3 * f + (k + 1) % 3];
+        const int ic = a.tris[3 * f + (k + 2) % 3];
+        const int nb = e.nbr[3 * f + k];
+        V3 A = {tr.v[3 * k], tr.v[3 * k + 1], tr.v[3 * k + 2]};
+        V3 B = {tr.v[3 * ((k + 1) % 3)], tr.v[3 * ((k + 1) % 3) + 1], tr.v[3 * ((k + 1) % 3) + 2]};
+        const V3 C = {tr.v[3 * ((k + 2) % 3)], tr.v[3 * ((k + 2) % 3) + 1], tr.v[3 * ((k + 2) % 3) + 2]};
+        if (ia > ib) { const int t = ia; ia = ib; ib = t; const V3 tv = A; A = B; B = tv; }
+        const bool lead = nb < 0 || f < nb;
+        const float sa = dot(Nw, A - x), sb = dot(Nw, B - x);
+        if (DUMP && shaded && lead && (near_plane(sa, A) || near_plane(sb, B))) {
+          // an end on the plane matters when it lies inside the wedge's span
+          const V3 E = near_plane(sa, A) ? A : B, u0 = y0 - x, u1 = y1 - x, w = E - x;
+          const float g00 = dot(u0, u0), g01 = dot(u0, u1), g11 = dot(u1, u1), r0 = dot(u0, w), r1 = dot(u1, w);
+          const float det = g00 * g11 - g01 * g01;
+          const float al = (g11 * r0 - g01 * r1) / det, be = (g00 * r1 - g01 * r0) / det, tot = al + be;
+          if (tot > -0.01f && be > -0.02f * fabsf(tot) && be < 1.02f * fabsf(tot) && tot < 1.02f) amb = true;
+        }
+        bool cand = shaded && lead && ((sa > 0.0f && sb < 0.0f) || (sa < 0.0f && sb > 0.0f));
+        V3 P = {0.0f, 0.0f, 0.0f}, nab = {0.0f, 0.0f, 0.0f}, yk = {0.0f, 0.0f, 0.0f};
+        float w1 = 0.0f, D1 = 1.0f, dist = 1.0f;
+        int J = 0;
+        if (cand) {
+          P = A + (B - A) * (sa / (sa - sb));
+          nab = cross(A - x, B - x);
+          D1 = dot(nab, e1);
+          w1 = D1 != 0.0f ? -dot(nab, y0 - x) / D1 : -1.0f;
+          yk = p0 + e1 * w1 + e2 * v;
+          const V3 dy = yk - x;
+          dist = sqrtf(dot(dy, dy));
+          const float tau = dot(P - x, dy) / (dist * dist);
+          const float dP = tau * dist;
+          const bool in_w = w1 > 0.0f && w1 < ell, in_t = tau > 0.0f && dP > kShadowTmin && tau < 1.0f;
+          if (DUMP && tau > 0.0f &&
+              (fabsf(w1) < kSeW || fabsf(w1 - ell) < kSeW || fabsf(dP - kShadowTmin) < kFlagT || fabsf(dist - dP) < kFlagT))
+            amb = true;
+          cand = in_w && in_t;
+          if (cand && DUMP && (near_plane(sa, A) || near_plane(sb, B))) amb = true;
+        }
+        if (cand) {
+          // faces of the edge other than x's own triangle, and their sides
+          int n = 0, right = 0;
+          for (int q = 0; q < 2; ++q) {
+            const int fq = q == 0 ? f : nb;
+            if (fq < 0 || fq == h.id) continue;
+            V3 Cq = C;
+            if (q == 1) {
+              const int* t = a.tris + 3 * fq;
+              const int cv = (t[0] != ia && t[0] != ib) ? t[0] : ((t[1] != ia && t[1] != ib) ? t[1] : t[2]);
+              Cq = ld3(a.verts, cv);
+            } else {
+              (void)ic;
+            }
+            const float scq = dot(Nw, Cq - x);
+            if (DUMP && near_plane(scq, Cq)) amb = true;
+            const bool with_a = (scq > 0.0f) == (sa > 0.0f);
+            const V3 Q = with_a ? B + (Cq - B) * (sb / (sb - scq)) : A + (Cq - A) * (sa / (sa - scq));
+            const float o = dot(cross(P - x, Q - x), Nw);
+            if (DUMP && fabsf(o) < kSeSide * sqrtf(dot(P - x, P - x)) * sqrtf(dot(Q - P, Q - P)) * nN) amb = true;
+            ++n;
+            right += o > 0.0f ? 1 : 0;
+          }
+          J = (n == 0 || (right != 0 && right != n)) ? 0 : (right == n ? 1 : -1);
+          cand = J != 0;
+        }
+        // the shadow ray to the jump's light point, the edge's faces and x's triangle excluded
+        Ray sr;
+        sr.o = x;
+        sr.d = (yk - x) * (1.0f / dist);
+        sr.tmin = kShadowTmin;
+        sr.tmax = dist;
+        ray_setup(sr);
+        HitState shd;
+        shd.tamb = 3.4e38f;
+        bool occ = false;
+        trace<true, DUMP, true>(a.nodes, a.recs, a.F, sr, cand, h.id, shd, occ, nullptr, f, nb);
+        if (DUMP && cand && shd.tamb < 3.0e38f) amb = true;
+        cand = cand && !occ;
+        if (cand) {
+          ++n_ok;
+          key = (key + (long long)ia * a.N + ib) % 2147483648LL;
+          // h at the jump: the render's light value there (cosine culls included)
+          LightSample ls;
+          ls.w1 = w1; ls.w2 = v; ls.q = yk;
+          const V3 dq = yk - x;
+          ls.dist2 = dot(dq, dq);
+          ls.dist = sqrtf(ls.dist2);
+          ls.l = dq * (1.0f / ls.dist);
+          ls.cos_s = dot(fr.ns, ls.l);
+          ls.cos_a = Lj.na[0] * ls.l.x + Lj.na[1] * ls.l.y + Lj.na[2] * ls.l.z;
+          ls.geom = ls.cos_s * ls.cos_a / ls.dist2;
+          const float alen = sqrtf(Lj.na[0] * Lj.na[0] + Lj.na[1] * Lj.na[1] + Lj.na[2] * Lj.na[2]);
+          if (DUMP && (fabsf(ls.cos_s) < kFlagCos || fabsf(ls.cos_a) < kFlagCos * alen)) amb = true;
+          if (ls.cos_s > 0.0f && ls.cos_a > 0.0f) {
+            float fv[3], gflag = 0.0f;
+            brdf_eval<DUMP>(a.variant, a.components, fr, ls, fv, gflag);
+            if (DUMP && gflag != 0.0f) amb = true;
+            const float hv = gpix.x * fv[0] * Lj.rad[0] + gpix.y * fv[1] * Lj.rad[1] + gpix.z * fv[2] * Lj.rad[2];
+            const float coef = wgt * kinv / (float)a.S * (float)J * hv * ls.geom;
+            if (coef != 0.0f) {
+              const float c = -coef / D1;
+              const V3 Ax = A - x, Bx = B - x, Yx = yk - x;
+              const V3 ga = cross(Bx, Yx) * c, gb = cross(Yx, Ax) * c, gy = nab * c;
+              gx_tot = gx_tot - ga - gb - gy;
+              gy_tot = gy_tot + gy;
+              ge1_tot = ge1_tot + gy * w1;
+              ge2_tot = ge2_tot + gy * v;
+              if (e.gverts) {
+                fix_add(e.gverts + 3 * ia, ga.x); fix_add(e.gverts + 3 * ia + 1, ga.y); fix_add(e.gverts + 3 * ia + 2, ga.z);
+                fix_add(e.gverts + 3 * ib, gb.x); fix_add(e.gverts + 3 * ib + 1, gb.y); fix_add(e.gverts + 3 * ib + 2, gb.z);
+              }
+            }
+          }
+        }
+      }
+    }
+    if (sp == 0) break;
+    --sp;
+    node = readlane_i(stack, sp);
+  }
+
+  // ---- light geometry, and x's path to its triangle and the camera
+  const bool has = gy_tot.x != 0.0f || gy_tot.y != 0.0f || gy_tot.z != 0.0f || gx_tot.x != 0.0f ||
+                   gx_tot.y != 0.0f || gx_tot.z != 0.0f;
+  if (has) {
+    if (e.glight) {
+      fix_t* gl = e.glight + 9 * (size_t)j;
+      fix_add(gl + 0, gy_tot.x); fix_add(gl + 1, gy_tot.y); fix_add(gl + 2, gy_tot.z);
+      fix_add(gl + 3, ge1_tot.x); fix_add(gl + 4, ge1_tot.y); fix_add(gl + 5, ge1_tot.z);
+      fix_add(gl + 6, ge2_tot.x); fix_add(gl + 7, ge2_tot.y); fix_add(gl + 8, ge2_tot.z);
+    }
+    const int* tv = a.tris + 3 * h.id;
+    const V3 v0 = ld3(a.verts, tv[0]), v1 = ld3(a.verts, tv[1]), v2 = ld3(a.verts, tv[2]);
+    const V3 d = sm.ray.d, o = sm.ray.o;
+    const V3 ea = v1 - v0, eb = v2 - v0;
+    const V3 n = cross(ea, eb);
+    const float idn = 1.0f / dot(d, n);
+    const float t = dot(v0 - o, n) * idn;
+    const float g_t = dot(gx_tot, d);
+    const V3 go = gx_tot - n * (g_t * idn);
+    const V3 gd = gx_tot * t - n * (g_t * t * idn);
+    // v0 - x from the FP64 barycentrics of the shading point (an FP32 o + t d
+    // would carry ~ulp(|o|) into this difference of nearby points)
+    const V3 gn = (ea * fr.b[1] + eb * fr.b[2]) * (-g_t * idn);
+    const V3 gea = cross(eb, gn), geb = cross(gn, ea);
+    const V3 gv0 = n * (g_t * idn) - gea - geb;
+    if (e.gverts) {
+      const V3 gvv[3] = {gv0, gea, geb};
+      for (int k = 0; k < 3; ++k) {
+        fix_add(e.gverts + 3 * tv[k], gvv[k].x);
+        fix_add(e.gverts + 3 * tv[k] + 1, gvv[k].y);
+        fix_add(e.gverts + 3 * tv[k] + 2, gvv[k].z);
+      }
+    }
+    if (e.gcam) {
+      // d = dw / |dw|, dw = R dc, o = T
+      const V3 gdw = (gd - d * dot(gd, d)) * sm.inv_len;
+      const float gR[9] = {gdw.x * sm.dc.x, gdw.x * sm.dc.y, gdw.x * sm.dc.z, gdw.y * sm.dc.x, gdw.y * sm.dc.y,
+                           gdw.y * sm.dc.z, gdw.z * sm.dc.x, gdw.z * sm.dc.y, gdw.z * sm.dc.z};
+      for (int k = 0; k < 9; ++k) fix_add(e.gcam + k, gR[k]);
+      fix_add(e.gcam + 9, go.x); fix_add(e.gcam + 10, go.y); fix_add(e.gcam + 11, go.z);
+    }
+  }
+  if (DUMP && valid) {
+    e.dbg_rec[4 * (size_t)i] = (int32_t)cs;
+    e.dbg_rec[4 * (size_t)i + 1] = j;
+    e.dbg_rec[4 * (size_t)i + 2] = n_ok;
+    e.dbg_rec[4 * (size_t)i + 3] = (int32_t)key;
+    e.dbg_flag[i] = amb ? 1 : 0;
+  }
+}
+
+template <bool DUMP, bool TEX>
+__global__ __launch_bounds__(256) void k_shadow_edges(RenderArgs a, ShadowEdgeArgs e) {
+  shadow_edge_sample<DUMP, TEX>(a, e, (int)(blockIdx.x * 256 + threadIdx.x));
+}
+
+void launch_shadow_edges(const RenderArgs& a, const ShadowEdgeArgs& e, hipStream_t st) {
+  if (e.n_samples <= 0) return;
+  const int blocks = (e.n_samples + 255) / 256;
+  const bool dump = e.dbg_rec != nullptr, tex = a.M > 0;
+  if (dump && tex) hipLaunchKernelGGL((k_shadow_edges<true, true>), dim3(blocks), dim3(256), 0, st, a, e);
+  else if (dump) hipLaunchKernelGGL((k_shadow_edges<true, false>), dim3(blocks), dim3(256), 0, st, a, e);
+  else if (tex) hipLaunchKernelGGL((k_shadow_edges<false, true>), dim3(blocks), dim3(256), 0, st, a, e);
+  else hipLaunchKernelGGL((k_shadow_edges<false, false>), dim3(blocks), dim3(256), 0, st, a, e);
+}
+
+}  // namespace fr

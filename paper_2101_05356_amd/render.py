@@ -272,6 +272,35 @@ def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_varian
     return out
 
 
+def shadow_edges(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, n_samples: int, brdf_variant=0, components=3,
+                 groups=("verts", "light_geom", "cam"), verts=None, dump=False, out=None):
+    """Shadow-edge (secondary visibility) boundary term of sum dEdp . image
+    from n_samples line samples, after a forward render of the same scene:
+    dict of gradients over `groups` (verts [N,3], light_geom [L,9], cam
+    [12]; added into the tensors of `out` when given), plus rec [n,4] and flag
+    [n] with dump=True."""
+    dev = sc.verts.device
+    N, L = mesh.n_verts, sc.n_lights
+    shapes = dict(verts=(N, 3), light_geom=(L, 9), cam=(12,))
+    res = dict(out) if out is not None else {k: torch.zeros(shapes[k], dtype=torch.float32, device=dev) for k in groups}
+    g = FrGrads()
+    for k in GRAD_GROUPS + TEX_GROUPS + ("sh",):
+        setattr(g, k, res[k].data_ptr() if k in res and k in shapes else None)
+    rec = flag = None
+    if dump:
+        rec = torch.full((max(n_samples, 1) * 4,), -7, dtype=torch.int32, device=dev)
+        flag = torch.zeros(max(n_samples, 1), dtype=torch.uint8, device=dev)
+    s = sc.struct(verts)
+    o = _opts(brdf_variant, components, 0, None, 0, None)
+    check(lib().fr_shadow_edges(mesh.h, ctypes.byref(s), ctypes.byref(o), _p(dEdp.contiguous()), int(n_samples),
+                                ctypes.byref(g), _p(rec) if dump else None, _p(flag) if dump else None, _stream()),
+          mesh.ctx.h, "fr_shadow_edges")
+    if dump:
+        res["rec"] = rec[:4 * n_samples].view(-1, 4)
+        res["flag"] = flag[:n_samples]
+    return res
+
+
 def blend(mean, basis, coef, out=None):
     K, M = basis.shape
     out = torch.empty(M, dtype=torch.float32, device=mean.device) if out is None else out
