@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--envmap-only", action="store_true", help="run only the environment-map measurement")
     ap.add_argument("--sh-steps", type=int, default=10, help="steps of the face under 7-band SH lighting (0 = skip)")
     ap.add_argument("--sh-only", action="store_true", help="run only the SH-lighting measurement")
+    ap.add_argument("--shadow-edge-samples", type=int, default=65536,
+                    help="line samples of the shadow-edge boundary term at the face workload (0 = skip)")
+    ap.add_argument("--shadow-edge-only", action="store_true", help="run only the shadow-edge measurement")
     return ap.parse_args()
 
 
@@ -311,6 +314,46 @@ def sh_bench(ctx, steps, warmup, bands=7, edge_samples=-1, seed=53):
     return r
 
 
+def shadow_edge_bench(ctx, n_samples, reps=20, warmup=3, seed=54):
+    """The shadow-edge (secondary visibility) boundary term at the face
+    workload (256 x 256, 16 spp, 72 area lights, 28,002-vertex mesh):
+    n_samples line samples per call into the vertex, light-geometry and
+    camera gradients, timed with HIP events on the launch stream; one dumped
+    call (untimed) counts the samples whose line crosses a shadow edge."""
+    import torch
+    from paper_2101_05356_amd import render as R
+    from paper_2101_05356_amd import scenes
+    sc = scenes.face_render_scene(W=256, H=256, spp=16, n_lights=72)
+    m = R.Mesh(ctx, sc.n_verts, sc.tris)
+    ds = R.DeviceScene.from_scene(sc)
+    m.update(ds.verts, rebuild=True)
+    img = R.render_forward(m, ds)
+    rng = np.random.default_rng(seed)
+    dEdp = torch.as_tensor(rng.normal(size=(256, 256, 3)).astype(np.float32)).cuda()
+    out = {k: torch.zeros(v, dtype=torch.float32, device="cuda") for k, v in
+           (("verts", (sc.n_verts, 3)), ("light_geom", (72, 9)), ("cam", (12,)))}
+    dump = R.shadow_edges(m, ds, dEdp, n_samples, dump=True)
+    torch.cuda.synchronize()
+    rec = dump["rec"].cpu().numpy()
+    for _ in range(warmup):
+        R.shadow_edges(m, ds, dEdp, n_samples, out=out)
+    torch.cuda.synchronize()
+    evs = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        R.shadow_edges(m, ds, dEdp, n_samples, out=out)
+        b.record()
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    del img
+    return {"samples": n_samples, "calls": reps, "ms_per_call": ms, "samples_per_s": n_samples / (ms * 1e-3),
+            "samples_with_jumps": int((rec[:, 2] > 0).sum()), "jumps": int(rec[:, 2].sum()),
+            "workload": f"256x256 face: {sc.n_verts:,}-vertex / {len(sc.tris):,}-triangle mesh, 16 spp, 72 area "
+                        f"lights; {n_samples} line samples (camera sample, light, line across it) per call"}
+
+
 def render_step_bench(ctx, sc, steps, warmup, groups, edge_samples=-1, seed=51):
     """Refit + forward (keeping its decisions) + loss + backward (taking them)
     per step on one scene; the deformed vertex sets and the target are made
@@ -387,6 +430,9 @@ def main():
     if args.sh_only:
         print(json.dumps({"sh": sh_bench(ctx, max(args.sh_steps, 1), 3)}), flush=True)
         return
+    if args.shadow_edge_only:
+        print(json.dumps({"shadow_edges": shadow_edge_bench(ctx, max(args.shadow_edge_samples, 1))}), flush=True)
+        return
     mt, rc = make_c2(ctx, W, S, L, args.edge_samples)
     settle_clocks(rc, 0.3)
     for _ in range(args.warmup):
@@ -453,6 +499,9 @@ def main():
     if args.sh_steps > 0 and not args.profile_only:
         out["sh"] = sh_bench(ctx, args.sh_steps, 3)
         print(json.dumps({"progress": "sh", **out["sh"]}), file=sys.stderr, flush=True)
+    if args.shadow_edge_samples > 0 and not args.profile_only:
+        out["shadow_edges"] = shadow_edge_bench(ctx, args.shadow_edge_samples)
+        print(json.dumps({"progress": "shadow_edges", **out["shadow_edges"]}), file=sys.stderr, flush=True)
     if not args.profile_only and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, S, L, W)
     print(json.dumps(out), flush=True)

@@ -1264,6 +1264,9 @@ std::vector<ShadowJump> shadow_jumps(const OrScene& sc, const std::vector<TriGeo
       const double D1 = dot(nab, L.e1);
       if (D1 == 0.0) continue;
       const double w1 = -dot(nab, y0 - x) / D1;
+      // an edge nearly parallel to the line: the jump's position (and its
+      // derivative, ~1/D1) is ill-conditioned; flagged when in range
+      const bool ill = std::fabs(D1) < 1e-3 * norm(nab) * norm(L.e1);
       const V3 yk = L.p0 + L.e1 * w1 + L.e2 * v;
       const V3 dy = yk - x;
       const double dist = norm(dy);
@@ -1275,6 +1278,7 @@ std::vector<ShadowJump> shadow_jumps(const OrScene& sc, const std::vector<TriGeo
       const bool near_t = std::fabs(dP - kShadowTmin) < kFlagEps || std::fabs(dist - dP) < kFlagEps;
       if (near_w || near_t) *flags |= FLAG_TRANGE;
       if (!(in_w && in_t)) continue;
+      if (ill) *flags |= FLAG_EDGE;
       int faces[2] = {f, g}, n = 0, right = 0;
       for (int q = 0; q < 2; ++q) {
         if (faces[q] < 0 || faces[q] == self) continue;
@@ -1341,12 +1345,17 @@ int32_t oracle_shadow_jumps(const OrScene* sc, const double* xp, int32_t self, i
 }
 
 // Shadow-edge boundary term of sum_p dEdp[p] . rgb[p] (dEdp [H*W*3]) from
-// n_samples line samples: sample i draws, from Philox counter (i, 0,
-// 0xC0000000, step), a camera sample (pixel y*W + x, sample s) uniformly
-// over the W*H*S of them (word 0), a light uniformly (word 1) and the line
-// w2 = v (word 2, 24 bits), and contributes, per jump,
-//   kappa^-1 (1/S) (dEdp . h(w1_k, v)) J_k dw1_k/dtheta / (n_samples p_ps p_j)
-// with p_ps, p_j the exact probabilities of the two draws.  The shading
+// n_samples line samples in groups of 64: group g draws, from Philox
+// counter (g, 0, 0xC0000000, step), an 8 x 8 pixel tile uniformly over the
+// tiles (word 0; edge tiles are clipped to the image) and a light uniformly
+// (word 1); sample i of the group draws, from counter (i, 1, 0xC0000000,
+// step), a camera sample uniformly over the tile's pixels and samples (word
+// 0) and the line w2 = v (word 1, 24 bits).  Each sample contributes, per jump,
+//   kappa^-1 (1/S) (dEdp . h(w1_k, v)) J_k dw1_k/dtheta / (n_samples p_cs p_j)
+// with p_cs = p(tile) p(camera sample | tile) and p_j the exact marginal
+// probabilities of its draws (a group's samples share their tile and light,
+// so that a wave's wedges are coherent; each sample's marginal is what the
+// weight uses, so the sum stays unbiased).  The shading
 // point x is the camera ray's hit, a function of the hit triangle and the
 // camera (Sec. 3.1), as in the render.  Accumulated (+=): g_verts [N*3],
 // g_light [L*9] (p0, e1, e2), g_cam [12].  rec [n*4] = (camera sample,
@@ -1363,16 +1372,25 @@ int oracle_shadow_edge_grad(const OrScene* sc, int32_t n_samples, const double* 
   const OrScene& s = *sc;
   const std::vector<int> nb = face_neighbours(s);
   const int N = s.n_verts, L = s.n_lights, W = s.width, S = s.spp;
-  const int64_t n_cs = (int64_t)W * s.height * S;
   if (n_samples <= 0) return 0;
   nthreads = std::max(1, std::min<int>(nthreads, n_samples));
   std::vector<std::vector<double>> gv(nthreads, std::vector<double>(3 * (size_t)N, 0.0)),
       gl(nthreads, std::vector<double>(9 * (size_t)std::max(L, 1), 0.0)), gc(nthreads, std::vector<double>(12, 0.0));
+  const int tx = (W + 7) / 8, ty = (s.height + 7) / 8;
   parallel_for(n_samples, nthreads, [&](int i, int th) {
-    const Rand4 r = philox4x32_10((uint32_t)i, 0u, PURPOSE_SHADOW_EDGE, s.step, s.seed);
-    const int64_t cs = pick_index(r.x[0], n_cs);
-    const int j = L > 0 ? (int)pick_index(r.x[1], L) : -1;
-    const double v = unit24(r.x[2]);
+    // group draw (tile, light) shared by samples 64 g .. 64 g + 63, then the
+    // sample's camera sample within the tile and its line
+    const Rand4 rg = philox4x32_10((uint32_t)(i / 64), 0u, PURPOSE_SHADOW_EDGE, s.step, s.seed);
+    const Rand4 r = philox4x32_10((uint32_t)i, 1u, PURPOSE_SHADOW_EDGE, s.step, s.seed);
+    const int tile = (int)pick_index(rg.x[0], (int64_t)tx * ty);
+    const int x0 = 8 * (tile % tx), y0 = 8 * (tile / tx);
+    const int tw = std::min(8, W - x0), tht = std::min(8, s.height - y0);
+    const int64_t n_in = (int64_t)tw * tht * S;
+    const int64_t k = pick_index(r.x[0], n_in);
+    const int64_t cs = ((int64_t)(y0 + (int)(k / S) / tw) * W + x0 + (int)(k / S) % tw) * S + k % S;
+    const int j = L > 0 ? (int)pick_index(rg.x[1], L) : -1;
+    const double v = unit24(r.x[1]);
+    const double p_cs = pick_prob(tile, (int64_t)tx * ty) * pick_prob(k, n_in);
     int32_t* rr = rec ? rec + 4 * (size_t)i : nullptr;
     if (rr) { rr[0] = (int32_t)cs; rr[1] = j; rr[2] = 0; rr[3] = 0; }
     uint8_t fl = 0;
@@ -1411,7 +1429,7 @@ int oracle_shadow_edge_grad(const OrScene* sc, int32_t n_samples, const double* 
     const Vec3<D18> X(D18::seed(xd.x.v, 6), D18::seed(xd.y.v, 7), D18::seed(xd.z.v, 8));
     const LightParams<double> Lp = light_params_d(s, j);
     const double kinv = Lp.shape == 1 ? 2.0 : 1.0;
-    const double wgt = 1.0 / ((double)n_samples * pick_prob(cs, n_cs) * pick_prob(j, L));
+    const double wgt = 1.0 / ((double)n_samples * p_cs * pick_prob(j, L));
     int n_ok = 0;
     int64_t key = 0;
     for (const ShadowJump& q : js) {

@@ -38,12 +38,22 @@ template <bool DUMP, bool TEX>
 __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const ShadowEdgeArgs& e, int i) {
   const int lane = lane_id();
   const bool valid = i < e.n_samples;
-  const U4 r = philox((uint32_t)i, 0u, PURPOSE_SHADOW_EDGE, a.step, a.k0, a.k1);
-  const uint64_t n_cs = (uint64_t)a.W * a.H * a.S;
-  const uint64_t cs = ((uint64_t)r.x * n_cs) >> 32;
-  const int j = a.L > 0 ? (int)(((uint64_t)r.y * (uint64_t)a.L) >> 32) : -1;
-  const float v = unit24(r.z);
-  const int pid = (int)(cs / a.S), s = (int)(cs % a.S);
+  // group of 64 samples (one wave): an 8 x 8 pixel tile and a light; per
+  // sample a camera sample within the tile and a line across the light
+  const U4 rg = philox((uint32_t)(i / 64), 0u, PURPOSE_SHADOW_EDGE, a.step, a.k0, a.k1);
+  const U4 r = philox((uint32_t)i, 1u, PURPOSE_SHADOW_EDGE, a.step, a.k0, a.k1);
+  const int tx = (a.W + 7) / 8, ty = (a.H + 7) / 8;
+  const uint64_t n_t = (uint64_t)tx * ty;
+  const int tile = (int)(((uint64_t)rg.x * n_t) >> 32);
+  const int x0 = 8 * (tile % tx), y0p = 8 * (tile / tx);
+  const int tw = min(8, a.W - x0), th = min(8, a.H - y0p);
+  const uint64_t n_in = (uint64_t)tw * th * a.S;
+  const uint64_t kin = ((uint64_t)r.x * n_in) >> 32;
+  const int s = (int)(kin % a.S), q = (int)(kin / a.S);
+  const int pid = (y0p + q / tw) * a.W + x0 + q % tw;
+  const uint64_t cs = (uint64_t)pid * a.S + s;
+  const int j = a.L > 0 ? (int)(((uint64_t)rg.y * (uint64_t)a.L) >> 32) : -1;
+  const float v = unit24(r.y);
   PixelSample ps;
   ps.pid = pid; ps.px = pid % a.W; ps.py = pid / a.W; ps.s0 = 0; ps.valid = valid;
   bool amb = false;
@@ -66,9 +76,25 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
   const V3 p0 = {Lj.p0[0], Lj.p0[1], Lj.p0[2]}, e1 = {Lj.e1[0], Lj.e1[1], Lj.e1[2]},
            e2 = {Lj.e2[0], Lj.e2[1], Lj.e2[2]};
   const float ell = Lj.shape == FR_LIGHT_TRIANGLE ? 1.0f - v : 1.0f;
+  // x = fr.x + xlo: the FP32 shading point plus its residual against the
+  // FP64 barycentric point, so that differences p - x with nearby points keep
+  // the FP64 point's accuracy (a near occluder's jump moves ~|light| /
+  // |occluder| times as fast as x)
   const V3 x = fr.x;
+  V3 xlo = {0.0f, 0.0f, 0.0f};
+  if (shaded) {
+    const int* tv = a.tris + 3 * h.id;
+    const int vi[3] = {tv[0], tv[1], tv[2]};
+    double bd[3];
+    bary64(a, fx, fy, vi, bd);
+    double X[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < 3; ++k)
+      for (int c = 0; c < 3; ++c) X[c] += bd[k] * (double)a.verts[3 * vi[k] + c];
+    xlo = {(float)(X[0] - (double)x.x), (float)(X[1] - (double)x.y), (float)(X[2] - (double)x.z)};
+  }
+  const auto rel = [&](V3 p) { return (p - x) - xlo; };
   const V3 y0 = p0 + e2 * v, y1 = y0 + e1 * ell;
-  const V3 Nw = cross(y0 - x, y1 - x);
+  const V3 Nw = cross(rel(y0), rel(y1));
   const float nN = sqrtf(dot(Nw, Nw));
   shaded = shaded && nN > 0.0f;
   const float pad = 1e-4f;
@@ -76,9 +102,12 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
                   fminf(x.z, fminf(y0.z, y1.z)) - pad};
   const V3 bhi = {fmaxf(x.x, fmaxf(y0.x, y1.x)) + pad, fmaxf(x.y, fmaxf(y0.y, y1.y)) + pad,
                   fmaxf(x.z, fmaxf(y0.z, y1.z)) + pad};
+  // outward in-plane normals of the wedge triangle's sides x -> y0 -> y1 -> x
+  const V3 sn0 = cross(rel(y0), Nw), sn1 = cross(y1 - y0, Nw), sn2 = cross(rel(y1) * -1.0f, Nw);
   const float kinv = Lj.shape == FR_LIGHT_TRIANGLE ? 2.0f : 1.0f;
   const float wgt = valid && a.L > 0
-                        ? (float)(1.0 / ((double)e.n_samples * pick_prob(cs, n_cs) * pick_prob((uint64_t)max(j, 0), (uint64_t)a.L)))
+                        ? (float)(1.0 / ((double)e.n_samples * pick_prob((uint64_t)tile, n_t) * pick_prob(kin, n_in) *
+                                         pick_prob((uint64_t)max(j, 0), (uint64_t)a.L)))
                         : 0.0f;
   const float* g = e.dEdp + 3 * (size_t)pid;
   const V3 gpix = valid ? V3{g[0], g[1], g[2]} : V3{0.0f, 0.0f, 0.0f};
@@ -86,7 +115,7 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
   long long key = 0;
   V3 gx_tot = {0.0f, 0.0f, 0.0f};
   V3 gy_tot = {0.0f, 0.0f, 0.0f}, ge1_tot = {0.0f, 0.0f, 0.0f}, ge2_tot = {0.0f, 0.0f, 0.0f};
-  const auto near_plane = [&](float sv, V3 E) { return fabsf(sv) < kSePlane * nN * (1.0f + sqrtf(dot(E - x, E - x))); };
+  const auto near_plane = [&](float sv, V3 E) { return fabsf(sv) < kSePlane * nN * (1.0f + sqrtf(dot(rel(E), rel(E)))); };
 
   // ---- wave-cooperative walk of the tree with every lane's wedge
   uint64_t live = ballot(shaded);
@@ -100,12 +129,19 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
       for (int k = 0; k < 4; ++k) {
         const V3 lo = {nd.lo[0][k], nd.lo[1][k], nd.lo[2][k]}, hi = {nd.hi[0][k], nd.hi[1][k], nd.hi[2][k]};
         const V3 c = (lo + hi) * 0.5f, ex = (hi - lo) * 0.5f;
-        const float dc = dot(Nw, c - x);
+        const float dc = dot(Nw, rel(c));
         const float rad = fabsf(Nw.x) * ex.x + fabsf(Nw.y) * ex.y + fabsf(Nw.z) * ex.z;
-        const bool straddle = fabsf(dc) <= rad * 1.0001f + 2.0f * kSePlane * nN * (1.0f + sqrtf(dot(c - x, c - x)) + rad / fmaxf(nN, 1e-30f));
+        const bool straddle = fabsf(dc) <= rad * 1.0001f + 2.0f * kSePlane * nN * (1.0f + sqrtf(dot(rel(c), rel(c))) + rad / fmaxf(nN, 1e-30f));
         const bool overlap = !(hi.x < blo.x || lo.x > bhi.x || hi.y < blo.y || lo.y > bhi.y || hi.z < blo.z ||
                                lo.z > bhi.z);
-        mk[k] = nd.c[k] != kEmpty ? (ballot(shaded && straddle && overlap) & live) : 0ull;
+        // a side's normal separates the box from the triangle when the whole
+        // box lies beyond that side (with a relative margin)
+        const auto beyond = [&](V3 m, V3 p) {
+          const float r = fabsf(m.x) * ex.x + fabsf(m.y) * ex.y + fabsf(m.z) * ex.z;
+          return dot(m, c - p) - r > 1e-4f * (r + sqrtf(dot(m, m)) * (1.0f + sqrtf(dot(c - p, c - p))));
+        };
+        const bool inside = !beyond(sn0, x) && !beyond(sn1, y0) && !beyond(sn2, y1);
+        mk[k] = nd.c[k] != kEmpty ? (ballot(shaded && straddle && overlap && inside) & live) : 0ull;
       }
       int next = kEmpty;
       for (int k = 3; k >= 0; --k) {
@@ -126,10 +162,10 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
         const V3 C = {tr.v[3 * ((k + 2) % 3)], tr.v[3 * ((k + 2) % 3) + 1], tr.v[3 * ((k + 2) % 3) + 2]};
         if (ia > ib) { const int t = ia; ia = ib; ib = t; const V3 tv = A; A = B; B = tv; }
         const bool lead = nb < 0 || f < nb;
-        const float sa = dot(Nw, A - x), sb = dot(Nw, B - x);
+        const float sa = dot(Nw, rel(A)), sb = dot(Nw, rel(B));
         if (DUMP && shaded && lead && (near_plane(sa, A) || near_plane(sb, B))) {
           // an end on the plane matters when it lies inside the wedge's span
-          const V3 E = near_plane(sa, A) ? A : B, u0 = y0 - x, u1 = y1 - x, w = E - x;
+          const V3 E = near_plane(sa, A) ? A : B, u0 = rel(y0), u1 = rel(y1), w = rel(E);
           const float g00 = dot(u0, u0), g01 = dot(u0, u1), g11 = dot(u1, u1), r0 = dot(u0, w), r1 = dot(u1, w);
           const float det = g00 * g11 - g01 * g01;
           const float al = (g11 * r0 - g01 * r1) / det, be = (g00 * r1 - g01 * r0) / det, tot = al + be;
@@ -141,13 +177,13 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
         int J = 0;
         if (cand) {
           P = A + (B - A) * (sa / (sa - sb));
-          nab = cross(A - x, B - x);
+          nab = cross(rel(A), rel(B));
           D1 = dot(nab, e1);
-          w1 = D1 != 0.0f ? -dot(nab, y0 - x) / D1 : -1.0f;
+          w1 = D1 != 0.0f ? -dot(nab, rel(y0)) / D1 : -1.0f;
           yk = p0 + e1 * w1 + e2 * v;
-          const V3 dy = yk - x;
+          const V3 dy = rel(yk);
           dist = sqrtf(dot(dy, dy));
-          const float tau = dot(P - x, dy) / (dist * dist);
+          const float tau = dot(rel(P), dy) / (dist * dist);
           const float dP = tau * dist;
           const bool in_w = w1 > 0.0f && w1 < ell, in_t = tau > 0.0f && dP > kShadowTmin && tau < 1.0f;
           if (DUMP && tau > 0.0f &&
@@ -155,6 +191,8 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
             amb = true;
           cand = in_w && in_t;
           if (cand && DUMP && (near_plane(sa, A) || near_plane(sb, B))) amb = true;
+          // an edge nearly parallel to the line: ill-conditioned position
+          if (cand && DUMP && fabsf(D1) < 2e-3f * sqrtf(dot(nab, nab)) * sqrtf(dot(e1, e1))) amb = true;
         }
         if (cand) {
           // faces of the edge other than x's own triangle, and their sides
@@ -170,12 +208,12 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
             } else {
               (void)ic;
             }
-            const float scq = dot(Nw, Cq - x);
+            const float scq = dot(Nw, rel(Cq));
             if (DUMP && near_plane(scq, Cq)) amb = true;
             const bool with_a = (scq > 0.0f) == (sa > 0.0f);
             const V3 Q = with_a ? B + (Cq - B) * (sb / (sb - scq)) : A + (Cq - A) * (sa / (sa - scq));
-            const float o = dot(cross(P - x, Q - x), Nw);
-            if (DUMP && fabsf(o) < kSeSide * sqrtf(dot(P - x, P - x)) * sqrtf(dot(Q - P, Q - P)) * nN) amb = true;
+            const float o = dot(cross(rel(P), rel(Q)), Nw);
+            if (DUMP && fabsf(o) < kSeSide * sqrtf(dot(rel(P), rel(P))) * sqrtf(dot(Q - P, Q - P)) * nN) amb = true;
             ++n;
             right += o > 0.0f ? 1 : 0;
           }
@@ -185,7 +223,7 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
         // the shadow ray to the jump's light point, the edge's faces and x's triangle excluded
         Ray sr;
         sr.o = x;
-        sr.d = (yk - x) * (1.0f / dist);
+        sr.d = rel(yk) * (1.0f / dist);
         sr.tmin = kShadowTmin;
         sr.tmax = dist;
         ray_setup(sr);
@@ -201,7 +239,7 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
           // h at the jump: the render's light value there (cosine culls included)
           LightSample ls;
           ls.w1 = w1; ls.w2 = v; ls.q = yk;
-          const V3 dq = yk - x;
+          const V3 dq = rel(yk);
           ls.dist2 = dot(dq, dq);
           ls.dist = sqrtf(ls.dist2);
           ls.l = dq * (1.0f / ls.dist);
@@ -218,7 +256,7 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
             const float coef = wgt * kinv / (float)a.S * (float)J * hv * ls.geom;
             if (coef != 0.0f) {
               const float c = -coef / D1;
-              const V3 Ax = A - x, Bx = B - x, Yx = yk - x;
+              const V3 Ax = rel(A), Bx = rel(B), Yx = rel(yk);
               const V3 ga = cross(Bx, Yx) * c, gb = cross(Yx, Ax) * c, gy = nab * c;
               gx_tot = gx_tot - ga - gb - gy;
               gy_tot = gy_tot + gy;

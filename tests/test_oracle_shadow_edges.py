@@ -183,8 +183,8 @@ def test_pick_probabilities_are_exact(oracle_lib):
 
 
 def test_one_pixel_estimator_assembled_by_hand(oracle_lib):
-    """A 1 x 1 image (every camera sample in the one pixel), one square
-    light: each sample i contributes (1/n) (dEdp . h(w1_k, v_i)) J_k
+    """A 1 x 1 image (one tile, every camera sample in the one pixel), one
+    square light: each sample i contributes (1/n) (dEdp . h(w1_k, v_i)) J_k
     dw1_k/dtheta, here for theta = the light's p0, e1, e2 (no path through
     the shading point), h the diffuse light value written out."""
     o = oracle_lib
@@ -205,9 +205,10 @@ def test_one_pixel_estimator_assembled_by_hand(oracle_lib):
     got = o.shadow_edge_grad(sc, dEdp, n, components=1, nthreads=4)
     ctr = np.zeros((n, 4), np.uint32)
     ctr[:, 0] = np.arange(n)
+    ctr[:, 1] = 1
     ctr[:, 2] = 0xC0000000
     ctr[:, 3] = sc.step
-    r = o.philox(sc.seed, ctr)
+    r = o.philox(sc.seed, ctr)          # per sample: camera sample within the (one) tile, line
     normals = o.vertex_normals(sc)
     V = sc.verts.astype(np.float64)
     want = np.zeros(9)
@@ -216,7 +217,7 @@ def test_one_pixel_estimator_assembled_by_hand(oracle_lib):
     nl = -np.cross(e1, e2) / np.linalg.norm(np.cross(e1, e2))
     for i in range(n):
         cs = (int(r[i, 0]) * sc.spp) >> 32
-        v = (int(r[i, 2]) >> 8) / 2.0 ** 24
+        v = (int(r[i, 1]) >> 8) / 2.0 ** 24
         assert got["rec"][i, 0] == cs and got["rec"][i, 1] == 0
         jit = o.philox(sc.seed, np.array([[0, cs, 0, sc.step]], np.uint32))[0]
         fx, fy = (int(jit[0]) >> 8) / 2.0 ** 24, (int(jit[1]) >> 8) / 2.0 ** 24
