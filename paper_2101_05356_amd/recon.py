@@ -192,9 +192,13 @@ class Stage1:
 
     def __init__(self, ctx: R.Context, mt: ModelTensors, target: torch.Tensor, camera: scenes.Camera, spp: int,
                  params0: torch.Tensor, stage0: np.ndarray, sigma_id: np.ndarray, sigma_alb: np.ndarray, seed: int = 4,
-                 edge_samples: int = -1, landmarks=None, w_land: float = 1.0):
+                 edge_samples: int = -1, landmarks=None, w_land: float = 1.0, shadow_edge_samples: int = 0):
         """landmarks: (vertex indices [68], film points [68, 2]) for the
-        landmark term E_land (weight alpha_1 = 1, Sec. 5), or None."""
+        landmark term E_land (weight alpha_1 = 1, Sec. 5), or None.
+        shadow_edge_samples > 0 adds the shadow-edge boundary term (line
+        samples across the lights) to the vertex and light-geometry gradients,
+        so that the light stage also moves the lights by the shadows' edges."""
+        self.shadow_edge_samples = shadow_edge_samples
         dev = mt.mean_geo.device
         self.land = None if landmarks is None else (torch.as_tensor(np.asarray(landmarks[0], np.int32), device=dev),
                                                      torch.as_tensor(np.asarray(landmarks[1], np.float32), device=dev))
@@ -250,6 +254,9 @@ class Stage1:
         E, dEdp = R.loss(img, self.target, smooth=True)
         g = R.render_backward(self.mesh, sc, dEdp, edge_samples=self.edge_samples, verts=self.v_w,
                               groups=("verts", "diffuse", "light_geom", "light_rad"), reuse_forward=True)
+        if self.shadow_edge_samples > 0:
+            R.shadow_edges(self.mesh, sc, dEdp, self.shadow_edge_samples, verts=self.v_w,
+                           out={"verts": g["verts"], "light_geom": g["light_geom"]})
         gx = torch.zeros_like(self.x)
         g_vobj = torch.zeros_like(self.v_obj)
         R.pose_backward(self.v_obj, self.x[sl["pose"]], g["verts"], g_vobj, gx[sl["pose"]])

@@ -103,3 +103,60 @@ def test_stage1_with_landmarks(oracle_lib):
     st._geometry()
     torch.cuda.synchronize()
     assert land() < 0.5 * l0, (l0, land())
+
+
+def test_stage1_with_shadow_edges(oracle_lib):
+    """The shadow-edge term in Stage I: the light-stage gradient with it is the
+    one without it plus the light-stage adjoint of the term's light-geometry
+    gradient, and that gradient matches the oracle's on the same FP32 scene
+    (within 1e-4 of its terms' magnitudes)."""
+    import oracle
+    recon, ctx, mt, cam, n = setup()
+    rng = np.random.default_rng(5)
+    params0 = torch.tensor(np.concatenate([rng.normal(0, 0.5, n - 6), [0.05, -0.05, 0.03, 0.02, -0.02, 0.01]])
+                           .astype(np.float32)).cuda()
+    stage0 = scenes.light_stage_params(d=3.0, a=0.3)
+    target = torch.tensor(scenes.smooth_random_image(rng, 32, 32, 0.0, 0.4)).cuda()
+    ns = 32768
+    outs = []
+    for k in (0, ns):
+        st = recon.Stage1(ctx, mt, target, cam, 4, params0, stage0, np.ones(mt.K_id), np.ones(mt.K_alb),
+                          shadow_edge_samples=k)
+        st.t = 1
+        outs.append((st,) + tuple(st.gradients()))
+    (st0, E0, gx0, gw0), (st1, E1, gx1, gw1) = outs
+    torch.cuda.synchronize()
+    assert float(E0) == float(E1)
+    sc = st1.scene()
+    img = G.R.render_forward(st1.mesh, sc, verts=st1.v_w)
+    _, dEdp = G.R.loss(img, target, smooth=True)
+    gse = G.R.shadow_edges(st1.mesh, sc, dEdp, ns, verts=st1.v_w, groups=("light_geom",))["light_geom"]
+    extra = G.R.light_stage_backward(st1.faces, st1.w, gse, torch.zeros_like(sc.light_rad))
+    torch.cuda.synchronize()
+    d, e = G.to_np(gw1 - gw0), G.to_np(extra)
+    assert np.abs(e).sum() > 0
+    assert np.allclose(d, e, rtol=1e-3, atol=1e-5 * np.abs(e).max())
+    osc = scenes.Scene(verts=G.to_np(st1.v_w).reshape(-1, 3), tris=mt.tris, diffuse=G.to_np(st1.diffuse).reshape(-1, 3),
+                       specular=G.to_np(mt.specular), roughness=G.to_np(mt.roughness),
+                       lights=scenes.Lights(p0=G.to_np(sc.light_p0), e1=G.to_np(sc.light_e1), e2=G.to_np(sc.light_e2),
+                                            rad=G.to_np(sc.light_rad), shape=G.to_np(sc.light_shape)),
+                       camera=cam, spp=4, seed=4, step=1)
+    # samples either side flags as near-ambiguous leave with their pixels' dE/dp
+    w = G.to_np(dEdp).reshape(-1, 3).copy()
+    dump = G.R.shadow_edges(st1.mesh, sc, dEdp, ns, verts=st1.v_w, groups=("light_geom",), dump=True)
+    torch.cuda.synchronize()
+    eo = oracle.shadow_edge_grad(osc, w.astype(np.float64), ns)
+    rec = G.to_np(dump["rec"])
+    assert np.array_equal(rec[:, :2], eo["rec"][:, :2])
+    flag = (G.to_np(dump["flag"]) != 0) | (eo["flag"] != 0)
+    w[np.unique(rec[flag, 0] // 4)] = 0.0
+    w64 = w.astype(np.float64)
+    eo = oracle.shadow_edge_grad(osc, w64, ns)
+    mag = oracle.shadow_edge_grad(osc, w64, ns, abs_terms=True)
+    gse2 = G.R.shadow_edges(st1.mesh, sc, torch.tensor(w.reshape(dEdp.shape)).cuda(), ns, verts=st1.v_w,
+                            groups=("light_geom",))["light_geom"]
+    torch.cuda.synchronize()
+    assert np.abs(eo["light"]).sum() > 0
+    got = G.to_np(gse2).astype(np.float64).ravel()
+    err = np.linalg.norm(got - eo["light"].ravel()) / np.linalg.norm(mag["light"].ravel())
+    assert err < 1e-4, err
