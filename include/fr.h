@@ -310,7 +310,10 @@ int fr_render_backward(fr_mesh* mesh, const fr_scene* scene, const fr_render_opt
  * shadow ray to y(w1_k, v) otherwise free), kappa^-1 (1/spp) (dEdp[pixel] .
  * h) J_k dw1_k/dtheta / (n_samples p), J_k = V(w1_k-) - V(w1_k+), p the
  * exact probability of the two draws.  Lights at infinity contribute nothing
- * here (their shadows are hard: a screen-space term, not built).  Manifold
+ * here (their shadows are hard: a screen-space term, not built); nor does
+ * a sample whose light is wholly below x's tangent plane (every corner 1e-4
+ * below) or whose x is behind the light (1e-3 of its area-normal size): h = 0
+ * on its line, so it records no jumps and skips the walk.  Manifold
  * meshes (an edge with more than two faces is not supported).  Call after
  * fr_render_forward of the same scene (the traversal uses its tree).
  * d_dEdp [H*W*3] device.  d_rec [n*4] / d_flag [n] (nullable, together):

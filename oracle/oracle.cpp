@@ -1409,6 +1409,21 @@ int oracle_shadow_edge_grad(const OrScene* sc, int32_t n_samples, const double* 
     const double cos_o = dot(fr.ns, fr.wo);
     if (std::fabs(cos_o) < kFlagEps) fl |= FLAG_COSO;
     if (!(cos_o > 0.0)) { done(); return; }
+    // a light wholly below the tangent plane at x (every corner lower than
+    // 1e-4), or x behind the light's emitting plane (by more than 1e-3 of the
+    // light's area-normal size): h = 0 on the whole line, the sample is skipped
+    {
+      const LightParams<double> Lc = light_params_d(s, j);
+      const V3 d0 = Lc.p0 - fr.x;
+      const double ca = dot(fr.ns, d0), cb = dot(fr.ns, Lc.e1), cc = dot(fr.ns, Lc.e2);
+      double top = std::max({ca, ca + cb, ca + cc});
+      if (Lc.shape != 1) top = std::max(top, ca + cb + cc);
+      const double kap = Lc.shape == 1 ? 0.5 : 1.0;
+      const V3 na = cross(Lc.e1, Lc.e2) * (-kap);
+      const double side = dot(na, d0), alen = std::fabs(na.x) + std::fabs(na.y) + std::fabs(na.z);
+      if (std::fabs(top + 1e-4) < 1e-6 || std::fabs(side + 1e-3 * alen) < 1e-6 * (1.0 + alen)) fl |= FLAG_COSL;
+      if (top < -1e-4 || side < -1e-3 * alen) { done(); return; }
+    }
     const std::vector<ShadowJump> js = shadow_jumps(s, P.tg, nb, fr.x, h.id, j, v, &fl);
     if (js.empty()) { done(); return; }
     // the shading point as a function of the hit triangle and the camera

@@ -72,6 +72,20 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
   if (DUMP && valid && h.id >= 0 && fabsf(fr.cos_o) < kFlagCos) amb = true;
   LightRec Lj = load_const(a.lights, max(j, 0));
   shaded = shaded && j >= 0 && Lj.shape != FR_LIGHT_DIRECTIONAL;
+  // a light wholly below x's tangent plane, or x behind the light's emitting
+  // plane (by the render's cull margins), gives h = 0 on every line: no walk
+  if (shaded) {
+    const V3 d0 = {Lj.p0[0] - fr.x.x, Lj.p0[1] - fr.x.y, Lj.p0[2] - fr.x.z};
+    const float ca = dot(fr.ns, d0);
+    const float cb = fr.ns.x * Lj.e1[0] + fr.ns.y * Lj.e1[1] + fr.ns.z * Lj.e1[2];
+    const float cc = fr.ns.x * Lj.e2[0] + fr.ns.y * Lj.e2[1] + fr.ns.z * Lj.e2[2];
+    float top = fmaxf(ca, fmaxf(ca + cb, ca + cc));
+    if (Lj.shape != FR_LIGHT_TRIANGLE) top = fmaxf(top, ca + cb + cc);
+    const float side = Lj.na[0] * d0.x + Lj.na[1] * d0.y + Lj.na[2] * d0.z;
+    const float alen = fabsf(Lj.na[0]) + fabsf(Lj.na[1]) + fabsf(Lj.na[2]);
+    if (DUMP && (fabsf(top + 1e-4f) < 1e-5f || fabsf(side + 1e-3f * alen) < 1e-5f * (1.0f + alen))) amb = true;
+    shaded = !(top < -1e-4f) && !(side < -1e-3f * alen);
+  }
   // the wedge: x and the line y0 -> y1 = y0 + ell e1 on the light
   const V3 p0 = {Lj.p0[0], Lj.p0[1], Lj.p0[2]}, e1 = {Lj.e1[0], Lj.e1[1], Lj.e1[2]},
            e2 = {Lj.e2[0], Lj.e2[1], Lj.e2[2]};
