@@ -98,6 +98,8 @@ def lib():
         L.oracle_sh_cosine_coeff.restype = ctypes.c_double
         L.oracle_g1_of_a.argtypes = [ctypes.c_double]
         L.oracle_g1_of_a.restype = ctypes.c_double
+        L.oracle_pick_prob.argtypes = [ctypes.c_int64, ctypes.c_int64]
+        L.oracle_pick_prob.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -284,6 +286,12 @@ def shadow_edge_grad(scene, dEdp_full, n_samples, brdf_variant=0, components=3, 
     lib().oracle_shadow_edge_grad(b.ref, int(n_samples), _ptr(g), _ptr(gv), _ptr(gl), _ptr(gc), _ptr(rec),
                                   _ptr(flag), nthreads or default_threads(), int(bool(abs_terms)))
     return dict(verts=gv, light=gl[:L], cam=gc, rec=rec, flag=flag)
+
+
+def pick_prob(i: int, n: int) -> float:
+    """Probability that floor(r n / 2^32) == i for r uniform over the 2^32
+    values of a 32-bit word (the shadow-edge estimator's draw weights)."""
+    return float(lib().oracle_pick_prob(int(i), int(n)))
 
 
 def shadow_jumps(scene, x, self_tri, light, v, cap=64):

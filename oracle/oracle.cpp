@@ -1498,6 +1498,10 @@ int oracle_shadow_edge_grad(const OrScene* sc, int32_t n_samples, const double* 
 // ---------------------------------------------------------------------------
 extern "C" {
 
+// Exact probability of the index floor(r n / 2^32) == i over the 2^32
+// values of r, as the shadow-edge estimator weights its draws.
+double oracle_pick_prob(int64_t i, int64_t n) { return pick_prob(i, n); }
+
 // World-space unit direction of the camera ray through film point (fx, fy).
 void oracle_camera_ray(const OrScene* sc, double fx, double fy, double* out_d) {
   const Prepared P = prepare(sc);

@@ -6,7 +6,11 @@ on a line w2 = v, d/dtheta of int h V dw1 gains sum_k h(w1_k) J_k
 dw1_k/dtheta at the jumps of V.  Pinned against independent brute force: V
 sampled by single shadow-ray casts, jump positions by central differences,
 the Leibniz identity by bisection-located visible intervals and quadrature,
-and the sampling weights by assembling a one-pixel estimator by hand."""
+the draw probabilities by exact integer counts, the sampling weights by
+assembling the estimator by hand (one pixel; a ragged multi-tile image with
+three lights, with the shading point's path to its triangle and the
+camera), and the whole term by unfrozen central differences of the render
+on a self-shadowing patch (statistical, three standard errors)."""
 import dataclasses
 import math
 
@@ -171,15 +175,181 @@ def test_leibniz_identity_on_a_line(oracle_lib):
         assert math.isclose(fd, an, rel_tol=1e-3, abs_tol=1e-6), (fd, an)
 
 
+def _count(i, n):
+    """Number of 32-bit words r with floor(r n / 2^32) == i: the r in
+    [ceil(i 2^32 / n), ceil((i + 1) 2^32 / n)), in exact integers."""
+    return _ceil_div((i + 1) << 32, n) - _ceil_div(i << 32, n)
+
+
+def _ceil_div(a, n):
+    return -((-a) // n)
+
+
 def test_pick_probabilities_are_exact(oracle_lib):
-    """floor(r n / 2^32) over all 2^32 values of r, counted in closed form,
-    sums to one; the oracle's light gradient weights use these counts."""
-    for n in (1, 3, 7, 1000, 65536 * 16, 1 << 31):
-        counts = [((((i + 1) << 32) + n - 1) // n) - (((i << 32) + n - 1) // n) for i in (0, n // 2, n - 1)]
-        assert all(c in (2 ** 32 // n, -(-2 ** 32 // n)) for c in counts)
-        lo = 2 ** 32 // n
-        # the number of indices with the larger count is 2^32 - n * lo
-        assert lo * n + (2 ** 32 - lo * n) == 2 ** 32
+    """The oracle's draw probabilities (the weights 1 / (n p) of the
+    shadow-edge estimator) against counts made by hand: for n = 3 the words
+    r <= 1431655765 (= floor((2^32 - 1) / 3)) give index 0, so p(0) =
+    1431655766 / 2^32 and p(1) = p(2) = 1431655765 / 2^32; powers of two
+    divide 2^32 evenly; and for every n the probabilities of all indices sum
+    to one.  The counting rule itself is checked by brute force over every
+    word of a 16-bit analogue."""
+    o = oracle_lib
+    two32 = 2.0 ** 32
+    assert o.pick_prob(0, 3) == 1431655766 / two32
+    assert o.pick_prob(1, 3) == 1431655765 / two32 and o.pick_prob(2, 3) == 1431655765 / two32
+    for k in (0, 1, 5, 12, 31):
+        assert all(o.pick_prob(i, 2 ** k) == 2.0 ** -k for i in (0, 2 ** k - 1))
+    for n in (5, 6, 7, 20 * 13 * 2, 1000, 65536 * 16 + 3):
+        idx = range(n) if n <= 2000 else (0, 1, n // 2, n - 1)
+        for i in idx:
+            assert o.pick_prob(i, n) == _count(i, n) / two32
+            assert abs(o.pick_prob(i, n) - 1.0 / n) <= 1.0 / two32
+        if n <= 2000:
+            assert sum(_count(i, n) for i in range(n)) == 2 ** 32
+    # the same rule at 16 bits, against every word
+    for n in (3, 6, 7, 20, 321):
+        r = np.arange(2 ** 16, dtype=np.int64)
+        got = np.bincount((r * n) >> 16, minlength=n)
+        want = [_ceil_div((i + 1) << 16, n) - _ceil_div(i << 16, n) for i in range(n)]
+        assert np.array_equal(got, want)
+
+
+def _film_dir(cam, W, H, fx, fy):
+    """Camera-space direction through film point (fx, fy), in pixels: the
+    pinhole of Sec. 3.1 (vertical field of view, y down on the film)."""
+    th = math.tan(0.5 * float(cam.fov_y))
+    return np.array([(2.0 * fx / W - 1.0) * th * W / H, (1.0 - 2.0 * fy / H) * th, -1.0])
+
+
+def _hit_point(V3x3, R, T, dc):
+    """Crossing of the camera ray T + t R dc / |R dc| with the plane of the
+    triangle V3x3 (rows v0, v1, v2), in FP64."""
+    d = R @ dc
+    d = d / np.linalg.norm(d)
+    n = np.cross(V3x3[1] - V3x3[0], V3x3[2] - V3x3[0])
+    t = ((V3x3[0] - T) @ n) / (d @ n)
+    return T + t * d
+
+
+def test_multitile_multilight_estimator_assembled_by_hand(oracle_lib):
+    """A ragged 20 x 13 image (3 x 2 tiles of 8 x 8, the right column 4 wide
+    and the bottom row 5 high), 2 spp, three square lights: every term of
+    the shadow-edge estimator written out from its definition.  Group g =
+    i // 64 draws its tile (n = 6) and light (n = 3); sample i draws its
+    camera sample among the tile's tw th S and its line v.  Each jump adds
+    (1/S) (dEdp . h) J dw1/dtheta / (n_samples p(tile) p(k | tile) p(j)),
+    with the probabilities counted in integers here, h the diffuse light
+    value, dw1/d(a, b, p0, e1, e2) to the occluder edge and the light, and
+    dw1/dx chained to the shading triangle and the camera through the
+    crossing of the camera ray with the triangle's plane, differentiated by
+    central differences.  A wrong marginal for the clipped tiles or for the
+    light would change the light, vertex and camera sums."""
+    from tests.test_oracle_grad import tilt_camera
+    o = oracle_lib
+    base = bump_scene()
+    lt = base.lights
+    sel = [3, 6, 7]
+    lights = scenes.Lights(p0=lt.p0[sel], e1=lt.e1[sel], e2=lt.e2[sel], rad=lt.rad[sel], shape=lt.shape[sel])
+    sc = tilt_camera(dataclasses.replace(base, lights=lights, spp=2))
+    sc.camera = dataclasses.replace(sc.camera, W=20, H=13)
+    W, H, S, L = 20, 13, 2, 3
+    n = 64 * 128
+    rng = np.random.default_rng(4)
+    dEdp = rng.normal(size=(H * W, 3))
+    got = o.shadow_edge_grad(sc, dEdp, n, components=1, nthreads=8)
+    tx, ty = 3, 2
+    cg = np.zeros((n // 64, 4), np.uint32)
+    cg[:, 0] = np.arange(n // 64)
+    cg[:, 2] = 0xC0000000
+    cg[:, 3] = sc.step
+    rg = o.philox(sc.seed, cg)
+    cs_ = np.zeros((n, 4), np.uint32)
+    cs_[:, 0] = np.arange(n)
+    cs_[:, 1] = 1
+    cs_[:, 2] = 0xC0000000
+    cs_[:, 3] = sc.step
+    r = o.philox(sc.seed, cs_)
+    V = sc.verts.astype(np.float64)
+    normals = o.vertex_normals(sc)
+    R, T = sc.camera.R.astype(np.float64), sc.camera.T.astype(np.float64)
+    want_l = np.zeros((L, 9))
+    want_v = np.zeros_like(V)
+    want_c = np.zeros(12)
+    clipped = used = 0
+    used_lights = set()
+    for i in range(n):
+        g0, g1 = int(rg[i // 64, 0]), int(rg[i // 64, 1])
+        tile, j = (g0 * tx * ty) >> 32, (g1 * L) >> 32
+        x0, y0 = 8 * (tile % tx), 8 * (tile // tx)
+        tw, tht = min(8, W - x0), min(8, H - y0)
+        n_in = tw * tht * S
+        k = (int(r[i, 0]) * n_in) >> 32
+        pid = (y0 + (k // S) // tw) * W + x0 + (k // S) % tw
+        s = k % S
+        assert got["rec"][i, 0] == pid * S + s and got["rec"][i, 1] == j
+        v = (int(r[i, 1]) >> 8) / 2.0 ** 24
+        p = _count(tile, tx * ty) * _count(k, n_in) * _count(j, L) / 2.0 ** 96
+        jit = o.philox(sc.seed, np.array([[pid, s, 0, sc.step]], np.uint32))[0]
+        fx, fy = pid % W + (int(jit[0]) >> 8) / 2.0 ** 24, pid // W + (int(jit[1]) >> 8) / 2.0 ** 24
+        dc = _film_dir(sc.camera, W, H, fx, fy)
+        d = R @ dc
+        d = d / np.linalg.norm(d)
+        assert np.allclose(d, o.camera_ray(sc, fx, fy), rtol=0, atol=1e-14)
+        hid, _, t, bu, bv = o.closest_hit(sc, T, d)
+        if hid < 0:
+            continue
+        vi = sc.tris[hid]
+        x = (1 - bu - bv) * V[vi[0]] + bu * V[vi[1]] + bv * V[vi[2]]
+        m = (1 - bu - bv) * normals[vi[0]] + bu * normals[vi[1]] + bv * normals[vi[2]]
+        ns = m / np.linalg.norm(m)
+        if ns @ -d <= 0:
+            continue
+        c = (1 - bu - bv) * sc.diffuse[vi[0]] + bu * sc.diffuse[vi[1]] + bv * sc.diffuse[vi[2]]
+        p0, e1, e2 = (a[j].astype(np.float64) for a in (lights.p0, lights.e1, lights.e2))
+        nl = -np.cross(e1, e2) / np.linalg.norm(np.cross(e1, e2))
+        js = o.shadow_jumps(sc, x, hid, j, v)
+        gx = np.zeros(3)
+        for w1, J, e, g in zip(js["w1"], js["J"], js["edge"], js["grad"]):
+            y = p0 + w1 * e1 + v * e2
+            dist = np.linalg.norm(y - x)
+            l = (y - x) / dist
+            cos_s, cos_l = ns @ l, nl @ l
+            if cos_s <= 0 or cos_l <= 0:
+                continue
+            hv = lights.rad[j] * c / math.pi * cos_s * cos_l * np.linalg.norm(np.cross(e1, e2)) / dist ** 2
+            coef = (dEdp[pid] @ hv) * J / S / (n * p)
+            want_l[j] += coef * g[9:18]
+            want_v[e[0]] += coef * g[0:3]
+            want_v[e[1]] += coef * g[3:6]
+            gx += coef * g[6:9]
+            used_lights.add(j)
+            used += 1
+            clipped += int(tw < 8 or tht < 8)
+        if not gx.any():
+            continue
+        # x as a function of the triangle's vertices and the camera (R, T)
+        tri = V[vi].copy()
+        hh = 1e-6
+        for q in range(9):
+            dp, dm = tri.copy(), tri.copy()
+            dp.flat[q] += hh
+            dm.flat[q] -= hh
+            want_v[vi[q // 3], q % 3] += gx @ (_hit_point(dp, R, T, dc) - _hit_point(dm, R, T, dc)) / (2 * hh)
+        for q in range(12):
+            Rp, Rm, Tp, Tm = R.copy(), R.copy(), T.copy(), T.copy()
+            if q < 9:
+                Rp.flat[q] += hh
+                Rm.flat[q] -= hh
+            else:
+                Tp[q - 9] += hh
+                Tm[q - 9] -= hh
+            want_c[q] += gx @ (_hit_point(tri, Rp, Tp, dc) - _hit_point(tri, Rm, Tm, dc)) / (2 * hh)
+    print("jumps used:", used, "in clipped tiles:", clipped)
+    assert used_lights == {0, 1, 2} and clipped >= 5 and used - clipped >= 5
+    assert np.abs(want_l).sum() > 0 and np.abs(want_c).sum() > 0
+    assert np.allclose(got["light"], want_l, rtol=1e-6, atol=1e-8 * np.abs(want_l).max())
+    assert np.allclose(got["verts"], want_v, rtol=1e-5, atol=1e-7 * np.abs(want_v).max())
+    assert np.allclose(got["cam"], want_c, rtol=1e-5, atol=1e-7 * np.abs(want_c).max())
 
 
 def test_one_pixel_estimator_assembled_by_hand(oracle_lib):
@@ -248,3 +418,59 @@ def test_one_pixel_estimator_assembled_by_hand(oracle_lib):
     # the hand-built shading point comes from the closest-hit solve, the
     # oracle's from the shading frame's: equal to ~1e-9, amplified in w1
     assert np.allclose(got["light"][0], want, rtol=1e-6, atol=1e-9 * np.abs(want).max())
+
+
+@pytest.mark.slow
+def test_interior_plus_both_boundary_terms_match_unfrozen_difference(oracle_lib):
+    """The self-shadowing bump patch (24 x 24, 16 spp, its 8 square lights,
+    a tilted camera): the unfrozen central difference of E = sum w . p,
+    with every decision recomputed on both sides, averaged over independent
+    sample sequences (the step counter), agrees within three standard errors
+    with the interior term plus the primary-visibility and shadow-edge
+    boundary terms, for two directions: every light translated (the shadows
+    slide over the patch; no primary edge moves) and the bump's height
+    scaled (occluder vertices move; the shadows change shape).  Without the
+    shadow-edge term both checks fail by more than five standard errors, so
+    the check covers the term's weights and sign end to end."""
+    import math as _m
+    from tests.test_oracle_grad import tilt_camera
+    o = oracle_lib
+    base = tilt_camera(scenes.patch_scene(W=24, H=24, spp=16))
+    rng = np.random.default_rng(10)
+    wimg = (1.0 + 0.5 * scenes.smooth_random_image(rng, 24, 24, -1.0, 1.0)).astype(np.float64).reshape(-1, 3)
+    v = base.verts.astype(np.float64)
+    L = base.lights.count
+    dl = np.zeros((L, 9))
+    dl[:, 0], dl[:, 1] = 1.0, 0.5
+    tz = np.zeros_like(v)
+    tz[:, 2] = v[:, 2]
+    h = 2.0 ** -7
+    for name in ("lights", "height"):
+        rows = []
+        for step in range(48):
+            sc = dataclasses.replace(base, step=step)
+            if name == "lights":
+                def mk(s_):
+                    p0 = (sc.lights.p0.astype(np.float64) + s_ * dl[:, :3]).astype(np.float32)
+                    return dataclasses.replace(sc, lights=dataclasses.replace(sc.lights, p0=p0))
+            else:
+                def mk(s_):
+                    return dataclasses.replace(sc, verts=(v + s_ * tz).astype(np.float32))
+            fd = ((o.render(mk(h))["rgb"] - o.render(mk(-h))["rgb"]) * wimg).sum() / (2 * h)
+            dec = o.render(sc)
+            gi = o.grad(sc, dec["hit"], dec["vis"], wimg)
+            se = o.shadow_edge_grad(sc, wimg, 20000)
+            if name == "lights":
+                rows.append((fd, float((gi["light"] * dl).sum()), 0.0, float((se["light"] * dl).sum())))
+            else:
+                pe = o.edge_grad(sc, wimg, n_samples=20000)
+                rows.append((fd, float((gi["verts"] * tz).sum()), float((pe["verts"] * tz).sum()),
+                             float((se["verts"] * tz).sum())))
+        d = np.array(rows)
+        resid = d[:, 0] - d[:, 1] - d[:, 2] - d[:, 3]
+        without = d[:, 0] - d[:, 1] - d[:, 2]
+        sem = resid.std(ddof=1) / _m.sqrt(len(resid))
+        sem_w = without.std(ddof=1) / _m.sqrt(len(resid))
+        print(name, "means (difference, interior, primary, shadow):", d.mean(0), "residual", resid.mean(), "sem", sem)
+        assert abs(resid.mean()) < 3 * sem, (name, d.mean(0), sem)
+        assert abs(without.mean()) > 5 * sem_w, (name, d.mean(0), sem_w)
