@@ -199,9 +199,21 @@ typedef struct {
    * either way. */
   int32_t reuse_forward;
   /* fr_render_forward only: nonzero also keeps the shadow decision of every
-   * sample and light (one bit each, held by the mesh: 4 bytes per sample and
+   * sample and light (one bit each, in the workspace: 4 bytes per sample and
    * chunk of light_chunk lights) for a backward with reuse_forward. */
   int32_t keep_shadows;
+  int32_t pad_;
+  /* Device scratch of the call (required): caller-owned device memory on the
+   * mesh's device, 256-byte aligned, at least the bytes
+   * fr_render_workspace_size gives for this scene and options.  No render
+   * call allocates device memory.  The workspace also carries a forward's
+   * decisions (camera-ray hits, kept shadow masks) to a backward with
+   * reuse_forward: pass both calls the same workspace.  Calls that may run at
+   * the same time (other streams, other threads) need distinct workspaces;
+   * with distinct workspaces, calls on one mesh may overlap (the mesh is only
+   * read by render calls; fr_mesh_update must not overlap them). */
+  void* workspace;
+  size_t workspace_bytes;
 } fr_render_opts;
 
 /* Gradients of a backward pass; every pointer is nullable ("not requested")
@@ -223,6 +235,16 @@ typedef struct {
   float* sh;            /* [B*B*3] SH coefficients (fr_scene.sh_bands > 0) */
 } fr_grads;
 
+/* Bytes of the workspace (fr_render_opts.workspace) that fr_render_forward,
+ * fr_render_backward and fr_shadow_edges need for scenes of this size
+ * (width, height, spp, n_lights, tex_size, sh_bands) under these options
+ * (light_chunk; keep_shadows adds the forward's kept shadow masks) on this
+ * mesh.  One workspace of this size serves all three calls.  Sec. 4 Eq.
+ * energy: the render and its gradient, whose per-call state (camera-ray hits,
+ * light table, partial images, fixed-point gradient sums) lives here.
+ * FR_ERR_INVALID_ARG on a null pointer or a non-positive size. */
+int fr_render_workspace_size(const fr_mesh* mesh, const fr_scene* scene, const fr_render_opts* opts, size_t* bytes);
+
 /* Forward render (Sec. 4 Eq. energy: p^S = F(chi), the Monte-Carlo estimate
  * of the rendering equation with direct light only, shadows by shadow rays,
  * Sec. 3.3 "Shadows approximation"; Cook-Torrance BRDF of Appendix A).
@@ -235,11 +257,15 @@ int fr_render_forward(fr_mesh* mesh, const fr_scene* scene, const fr_render_opts
 
 /* Photometric loss (Sec. 4 Eq. energy and "Variance Reduction"): optional
  * 3x3 Gaussian smoothing (sigma 1, clamp-to-edge) of d_image, then
- * E = sum |p~ - p^R| over pixels and channels (FP64 accumulation).
- * d_loss [1] float receives E (overwritten); d_dEdp [H*W*3] (nullable)
- * receives dE/dp = K^T * sign(p~ - p^R) (overwritten). */
+ * E = sum |p~ - p^R| over pixels and channels (FP64 accumulation in a fixed
+ * order).  d_loss [1] float receives E (overwritten); d_dEdp [H*W*3]
+ * (nullable) receives dE/dp = K^T * sign(p~ - p^R) (overwritten).  d_work:
+ * caller-owned device scratch, 256-byte aligned, of at least
+ * fr_loss_workspace_size(width, height, smooth) bytes (FR_ERR_SHAPE if
+ * smaller); calls that may overlap need distinct scratch. */
+size_t fr_loss_workspace_size(int32_t width, int32_t height, int32_t smooth);
 int fr_loss(const float* d_image, const float* d_target, int32_t width, int32_t height, int32_t smooth,
-            float* d_loss, float* d_dEdp, fr_stream stream);
+            float* d_loss, float* d_dEdp, void* d_work, size_t work_bytes, fr_stream stream);
 
 /* Stage II regularisers of the personalised reflectance maps (Sec. 4
  * "Stage II", Eq. loss3; the paper's weights are w_sym = w_chroma = 0.3,
@@ -251,8 +277,10 @@ int fr_loss(const float* d_image, const float* d_target, int32_t width, int32_t 
  * M - 1 - i), E_c the L1 difference of chromaticities x / (x_r + x_g + x_b +
  * 1e-6) to the Stage I maps C0, S0, E_m the squared differences of each
  * texel to its in-map 4-neighbours, E_b the squared excess outside [0, 1].
- * d_loss [1] float is overwritten (FP64 sums); the gradients (nullable) are
- * accumulated (+=). */
+ * d_loss [1] float is overwritten (FP64 sums in a fixed order); the
+ * gradients (nullable) are accumulated (+=).  d_work: caller-owned device
+ * scratch, 256-byte aligned, of at least fr_map_regularizers_workspace_size(M)
+ * bytes (FR_ERR_SHAPE if smaller). */
 typedef struct { float w_sym, w_chroma, w_smooth, w_box; } fr_map_reg_weights;
 
 /* Stage I priors (Sec. 4 "Stage I", Eq. loss1; Sec. 5 weights w_i = w_c =
@@ -261,7 +289,9 @@ typedef struct { float w_sym, w_chroma, w_smooth, w_box; } fr_map_reg_weights;
  *   FR_PRIOR_BOX          weight sum (min(x, 0)^2 + max(x - 1, 0)^2);
  *   FR_PRIOR_LIGHT_CHROMA weight sum_j ||I_j - mean_c I_j||^2 over the n / 3
  *                         RGB intensities I_j (d_sigma unused).
- * d_loss [1] float is overwritten (FP64 sums); d_g (nullable) += dE/dx. */
+ * d_loss [1] float is overwritten (FP64 sums in a fixed order, one
+ * workgroup: meant for parameter vectors, not images); d_g (nullable)
+ * += dE/dx.  No scratch memory. */
 enum { FR_PRIOR_STATISTICAL = 0, FR_PRIOR_BOX = 1, FR_PRIOR_LIGHT_CHROMA = 2 };
 
 /* Landmark loss (Sec. 4 Eq. landmark): sum_l || Pi(v_l) - z_l ||^2 over n
@@ -274,9 +304,10 @@ int fr_landmark_loss(const float* d_verts, const int32_t* d_idx, int32_t n, cons
                      int32_t H, const float* d_z, float* d_loss, float* d_gverts, float* d_gcam, fr_stream stream);
 int fr_prior(const float* d_x, const float* d_sigma, int32_t n, int32_t kind, float weight, float* d_loss, float* d_g,
              fr_stream stream);
+size_t fr_map_regularizers_workspace_size(int32_t M);
 int fr_map_regularizers(const float* d_c, const float* d_s, const float* d_r, const float* d_c0, const float* d_s0,
                         int32_t M, const fr_map_reg_weights* weights, float* d_loss, float* d_gc, float* d_gs,
-                        float* d_gr, fr_stream stream);
+                        float* d_gr, void* d_work, size_t work_bytes, fr_stream stream);
 
 /* Backward pass: the adjoint of fr_render_forward for a given dE/dp
  * d_dEdp [H*W*3], recomputing every intersection and shadow decision from the
@@ -291,7 +322,7 @@ int fr_map_regularizers(const float* d_c, const float* d_s, const float* d_r, co
  * Any number of lights: more than 128 are taken in groups of 128, one
  * adjoint and one boundary-term launch per group (the sample-level chain
  * is linear in the summed per-light adjoints, so the groups' chains add).
- * Uses the mesh's internal scratch; calls on one mesh must not overlap. */
+ * Scratch and the forward's decisions come from opts->workspace. */
 int fr_render_backward(fr_mesh* mesh, const fr_scene* scene, const fr_render_opts* opts, const float* d_dEdp,
                        fr_grads* grads, fr_stream stream);
 
@@ -301,26 +332,31 @@ int fr_render_backward(fr_mesh* mesh, const fr_scene* scene, const fr_render_opt
  * and ->cam (the other fields are ignored; each pointer nullable).  Light j
  * seen from a shading point x contributes kappa^-1 int int h V dw1 dw2 over
  * its parameters (y = p0 + w1 e1 + w2 e2; kappa = 1 parallelogram, 1/2
- * triangle; h the render's per-sample light value).  Sample i draws, from
- * Philox counter (i, 0, 0xC0000000, step), a camera sample uniformly over the
- * W*H*spp (word 0: floor(r n / 2^32)), a light uniformly (word 1) and a line
- * w2 = v (word 2, 24 bits), traces the camera ray, and adds, for each jump
- * w1_k of V along the line (an occluder edge crossing the wedge from x to the
- * line, its faces other than x's triangle on one side as seen from x, the
- * shadow ray to y(w1_k, v) otherwise free), kappa^-1 (1/spp) (dEdp[pixel] .
- * h) J_k dw1_k/dtheta / (n_samples p), J_k = V(w1_k-) - V(w1_k+), p the
- * exact probability of the two draws.  Lights at infinity contribute nothing
- * here (their shadows are hard: a screen-space term, not built); nor does
- * a sample whose light is wholly below x's tangent plane (every corner 1e-4
- * below) or whose x is behind the light (1e-3 of its area-normal size): h = 0
- * on its line, so it records no jumps and skips the walk.  Manifold
+ * triangle; h the render's per-sample light value).  Samples come in groups
+ * of 64: group g draws, from Philox counter (g, 0, 0xC0000000, step), an
+ * 8 x 8 pixel tile (word 0: floor(r n_tiles / 2^32); tiles at the right and
+ * bottom borders are clipped to the image) and a light (word 1, the same
+ * rule over n_lights); sample i of the group draws, from counter (i, 1,
+ * 0xC0000000, step), a camera sample among the tile's pixels and samples
+ * (word 0) and the line w2 = v (word 1, its top 24 bits).  Each sample traces
+ * its camera ray and adds, for each jump w1_k of V along the line (an
+ * occluder edge crossing the wedge from x to the line, its faces other than
+ * x's triangle on one side as seen from x, the shadow ray to y(w1_k, v)
+ * otherwise free), kappa^-1 (1/spp) (dEdp[pixel] . h) J_k dw1_k/dtheta /
+ * (n_samples p), J_k = V(w1_k-) - V(w1_k+), p = p(tile) p(camera sample |
+ * tile) p(light), each the exact probability of its draw (the count of
+ * 32-bit words that select it, over 2^32).  Lights at infinity contribute
+ * nothing here (their shadows are hard: a screen-space term, not built); nor
+ * does a sample whose light is wholly below x's tangent plane (every corner
+ * 1e-4 below) or whose x is behind the light (1e-3 of its area-normal size):
+ * h = 0 on its line, so it records no jumps and skips the walk.  Manifold
  * meshes (an edge with more than two faces is not supported).  Call after
- * fr_render_forward of the same scene (the traversal uses its tree).
+ * fr_mesh_update of the same vertices (the walk uses the mesh's tree).
  * d_dEdp [H*W*3] device.  d_rec [n*4] / d_flag [n] (nullable, together):
  * per sample (camera sample, light, jumps that passed the occlusion test,
  * sum of their edges' lower vertex id * N + upper id, mod 2^31) and 1 when a
  * decision was near-ambiguous.  Requires W*H*spp < 2^31 (FR_ERR_LIMIT).
- * Uses the mesh's internal scratch; calls on one mesh must not overlap. */
+ * Scratch from opts->workspace (a forward's kept decisions there stay). */
 int fr_shadow_edges(fr_mesh* mesh, const fr_scene* scene, const fr_render_opts* opts, const float* d_dEdp,
                     int32_t n_samples, fr_grads* grads, int32_t* d_rec, uint8_t* d_flag, fr_stream stream);
 
@@ -360,6 +396,13 @@ int fr_light_stage(const float* d_faces, const float* d_params, int32_t n_lights
  * of fr_grads) and d_g_rad [J*3] (each nullable). */
 int fr_light_stage_backward(const float* d_faces, const float* d_params, int32_t n_lights, const float* d_g_geom,
                             const float* d_g_rad, float* d_gparams, fr_stream stream);
+
+/* d_y[i] += a * s * d_x[i], i < n, with s = d_s[0] (a device scalar, e.g. the
+ * upstream gradient of a loss) or 1 when d_s is NULL: how an optimisation
+ * step adds up the terms of its objective (Sec. 4 Eq. loss1, Eq. loss3) and
+ * their gradients on the device.  Device pointers; d_y and d_x must not
+ * overlap unless equal. */
+int fr_axpy(float* d_y, const float* d_x, float a, const float* d_s, int32_t n, fr_stream stream);
 
 /* Adam (Sec. 5 "Implementation Details": beta1 0.9, beta2 0.999, one learning
  * rate per parameter group), step number t >= 1, per-element learning rate

@@ -78,7 +78,8 @@ def lib():
         L.oracle_render.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, ctypes.c_int32]
         L.oracle_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int32,
                                   ctypes.c_int32, P]
-        L.oracle_edge_grad.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_int32]
+        L.oracle_edge_grad.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_int32,
+                                       ctypes.c_int32]
         L.oracle_shadow_jumps.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                           P, P, P, P, P]
         L.oracle_shadow_jumps.restype = ctypes.c_int32
@@ -249,11 +250,14 @@ def edge_count(scene) -> int:
     return int(lib().oracle_edge_count(_Bound(scene).ref))
 
 
-def edge_grad(scene, dEdp_full, n_samples, select=None, brdf_variant=0, components=3, nthreads=None):
+def edge_grad(scene, dEdp_full, n_samples, select=None, brdf_variant=0, components=3, nthreads=None,
+              abs_terms=False):
     """Primary-visibility boundary term of edge sampling (n_samples samples over
     the silhouette edges).  Returns dict: verts [N,3], cam [12], edge [n,4]
     (edge id, pixel id, hit of the minus ray, hit of the plus ray), flag [n],
-    ltot (total film length of the silhouette)."""
+    ltot (total film length of the silhouette).  abs_terms: per element the
+    sum of (|f-| + |f+|) . |dE/dp| times the velocity's magnitude instead
+    (the size of the shaded values each term's difference cancels)."""
     b = _Bound(scene, brdf_variant, components)
     N = scene.n_verts
     sel = None if select is None else np.ascontiguousarray(select, dtype=np.int32)
@@ -265,7 +269,7 @@ def edge_grad(scene, dEdp_full, n_samples, select=None, brdf_variant=0, componen
     flag = np.zeros(n_sel, np.uint8)
     ltot = np.zeros(1)
     lib().oracle_edge_grad(b.ref, int(n_samples), n_sel, _ptr(sel), _ptr(g), _ptr(gv), _ptr(gc), _ptr(edge),
-                           _ptr(flag), _ptr(ltot), nthreads or default_threads())
+                           _ptr(flag), _ptr(ltot), nthreads or default_threads(), int(bool(abs_terms)))
     return dict(verts=gv, cam=gc, edge=edge, flag=flag, ltot=float(ltot[0]))
 
 

@@ -82,6 +82,8 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kShadowTmin = 1e-4;   // shadow-ray start offset (reading)
 constexpr double kFlagEps = 1e-6;      // decision-ambiguity band (world units)
 constexpr double kRoughMin = 1e-3, kRoughMax = 1.0;
+// Film offset (pixels) of the boundary term's two side rays from the edge point.
+constexpr double kEdgeSide = 1e-2;
 constexpr double kMissFar = 1e4;       // length of a primary-ray segment that hits nothing
 
 // Flag bits.
@@ -974,7 +976,7 @@ int oracle_grad(const OrScene* sc, int32_t n_pix, const int32_t* pix, const int3
 // Each silhouette edge gets probability proportional to its length on the
 // film (pixel units); a sample picks the edge by the running sum, a point
 // y = a + u (b - a) on it, and shades two rays through y -/+ eps m, with m the
-// unit film normal perp(b - a) and eps = 1e-3 pixel.  The pick is stratified:
+// unit film normal perp(b - a) and eps = 1e-2 pixel.  The pick is stratified:
 // sample k draws its position in the running sum from [k, k+1)/n_samples.
 // The estimate
 //     sum_k  (ltot / n_samples) (f_minus - f_plus) . dEdp[pixel(y)] (m . dy/dtheta)
@@ -1028,7 +1030,11 @@ extern "C" {
 
 int oracle_edge_grad(const OrScene* sc, int32_t n_samples, int32_t n_sel, const int32_t* sel,
                      const double* dEdp, double* g_verts, double* g_cam, int32_t* edge_out, uint8_t* flag_out,
-                     double* ltot_out, int32_t nthreads) {
+                     double* ltot_out, int32_t nthreads, int32_t abs_terms) {
+  // abs_terms != 0: accumulate, per element, (|f-| + |f+|) . |dEdp| times the
+  // magnitude of the velocity instead: the size of the two shaded values whose
+  // difference each term carries (the condition of that difference; a test
+  // tolerance, not a gradient)
   const Prepared P = prepare(sc);
   const OrScene& s = *sc;
   const EdgeList E = build_edges(s);
@@ -1083,7 +1089,7 @@ int oracle_edge_grad(const OrScene* sc, int32_t n_samples, int32_t n_sel, const 
     if (in_img) {
       for (int side = 0; side < 2; ++side) {
         const double sg = side == 0 ? -1.0 : 1.0;
-        const double fx = yx + sg * 1e-3 * mx, fy = yy + sg * 1e-3 * my;
+        const double fx = yx + sg * kEdgeSide * mx, fy = yy + sg * kEdgeSide * my;
         const V3 d = normalize(mul3(P.R, film_dir(P.cc, fx, fy)));
         const HitResult h = closest_hit(P.tg, P.T, d);
         flag |= h.flags;
@@ -1109,9 +1115,12 @@ int oracle_edge_grad(const OrScene* sc, int32_t n_samples, int32_t n_sel, const 
     if (edge_out) { edge_out[4 * is] = e; edge_out[4 * is + 1] = pid; edge_out[4 * is + 2] = hits[0]; edge_out[4 * is + 3] = hits[1]; }
     if (flag_out) flag_out[is] = flag;
     if (!in_img) return;
-    const double dlt = (fpm[0][0] - fpm[1][0]) * dEdp[3 * pid] + (fpm[0][1] - fpm[1][1]) * dEdp[3 * pid + 1] +
-                       (fpm[0][2] - fpm[1][2]) * dEdp[3 * pid + 2];
+    double dlt = 0.0;
+    for (int c = 0; c < 3; ++c)
+      dlt += abs_terms ? (std::fabs(fpm[0][c]) + std::fabs(fpm[1][c])) * std::fabs(dEdp[3 * pid + c])
+                       : (fpm[0][c] - fpm[1][c]) * dEdp[3 * pid + c];
     const double wgt = ltot / n_samples * dlt;
+    const auto T = [abs_terms](double x) { return abs_terms ? std::fabs(x) : x; };
     if (wgt == 0.0) return;
     // Film velocity of the edge point: X(w) = (1-w) A + w B, w perspective-correct.
     const double w = (u / pb.depth) / ((1.0 - u) / pa.depth + u / pb.depth);
@@ -1126,8 +1135,8 @@ int oracle_edge_grad(const OrScene* sc, int32_t n_samples, int32_t n_sel, const 
     double vn[18];
     for (int i = 0; i < 18; ++i) vn[i] = mx * y.x.d[i] + my * y.y.d[i];
     std::vector<double>& G = gv[tid];
-    for (int a = 0; a < 3; ++a) { G[3 * E.a[e] + a] += wgt * vn[a]; G[3 * E.b[e] + a] += wgt * vn[3 + a]; }
-    for (int i = 0; i < 12; ++i) gc[tid][i] += wgt * vn[6 + i];
+    for (int a = 0; a < 3; ++a) { G[3 * E.a[e] + a] += T(wgt * vn[a]); G[3 * E.b[e] + a] += T(wgt * vn[3 + a]); }
+    for (int i = 0; i < 12; ++i) gc[tid][i] += T(wgt * vn[6 + i]);
   });
   for (int t = 0; t < nthreads; ++t) {
     if (g_verts) for (int i = 0; i < 3 * s.n_verts; ++i) g_verts[i] += gv[t][i];

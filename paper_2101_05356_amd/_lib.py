@@ -36,7 +36,8 @@ class FrRenderOpts(ctypes.Structure):
                 ("edge_samples", ctypes.c_int32), ("light_chunk", ctypes.c_int32),
                 ("dbg_hit", P), ("dbg_pflag", P), ("dbg_vis", P), ("dbg_stats", P),
                 ("ev_kernel_begin", P), ("ev_kernel_end", P),
-                ("reuse_forward", ctypes.c_int32), ("keep_shadows", ctypes.c_int32)]
+                ("reuse_forward", ctypes.c_int32), ("keep_shadows", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("workspace", P), ("workspace_bytes", ctypes.c_size_t)]
 
 
 class FrMapRegWeights(ctypes.Structure):
@@ -99,8 +100,10 @@ SIGNATURES = {
     "fr_mesh_normals": ([P], P),
     "fr_mesh_edges": ([P, P, P], _i32),
     "fr_mesh_bvh_depth": ([P], _i32),
+    "fr_render_workspace_size": ([P, P, P, P], ctypes.c_int),
     "fr_render_forward": ([P, P, P, P, P], ctypes.c_int),
-    "fr_loss": ([P, P, _i32, _i32, _i32, P, P, P], ctypes.c_int),
+    "fr_loss_workspace_size": ([_i32, _i32, _i32], ctypes.c_size_t),
+    "fr_loss": ([P, P, _i32, _i32, _i32, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
     "fr_render_backward": ([P, P, P, P, P, P], ctypes.c_int),
     "fr_shadow_edges": ([P, P, P, P, ctypes.c_int32, P, P, P, P], ctypes.c_int),
     "fr_blend": ([P, P, P, _i32, _i32, P, P], ctypes.c_int),
@@ -108,10 +111,12 @@ SIGNATURES = {
     "fr_pose_forward": ([P, _i32, P, P, P], ctypes.c_int),
     "fr_pose_backward": ([P, _i32, P, P, P, P, P], ctypes.c_int),
     "fr_light_stage": ([P, P, _i32, P, P, P, P, P, P], ctypes.c_int),
-    "fr_map_regularizers": ([P, P, P, P, P, _i32, P, P, P, P, P, P], ctypes.c_int),
+    "fr_map_regularizers_workspace_size": ([_i32], ctypes.c_size_t),
+    "fr_map_regularizers": ([P, P, P, P, P, _i32, P, P, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
     "fr_prior": ([P, P, _i32, _i32, ctypes.c_float, P, P, P], ctypes.c_int),
     "fr_landmark_loss": ([P, P, _i32, P, ctypes.c_float, _i32, _i32, P, P, P, P, P], ctypes.c_int),
     "fr_light_stage_backward": ([P, P, _i32, P, P, P, P], ctypes.c_int),
+    "fr_axpy": ([P, P, ctypes.c_float, P, _i32, P], ctypes.c_int),
     "fr_adam_step": ([P, P, P, P, P, _i32, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, P],
                      ctypes.c_int),
     "fr_model_create": ([P, _i32, _i32, P, P, P, _i32, P, P, _i32, P, P, P], ctypes.c_int),

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -48,16 +49,23 @@ struct PrimKey {
   }
 };
 
+// What a caller's workspace holds from the last render call that used it:
+// the camera-ray hits of the call with key `prim` (at the workspace's start)
+// and, when a forward kept them, its shadow masks for the lights of `vis`
+// (vis_bytes at offset vis_off).
+struct WsState {
+  PrimKey prim;
+  LightKey vis;
+  size_t vis_off = 0, vis_bytes = 0;
+};
+
 struct fr_mesh {
   fr_ctx* ctx = nullptr;
   fr::MeshDev d;
   uint64_t version = 0;   // bumped by every fr_mesh_update
-  PrimKey prim_key;
-  LightKey vis_key;
+  std::mutex mu;          // guards ws
+  std::map<const void*, WsState> ws;   // keyed by workspace address
   std::vector<int32_t> h_edges, h_edge_faces;
-  double* loss_scratch = nullptr;   // per-block loss partials
-  float* loss_gtmp = nullptr;       // sign image before the adjoint smoothing
-  int loss_cap = 0;
 };
 
 namespace {
@@ -80,6 +88,72 @@ hipError_t dalloc(T** p, size_t n) {
 }
 
 bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// Carves typed sub-buffers out of one allocation (256-byte aligned).
+struct Carver {
+  size_t off = 0;
+  char* base = nullptr;
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+    off += sizeof(T) * std::max<size_t>(n, 1);
+    return p;
+  }
+};
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// A render call's workspace: [camera-ray hits | light table | kept shadow
+// masks | call region].  The hits and the masks carry a forward's decisions
+// to the backward that takes them; the call region holds one call's scratch
+// and nothing in it outlives the call.
+size_t ws_prim_bytes(const fr_scene* s) {
+  return al256((size_t)s->width * s->height * s->spp * sizeof(fr::PrimHit));
+}
+size_t ws_light_bytes(const fr_scene* s) { return al256((size_t)std::max(s->n_lights, 1) * sizeof(fr::LightRec)); }
+int fwd_chunk(const fr_render_opts* o) { return o->light_chunk > 0 ? o->light_chunk : fr::kLightChunkFwd; }
+size_t ws_vis_bytes(const fr_scene* s, int lc) {
+  return s->n_lights > 0 ? al256((size_t)fr::cdiv(s->n_lights, lc) * s->width * s->height * s->spp * 4) : 0;
+}
+// forward: the per-light-chunk partial images
+size_t ws_fwd_region(const fr_scene* s, int lc) {
+  const size_t nch = std::max(1, fr::cdiv(s->n_lights, lc));
+  return nch > 1 ? al256(nch * 3 * (size_t)s->width * s->height * sizeof(float)) : 0;
+}
+// backward: fixed-point accumulators, the normals' adjoint, the light/camera
+// slots, texel sums and the boundary term's silhouette CDF
+struct BwdScratch {
+  fr::fix_t* acc;        // [13N + 12]: verts, normals, diffuse, specular (3N each), roughness (N), camera (12)
+  float* gnorm;          // [3N]
+  fr::fix_t* slots;      // [kSlots (12 Lg + 12 + 3 B^2)]
+  fr::fix_t* tex;        // [7 M^2]
+  double* edge_len;      // [E]
+  double* edge_cdf;      // [E]
+  uint8_t* face_front;   // [F]
+  double* scan_part;     // [ceil(E / 1024)]
+};
+size_t carve_bwd(const fr::MeshDev& d, const fr_scene* s, char* base, BwdScratch* out) {
+  Carver c;
+  c.base = base;
+  BwdScratch b;
+  const size_t N = d.N, Lg = std::min(s->n_lights, fr::kBwdMaxLights), B = std::max(s->sh_bands, 0);
+  const size_t MM = (size_t)std::max(s->tex_size, 0) * std::max(s->tex_size, 0);
+  b.acc = c.take<fr::fix_t>(13 * N + 12);
+  b.gnorm = c.take<float>(3 * N);
+  b.slots = c.take<fr::fix_t>((size_t)fr::kSlots * (12 * Lg + 12 + 3 * B * B));
+  b.tex = MM > 0 ? c.take<fr::fix_t>(7 * MM) : nullptr;
+  b.edge_len = c.take<double>(d.E);
+  b.edge_cdf = c.take<double>(d.E);
+  b.face_front = c.take<uint8_t>(d.F);
+  b.scan_part = c.take<double>(std::max(1, (d.E + 1023) / 1024));
+  if (out) *out = b;
+  return al256(c.off);
+}
+// shadow-edge term: fixed-point sums of verts, light geometry, camera
+size_t ws_se_region(const fr::MeshDev& d, const fr_scene* s) {
+  return al256((3 * (size_t)d.N + 9 * (size_t)std::max(s->n_lights, 0) + 12) * sizeof(fr::fix_t));
+}
 
 // Constants of the SH lighting: A_l, the clamped cosine's SH coefficients
 // (pi, 2 pi / 3, then 0 for odd l and 2 pi (-1)^(l/2+1) C(l, l/2) /
@@ -128,7 +202,7 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
   const fr::MeshDev& d = m->d;
   a.nodes = d.nodes4; a.recs = d.recs; a.tris = d.tris; a.verts = s->verts; a.normals = d.normals;
   a.diffuse = s->diffuse; a.specular = s->specular; a.roughness = s->roughness;
-  a.lights = d.lights; a.cam = s->cam;
+  a.lights = nullptr; a.cam = s->cam;   // the light table: set by the caller
   a.M = maps ? s->tex_size : 0;
   a.uv = maps ? s->tex_uv : nullptr;
   a.tex_c = maps ? s->tex_diffuse : nullptr;
@@ -148,7 +222,7 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
   a.lc = o->light_chunk > 0 ? o->light_chunk : default_chunk;
   a.n_lchunks = std::max(1, (s->n_lights + a.lc - 1) / a.lc);
   a.partial = nullptr;
-  a.prim = nullptr;   // set by the caller (ensure_prim, or a job's own buffer)
+  a.prim = nullptr;   // set by the caller (from its workspace, or a job's own buffer)
   a.vis_out = nullptr; a.vis_in = nullptr; a.vis_lc = 0;
   a.light0 = 0;
   if (s->sh_bands < 0 || s->sh_bands > fr::kMaxShBands || (s->sh_bands > 0 && !s->sh))
@@ -171,20 +245,6 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
   a.dbg_hit = o->dbg_hit; a.dbg_pflag = o->dbg_pflag; a.dbg_vis = o->dbg_vis; a.dbg_stats = o->dbg_stats;
   return FR_OK;
 }
-
-int ensure_lights(fr_mesh* m, int L) {
-  if (L <= m->d.light_cap) return FR_OK;
-  if (m->d.lights) (void)hipFree(m->d.lights);
-  if (m->d.ltmp) (void)hipFree(m->d.ltmp);
-  m->d.lights = nullptr;
-  m->d.ltmp = nullptr;
-  const int cap = std::max(L, 128);
-  if (dalloc(&m->d.lights, cap) != hipSuccess || dalloc(&m->d.ltmp, (size_t)cap * 12) != hipSuccess)
-    return fail(m->ctx, FR_ERR_OOM, "light table allocation failed");
-  m->d.light_cap = cap;
-  return FR_OK;
-}
-
 
 // Host-side topology of a mesh: triangles, vertex->face CSR (faces in
 // increasing order), unique edges (lower id first, sorted) and their faces.
@@ -224,7 +284,10 @@ int build_topology(fr_ctx* ctx, int32_t n_verts, int32_t n_tris, const int32_t* 
   return FR_OK;
 }
 
-int mesh_from_topology(fr_ctx* ctx, const HostTopo& t, fr_mesh** out) {
+// with_scratch: the mesh also holds the per-call buffers of the adjoint
+// (fixed-point sums, the normals' adjoint, the silhouette CDF), which a batch
+// job's step uses in place of a caller's workspace.
+int mesh_from_topology(fr_ctx* ctx, const HostTopo& t, bool with_scratch, fr_mesh** out) {
   FR_HIP(ctx, hipSetDevice(ctx->device));
   fr_mesh* m = new fr_mesh();
   m->ctx = ctx;
@@ -237,7 +300,7 @@ int mesh_from_topology(fr_ctx* ctx, const HostTopo& t, fr_mesh** out) {
   const int F = t.F, NI = std::max(F - 1, 1), nb = (F + 1023) / 1024, n_verts = t.N;
   bool ok = dalloc(&d.tris, 3 * (size_t)F) == hipSuccess && dalloc(&d.vf_off, n_verts + 1) == hipSuccess &&
             dalloc(&d.vf_idx, 3 * (size_t)F) == hipSuccess && dalloc(&d.normals, 3 * (size_t)n_verts) == hipSuccess &&
-            dalloc(&d.nlen, n_verts) == hipSuccess && dalloc(&d.gnorm, 3 * (size_t)n_verts) == hipSuccess &&
+            dalloc(&d.nlen, n_verts) == hipSuccess &&
             dalloc(&d.edges, 2 * (size_t)d.E) == hipSuccess && dalloc(&d.edge_faces, 2 * (size_t)d.E) == hipSuccess &&
             dalloc(&d.nodes, NI) == hipSuccess && dalloc(&d.recs, F + 1) == hipSuccess &&
             dalloc(&d.order, F) == hipSuccess && dalloc(&d.node_parent, NI) == hipSuccess &&
@@ -245,10 +308,12 @@ int mesh_from_topology(fr_ctx* ctx, const HostTopo& t, fr_mesh** out) {
             dalloc(&d.keys[0], F) == hipSuccess && dalloc(&d.keys[1], F) == hipSuccess &&
             dalloc(&d.vals[0], F) == hipSuccess && dalloc(&d.vals[1], F) == hipSuccess &&
             dalloc(&d.hist, 256 * (size_t)nb) == hipSuccess && dalloc(&d.partial, 64 * 6) == hipSuccess &&
-            dalloc(&d.scene_box, 6) == hipSuccess && dalloc(&d.depth, 2) == hipSuccess &&
-            dalloc(&d.edge_len, d.E) == hipSuccess && dalloc(&d.edge_cdf, d.E) == hipSuccess &&
-            dalloc(&d.face_front, F) == hipSuccess && dalloc(&d.scan_part, (size_t)std::max(1, (d.E + 1023) / 1024)) == hipSuccess &&
-            dalloc(&d.acc, 13 * (size_t)n_verts + 12) == hipSuccess;
+            dalloc(&d.scene_box, 6) == hipSuccess && dalloc(&d.depth, 2) == hipSuccess;
+  if (ok && with_scratch)
+    ok = dalloc(&d.gnorm, 3 * (size_t)n_verts) == hipSuccess && dalloc(&d.edge_len, d.E) == hipSuccess &&
+         dalloc(&d.edge_cdf, d.E) == hipSuccess && dalloc(&d.face_front, F) == hipSuccess &&
+         dalloc(&d.scan_part, (size_t)std::max(1, (d.E + 1023) / 1024)) == hipSuccess &&
+         dalloc(&d.acc, 13 * (size_t)n_verts + 12) == hipSuccess;
   if (!ok) { fr_mesh_destroy(m); return fail(ctx, FR_ERR_OOM, "mesh allocation failed"); }
   ok = hipMemcpy(d.tris, t.tris.data(), sizeof(int32_t) * 3 * F, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(d.vf_off, t.off.data(), sizeof(int32_t) * (n_verts + 1), hipMemcpyHostToDevice) == hipSuccess &&
@@ -321,16 +386,16 @@ int fr_mesh_create(fr_ctx* ctx, int32_t n_verts, int32_t n_tris, const int32_t* 
   HostTopo topo;
   int rc = build_topology(ctx, n_verts, n_tris, h_tris, topo);
   if (rc != FR_OK) return rc;
-  return mesh_from_topology(ctx, topo, out);
+  return mesh_from_topology(ctx, topo, false, out);
 }
 
 int fr_mesh_destroy(fr_mesh* m) {
   if (!m) return FR_OK;
   fr::MeshDev& d = m->d;
-  void* ptrs[] = {d.tris, d.vf_off, d.vf_idx, d.normals, d.nlen, d.gnorm, d.edges, d.edge_faces, d.face_nbr, d.se_acc, d.nodes, d.recs,
+  void* ptrs[] = {d.tris, d.vf_off, d.vf_idx, d.normals, d.nlen, d.gnorm, d.edges, d.edge_faces, d.face_nbr, d.nodes, d.recs,
                   d.order, d.node_parent, d.leaf_parent, d.flags, d.keys[0], d.keys[1], d.vals[0], d.vals[1],
-                  d.hist, d.partial, d.scene_box, d.depth, d.lights, d.ltmp, d.edge_len, d.edge_cdf, d.face_front,
-                  d.scan_part, d.img_partial, d.prim, d.vis, d.acc, d.tex_acc, d.slots, d.nodes4, d.n4_src, d.top_nodes, d.top_level_off, m->loss_scratch, m->loss_gtmp};
+                  d.hist, d.partial, d.scene_box, d.depth, d.edge_len, d.edge_cdf, d.face_front,
+                  d.scan_part, d.acc, d.nodes4, d.n4_src, d.top_nodes, d.top_level_off};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -388,23 +453,23 @@ int bwd_chunks(fr_mesh* m, fr::RenderArgs& a) {
   return FR_OK;
 }
 
-PrimKey prim_key_of(const fr_mesh* m, const fr_scene* s) {
+PrimKey prim_key_of(const fr_mesh* m, const fr_scene* s, const void* ws) {
   PrimKey k;
   k.valid = true;
   k.W = s->width; k.H = s->height; k.S = s->spp;
   k.seed = s->seed; k.step = s->step; k.fov = s->fov_y;
   k.verts = s->verts; k.cam = s->cam;
-  k.buf = m->d.prim;
+  k.buf = ws;
   k.version = m->version;
   return k;
 }
 
-LightKey light_key_of(const fr_mesh* m, const fr_scene* s, int lc) {
+LightKey light_key_of(const fr_scene* s, int lc, const void* ws) {
   LightKey k;
   k.valid = true;
   k.L = s->n_lights; k.lc = lc;
   k.p0 = s->light_p0; k.e1 = s->light_e1; k.e2 = s->light_e2; k.shape = s->light_shape;
-  k.buf = m->d.vis;
+  k.buf = ws;
   return k;
 }
 
@@ -413,17 +478,43 @@ bool same_lights(const LightKey& a, const LightKey& b) {
          a.buf == b.buf;
 }
 
-// The mesh's primary-hit buffer, grown to the call's W*H*S samples.
-int ensure_prim(fr_mesh* m, fr::RenderArgs& a) {
-  const size_t need = (size_t)a.W * a.H * a.S;
-  if (need > m->d.prim_cap) {
-    if (m->d.prim) (void)hipFree(m->d.prim);
-    m->d.prim = nullptr;
-    m->d.prim_cap = 0;
-    if (dalloc(&m->d.prim, need) != hipSuccess) return fail(m->ctx, FR_ERR_OOM, "primary-hit buffer allocation failed");
-    m->d.prim_cap = need;
-  }
-  a.prim = m->d.prim;
+// The caller's workspace of a render call: its base, and what it holds from
+// the last call that used it.  Kept shadow masks count only where this call's
+// layout puts them (right after its light table); a call whose hits or light
+// table would cover them forgets them.
+int ws_open(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, char** base, WsState* st) {
+  if (!o->workspace)
+    return fail(m->ctx, FR_ERR_INVALID_ARG, "opts->workspace is required (size from fr_render_workspace_size)");
+  if (reinterpret_cast<uintptr_t>(o->workspace) & 255)
+    return fail(m->ctx, FR_ERR_INVALID_ARG, "opts->workspace must be 256-byte aligned");
+  *base = static_cast<char*>(o->workspace);
+  std::lock_guard<std::mutex> lk(m->mu);
+  *st = m->ws[o->workspace];
+  if (st->vis.valid && st->vis_off != ws_prim_bytes(s) + ws_light_bytes(s)) st->vis = LightKey{};
+  if (!st->vis.valid) st->vis_off = st->vis_bytes = 0;
+  return FR_OK;
+}
+
+int ws_need(fr_mesh* m, const fr_render_opts* o, size_t need) {
+  if (o->workspace_bytes < need)
+    return fail(m->ctx, FR_ERR_SHAPE, "workspace of " + std::to_string(o->workspace_bytes) + " bytes; this call needs " +
+                                          std::to_string(need));
+  return FR_OK;
+}
+
+void ws_store(fr_mesh* m, const void* base, const WsState& st) {
+  std::lock_guard<std::mutex> lk(m->mu);
+  m->ws[base] = st;
+}
+
+int fr_render_workspace_size(const fr_mesh* m, const fr_scene* s, const fr_render_opts* o, size_t* bytes) {
+  if (!m || !s || !o || !bytes) return FR_ERR_INVALID_ARG;
+  if (s->width <= 0 || s->height <= 0 || s->spp <= 0 || s->n_lights < 0 || s->tex_size < 0 || s->sh_bands < 0 ||
+      o->light_chunk < 0 || o->light_chunk > 32)
+    return FR_ERR_INVALID_ARG;
+  const int lc = fwd_chunk(o);
+  const size_t region = std::max({ws_fwd_region(s, lc), carve_bwd(m->d, s, nullptr, nullptr), ws_se_region(m->d, s)});
+  *bytes = ws_prim_bytes(s) + ws_light_bytes(s) + (o->keep_shadows ? ws_vis_bytes(s, lc) : 0) + region;
   return FR_OK;
 }
 
@@ -435,63 +526,50 @@ int fr_render_forward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fl
   const bool any_dbg = o->dbg_hit || o->dbg_pflag || o->dbg_vis || o->dbg_stats;
   if (any_dbg && !(o->dbg_hit && o->dbg_pflag && o->dbg_vis))
     return fail(m->ctx, FR_ERR_INVALID_ARG, "the forward dump needs dbg_hit, dbg_pflag and dbg_vis");
-  if ((rc = ensure_lights(m, s->n_lights)) != FR_OK) return rc;
-  if ((rc = ensure_prim(m, a)) != FR_OK) return rc;
-  a.lights = m->d.lights;
-  if (a.n_lchunks > 1) {
-    const size_t need = (size_t)a.n_lchunks * 3 * a.W * a.H;
-    if (need > m->d.img_partial_cap) {
-      if (m->d.img_partial) (void)hipFree(m->d.img_partial);
-      m->d.img_partial = nullptr;
-      m->d.img_partial_cap = 0;
-      if (dalloc(&m->d.img_partial, need) != hipSuccess)
-        return fail(m->ctx, FR_ERR_OOM, "partial image allocation failed");
-      m->d.img_partial_cap = need;
-    }
-    a.partial = m->d.img_partial;
-  }
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (s->n_lights > 0) fr::launch_light_setup(*s, m->d.lights, st);
-  if (o->keep_shadows && s->n_lights > 0) {
-    const size_t need = (size_t)a.n_lchunks * a.W * a.H * a.S;
-    if (need > m->d.vis_cap) {
-      if (m->d.vis) (void)hipFree(m->d.vis);
-      m->d.vis = nullptr;
-      m->d.vis_cap = 0;
-      if (dalloc(&m->d.vis, need) != hipSuccess) return fail(m->ctx, FR_ERR_OOM, "shadow-mask allocation failed");
-      m->d.vis_cap = need;
-    }
-    a.vis_out = m->d.vis;
+  char* base = nullptr;
+  WsState st;
+  if ((rc = ws_open(m, s, o, &base, &st)) != FR_OK) return rc;
+  const bool keep = o->keep_shadows && s->n_lights > 0;
+  const size_t pb = ws_prim_bytes(s), lb = ws_light_bytes(s), vb = keep ? ws_vis_bytes(s, a.lc) : 0;
+  if ((rc = ws_need(m, o, pb + lb + vb + ws_fwd_region(s, a.lc))) != FR_OK) return rc;
+  a.prim = reinterpret_cast<fr::PrimHit*>(base);
+  fr::LightRec* lights = reinterpret_cast<fr::LightRec*>(base + pb);
+  a.lights = lights;
+  if (keep) {
+    a.vis_out = reinterpret_cast<uint32_t*>(base + pb + lb);
     a.vis_lc = a.lc;
   }
-  m->prim_key.valid = false;
-  m->vis_key.valid = false;
-  fr::launch_render_forward(a, d_image, st, static_cast<hipEvent_t>(o->ev_kernel_begin),
+  if (a.n_lchunks > 1) a.partial = reinterpret_cast<float*>(base + pb + lb + vb);
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  if (s->n_lights > 0) fr::launch_light_setup(*s, lights, hs);
+  fr::launch_render_forward(a, d_image, hs, static_cast<hipEvent_t>(o->ev_kernel_begin),
                             static_cast<hipEvent_t>(o->ev_kernel_end));
   FR_HIP(m->ctx, hipGetLastError());
-  m->prim_key = prim_key_of(m, s);
-  if (a.vis_out) m->vis_key = light_key_of(m, s, a.lc);
+  WsState now;
+  now.prim = prim_key_of(m, s, base);
+  if (keep) {
+    now.vis = light_key_of(s, a.lc, base);
+    now.vis_off = pb + lb;
+    now.vis_bytes = vb;
+  }
+  ws_store(m, base, now);
   return FR_OK;
 }
 
+size_t fr_loss_workspace_size(int32_t W, int32_t H, int32_t smooth) {
+  return W > 0 && H > 0 ? fr::loss_scratch_bytes(W, H, smooth != 0) : 0;
+}
+
 int fr_loss(const float* d_image, const float* d_target, int32_t W, int32_t H, int32_t smooth, float* d_loss,
-            float* d_dEdp, fr_stream stream) {
-  if (!d_image || !d_target || !d_loss || W <= 0 || H <= 0) return FR_ERR_INVALID_ARG;
-  // scratch: per-block partial sums and the sign image (allocated per call size class)
-  static thread_local double* scratch = nullptr;
-  static thread_local float* gtmp = nullptr;
-  static thread_local size_t cap = 0;
-  const size_t npx = (size_t)W * H;
-  if (npx > cap) {
-    if (scratch) (void)hipFree(scratch);
-    if (gtmp) (void)hipFree(gtmp);
-    scratch = nullptr; gtmp = nullptr; cap = 0;
-    if (dalloc(&scratch, (npx + 255) / 256) != hipSuccess || dalloc(&gtmp, 3 * npx) != hipSuccess)
-      return FR_ERR_OOM;
-    cap = npx;
-  }
-  fr::launch_loss(d_image, d_target, W, H, smooth, d_loss, d_dEdp, scratch, gtmp,
-                  reinterpret_cast<hipStream_t>(stream));
+            float* d_dEdp, void* d_work, size_t work_bytes, fr_stream stream) {
+  if (!d_image || !d_target || !d_loss || !d_work || W <= 0 || H <= 0) return FR_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(d_work) & 255) return FR_ERR_INVALID_ARG;
+  if (work_bytes < fr::loss_scratch_bytes(W, H, smooth != 0)) return FR_ERR_SHAPE;
+  Carver c;
+  c.base = static_cast<char*>(d_work);
+  double* part = c.take<double>(((size_t)W * H + 255) / 256);
+  float* gtmp = smooth ? c.take<float>(3 * (size_t)W * H) : nullptr;
+  fr::launch_loss(d_image, d_target, W, H, smooth, d_loss, d_dEdp, part, gtmp, reinterpret_cast<hipStream_t>(stream));
   return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
 }
 
@@ -509,34 +587,21 @@ int fr_prior(const float* d_x, const float* d_sigma, int32_t n, int32_t kind, fl
   if (!d_x || !d_loss || n < 0 || kind < FR_PRIOR_STATISTICAL || kind > FR_PRIOR_LIGHT_CHROMA ||
       (kind == FR_PRIOR_STATISTICAL && !d_sigma) || (kind == FR_PRIOR_LIGHT_CHROMA && n % 3))
     return FR_ERR_INVALID_ARG;
-  static thread_local double* scratch = nullptr;
-  static thread_local size_t cap = 0;
-  const size_t nb = std::max<size_t>(1, ((size_t)n + 255) / 256);
-  if (nb > cap) {
-    if (scratch) (void)hipFree(scratch);
-    scratch = nullptr; cap = 0;
-    if (dalloc(&scratch, nb) != hipSuccess) return FR_ERR_OOM;
-    cap = nb;
-  }
-  fr::launch_prior(d_x, d_sigma, n, kind, weight, d_loss, d_g, scratch, reinterpret_cast<hipStream_t>(stream));
+  fr::launch_prior(d_x, d_sigma, n, kind, weight, d_loss, d_g, reinterpret_cast<hipStream_t>(stream));
   return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
 }
 
+size_t fr_map_regularizers_workspace_size(int32_t M) { return M > 0 ? fr::map_reg_scratch_bytes(M) : 0; }
+
 int fr_map_regularizers(const float* d_c, const float* d_s, const float* d_r, const float* d_c0, const float* d_s0,
                         int32_t M, const fr_map_reg_weights* w, float* d_loss, float* d_gc, float* d_gs, float* d_gr,
-                        fr_stream stream) {
-  if (!d_c || !d_s || !d_r || !d_c0 || !d_s0 || !w || !d_loss || M <= 0 || M > 16384) return FR_ERR_INVALID_ARG;
-  static thread_local double* scratch = nullptr;
-  static thread_local size_t cap = 0;
-  const size_t nb = ((size_t)M * M + 255) / 256;
-  if (nb > cap) {
-    if (scratch) (void)hipFree(scratch);
-    scratch = nullptr; cap = 0;
-    if (dalloc(&scratch, nb) != hipSuccess) return FR_ERR_OOM;
-    cap = nb;
-  }
+                        void* d_work, size_t work_bytes, fr_stream stream) {
+  if (!d_c || !d_s || !d_r || !d_c0 || !d_s0 || !w || !d_loss || !d_work || M <= 0 || M > 16384)
+    return FR_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(d_work) & 255) return FR_ERR_INVALID_ARG;
+  if (work_bytes < fr::map_reg_scratch_bytes(M)) return FR_ERR_SHAPE;
   const fr::MapRegWeights mw{w->w_sym, w->w_chroma, w->w_smooth, w->w_box};
-  fr::launch_map_regularizers(d_c, d_s, d_r, d_c0, d_s0, M, mw, d_loss, d_gc, d_gs, d_gr, scratch,
+  fr::launch_map_regularizers(d_c, d_s, d_r, d_c0, d_s0, M, mw, d_loss, d_gc, d_gs, d_gr, static_cast<double*>(d_work),
                               reinterpret_cast<hipStream_t>(stream));
   return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
 }
@@ -551,20 +616,22 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
     return fail(m->ctx, FR_ERR_INVALID_ARG, "the backward dump takes dbg_hit and dbg_pflag only");
   if ((rc = bwd_chunks(m, a)) != FR_OK) return rc;
   a.dbg_hit = nullptr; a.dbg_pflag = nullptr; a.dbg_vis = nullptr; a.dbg_stats = nullptr;
-  if ((rc = ensure_lights(m, s->n_lights)) != FR_OK) return rc;
-  if ((rc = ensure_prim(m, a)) != FR_OK) return rc;
-  a.lights = m->d.lights;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  fr::MeshDev& d = m->d;
-  const size_t need = (size_t)fr::kSlots *
-                      (12 * (size_t)std::min(s->n_lights, fr::kBwdMaxLights) + 12 + 3 * (size_t)a.sh_bands * a.sh_bands);
-  if (need > d.slots_cap) {
-    if (d.slots) (void)hipFree(d.slots);
-    d.slots = nullptr;
-    d.slots_cap = 0;
-    FR_HIP(m->ctx, dalloc(&d.slots, need));
-    d.slots_cap = need;
-  }
+  char* base = nullptr;
+  WsState st;
+  if ((rc = ws_open(m, s, o, &base, &st)) != FR_OK) return rc;
+  const size_t pb = ws_prim_bytes(s), lb = ws_light_bytes(s);
+  // the call's scratch goes after any kept shadow masks, used here or not
+  const size_t roff = pb + lb + st.vis_bytes;
+  BwdScratch w;
+  if ((rc = ws_need(m, o, roff + carve_bwd(m->d, s, base + roff, &w))) != FR_OK) return rc;
+  a.prim = reinterpret_cast<fr::PrimHit*>(base);
+  fr::LightRec* lights = reinterpret_cast<fr::LightRec*>(base + pb);
+  a.lights = lights;
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  // the mesh's buffers, with the per-call ones from the workspace
+  fr::MeshDev d = m->d;
+  d.acc = w.acc; d.gnorm = w.gnorm; d.edge_len = w.edge_len; d.edge_cdf = w.edge_cdf; d.face_front = w.face_front;
+  d.scan_part = w.scan_part;
   // fixed-point accumulators: verts, normals, diffuse, specular (3N each), roughness (N), camera (12)
   const size_t N = d.N;
   fr::fix_t* acc_v = d.acc;
@@ -573,59 +640,51 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
   fr::fix_t* acc_s = d.acc + 9 * N;
   fr::fix_t* acc_r = d.acc + 12 * N;
   fr::fix_t* acc_cam = d.acc + 13 * N;
-  fr::launch_zero_fix(d.acc, 13 * N + 12, st);
+  fr::launch_zero_fix(d.acc, 13 * N + 12, hs);
   // texel accumulators [7 M^2]: diffuse, specular (3 M^2 each), roughness (M^2)
   const size_t MM = (size_t)a.M * a.M;
   const bool want_tex = a.M > 0 && (g->tex_diffuse || g->tex_specular || g->tex_roughness);
-  if (want_tex) {
-    if (7 * MM > d.tex_acc_cap) {
-      if (d.tex_acc) (void)hipFree(d.tex_acc);
-      d.tex_acc = nullptr;
-      d.tex_acc_cap = 0;
-      FR_HIP(m->ctx, dalloc(&d.tex_acc, 7 * MM));
-      d.tex_acc_cap = 7 * MM;
-    }
-    fr::launch_zero_fix(d.tex_acc, 7 * MM, st);
-  }
-  if (s->n_lights > 0) fr::launch_light_setup(*s, d.lights, st);
+  if (want_tex) fr::launch_zero_fix(w.tex, 7 * MM, hs);
+  if (s->n_lights > 0) fr::launch_light_setup(*s, lights, hs);
   const bool want_n = g->normals || g->verts;
   const bool vtx_refl = a.M == 0;
   fr::FixGrads fg = {g->verts ? acc_v : nullptr, want_n ? acc_n : nullptr,
                      vtx_refl && g->diffuse ? acc_c : nullptr, vtx_refl && g->specular ? acc_s : nullptr,
                      vtx_refl && g->roughness ? acc_r : nullptr, nullptr, nullptr, nullptr};
   if (want_tex) {
-    fg.tex_c = g->tex_diffuse ? d.tex_acc : nullptr;
-    fg.tex_s = g->tex_specular ? d.tex_acc + 3 * MM : nullptr;
-    fg.tex_r = g->tex_roughness ? d.tex_acc + 6 * MM : nullptr;
+    fg.tex_c = g->tex_diffuse ? w.tex : nullptr;
+    fg.tex_s = g->tex_specular ? w.tex + 3 * MM : nullptr;
+    fg.tex_r = g->tex_roughness ? w.tex + 6 * MM : nullptr;
   }
-  const PrimKey key = prim_key_of(m, s);
-  const bool reuse = o->reuse_forward && m->prim_key == key;
-  if (reuse && s->n_lights > 0 && same_lights(m->vis_key, light_key_of(m, s, m->vis_key.lc))) {
-    a.vis_in = m->d.vis;
-    a.vis_lc = m->vis_key.lc;
+  const PrimKey key = prim_key_of(m, s, base);
+  const bool reuse = o->reuse_forward && st.prim == key;
+  const bool use_vis = reuse && s->n_lights > 0 && same_lights(st.vis, light_key_of(s, st.vis.lc, base));
+  if (use_vis) {
+    a.vis_in = reinterpret_cast<const uint32_t*>(base + st.vis_off);
+    a.vis_lc = st.vis.lc;
   }
-  const LightKey vkeep = a.vis_in ? m->vis_key : LightKey{};
-  m->prim_key.valid = false;
-  m->vis_key.valid = false;
-  fr::launch_render_backward(a, d_dEdp, fg, d.slots, *g, st, static_cast<hipEvent_t>(o->ev_kernel_begin),
+  fr::launch_render_backward(a, d_dEdp, fg, w.slots, *g, hs, static_cast<hipEvent_t>(o->ev_kernel_begin),
                              static_cast<hipEvent_t>(o->ev_kernel_end), !reuse);
   FR_HIP(m->ctx, hipGetLastError());
-  m->prim_key = key;
-  m->vis_key = vkeep;
-  if (g->normals) fr::launch_fix_to_float(acc_n, g->normals, 3 * d.N, st);
-  if (g->verts) fr::launch_normals_backward(d, s->verts, acc_n, d.gnorm, acc_v, st);
+  // the hits now belong to this call; the masks stay only if they were this call's
+  WsState now;
+  now.prim = key;
+  if (use_vis) { now.vis = st.vis; now.vis_off = st.vis_off; now.vis_bytes = st.vis_bytes; }
+  ws_store(m, base, now);
+  if (g->normals) fr::launch_fix_to_float(acc_n, g->normals, 3 * d.N, hs);
+  if (g->verts) fr::launch_normals_backward(d, s->verts, acc_n, d.gnorm, acc_v, hs);
   const int ns = o->edge_samples < 0 ? s->width * s->height : o->edge_samples;
   if (ns > 0 && (g->verts || g->cam || o->dbg_hit))
     fr::launch_edges(d, a, d_dEdp, ns, g->verts ? acc_v : nullptr, g->cam ? acc_cam : nullptr, o->dbg_hit,
-                     o->dbg_pflag, std::tan(0.5 * (double)s->fov_y), st);
-  if (g->verts) fr::launch_fix_to_float(acc_v, g->verts, 3 * d.N, st);
-  if (fg.diffuse) fr::launch_fix_to_float(acc_c, g->diffuse, 3 * d.N, st);
-  if (fg.specular) fr::launch_fix_to_float(acc_s, g->specular, 3 * d.N, st);
-  if (fg.roughness) fr::launch_fix_to_float(acc_r, g->roughness, d.N, st);
-  if (fg.tex_c) fr::launch_fix_to_float(fg.tex_c, g->tex_diffuse, (int)(3 * MM), st);
-  if (fg.tex_s) fr::launch_fix_to_float(fg.tex_s, g->tex_specular, (int)(3 * MM), st);
-  if (fg.tex_r) fr::launch_fix_to_float(fg.tex_r, g->tex_roughness, (int)MM, st);
-  if (g->cam) fr::launch_fix_to_float(acc_cam, g->cam, 12, st);
+                     o->dbg_pflag, std::tan(0.5 * (double)s->fov_y), hs);
+  if (g->verts) fr::launch_fix_to_float(acc_v, g->verts, 3 * d.N, hs);
+  if (fg.diffuse) fr::launch_fix_to_float(acc_c, g->diffuse, 3 * d.N, hs);
+  if (fg.specular) fr::launch_fix_to_float(acc_s, g->specular, 3 * d.N, hs);
+  if (fg.roughness) fr::launch_fix_to_float(acc_r, g->roughness, d.N, hs);
+  if (fg.tex_c) fr::launch_fix_to_float(fg.tex_c, g->tex_diffuse, (int)(3 * MM), hs);
+  if (fg.tex_s) fr::launch_fix_to_float(fg.tex_s, g->tex_specular, (int)(3 * MM), hs);
+  if (fg.tex_r) fr::launch_fix_to_float(fg.tex_r, g->tex_roughness, (int)MM, hs);
+  if (g->cam) fr::launch_fix_to_float(acc_cam, g->cam, 12, hs);
   FR_HIP(m->ctx, hipGetLastError());
   return FR_OK;
 }
@@ -640,35 +699,35 @@ int fr_shadow_edges(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, cons
   if ((long long)s->width * s->height * s->spp >= (1ll << 31))
     return fail(m->ctx, FR_ERR_LIMIT, "the shadow-edge term needs W*H*spp < 2^31");
   a.dbg_hit = nullptr; a.dbg_pflag = nullptr; a.dbg_vis = nullptr; a.dbg_stats = nullptr;
-  if ((rc = ensure_lights(m, s->n_lights)) != FR_OK) return rc;
-  a.lights = m->d.lights;
-  fr::MeshDev& d = m->d;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const size_t N = d.N, L = s->n_lights, need = 3 * N + 9 * L + 12;
-  if (need > d.se_cap) {
-    if (d.se_acc) (void)hipFree(d.se_acc);
-    d.se_acc = nullptr;
-    d.se_cap = 0;
-    FR_HIP(m->ctx, dalloc(&d.se_acc, need));
-    d.se_cap = need;
-  }
+  char* base = nullptr;
+  WsState st;
+  if ((rc = ws_open(m, s, o, &base, &st)) != FR_OK) return rc;
+  const size_t pb = ws_prim_bytes(s), lb = ws_light_bytes(s), roff = pb + lb + st.vis_bytes;
+  const size_t N = m->d.N, L = s->n_lights, nacc = 3 * N + 9 * L + 12;
+  if ((rc = ws_need(m, o, roff + ws_se_region(m->d, s))) != FR_OK) return rc;
+  // the hits and any kept masks stay as they are (this call traces its own camera rays)
+  ws_store(m, base, st);
   if (n_samples == 0 || L == 0) return FR_OK;
-  fr::launch_zero_fix(d.se_acc, need, st);
-  fr::launch_light_setup(*s, d.lights, st);
+  fr::LightRec* lights = reinterpret_cast<fr::LightRec*>(base + pb);
+  a.lights = lights;
+  fr::fix_t* acc = reinterpret_cast<fr::fix_t*>(base + roff);
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  fr::launch_zero_fix(acc, nacc, hs);
+  fr::launch_light_setup(*s, lights, hs);
   fr::ShadowEdgeArgs e;
-  e.nbr = d.face_nbr;
+  e.nbr = m->d.face_nbr;
   e.n_samples = n_samples;
   e.dEdp = d_dEdp;
-  e.gverts = g->verts ? d.se_acc : nullptr;
-  e.glight = g->light_geom ? d.se_acc + 3 * N : nullptr;
-  e.gcam = g->cam ? d.se_acc + 3 * N + 9 * L : nullptr;
+  e.gverts = g->verts ? acc : nullptr;
+  e.glight = g->light_geom ? acc + 3 * N : nullptr;
+  e.gcam = g->cam ? acc + 3 * N + 9 * L : nullptr;
   e.dbg_rec = d_rec;
   e.dbg_flag = d_flag;
-  fr::launch_shadow_edges(a, e, st);
+  fr::launch_shadow_edges(a, e, hs);
   FR_HIP(m->ctx, hipGetLastError());
-  if (g->verts) fr::launch_fix_to_float(d.se_acc, g->verts, (int)(3 * N), st);
-  if (g->light_geom) fr::launch_fix_to_float(d.se_acc + 3 * N, g->light_geom, (int)(9 * L), st);
-  if (g->cam) fr::launch_fix_to_float(d.se_acc + 3 * N + 9 * L, g->cam, 12, st);
+  if (g->verts) fr::launch_fix_to_float(acc, g->verts, (int)(3 * N), hs);
+  if (g->light_geom) fr::launch_fix_to_float(acc + 3 * N, g->light_geom, (int)(9 * L), hs);
+  if (g->cam) fr::launch_fix_to_float(acc + 3 * N + 9 * L, g->cam, 12, hs);
   FR_HIP(m->ctx, hipGetLastError());
   return FR_OK;
 }
@@ -716,6 +775,12 @@ int fr_pose_backward(const float* d_v, int32_t n, const float* d_pose, const flo
   return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
 }
 
+int fr_axpy(float* d_y, const float* d_x, float a, const float* d_s, int32_t n, fr_stream stream) {
+  if (!d_y || !d_x || n < 0) return FR_ERR_INVALID_ARG;
+  fr::launch_axpy(d_y, d_x, a, d_s, n, reinterpret_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
+}
+
 int fr_adam_step(float* d_param, const float* d_grad, float* d_m, float* d_v, const float* d_lr, int32_t n, int32_t t,
                  float beta1, float beta2, float eps, fr_stream stream) {
   if (!d_param || !d_grad || !d_m || !d_v || !d_lr || n <= 0 || t < 1) return FR_ERR_INVALID_ARG;
@@ -746,19 +811,6 @@ struct JobHost {
   size_t bytes = 0;
   int n_param = 0, W = 0, H = 0, hist_cap = 0;
   fr::JobDev dev{};
-};
-
-// Carves typed sub-buffers out of one allocation (256-byte aligned).
-struct Carver {
-  size_t off = 0;
-  char* base = nullptr;
-  template <class T>
-  T* take(size_t n) {
-    off = (off + 255) & ~size_t(255);
-    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
-    off += sizeof(T) * std::max<size_t>(n, 1);
-    return p;
-  }
 };
 
 // Lays out (base == nullptr: only sizes) the device buffers of one job.
@@ -879,7 +931,7 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   if (rc != FR_OK) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   JobHost* jh = new JobHost();
-  rc = mesh_from_topology(ctx, md->topo, &jh->mesh);
+  rc = mesh_from_topology(ctx, md->topo, true, &jh->mesh);
   if (rc != FR_OK) { delete jh; return rc; }
   fr::JobDev& J = jh->dev;
   const int L = d->n_lights;

@@ -8,7 +8,7 @@
 //    FP64 scan gives the running sum.
 // 3. Edge sample k picks the edge whose running-sum interval holds
 //    ((k + u0)/n) * total (stratified), a point y = a + u1 (b - a) on its film
-//    image, and traces two camera rays through y -/+ 1e-3 m (m the unit film
+//    image, and traces two camera rays through y -/+ 1e-2 m (m the unit film
 //    normal), each shaded with one point per light from counters
 //    (k, 0, 0x80000001 + j, step).  The estimate
 //       (total / n) ((f- - f+) . dE/dp[pixel of y]) (m . dy/dtheta)
@@ -17,6 +17,12 @@
 #include "fr_shade.h"
 
 namespace fr {
+
+// Film offset of the side rays from the edge, in pixels.  It must exceed the
+// FP32 tracer's near-edge band (4e-6 + 2e-6 t world units) on the film: at a
+// 256^2 face 1e-3 pixel is ~8e-6 world units and would leave every side ray
+// undecidable; 1e-2 pixel is ~8e-5 (and ~2e-5 at 1024^2).
+constexpr double kEdgeSide = 1e-2;
 
 __device__ __forceinline__ void face_front_block(const float* __restrict__ v, const int32_t* __restrict__ tris, int F,
                                                     const float* __restrict__ cam, uint8_t* __restrict__ front, int bid) {
@@ -142,12 +148,14 @@ __global__ __launch_bounds__(256) void k_edge_scan_add(double* __restrict__ cdf,
   edge_scan_add_block(cdf, E, part, blockIdx.x);
 }
 
-// Side ray through film point (fx, fy): its closest hit with the FP64
+// Side ray through film point (fx, fy) (FP64: at a grazing silhouette the
+// shading point moves ~1/cos_o times faster than the film point, so an FP32
+// film point would misplace it): its closest hit with the FP64
 // barycentrics of the crossing (traced once per edge sample and side).
 template <bool DUMP>
-__device__ __forceinline__ PrimHit side_trace(const RenderArgs& a, float fx, float fy, bool active, bool& amb) {
+__device__ __forceinline__ PrimHit side_trace(const RenderArgs& a, double fx, double fy, bool active, bool& amb) {
   Sample sm;
-  camera_ray_film(a, fx, fy, sm);
+  camera_ray_film(a, (float)fx, (float)fy, sm);
   HitState h;
   h.t = 3.4e38f; h.id = -1; h.tamb = 3.4e38f;
   bool dummy = false;
@@ -158,7 +166,7 @@ __device__ __forceinline__ PrimHit side_trace(const RenderArgs& a, float fx, flo
     const int* t = a.tris + 3 * h.id;
     const int vi[3] = {t[0], t[1], t[2]};
     double bd[3];
-    bary64(a, (double)fx, (double)fy, vi, bd);
+    bary64(a, fx, fy, vi, bd);
     ph.b1 = bd[1];
     ph.b2 = bd[2];
   }
@@ -168,10 +176,10 @@ __device__ __forceinline__ PrimHit side_trace(const RenderArgs& a, float fx, flo
 // Shaded radiance (no 1/S) of the side ray through (fx, fy) with hit ph, over
 // lights [j0, j1).
 template <bool DUMP, bool TEX>
-__device__ __forceinline__ V3 side_shade(const RenderArgs& a, float fx, float fy, const PrimHit& ph, int k, int j0,
+__device__ __forceinline__ V3 side_shade(const RenderArgs& a, double fx, double fy, const PrimHit& ph, int k, int j0,
                                          int j1, bool with_sh, bool& amb) {
   Sample sm;
-  camera_ray_film(a, fx, fy, sm);
+  camera_ray_film(a, (float)fx, (float)fy, sm);
   const double bd[3] = {1.0 - ph.b1 - ph.b2, ph.b1, ph.b2};
   Frame fr = {};
   const bool shaded = ph.id >= 0 && shading_frame<TEX>(a, sm, ph.id, ph.t, bd, fr);
@@ -232,7 +240,8 @@ __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const Ed
   const double ltot = e.cdf[e.E - 1];
   int eid = 0, pid = -1;
   bool amb = false;
-  float fx = 0.0f, fy = 0.0f, mx = 0.0f, my = 0.0f, u1 = 0.0f;
+  double fx = 0.0, fy = 0.0, mxd = 0.0, myd = 0.0;
+  float mx = 0.0f, my = 0.0f, u1 = 0.0f;
   double pax = 0, pay = 0, paz = 1, pbz = 1;
   if (in && ltot > 0.0) {
     const U4 r = philox((uint32_t)k, 0u, PURPOSE_EDGE, a.step, a.k0, a.k1);
@@ -251,17 +260,20 @@ __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const Ed
     const double u = (double)unit24(r.y);
     const double yx = pa.x + u * (pb.x - pa.x), yy = pa.y + u * (pb.y - pa.y);
     const double lx = pb.x - pa.x, ly = pb.y - pa.y, ll = hypot(lx, ly);
-    mx = (float)(-ly / ll);
-    my = (float)(lx / ll);
-    fx = (float)yx;
-    fy = (float)yy;
+    mxd = -ly / ll;
+    myd = lx / ll;
+    mx = (float)mxd;
+    my = (float)myd;
+    fx = yx;
+    fy = yy;
     const int pxi = (int)floor(yx), pyi = (int)floor(yy);
     if (pxi >= 0 && pxi < a.W && pyi >= 0 && pyi < a.H) pid = pyi * a.W + pxi;
     u1 = (float)u;
     pax = pa.x; pay = pa.y; paz = pa.z; pbz = pb.z;
   }
   const bool active = pid >= 0;
-  const float fxm = fx - 1e-3f * mx, fym = fy - 1e-3f * my, fxp = fx + 1e-3f * mx, fyp = fy + 1e-3f * my;
+  const double fxm = fx - kEdgeSide * mxd, fym = fy - kEdgeSide * myd, fxp = fx + kEdgeSide * mxd,
+               fyp = fy + kEdgeSide * myd;
   if (wv < 2) side_hit[wv][lane] = side_trace<DUMP>(a, wv ? fxp : fxm, wv ? fyp : fym, active, amb);
   __syncthreads();
   const PrimHit hm = side_hit[0][lane], hp = side_hit[1][lane];

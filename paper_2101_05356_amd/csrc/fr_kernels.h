@@ -31,10 +31,19 @@ __host__ __device__ inline float adam_bias(float b, int t) {
 // Range: |sum| < 2^31; resolution 2^-32.
 typedef unsigned long long fix_t;
 constexpr double kFixOne = 4294967296.0;   // 2^32
-__device__ __forceinline__ fix_t to_fix(float v) { return (fix_t)__float2ll_rn(v * 4294967296.0f); }
-__device__ __forceinline__ fix_t to_fix_d(double v) { return (fix_t)__double2ll_rn(v * kFixOne); }
+// A contribution beyond the range saturates at +-2^62 (the conversion is then
+// defined; a gradient that large is far outside any render's range).
+__device__ __forceinline__ fix_t to_fix(float v) {
+  return (fix_t)__float2ll_rn(fminf(fmaxf(v * 4294967296.0f, -4.611686e18f), 4.611686e18f));
+}
+__device__ __forceinline__ fix_t to_fix_d(double v) {
+  return (fix_t)__double2ll_rn(fmin(fmax(v * kFixOne, -4.611686018427388e18), 4.611686018427388e18));
+}
 __device__ __forceinline__ void fix_add(fix_t* p, float v) {
   if (v != 0.0f) atomicAdd(p, to_fix(v));
+}
+__device__ __forceinline__ void fix_add_d(fix_t* p, double v) {
+  if (v != 0.0) atomicAdd(p, to_fix_d(v));
 }
 __host__ __device__ __forceinline__ double from_fix(fix_t a) { return (double)(long long)a * (1.0 / kFixOne); }
 
@@ -104,18 +113,16 @@ struct MeshDev {
   int32_t* vf_idx = nullptr;        // [3F]
   float* normals = nullptr;         // [N*3]
   float* nlen = nullptr;            // [N] length of the unnormalised normal sum
-  float* gnorm = nullptr;           // [N*3] backward scratch: projected dE/dn
+  // Per-call buffers of the adjoint.  A render call takes them from the
+  // caller's workspace; only a batch job's mesh holds its own.
+  float* gnorm = nullptr;           // [N*3] projected dE/dn
   // fixed-point backward accumulators [13N + 12]: verts, normals, diffuse,
   // specular (3N each), roughness (N), camera (12)
   fix_t* acc = nullptr;
-  fix_t* slots = nullptr;           // [kSlots * (12 L + 12)] light/camera partial slots
-  size_t slots_cap = 0;
   // unique edges and their faces, for the boundary term
   int32_t* edges = nullptr;         // [E*2]
   int32_t* edge_faces = nullptr;    // [E*2]
   int32_t* face_nbr = nullptr;      // [F*3] face across each edge of a face (-1: open edge)
-  fix_t* se_acc = nullptr;          // [3N + 9L + 12] shadow-edge accumulators: verts, light geometry, camera
-  size_t se_cap = 0;
   // BVH: binary tree (build + refit) and its 4-wide collapse (traversal)
   BvhNode* nodes = nullptr;         // [max(F-1,1)]
   Bvh4Node* nodes4 = nullptr;       // [n4]
@@ -136,22 +143,11 @@ struct MeshDev {
   float* partial = nullptr;         // [64*6]
   float* scene_box = nullptr;       // [6]
   int32_t* depth = nullptr;         // [2]: depth, validation error count
-  // per-render scratch
-  LightRec* lights = nullptr;       // [light_cap]
-  int light_cap = 0;
-  float* ltmp = nullptr;            // light-gradient partials
+  // per-call buffers of the boundary term (as gnorm and acc above)
   double* edge_len = nullptr;       // [E] film length of silhouette edges (0 otherwise)
   double* edge_cdf = nullptr;       // [E] inclusive running sum
   uint8_t* face_front = nullptr;    // [F]
   double* scan_part = nullptr;      // [ceil(E/1024)] tile totals of the edge CDF scan
-  PrimHit* prim = nullptr;          // [W*H*S] primary hits of the current render call
-  size_t prim_cap = 0;
-  uint32_t* vis = nullptr;          // [n_lchunks][W*H*S] shadow masks a forward kept for its adjoint
-  size_t vis_cap = 0;
-  float* img_partial = nullptr;     // per-light-chunk partial images
-  size_t img_partial_cap = 0;
-  fix_t* tex_acc = nullptr;         // [7 M^2] fixed-point texel gradients: diffuse, specular, roughness
-  size_t tex_acc_cap = 0;
   int bvh_depth = -1;
   int built = 0;
 };
@@ -233,7 +229,7 @@ void launch_light_stage(const float* faces, const float* P, int J, float* p0, fl
 void launch_light_stage_backward(const float* faces, const float* P, int J, const float* gg, const float* gr,
                                  float* gP, hipStream_t st);
 void launch_zero(float* p, int n, hipStream_t st);
-void launch_axpy(float* dst, const float* src, int n, hipStream_t st);
+void launch_axpy(float* dst, const float* src, float a, const float* s, int n, hipStream_t st);   // dst += a s[0] src
 // render.hip
 // The primary pass (camera-ray hits into a.prim); the render launchers run it first.
 void launch_primary(const RenderArgs& a, hipStream_t st);
@@ -253,13 +249,17 @@ constexpr int kSlots = 1024;
 struct MapRegWeights { float w_sym, w_chroma, w_smooth, w_box; };
 void launch_landmarks(const float* V, const int32_t* idx, int n, const float* cam, float tan_half, int W, int H,
                       const float* z, float* loss, float* gV, float* gcam, hipStream_t st);
-void launch_prior(const float* x, const float* sigma, int n, int kind, float w, float* loss, float* g, double* scratch,
-                  hipStream_t st);
+void launch_prior(const float* x, const float* sigma, int n, int kind, float w, float* loss, float* g, hipStream_t st);
 void launch_map_regularizers(const float* Cm, const float* Sm, const float* Rm, const float* C0, const float* S0, int M,
                              const MapRegWeights& w, float* loss, float* gC, float* gS, float* gR, double* scratch,
                              hipStream_t st);
+// scratch: ceil(W H / 256) FP64 block sums; gtmp: the [H*W*3] sign image (smoothing only)
 void launch_loss(const float* img, const float* target, int W, int H, int smooth, float* loss, float* dEdp,
                  double* scratch, float* gtmp, hipStream_t st);
+// Device bytes of fr_loss's scratch for a W x H image, and of the map
+// regularisers' for M x M maps (both 256-byte aligned pieces).
+size_t loss_scratch_bytes(int W, int H, int smooth);
+size_t map_reg_scratch_bytes(int M);
 // backward.hip
 // Interior adjoint: per-vertex gradients into `fg`, light and camera
 // gradients into the slots and then added to g.light_geom, g.light_rad, g.cam.

@@ -30,7 +30,7 @@ __device__ __forceinline__ void loss_block(const float* __restrict__ img, const 
       }
       const float d = p - tgt[3 * pid + c];
       acc += (double)fabsf(d);
-      gsign[3 * pid + c] = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
+      if (gsign) gsign[3 * pid + c] = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
     }
   }
   red[threadIdx.x] = acc;
@@ -206,32 +206,31 @@ void launch_map_regularizers(const float* Cm, const float* Sm, const float* Rm, 
 // ---------------------------------------------------------------------------
 // Stage I priors (Sec. 4 "Stage I", Eq. loss1): statistical w sum (x/sigma)^2,
 // soft box w sum (min(x,0)^2 + max(x-1,0)^2), and the light prior
-// w sum_j ||I_j - mean_c(I_j)||^2 over RGB triples.  One thread per value
-// (per light for the light prior); FP64 block and final sums.
+// w sum_j ||I_j - mean_c(I_j)||^2 over RGB triples.  One workgroup: thread t
+// takes values (lights, for the light prior) t, t + 256, ... in order, then a
+// fixed-order FP64 tree sum (the priors act on parameter vectors of a few
+// hundred values; no scratch memory).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_prior(const float* __restrict__ x, const float* __restrict__ sigma, int n,
-                                               int kind, float w, float* __restrict__ g,
-                                               double* __restrict__ partial) {
+                                               int kind, float w, float* __restrict__ g, float* __restrict__ loss) {
   __shared__ double red[256];
-  const int i = blockIdx.x * 256 + threadIdx.x;
   double e = 0.0;
-  if (kind == FR_PRIOR_LIGHT_CHROMA) {
-    if (i < n / 3) {
-      const float m = (x[3 * i] + x[3 * i + 1] + x[3 * i + 2]) * (1.0f / 3.0f);
+  const int m = kind == FR_PRIOR_LIGHT_CHROMA ? n / 3 : n;
+  for (int i = threadIdx.x; i < m; i += 256) {
+    if (kind == FR_PRIOR_LIGHT_CHROMA) {
+      const float mu = (x[3 * i] + x[3 * i + 1] + x[3 * i + 2]) * (1.0f / 3.0f);
       for (int c = 0; c < 3; ++c) {
-        const float d = x[3 * i + c] - m;
+        const float d = x[3 * i + c] - mu;
         e += (double)w * (double)d * (double)d;
         if (g) g[3 * i + c] += w * 2.0f * d;
       }
-    }
-  } else if (i < n) {
-    if (kind == FR_PRIOR_STATISTICAL) {
+    } else if (kind == FR_PRIOR_STATISTICAL) {
       const float q = x[i] / sigma[i];
-      e = (double)w * (double)q * (double)q;
+      e += (double)w * (double)q * (double)q;
       if (g) g[i] += w * 2.0f * q / sigma[i];
     } else {
       const float lo = fminf(x[i], 0.0f), hi = fmaxf(x[i] - 1.0f, 0.0f);
-      e = (double)w * ((double)lo * lo + (double)hi * hi);
+      e += (double)w * ((double)lo * lo + (double)hi * hi);
       if (g) g[i] += w * (2.0f * lo + 2.0f * hi);
     }
   }
@@ -241,14 +240,11 @@ __global__ __launch_bounds__(256) void k_prior(const float* __restrict__ x, cons
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) loss[0] = (float)red[0];
 }
 
-void launch_prior(const float* x, const float* sigma, int n, int kind, float w, float* loss, float* g, double* scratch,
-                  hipStream_t st) {
-  const int blocks = std::max(1, cdiv(n, 256));
-  hipLaunchKernelGGL(k_prior, dim3(blocks), dim3(256), 0, st, x, sigma, n, kind, w, g, scratch);
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, scratch, blocks, loss);
+void launch_prior(const float* x, const float* sigma, int n, int kind, float w, float* loss, float* g, hipStream_t st) {
+  hipLaunchKernelGGL(k_prior, dim3(1), dim3(256), 0, st, x, sigma, n, kind, w, g, loss);
 }
 
 // ---------------------------------------------------------------------------
@@ -311,13 +307,22 @@ void launch_landmarks(const float* V, const int32_t* idx, int n, const float* ca
   hipLaunchKernelGGL(k_landmarks, dim3(1), dim3(256), 0, st, V, idx, n, cam, tan_half, W, H, z, loss, gV, gcam);
 }
 
+static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t loss_scratch_bytes(int W, int H, int smooth) {
+  const size_t px = (size_t)W * H;
+  return al256((px + 255) / 256 * sizeof(double)) + (smooth ? al256(3 * px * sizeof(float)) : 0);
+}
+
+size_t map_reg_scratch_bytes(int M) { return al256(((size_t)M * M + 255) / 256 * sizeof(double)); }
+
 void launch_loss(const float* img, const float* target, int W, int H, int smooth, float* loss, float* dEdp,
                  double* scratch, float* gtmp, hipStream_t st) {
   const double e = 0.60653065971263342;   // exp(-1/2)
   const double z = (1.0 + 2.0 * e) * (1.0 + 2.0 * e);
   const Taps w{(float)(1.0 / z), (float)(e / z), (float)(e * e / z)};
   const int blocks = (W * H + 255) / 256;
-  float* gs = (smooth && dEdp) ? gtmp : (dEdp ? dEdp : gtmp);
+  float* gs = dEdp ? (smooth ? gtmp : dEdp) : nullptr;
   hipLaunchKernelGGL(k_loss, dim3(blocks), dim3(256), 0, st, img, target, W, H, smooth, w, gs, scratch);
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, scratch, blocks, loss);
   if (smooth && dEdp) hipLaunchKernelGGL(k_smooth_adjoint, dim3(blocks), dim3(256), 0, st, gtmp, W, H, w, dEdp);

@@ -20,14 +20,8 @@ namespace fr {
 // ---------------------------------------------------------------------------
 constexpr int kVtxLanes = 8;
 
-struct D3 { double x, y, z; };
 __device__ __forceinline__ D3 d3(const float* __restrict__ p, int i) {
   return {(double)p[3 * i], (double)p[3 * i + 1], (double)p[3 * i + 2]};
-}
-__device__ __forceinline__ D3 operator+(D3 a, D3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
-__device__ __forceinline__ D3 operator-(D3 a, D3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ __forceinline__ D3 crossd(D3 a, D3 b) {
-  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 // Sum over the eight lanes of a group; every lane of the wave must call it.
 __device__ __forceinline__ D3 group8_sum(D3 a) {
@@ -433,21 +427,20 @@ __global__ void k_zero_f32(float* __restrict__ p, int n) {
   zero_f32_block(p, n, blockIdx.x);
 }
 
-__device__ __forceinline__ void axpy_block(float* __restrict__ dst, const float* __restrict__ src, int n, int bid) {
-  const int i = bid * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] += src[i];
-}
-
-__global__ void k_axpy(float* __restrict__ dst, const float* __restrict__ src, int n) {
-  axpy_block(dst, src, n, blockIdx.x);
+// dst += a s[0] src (s nullable: 1): the sums of loss terms and gradient
+// contributions that the optimisation steps compose.
+__global__ void k_axpy(float* __restrict__ dst, const float* __restrict__ src, float a, const float* __restrict__ s,
+                       int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] += (s ? a * s[0] : a) * src[i];
 }
 
 void launch_zero(float* p, int n, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(k_zero_f32, dim3(cdiv(n, 256)), dim3(256), 0, st, p, n);
 }
 
-void launch_axpy(float* dst, const float* src, int n, hipStream_t st) {
-  if (n > 0) hipLaunchKernelGGL(k_axpy, dim3(cdiv(n, 256)), dim3(256), 0, st, dst, src, n);
+void launch_axpy(float* dst, const float* src, float a, const float* s, int n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_axpy, dim3(cdiv(n, 256)), dim3(256), 0, st, dst, src, a, s, n);
 }
 
 // ---------------------------------------------------------------------------

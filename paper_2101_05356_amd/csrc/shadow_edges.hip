@@ -34,6 +34,13 @@ __device__ __forceinline__ double pick_prob(uint64_t i, uint64_t n) {
   return (double)(hi - lo) * (1.0 / 4294967296.0);
 }
 
+// FP64 vectors of the jumps' derivative chain: a jump's position and its
+// dw1/dtheta are ill conditioned when x is far from the occluder edge or the
+// edge nearly parallel to the line (1/D1); jumps are rare (under 1 % of the
+// line samples at the face workload), so they are solved in FP64.
+__device__ __forceinline__ D3 d3(V3 a) { return {(double)a.x, (double)a.y, (double)a.z}; }
+__device__ __forceinline__ void fix_add3(fix_t* p, D3 v) { fix_add_d(p, v.x); fix_add_d(p + 1, v.y); fix_add_d(p + 2, v.z); }
+
 template <bool DUMP, bool TEX>
 __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const ShadowEdgeArgs& e, int i) {
   const int lane = lane_id();
@@ -96,19 +103,23 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
   // |occluder| times as fast as x)
   const V3 x = fr.x;
   V3 xlo = {0.0f, 0.0f, 0.0f};
+  double bd[3] = {1.0, 0.0, 0.0};
+  D3 Xd = {0.0, 0.0, 0.0};   // the FP64 barycentric point
   if (shaded) {
     const int* tv = a.tris + 3 * h.id;
     const int vi[3] = {tv[0], tv[1], tv[2]};
-    double bd[3];
     bary64(a, fx, fy, vi, bd);
     double X[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < 3; ++k)
       for (int c = 0; c < 3; ++c) X[c] += bd[k] * (double)a.verts[3 * vi[k] + c];
     xlo = {(float)(X[0] - (double)x.x), (float)(X[1] - (double)x.y), (float)(X[2] - (double)x.z)};
+    Xd = {X[0], X[1], X[2]};
   }
   const auto rel = [&](V3 p) { return (p - x) - xlo; };
   const V3 y0 = p0 + e2 * v, y1 = y0 + e1 * ell;
-  const V3 Nw = cross(rel(y0), rel(y1));
+  // (y0 - x) x (y1 - x) = (y0 - x) x (y1 - y0): the second form keeps the wedge's
+  // normal free of the cancellation of two nearly parallel long vectors
+  const V3 Nw = cross(rel(y0), e1 * ell);
   const float nN = sqrtf(dot(Nw, Nw));
   shaded = shaded && nN > 0.0f;
   const float pad = 1e-4f;
@@ -119,16 +130,16 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
   // outward in-plane normals of the wedge triangle's sides x -> y0 -> y1 -> x
   const V3 sn0 = cross(rel(y0), Nw), sn1 = cross(y1 - y0, Nw), sn2 = cross(rel(y1) * -1.0f, Nw);
   const float kinv = Lj.shape == FR_LIGHT_TRIANGLE ? 2.0f : 1.0f;
-  const float wgt = valid && a.L > 0
-                        ? (float)(1.0 / ((double)e.n_samples * pick_prob((uint64_t)tile, n_t) * pick_prob(kin, n_in) *
-                                         pick_prob((uint64_t)max(j, 0), (uint64_t)a.L)))
-                        : 0.0f;
+  const double wgt = valid && a.L > 0
+                         ? 1.0 / ((double)e.n_samples * pick_prob((uint64_t)tile, n_t) * pick_prob(kin, n_in) *
+                                  pick_prob((uint64_t)max(j, 0), (uint64_t)a.L))
+                         : 0.0;
   const float* g = e.dEdp + 3 * (size_t)pid;
   const V3 gpix = valid ? V3{g[0], g[1], g[2]} : V3{0.0f, 0.0f, 0.0f};
   int n_ok = 0;
   long long key = 0;
-  V3 gx_tot = {0.0f, 0.0f, 0.0f};
-  V3 gy_tot = {0.0f, 0.0f, 0.0f}, ge1_tot = {0.0f, 0.0f, 0.0f}, ge2_tot = {0.0f, 0.0f, 0.0f};
+  D3 gx_tot = {0.0, 0.0, 0.0};
+  D3 gy_tot = {0.0, 0.0, 0.0}, ge1_tot = {0.0, 0.0, 0.0}, ge2_tot = {0.0, 0.0, 0.0};
   const auto near_plane = [&](float sv, V3 E) { return fabsf(sv) < kSePlane * nN * (1.0f + sqrtf(dot(rel(E), rel(E)))); };
 
   // ---- wave-cooperative walk of the tree with every lane's wedge
@@ -191,7 +202,10 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
         int J = 0;
         if (cand) {
           P = A + (B - A) * (sa / (sa - sb));
-          nab = cross(rel(A), rel(B));
+          // (A - x) x (B - x) = (A - x) x (B - A): an edge far from x makes the two
+          // x-relative vectors nearly parallel, and 1 / D1 would amplify their
+          // product's cancellation
+          nab = cross(rel(A), B - A);
           D1 = dot(nab, e1);
           w1 = D1 != 0.0f ? -dot(nab, rel(y0)) / D1 : -1.0f;
           yk = p0 + e1 * w1 + e2 * v;
@@ -267,18 +281,26 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
             brdf_eval<DUMP>(a.variant, a.components, fr, ls, fv, gflag);
             if (DUMP && gflag != 0.0f) amb = true;
             const float hv = gpix.x * fv[0] * Lj.rad[0] + gpix.y * fv[1] * Lj.rad[1] + gpix.z * fv[2] * Lj.rad[2];
-            const float coef = wgt * kinv / (float)a.S * (float)J * hv * ls.geom;
-            if (coef != 0.0f) {
-              const float c = -coef / D1;
-              const V3 Ax = rel(A), Bx = rel(B), Yx = rel(yk);
-              const V3 ga = cross(Bx, Yx) * c, gb = cross(Yx, Ax) * c, gy = nab * c;
-              gx_tot = gx_tot - ga - gb - gy;
+            const double coef = wgt * (double)kinv / (double)a.S * (double)J * (double)hv * (double)ls.geom;
+            if (coef != 0.0) {
+              // the jump again in FP64: D(w1) = det[A - x, B - x, y(w1) - x] = (A - x) x (B - A) . (y(w1) - x)
+              const D3 Ad = d3(A), Bd = d3(B), e1d = d3(e1), e2d = d3(e2);
+              const D3 nabd = crossd(Ad - Xd, Bd - Ad);
+              const double D1d = dotd(nabd, e1d);
+              const D3 y0d = d3(p0) + e2d * (double)v;
+              const double w1d = -dotd(nabd, y0d - Xd) / D1d;
+              const D3 Yd = y0d + e1d * w1d;
+              const double c = -coef / D1d;
+              // dw1/dtheta = -(dD/dtheta) / (dD/dw1); dD/dx = -(dD/da + dD/db + dD/dy) by
+              // translation invariance, and Bx x Yx + Yx x Ax + Ax x Bx = (B - A) x (Y - A)
+              const D3 ga = crossd(Bd - Xd, Yd - Xd) * c, gb = crossd(Yd - Xd, Ad - Xd) * c, gy = nabd * c;
+              gx_tot = gx_tot - crossd(Bd - Ad, Yd - Ad) * c;
               gy_tot = gy_tot + gy;
-              ge1_tot = ge1_tot + gy * w1;
-              ge2_tot = ge2_tot + gy * v;
+              ge1_tot = ge1_tot + gy * w1d;
+              ge2_tot = ge2_tot + gy * (double)v;
               if (e.gverts) {
-                fix_add(e.gverts + 3 * ia, ga.x); fix_add(e.gverts + 3 * ia + 1, ga.y); fix_add(e.gverts + 3 * ia + 2, ga.z);
-                fix_add(e.gverts + 3 * ib, gb.x); fix_add(e.gverts + 3 * ib + 1, gb.y); fix_add(e.gverts + 3 * ib + 2, gb.z);
+                fix_add3(e.gverts + 3 * ia, ga);
+                fix_add3(e.gverts + 3 * ib, gb);
               }
             }
           }
@@ -290,46 +312,49 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
     node = readlane_i(stack, sp);
   }
 
-  // ---- light geometry, and x's path to its triangle and the camera
-  const bool has = gy_tot.x != 0.0f || gy_tot.y != 0.0f || gy_tot.z != 0.0f || gx_tot.x != 0.0f ||
-                   gx_tot.y != 0.0f || gx_tot.z != 0.0f;
+  // ---- light geometry, and x's path to its triangle and the camera (FP64:
+  // x = o + t d, t = (v0 - o) . n / (d . n), d = R dc / |R dc|, o = T)
+  const bool has = gy_tot.x != 0.0 || gy_tot.y != 0.0 || gy_tot.z != 0.0 || gx_tot.x != 0.0 || gx_tot.y != 0.0 ||
+                   gx_tot.z != 0.0;
   if (has) {
     if (e.glight) {
       fix_t* gl = e.glight + 9 * (size_t)j;
-      fix_add(gl + 0, gy_tot.x); fix_add(gl + 1, gy_tot.y); fix_add(gl + 2, gy_tot.z);
-      fix_add(gl + 3, ge1_tot.x); fix_add(gl + 4, ge1_tot.y); fix_add(gl + 5, ge1_tot.z);
-      fix_add(gl + 6, ge2_tot.x); fix_add(gl + 7, ge2_tot.y); fix_add(gl + 8, ge2_tot.z);
+      fix_add3(gl, gy_tot);
+      fix_add3(gl + 3, ge1_tot);
+      fix_add3(gl + 6, ge2_tot);
     }
     const int* tv = a.tris + 3 * h.id;
-    const V3 v0 = ld3(a.verts, tv[0]), v1 = ld3(a.verts, tv[1]), v2 = ld3(a.verts, tv[2]);
-    const V3 d = sm.ray.d, o = sm.ray.o;
-    const V3 ea = v1 - v0, eb = v2 - v0;
-    const V3 n = cross(ea, eb);
-    const float idn = 1.0f / dot(d, n);
-    const float t = dot(v0 - o, n) * idn;
-    const float g_t = dot(gx_tot, d);
-    const V3 go = gx_tot - n * (g_t * idn);
-    const V3 gd = gx_tot * t - n * (g_t * t * idn);
-    // v0 - x from the FP64 barycentrics of the shading point (an FP32 o + t d
-    // would carry ~ulp(|o|) into this difference of nearby points)
-    const V3 gn = (ea * fr.b[1] + eb * fr.b[2]) * (-g_t * idn);
-    const V3 gea = cross(eb, gn), geb = cross(gn, ea);
-    const V3 gv0 = n * (g_t * idn) - gea - geb;
+    const D3 v0 = d3(ld3(a.verts, tv[0])), v1 = d3(ld3(a.verts, tv[1])), v2 = d3(ld3(a.verts, tv[2]));
+    const float* R = a.cam;
+    const D3 dc = {(2.0 * fx / (double)a.W - 1.0) * a.tan_half_d * a.aspect_d, (1.0 - 2.0 * fy / (double)a.H) * a.tan_half_d,
+                   -1.0};
+    const D3 dw = {R[0] * dc.x + R[1] * dc.y + R[2] * dc.z, R[3] * dc.x + R[4] * dc.y + R[5] * dc.z,
+                   R[6] * dc.x + R[7] * dc.y + R[8] * dc.z};
+    const double inv_len = 1.0 / sqrt(dotd(dw, dw));
+    const D3 d = dw * inv_len, o = {(double)R[9], (double)R[10], (double)R[11]};
+    const D3 ea = v1 - v0, eb = v2 - v0;
+    const D3 n = crossd(ea, eb);
+    const double idn = 1.0 / dotd(d, n);
+    const double t = dotd(v0 - o, n) * idn;
+    const double g_t = dotd(gx_tot, d);
+    const D3 go = gx_tot - n * (g_t * idn);
+    const D3 gd = gx_tot * t - n * (g_t * t * idn);
+    // v0 - x = -(b1 ea + b2 eb) from the FP64 barycentrics of the shading point
+    const D3 gn = (ea * bd[1] + eb * bd[2]) * (-g_t * idn);
+    const D3 gea = crossd(eb, gn), geb = crossd(gn, ea);
+    const D3 gv0 = n * (g_t * idn) - gea - geb;
     if (e.gverts) {
-      const V3 gvv[3] = {gv0, gea, geb};
-      for (int k = 0; k < 3; ++k) {
-        fix_add(e.gverts + 3 * tv[k], gvv[k].x);
-        fix_add(e.gverts + 3 * tv[k] + 1, gvv[k].y);
-        fix_add(e.gverts + 3 * tv[k] + 2, gvv[k].z);
-      }
+      fix_add3(e.gverts + 3 * tv[0], gv0);
+      fix_add3(e.gverts + 3 * tv[1], gea);
+      fix_add3(e.gverts + 3 * tv[2], geb);
     }
     if (e.gcam) {
-      // d = dw / |dw|, dw = R dc, o = T
-      const V3 gdw = (gd - d * dot(gd, d)) * sm.inv_len;
-      const float gR[9] = {gdw.x * sm.dc.x, gdw.x * sm.dc.y, gdw.x * sm.dc.z, gdw.y * sm.dc.x, gdw.y * sm.dc.y,
-                           gdw.y * sm.dc.z, gdw.z * sm.dc.x, gdw.z * sm.dc.y, gdw.z * sm.dc.z};
-      for (int k = 0; k < 9; ++k) fix_add(e.gcam + k, gR[k]);
-      fix_add(e.gcam + 9, go.x); fix_add(e.gcam + 10, go.y); fix_add(e.gcam + 11, go.z);
+      // d = dw / |dw|, dw = R dc
+      const D3 gdw = (gd - d * dotd(gd, d)) * inv_len;
+      const double gdv[3] = {gdw.x, gdw.y, gdw.z}, dcv[3] = {dc.x, dc.y, dc.z};
+      for (int r = 0; r < 3; ++r)
+        for (int q2 = 0; q2 < 3; ++q2) fix_add_d(e.gcam + 3 * r + q2, gdv[r] * dcv[q2]);
+      fix_add3(e.gcam + 9, go);
     }
   }
   if (DUMP && valid) {

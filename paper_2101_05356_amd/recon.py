@@ -164,13 +164,13 @@ class Reconstruction:
         E, dEdp = R.loss(img, job.target, smooth=job.smooth)
         self.grad.zero_()
         self.g_vobj.zero_()
+        # the adjoint adds the radiance gradient straight into its parameter slots
         g = R.render_backward(self.mesh, sc, dEdp, job.brdf_variant, edge_samples=job.edge_samples,
                               groups=("verts", "diffuse", "light_rad"), verts=self.v_w, events=ev.get("bwd"),
-                              reuse_forward=True)
+                              reuse_forward=True, out={"light_rad": self.grad[sl["rad"]].view(-1, 3)})
         R.pose_backward(self.v_obj, self.param[sl["pose"]], g["verts"], self.g_vobj, self.grad[sl["pose"]])
         R.blend_backward(mt.basis_geo, self.g_vobj, self.grad[sl["geo"]])
         R.blend_backward(mt.basis_alb, g["diffuse"], self.grad[sl["alb"]])
-        self.grad[sl["rad"]] += g["light_rad"].view(-1)
         R.adam_step(self.param, self.grad, self.m, self.v, self.lr, self.t)
         self.last_image = img
         return E
@@ -267,18 +267,20 @@ class Stage1:
         e_box, _ = R.prior(self.x[K_id:mt.K_geo], R.PRIOR_BOX, 1.0, g=gx[K_id:mt.K_geo])
         e_l, _ = R.prior(sc.light_rad, R.PRIOR_LIGHT_CHROMA, 0.01, g=g["light_rad"])
         gw = R.light_stage_backward(self.faces, self.w, g["light_geom"], g["light_rad"])
-        total = E + e_id + e_alb + e_box + e_l
+        total = E   # Eq. loss1: the photometric term plus the priors, summed on the device
+        for e in (e_id, e_alb, e_box, e_l):
+            R.axpy(total, e)
         if self.land is not None:
             # E_land on the posed vertices, back through pose and blend
-            g_lv = torch.zeros_like(self.v_w)
+            g_l = torch.zeros_like(self.v_w)
             e_land = R.landmark_loss(self.v_w, self.land[0], self.ds.cam, self.ds.fov_y, self.ds.W, self.ds.H,
-                                     self.land[1], gverts=g_lv)
-            if self.w_land != 1.0:
-                g_lv *= self.w_land
+                                     self.land[1], gverts=g_l)
+            g_lv = torch.zeros_like(self.v_w)
+            R.axpy(g_lv, g_l, self.w_land)
             g_lobj = torch.zeros_like(self.v_obj)
             R.pose_backward(self.v_obj, self.x[sl["pose"]], g_lv, g_lobj, gx[sl["pose"]])
             R.blend_backward(mt.basis_geo, g_lobj, gx[sl["geo"]])
-            total = total + self.w_land * e_land
+            R.axpy(total, e_land, self.w_land)
         return total, gx, gw
 
     def step(self):
@@ -320,13 +322,13 @@ class Stage2:
         sc = dataclasses.replace(self.scene, tex_diffuse=C, tex_specular=S, tex_roughness=Rm, step=self.t)
         img = R.render_forward(self.mesh, sc, keep_shadows=True)
         E, dEdp = R.loss(img, self.target, smooth=True)
-        g = R.render_backward(self.mesh, sc, dEdp, groups=R.TEX_GROUPS, reuse_forward=True)
         w = self.weights
         Er, gC, gS, gR = R.map_regularizers(C, S, Rm, self.C0, self.S0, w_sym=w[0], w_chroma=w[1], w_smooth=w[2],
                                             w_box=w[3])
-        for x, gr, gt, m, v, lr in zip(self.maps, (gC, gS, gR), (g["tex_diffuse"], g["tex_specular"],
-                                                                 g["tex_roughness"]), self.m, self.v, self.lr):
-            gr += gt
+        # the adjoint adds the texel gradients onto the regularisers' (Eq. loss3)
+        R.render_backward(self.mesh, sc, dEdp, groups=R.TEX_GROUPS, reuse_forward=True,
+                          out={"tex_diffuse": gC, "tex_specular": gS, "tex_roughness": gR})
+        for x, gr, m, v, lr in zip(self.maps, (gC, gS, gR), self.m, self.v, self.lr):
             R.adam_step(x, gr, m, v, lr, self.t)
         return E, Er
 

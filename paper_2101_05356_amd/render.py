@@ -64,11 +64,30 @@ class Mesh:
         check(rc, ctx.h, "fr_mesh_create")
         self.h = h
         self._verts = None
+        self._ws = None
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None and _lib._lib is not None:
             _lib._lib.fr_mesh_destroy(self.h)
             self.h = None
+
+    def workspace_bytes(self, sc: "DeviceScene", light_chunk: int = 0, keep_shadows: bool = True) -> int:
+        """Device bytes a render call of this scene size needs (fr_render_workspace_size)."""
+        s = sc.struct()
+        o = FrRenderOpts()
+        o.light_chunk, o.keep_shadows = int(light_chunk), int(bool(keep_shadows))
+        n = ctypes.c_size_t()
+        check(lib().fr_render_workspace_size(self.h, ctypes.byref(s), ctypes.byref(o), ctypes.byref(n)), self.ctx.h,
+              "fr_render_workspace_size")
+        return int(n.value)
+
+    def workspace(self, sc: "DeviceScene", light_chunk: int = 0) -> torch.Tensor:
+        """The mesh's own workspace (a torch device buffer, grown on demand and
+        kept, so that a forward's decisions reach the backward that follows)."""
+        need = self.workspace_bytes(sc, light_chunk)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=sc.verts.device)
+        return self._ws
 
     def update(self, verts: torch.Tensor, rebuild: bool = False, builder: str = "sah"):
         """Normals + BVH over world positions verts [N,3] (kept alive by the mesh).
@@ -180,6 +199,12 @@ def _event_handle(ev):
     return ev.cuda_event
 
 
+def _set_ws(o: FrRenderOpts, mesh: Mesh, sc: DeviceScene, workspace, light_chunk=0):
+    ws = mesh.workspace(sc, light_chunk) if workspace is None else workspace
+    assert ws.dtype == torch.uint8 and ws.is_contiguous()
+    o.workspace, o.workspace_bytes = ws.data_ptr(), ws.numel()
+
+
 def _opts(brdf_variant=0, components=3, edge_samples=0, dbg=None, light_chunk=0, events=None) -> FrRenderOpts:
     o = FrRenderOpts()
     o.brdf_variant, o.components, o.edge_samples = int(brdf_variant), int(components), int(edge_samples)
@@ -194,12 +219,13 @@ def _opts(brdf_variant=0, components=3, edge_samples=0, dbg=None, light_chunk=0,
 
 
 def render_forward(mesh: Mesh, sc: DeviceScene, brdf_variant=0, components=3, dump=False, verts=None, stats=None,
-                   light_chunk=0, events=None, keep_shadows=False):
+                   light_chunk=0, events=None, keep_shadows=False, workspace=None):
     """Image [H,W,3]; with dump=True also (hit [H*W,S], pflag [H*W,S], vis [H*W,S,L]).
     `stats` (a uint64-sized int64 tensor [10], dump only) accumulates traversal counts.
     `events` (two torch.cuda.Event with timing) bracket the render kernel itself.
-    `keep_shadows`: the mesh keeps the shadow decisions for a backward with
-    reuse_forward."""
+    `keep_shadows`: the workspace keeps the shadow decisions for a backward
+    with reuse_forward.  `workspace`: a uint8 device tensor of at least
+    mesh.workspace_bytes(sc) bytes (default: the mesh's own)."""
     dev = sc.verts.device
     img = torch.empty((sc.H, sc.W, 3), dtype=torch.float32, device=dev)
     dbg = None
@@ -210,6 +236,7 @@ def render_forward(mesh: Mesh, sc: DeviceScene, brdf_variant=0, components=3, du
     s = sc.struct(verts)
     o = _opts(brdf_variant, components, 0, dbg, light_chunk, events)
     o.keep_shadows = int(bool(keep_shadows))
+    _set_ws(o, mesh, sc, workspace, light_chunk)
     if stats is not None:
         assert dump and stats.dtype == torch.int64 and stats.numel() == 10
         o.dbg_stats = stats.data_ptr()
@@ -221,13 +248,17 @@ def render_forward(mesh: Mesh, sc: DeviceScene, brdf_variant=0, components=3, du
     return img, dbg[0].view(-1, S), dbg[1].view(-1, S), dbg[2].view(-1, S, max(L, 1))
 
 
-def loss(image: torch.Tensor, target: torch.Tensor, smooth: bool = True, want_grad: bool = True):
-    """(E [1], dE/dp [H,W,3] or None)."""
+def loss(image: torch.Tensor, target: torch.Tensor, smooth: bool = True, want_grad: bool = True, workspace=None):
+    """(E [1], dE/dp [H,W,3] or None).  `workspace`: a uint8 device tensor
+    of at least fr_loss_workspace_size bytes (default: a new torch buffer)."""
     H, W = image.shape[:2]
     out = torch.empty(1, dtype=torch.float32, device=image.device)
     g = torch.empty_like(image) if want_grad else None
-    check(lib().fr_loss(_p(image), _p(target), W, H, 1 if smooth else 0, _p(out), _p(g), _stream()), None,
-          "fr_loss")
+    if workspace is None:
+        workspace = torch.empty(int(lib().fr_loss_workspace_size(W, H, int(bool(smooth)))), dtype=torch.uint8,
+                                device=image.device)
+    check(lib().fr_loss(_p(image), _p(target), W, H, 1 if smooth else 0, _p(out), _p(g), _p(workspace),
+                        workspace.numel(), _stream()), None, "fr_loss")
     return out, g
 
 
@@ -237,13 +268,14 @@ TEX_GROUPS = ("tex_diffuse", "tex_specular", "tex_roughness")
 
 def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_variant=0, components=3,
                     edge_samples=0, groups=GRAD_GROUPS, verts=None, edge_dump=False, light_chunk=0, events=None,
-                    reuse_forward=False):
+                    reuse_forward=False, workspace=None, out=None):
     """Gradients (dict of new tensors) of sum dEdp . image.  `events` (two
     torch.cuda.Event with timing) bracket the interior adjoint kernel.
     `reuse_forward`: take the camera-ray hits of the last render of this mesh
     when it had the same size, samples, counters, vertex and camera buffers,
     and its shadow decisions when it kept them for the same light buffers
-    (their contents unchanged since; the library checks the rest)."""
+    (their contents unchanged since; the library checks the rest).  `out`:
+    tensors (by group name) the gradients are added into instead of new ones."""
     dev = sc.verts.device
     N, L, M = mesh.n_verts, sc.n_lights, sc.tex_size
     B = sc.sh_bands
@@ -252,7 +284,11 @@ def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_varian
                   tex_roughness=(M, M), sh=(B * B, 3))
     if M > 0 and groups is GRAD_GROUPS:
         groups = tuple(k for k in GRAD_GROUPS if k not in ("diffuse", "specular", "roughness")) + TEX_GROUPS
-    out = {k: torch.zeros(shapes[k], dtype=torch.float32, device=dev) for k in groups}
+    given = dict(out) if out is not None else {}
+    out = {k: given[k] if k in given else torch.zeros(shapes[k], dtype=torch.float32, device=dev)
+           for k in tuple(groups) + tuple(k for k in given if k not in groups)}
+    for k, t in out.items():
+        assert t.dtype == torch.float32 and t.is_contiguous() and t.numel() == int(np.prod(shapes[k])), k
     g = FrGrads()
     for k in GRAD_GROUPS + TEX_GROUPS + ("sh",):
         setattr(g, k, out[k].data_ptr() if k in out else None)
@@ -264,6 +300,7 @@ def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_varian
     s = sc.struct(verts)
     o = _opts(brdf_variant, components, edge_samples, dbg, light_chunk, events)
     o.reuse_forward = int(bool(reuse_forward))
+    _set_ws(o, mesh, sc, workspace)
     check(lib().fr_render_backward(mesh.h, ctypes.byref(s), ctypes.byref(o), _p(dEdp.contiguous()), ctypes.byref(g),
                                    _stream()), mesh.ctx.h, "fr_render_backward")
     if edge_dump and dbg is not None:
@@ -273,7 +310,7 @@ def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_varian
 
 
 def shadow_edges(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, n_samples: int, brdf_variant=0, components=3,
-                 groups=("verts", "light_geom", "cam"), verts=None, dump=False, out=None):
+                 groups=("verts", "light_geom", "cam"), verts=None, dump=False, out=None, workspace=None):
     """Shadow-edge (secondary visibility) boundary term of sum dEdp . image
     from n_samples line samples, after a forward render of the same scene:
     dict of gradients over `groups` (verts [N,3], light_geom [L,9], cam
@@ -292,6 +329,7 @@ def shadow_edges(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, n_samples: int
         flag = torch.zeros(max(n_samples, 1), dtype=torch.uint8, device=dev)
     s = sc.struct(verts)
     o = _opts(brdf_variant, components, 0, None, 0, None)
+    _set_ws(o, mesh, sc, workspace)
     check(lib().fr_shadow_edges(mesh.h, ctypes.byref(s), ctypes.byref(o), _p(dEdp.contiguous()), int(n_samples),
                                 ctypes.byref(g), _p(rec) if dump else None, _p(flag) if dump else None, _stream()),
           mesh.ctx.h, "fr_shadow_edges")
@@ -331,8 +369,9 @@ def map_regularizers(C, S, R, C0, S0, w_sym=0.3, w_chroma=0.3, w_smooth=2e-4, w_
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     g = [torch.zeros_like(x) for x in (C, S, R)] if grads else [None, None, None]
     w = FrMapRegWeights(float(w_sym), float(w_chroma), float(w_smooth), float(w_box))
+    ws = torch.empty(int(lib().fr_map_regularizers_workspace_size(M)), dtype=torch.uint8, device=dev)
     check(lib().fr_map_regularizers(*[_p(x.contiguous()) for x in (C, S, R, C0, S0)], M, ctypes.byref(w), _p(loss),
-                                    *[_p(x) for x in g], _stream()), None, "fr_map_regularizers")
+                                    *[_p(x) for x in g], _p(ws), ws.numel(), _stream()), None, "fr_map_regularizers")
     return (loss, *g)
 
 
@@ -392,6 +431,13 @@ def pose_backward(v, pose, gw, gv=None, gpose=None):
     return gv, gpose
 
 
+def axpy(y, x, a=1.0, s=None):
+    """y += a * s[0] * x on the device (s: a device scalar tensor, or None for 1)."""
+    assert y.is_contiguous() and x.is_contiguous() and y.numel() == x.numel()
+    check(lib().fr_axpy(_p(y), _p(x), float(a), _p(s), y.numel(), _stream()), None, "fr_axpy")
+    return y
+
+
 def adam_step(param, grad, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
     check(lib().fr_adam_step(_p(param), _p(grad), _p(m), _p(v), _p(lr), param.numel(), int(t), beta1, beta2, eps,
                              _stream()), None, "fr_adam_step")
@@ -423,9 +469,12 @@ class RenderFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g_img, g_loss):
         (dEdp,) = ctx.saved_tensors
-        seed = dEdp * g_loss.reshape(1, 1, 1) if g_loss is not None else torch.zeros_like(dEdp)
+        # seed = g_loss dE/dp + g_img, composed by the library
+        seed = torch.zeros_like(dEdp)
+        if g_loss is not None:
+            axpy(seed, dEdp, 1.0, g_loss.reshape(1).contiguous())
         if g_img is not None:
-            seed = seed + g_img
+            axpy(seed, g_img.contiguous())
         o = ctx.opts
         g = render_backward(ctx.mesh, ctx.sc, seed, o.get("brdf_variant", 0), o.get("components", 3),
                             o.get("edge_samples", 0),

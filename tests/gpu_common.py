@@ -7,7 +7,9 @@ same seeded inputs and compare them under the parity contract:
   the GPU);
 * values are compared after the oracle re-evaluates flagged decisions with the
   GPU's choice: pixels |d| <= 1e-4 max(|p|, 1e-3 max p); gradients per group
-  ||d||_2 <= 1e-4 ||g||_2 and per element |d| <= 1e-4 max(|g|, 1e-2 ||g||_inf).
+  ||d||_2 <= 1e-4 ||g||_2 and per element |d| <= 1e-4 max(|g|, 1e-2 ||g||_inf)
+  (an element whose FP32 sum is ill conditioned: |d| <= 1e-4 of the sum of
+  its terms' magnitudes).
 """
 import dataclasses
 
@@ -65,6 +67,21 @@ def decisions_compare(sc, gpu_hit, gpu_pflag, gpu_vis, orc, pixels=None):
     return rep, merged_hit, merged_vis
 
 
+def replay_rgb(sc, orc, merged_hit, merged_vis, pixels=None, **kw):
+    """The oracle's pixel values under the merged decisions: its own values
+    where every sample's decisions are its own, re-evaluated (forced to the
+    GPU's decisions) only on the pixels that hold a flagged sample."""
+    import oracle
+    rows = np.nonzero((merged_hit != orc["hit"]).any(1) | (merged_vis != orc["vis"]).any((1, 2)))[0]
+    rgb = np.array(orc["rgb"], np.float64).reshape(-1, 3)
+    if rows.size:
+        W = sc.camera.W
+        px = (np.arange(W * sc.camera.H) if pixels is None else np.asarray(pixels))[rows].astype(np.int32)
+        rep = oracle.render(sc, pixels=px, force_hit=merged_hit[rows], force_vis=merged_vis[rows], **kw)
+        rgb[rows] = rep["rgb"]
+    return rgb
+
+
 def pixel_tol_ok(gpu, ref):
     gpu = np.asarray(gpu, np.float64).reshape(-1, 3)
     ref = np.asarray(ref, np.float64).reshape(-1, 3)
@@ -75,24 +92,76 @@ def pixel_tol_ok(gpu, ref):
 
 
 def grad_tol_ok(gpu, ref, rel=1e-4, floor_frac=1e-2, mag=None, cond_max=10.0):
-    """L2 and element-wise relative error of a gradient group.  With `mag`
-    (per element, the sum of the magnitudes of the per-pixel terms the
-    element sums), the element-wise bar applies only to elements whose sum is
-    well conditioned (mag <= cond_max * max(|ref|, floor)): an FP32 sum of
-    terms of mixed sign has an error proportional to mag, not to |sum|; the
-    L2 bar covers every element."""
+    """Parity bar of a gradient group: ||d||_2 <= rel ||g||_2 over the group,
+    and per element |d_k| <= rel max(|g_k|, floor_frac ||g||_inf).  With
+    `mag` (per element, the sum of the magnitudes of the terms the element
+    sums: the condition of an FP32 sum of terms of mixed sign, whose error
+    scales with mag, not with |sum|), an element whose sum is ill conditioned
+    (mag_k > cond_max max(|g_k|, floor)) is held to |d_k| <= rel mag_k
+    instead, and a group whose terms' magnitudes exceed cond_max times its
+    norm is held in L2 to the norm of its element bounds.  Returns (ok,
+    relative L2 error, worst element-wise ratio to its bound times rel,
+    number of elements held to the magnitude bound)."""
     gpu = np.asarray(gpu, np.float64).ravel()
     ref = np.asarray(ref, np.float64).ravel()
     n = np.linalg.norm(ref)
     if n == 0.0:
-        return bool(np.all(gpu == 0.0)), 0.0, 0.0
+        return bool(np.all(gpu == 0.0)), 0.0, 0.0, 0
     l2 = float(np.linalg.norm(gpu - ref) / n)
     floor = floor_frac * np.abs(ref).max()
-    e = np.abs(gpu - ref) / np.maximum(np.abs(ref), floor)
+    scale = np.maximum(np.abs(ref), floor)
+    n_mag = 0
+    l2_bar = rel
     if mag is not None:
-        e = e[np.asarray(mag, np.float64).ravel() <= cond_max * np.maximum(np.abs(ref), floor)]
+        mg = np.asarray(mag, np.float64).ravel()
+        ill = mg > cond_max * scale
+        scale = np.where(ill, mg, scale)
+        n_mag = int(ill.sum())
+        # a group whose sum cancels as a whole (its terms' magnitudes above
+        # cond_max times its norm) is held in L2 to the norm of the element
+        # bounds: an FP32 evaluation cannot resolve it better than its terms
+        if np.linalg.norm(mg) > cond_max * n:
+            l2_bar = rel * np.linalg.norm(scale) / n
+    e = np.abs(gpu - ref) / scale
     elem = float(e.max()) if e.size else 0.0
-    return (l2 <= rel and elem <= rel), l2, elem
+    return (l2 <= l2_bar and elem <= rel), l2, elem, n_mag
+
+
+def edge_term_parity(sc, m, ds, w, ns, flag_max, rel=1e-4, note=print):
+    """Primary-visibility boundary term of the GPU against the oracle's on the
+    same draws: the records (edge, pixel, side-ray hits) bit for bit on the
+    samples neither side flags; then, with the flagged samples' pixels zeroed
+    in dE/dp on both sides (which removes exactly their terms, and their
+    pixels' other terms, from both sums), the vertex and camera gradients
+    under grad_tol_ok.  The comparison always runs."""
+    import oracle
+    H, W = sc.camera.H, sc.camera.W
+    g = R.render_backward(m, ds, torch.tensor(w.reshape(H, W, 3)).cuda(), edge_samples=ns, groups=("cam",),
+                          edge_dump=True)
+    torch.cuda.synchronize()
+    rec, fl = to_np(g["edge_rec"]), to_np(g["edge_flag"])
+    eo = oracle.edge_grad(sc, w.astype(np.float64), ns)
+    flag = (fl != 0) | (eo["flag"] != 0)
+    note(f"edge samples: {ns}, flagged {flag.mean():.4f}")
+    assert flag.mean() < flag_max
+    assert np.array_equal(rec[~flag], eo["edge"][~flag]), "edge picks, pixels and side hits must match"
+    drop = np.unique(np.concatenate([rec[flag, 1], eo["edge"][flag, 1]]))
+    w2 = w.copy()
+    w2[drop[drop >= 0]] = 0.0
+    d2 = torch.tensor(w2.reshape(H, W, 3)).cuda()
+    ge = R.render_backward(m, ds, d2, edge_samples=ns, groups=("verts", "cam"))
+    gi = R.render_backward(m, ds, d2, edge_samples=0, groups=("verts", "cam"))
+    torch.cuda.synchronize()
+    eo2 = oracle.edge_grad(sc, w2.astype(np.float64), ns)
+    # each term carries the FP32 difference f- - f+ of two shaded values:
+    # its error scales with |f-| + |f+|, the magnitude sums below
+    mg = oracle.edge_grad(sc, w2.astype(np.float64), ns, abs_terms=True)
+    okv = grad_tol_ok(to_np(ge["verts"]) - to_np(gi["verts"]), eo2["verts"], rel=rel, mag=mg["verts"])
+    okc = grad_tol_ok(to_np(ge["cam"]) - to_np(gi["cam"]), eo2["cam"], rel=rel, mag=mg["cam"])
+    note(f"edge grads (ok, l2, worst element, magnitude-bounded): verts {okv}, cam {okc}")
+    assert np.abs(eo2["verts"]).sum() > 0
+    assert okv[0] and okc[0], (okv, okc)
+    return okv, okc
 
 
 def magnitude_sums(sc, hit, vis, dEdp, groups, pixels=None):

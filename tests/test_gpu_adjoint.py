@@ -26,6 +26,7 @@ import numpy as np
 import pytest
 
 from paper_2101_05356_amd import scenes
+from tests import gpu_common as G
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -91,9 +92,9 @@ def test_batched_step_gradient_matches_oracle_gradient_and_differences(oracle_li
     ga[sl["alb"]] = oracle.blend_vjp(model.basis_alb.astype(np.float64), g["diffuse"].reshape(-1))
     ga[sl["pose"]] = gpose
     ga[sl["rad"]] = g["rad"].reshape(-1)
-    rel_l2 = np.linalg.norm(g_gpu - ga) / np.linalg.norm(ga)
-    worst = np.max(np.abs(g_gpu - ga) / (np.abs(ga) + 1e-3 * np.abs(ga).max()))
-    assert rel_l2 < 1e-4 and worst < 1e-3, (rel_l2, worst)
+    ok, rel_l2, worst, _ = G.grad_tol_ok(g_gpu, ga)
+    print(f"batched step gradient vs oracle: relative L2 {rel_l2:.3e}, worst element {worst:.3e}", flush=True)
+    assert ok, (rel_l2, worst)
 
     # (2) finite differences of the oracle's loss
     def loss(p):

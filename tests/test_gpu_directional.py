@@ -45,10 +45,10 @@ def _backward_parity(sc, pixels=None, variant=0, seed=3):
     few hundred lights from every direction, a vertex's normal or roughness
     gradient sums hundreds of per-light terms of both signs within each
     sample (opposite lights pull the normal opposite ways), in FP32 on the
-    GPU: the element-wise bar applies to the elements whose sum is well
-    conditioned (sum of term magnitudes, per pixel and per (sample, light)
-    term, at most 10x the sum; gpu_common.grad_tol_ok), the L2 bar to every
-    element."""
+    GPU: an element whose sum is ill conditioned (sum of term magnitudes, per
+    pixel and per (sample, light) term, above 10x the sum) is held to 1e-4 of
+    that magnitude sum, every other element to 1e-4 of its value
+    (gpu_common.grad_tol_ok), and the L2 bar covers every element."""
     import oracle
     m, ds, img, hit, vis, mh, mv = _forward_parity(sc, pixels=pixels, variant=variant)
     W, H = sc.camera.W, sc.camera.H
@@ -70,8 +70,8 @@ def _backward_parity(sc, pixels=None, variant=0, seed=3):
     mag = {k: np.maximum(v, np.abs(terms[k])) for k, v in mag.items()}
     res = {gk: G.grad_tol_ok(G.to_np(g[gk]), go[ok_], mag=mag[ok_]) for gk, ok_ in pairs}
     _note(f"gradients (ok, l2, worst element): {res}")
-    for k, (ok_, l2, el) in res.items():
-        assert ok_, (k, l2, el)
+    for k, (ok_, l2, el, n_mag) in res.items():
+        assert ok_, (k, l2, el, n_mag)
     # the directions' gradients (p0 slots) are there; e1, e2 slots stay zero
     gl = G.to_np(g["light_geom"]).reshape(-1, 3, 3)
     env = sc.lights.shape == scenes.LIGHT_DIRECTIONAL
@@ -109,33 +109,10 @@ def test_environment_edge_term(oracle_lib):
     with 8 lights: up to 5 %); its pixel's dE/dp is then zeroed on both
     sides, which removes exactly its term (and its pixel's other terms)
     from both gradients."""
-    import oracle
     sc = mixed_patch(W=32, H=32, spp=2)
     m, ds = G.gpu_setup(sc)
-    ns = 32 * 32
-    w = np.random.default_rng(9).normal(size=(ns, 3)).astype(np.float32)
-    g = G.R.render_backward(m, ds, torch.tensor(w.reshape(32, 32, 3)).cuda(), edge_samples=ns, groups=("cam",),
-                            edge_dump=True)
-    torch.cuda.synchronize()
-    rec, fl = G.to_np(g["edge_rec"]), G.to_np(g["edge_flag"])
-    eo = oracle.edge_grad(sc, w.astype(np.float64), ns)
-    flag = (fl != 0) | (eo["flag"] != 0)
-    _note(f"edge samples: {ns}, flagged {flag.mean():.4f}")
-    assert flag.mean() < 0.05
-    assert np.array_equal(rec[~flag], eo["edge"][~flag])
-    drop = np.unique(np.concatenate([rec[flag, 1], eo["edge"][flag, 1]]))
-    w2 = w.copy()
-    w2[drop[drop >= 0]] = 0.0
-    d2 = torch.tensor(w2.reshape(32, 32, 3)).cuda()
-    ge = G.R.render_backward(m, ds, d2, edge_samples=ns, groups=("verts", "cam"))
-    gi = G.R.render_backward(m, ds, d2, edge_samples=0, groups=("verts", "cam"))
-    torch.cuda.synchronize()
-    eo2 = oracle.edge_grad(sc, w2.astype(np.float64), ns)
-    okv = G.grad_tol_ok(G.to_np(ge["verts"]) - G.to_np(gi["verts"]), eo2["verts"], rel=2e-4)
-    okc = G.grad_tol_ok(G.to_np(ge["cam"]) - G.to_np(gi["cam"]), eo2["cam"], rel=2e-4)
-    _note(f"edge grads: verts {okv}, cam {okc}")
-    assert np.abs(eo2["verts"]).sum() > 0
-    assert okv[1] < 2e-4 and okc[1] < 2e-4
+    w = np.random.default_rng(9).normal(size=(32 * 32, 3)).astype(np.float32)
+    G.edge_term_parity(sc, m, ds, w, 32 * 32, flag_max=0.05, note=_note)
 
 
 def test_kept_decisions_across_light_groups_bit_identical(oracle_lib):

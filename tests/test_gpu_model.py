@@ -48,7 +48,7 @@ def test_pose_and_adjoint(oracle_lib):
     G.R.pose_backward(t32(v), t32(pose), t32(gw), gv, gp)
     rv, rp = oracle.pose_vjp(v, pose, gw)
     assert np.allclose(G.to_np(gv).reshape(N, 3), rv, rtol=1e-5, atol=2e-6)
-    ok, l2, el = G.grad_tol_ok(G.to_np(gp), rp)
+    ok, l2, el, _ = G.grad_tol_ok(G.to_np(gp), rp)
     assert l2 < 1e-5, (l2, el)
 
 

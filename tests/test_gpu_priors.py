@@ -24,7 +24,7 @@ def test_priors_parity(oracle_lib, n):
         E, go = oracle.prior(x, kind, w, s)
         assert abs(float(loss.item()) - E) <= 1e-5 * max(abs(E), 1e-6), (kind, float(loss.item()), E)
         if np.abs(go).sum() > 0:
-            ok, l2, el = G.grad_tol_ok(G.to_np(g), go)
+            ok, l2, el, _ = G.grad_tol_ok(G.to_np(g), go)
             assert ok, (kind, l2, el)
         else:
             assert not np.any(G.to_np(g))

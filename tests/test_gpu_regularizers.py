@@ -25,5 +25,5 @@ def test_map_regularizers_parity(oracle_lib, M):
     E, (oC, oS, oR) = oracle.map_regularizers(C, S, R, C0, S0)
     assert abs(float(loss.item()) - E) <= 1e-5 * max(abs(E), 1.0)
     for got, want in ((gC, oC), (gS, oS), (gR, oR)):
-        ok, l2, el = G.grad_tol_ok(G.to_np(got), want)
+        ok, l2, el, _ = G.grad_tol_ok(G.to_np(got), want)
         assert ok, (M, l2, el)

@@ -23,8 +23,11 @@ def _forward_parity(sc, pixels=None, variant=0, components=3):
     import oracle
     m, ds = G.gpu_setup(sc)
     img, hit, pflag, vis = G.R.render_forward(m, ds, brdf_variant=variant, components=components, dump=True)
+    # the production kernel (no dump; the one every step and the bench run)
+    prod = G.R.render_forward(m, ds, brdf_variant=variant, components=components)
     torch.cuda.synchronize()
     img = G.to_np(img).reshape(-1, 3)
+    assert np.array_equal(G.to_np(prod).reshape(-1, 3), img), "the production forward must equal the dump build"
     hit, pflag, vis = G.to_np(hit), G.to_np(pflag), G.to_np(vis)
     assert np.all(hit >= -1), "every sample of the dump must be written"
     assert np.all((vis & 0x7F) <= 3), "every shadow code of the dump must be written"
@@ -33,9 +36,9 @@ def _forward_parity(sc, pixels=None, variant=0, components=3):
     _note(f"decisions: {rep}")
     assert rep["hit_mismatch"] == 0 and rep["vis_mismatch"] == 0, rep
     assert rep["prim_flagged"] < 5e-3 and rep["shadow_flagged"] < 5e-3, rep
-    replay = oracle.render(sc, pixels=pixels, force_hit=mh, force_vis=mv, brdf_variant=variant, components=components)
+    ref = G.replay_rgb(sc, orc, mh, mv, pixels, brdf_variant=variant, components=components)
     gpu_px = img if pixels is None else img[pixels]
-    ok, worst = G.pixel_tol_ok(gpu_px, replay["rgb"])
+    ok, worst = G.pixel_tol_ok(gpu_px, ref)
     _note(f"pixels: worst relative error {worst:.3e}")
     assert ok, worst
     return m, ds, img, hit, vis, mh, mv
@@ -69,6 +72,12 @@ def test_diffuse_and_specular_masks(oracle_lib):
 
 
 def test_loss_parity(oracle_lib):
+    """Loss and dE/dp.  Without smoothing the residual p - p^R is one FP32
+    subtraction, whose sign is exact (an exact zero stays zero), so dE/dp
+    must match everywhere.  With smoothing, a smoothed residual within 1e-5
+    of zero has a sign decided by rounding; dE/dp is compared on every
+    element outside the 3 x 3 neighbourhoods (the adjoint smoothing's reach)
+    of such residuals."""
     import oracle
     rng = np.random.default_rng(1)
     for (W, H) in [(64, 64), (37, 23), (1, 5), (256, 256)]:
@@ -78,15 +87,33 @@ def test_loss_parity(oracle_lib):
         for smooth in (True, False):
             E, g = G.R.loss(torch.tensor(img).cuda(), torch.tensor(tgt).cuda(), smooth)
             Eo, go, ps = oracle.loss_and_grad(img, tgt, smooth)
-            resid = (ps - tgt)
-            amb = np.abs(resid) < 1e-5                # sign decided within FP32 rounding
             assert abs(float(E.item()) - Eo) <= 1e-5 * Eo
             gg = G.to_np(g)
-            if not amb.any():
-                assert np.allclose(gg, go, rtol=1e-5, atol=1e-6)
+            if smooth:
+                amb = np.abs(ps - tgt) < 1e-5
+                near = np.zeros_like(amb)
+                for dy in (-1, 0, 1):
+                    for dx in (-1, 0, 1):
+                        sh = np.roll(np.roll(amb, dy, 0), dx, 1)
+                        if dy == 1: sh[0] = False
+                        if dy == -1: sh[-1] = False
+                        if dx == 1: sh[:, 0] = False
+                        if dx == -1: sh[:, -1] = False
+                        near |= sh
+                keep = ~near
+                _note(f"loss {W}x{H}: {int(amb.sum())} near-zero smoothed residuals, {int(near.sum())} elements masked")
+            else:
+                assert (gg[0, 0] == 0).all() and (go[0, 0] == 0).all()
+                keep = np.ones(gg.shape, bool)
+            assert keep.mean() > 0.99
+            assert np.allclose(gg[keep], go[keep], rtol=1e-5, atol=1e-6)
 
 
-def _backward_parity(sc, pixels=None, variant=0, seed=3):
+def _backward_parity(sc, pixels=None, variant=0, seed=3, conditioned=False):
+    """Forward parity, then the interior adjoint of a seeded dE/dp on the
+    pixels.  conditioned: elements whose FP32 per-sample sums are ill
+    conditioned (the oracle's term magnitudes, abs_terms) are held to 1e-4 of
+    those magnitudes (gpu_common.grad_tol_ok)."""
     import oracle
     m, ds, img, hit, vis, mh, mv = _forward_parity(sc, pixels=pixels, variant=variant)
     W, H = sc.camera.W, sc.camera.H
@@ -97,15 +124,16 @@ def _backward_parity(sc, pixels=None, variant=0, seed=3):
     g = G.R.render_backward(m, ds, torch.tensor(dEdp.reshape(H, W, 3)).cuda(), brdf_variant=variant)
     torch.cuda.synchronize()
     go = oracle.grad(sc, mh, mv, dEdp[rows].astype(np.float64), pixels=pixels, brdf_variant=variant)
+    mag = (oracle.grad(sc, mh, mv, dEdp[rows].astype(np.float64), pixels=pixels, brdf_variant=variant,
+                       abs_terms=True) if conditioned else {})
     pairs = [("verts", "verts"), ("normals", "normals"), ("diffuse", "diffuse"), ("specular", "specular"),
-             ("roughness", "rough"), ("light_rad", "rad"), ("cam", "cam")]
+             ("roughness", "rough"), ("light_rad", "rad"), ("cam", "cam"), ("light_geom", "light")]
     res = {}
     for gk, ok_ in pairs:
-        res[gk] = G.grad_tol_ok(G.to_np(g[gk]), go[ok_])
-    res["light_geom"] = G.grad_tol_ok(G.to_np(g["light_geom"]), go["light"])
+        res[gk] = G.grad_tol_ok(G.to_np(g[gk]), go[ok_], mag=mag.get(ok_))
     _note(f"gradients (ok, l2, worst element): {res}")
-    for k, (ok_, l2, el) in res.items():
-        assert ok_, (k, l2, el)
+    for k, (ok_, l2, el, n_mag) in res.items():
+        assert ok_, (k, l2, el, n_mag)
 
 
 @pytest.mark.parametrize("variant", [0, 1])
@@ -118,6 +146,17 @@ def test_face_backward_parity_subset(oracle_lib):
     sc = scenes.face_render_scene()
     px = scenes.random_pixel_subset(np.random.default_rng(5), sc.camera.W, sc.camera.H, 32)
     _backward_parity(sc, pixels=px)
+
+
+def test_face_parity_4096_pixels(oracle_lib):
+    """The headline workload (256 x 256 face, 28,002 vertices / 56,000
+    triangles, 16 spp, 72 lights) on 4,096 seeded pixels: every camera and
+    shadow decision of their 65,536 samples (4.7 M shadow decisions), the
+    production kernel's pixels, and every gradient group of the interior
+    adjoint of a seeded dE/dp on those pixels."""
+    sc = scenes.face_render_scene()
+    px = scenes.random_pixel_subset(np.random.default_rng(31), sc.camera.W, sc.camera.H, 4096)
+    _backward_parity(sc, pixels=px, conditioned=True)
 
 
 def test_refit_matches_rebuild(oracle_lib):
@@ -166,34 +205,30 @@ def test_tree_builders_agree_bit_for_bit(oracle_lib):
 
 
 def test_edge_term_parity_patch(oracle_lib):
-    import oracle
     sc = scenes.patch_scene(W=48, H=48, spp=4)
     m, ds = G.gpu_setup(sc)
-    rng = np.random.default_rng(9)
-    w = rng.normal(size=(48 * 48, 3)).astype(np.float32)
-    ns = 48 * 48
-    g = G.R.render_backward(m, ds, torch.tensor(w.reshape(48, 48, 3)).cuda(), edge_samples=ns,
-                            groups=("cam",), edge_dump=True)
-    torch.cuda.synchronize()
-    rec, fl = G.to_np(g["edge_rec"]), G.to_np(g["edge_flag"])
-    eo = oracle.edge_grad(sc, w.astype(np.float64), ns)
-    flag = (fl != 0) | (eo["flag"] != 0)
-    _note(f"edge samples: {ns}, flagged {flag.mean():.4f}")
-    assert flag.mean() < 0.01
-    assert np.array_equal(rec[~flag], eo["edge"][~flag]), "edge picks, pixels and side hits must match"
-    # gradient: GPU interior-free edge term vs oracle edge term
-    ge = G.R.render_backward(m, ds, torch.tensor(w.reshape(48, 48, 3)).cuda(), edge_samples=ns,
-                             groups=("verts", "cam"))
-    gi = G.R.render_backward(m, ds, torch.tensor(w.reshape(48, 48, 3)).cuda(), edge_samples=0,
-                             groups=("verts", "cam"))
-    torch.cuda.synchronize()
-    gv = G.to_np(ge["verts"]) - G.to_np(gi["verts"])
-    gc = G.to_np(ge["cam"]) - G.to_np(gi["cam"])
-    if not flag.any():
-        okv = G.grad_tol_ok(gv, eo["verts"], rel=2e-4)
-        okc = G.grad_tol_ok(gc, eo["cam"], rel=2e-4)
-        _note(f"edge grads: verts {okv}, cam {okc}")
-        assert okv[1] < 2e-4 and okc[1] < 2e-4
+    w = np.random.default_rng(9).normal(size=(48 * 48, 3)).astype(np.float32)
+    G.edge_term_parity(sc, m, ds, w, 48 * 48, flag_max=0.01, note=_note)
+
+
+def test_edge_term_parity_face(oracle_lib):
+    """The boundary term at the headline workload's scale: the 256 x 256 face
+    (28,002 vertices, 56,000 triangles, 16 spp) under its 72 lights, whose
+    side rays the adjoint shades in light groups; dE/dp on 4,096 seeded
+    pixels, 4,096 edge samples over the face's silhouette.  A sample is
+    flagged when any of its 2 x 73 decisions is near-ambiguous; at the
+    closed face's silhouette the side rays hit grazing surface and their
+    shadow rays leave it at grazing angles, so about a fifth of the samples
+    carry one (the FP64 oracle alone flags ~5 % with its 1e-6 band, the FP32
+    band is several times wider); their pixels are removed on both sides."""
+    sc = scenes.face_render_scene()
+    m, ds = G.gpu_setup(sc)
+    W, H = sc.camera.W, sc.camera.H
+    rng = np.random.default_rng(12)
+    w = np.zeros((W * H, 3), np.float32)
+    px = scenes.random_pixel_subset(rng, W, H, 4096)
+    w[px] = rng.normal(size=(len(px), 3)).astype(np.float32)
+    G.edge_term_parity(sc, m, ds, w, 4096, flag_max=0.3, note=_note)
 
 
 def test_backward_reusing_the_forward_decisions_is_bit_identical(oracle_lib):

@@ -3,9 +3,10 @@ FP64 oracle through the C ABI (Sec. 4 "Edge Sampling" for the shadow rays of
 Sec. 3.3): the draws (camera sample, light) bit for bit on every sample, the
 jump counts and edge keys bit for bit on the samples neither side flags as
 near-ambiguous, and the vertex, light-geometry and camera gradients to the
-boundary-term tolerance once the flagged samples' pixels are zeroed in dE/dp
-on both sides (which removes exactly their terms, and their pixels' other
-terms, from both sums)."""
+gradient bar (1e-4 in L2, element-wise 1e-4 of the value or of the terms'
+magnitudes where the sum is ill conditioned) once the flagged samples'
+pixels are zeroed in dE/dp on both sides (which removes exactly their terms,
+and their pixels' other terms, from both sums)."""
 import dataclasses
 import sys
 
@@ -50,19 +51,18 @@ def _parity(sc, n, seed=9, max_flag=0.02, min_jumps=50):
     g2 = G.R.shadow_edges(m, ds, d2, n)
     torch.cuda.synchronize()
     e2 = oracle.shadow_edge_grad(sc, w2.astype(np.float64), n)
-    # Each element sums hundreds of Monte-Carlo terms of both signs (random
-    # dE/dp): its FP32 error scales with the sum of the terms' magnitudes
-    # (mag), so the bar is 1e-4 of |mag|; the plain relative L2 is reported.
+    # Each element sums Monte-Carlo terms of both signs (random dE/dp): an
+    # element whose sum is ill conditioned is held to 1e-4 of the sum of its
+    # terms' magnitudes, every other one to 1e-4 of its value, and each group
+    # to 1e-4 in L2 (gpu_common.grad_tol_ok)
     mag = oracle.shadow_edge_grad(sc, w2.astype(np.float64), n, abs_terms=True)
     res = {}
     for gk, k in (("verts", "verts"), ("light_geom", "light"), ("cam", "cam")):
-        got, ref, mg = G.to_np(g2[gk]).astype(np.float64).ravel(), e2[k].ravel(), mag[k].ravel()
-        res[k] = (float(np.linalg.norm(got - ref) / np.linalg.norm(mg)), float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
-                  float(np.linalg.norm(mg) / np.linalg.norm(ref)))
-    _note(f"gradients (err / |mag|, err / |ref|, |mag| / |ref|): {res}")
+        res[k] = G.grad_tol_ok(G.to_np(g2[gk]), e2[k], mag=mag[k])
+    _note(f"gradients (ok, l2, worst element, magnitude-bounded): {res}")
     assert np.abs(e2["verts"]).sum() > 0 and np.abs(e2["light"]).sum() > 0
-    for k, (rm, rl, _) in res.items():
-        assert rm < 1e-4 and rl < 1e-2, (k, rm, rl)
+    for k, r in res.items():
+        assert r[0], (k, r)
     return g2, e2
 
 

@@ -51,7 +51,7 @@ def test_stage1_light_stage_gradient_matches_oracle(oracle_lib):
     _, gp = oracle.prior(osc.lights.rad, oracle.PRIOR_LIGHT_CHROMA, 0.01)
     want = oracle.light_stage_vjp(scenes.icosahedron_faces().astype(np.float64), stage0.astype(np.float64),
                                   go["light"], go["rad"] + gp)
-    ok, l2, el = G.grad_tol_ok(G.to_np(gw), want)
+    ok, l2, el, _ = G.grad_tol_ok(G.to_np(gw), want)
     assert np.abs(want).sum() > 0 and ok, (l2, el)
 
 

@@ -49,7 +49,7 @@ def test_stage2_gradient_matches_oracle(oracle_lib):
     for got_r, got_t, want_r, want_t in ((gC, g["tex_diffuse"], oC, go["tex_diffuse"]),
                                          (gS, g["tex_specular"], oS, go["tex_specular"]),
                                          (gR, g["tex_roughness"], oR, go["tex_rough"])):
-        ok, l2, el = G.grad_tol_ok(G.to_np(got_r) + G.to_np(got_t), want_r + want_t)
+        ok, l2, el, _ = G.grad_tol_ok(G.to_np(got_r) + G.to_np(got_t), want_r + want_t)
         assert ok, (l2, el)
 
 

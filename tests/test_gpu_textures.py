@@ -88,8 +88,8 @@ def _parity(sc, pixels=None, seed=3, check_grads=True, built_on=None, conditione
         mag = G.magnitude_sums(sc, mh, mv, full, [ok_ for _, ok_ in pairs], pixels=pixels)
     res = {gk: G.grad_tol_ok(G.to_np(g[gk]), go[ok_], mag=mag.get(ok_)) for gk, ok_ in pairs}
     _note(f"gradients (ok, l2, worst element): {res}")
-    for k, (ok_, l2, el) in res.items():
-        assert ok_, (k, l2, el)
+    for k, (ok_, l2, el, n_mag) in res.items():
+        assert ok_, (k, l2, el, n_mag)
     # with maps in use the per-vertex reflectance receives nothing
     assert not np.any(G.to_np(g["diffuse"]))
     assert np.abs(go["tex_diffuse"]).sum() > 0 and np.abs(go["tex_rough"]).sum() > 0
@@ -129,28 +129,11 @@ def test_textured_face_subset(oracle_lib):
 def test_textured_edge_term(oracle_lib):
     """Boundary term over a textured patch: the radiance difference across
     each silhouette edge is read from the maps on both sides."""
-    import oracle
     sc = tilted(scenes.patch_scene(W=40, H=40, spp=4))
     sc = scenes.with_maps(sc, scenes.patch_corner_uv(sc), 32, seed=3)
     m, ds = G.gpu_setup(sc)
     w = np.random.default_rng(9).normal(size=(40 * 40, 3)).astype(np.float32)
-    ns = 40 * 40
-    dEdp = torch.tensor(w.reshape(40, 40, 3)).cuda()
-    g = G.R.render_backward(m, ds, dEdp, edge_samples=ns, groups=("cam",), edge_dump=True)
-    ge = G.R.render_backward(m, ds, dEdp, edge_samples=ns, groups=("verts", "cam"))
-    gi = G.R.render_backward(m, ds, dEdp, edge_samples=0, groups=("verts", "cam"))
-    torch.cuda.synchronize()
-    rec, fl = G.to_np(g["edge_rec"]), G.to_np(g["edge_flag"])
-    eo = oracle.edge_grad(sc, w.astype(np.float64), ns)
-    flag = (fl != 0) | (eo["flag"] != 0)
-    _note(f"edge samples: {ns}, flagged {flag.mean():.4f}")
-    assert flag.mean() < 0.01
-    assert np.array_equal(rec[~flag], eo["edge"][~flag])
-    if not flag.any():
-        okv = G.grad_tol_ok(G.to_np(ge["verts"]) - G.to_np(gi["verts"]), eo["verts"], rel=2e-4)
-        okc = G.grad_tol_ok(G.to_np(ge["cam"]) - G.to_np(gi["cam"]), eo["cam"], rel=2e-4)
-        _note(f"edge grads: verts {okv}, cam {okc}")
-        assert okv[1] < 2e-4 and okc[1] < 2e-4
+    G.edge_term_parity(sc, m, ds, w, 40 * 40, flag_max=0.01, note=_note)
 
 
 def test_large_textured_spot_check(oracle_lib):
@@ -173,3 +156,4 @@ def test_large_textured_spot_check(oracle_lib):
     px = np.sort(np.concatenate([on[:26], off[:6]])).astype(np.int32)
     _note(f"pixels {px.tolist()}")
     _parity(sc, pixels=px, built_on=sc0.verts, flag_max=2e-2)
+
