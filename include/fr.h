@@ -267,6 +267,20 @@ size_t fr_loss_workspace_size(int32_t width, int32_t height, int32_t smooth);
 int fr_loss(const float* d_image, const float* d_target, int32_t width, int32_t height, int32_t smooth,
             float* d_loss, float* d_dEdp, void* d_work, size_t work_bytes, fr_stream stream);
 
+/* fr_loss for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * computation, arguments and results, with the scratch in a static device
+ * array of the library instead of a caller workspace.  The array holds the
+ * scratch of images of at most 2^20 pixels (1024 x 1024; 12.6 MB per device,
+ * resolved at fr_ctx_create or at the first call on a device and held until
+ * the process ends); larger images return FR_ERR_LIMIT before any launch.
+ * Every call on a device shares that device's array (each call writes all the
+ * scratch it reads, so nothing carries over between calls): calls that
+ * overlap in time on one device race; serialise them on one stream.
+ * FR_ERR_DEVICE if the runtime cannot give the array's address. */
+int fr_loss_noalloc(const float* d_image, const float* d_target, int32_t width, int32_t height, int32_t smooth,
+                    float* d_loss, float* d_dEdp, fr_stream stream);
+
 /* Stage II regularisers of the personalised reflectance maps (Sec. 4
  * "Stage II", Eq. loss3; the paper's weights are w_sym = w_chroma = 0.3,
  * w_smooth = 0.0002, w_box = 1):

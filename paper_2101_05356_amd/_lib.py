@@ -104,6 +104,7 @@ SIGNATURES = {
     "fr_render_forward": ([P, P, P, P, P], ctypes.c_int),
     "fr_loss_workspace_size": ([_i32, _i32, _i32], ctypes.c_size_t),
     "fr_loss": ([P, P, _i32, _i32, _i32, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
+    "fr_loss_noalloc": ([P, P, _i32, _i32, _i32, P, P, P], ctypes.c_int),
     "fr_render_backward": ([P, P, P, P, P, P], ctypes.c_int),
     "fr_shadow_edges": ([P, P, P, P, ctypes.c_int32, P, P, P, P], ctypes.c_int),
     "fr_blend": ([P, P, P, _i32, _i32, P, P], ctypes.c_int),

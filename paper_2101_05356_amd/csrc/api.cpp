@@ -370,6 +370,8 @@ int fr_ctx_create(int hip_device, fr_ctx** out) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return FR_ERR_DEVICE;
   if (hipSetDevice(hip_device) != hipSuccess) return FR_ERR_DEVICE;
+  // the static scratch of fr_loss_noalloc on this device
+  if (!fr::noalloc_scratch(hip_device)) return FR_ERR_DEVICE;
   fr_ctx* c = new fr_ctx();
   c->device = hip_device;
   *out = c;

@@ -7,3 +7,4 @@
 #include "backward.hip"
 #include "edges.hip"
 #include "shadow_edges.hip"
+#include "noalloc.hip"

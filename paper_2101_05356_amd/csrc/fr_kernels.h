@@ -259,6 +259,9 @@ void launch_loss(const float* img, const float* target, int W, int H, int smooth
 // Device bytes of fr_loss's scratch for a W x H image, and of the map
 // regularisers' for M x M maps (both 256-byte aligned pieces).
 size_t loss_scratch_bytes(int W, int H, int smooth);
+// noalloc.hip: device address of fr_loss_noalloc's static scratch on device
+// dev (the current device), resolved once per device; nullptr on failure.
+void* noalloc_scratch(int dev);
 size_t map_reg_scratch_bytes(int M);
 // backward.hip
 // Interior adjoint: per-vertex gradients into `fg`, light and camera
