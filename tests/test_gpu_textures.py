@@ -157,3 +157,72 @@ def test_large_textured_spot_check(oracle_lib):
     _note(f"pixels {px.tolist()}")
     _parity(sc, pixels=px, built_on=sc0.verts, flag_max=2e-2)
 
+
+
+def test_large_textured_512_pixels(oracle_lib):
+    """The large workload at full size (1024 x 1024, 100,002 vertices,
+    200,000 triangles, 1024^2 maps, 64 spp, 128 lights), its tree built over
+    the undeformed mesh and refit to the deformed one, on 512 seeded pixels
+    (448 on the face): every camera and shadow decision (3.7 M shadow
+    decisions), the production kernel's pixels and every gradient group of
+    the interior adjoint against the FP64 oracle's outputs stored by
+    tests/golden/make_large_golden.py (the brute-force oracle needs ~0.4 s
+    per face pixel).  Samples either side flags are replayed by the oracle
+    under the GPU's decisions: their pixels' values and gradient terms are
+    recomputed and swapped in."""
+    import os
+    import oracle
+    from tests.golden import make_large_golden as gold
+    gd = np.load(gold.OUT)
+    sc0, sc = gold.large_scene()
+    assert str(gd["fingerprint"]) == gold.fingerprint(sc), "input generators changed: rerun make_large_golden.py"
+    px = gd["pixels"]
+    W, H = sc.camera.W, sc.camera.H
+    m, ds = _setup(sc, sc0.verts)
+    img, hit, pflag, vis = G.R.render_forward(m, ds, dump=True)
+    prod = G.R.render_forward(m, ds)
+    torch.cuda.synchronize()
+    pt = torch.as_tensor(px.astype(np.int64), device=hit.device)
+    hit, pflag, vis = G.to_np(hit[pt]), G.to_np(pflag[pt]), G.to_np(vis[pt])
+    img = G.to_np(img).reshape(-1, 3)
+    assert np.array_equal(G.to_np(prod).reshape(-1, 3), img), "the production forward must equal the dump build"
+    orc = dict(hit=gd["hit"], pflag=gd["pflag"], vis=gd["vis"], sflag=gd["sflag"], rgb=gd["rgb"])
+    rep, mh, mv = G.decisions_compare(sc, hit, pflag, vis, orc)
+    _note(f"decisions: {rep}")
+    assert rep["hit_mismatch"] == 0 and rep["vis_mismatch"] == 0, rep
+    assert rep["prim_flagged"] < 2e-2 and rep["shadow_flagged"] < 2e-2, rep
+    ok, worst = G.pixel_tol_ok(img[px], G.replay_rgb(sc, orc, mh, mv, px))
+    _note(f"pixels: worst relative error {worst:.3e}")
+    assert ok, worst
+    # gradients: the stored ones, with the replayed pixels' terms swapped in
+    dEdp = np.zeros((H * W, 3), np.float32)
+    dEdp[px] = gd["dEdp"]
+    groups = ("verts", "normals", "light_geom", "light_rad", "cam") + G.R.TEX_GROUPS
+    g = G.R.render_backward(m, ds, torch.tensor(dEdp.reshape(H, W, 3)).cuda(), groups=groups)
+    torch.cuda.synchronize()
+    ref, mag = {}, {}
+    for k in gold.GROUPS:
+        n = int(gd[f"{k}_size"])
+        ref[k], mag[k] = np.zeros(n), np.zeros(n)
+        ref[k][gd[f"{k}_idx"]] = gd[f"{k}_val"]
+        mag[k][gd[f"{k}_idx"]] = gd[f"{k}_mag"]
+    rows = np.nonzero((mh != orc["hit"]).any(1) | (mv != orc["vis"]).any((1, 2)))[0]
+    _note(f"pixels replayed: {rows.size}")
+    if rows.size:
+        sub, d = px[rows], gd["dEdp"][rows].astype(np.float64)
+        old = oracle.grad(sc, orc["hit"][rows], orc["vis"][rows], d, pixels=sub)
+        new = oracle.grad(sc, mh[rows], mv[rows], d, pixels=sub)
+        newmag = oracle.grad(sc, mh[rows], mv[rows], d, pixels=sub, abs_terms=True)
+        for k in gold.GROUPS:
+            ref[k] += np.asarray(new[k], np.float64).ravel() - np.asarray(old[k], np.float64).ravel()
+            mag[k] += np.asarray(newmag[k], np.float64).ravel()
+    pairs = [("verts", "verts"), ("normals", "normals"), ("light_rad", "rad"), ("light_geom", "light"),
+             ("cam", "cam"), ("tex_diffuse", "tex_diffuse"), ("tex_specular", "tex_specular"),
+             ("tex_roughness", "tex_rough")]
+    res = {gk: G.grad_tol_ok(G.to_np(g[gk]), ref[k], mag=mag[k]) for gk, k in pairs}
+    _note(f"gradients (ok, l2, worst element, magnitude-bounded): {res}")
+    for k, r in res.items():
+        assert r[0], (k, r)
+    # elements the oracle leaves untouched stay zero
+    for gk, k in pairs:
+        assert not np.any(G.to_np(g[gk]).ravel()[mag[k] == 0.0]), gk
