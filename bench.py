@@ -58,7 +58,10 @@ def parse():
     ap.add_argument("--lights", type=int, default=72)
     ap.add_argument("--edge-samples", type=int, default=-1, help="-1 = W*H")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--recon-steps", type=int, default=150,
+                    help="steps of a whole reconstruction timed from its start (0 = skip)")
+    ap.add_argument("--recompute-steps", type=int, default=20,
+                    help="steps whose adjoint traces its own decisions instead of taking the forward's (0 = skip)")
     ap.add_argument("--profile-only", action="store_true",
                     help="skip the traversal statistics and the CPU baseline (for profilers)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -83,43 +86,104 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_ops(stats, W, H, S, L, backward=False):
+def algorithmic_ops(stats, W, H, S, L, backward=False, traced=False):
     """Lane-operations the algorithm needs for one render (forward: camera and
     shadow traversals + shading) or one adjoint pass (backward: ~3x shading;
-    the camera-ray hits and shadow decisions are the forward's, reused), from
-    the counted per-ray visits of the tree."""
+    with `traced` it also traces the camera and shadow rays again instead of
+    taking the forward's decisions), from the counted per-ray visits of the
+    tree.  Every camera sample draws its jitter and builds its ray; the
+    shading frame and the per-light work (light point, cosines, cull) count
+    only for samples that reach a shading point (stats[10])."""
     cam_box, cam_leaf, cam_rays, sh_box, sh_leaf, sh_rays = stats[:6]
+    shaded = stats[10]
     samples = W * H * S
-    trav = 0 if backward else (cam_box + sh_box) * C_BOX + (cam_leaf + sh_leaf) * C_LEAF
-    shade = samples * (C_RNG + C_CAM) + cam_rays * C_FRAME + cam_rays * L * (C_RNG + C_LIGHT)
-    shade += sh_rays * (C_SETUP + C_BRDF)
-    if backward:
-        shade = samples * (C_RNG + C_CAM) + cam_rays * C_FRAME * ADJ_FACTOR + cam_rays * L * (
-            C_RNG + C_LIGHT * ADJ_FACTOR) + sh_rays * (C_SETUP + C_BRDF * ADJ_FACTOR)
+    trav = (cam_box + sh_box) * C_BOX + (cam_leaf + sh_leaf) * C_LEAF
+    if backward and not traced:
+        trav = 0
+    f = ADJ_FACTOR if backward else 1.0
+    shade = samples * (C_RNG + C_CAM) + shaded * C_FRAME * f + shaded * L * (C_RNG + C_LIGHT * f)
+    shade += sh_rays * (C_SETUP + C_BRDF * f)
     return trav + shade
 
 
-def cpu_baseline(seconds, spp, n_lights, width):
-    """The FP64 oracle (brute force) on a bounded random sample of pixels of the
-    same face workload: forward decisions + shading + dual-number gradient."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(spp, n_lights, width, n_all=768, n_one=48, reps=3):
+    """The FP64 oracle (brute force) on bounded random samples of pixels of the
+    same face workload (forward decisions + shading + dual-number gradient),
+    on all host threads and on one, each the median of `reps` runs over a
+    fixed pixel sample."""
     import oracle
     from paper_2101_05356_amd import scenes
     oracle.build()
     sc = scenes.face_render_scene(W=width, H=width, spp=spp, n_lights=n_lights)
-    rng = np.random.default_rng(99)
     threads = os.cpu_count() or 1
-    done, rays, t0 = 0, 0, time.perf_counter()
-    while time.perf_counter() - t0 < seconds and done < width * width:
-        px = scenes.random_pixel_subset(rng, width, width, 64)
-        r = oracle.render(sc, pixels=px, nthreads=threads)
-        oracle.grad(sc, r["hit"], r["vis"], np.ones((len(px), 3)), pixels=px, nthreads=threads,
+
+    def rate(n_px, nthreads, seed):
+        px = scenes.random_pixel_subset(np.random.default_rng(seed), width, width, n_px)
+        t0 = time.perf_counter()
+        r = oracle.render(sc, pixels=px, nthreads=nthreads)
+        oracle.grad(sc, r["hit"], r["vis"], np.ones((len(px), 3)), pixels=px, nthreads=nthreads,
                     include_normals_path=False)
-        done += len(px)
-        rays += len(px) * spp * (1 + n_lights)
-    dt = time.perf_counter() - t0
-    return {"value": rays / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} random pixels of the {width}x{width} face (spp {spp}, {n_lights} lights): FP64 "
-                      f"brute-force forward decisions + shading + dual-number interior gradient, {dt:.1f} s"}
+        dt = time.perf_counter() - t0
+        return len(px) * spp * (1 + n_lights) / dt, dt
+
+    t_start = time.perf_counter()
+    all_runs = [rate(n_all, threads, 99 + k) for k in range(reps)]
+    one_runs = [rate(n_one, 1, 199 + k) for k in range(reps)]
+    med = lambda runs: float(np.median([r for r, _ in runs]))
+    return {"value": med(all_runs), "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "value_1_core": med(one_runs), "runs": reps,
+            "sample": f"median of {reps} runs each: {n_all} random pixels on {threads} threads, {n_one} on 1 thread, "
+                      f"of the {width}x{width} face (spp {spp}, {n_lights} lights); FP64 brute-force forward "
+                      f"decisions + shading + dual-number interior gradient; {time.perf_counter() - t_start:.1f} s "
+                      f"in all"}
+
+
+def valu_probe(blocks=2048, iters=8192, reps=5):
+    """Achievable non-packed FP32 lane-FMA rate (fr_probe_valu: eight
+    independent FMA chains per lane), median of `reps` launches timed with
+    HIP events on the launch stream."""
+    import torch
+    from paper_2101_05356_amd import render as R
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        R.probe_valu(blocks, iters, out)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        R.probe_valu(blocks, iters, out)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b) * 1e-3)
+    return blocks * 256 * 8 * iters / float(np.median(ts))
+
+
+def copy_probe(n_bytes=1 << 30, reps=5):
+    """Device-to-device copy rate (read + write bytes / s) of a plain copy
+    kernel, median of `reps`."""
+    import torch
+    a = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    return 2.0 * n_bytes / float(np.median(ts))
 
 
 KERNEL_SOURCES = {
@@ -178,7 +242,7 @@ def settle_clocks(rc, seconds):
 def traversal_stats(rc):
     import torch
     from paper_2101_05356_amd import render as R
-    st = torch.zeros(10, dtype=torch.int64, device="cuda")
+    st = torch.zeros(11, dtype=torch.int64, device="cuda")
     R.render_forward(rc.mesh, rc.scene(), verts=rc.v_w, dump=True, stats=st)
     torch.cuda.synchronize()
     return st.cpu().numpy().astype(np.float64)
@@ -465,11 +529,15 @@ def main():
         ops_b = algorithmic_ops(stats, W, H, S, L, backward=True)
         dom, ops, ms = ("k_render_bwd_kept", ops_b, bwd_ms) if bwd_ms >= fwd_ms else ("k_render_fwd", ops_f, fwd_ms)
         ach = ops / (ms * 1e-3)
+        peak_meas = valu_probe()
         out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": ach / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                            "unit": "Tlane-op/s", "frac": ach / PEAK_LANE_OPS, "traffic": measured_traffic(dom),
+                           "peak_measured": peak_meas / 1e12, "frac_of_measured_peak": ach / peak_meas,
+                           "lane_ops_per_launch": ops, "kernel_ms": ms,
                            "other": {k: {"ms": t, "achieved": o / (t * 1e-3) / 1e12, "frac": o / (t * 1e-3) / PEAK_LANE_OPS}
                                      for k, o, t in (("k_render_fwd", ops_f, fwd_ms), ("k_render_bwd_kept", ops_b, bwd_ms))
                                      if k != dom}}
+        out["hbm_copy_gbs"] = copy_probe() / 1e9
         cam_rays, sh_rays = stats[2], stats[5]
         out["traversal"] = {
             "tree": "binned-SAH binary tree collapsed to 4-wide, one triangle per leaf",
@@ -482,7 +550,41 @@ def main():
             "simd_efficiency": (stats[0] + stats[1] + stats[3] + stats[4]) /
                                max(64.0 * (4 * (stats[6] + stats[8]) + stats[7] + stats[9]), 1.0)}
         out["rays_cast_per_s"] = (W * H * S + sh_rays) * args.steps / dt
+        out["camera_samples_shaded"] = stats[10]
+    if args.recompute_steps > 0:
+        # the same step with an adjoint that traces its camera and shadow rays again
+        evr = []
+        t0 = time.perf_counter()
+        for _ in range(args.recompute_steps):
+            pair = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                    for k in ("fwd", "bwd")}
+            rc.step(pair, reuse=False)
+            evr.append(pair)
+        torch.cuda.synchronize()
+        dtr = time.perf_counter() - t0
+        bwd_r = float(np.mean([p["bwd"][0].elapsed_time(p["bwd"][1]) for p in evr]))
+        rec = {"steps": args.recompute_steps, "ms_per_step": 1e3 * dtr / args.recompute_steps,
+               "rays_per_s": nominal * args.recompute_steps / dtr, "render_bwd_kernel_ms": bwd_r,
+               "adjoint": "k_render_bwd: camera and shadow rays traced again from the same counters"}
+        if not args.profile_only:
+            ops_r = algorithmic_ops(stats, W, H, S, L, backward=True, traced=True)
+            rec["achieved"] = ops_r / (bwd_r * 1e-3) / 1e12
+            rec["frac"] = ops_r / (bwd_r * 1e-3) / PEAK_LANE_OPS
+        out["recompute"] = rec
     del rc
+    if args.recon_steps > 0:
+        # a whole reconstruction from its start: every step, early and late
+        _, rc2 = make_c2(ctx, W, S, L, args.edge_samples)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = [rc2.step() for _ in range(args.recon_steps)]
+        torch.cuda.synchronize()
+        dt2 = time.perf_counter() - t0
+        out["recon"] = {"steps": args.recon_steps, "ms_per_step": 1e3 * dt2 / args.recon_steps,
+                        "rays_per_s": nominal * args.recon_steps / dt2, "loss_first": float(losses[0].item()),
+                        "loss_last": float(losses[-1].item()),
+                        "workload": "the same face reconstruction timed from step 1 (no warm-up) to the last"}
+        del rc2
     if args.batch_jobs > 0:
         out["batch"] = batch_bench(ctx, mt, args.batch_jobs, args.batch_steps, 2)
         print(json.dumps({"progress": "batch", **out["batch"]}), file=sys.stderr, flush=True)
@@ -503,7 +605,7 @@ def main():
         out["shadow_edges"] = shadow_edge_bench(ctx, args.shadow_edge_samples)
         print(json.dumps({"progress": "shadow_edges", **out["shadow_edges"]}), file=sys.stderr, flush=True)
     if not args.profile_only and not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, S, L, W)
+        out["cpu_baseline"] = cpu_baseline(S, L, W)
     print(json.dumps(out), flush=True)
 
 

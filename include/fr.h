@@ -172,11 +172,12 @@ typedef struct {
   uint8_t* dbg_pflag;
   uint8_t* dbg_vis;
   /* Traversal statistics of the forward dump (device, nullable, accumulated):
-   * [10] uint64: for camera rays, the child boxes a single-ray traversal of
+   * [11] uint64: for camera rays, the child boxes a single-ray traversal of
    * each ray tests (the children of every 4-wide node its ray enters), its
    * triangle tests, and the rays traced; the same three for shadow rays;
    * then the node visits and leaf visits executed by the wave packets for
-   * camera rays, then for shadow rays. */
+   * camera rays, then for shadow rays; then the camera samples that reach a
+   * shading point (a hit facing the camera). */
   uint64_t* dbg_stats;
   /* Timing (nullable): two hipEvent_t recorded on the stream immediately
    * before the primary pass (the camera rays of every sample; the main
@@ -555,6 +556,16 @@ int fr_server_stats(fr_server* server, fr_stats* out);
 int fr_server_wait(fr_server* server, double timeout_s);
 /* Seconds since the server was created (the clock of fr_result). */
 double fr_server_clock(fr_server* server);
+
+/* ---------------------------------------------------------------------------
+ * Measurement probe (not part of the render): `blocks` workgroups of 256
+ * lanes each run eight independent FP32 FMA chains of `iters` steps (8 *
+ * iters lane-FMAs per lane, no memory traffic but one store per lane into
+ * d_out [blocks*256]).  Timed by the caller, it gives the achievable rate of
+ * the non-packed FP32 lane-operations that the ALU roofline of the render
+ * kernels counts.
+ * ------------------------------------------------------------------------- */
+int fr_probe_valu(int32_t blocks, int32_t iters, float* d_out, fr_stream stream);
 
 #ifdef __cplusplus
 }

@@ -142,6 +142,7 @@ SIGNATURES = {
     "fr_server_stats": ([P, P], ctypes.c_int),
     "fr_server_wait": ([P, ctypes.c_double], ctypes.c_int),
     "fr_server_clock": ([P], ctypes.c_double),
+    "fr_probe_valu": ([_i32, _i32, P, P], ctypes.c_int),
 }
 
 

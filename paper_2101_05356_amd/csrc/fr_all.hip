@@ -8,3 +8,4 @@
 #include "edges.hip"
 #include "shadow_edges.hip"
 #include "noalloc.hip"
+#include "probe.hip"

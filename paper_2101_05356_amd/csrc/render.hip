@@ -95,6 +95,7 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
   PixelSample ps = pixel_sample(a, tile, lane);
   float acc[3] = {0.0f, 0.0f, 0.0f};
   TravStats st2 = {0, 0, 0, 0, 0};
+  uint32_t n_shaded = 0;   // dump statistics: camera samples with a shading point (counted by light chunk 0)
   for (int chunk = 0; chunk < a.chunks; ++chunk) {
     const int s = ps.s0 + chunk * 64;
     Sample sm;
@@ -105,6 +106,7 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
     if (ps.valid) ph = load_prim(a, rs, bd);
     Frame fr;
     const bool shaded = ps.valid && ph.id >= 0 && shading_frame<TEX>(a, sm, ph.id, ph.t, bd, fr);
+    if (DUMP && shaded && it.chunk == 0) ++n_shaded;
     // shadow decisions of every light of the chunk, then the shading of the visible ones
     const auto draw = [&](int j) { return philox((uint32_t)ps.pid, (uint32_t)s, 1u + (uint32_t)(a.light0 + j), a.step, a.k0, a.k1); };
     const auto note = [&](int j, bool lit, bool occ, const LightSample& ls, const HitState& sh) {
@@ -149,11 +151,11 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
   if (DUMP && a.dbg_stats) {
     // shadow-ray counts (the primary pass adds the camera rays'): lane counts
     // summed over the wave, wave counts taken once per wave
-    const uint32_t v[5] = {st2.lane_box, st2.lane_leaf, st2.rays, st2.wave_int, st2.wave_leaf};
-    const int slot[5] = {3, 4, 5, 8, 9};
-    for (int k = 0; k < 5; ++k) {
+    const uint32_t v[6] = {st2.lane_box, st2.lane_leaf, st2.rays, st2.wave_int, st2.wave_leaf, n_shaded};
+    const int slot[6] = {3, 4, 5, 8, 9, 10};
+    for (int k = 0; k < 6; ++k) {
       uint32_t x = v[k];
-      if (k < 3)
+      if (k < 3 || k == 5)
         for (int off = 32; off >= 1; off >>= 1) x += (uint32_t)__shfl_xor((int)x, off, 64);
       if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(a.dbg_stats) + slot[k], (unsigned long long)x);
     }

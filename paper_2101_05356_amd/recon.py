@@ -150,24 +150,26 @@ class Reconstruction:
     def render(self):
         return R.render_forward(self.mesh, self.scene(), self.job.brdf_variant, verts=self.v_w)
 
-    def step(self, events=None):
+    def step(self, events=None, reuse=True):
         """One optimisation step; `events` ({"fwd"|"bwd": (start, end)} torch
         events) times the forward render kernel and the interior adjoint kernel.
-        Returns the loss (device tensor [1]) of the image rendered at this step."""
+        `reuse`: the adjoint takes the forward's decisions (camera-ray hits,
+        shadow masks); False makes it trace them again.  Returns the loss
+        (device tensor [1]) of the image rendered at this step."""
         job, mt, sl = self.job, self.mt, self.sl
         self.t += 1
         self.geometry(rebuild=False)
         sc = self.scene()
         ev = events or {}
         img = R.render_forward(self.mesh, sc, job.brdf_variant, verts=self.v_w, events=ev.get("fwd"),
-                               keep_shadows=True)
+                               keep_shadows=reuse)
         E, dEdp = R.loss(img, job.target, smooth=job.smooth)
         self.grad.zero_()
         self.g_vobj.zero_()
         # the adjoint adds the radiance gradient straight into its parameter slots
         g = R.render_backward(self.mesh, sc, dEdp, job.brdf_variant, edge_samples=job.edge_samples,
                               groups=("verts", "diffuse", "light_rad"), verts=self.v_w, events=ev.get("bwd"),
-                              reuse_forward=True, out={"light_rad": self.grad[sl["rad"]].view(-1, 3)})
+                              reuse_forward=reuse, out={"light_rad": self.grad[sl["rad"]].view(-1, 3)})
         R.pose_backward(self.v_obj, self.param[sl["pose"]], g["verts"], self.g_vobj, self.grad[sl["pose"]])
         R.blend_backward(mt.basis_geo, self.g_vobj, self.grad[sl["geo"]])
         R.blend_backward(mt.basis_alb, g["diffuse"], self.grad[sl["alb"]])

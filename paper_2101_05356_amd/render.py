@@ -221,7 +221,7 @@ def _opts(brdf_variant=0, components=3, edge_samples=0, dbg=None, light_chunk=0,
 def render_forward(mesh: Mesh, sc: DeviceScene, brdf_variant=0, components=3, dump=False, verts=None, stats=None,
                    light_chunk=0, events=None, keep_shadows=False, workspace=None):
     """Image [H,W,3]; with dump=True also (hit [H*W,S], pflag [H*W,S], vis [H*W,S,L]).
-    `stats` (a uint64-sized int64 tensor [10], dump only) accumulates traversal counts.
+    `stats` (a uint64-sized int64 tensor [11], dump only) accumulates traversal counts.
     `events` (two torch.cuda.Event with timing) bracket the render kernel itself.
     `keep_shadows`: the workspace keeps the shadow decisions for a backward
     with reuse_forward.  `workspace`: a uint8 device tensor of at least
@@ -238,7 +238,7 @@ def render_forward(mesh: Mesh, sc: DeviceScene, brdf_variant=0, components=3, du
     o.keep_shadows = int(bool(keep_shadows))
     _set_ws(o, mesh, sc, workspace, light_chunk)
     if stats is not None:
-        assert dump and stats.dtype == torch.int64 and stats.numel() == 10
+        assert dump and stats.dtype == torch.int64 and stats.numel() == 11
         o.dbg_stats = stats.data_ptr()
     check(lib().fr_render_forward(mesh.h, ctypes.byref(s), ctypes.byref(o), _p(img), _stream()), mesh.ctx.h,
           "fr_render_forward")
@@ -436,6 +436,12 @@ def axpy(y, x, a=1.0, s=None):
     assert y.is_contiguous() and x.is_contiguous() and y.numel() == x.numel()
     check(lib().fr_axpy(_p(y), _p(x), float(a), _p(s), y.numel(), _stream()), None, "fr_axpy")
     return y
+
+
+def probe_valu(blocks, iters, out):
+    """The FMA-chain measurement probe (fr_probe_valu) into out [blocks*256]."""
+    assert out.dtype == torch.float32 and out.numel() >= blocks * 256
+    check(lib().fr_probe_valu(int(blocks), int(iters), _p(out), _stream()), None, "fr_probe_valu")
 
 
 def adam_step(param, grad, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
