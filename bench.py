@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recon-steps", type=int, default=150,
                     help="steps of a whole reconstruction timed from its start (0 = skip)")
+    ap.add_argument("--two-stage-steps", type=int, default=150,
+                    help="Stage I steps of the timed two-stage reconstruction (Stage II: a third of them; 0 = skip)")
     ap.add_argument("--recompute-steps", type=int, default=20,
                     help="steps whose adjoint traces its own decisions instead of taking the forward's (0 = skip)")
     ap.add_argument("--profile-only", action="store_true",
@@ -418,6 +420,48 @@ def shadow_edge_bench(ctx, n_samples, reps=20, warmup=3, seed=54):
                         f"lights; {n_samples} line samples (camera sample, light, line across it) per call"}
 
 
+def two_stage_bench(ctx, mt, W=256, spp=16, steps1=150, steps2=50, M=256, seed=61):
+    """The whole two-stage reconstruction of a synthetic 256 x 256 face
+    (Stage I: morphable model + 20-light icosahedron light stage; Stage II:
+    256^2 personalised maps started from the baked Stage I albedo), timed
+    from the first Stage I step to the last Stage II step; recovery errors
+    against the synthetic truth."""
+    import torch
+    from paper_2101_05356_amd import recon, scenes
+    from paper_2101_05356_amd import render as R
+    rng = np.random.default_rng(seed)
+    n = mt.K_geo + mt.K_alb + 6
+    truth = np.concatenate([rng.standard_normal(n - 6), np.radians(rng.uniform(-10, 10, 3)),
+                            rng.normal(0, 0.05, 3)]).astype(np.float32)
+    cam = scenes.face_camera(W, W)
+    faces = scenes.light_stage_faces("icosahedron")
+    stage_true = scenes.light_stage_params(faces.shape[0], d=3.0, a=0.05, seed=23)
+    ref = recon.Stage1(ctx, mt, torch.zeros((W, W, 3), device="cuda"), cam, spp, torch.tensor(truth).cuda(),
+                       stage_true, np.ones(mt.K_id), np.ones(mt.K_alb))
+    target = R.render_forward(ref.mesh, ref.scene(), verts=ref.v_w).contiguous()
+    alb_true = ref.diffuse.view(-1, 3).cpu().numpy()
+    start = np.zeros_like(truth)
+    start[n - 6:] = truth[n - 6:] + np.array([0.05, -0.05, 0.03, 0.02, -0.02, 0.01], np.float32)
+    stage0 = scenes.light_stage_params(faces.shape[0], d=3.0, a=0.05, seed=29)
+    uv = scenes.latlong_corner_uv(200, 140, mt.tris)
+    del ref
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = recon.two_stage(ctx, mt, target, cam, spp, torch.tensor(start).cuda(), uv, stage0=stage0, steps1=steps1,
+                          steps2=steps2, M=M, truth=(torch.tensor(truth).cuda(), alb_true))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    o1, o2 = out["objective1"], out["objective2"]
+    return {"seconds": dt, "steps_stage1": steps1, "steps_stage2": steps2, "ms_per_step": 1e3 * dt / (steps1 + steps2),
+            "objective1_first_last": [float(o1[0].item()), float(o1[-1].item())],
+            "objective2_first_last": [float(o2[0][0].item() + o2[0][1].item()),
+                                      float(o2[-1][0].item() + o2[-1][1].item())],
+            "vertex_rms_start": out["vertex_rms_start"], "vertex_rms_stage1": out["vertex_rms_stage1"],
+            "albedo_err_stage2_start": out["albedo_err_start"], "albedo_err_stage2_end": out["albedo_err_stage2"],
+            "workload": f"{W}x{W} synthetic face, {spp} spp, Stage I {steps1} steps (20-light icosahedron stage, "
+                        f"priors, edge samples W*H) then Stage II {steps2} steps on {M}^2 maps"}
+
+
 def render_step_bench(ctx, sc, steps, warmup, groups, edge_samples=-1, seed=51):
     """Refit + forward (keeping its decisions) + loss + backward (taking them)
     per step on one scene; the deformed vertex sets and the target are made
@@ -585,6 +629,10 @@ def main():
                         "loss_last": float(losses[-1].item()),
                         "workload": "the same face reconstruction timed from step 1 (no warm-up) to the last"}
         del rc2
+    if args.two_stage_steps > 0:
+        out["two_stage"] = two_stage_bench(ctx, mt, W=W, spp=S, steps1=args.two_stage_steps,
+                                           steps2=max(args.two_stage_steps // 3, 1))
+        print(json.dumps({"progress": "two_stage", **out["two_stage"]}), file=sys.stderr, flush=True)
     if args.batch_jobs > 0:
         out["batch"] = batch_bench(ctx, mt, args.batch_jobs, args.batch_steps, 2)
         print(json.dumps({"progress": "batch", **out["batch"]}), file=sys.stderr, flush=True)

@@ -412,6 +412,21 @@ int fr_light_stage(const float* d_faces, const float* d_params, int32_t n_lights
 int fr_light_stage_backward(const float* d_faces, const float* d_params, int32_t n_lights, const float* d_g_geom,
                             const float* d_g_rad, float* d_gparams, fr_stream stream);
 
+/* A per-vertex attribute written into an M x M texture map: the Stage II
+ * maps start from the Stage I statistical albedo read in texture space
+ * (Sec. 4 "Stage II").  d_tris [F*3] vertex ids and d_uv [F*3*2] per-corner
+ * texture coordinates (the layout of fr_scene.tex_uv), d_attr [N*channels]
+ * (channels 1..4), d_map [M*M*channels], texel (i, j) at j M + i.  Texel
+ * (i, j) with centre c = ((i + 1/2)/M, (j + 1/2)/M) inside the texture
+ * triangle of face f receives sum_k b_k attr[tris[f][k]] (b the barycentrics
+ * of c); a centre on an edge or vertex belongs to one face only (each edge
+ * function positive, or zero on a left or top edge of the counter-clockwise
+ * triangle, edges evaluated from their lexicographically lower end); texels
+ * that no face holds are left as they are.  FP64 arithmetic.  Device
+ * pointers. */
+int fr_bake_vertex_map(const int32_t* d_tris, const float* d_uv, int32_t n_tris, const float* d_attr, int32_t channels,
+                       int32_t M, float* d_map, fr_stream stream);
+
 /* d_y[i] += a * s * d_x[i], i < n, with s = d_s[0] (a device scalar, e.g. the
  * upstream gradient of a loss) or 1 when d_s is NULL: how an optimisation
  * step adds up the terms of its objective (Sec. 4 Eq. loss1, Eq. loss3) and

@@ -566,6 +566,64 @@ def light_stage_vjp(faces, params, g_geom, g_rad, h=1e-30):
 # difference (each pair twice); E_b(x) = min(x, 0)^2 + max(x - 1, 0)^2;
 # sign(0) = 0 in the gradients of the L1 terms.
 # ---------------------------------------------------------------------------
+def bake_map(tris, uv, attr, M, init=None):
+    """Per-vertex attribute attr [N, C] written into an M x M map [M, M, C]
+    in texture space: texel (i, j), centre c = ((i + 1/2) / M, (j + 1/2) / M),
+    takes sum_k b_k attr[tris[f, k]], b the barycentrics of c in the texture
+    triangle uv[f] [3, 2] of the face f that contains c.  A centre on an edge
+    or vertex belongs to one face only: it is inside when each edge function
+    (counter-clockwise order; each edge evaluated from its lexicographically
+    lower end so that its two faces get opposite values) is positive, or zero
+    on a left edge (going down) or a top edge (horizontal, going left).  Texels no face holds keep `init`
+    (zeros).  FP64 throughout, written from the definition: every face tests
+    every texel centre of its bounding box."""
+    tris = np.asarray(tris)
+    uv = np.asarray(uv, np.float64).reshape(-1, 3, 2)
+    attr = np.asarray(attr, np.float64)
+    C = attr.shape[1]
+    out = np.zeros((M, M, C)) if init is None else np.array(init, np.float64).reshape(M, M, C)
+    owner = np.full((M, M), -1)
+    for f in range(tris.shape[0]):
+        p = uv[f].copy()
+        idx = list(tris[f])
+        area = (p[1, 0] - p[0, 0]) * (p[2, 1] - p[0, 1]) - (p[1, 1] - p[0, 1]) * (p[2, 0] - p[0, 0])
+        if area == 0.0:
+            continue
+        if area < 0.0:
+            p = p[[0, 2, 1]]
+            idx = [idx[0], idx[2], idx[1]]
+            area = -area
+        lo = np.floor(p.min(0) * M - 0.5).astype(int)
+        hi = np.ceil(p.max(0) * M - 0.5).astype(int)
+        ii = np.arange(max(lo[0], 0), min(hi[0], M - 1) + 1)
+        jj = np.arange(max(lo[1], 0), min(hi[1], M - 1) + 1)
+        if ii.size == 0 or jj.size == 0:
+            continue
+        cu, cv = np.meshgrid((ii + 0.5) / M, (jj + 0.5) / M)
+        ins = np.ones(cu.shape, bool)
+        ws = []
+        for k in range(3):
+            a, b = p[k], p[(k + 1) % 3]
+            # evaluated from the lexicographically lower end, so that the two
+            # faces of an edge get exactly opposite values
+            flip = (b[0], b[1]) < (a[0], a[1])
+            lo_, hi_ = (b, a) if flip else (a, b)
+            e = (hi_[0] - lo_[0]) * (cv - lo_[1]) - (hi_[1] - lo_[1]) * (cu - lo_[0])
+            e = -e if flip else e
+            dx, dy = b[0] - a[0], b[1] - a[1]
+            top_left = dy < 0.0 or (dy == 0.0 and dx < 0.0)
+            ins &= (e > 0.0) | ((e == 0.0) & top_left)
+            ws.append(e)
+        # the edge function of edge k weighs the opposite corner (k + 2) % 3
+        bar = [ws[1] / area, ws[2] / area, ws[0] / area]
+        val = sum(bar[k][..., None] * attr[idx[k]][None, None, :] for k in range(3))
+        J, I = np.meshgrid(jj, ii, indexing="ij")
+        assert not np.any((owner[J, I] >= 0) & ins), "a texel centre inside two faces"
+        owner[J[ins], I[ins]] = f
+        out[J[ins], I[ins]] = val[ins]
+    return out, owner
+
+
 def _flip(X):
     return X[:, ::-1]
 

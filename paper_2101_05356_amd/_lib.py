@@ -117,6 +117,7 @@ SIGNATURES = {
     "fr_prior": ([P, P, _i32, _i32, ctypes.c_float, P, P, P], ctypes.c_int),
     "fr_landmark_loss": ([P, P, _i32, P, ctypes.c_float, _i32, _i32, P, P, P, P, P], ctypes.c_int),
     "fr_light_stage_backward": ([P, P, _i32, P, P, P, P], ctypes.c_int),
+    "fr_bake_vertex_map": ([P, P, _i32, P, _i32, _i32, P, P], ctypes.c_int),
     "fr_axpy": ([P, P, ctypes.c_float, P, _i32, P], ctypes.c_int),
     "fr_adam_step": ([P, P, P, P, P, _i32, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, P],
                      ctypes.c_int),

@@ -777,6 +777,14 @@ int fr_pose_backward(const float* d_v, int32_t n, const float* d_pose, const flo
   return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
 }
 
+int fr_bake_vertex_map(const int32_t* d_tris, const float* d_uv, int32_t n_tris, const float* d_attr, int32_t channels,
+                       int32_t M, float* d_map, fr_stream stream) {
+  if (!d_tris || !d_uv || !d_attr || !d_map || n_tris < 0 || channels < 1 || channels > 4 || M <= 0 || M > 16384)
+    return FR_ERR_INVALID_ARG;
+  fr::launch_bake_map(d_tris, d_uv, n_tris, d_attr, channels, M, d_map, reinterpret_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;
+}
+
 int fr_axpy(float* d_y, const float* d_x, float a, const float* d_s, int32_t n, fr_stream stream) {
   if (!d_y || !d_x || n < 0) return FR_ERR_INVALID_ARG;
   fr::launch_axpy(d_y, d_x, a, d_s, n, reinterpret_cast<hipStream_t>(stream));

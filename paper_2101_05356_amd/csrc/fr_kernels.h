@@ -228,6 +228,8 @@ void launch_light_stage(const float* faces, const float* P, int J, float* p0, fl
                         int32_t* shape, hipStream_t st);
 void launch_light_stage_backward(const float* faces, const float* P, int J, const float* gg, const float* gr,
                                  float* gP, hipStream_t st);
+void launch_bake_map(const int32_t* tris, const float* uv, int F, const float* attr, int C, int M, float* map,
+                     hipStream_t st);
 void launch_zero(float* p, int n, hipStream_t st);
 void launch_axpy(float* dst, const float* src, float a, const float* s, int n, hipStream_t st);   // dst += a s[0] src
 // render.hip

@@ -444,6 +444,75 @@ void launch_axpy(float* dst, const float* src, float a, const float* s, int n, h
 }
 
 // ---------------------------------------------------------------------------
+// Per-vertex attribute baked into an M x M texture map (the Stage II maps
+// start from the Stage I statistical albedo, Sec. 4 "Stage II"): one thread per
+// face tests the texel centres ((i + 1/2)/M, (j + 1/2)/M) of its texture
+// triangle's bounding box; a centre is the face's when every edge function
+// (counter-clockwise) is positive, or zero on a left or top edge, each edge
+// evaluated from its lexicographically lower end so that the two faces of an
+// edge get exactly opposite values.  Every texel has at most one owner, so the
+// writes never collide.  FP64 throughout.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bake_map(const int32_t* __restrict__ tris, const float* __restrict__ uv, int F,
+                                                  const float* __restrict__ attr, int C, int M,
+                                                  float* __restrict__ map) {
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  if (f >= F) return;
+  double px[3], py[3];
+  int vid[3];
+  for (int k = 0; k < 3; ++k) {
+    px[k] = uv[6 * f + 2 * k];
+    py[k] = uv[6 * f + 2 * k + 1];
+    vid[k] = tris[3 * f + k];
+  }
+  double area = (px[1] - px[0]) * (py[2] - py[0]) - (py[1] - py[0]) * (px[2] - px[0]);
+  if (area == 0.0) return;
+  if (area < 0.0) {
+    double t = px[1]; px[1] = px[2]; px[2] = t;
+    t = py[1]; py[1] = py[2]; py[2] = t;
+    const int v = vid[1]; vid[1] = vid[2]; vid[2] = v;
+    area = -area;
+  }
+  const double Md = (double)M;
+  const int i0 = max(0, (int)floor(fmin(px[0], fmin(px[1], px[2])) * Md - 0.5));
+  const int i1 = min(M - 1, (int)ceil(fmax(px[0], fmax(px[1], px[2])) * Md - 0.5));
+  const int j0 = max(0, (int)floor(fmin(py[0], fmin(py[1], py[2])) * Md - 0.5));
+  const int j1 = min(M - 1, (int)ceil(fmax(py[0], fmax(py[1], py[2])) * Md - 0.5));
+  for (int j = j0; j <= j1; ++j) {
+    const double cv = ((double)j + 0.5) / Md;
+    for (int i = i0; i <= i1; ++i) {
+      const double cu = ((double)i + 0.5) / Md;
+      double w[3];
+      bool in = true;
+      for (int k = 0; k < 3; ++k) {
+        const int k1 = k == 2 ? 0 : k + 1;
+        const double ax = px[k], ay = py[k], bx = px[k1], by = py[k1];
+        const bool flip = bx < ax || (bx == ax && by < ay);
+        const double lx = flip ? bx : ax, ly = flip ? by : ay, hx = flip ? ax : bx, hy = flip ? ay : by;
+        double e = (hx - lx) * (cv - ly) - (hy - ly) * (cu - lx);
+        if (flip) e = -e;
+        const double dx = bx - ax, dy = by - ay;
+        const bool top_left = dy < 0.0 || (dy == 0.0 && dx < 0.0);
+        in = in && (e > 0.0 || (e == 0.0 && top_left));
+        w[k] = e;
+      }
+      if (!in) continue;
+      // edge k's function weighs the opposite corner (k + 2) % 3
+      const double b0 = w[1] / area, b1 = w[2] / area, b2 = w[0] / area;
+      for (int c = 0; c < C; ++c)
+        map[((size_t)j * M + i) * C + c] = (float)(b0 * (double)attr[(size_t)vid[0] * C + c] +
+                                                   b1 * (double)attr[(size_t)vid[1] * C + c] +
+                                                   b2 * (double)attr[(size_t)vid[2] * C + c]);
+    }
+  }
+}
+
+void launch_bake_map(const int32_t* tris, const float* uv, int F, const float* attr, int C, int M, float* map,
+                     hipStream_t st) {
+  if (F > 0) hipLaunchKernelGGL(k_bake_map, dim3(cdiv(F, 256)), dim3(256), 0, st, tris, uv, F, attr, C, M, map);
+}
+
+// ---------------------------------------------------------------------------
 // Virtual light stage (Sec. 3.3, Eq. lightIntensity): light j on face
 // (V0, V1, V2) with (d, a, p1, p2, i).  With C the face's centroid,
 // scale = d / |C|, B = V0 + p1 (V1 - V0) + p2 (V2 - V0) and

@@ -194,12 +194,16 @@ class Stage1:
 
     def __init__(self, ctx: R.Context, mt: ModelTensors, target: torch.Tensor, camera: scenes.Camera, spp: int,
                  params0: torch.Tensor, stage0: np.ndarray, sigma_id: np.ndarray, sigma_alb: np.ndarray, seed: int = 4,
-                 edge_samples: int = -1, landmarks=None, w_land: float = 1.0, shadow_edge_samples: int = 0):
+                 edge_samples: int = -1, landmarks=None, w_land: float = 1.0, shadow_edge_samples: int = 0,
+                 layout: str = "icosahedron"):
         """landmarks: (vertex indices [68], film points [68, 2]) for the
         landmark term E_land (weight alpha_1 = 1, Sec. 5), or None.
         shadow_edge_samples > 0 adds the shadow-edge boundary term (line
         samples across the lights) to the vertex and light-geometry gradients,
-        so that the light stage also moves the lights by the shadows' edges."""
+        so that the light stage also moves the lights by the shadows' edges.
+        layout: the light stage's base shape (scenes.light_stage_faces:
+        tetrahedron, octahedron, icosahedron or sphere; one light per face,
+        stage0 [faces, 7])."""
         self.shadow_edge_samples = shadow_edge_samples
         dev = mt.mean_geo.device
         self.land = None if landmarks is None else (torch.as_tensor(np.asarray(landmarks[0], np.int32), device=dev),
@@ -208,7 +212,8 @@ class Stage1:
         self.camera = camera
         self.mt, self.target, self.edge_samples = mt, target, edge_samples
         self.sl = param_slices(mt.K_geo, mt.K_alb, 0)
-        self.faces = torch.tensor(scenes.icosahedron_faces(), device=dev)
+        self.faces = torch.tensor(scenes.light_stage_faces(layout), device=dev)
+        assert self.faces.shape[0] == np.asarray(stage0).shape[0], "one stage parameter row per face"
         self.x = params0[:self.sl["pose"].stop].clone()
         self.w = torch.tensor(np.asarray(stage0, np.float32), device=dev)
         lr = learning_rates(mt, 0)[:self.x.numel()]
@@ -333,6 +338,62 @@ class Stage2:
         for x, gr, m, v, lr in zip(self.maps, (gC, gS, gR), self.m, self.v, self.lr):
             R.adam_step(x, gr, m, v, lr, self.t)
         return E, Er
+
+
+def two_stage(ctx: R.Context, mt: ModelTensors, target: torch.Tensor, camera: scenes.Camera, spp: int,
+              params0: torch.Tensor, uv: np.ndarray, stage0=None, layout: str = "icosahedron", steps1: int = 150,
+              steps2: int = 50, M: int = 256, sigma_id=None, sigma_alb=None, edge_samples: int = -1,
+              shadow_edge_samples: int = 0, roughness0: float = 0.4, truth=None):
+    """The two-stage optimisation of Sec. 4 ("Optimization strategy"):
+    Stage I fits identity, expression, statistical albedo, pose and the
+    virtual light stage (`layout`) for `steps1` Adam steps (Sec. 5 rates);
+    then its albedo (the blend of the albedo basis at the Stage I
+    coefficients) and the model's specular are written into M x M texture
+    maps through the mesh's per-corner coordinates `uv` [F, 3, 2] (texels no
+    face holds start at 0.5), and Stage II fits the personalised diffuse,
+    specular and roughness maps (roughness uniform `roughness0` at the start)
+    for `steps2` steps under the map regularisers, geometry and lights fixed.
+    Every step runs in libfr.  `truth`: (true parameters, true per-vertex
+    albedo [N, 3]) for recovery errors.  Returns a dict: the two stages, their
+    objectives per step and, with `truth`, the world-space vertex RMS error of
+    the start and of Stage I's result and the albedo map error (mean |.|
+    over held texels) of Stage II's start and result."""
+    dev = mt.mean_geo.device
+    faces = scenes.light_stage_faces(layout)
+    stage0 = scenes.light_stage_params(faces.shape[0]) if stage0 is None else stage0
+    sig_id = np.ones(mt.K_id) if sigma_id is None else sigma_id
+    sig_alb = np.ones(mt.K_alb) if sigma_alb is None else sigma_alb
+    st1 = Stage1(ctx, mt, target, camera, spp, params0, stage0, sig_id, sig_alb, edge_samples=edge_samples,
+                 shadow_edge_samples=shadow_edge_samples, layout=layout)
+    out = {"stage1": st1}
+    v_true = None
+    if truth is not None:
+        ref = Stage1(ctx, mt, torch.zeros_like(target), camera, spp, truth[0], stage0, sig_id, sig_alb, layout=layout)
+        v_true = ref.v_w.view(-1, 3).clone()
+        out["vertex_rms_start"] = float(torch.sqrt(((st1.v_w.view(-1, 3) - v_true) ** 2).sum(1).mean()).item())
+    out["objective1"] = [st1.step() for _ in range(steps1)]
+    if v_true is not None:
+        out["vertex_rms_stage1"] = float(torch.sqrt(((st1.v_w.view(-1, 3) - v_true) ** 2).sum(1).mean()).item())
+    # Stage II: Stage I's albedo and the model's specular in texture space
+    tris = torch.as_tensor(np.ascontiguousarray(mt.tris, np.int32), device=dev)
+    uv_t = torch.as_tensor(np.ascontiguousarray(uv, np.float32).reshape(-1, 3, 2), device=dev)
+    C0 = R.bake_vertex_map(tris, uv_t, st1.diffuse.view(-1, 3), M, torch.full((M, M, 3), 0.5, device=dev))
+    S0 = R.bake_vertex_map(tris, uv_t, mt.specular.view(-1, 3).contiguous(), M,
+                           torch.full((M, M, 3), 0.5, device=dev))
+    sc1 = st1.scene()
+    sc2 = dataclasses.replace(sc1, uv=uv_t, tex_diffuse=C0, tex_specular=S0,
+                              tex_roughness=torch.full((M, M), roughness0, device=dev))
+    st2 = Stage2(st1.mesh, sc2, target, C0, S0, roughness0=roughness0)
+    out["stage2"] = st2
+    if truth is not None:
+        C_true = R.bake_vertex_map(tris, uv_t, torch.as_tensor(np.ascontiguousarray(truth[1], np.float32),
+                                                               device=dev), M, torch.full((M, M, 3), -1.0, device=dev))
+        held = C_true[..., 0] >= 0.0
+        out["albedo_err_start"] = float((st2.maps[0] - C_true).abs()[held].mean().item())
+    out["objective2"] = [st2.step() for _ in range(steps2)]
+    if truth is not None:
+        out["albedo_err_stage2"] = float((st2.maps[0] - C_true).abs()[held].mean().item())
+    return out
 
 
 def render_params(ctx, mt: ModelTensors, job: JobSpec, params: torch.Tensor) -> torch.Tensor:

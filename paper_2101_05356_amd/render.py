@@ -431,6 +431,17 @@ def pose_backward(v, pose, gw, gv=None, gpose=None):
     return gv, gpose
 
 
+def bake_vertex_map(tris, uv, attr, M, out):
+    """Per-vertex attr [N, C] into the texture map out [M, M, C] (texels no
+    face holds keep their value): fr_bake_vertex_map.  tris [F, 3] int32 and
+    uv [F, 3, 2] on the device."""
+    C = int(attr.shape[1])
+    assert out.is_contiguous() and out.numel() == M * M * C and attr.is_contiguous()
+    check(lib().fr_bake_vertex_map(_p(tris.contiguous()), _p(uv.contiguous()), int(tris.shape[0]), _p(attr), C, int(M),
+                                   _p(out), _stream()), None, "fr_bake_vertex_map")
+    return out
+
+
 def axpy(y, x, a=1.0, s=None):
     """y += a * s[0] * x on the device (s: a device scalar tensor, or None for 1)."""
     assert y.is_contiguous() and x.is_contiguous() and y.numel() == x.numel()

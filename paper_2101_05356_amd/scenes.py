@@ -432,6 +432,59 @@ def icosahedron_faces() -> np.ndarray:
     return _f32(np.array(faces))
 
 
+def _outward(faces):
+    """Order each face so that (v1 - v0) x (v2 - v0) points away from the origin."""
+    out = []
+    for f in faces:
+        f = [np.asarray(x, np.float64) for x in f]
+        if np.dot(np.cross(f[1] - f[0], f[2] - f[0]), f[0] + f[1] + f[2]) < 0:
+            f = [f[0], f[2], f[1]]
+        out.append(f)
+    return np.array(out)
+
+
+def _hull_faces(v):
+    """Triangular facets of the convex hull of a few points (every other
+    point strictly on the inner side of the facet's plane)."""
+    faces = []
+    n = len(v)
+    for i in range(n):
+        for j in range(i + 1, n):
+            for k in range(j + 1, n):
+                nrm = np.cross(v[j] - v[i], v[k] - v[i])
+                s = (v - v[i]) @ nrm
+                others = np.delete(s, [i, j, k])
+                if np.all(others < -1e-9) or np.all(others > 1e-9):
+                    faces.append([v[i], v[j], v[k]])
+    return _outward(faces)
+
+
+def light_stage_faces(layout: str = "icosahedron") -> np.ndarray:
+    """Base shapes of the virtual light stage (Sec. 3.3; the configurations
+    compared in the paper's light-stage ablation): one light per face of a
+    convex shape of unit circumradius centred at the origin, faces oriented
+    outwards.  "tetrahedron" (4 lights), "octahedron" (8), "icosahedron"
+    (20, the paper's choice), "sphere" (80: the icosahedron with every face
+    split in four at its edge midpoints, the new vertices pushed out to the
+    unit sphere; the paper says only "spherical ... eighty lights")."""
+    if layout == "icosahedron":
+        return icosahedron_faces()
+    if layout == "tetrahedron":
+        v = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], np.float64) / math.sqrt(3.0)
+        return _f32(_hull_faces(v))
+    if layout == "octahedron":
+        v = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], np.float64)
+        return _f32(_hull_faces(v))
+    if layout == "sphere":
+        out = []
+        for f in icosahedron_faces().astype(np.float64):
+            m = [(f[k] + f[(k + 1) % 3]) / 2.0 for k in range(3)]
+            m = [x / np.linalg.norm(x) for x in m]
+            out += [[f[0], m[0], m[2]], [m[0], f[1], m[1]], [m[2], m[1], f[2]], [m[0], m[1], m[2]]]
+        return _f32(_outward(out))
+    raise ValueError(f"unknown light-stage layout {layout!r}")
+
+
 def light_stage_params(n_faces: int = 20, d: float = 3.0, a: float = 0.05, seed: int = 19) -> np.ndarray:
     """Initial virtual-light-stage parameters [J, 7] = (d, a, p1, p2, i_rgb):
     every light at its face's centre (p = (1/3, 1/3)), distance d, relative

@@ -24,15 +24,19 @@ def setup(seed=31, W=32, spp=4):
     return recon, ctx, mt, cam, n
 
 
-def test_stage1_light_stage_gradient_matches_oracle(oracle_lib):
+@pytest.mark.parametrize("layout", ["icosahedron", "sphere", "tetrahedron", "octahedron"])
+def test_stage1_light_stage_gradient_matches_oracle(oracle_lib, layout):
+    """One light per face of each base shape of the light-stage ablation
+    (icosahedron 20, sphere 80, tetrahedron 4, octahedron 8)."""
     import oracle
     recon, ctx, mt, cam, n = setup()
     rng = np.random.default_rng(3)
     params0 = torch.tensor(np.concatenate([rng.normal(0, 0.5, n - 6), [0.05, -0.05, 0.03, 0.02, -0.02, 0.01]])
                            .astype(np.float32)).cuda()
-    stage0 = scenes.light_stage_params(d=3.0, a=0.05)
+    faces = scenes.light_stage_faces(layout)
+    stage0 = scenes.light_stage_params(faces.shape[0], d=3.0, a=0.05)
     target = torch.tensor(scenes.smooth_random_image(rng, 32, 32, 0.0, 0.4)).cuda()
-    st = recon.Stage1(ctx, mt, target, cam, 4, params0, stage0, np.ones(mt.K_id), np.ones(mt.K_alb))
+    st = recon.Stage1(ctx, mt, target, cam, 4, params0, stage0, np.ones(mt.K_id), np.ones(mt.K_alb), layout=layout)
     st.t = 1
     E, gx, gw = st.gradients()
     sc = st.scene()
@@ -49,8 +53,7 @@ def test_stage1_light_stage_gradient_matches_oracle(oracle_lib):
     _, dEdp = G.R.loss(img, target, smooth=True)
     go = oracle.grad(osc, mh, mv, G.to_np(dEdp).reshape(-1, 3).astype(np.float64))
     _, gp = oracle.prior(osc.lights.rad, oracle.PRIOR_LIGHT_CHROMA, 0.01)
-    want = oracle.light_stage_vjp(scenes.icosahedron_faces().astype(np.float64), stage0.astype(np.float64),
-                                  go["light"], go["rad"] + gp)
+    want = oracle.light_stage_vjp(faces.astype(np.float64), stage0.astype(np.float64), go["light"], go["rad"] + gp)
     ok, l2, el, _ = G.grad_tol_ok(G.to_np(gw), want)
     assert np.abs(want).sum() > 0 and ok, (l2, el)
 

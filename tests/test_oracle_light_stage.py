@@ -75,3 +75,37 @@ def test_complex_step_derivative_matches_central_differences(oracle_lib):
         e[j, k] = h
         fd = (F(P + e) - F(P - e)) / (2 * h)
         assert np.isclose(an[j, k], fd, rtol=1e-6, atol=1e-8), (j, k, an[j, k], fd)
+
+
+def _solid_angle(a, b, c):
+    """Solid angle of the spherical triangle a, b, c seen from the origin
+    (Van Oosterom and Strackee, 1983)."""
+    num = np.dot(a, np.cross(b, c))
+    la, lb, lc = np.linalg.norm(a), np.linalg.norm(b), np.linalg.norm(c)
+    den = la * lb * lc + np.dot(a, b) * lc + np.dot(a, c) * lb + np.dot(b, c) * la
+    return 2.0 * np.arctan2(num, den)
+
+
+@pytest.mark.parametrize("layout,n", [("tetrahedron", 4), ("octahedron", 8), ("icosahedron", 20), ("sphere", 80)])
+def test_light_stage_layouts(layout, n):
+    """The base shapes of the paper's light-stage ablation: the face count,
+    every vertex on the unit sphere, faces oriented outwards, a closed
+    two-manifold (each edge in exactly two faces, traversed both ways), and
+    the faces seen from the origin tile the sphere (solid angles sum to 4 pi,
+    none negative)."""
+    f = scenes.light_stage_faces(layout).astype(np.float64)
+    assert f.shape == (n, 3, 3)
+    assert np.allclose(np.linalg.norm(f, axis=-1), 1.0, atol=1e-6)
+    for tri in f:
+        assert np.dot(np.cross(tri[1] - tri[0], tri[2] - tri[0]), tri.sum(0)) > 0
+    key = lambda p: tuple(np.round(p, 5))
+    edges = {}
+    for tri in f:
+        for k in range(3):
+            e = (key(tri[k]), key(tri[(k + 1) % 3]))
+            edges[e] = edges.get(e, 0) + 1
+    assert all(c == 1 for c in edges.values()) and all((b, a) in edges for a, b in edges)
+    om = np.array([_solid_angle(*tri) for tri in f])
+    assert np.all(om > 0) and abs(om.sum() - 4 * np.pi) < 1e-5
+    if layout == "icosahedron":
+        assert np.array_equal(scenes.light_stage_faces(layout), scenes.icosahedron_faces())
