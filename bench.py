@@ -70,10 +70,23 @@ def parse():
                     help="only run 5 plain device-to-device copies of BYTES (counter calibration)")
     ap.add_argument("--batch-jobs", type=int, default=32, help="faces in the batched-step measurement (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
-    ap.add_argument("--serve-requests", type=int, default=8, help="requests in the serving measurement (0 = skip)")
-    ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-requests", type=int, default=16, help="requests per arrival rate in the serving "
+                                                                      "measurement (0 = skip)")
+    ap.add_argument("--serve-rates", type=str, default="2,20,200",
+                    help="Poisson arrival rates (requests/s), comma-separated")
     ap.add_argument("--serve-steps", type=int, default=150, help="Adam steps per request")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-work-cap", type=float, default=None,
+                    help="nominal rays per step admitted together (0 = no cap; default: the server's tuned value)")
+    ap.add_argument("--serve-extra-caps", type=str, default="",
+                    help="more batched runs at every rate, one per work cap (comma-separated)")
+    ap.add_argument("--serve-serial-rate", type=float, default=None,
+                    help="arrival rate of the measured serial run (default: the highest of --serve-rates)")
+    ap.add_argument("--serve-serial-check", type=float, default=None,
+                    help="also measure the serial server at this rate (checks the FIFO recursion)")
+    ap.add_argument("--serve-small-budget-gb", type=float, default=None,
+                    help="also run the batched server at the highest rate under this HBM budget")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving measurement")
     ap.add_argument("--large-steps", type=int, default=3,
                     help="steps of the 1024^2 textured render measurement (0 = skip)")
     ap.add_argument("--large-only", action="store_true", help="run only the large textured render measurement")
@@ -281,12 +294,12 @@ def batch_bench(ctx, mt, n_jobs, steps, warmup, seed=31):
             "workload": f"{n_jobs} faces, W from {{128..512}}, spp from {{4,8,16}}, 36..72 of 72 lights"}
 
 
-def serve_bench(ctx, mt, n_req, rate, n_steps, budget, seed=41):
-    """Poisson arrivals of reconstruction requests (resolution from
-    {128..512}^2, spp from {4, 8, 16, 32}, 72 lights, target rendered at 32
-    spp with its own seed), served with continuous batching and, as the
-    baseline, one at a time (one slot) with the same arrival times."""
-    from paper_2101_05356_amd import recon, serve
+
+
+def serve_requests(ctx, mt, n_req, n_steps, seed=41):
+    """Reconstruction requests: resolution from {128..512}^2, spp from
+    {4, 8, 16, 32}, 72 lights, target rendered at 32 spp with its own seed."""
+    from paper_2101_05356_amd import recon
     rng = np.random.default_rng(seed)
     reqs = []
     for i in range(n_req):
@@ -295,37 +308,143 @@ def serve_bench(ctx, mt, n_req, rate, n_steps, budget, seed=41):
         job, _ = recon.face_job(mt, np.random.default_rng(3000 + i), ctx, W=W, spp=spp, n_lights=72,
                                 seed=4000 + i, target_spp=32, target_seed=5000 + i, hist_cap=n_steps)
         reqs.append(job)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
-    arrivals -= arrivals[0]
-    model = recon.Model(ctx, mt)
+    return reqs
 
-    def run(max_slots):
-        srv = serve.Server(model, hbm_budget=budget, max_slots=max_slots, quantum=10)
-        try:
-            t0 = time.perf_counter()
-            ids = []
-            for a, job in zip(arrivals, reqs):
+
+def poisson_arrivals(n, rate, seed):
+    t = np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, n))
+    return t - t[0]
+
+
+def serve_run(model, reqs, arrivals, n_steps, budget, max_slots, work_cap, label, quantum=10):
+    """Submit `reqs` at `arrivals` (seconds from the start) to a server and
+    wait for all of them; prints a progress line every 30 s."""
+    from paper_2101_05356_amd import serve
+    srv = serve.Server(model, hbm_budget=budget, max_slots=max_slots, quantum=quantum, work_cap=work_cap)
+    last = [time.perf_counter()]
+
+    def progress(msg):
+        if time.perf_counter() - last[0] > 30.0:
+            print(json.dumps({"progress": "serving", "run": label, **msg}), file=sys.stderr, flush=True)
+            last[0] = time.perf_counter()
+    try:
+        t0 = time.perf_counter()
+        ids = []
+        for a, job in zip(arrivals, reqs):
+            while True:
                 wait = t0 + a - time.perf_counter()
-                if wait > 0:
-                    time.sleep(wait)
-                ids.append(srv.submit(job, n_steps))
-            if not srv.wait(1800.0):
-                raise RuntimeError("serving did not finish")
+                if wait <= 0:
+                    break
+                time.sleep(min(wait, 5.0))
+                progress({"submitted": len(ids)})
+            ids.append(srv.submit(job, n_steps))
+        deadline = time.perf_counter() + 3600.0
+        while not srv.wait(20.0):
             st = srv.stats()
-            res = [srv.poll(i, want_params=False) for i in ids]
-        finally:
-            srv.close()
-        return st, res
+            progress({"completed": st["completed"], "active": st["active"], "queued": st["queued"]})
+            if time.perf_counter() > deadline:
+                raise RuntimeError("serving did not finish")
+        st = srv.stats()
+        res = [srv.poll(i, want_params=False) for i in ids]
+    finally:
+        srv.close()
+    return st, res
 
-    st_b, res_b = run(max_slots=64)
-    st_s, res_s = run(max_slots=1)
-    rel = max(abs(a["final_loss"] - b["final_loss"]) / abs(b["final_loss"]) for a, b in zip(res_b, res_s))
-    pick = lambda st: {k: st[k] for k in ("recons_per_s", "p50_s", "p99_s", "mean_s", "peak_active", "completed",
-                                           "failed", "busy_s")}
-    return {"requests": n_req, "rate_per_s": rate, "steps_per_request": n_steps, "hbm_budget_gb": budget / 2**30,
-            "batched": pick(st_b), "serial": pick(st_s), "final_loss_max_rel_diff_vs_serial": rel,
-            "offered_load_over_serial_capacity": rate / max(st_s["recons_per_s"], 1e-9),
-            "workload": "C2 faces, W from {128..512}, spp from {4,8,16,32}, 72 lights, Adam with the Sec. 5 rates"}
+
+def serving_from_args(ctx, mt, args):
+    floats = lambda t: [float(x) for x in t.split(",") if x.strip()]
+    from paper_2101_05356_amd import serve
+    cap = serve.Server.DEFAULT_WORK_CAP if args.serve_work_cap is None else args.serve_work_cap
+    small = None if args.serve_small_budget_gb is None else int(args.serve_small_budget_gb * 2**30)
+    return serve_sweep(ctx, mt, args.serve_requests, floats(args.serve_rates), args.serve_steps,
+                       int(args.serve_budget_gb * 2**30), cap, serial_check_rate=args.serve_serial_check,
+                       small_budget=small, caps=floats(args.serve_extra_caps), serial_rate=args.serve_serial_rate)
+
+
+def fifo_latencies(arrivals, service):
+    """One-at-a-time FIFO service: request i starts when it has arrived and
+    request i-1 is done, and takes service[i]."""
+    done, lat = 0.0, []
+    for a, s in zip(arrivals, service):
+        done = max(done, a) + s
+        lat.append(done - a)
+    return np.asarray(lat)
+
+
+def nearest_rank(v, q):
+    v = np.sort(np.asarray(v))
+    return float(v[min(max(int(math.ceil(q * len(v))), 1), len(v)) - 1])
+
+
+def serve_sweep(ctx, mt, n_req, rates, n_steps, budget, work_cap, serial_check_rate=None, small_budget=None,
+                caps=None, serial_rate=None, seed=41):
+    """Poisson arrivals of reconstruction requests at each rate in `rates`,
+    served by the continuous-batching server (work cap `work_cap`, HBM budget
+    `budget`).  The serial baseline (one slot) is measured at `serial_rate`
+    (default: the highest rate, where the queue never empties), which gives
+    each request's service time (its completion minus the later of its
+    arrival and the previous completion); the serial latencies at the
+    other rates follow from those service times by the FIFO recursion, and
+    one more serial run at `serial_check_rate` measures how far that
+    recursion is from a real serial server.  `small_budget`: one more batched
+    run at the highest rate under that HBM budget.  `caps`: more batched runs
+    at every rate, one per work cap."""
+    from paper_2101_05356_amd import recon
+    reqs = serve_requests(ctx, mt, n_req, n_steps, seed)
+    model = recon.Model(ctx, mt)
+    work = np.array([j.W * j.H * j.spp * (1 + j.L) for j in reqs], np.float64)
+    keys = ("recons_per_s", "p50_s", "p99_s", "mean_s", "peak_active", "completed", "failed", "busy_s")
+    pick = lambda st: {k: st[k] for k in keys}
+    rmax = max(rates)
+    arr_max = poisson_arrivals(n_req, rmax, seed)
+    rser = rmax if serial_rate is None else serial_rate
+    st_s, res_s = serve_run(model, reqs, poisson_arrivals(n_req, rser, seed), n_steps, budget, 1, 0.0, "serial")
+    done = np.array([r["t_done"] for r in res_s])
+    sub = np.array([r["t_submit"] for r in res_s])
+    order = np.argsort(done)
+    service = np.empty(n_req)
+    prev = None
+    for i in order:
+        service[i] = done[i] - (sub[i] if prev is None else max(prev, sub[i]))
+        prev = done[i]
+    serial_cap = n_req / service.sum()
+    out = {"requests": n_req, "steps_per_request": n_steps, "hbm_budget_gb": budget / 2**30, "work_cap": work_cap,
+           "serial_capacity_recons_per_s": serial_cap, "serial_measured_at_rate": rser,
+           "mean_work_rays_per_step": float(work.mean()),
+           "workload": "C2 faces, W from {128..512}, spp from {4,8,16,32}, 72 lights, 150 Adam steps each",
+           "sweep": []}
+    losses_serial = {i: r["final_loss"] for i, r in enumerate(res_s)}
+    for rate in sorted(rates):
+        arr = arr_max if rate == rmax else poisson_arrivals(n_req, rate, seed)
+        row = {"rate_per_s": rate, "offered_load_over_serial_capacity": rate / serial_cap}
+        for cap in ([work_cap] + list(caps or [])):
+            st_b, res_b = serve_run(model, reqs, arr, n_steps, budget, 64, cap, f"batched@{rate}")
+            rel = max(abs(a["final_loss"] - losses_serial[i]) / abs(losses_serial[i]) for i, a in enumerate(res_b))
+            b = pick(st_b)
+            b["final_loss_max_rel_diff_vs_serial"] = rel
+            row["batched" if cap == work_cap else f"batched_cap_{cap:g}"] = b
+        if rate == rser:
+            row["serial"] = dict(pick(st_s), kind="measured")
+        else:
+            lat = fifo_latencies(arr, service)
+            row["serial"] = {"recons_per_s": n_req / (float(np.max(arr + lat)) - arr[0]),
+                             "p50_s": nearest_rank(lat, 0.5), "p99_s": nearest_rank(lat, 0.99),
+                             "mean_s": float(lat.mean()), "kind": "FIFO recursion on the measured service times"}
+        out["sweep"].append(row)
+        print(json.dumps({"progress": "serving", "rate": rate, "batched_p50": row["batched"]["p50_s"],
+                          "serial_p50": row["serial"]["p50_s"]}), file=sys.stderr, flush=True)
+    if serial_check_rate is not None:
+        arr = poisson_arrivals(n_req, serial_check_rate, seed)
+        st_c, _ = serve_run(model, reqs, arr, n_steps, budget, 1, 0.0, f"serial@{serial_check_rate}")
+        lat = fifo_latencies(arr, service)
+        out["serial_check"] = {"rate_per_s": serial_check_rate, "measured": pick(st_c),
+                               "recursion": {"p50_s": nearest_rank(lat, 0.5), "p99_s": nearest_rank(lat, 0.99),
+                                             "mean_s": float(lat.mean())}}
+    if small_budget is not None:
+        st_g, _ = serve_run(model, reqs, arr_max, n_steps, small_budget, 64, work_cap, "small_budget")
+        out["small_budget"] = {"hbm_budget_gb": small_budget / 2**30, "rate_per_s": rmax, **pick(st_g),
+                               "peak_bytes_gb": st_g["peak_bytes"] / 2**30}
+    return out
 
 
 def large_bench(ctx, steps, warmup, edge_samples=-1, seed=51):
@@ -541,6 +660,11 @@ def main():
     if args.shadow_edge_only:
         print(json.dumps({"shadow_edges": shadow_edge_bench(ctx, max(args.shadow_edge_samples, 1))}), flush=True)
         return
+    if args.serving_only:
+        from paper_2101_05356_amd import recon, scenes
+        mt = recon.ModelTensors.from_model(scenes.synthetic_morph_model(seed=11))
+        print(json.dumps({"serving": serving_from_args(ctx, mt, args)}), flush=True)
+        return
     mt, rc = make_c2(ctx, W, S, L, args.edge_samples)
     settle_clocks(rc, 0.3)
     for _ in range(args.warmup):
@@ -637,9 +761,8 @@ def main():
         out["batch"] = batch_bench(ctx, mt, args.batch_jobs, args.batch_steps, 2)
         print(json.dumps({"progress": "batch", **out["batch"]}), file=sys.stderr, flush=True)
     if args.serve_requests > 0:
-        out["serving"] = serve_bench(ctx, mt, args.serve_requests, args.serve_rate, args.serve_steps,
-                                     int(args.serve_budget_gb * 2**30))
-        print(json.dumps({"progress": "serving"}), file=sys.stderr, flush=True)
+        out["serving"] = serving_from_args(ctx, mt, args)
+        print(json.dumps({"progress": "serving done"}), file=sys.stderr, flush=True)
     if args.large_steps > 0 and not args.profile_only:
         out["large"] = large_bench(ctx, args.large_steps, 1)
         print(json.dumps({"progress": "large", **out["large"]}), file=sys.stderr, flush=True)

@@ -512,8 +512,8 @@ int32_t fr_batch_losses(fr_batch* batch, int32_t cap, int32_t* h_ids, float* h_l
  * Serving.  A server owns a worker thread, a HIP stream and a batch on the
  * model's device, and runs submitted reconstructions with continuous
  * batching: between optimisation steps it admits queued requests in arrival
- * order while a slot is free and the request's device bytes (fr_job_bytes)
- * fit the HBM budget, steps all admitted requests together, fails a request
+ * order while a slot is free, the request's device bytes (fr_job_bytes)
+ * fit the HBM budget and its rays per step fit the work cap, steps all admitted requests together, fails a request
  * whose loss turns non-finite (FR_ERR_NONFINITE), and retires the ones that
  * reached their step count.  A request is never split or preempted; a request
  * that does not fit the remaining budget blocks those behind it (strict FIFO).
@@ -527,6 +527,10 @@ typedef struct {
   int32_t quantum;       /* steps per scheduling round at most (bounds admission delay) */
   int32_t use_graph;     /* 1: replay each round's step from a hipGraph */
   int32_t pad_;
+  double work_cap;       /* nominal rays per step (width*height*spp*(1+lights), summed over
+                            the admitted requests) admitted together at most; <= 0: no cap.
+                            The request at the head of the queue is admitted whenever
+                            nothing runs, whatever its work. */
 } fr_server_opts;
 
 typedef struct {

@@ -25,7 +25,10 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB: load another build of oracle.cpp (e.g. one built with the
+# address and undefined-behaviour sanitizers); build() leaves it alone.
+_SO_DEFAULT = os.path.join(_HERE, "liboracle.so")
+_SO = os.environ.get("ORACLE_LIB", _SO_DEFAULT)
 _SRC = os.path.join(_HERE, "oracle.cpp")
 
 VIS_OCCLUDED, VIS_VISIBLE, VIS_CULLED, VIS_NONE = 0, 1, 2, 3
@@ -36,6 +39,8 @@ NO_FORCE_VIS = 0xFF
 
 def build(force: bool = False) -> str:
     """Compile liboracle.so with g++ (FP64, no FMA contraction)."""
+    if _SO != _SO_DEFAULT:
+        return _SO
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", "-pthread",
                _SRC, "-o", _SO + ".tmp"]

@@ -62,7 +62,7 @@ class FrJobDesc(ctypes.Structure):
 
 class FrServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("quantum", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("pad_", ctypes.c_int32), ("work_cap", ctypes.c_double)]
 
 
 class FrRequest(ctypes.Structure):

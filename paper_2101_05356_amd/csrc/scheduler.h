@@ -3,9 +3,15 @@
 // Requests (one face reconstruction each: a target image, initial
 // parameters, a number of Adam steps) arrive at any time.  Between steps the
 // scheduler
-//   1. admits queued requests in arrival order while a slot is free and the
-//      request's device bytes fit the remaining HBM budget (strict FIFO: a
-//      request that does not fit blocks the ones behind it, so none starves);
+//   1. admits queued requests in arrival order while a slot is free, the
+//      request's device bytes fit the remaining HBM budget and its work per
+//      step (nominal rays) fits the remaining work cap (strict FIFO: a
+//      request that does not fit blocks the ones behind it, so none starves;
+//      the head request is always admitted when nothing runs, whatever its
+//      work).  The work cap keeps a round near the size that already fills
+//      the device: past it, stepping more requests together only slows every
+//      one of them down (processor sharing) without raising the rate at
+//      which requests complete;
 //   2. advances every active request by k steps in one batched call, with k
 //      the smallest number of steps any active request still needs (capped by
 //      a quantum, so new arrivals wait at most `quantum` steps);
@@ -18,6 +24,7 @@
 // Exec must provide:
 //   using Req = ...;                         request payload (movable)
 //   size_t bytes(const Req&);                device bytes one active request holds
+//   double work(const Req&);                 work of one step of the request (any unit)
 //   int add(Req&, int32_t* handle);          FR_OK or an error code
 //   int remove(int32_t handle);
 //   int step(int n);                         advance every active request n steps
@@ -69,14 +76,17 @@ class Scheduler {
     int steps_total = 0, steps_done = 0;
     int32_t handle = -1;
     size_t bytes = 0;
+    double work = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
     float final_loss = NAN;
     bool cancel = false;
     std::vector<float> params, losses;
   };
 
-  Scheduler(Exec& ex, size_t budget, int max_slots, int quantum)
-      : ex_(ex), budget_(budget), max_slots_(std::max(max_slots, 1)), quantum_(std::max(quantum, 1)) {}
+  // work_cap <= 0: no cap.
+  Scheduler(Exec& ex, size_t budget, int max_slots, int quantum, double work_cap = 0.0)
+      : ex_(ex), budget_(budget), max_slots_(std::max(max_slots, 1)), quantum_(std::max(quantum, 1)),
+        work_cap_(work_cap > 0.0 ? work_cap : 0.0) {}
 
   // Queue request `id` (unique, chosen by the caller; t_submit: arrival time
   // on the executor's clock).
@@ -88,6 +98,7 @@ class Scheduler {
     e.id = nid;
     e.steps_total = n_steps;
     e.bytes = b;
+    e.work = ex_.work(r);
     e.t_submit = t_submit;
     ++stats_.submitted;
     if (b == 0 || b > budget_) {   // could never be admitted
@@ -137,6 +148,7 @@ class Scheduler {
     while (!queue_.empty() && (int)active_.size() < max_slots_) {
       Entry& e = all_[queue_.front()];
       if (used_ + e.bytes > budget_) break;
+      if (work_cap_ > 0.0 && !active_.empty() && work_ + e.work > work_cap_) break;
       queue_.pop_front();
       int32_t h = -1;
       const int rc = ex_.add(e.req, &h);
@@ -150,11 +162,13 @@ class Scheduler {
       e.state = REQ_RUNNING;
       e.t_admit = ex_.now();
       used_ += e.bytes;
+      work_ += e.work;
       active_.push_back(e.id);
       changed.push_back(e.id);
     }
     stats_.peak_active = std::max<int32_t>(stats_.peak_active, (int32_t)active_.size());
     stats_.peak_bytes = std::max(stats_.peak_bytes, used_);
+    peak_work_ = std::max(peak_work_, work_);
     if (active_.empty()) return changed;
     // advance
     int k = quantum_;
@@ -200,6 +214,21 @@ class Scheduler {
     return changed;
   }
 
+  // Remove every active request from the executor and drop the queue (on
+  // shutdown; the requests end cancelled).
+  void drop_all() {
+    while (!active_.empty()) {
+      Entry& e = all_[active_.back()];
+      release(active_.size() - 1);
+      finish(e, REQ_CANCELLED, SCHED_OK);
+    }
+    for (uint64_t id : queue_) finish(all_[id], REQ_CANCELLED, SCHED_OK);
+    queue_.clear();
+  }
+
+  // Largest work admitted together so far.
+  double peak_work() const { return peak_work_; }
+
   const Entry* find(uint64_t id) const {
     auto it = all_.find(id);
     return it == all_.end() ? nullptr : &it->second;
@@ -235,6 +264,7 @@ class Scheduler {
     Entry& e = all_[active_[i]];
     ex_.remove(e.handle);
     used_ -= e.bytes;
+    work_ = active_.size() > 1 ? std::max(0.0, work_ - e.work) : 0.0;
     active_.erase(active_.begin() + (long)i);
   }
 
@@ -255,7 +285,9 @@ class Scheduler {
   Exec& ex_;
   size_t budget_;
   int max_slots_, quantum_;
+  double work_cap_;
   size_t used_ = 0;
+  double work_ = 0, peak_work_ = 0;
   std::deque<uint64_t> queue_;
   std::vector<uint64_t> active_;
   std::map<uint64_t, Entry> all_;

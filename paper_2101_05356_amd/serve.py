@@ -25,11 +25,20 @@ def _host(a, dtype=np.float32):
 
 
 class Server:
-    def __init__(self, model: Model, hbm_budget: int, max_slots: int = 32, quantum: int = 10, use_graph=True):
+    # Work cap measured on the face workload mix (128^2..512^2, 4..32 spp, 72
+    # lights): past ~8e8 nominal rays per step, stepping more requests
+    # together raises the completion rate little and delays every request.
+    DEFAULT_WORK_CAP = 8.0e8
+
+    def __init__(self, model: Model, hbm_budget: int, max_slots: int = 32, quantum: int = 10, use_graph=True,
+                 work_cap: float = DEFAULT_WORK_CAP):
+        """work_cap: nominal rays per step (W*H*spp*(1+lights) summed over the
+        requests stepped together) admitted at most; 0 = no cap."""
         self.model = model
         o = FrServerOpts()
         o.hbm_budget, o.max_slots, o.quantum, o.use_graph = int(hbm_budget), int(max_slots), int(quantum), \
             int(bool(use_graph))
+        o.work_cap = float(work_cap)
         h = ctypes.c_void_p()
         check(lib().fr_server_create(model.h, ctypes.byref(o), ctypes.byref(h)), model.ctx.h, "fr_server_create")
         self.h = h

@@ -18,6 +18,7 @@ struct SimExec {
     int nan_at = -1;     // loss turns NaN once this many steps are done
     int fail_add = 0;    // add() fails with this code
     int tag = 0;
+    double work = 0.0;   // work per step, checked against the work cap
   };
   struct Job {
     Req r;
@@ -26,8 +27,16 @@ struct SimExec {
   std::map<int32_t, Job> jobs;
   int32_t next = 1;
   double clock = 0.0, overhead = 0.001;
+  double floor = 0.0;   // a step costs at least this much (a device that is not yet full)
   int max_active = 0;
+  double max_work = 0.0;   // largest summed work stepped together
   size_t bytes(const Req& r) { return r.bytes; }
+  double work(const Req& r) { return r.work; }
+  double active_work() const {
+    double w = 0;
+    for (auto& kv : jobs) w += kv.second.r.work;
+    return w;
+  }
   int add(Req& r, int32_t* h) {
     if (r.fail_add) return r.fail_add;
     *h = next++;
@@ -37,9 +46,10 @@ struct SimExec {
   }
   int remove(int32_t h) { return jobs.erase(h) ? 0 : 8; }
   int step(int n) {
-    double c = overhead;
+    max_work = std::max(max_work, active_work());
+    double c = 0.0;
     for (auto& kv : jobs) { c += kv.second.r.cost; kv.second.t += n; }
-    clock += n * c;
+    clock += n * (overhead + std::max(c, floor));
     return 0;
   }
   int last_losses(std::vector<std::pair<int32_t, float>>& out) {
@@ -70,7 +80,7 @@ struct Run {
   fr::Scheduler<SimExec> s;
   std::map<uint64_t, int> submit_rc;
   std::vector<uint64_t> done_order;
-  Run(size_t budget, int slots, int quantum) : s(ex, budget, slots, quantum) {}
+  Run(size_t budget, int slots, int quantum, double work_cap = 0.0) : s(ex, budget, slots, quantum, work_cap) {}
 
   // Feed arrivals in time order; between arrivals run scheduling rounds.
   void drive(std::vector<Arrival> arr, const std::map<int, std::vector<uint64_t>>& cancel_at_tick = {}) {
@@ -97,7 +107,8 @@ struct Run {
   }
 
   void print(const char* name) {
-    printf("{\"scenario\": \"%s\", \"max_active\": %d, \"reqs\": {", name, ex.max_active);
+    printf("{\"scenario\": \"%s\", \"max_active\": %d, \"max_work\": %.6f, \"peak_work\": %.6f, \"reqs\": {", name,
+           ex.max_active, ex.max_work, s.peak_work());
     bool first = true;
     for (auto& kv : submit_rc) {
       const auto* e = s.find(kv.first);
@@ -119,9 +130,9 @@ struct Run {
   }
 };
 
-static SimExec::Req req(size_t bytes, double cost = 0.01, int nan_at = -1, int fail_add = 0) {
+static SimExec::Req req(size_t bytes, double cost = 0.01, int nan_at = -1, int fail_add = 0, double work = 0.0) {
   SimExec::Req r;
-  r.bytes = bytes; r.cost = cost; r.nan_at = nan_at; r.fail_add = fail_add;
+  r.bytes = bytes; r.cost = cost; r.nan_at = nan_at; r.fail_add = fail_add; r.work = work;
   return r;
 }
 
@@ -173,6 +184,24 @@ int main(int argc, char** argv) {
     Run r(1000, 4, 3);
     r.drive({{0.0, req(1), 6, 1}, {10.0, req(1), 6, 2}, {10.0, req(1), 3, 3}, {30.0, req(1), 1, 4}});
     r.print("arrivals");
+  } else if (sc == "work_cap") {     // the work cap bounds what is stepped together, in FIFO order
+    Run r(1000, 8, 4, 10.0);
+    // works 4, 4, 4, 12 (above the cap: runs alone), 1, 1
+    const double w[6] = {4, 4, 4, 12, 1, 1};
+    std::vector<Arrival> a;
+    for (int i = 1; i <= 6; ++i) a.push_back({0.0, req(1, 0.01, -1, 0, w[i - 1]), 4 + i, (uint64_t)i});
+    r.drive(a);
+    r.print("work_cap");
+  } else if (sc == "cap_latency_uncapped" || sc == "cap_latency_capped") {
+    // batch arrival of eight equal requests on a device that one request
+    // keeps half busy: a step of k requests costs max(2, k) * 0.05
+    Run r(1000, 16, 10, sc == "cap_latency_capped" ? 2.0 : 0.0);
+    r.ex.overhead = 0.0;
+    r.ex.floor = 0.1;
+    std::vector<Arrival> a;
+    for (int i = 1; i <= 8; ++i) a.push_back({0.0, req(1, 0.05, -1, 0, 1.0), 20, (uint64_t)i});
+    r.drive(a);
+    r.print(sc.c_str());
   } else {
     fprintf(stderr, "unknown scenario\n");
     return 2;

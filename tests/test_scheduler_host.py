@@ -104,3 +104,26 @@ def test_idle_gaps_between_arrivals(sim):
     for i, r in d["reqs"].items():
         assert r["state"] == DONE and r["t_admit"] == pytest.approx(r["t_submit"])
     assert d["reqs"][4]["t_done"] - d["reqs"][4]["t_submit"] < 0.1
+
+
+def test_work_cap_bounds_the_work_stepped_together(sim):
+    d = sim("work_cap")          # works 4, 4, 4, 12, 1, 1 under a cap of 10
+    assert d["max_work"] == 12 and d["peak_work"] == 12   # the over-cap request ran alone
+    assert all(r["state"] == DONE and r["steps_done"] == 4 + i for i, r in d["reqs"].items())
+    admits = [d["reqs"][i]["t_admit"] for i in range(1, 7)]
+    assert admits == sorted(admits)                          # FIFO
+    # 1 and 2 together (8), 3 waits for a free share, 4 waits until it is alone
+    assert d["reqs"][3]["t_admit"] > 0.0
+    assert d["reqs"][4]["t_admit"] >= max(d["reqs"][i]["t_done"] for i in (1, 2, 3))
+    assert d["reqs"][5]["t_admit"] >= d["reqs"][4]["t_done"]
+
+
+def test_work_cap_lowers_latency_at_equal_throughput(sim):
+    """Stepping past the point where the device is full only shares it: under
+    a batch arrival the capped server completes requests in FIFO waves, with
+    half the median latency and the same completion rate."""
+    u, c = sim("cap_latency_uncapped"), sim("cap_latency_capped")
+    assert u["max_active"] == 8 and c["max_active"] == 2
+    assert u["stats"]["p50"] == pytest.approx(8.0) and c["stats"]["p50"] == pytest.approx(4.0)
+    assert c["stats"]["recons_per_s"] == pytest.approx(u["stats"]["recons_per_s"])
+    assert c["done_order"] == [1, 2, 3, 4, 5, 6, 7, 8]
