@@ -85,7 +85,11 @@ def parse():
     ap.add_argument("--serve-serial-check", type=float, default=None,
                     help="also measure the serial server at this rate (checks the FIFO recursion)")
     ap.add_argument("--serve-small-budget-gb", type=float, default=None,
-                    help="also run the batched server at the highest rate under this HBM budget")
+                    help="also run the batched server under this HBM budget")
+    ap.add_argument("--serve-small-budget-rate", type=float, default=200.0,
+                    help="arrival rate of the small-budget run")
+    ap.add_argument("--serve-small-budget-work-cap", type=float, default=None,
+                    help="work cap of the small-budget run (default: the sweep's)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving measurement")
     ap.add_argument("--large-steps", type=int, default=3,
                     help="steps of the 1024^2 textured render measurement (0 = skip)")
@@ -298,7 +302,12 @@ def batch_bench(ctx, mt, n_jobs, steps, warmup, seed=31):
 
 def serve_requests(ctx, mt, n_req, n_steps, seed=41):
     """Reconstruction requests: resolution from {128..512}^2, spp from
-    {4, 8, 16, 32}, 72 lights, target rendered at 32 spp with its own seed."""
+    {4, 8, 16, 32}, 72 lights, target rendered at 32 spp with its own seed.
+    The target, start point and rates are returned as host arrays, so that a
+    submission touches no device memory (a copy out of a device tensor would
+    wait behind the server's queued steps)."""
+    import dataclasses
+
     from paper_2101_05356_amd import recon
     rng = np.random.default_rng(seed)
     reqs = []
@@ -307,7 +316,8 @@ def serve_requests(ctx, mt, n_req, n_steps, seed=41):
         spp = int(rng.choice([4, 8, 16, 32]))
         job, _ = recon.face_job(mt, np.random.default_rng(3000 + i), ctx, W=W, spp=spp, n_lights=72,
                                 seed=4000 + i, target_spp=32, target_seed=5000 + i, hist_cap=n_steps)
-        reqs.append(job)
+        reqs.append(dataclasses.replace(job, target=job.target.cpu().numpy(), params=job.params.cpu().numpy(),
+                                        lr=job.lr.cpu().numpy()))
     return reqs
 
 
@@ -329,7 +339,7 @@ def serve_run(model, reqs, arrivals, n_steps, budget, max_slots, work_cap, label
             last[0] = time.perf_counter()
     try:
         t0 = time.perf_counter()
-        ids = []
+        ids, late = [], []
         for a, job in zip(arrivals, reqs):
             while True:
                 wait = t0 + a - time.perf_counter()
@@ -337,6 +347,7 @@ def serve_run(model, reqs, arrivals, n_steps, budget, max_slots, work_cap, label
                     break
                 time.sleep(min(wait, 5.0))
                 progress({"submitted": len(ids)})
+            late.append(time.perf_counter() - (t0 + a))   # submission behind its arrival time
             ids.append(srv.submit(job, n_steps))
         deadline = time.perf_counter() + 3600.0
         while not srv.wait(20.0):
@@ -345,6 +356,7 @@ def serve_run(model, reqs, arrivals, n_steps, budget, max_slots, work_cap, label
             if time.perf_counter() > deadline:
                 raise RuntimeError("serving did not finish")
         st = srv.stats()
+        st["submit_late_max_s"] = float(max(late))
         res = [srv.poll(i, want_params=False) for i in ids]
     finally:
         srv.close()
@@ -358,7 +370,9 @@ def serving_from_args(ctx, mt, args):
     small = None if args.serve_small_budget_gb is None else int(args.serve_small_budget_gb * 2**30)
     return serve_sweep(ctx, mt, args.serve_requests, floats(args.serve_rates), args.serve_steps,
                        int(args.serve_budget_gb * 2**30), cap, serial_check_rate=args.serve_serial_check,
-                       small_budget=small, caps=floats(args.serve_extra_caps), serial_rate=args.serve_serial_rate)
+                       small_budget=small, caps=floats(args.serve_extra_caps), serial_rate=args.serve_serial_rate,
+                       small_budget_cap=args.serve_small_budget_work_cap,
+                       small_budget_rate=args.serve_small_budget_rate)
 
 
 def fifo_latencies(arrivals, service):
@@ -377,7 +391,7 @@ def nearest_rank(v, q):
 
 
 def serve_sweep(ctx, mt, n_req, rates, n_steps, budget, work_cap, serial_check_rate=None, small_budget=None,
-                caps=None, serial_rate=None, seed=41):
+                caps=None, serial_rate=None, small_budget_cap=None, small_budget_rate=200.0, seed=41):
     """Poisson arrivals of reconstruction requests at each rate in `rates`,
     served by the continuous-batching server (work cap `work_cap`, HBM budget
     `budget`).  The serial baseline (one slot) is measured at `serial_rate`
@@ -387,13 +401,14 @@ def serve_sweep(ctx, mt, n_req, rates, n_steps, budget, work_cap, serial_check_r
     other rates follow from those service times by the FIFO recursion, and
     one more serial run at `serial_check_rate` measures how far that
     recursion is from a real serial server.  `small_budget`: one more batched
-    run at the highest rate under that HBM budget.  `caps`: more batched runs
+    run at `small_budget_rate` under that HBM budget.  `caps`: more batched runs
     at every rate, one per work cap."""
     from paper_2101_05356_amd import recon
     reqs = serve_requests(ctx, mt, n_req, n_steps, seed)
     model = recon.Model(ctx, mt)
     work = np.array([j.W * j.H * j.spp * (1 + j.L) for j in reqs], np.float64)
-    keys = ("recons_per_s", "p50_s", "p99_s", "mean_s", "peak_active", "completed", "failed", "busy_s")
+    keys = ("recons_per_s", "p50_s", "p99_s", "mean_s", "peak_active", "completed", "failed", "busy_s",
+            "submit_late_max_s")
     pick = lambda st: {k: st[k] for k in keys}
     rmax = max(rates)
     arr_max = poisson_arrivals(n_req, rmax, seed)
@@ -441,9 +456,11 @@ def serve_sweep(ctx, mt, n_req, rates, n_steps, budget, work_cap, serial_check_r
                                "recursion": {"p50_s": nearest_rank(lat, 0.5), "p99_s": nearest_rank(lat, 0.99),
                                              "mean_s": float(lat.mean())}}
     if small_budget is not None:
-        st_g, _ = serve_run(model, reqs, arr_max, n_steps, small_budget, 64, work_cap, "small_budget")
-        out["small_budget"] = {"hbm_budget_gb": small_budget / 2**30, "rate_per_s": rmax, **pick(st_g),
-                               "peak_bytes_gb": st_g["peak_bytes"] / 2**30}
+        cap_g = work_cap if small_budget_cap is None else small_budget_cap
+        arr_g = poisson_arrivals(n_req, small_budget_rate, seed)
+        st_g, _ = serve_run(model, reqs, arr_g, n_steps, small_budget, 64, cap_g, "small_budget")
+        out["small_budget"] = {"hbm_budget_gb": small_budget / 2**30, "rate_per_s": small_budget_rate, "work_cap": cap_g,
+                               **pick(st_g), "peak_bytes_gb": st_g["peak_bytes"] / 2**30}
     return out
 
 

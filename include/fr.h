@@ -449,8 +449,8 @@ int fr_adam_step(float* d_param, const float* d_grad, float* d_m, float* d_v, co
  * (3L)] are optimised with Adam (Sec. 5) against its target image, with its
  * own image size, samples per pixel and lights.  fr_batch_step advances every
  * job of a batch by one or more optimisation steps (blend, pose, normals +
- * refit, render, loss, backward with edge sampling, adjoints, Adam), with one
- * launch per stage covering all jobs; with use_graph the launch sequence is
+ * refit, render, loss, backward with edge sampling and, for a job that asks
+ * for it, the shadow-edge term, adjoints, Adam), with one launch per stage covering all jobs; with use_graph the launch sequence is
  * captured into a hipGraph once per job set and replayed.
  * ------------------------------------------------------------------------- */
 typedef struct fr_model fr_model;
@@ -464,7 +464,10 @@ typedef struct {
   int32_t hist_cap;        /* per-step losses kept on the device */
   uint64_t seed;           /* Philox key of this job's renders */
   float fov_y;             /* host value, radians */
-  int32_t pad_;
+  int32_t shadow_edge_samples; /* line samples per step of the shadow-edge boundary term
+                                  (Sec. 4 "Edge Sampling" on the shadow rays of Sec. 3.3; the
+                                  fr_shadow_edges estimator, vertex gradients only):
+                                  0 = off, -1 = W*H */
   /* host or device memory, copied at fr_batch_add (free to reuse afterwards): */
   const float* cam;        /* [12] camera R (row-major), T */
   const float* light_p0;   /* [L*3] */

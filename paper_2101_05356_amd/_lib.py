@@ -10,7 +10,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfr.so")
+# FR_LIB: load another build of the library (for comparing builds side by side)
+LIB_PATH = os.environ.get("FR_LIB", os.path.join(HERE, "libfr.so"))
 
 FR_OK, FR_ERR_INVALID_ARG, FR_ERR_SHAPE, FR_ERR_OOM, FR_ERR_BUDGET = 0, 1, 2, 3, 4
 FR_ERR_DEVICE, FR_ERR_NONFINITE, FR_ERR_LIMIT, FR_ERR_NOT_FOUND = 5, 6, 7, 8
@@ -55,7 +56,7 @@ class FrJobDesc(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("spp", ctypes.c_int32),
                 ("n_lights", ctypes.c_int32), ("edge_samples", ctypes.c_int32), ("smooth", ctypes.c_int32),
                 ("brdf_variant", ctypes.c_int32), ("hist_cap", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("fov_y", ctypes.c_float), ("pad_", ctypes.c_int32),
+                ("fov_y", ctypes.c_float), ("shadow_edge_samples", ctypes.c_int32),
                 ("cam", P), ("light_p0", P), ("light_e1", P), ("light_e2", P), ("light_shape", P),
                 ("target", P), ("params", P), ("lr", P)]
 

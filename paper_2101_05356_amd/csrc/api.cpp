@@ -857,6 +857,8 @@ int validate_job(fr_model* md, const fr_job_desc* d) {
       !d->lr)
     return fail(ctx, FR_ERR_INVALID_ARG, "null job pointer");
   if (!(d->fov_y > 0.0f && d->fov_y < 3.1f)) return fail(ctx, FR_ERR_INVALID_ARG, "fov_y must be in (0, 3.1)");
+  if (d->edge_samples < -1 || d->shadow_edge_samples < -1)
+    return fail(ctx, FR_ERR_INVALID_ARG, "edge sample counts must be -1 (W*H) or >= 0");
   return FR_OK;
 }
 
@@ -1008,6 +1010,11 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   J.ea.th = std::tan(0.5 * (double)d->fov_y);
   J.ea.aspect = (double)d->width / (double)d->height;
   J.ea.dEdp = J.dEdp; J.ea.gverts = md_.acc; J.ea.gcam = nullptr; J.ea.dbg_rec = nullptr; J.ea.dbg_flag = nullptr;
+  // shadow-edge term: vertex gradients only (the batch optimises no light geometry or camera)
+  J.se = fr::ShadowEdgeArgs{};
+  J.se.nbr = md_.face_nbr;
+  J.se.n_samples = d->shadow_edge_samples < 0 ? d->width * d->height : d->shadow_edge_samples;
+  J.se.dEdp = J.dEdp; J.se.gverts = md_.acc;
   J.mean_geo = md->mean_geo; J.basis_geo = md->basis_geo; J.mean_alb = md->mean_alb; J.basis_alb = md->basis_alb;
   J.K_geo = md->K_geo; J.K_alb = md->K_alb; J.N = N; J.F = md->topo.F; J.M = M;
   J.hist_cap = jh->hist_cap;

@@ -13,6 +13,7 @@ struct JobDev {
   RenderArgs ra;            // forward view (light chunks for the forward)
   RenderArgs rb;            // backward view (light chunks for the backward)
   EdgeArgs ea;              // boundary term
+  ShadowEdgeArgs se;        // shadow-edge boundary term (n_samples 0: off)
   const float* mean_geo; const float* basis_geo; const float* mean_alb; const float* basis_alb;
   int K_geo, K_alb, N, F, M;
   float* v_obj; float* v_w; float* diffuse;

@@ -119,6 +119,11 @@ FR_BATCH_KERNEL(kb_edge_len, 256) {
 FR_BATCH_KERNEL(kb_edge_scan, 256) { FR_JOB_PROLOGUE edge_scan_local_block(J.edge_len, J.ea.E, J.edge_cdf, J.scan_part, lb); }
 FR_BATCH_KERNEL(kb_edge_scan_add, 256) { FR_JOB_PROLOGUE edge_scan_add_block(J.edge_cdf, J.ea.E, J.scan_part, lb); }
 __attribute__((amdgpu_waves_per_eu(6))) FR_BATCH_KERNEL(kb_edge_samples, 256) { FR_JOB_PROLOGUE edge_samples_block<false, false>(J.rb, J.ea, lb); }
+// shadow-edge term into the vertex accumulators (its jumps' light points are
+// shaded with the step's light records; the camera rays are traced again)
+FR_BATCH_KERNEL(kb_shadow_edges, 256) {
+  FR_JOB_PROLOGUE shadow_edge_sample<false, false>(J.rb, J.se, lb * 256 + (int)threadIdx.x);
+}
 FR_BATCH_KERNEL(kb_pose_bwd_v, 256) { FR_JOB_PROLOGUE pose_bwd_v_block(J.N, J.param + J.off_pose, J.g_verts, J.g_vobj, lb); }
 FR_BATCH_KERNEL(kb_pose_bwd_p, 1024) {
   FR_JOB_PROLOGUE pose_bwd_p_block(J.v_obj, J.N, J.param + J.off_pose, J.g_verts, J.grad + J.off_pose, lb);
@@ -150,7 +155,7 @@ __global__ void kb_advance(JobDev* jobs, int njobs) {
 enum Stage {
   S_BLEND_GEO, S_BLEND_ALB, S_POSE, S_NORMALS, S_REFIT, S_REFIT_TOP, S_GATHER4, S_LIGHTS, S_PRIM, S_FWD, S_SUM, S_LOSS,
   S_LOSS_FINAL, S_SMOOTH_ADJ, S_ZERO_GRADS, S_BWD, S_SLOTS, S_NBWD_P, S_NBWD_G, S_FACE_FRONT, S_EDGE_LEN, S_EDGE_SCAN, S_EDGE_SCAN_ADD,
-  S_EDGE_SAMPLES, S_FIX_FINALIZE, S_POSE_BWD_V, S_POSE_BWD_P, S_BLEND_BWD_GEO, S_BLEND_BWD_ALB, S_ADAM, S_COUNT
+  S_EDGE_SAMPLES, S_SHADOW_EDGES, S_FIX_FINALIZE, S_POSE_BWD_V, S_POSE_BWD_P, S_BLEND_BWD_GEO, S_BLEND_BWD_ALB, S_ADAM, S_COUNT
 };
 
 static int stage_blocks(const JobDev& J, int s) {
@@ -176,6 +181,7 @@ static int stage_blocks(const JobDev& J, int s) {
     case S_EDGE_LEN: return J.ea.n_samples > 0 ? cdiv(J.ea.E, 256) : 0;
     case S_EDGE_SCAN: case S_EDGE_SCAN_ADD: return J.ea.n_samples > 0 ? cdiv(J.ea.E, kScanTile) : 0;
     case S_EDGE_SAMPLES: return J.ea.n_samples > 0 ? J.ea.bx * J.ea.n_groups : 0;
+    case S_SHADOW_EDGES: return J.se.n_samples > 0 ? cdiv(J.se.n_samples, 256) : 0;
     case S_POSE_BWD_P: return 1;
     case S_BLEND_BWD_GEO: return J.K_geo;
     case S_BLEND_BWD_ALB: return J.K_alb;
@@ -260,6 +266,7 @@ void Batch::launch_step(hipStream_t st) {
   FR_LAUNCH(kb_edge_scan, S_EDGE_SCAN, 256, 0);
   FR_LAUNCH(kb_edge_scan_add, S_EDGE_SCAN_ADD, 256, 0);
   FR_LAUNCH(kb_edge_samples, S_EDGE_SAMPLES, 256, 0);
+  FR_LAUNCH(kb_shadow_edges, S_SHADOW_EDGES, 256, 0);
   FR_LAUNCH(kb_fix_finalize, S_FIX_FINALIZE, 256, 0);
   FR_LAUNCH(kb_pose_bwd_v, S_POSE_BWD_V, 256, 0);
   FR_LAUNCH(kb_pose_bwd_p, S_POSE_BWD_P, 1024, 0);

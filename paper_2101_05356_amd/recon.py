@@ -97,6 +97,7 @@ class JobSpec:
     lr: torch.Tensor           # [n_param]
     seed: int = 4
     edge_samples: int = -1     # -1: W*H, 0: off
+    shadow_edge_samples: int = 0   # shadow-edge term in the batched step: -1: W*H, 0: off
     smooth: bool = True
     brdf_variant: int = 0
     hist_cap: int = 1024
@@ -474,6 +475,7 @@ def _desc(job: JobSpec):
     d.edge_samples, d.smooth, d.brdf_variant, d.hist_cap = job.edge_samples, int(job.smooth), job.brdf_variant, \
         job.hist_cap
     d.seed, d.fov_y = job.seed, float(job.camera.fov_y)
+    d.shadow_edge_samples = job.shadow_edge_samples
     d.cam, d.light_p0, d.light_e1, d.light_e2 = (keep[k].data_ptr() for k in ("cam", "p0", "e1", "e2"))
     d.light_shape, d.target, d.params, d.lr = (keep[k].data_ptr() for k in ("shape", "target", "params", "lr"))
     return d, keep

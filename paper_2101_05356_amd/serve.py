@@ -45,7 +45,9 @@ class Server:
         self.jobs = {}
 
     def submit(self, job: JobSpec, n_steps: int) -> int:
-        """Queue a reconstruction of `n_steps` Adam steps; inputs are copied."""
+        """Queue a reconstruction of `n_steps` Adam steps; inputs are copied.
+        Pass host arrays: a device tensor is first copied to the host, and
+        that copy waits for work already queued on the device."""
         lt, cam = job.lights, job.camera
         arrays = dict(cam=_host(np.concatenate([np.asarray(cam.R, np.float32).reshape(9),
                                                 np.asarray(cam.T, np.float32)])),
@@ -57,6 +59,7 @@ class Server:
         d.edge_samples, d.smooth, d.brdf_variant, d.hist_cap = job.edge_samples, int(job.smooth), \
             job.brdf_variant, max(job.hist_cap, n_steps)
         d.seed, d.fov_y = job.seed, float(cam.fov_y)
+        d.shadow_edge_samples = job.shadow_edge_samples
         ptr = lambda k: arrays[k].ctypes.data_as(ctypes.c_void_p).value
         d.cam, d.light_p0, d.light_e1, d.light_e2 = ptr("cam"), ptr("p0"), ptr("e1"), ptr("e2")
         d.light_shape, d.target, d.params, d.lr = ptr("shape"), ptr("target"), ptr("params"), ptr("lr")

@@ -124,3 +124,64 @@ def test_batched_step_gradient_matches_oracle_gradient_and_differences(oracle_li
             bad.append((int(i), f1, float(ga[i]), tol(H_FD)))
     assert len(skipped) <= 4, skipped
     assert not bad, bad
+
+
+def test_batched_step_shadow_edge_term_equals_the_per_call_term(oracle_lib):
+    """A job with shadow_edge_samples = n adds to its batched gradient what
+    fr_shadow_edges gives for the same step (same Philox key and counter, same
+    dE/dp, same light records), carried through the pose and blend adjoints.
+    The batch's gradient with the term minus the one without it is compared
+    with the per-call vertex gradient composed with the oracle's pose and
+    blend adjoints: albedo and radiance entries must not move at all; the
+    geometry and pose entries agree to 1e-4 of the term's size plus the FP32
+    rounding of the two whole gradients (each rounded once to FP32 per vertex
+    and summed in FP32 by the blend adjoint: 1e-6 of their size).  The term's
+    own accuracy against the oracle is tested on its own entry point."""
+    import dataclasses
+
+    import oracle
+    from paper_2101_05356_amd import recon
+    from paper_2101_05356_amd import render as R
+    ctx = R.Context(0)
+    Wse, n_se = 48, 64 * 128
+    model = scenes.synthetic_morph_model(seed=5, n_lon=24, n_ring=16, K_s=16, K_e=12, K_r=16)
+    mt = recon.ModelTensors.from_model(model)
+    job, _ = recon.face_job(mt, np.random.default_rng(SEED), ctx, W=Wse, spp=SPP, n_lights=L, seed=SEED,
+                            edge_samples=0, hist_cap=4)
+    job.target = torch.full((Wse, Wse, 3), 100.0, dtype=torch.float32, device="cuda")
+    p0 = job.params.cpu().numpy().astype(np.float64)
+    grads = []
+    for n in (0, n_se):
+        b = recon.Batch(recon.Model(ctx, mt))
+        jid = b.add(dataclasses.replace(job, shadow_edge_samples=n))
+        b.step(1, graph=True)
+        torch.cuda.synchronize()
+        grads.append(b.read(jid)["grad"].astype(np.float64))
+        del b
+    delta = grads[1] - grads[0]
+
+    # the per-call term at the same state: step counter 1, dE/dp of the step's own loss
+    rc = recon.Reconstruction(ctx, mt, job)
+    rc.t = 1
+    sc = rc.scene()
+    img = R.render_forward(rc.mesh, sc, verts=rc.v_w)
+    _, dEdp = R.loss(img, job.target, smooth=True)
+    gv = R.shadow_edges(rc.mesh, sc, dEdp, n_se, verts=rc.v_w, groups=("verts",))["verts"]
+    torch.cuda.synchronize()
+    gv = G.to_np(gv).astype(np.float64)
+    assert np.abs(gv).max() > 0, "no shadow-edge jumps on this face"
+
+    sl = recon.param_slices(mt.K_geo, mt.K_alb, L)
+    basis_geo = np.concatenate([model.basis_id, model.basis_exp]).astype(np.float64)
+    v_obj = oracle.blend(model.mean_shape, basis_geo, p0[sl["geo"]]).reshape(-1, 3)
+    gv_obj, gpose = oracle.pose_vjp(v_obj, p0[sl["pose"]], gv)
+    want = np.zeros_like(p0)
+    want[sl["geo"]] = oracle.blend_vjp(basis_geo, gv_obj.reshape(-1))
+    want[sl["pose"]] = gpose
+    assert np.array_equal(delta[sl["alb"]], np.zeros_like(delta[sl["alb"]]))
+    assert np.array_equal(delta[sl["rad"]], np.zeros_like(delta[sl["rad"]]))
+    err = np.linalg.norm(delta - want)
+    bound = 1e-4 * np.linalg.norm(want) + 1e-6 * (np.linalg.norm(grads[0]) + np.linalg.norm(grads[1]))
+    print(f"batched shadow-edge term vs per-call: |diff| {err:.3e}, bound {bound:.3e}, "
+          f"|term| {np.linalg.norm(want):.3e}, |grad| {np.linalg.norm(grads[0]):.3e}", flush=True)
+    assert err <= bound, (err, bound)
