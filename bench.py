@@ -40,7 +40,8 @@ C_FRAME = 45      # hit point, interpolated normal + normalise, attributes, cos_
 C_LIGHT = 35      # light point, direction, distance, two cosines, geometry term
 C_SETUP = 15      # shadow-ray setup (reciprocal direction, shear)
 C_BRDF = 60       # half vector, D, two G1, Fresnel, combination
-C_BOX = 15        # one slab test (6 fma + 6 min/max + min3/max3 + 1 cmp)
+C_BOX = 11        # one slab test with the ray's own direction signs: 6 fma (entry and exit plane per axis),
+                  # max3 + max (entry, with tmin), min3 + min (exit, with tmax), 1 cmp
 C_LEAF = 34       # watertight ray/triangle test
 ADJ_FACTOR = 3.0  # reverse-mode shading costs ~3x the forward shading
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock (packed FP32 disabled)

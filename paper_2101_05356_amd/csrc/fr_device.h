@@ -271,7 +271,7 @@ __device__ __forceinline__ float shear(const V3& M, float c, float x, float y, f
 // crossing distance when the ray passes within the ambiguity band of the
 // triangle boundary, or crosses it within kFlagT of tmin / tmax (0 for grazing
 // rays, whose distance is ill-conditioned).
-template <bool DUMP>
+template <bool DUMP, bool NEED_T = true>
 __device__ __forceinline__ bool tri_test(const Ray& r, const float* v, float tmax, float& t, float& amb_t) {
   const float Ax = shear(r.Mx, r.cx, v[0], v[1], v[2]), Ay = shear(r.My, r.cy, v[0], v[1], v[2]);
   const float Bx = shear(r.Mx, r.cx, v[3], v[4], v[5]), By = shear(r.My, r.cy, v[3], v[4], v[5]);
@@ -307,12 +307,18 @@ __device__ __forceinline__ bool tri_test(const Ray& r, const float* v, float tma
     if (inside_all && det != 0.0f && (fabsf(tc - r.tmin) < kFlagT || fabsf(tc - tmax) < kFlagT))
       amb_t = fminf(amb_t, tc);
   }
-  if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
-  if (det == 0.0f) return false;
-  const bool in_range = det > 0.0f ? (T > r.tmin * det && T < tmax * det) : (T < r.tmin * det && T > tmax * det);
-  if (!in_range) return false;
-  t = T / det;
-  return true;
+  // Branch-free acceptance: U, V, W of one sign (min >= 0 or max <= 0; a NaN
+  // is ignored by the min/max as by the comparisons it replaces), det != 0,
+  // and T / det in (tmin, tmax) compared without dividing: with s the sign
+  // of det, s T against tmin |det| and tmax |det| (negation is exact).
+  const bool sides = fminf(fminf(U, V), W) >= 0.0f || fmaxf(fmaxf(U, V), W) <= 0.0f;
+  const float Ts = det < 0.0f ? -T : T, D = fabsf(det);
+  const bool hit = sides && det != 0.0f && Ts > r.tmin * D && Ts < tmax * D;
+  if (NEED_T) {   // any-hit queries need no distance
+    const float tt = T / det;
+    t = hit ? tt : t;
+  }
+  return hit;
 }
 
 struct HitState {
@@ -369,6 +375,15 @@ template <bool ANY, bool DUMP, bool EX, int OCT>
 __device__ __forceinline__ void trace_impl(const Bvh4Node* __restrict__ nodes, const TriRec* __restrict__ tris,
                                            int n_tris, const Ray& r, bool active, int exclude, HitState& h,
                                            bool& occluded, TravStats* st, int ex2, int ex3, uint64_t live) {
+  // Keep the tree and record bases in SGPRs for the whole walk: without the
+  // opaque copy the compiler reloads them from the kernel arguments at every
+  // node, a second dependent scalar load in front of each node fetch.
+  {
+    uint64_t pn = reinterpret_cast<uint64_t>(nodes), pt = reinterpret_cast<uint64_t>(tris);
+    asm("" : "+s"(pn), "+s"(pt));
+    nodes = reinterpret_cast<const Bvh4Node*>(pn);
+    tris = reinterpret_cast<const TriRec*>(pt);
+  }
   const int lane = lane_id();
   if (DUMP && st && active) {
     st->rays += 1;
@@ -382,6 +397,8 @@ __device__ __forceinline__ void trace_impl(const Bvh4Node* __restrict__ nodes, c
   int sp = 0;
   int node = n_tris > 1 ? 0 : ~0;
   const float tpad = DUMP ? kFlagT : 0.0f;
+  // canonical once, so that the min/max of every box test need not canonicalise it again
+  const float tmax0 = __builtin_canonicalizef(r.tmax);
   // A tree visits each of its nodes and leaves at most once; the cap only
   // guards against a corrupted structure.
   int budget = 2 * n_tris + 64;
@@ -389,7 +406,7 @@ __device__ __forceinline__ void trace_impl(const Bvh4Node* __restrict__ nodes, c
   while (--budget > 0) {
     if (node >= 0) {
       const Bvh4Node nd = load_const(nodes, node);  // two 64-byte scalar loads
-      const float tcur = DUMP ? (ANY ? r.tmax : h.t) + tpad : (ANY ? r.tmax : h.t);
+      const float tcur = DUMP ? (ANY ? tmax0 : h.t) + tpad : (ANY ? tmax0 : h.t);
       float tn0, tn1, tn2, tn3, tf;
       const auto box = [&](int k, float& tn) {
         if (OCT >= 0) slab4_oct<(OCT < 0 ? 0 : OCT)>(r, nd, k, tcur, tn, tf);
@@ -442,7 +459,7 @@ __device__ __forceinline__ void trace_impl(const Bvh4Node* __restrict__ nodes, c
       const float tmax = ANY ? r.tmax : h.t;
       float amb = 3.4e38f;
       const bool other = tr.id != exclude && (!EX || (tr.id != ex2 && tr.id != ex3));
-      const bool hit = tri_test<DUMP>(r, tr.v, tmax, t, amb) & active & other;
+      const bool hit = tri_test<DUMP, !ANY || DUMP>(r, tr.v, tmax, t, amb) & active & other;
       if (DUMP && active && other) h.tamb = fminf(h.tamb, amb);
       if (DUMP && !ANY && hit && h.id >= 0 && fabsf(t - h.t) < kFlagT) h.tamb = fminf(h.tamb, t);
       if (ANY) {
