@@ -29,18 +29,19 @@ __device__ __forceinline__ V3 project_out(V3 g, V3 u, float inv_len) {
 __device__ __forceinline__ void g1_fwd_bwd(float nv, float hv, float r, float& G1, float& dG1_dnv, float& dG1_dr) {
   dG1_dnv = 0.0f;
   dG1_dr = 0.0f;
-  if (!(hv / nv > 0.0f)) { G1 = 0.0f; return; }
+  if (!(hv * nv > 0.0f)) { G1 = 0.0f; return; }   // h.v / n.v > 0: the same sign
   const float s2 = 1.0f - nv * nv;
   if (s2 <= 0.0f) { G1 = 1.0f; return; }
-  const float rs = sqrtf(s2);
-  const float a = nv / (r * rs);
+  const float irs = rsqrt_hw(s2), ir = rcp_hw(r);
+  const float a = nv * irs * ir;
   if (!(a < 1.6f)) { G1 = 1.0f; return; }
   const float P = 3.535f * a + 2.181f * a * a, Q = 1.0f + 2.276f * a + 2.577f * a * a;
-  G1 = P / Q;
+  const float iQ = rcp_hw(Q);
+  G1 = P * iQ;
   const float dP = 3.535f + 4.362f * a, dQ = 2.276f + 5.154f * a;
-  const float dG = (dP * Q - P * dQ) / (Q * Q);
-  dG1_dnv = dG / (r * s2 * rs);     // da/dnv = (1 - nv^2)^(-3/2) / r
-  dG1_dr = -dG * a / r;             // da/dr = -a / r
+  const float dG = (dP * Q - P * dQ) * iQ * iQ;
+  dG1_dnv = dG * ir * irs * irs * irs;   // da/dnv = (1 - nv^2)^(-3/2) / r
+  dG1_dr = -dG * a * ir;                 // da/dr = -a / r
 }
 
 // The shadow decisions of lights [j0, j1) (global indices) for sample rs,
@@ -125,24 +126,28 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
           V3 f = {0, 0, 0};
           if (a.components & 1) f = fr.c * (1.0f / kPi);
           V3 hraw = ls.l + fr.wo;
-          const float ih = 1.0f / sqrtf(dot(hraw, hraw));
+          const float ih = rsqrt_hw(dot(hraw, hraw));
           const V3 hv = hraw * ih;
           float nh = 0, ex = 0, nd = 0, D = 0, oh = 0, G1o = 0, G1l = 0, dG1o = 0, dG1l = 0, dG1o_r = 0, dG1l_r = 0;
+          float lg2nh = 0, ir = 0, iden = 0;
           float om = 0, fw = 0, spec = 0;
           V3 Fv = {0, 0, 0};
           const bool do_spec = (a.components & 2) != 0;
           if (do_spec) {
-            nh = dot(fr.ns, hv);
-            ex = 2.0f / fr.r - 2.0f;
-            nd = a.variant == FR_BRDF_NORMALIZED ? 1.0f / (kPi * fr.r) : (2.0f / fr.r + 2.0f) / (2.0f * kPi);
-            D = nd * powf(nh, ex);
+            nh = dot(fr.ns, hv);   // > 0: n.l > 0 and n.o > 0 here
+            ir = rcp_hw(fr.r);
+            ex = 2.0f * ir - 2.0f;
+            nd = a.variant == FR_BRDF_NORMALIZED ? ir * (1.0f / kPi) : (2.0f * ir + 2.0f) * (1.0f / (2.0f * kPi));
+            lg2nh = log2_hw(nh);
+            D = nd * exp2_hw(ex * lg2nh);
             oh = dot(fr.wo, hv);
             const float lh = dot(ls.l, hv);
             g1_fwd_bwd(fr.cos_o, oh, fr.r, G1o, dG1o, dG1o_r);
             g1_fwd_bwd(ls.cos_s, lh, fr.r, G1l, dG1l, dG1l_r);
             om = 1.0f - oh;
             fw = a.variant == FR_BRDF_NORMALIZED ? om * om * om * om * om : om;
-            spec = D * G1o * G1l / (4.0f * fr.cos_o * ls.cos_s);
+            iden = rcp_hw(4.0f * fr.cos_o * ls.cos_s);
+            spec = D * G1o * G1l * iden;
             Fv = {fr.s.x + (1.0f - fr.s.x) * fw, fr.s.y + (1.0f - fr.s.y) * fw, fr.s.z + (1.0f - fr.s.z) * fw};
             f = f + V3{Fv.x * spec, Fv.y * spec, Fv.z * spec};
           }
@@ -162,18 +167,18 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
             const float gfw = gF.x * (1.0f - fr.s.x) + gF.y * (1.0f - fr.s.y) + gF.z * (1.0f - fr.s.z);
             const float gom = a.variant == FR_BRDF_NORMALIZED ? gfw * 5.0f * om * om * om * om : gfw;
             float goh = -gom;
-            const float den = 4.0f * fr.cos_o * ls.cos_s;
-            const float gD = gspec * G1o * G1l / den;
-            const float gG1o = gspec * D * G1l / den, gG1l = gspec * D * G1o / den;
-            gcos_o -= gspec * spec / fr.cos_o;
-            gcos_s -= gspec * spec / ls.cos_s;
+            const float gD = gspec * G1o * G1l * iden;
+            const float gG1o = gspec * D * G1l * iden, gG1l = gspec * D * G1o * iden;
+            gcos_o -= gspec * spec * rcp_hw(fr.cos_o);
+            gcos_s -= gspec * spec * rcp_hw(ls.cos_s);
             gcos_o += gG1o * dG1o;
             gcos_s += gG1l * dG1l;
             gr += gG1o * dG1o_r + gG1l * dG1l_r;
             // D = nd * nh^ex
-            const float gnh = gD * D * ex / nh;
-            const float dlnnd = a.variant == FR_BRDF_NORMALIZED ? -1.0f / fr.r : -1.0f / (fr.r * (1.0f + fr.r));
-            gr += gD * D * (dlnnd - 2.0f * logf(nh) / (fr.r * fr.r));
+            const float gnh = gD * D * ex * rcp_hw(nh);
+            const float dlnnd = a.variant == FR_BRDF_NORMALIZED ? -ir : -ir * rcp_hw(1.0f + fr.r);
+            // d ln D / dr = dln nd/dr - 2 ln(nh) / r^2 (ln = log2 ln 2)
+            gr += gD * D * (dlnnd - 2.0f * 0.69314718f * lg2nh * ir * ir);
             // nh = ns . h, oh = wo . h, h = normalize(l + wo)
             const V3 gh = fr.ns * gnh + fr.wo * goh;
             gns = gns + hv * gnh;
@@ -183,9 +188,10 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
             gwo = gwo + ghraw;
           }
           // geom = cos_s cos_a / dist2
-          gcos_s += ggeom * ls.cos_a / ls.dist2;
-          const float gcos_a = ggeom * ls.cos_s / ls.dist2;
-          const float gdist2 = -ggeom * ls.geom / ls.dist2;
+          const float id2 = rcp_hw(ls.dist2);
+          gcos_s += ggeom * ls.cos_a * id2;
+          const float gcos_a = ggeom * ls.cos_s * id2;
+          const float gdist2 = -ggeom * ls.geom * id2;
           // cos_o = ns . wo ; cos_s = ns . l ; cos_a = na . l
           gns = gns + fr.wo * gcos_o + ls.l * gcos_s;
           gwo = gwo + fr.ns * gcos_o;
@@ -203,7 +209,7 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
             const V3 e1 = {Lj.e1[0], Lj.e1[1], Lj.e1[2]}, e2 = {Lj.e2[0], Lj.e2[1], Lj.e2[2]};
             const V3 ge1n = cross(e2, gna) * (-kap), ge2n = cross(gna, e1) * (-kap);
             // l = dq / |dq|, dist2 = dq . dq
-            V3 gdq = project_out(gl, ls.l, 1.0f / ls.dist);
+            V3 gdq = project_out(gl, ls.l, rcp_hw(ls.dist));
             gdq = gdq + (ls.q - fr.x) * (2.0f * gdist2);
             gx = gx - gdq;
             // q = p0 + w1 e1 + w2 e2

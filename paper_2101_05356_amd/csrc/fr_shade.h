@@ -384,12 +384,12 @@ __device__ __forceinline__ uint32_t shadow_mask(const RenderArgs& a, int j0, int
 // Walter et al.'s rational G1 with a = n.v / (r sqrt(1 - (n.v)^2)).
 template <bool DUMP>
 __device__ __forceinline__ float smith_g1(float nv, float hv, float r, float& flag) {
-  if (!(hv / nv > 0.0f)) return 0.0f;
+  if (!(hv * nv > 0.0f)) return 0.0f;   // h.v / n.v > 0: the same sign
   const float s2 = 1.0f - nv * nv;
   if (s2 <= 0.0f) return 1.0f;
-  const float a = nv / (r * sqrtf(s2));
+  const float a = nv * rsqrt_hw(s2) * rcp_hw(r);
   if (DUMP && fabsf(a - 1.6f) < kFlagG1 * 1.6f) flag = 1.0f;
-  if (a < 1.6f) return (3.535f * a + 2.181f * a * a) / (1.0f + 2.276f * a + 2.577f * a * a);
+  if (a < 1.6f) return (3.535f * a + 2.181f * a * a) * rcp_hw(1.0f + 2.276f * a + 2.577f * a * a);
   return 1.0f;
 }
 
@@ -404,16 +404,17 @@ __device__ __forceinline__ void brdf_eval(int variant, int components, const Fra
   }
   if (components & 2) {
     V3 hv = ls.l + f.wo;
-    hv = hv * (1.0f / sqrtf(dot(hv, hv)));
-    const float nh = dot(f.ns, hv);
-    const float ex = 2.0f / f.r - 2.0f;
-    const float nd = variant == FR_BRDF_NORMALIZED ? 1.0f / (kPi * f.r) : (2.0f / f.r + 2.0f) / (2.0f * kPi);
-    const float D = nd * powf(nh, ex);
+    hv = hv * rsqrt_hw(dot(hv, hv));
+    const float nh = dot(f.ns, hv);   // > 0: n.l > 0 and n.o > 0 here
+    const float ir = rcp_hw(f.r);
+    const float ex = 2.0f * ir - 2.0f;
+    const float nd = variant == FR_BRDF_NORMALIZED ? ir * (1.0f / kPi) : (2.0f * ir + 2.0f) * (1.0f / (2.0f * kPi));
+    const float D = nd * exp2_hw(ex * log2_hw(nh));
     const float oh = dot(f.wo, hv), lh = dot(ls.l, hv);
     const float G = smith_g1<DUMP>(f.cos_o, oh, f.r, flag) * smith_g1<DUMP>(ls.cos_s, lh, f.r, flag);
     const float om = 1.0f - oh;
     const float fw = variant == FR_BRDF_NORMALIZED ? om * om * om * om * om : om;
-    const float spec = D * G / (4.0f * f.cos_o * ls.cos_s);
+    const float spec = D * G * rcp_hw(4.0f * f.cos_o * ls.cos_s);
     out[0] += (f.s.x + (1.0f - f.s.x) * fw) * spec;
     out[1] += (f.s.y + (1.0f - f.s.y) * fw) * spec;
     out[2] += (f.s.z + (1.0f - f.s.z) * fw) * spec;
