@@ -496,17 +496,19 @@ __device__ __forceinline__ void trace_impl(const Bvh4Node* __restrict__ nodes, c
 // Wave-packet traversal of the 4-wide tree.  Every lane of the wave must call
 // it (uniform control flow).  ANY = true: shadow/any-hit query over
 // (tmin, tmax), `occluded` is set on the first accepted triangle and the lane
-// drops out; when the live rays' direction signs agree on every axis (a
-// packet of shadow rays from neighbouring points to one light, nearly
-// always) the traversal runs the slab test specialised to that octant.
-// ANY = false: closest hit, ties in t resolved to the lowest triangle id.
+// drops out.  ANY = false: closest hit, ties in t resolved to the lowest
+// triangle id.  When the live rays' direction signs agree on every axis (a
+// packet of shadow rays from neighbouring points to one light, or of camera
+// rays through neighbouring pixels: nearly always) the traversal runs the
+// slab test specialised to that octant, whose entry distances are the
+// general test's bit for bit (the closest-hit order uses them).
 template <bool ANY, bool DUMP, bool EX = false>
 __device__ __forceinline__ void trace(const Bvh4Node* __restrict__ nodes, const TriRec* __restrict__ tris, int n_tris,
                                       const Ray& r, bool active, int exclude, HitState& h, bool& occluded,
                                       TravStats* st = nullptr, int ex2 = -1, int ex3 = -1) {
   const uint64_t live = ballot(active);
   if (live == 0) return;
-  if (ANY) {
+  {
     const uint64_t sx = ballot(active && r.inv.x < 0.0f), sy = ballot(active && r.inv.y < 0.0f);
     const uint64_t sz = ballot(active && r.inv.z < 0.0f);
     if ((sx == 0 || sx == live) && (sy == 0 || sy == live) && (sz == 0 || sz == live)) {
