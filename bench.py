@@ -10,11 +10,16 @@ synthetic and resident in HBM before the timed region.
 Prints one JSON line (see the "metric" field).  The headline value is nominal
 forward rays per second of whole steps: W*H*spp*(1 + L) / step time.  The
 same line carries the roofline of the dominant kernel, traversal statistics,
-the batched step over 32 faces of mixed sizes ("batch"), the serving run
-(Poisson arrivals, continuous batching vs one at a time: recons/s, p50/p99
-latency; "serving"), the large textured render (1024x1024, 200,000 triangles,
-1024^2 maps, 64 spp, 128 lights, refit every step; "large") and the FP64
-oracle's rate on the host ("cpu_baseline").
+the forward with the per-lane shadow-ray walk beside the wave packet
+("shadow_traversal"), the adjoint that traces its own decisions
+("recompute"), a whole reconstruction from its first step ("recon"), the
+two-stage reconstruction ("two_stage"), the batched step over 32 faces of
+mixed sizes ("batch"), the serving run (Poisson arrivals at several rates,
+continuous batching vs one at a time: recons/s, p50/p99 latency;
+"serving"; --serving-only runs the full rate sweep), the large textured
+render (1024x1024, 200,000 triangles, 1024^2 maps, 64 spp, 128 lights, refit
+every step; "large"), the environment-map and SH lighting legs, the
+shadow-edge term and the FP64 oracle's rate on the host ("cpu_baseline").
 """
 from __future__ import annotations
 
@@ -233,6 +238,29 @@ def measured_traffic(kernel):
     if h.hexdigest()[:16] != rec["sources_sha256_16"]:
         return None
     return rec["fetch_bytes"] + rec["write_bytes"]
+
+
+def traversal_compare(rc, reps=10):
+    """Forward time (primary pass + forward kernel, HIP events) with the
+    wave-packet and with the per-lane shadow-ray walk at the reconstruction's
+    current state, medians of `reps` renders each, and whether the two
+    images agree bit for bit."""
+    import torch
+    from paper_2101_05356_amd import render as R
+    sc = rc.scene()
+    res, imgs = {}, {}
+    for trav, name in ((0, "packet"), (1, "per_lane")):
+        ms = []
+        for i in range(reps + 1):
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            img = R.render_forward(rc.mesh, sc, verts=rc.v_w, events=ev, shadow_traversal=trav)
+            torch.cuda.synchronize()
+            if i:
+                ms.append(ev[0].elapsed_time(ev[1]))
+        res[name + "_ms"] = float(np.median(ms))
+        imgs[name] = img
+    res["images_equal"] = bool(torch.equal(imgs["packet"], imgs["per_lane"]))
+    return res
 
 
 def make_c2(ctx, width, spp, n_lights, edge_samples):
@@ -737,6 +765,7 @@ def main():
                                max(64.0 * (4 * (stats[6] + stats[8]) + stats[7] + stats[9]), 1.0)}
         out["rays_cast_per_s"] = (W * H * S + sh_rays) * args.steps / dt
         out["camera_samples_shaded"] = stats[10]
+        out["shadow_traversal"] = traversal_compare(rc)
     if args.recompute_steps > 0:
         # the same step with an adjoint that traces its camera and shadow rays again
         evr = []

@@ -203,7 +203,12 @@ typedef struct {
    * sample and light (one bit each, in the workspace: 4 bytes per sample and
    * chunk of light_chunk lights) for a backward with reuse_forward. */
   int32_t keep_shadows;
-  int32_t pad_;
+  /* fr_render_forward only: how the shadow rays walk the tree.  0: the wave
+   * packet (the 64 lanes of a wave share one traversal order, nodes fetched
+   * by scalar loads; the default and the faster); 1: each lane walks alone
+   * (its own stack and vector loads).  The same results either way; ignored
+   * by debug dumps.  Other values: FR_ERR_INVALID_ARG. */
+  int32_t shadow_traversal;
   /* Device scratch of the call (required): caller-owned device memory on the
    * mesh's device, 256-byte aligned, at least the bytes
    * fr_render_workspace_size gives for this scene and options.  No render

@@ -37,7 +37,7 @@ class FrRenderOpts(ctypes.Structure):
                 ("edge_samples", ctypes.c_int32), ("light_chunk", ctypes.c_int32),
                 ("dbg_hit", P), ("dbg_pflag", P), ("dbg_vis", P), ("dbg_stats", P),
                 ("ev_kernel_begin", P), ("ev_kernel_end", P),
-                ("reuse_forward", ctypes.c_int32), ("keep_shadows", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("reuse_forward", ctypes.c_int32), ("keep_shadows", ctypes.c_int32), ("shadow_traversal", ctypes.c_int32),
                 ("workspace", P), ("workspace_bytes", ctypes.c_size_t)]
 
 

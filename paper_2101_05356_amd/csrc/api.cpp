@@ -188,6 +188,8 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
   if (!pow2(s->spp) || s->spp > 1024) return fail(ctx, FR_ERR_LIMIT, "spp must be a power of two in [1, 1024]");
   if ((long long)s->width * s->height > (1ll << 26)) return fail(ctx, FR_ERR_LIMIT, "image larger than 2^26 pixels");
   if (s->tex_size < 0 || s->tex_size > 16384) return fail(ctx, FR_ERR_LIMIT, "tex_size must be in [0, 16384]");
+  if (o->shadow_traversal != 0 && o->shadow_traversal != 1)
+    return fail(ctx, FR_ERR_INVALID_ARG, "shadow_traversal must be 0 (wave packet) or 1 (per lane)");
   const bool maps = s->tex_size > 0;
   if (!s->verts || !s->cam || (!maps && (!s->diffuse || !s->specular || !s->roughness)))
     return fail(ctx, FR_ERR_INVALID_ARG, "null scene pointer");
@@ -220,6 +222,7 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
   if (o->light_chunk < 0 || o->light_chunk > 32)
     return fail(ctx, FR_ERR_INVALID_ARG, "light_chunk must be in [0, 32]");
   a.lc = o->light_chunk > 0 ? o->light_chunk : default_chunk;
+  a.shadow_traversal = o->shadow_traversal;
   a.n_lchunks = std::max(1, (s->n_lights + a.lc - 1) / a.lc);
   a.partial = nullptr;
   a.prim = nullptr;   // set by the caller (from its workspace, or a job's own buffer)

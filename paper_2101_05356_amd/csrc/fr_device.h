@@ -525,4 +525,64 @@ __device__ __forceinline__ void trace(const Bvh4Node* __restrict__ nodes, const 
   trace_impl<ANY, DUMP, EX, -1>(nodes, tris, n_tris, r, active, exclude, h, occluded, st, ex2, ex3, live);
 }
 
+// Per-lane any-hit traversal: the alternative to the wave packet for shadow
+// rays.  Every lane walks the tree with its own ray alone: its own stack (64
+// entries in private memory; a lane's pending siblings are a subset of the
+// packet's, so the host's depth bound for the packet stack holds), nodes and
+// triangle records fetched by per-lane vector loads (lanes at the same node
+// read the same lines), the general min/max slab test (lanes differ in
+// their direction signs).  The loop runs while any lane is still walking;
+// lanes at an internal node and lanes at a leaf take their branches under
+// their own masks.  The answer (an accepted triangle in (tmin, tmax) other
+// than `exclude`) does not depend on the order of the walk, so it is the
+// packet's bit for bit.
+__device__ __forceinline__ bool trace_lane_any(const Bvh4Node* __restrict__ nodes, const TriRec* __restrict__ tris,
+                                               int n_tris, const Ray& r, bool active, int exclude) {
+  int stk[kStackDepth];
+  int sp = 0;
+  int node = n_tris > 1 ? 0 : ~0;
+  bool walking = active, occ = false;
+  int budget = 2 * n_tris + 64;   // each node and leaf at most once (guards a corrupted structure)
+  while (ballot(walking) != 0ull) {
+    if (walking) {
+      int next = kEmpty;
+      if (node >= 0) {
+        const float4* q = reinterpret_cast<const float4*>(nodes + node);
+        const float4 lx = q[0], ly = q[1], lz = q[2], hx = q[3], hy = q[4], hz = q[5];
+        const int4 c = reinterpret_cast<const int4*>(q)[6];
+        const float lox[4] = {lx.x, lx.y, lx.z, lx.w}, loy[4] = {ly.x, ly.y, ly.z, ly.w}, loz[4] = {lz.x, lz.y, lz.z, lz.w};
+        const float hix[4] = {hx.x, hx.y, hx.z, hx.w}, hiy[4] = {hy.x, hy.y, hy.z, hy.w}, hiz[4] = {hz.x, hz.y, hz.z, hz.w};
+        const int cc[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+        for (int k = 3; k >= 0; --k) {
+          const float b[6] = {lox[k], loy[k], loz[k], hix[k], hiy[k], hiz[k]};
+          float tn, tf;
+          slab(r, b, r.tmax, tn, tf);
+          if (cc[k] != kEmpty && tn <= tf) {
+            if (next != kEmpty) stk[sp++] = next;
+            next = cc[k];
+          }
+        }
+      } else {
+        const float4* q = reinterpret_cast<const float4*>(tris + ~node);
+        const float4 a0 = q[0], a1 = q[1], a2 = q[2];
+        const float v[9] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w, a2.x};
+        const int id = __float_as_int(a2.y);
+        float t = 0.0f, amb = 3.4e38f;
+        if (tri_test<false, false>(r, v, r.tmax, t, amb) && id != exclude) {
+          occ = true;
+          walking = false;
+        }
+      }
+      if (walking) {
+        if (next != kEmpty) node = next;
+        else if (sp > 0) node = stk[--sp];
+        else walking = false;
+      }
+      if (--budget <= 0) walking = false;
+    }
+  }
+  return occ;
+}
+
 }  // namespace fr

@@ -177,6 +177,7 @@ struct RenderArgs {
   int chunks;             // S / 64 when S > 64, else 1
   int lanes_per_pixel;    // min(S, 64)
   int lc, n_lchunks;      // lights per work item, light chunks per tile
+  int shadow_traversal;   // forward: 0 wave packet, 1 per-lane walk
   int light0;             // global index of lights[0] (> 0 in the adjoint's later light groups)
   // spherical-harmonics lighting: coefficients [B*B*3] (B = sh_bands, 0 =
   // none), A_l, and the basis normalisation per (l, m >= 0) at

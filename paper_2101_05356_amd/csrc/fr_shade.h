@@ -352,7 +352,7 @@ __device__ __forceinline__ bool light_may_contribute(const LightRec& Lj, const F
 // cross from the traversals to the shading: the two never hold their
 // registers at the same time.  note(j, lit, occ, ls, sh) sees every light a
 // wave traces (debug dumps); skip(j) every light the wave culls as a whole.
-template <bool DUMP, class Draw, class Note, class Skip>
+template <bool DUMP, bool LANE = false, class Draw, class Note, class Skip>
 __device__ __forceinline__ uint32_t shadow_mask(const RenderArgs& a, int j0, int j1, bool shaded, const Frame& fr,
                                                 int self, Draw draw, Note note, Skip skip, TravStats* st) {
   uint32_t mask = 0;
@@ -371,7 +371,8 @@ __device__ __forceinline__ uint32_t shadow_mask(const RenderArgs& a, int j0, int
     HitState sh;
     sh.tamb = 3.4e38f;
     bool occ = false;
-    trace<true, DUMP>(a.nodes, a.recs, a.F, sr, lit, self, sh, occ, st);
+    if (LANE && !DUMP) occ = trace_lane_any(a.nodes, a.recs, a.F, sr, lit, self);
+    else trace<true, DUMP>(a.nodes, a.recs, a.F, sr, lit, self, sh, occ, st);
     if (lit && !occ) mask |= 1u << (j - j0);
     if (DUMP) note(j, lit, occ, ls, sh);
   }

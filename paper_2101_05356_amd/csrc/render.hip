@@ -85,7 +85,7 @@ void launch_primary(const RenderArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_primary<false>, dim3(blocks), dim3(256), 0, st, a);
 }
 
-template <bool DUMP, bool TEX>
+template <bool DUMP, bool TEX, bool LANE = false>
 __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __restrict__ image, int bid) {
   const int lane = threadIdx.x & 63;
   const Item it = wave_item(a, bid);
@@ -119,7 +119,7 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
     const auto skip = [&](int j) {
       if (DUMP && ps.valid) a.dbg_vis[rs * a.L + j] = shaded ? VIS_CULLED : VIS_NONE;
     };
-    const uint32_t vmask = shadow_mask<DUMP>(a, j0, j1, shaded, fr, ph.id, draw, note, skip, &st2);
+    const uint32_t vmask = shadow_mask<DUMP, LANE>(a, j0, j1, shaded, fr, ph.id, draw, note, skip, &st2);
     if (a.vis_out && ps.valid) a.vis_out[(size_t)it.chunk * ((size_t)a.W * a.H * a.S) + rs] = vmask;
     for (int j = j0; j < j1; ++j) {
       const bool vis = (vmask >> (j - j0)) & 1u;
@@ -176,6 +176,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   render_fwd_block<DUMP, TEX>(a, image, blockIdx.x);
 }
 
+// The forward with the per-lane shadow-ray traversal (fr_render_opts.
+// shadow_traversal = 1; production builds only): same results, measured
+// against the wave packet.
+template <bool TEX>
+__global__ __launch_bounds__(256) void k_render_fwd_lane(RenderArgs a, float* __restrict__ image) {
+  render_fwd_block<false, TEX, true>(a, image, blockIdx.x);
+}
+
 // image = sum over light chunks of the partial images, in chunk order.
 __device__ __forceinline__ void sum_chunks_block(const float* __restrict__ partial, int n, int nch,
                                                  float* __restrict__ image, int bid) {
@@ -195,7 +203,10 @@ void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st, hi
   const int blocks = wave_blocks_items(a);
   if (e0) (void)hipEventRecord(e0, st);
   launch_primary(a, st);
-  if (a.M > 0) {
+  if (a.shadow_traversal == 1 && !a.dbg_hit) {
+    if (a.M > 0) hipLaunchKernelGGL((k_render_fwd_lane<true>), dim3(blocks), dim3(256), 0, st, a, image);
+    else hipLaunchKernelGGL((k_render_fwd_lane<false>), dim3(blocks), dim3(256), 0, st, a, image);
+  } else if (a.M > 0) {
     if (a.dbg_hit)
       hipLaunchKernelGGL((k_render_fwd<true, true>), dim3(blocks), dim3(256), 0, st, a, image);
     else

@@ -219,8 +219,9 @@ def _opts(brdf_variant=0, components=3, edge_samples=0, dbg=None, light_chunk=0,
 
 
 def render_forward(mesh: Mesh, sc: DeviceScene, brdf_variant=0, components=3, dump=False, verts=None, stats=None,
-                   light_chunk=0, events=None, keep_shadows=False, workspace=None):
+                   light_chunk=0, events=None, keep_shadows=False, workspace=None, shadow_traversal=0):
     """Image [H,W,3]; with dump=True also (hit [H*W,S], pflag [H*W,S], vis [H*W,S,L]).
+    `shadow_traversal`: 0 the wave packet, 1 the per-lane walk (same results).
     `stats` (a uint64-sized int64 tensor [11], dump only) accumulates traversal counts.
     `events` (two torch.cuda.Event with timing) bracket the render kernel itself.
     `keep_shadows`: the workspace keeps the shadow decisions for a backward
@@ -236,6 +237,7 @@ def render_forward(mesh: Mesh, sc: DeviceScene, brdf_variant=0, components=3, du
     s = sc.struct(verts)
     o = _opts(brdf_variant, components, 0, dbg, light_chunk, events)
     o.keep_shadows = int(bool(keep_shadows))
+    o.shadow_traversal = int(shadow_traversal)
     _set_ws(o, mesh, sc, workspace, light_chunk)
     if stats is not None:
         assert dump and stats.dtype == torch.int64 and stats.numel() == 11

@@ -284,3 +284,29 @@ def test_backward_reusing_the_forward_decisions_is_bit_identical(oracle_lib):
     assert same(bwd(s1, True), want1)
     fwd(dataclasses.replace(s1, spp=8), True)            # larger buffers on this mesh
     assert same(bwd(s1, True), want1)
+
+
+@pytest.mark.parametrize("textured", [False, True])
+def test_per_lane_shadow_traversal_gives_the_packet_results(oracle_lib, textured):
+    """The per-lane shadow-ray walk (fr_render_opts.shadow_traversal = 1)
+    answers the same any-hit queries as the wave packet, so the production
+    forward's image and kept shadow decisions are the packet's bit for bit."""
+    if textured:
+        sc = scenes.patch_scene(W=40, H=24, spp=4)
+        sc = scenes.with_maps(sc, scenes.patch_corner_uv(sc), 16, seed=5)
+    else:
+        sc = scenes.face_render_scene(W=64, H=64, spp=4, n_lights=12)
+    m, ds = G.gpu_setup(sc)
+    outs = []
+    for trav in (0, 1):
+        # zero-filled, so that the workspaces' padding compares equal too:
+        # hits, light records, kept shadow masks and partial images
+        ws = torch.zeros(m.workspace_bytes(ds, keep_shadows=True), dtype=torch.uint8, device="cuda")
+        img = G.R.render_forward(m, ds, keep_shadows=True, workspace=ws, shadow_traversal=trav)
+        torch.cuda.synchronize()
+        outs.append((G.to_np(img), G.to_np(ws)))
+    assert np.array_equal(outs[0][0], outs[1][0]), "images differ"
+    assert np.array_equal(outs[0][1], outs[1][1]), "kept decisions differ"
+    from paper_2101_05356_amd import _lib
+    with pytest.raises(_lib.FrError, match="shadow_traversal"):
+        G.R.render_forward(m, ds, shadow_traversal=2)
