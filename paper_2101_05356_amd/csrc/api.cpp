@@ -139,7 +139,7 @@ size_t carve_bwd(const fr::MeshDev& d, const fr_scene* s, char* base, BwdScratch
   BwdScratch b;
   const size_t N = d.N, Lg = std::min(s->n_lights, fr::kBwdMaxLights), B = std::max(s->sh_bands, 0);
   const size_t MM = (size_t)std::max(s->tex_size, 0) * std::max(s->tex_size, 0);
-  b.acc = c.take<fr::fix_t>(13 * N + 12);
+  b.acc = c.take<fr::fix_t>(13 * N + 13);   // the last word holds max |dE/dp| (float bits)
   b.gnorm = c.take<float>(3 * N);
   b.slots = c.take<fr::fix_t>((size_t)fr::kSlots * (12 * Lg + 12 + 3 * B * B));
   b.tex = MM > 0 ? c.take<fr::fix_t>(7 * MM) : nullptr;
@@ -151,8 +151,9 @@ size_t carve_bwd(const fr::MeshDev& d, const fr_scene* s, char* base, BwdScratch
   return al256(c.off);
 }
 // shadow-edge term: fixed-point sums of verts, light geometry, camera
+// and one word for max |dE/dp|
 size_t ws_se_region(const fr::MeshDev& d, const fr_scene* s) {
-  return al256((3 * (size_t)d.N + 9 * (size_t)std::max(s->n_lights, 0) + 12) * sizeof(fr::fix_t));
+  return al256((3 * (size_t)d.N + 9 * (size_t)std::max(s->n_lights, 0) + 13) * sizeof(fr::fix_t));
 }
 
 // Constants of the SH lighting: A_l, the clamped cosine's SH coefficients
@@ -223,6 +224,7 @@ int build_args(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fr::Rende
     return fail(ctx, FR_ERR_INVALID_ARG, "light_chunk must be in [0, 32]");
   a.lc = o->light_chunk > 0 ? o->light_chunk : default_chunk;
   a.shadow_traversal = o->shadow_traversal;
+  a.gmax = nullptr;
   a.n_lchunks = std::max(1, (s->n_lights + a.lc - 1) / a.lc);
   a.partial = nullptr;
   a.prim = nullptr;   // set by the caller (from its workspace, or a job's own buffer)
@@ -645,7 +647,11 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
   fr::fix_t* acc_s = d.acc + 9 * N;
   fr::fix_t* acc_r = d.acc + 12 * N;
   fr::fix_t* acc_cam = d.acc + 13 * N;
-  fr::launch_zero_fix(d.acc, 13 * N + 12, hs);
+  // max |dE/dp| sets the power-of-two scale of the fixed-point sums
+  uint32_t* gmax = reinterpret_cast<uint32_t*>(d.acc + 13 * N + 12);
+  fr::launch_zero_fix(d.acc, 13 * N + 13, hs);
+  fr::launch_abs_max(d_dEdp, 3 * a.W * a.H, gmax, hs);
+  a.gmax = gmax;
   // texel accumulators [7 M^2]: diffuse, specular (3 M^2 each), roughness (M^2)
   const size_t MM = (size_t)a.M * a.M;
   const bool want_tex = a.M > 0 && (g->tex_diffuse || g->tex_specular || g->tex_roughness);
@@ -676,20 +682,20 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
   now.prim = key;
   if (use_vis) { now.vis = st.vis; now.vis_off = st.vis_off; now.vis_bytes = st.vis_bytes; }
   ws_store(m, base, now);
-  if (g->normals) fr::launch_fix_to_float(acc_n, g->normals, 3 * d.N, hs);
+  if (g->normals) fr::launch_fix_to_float(acc_n, g->normals, 3 * d.N, hs, gmax);
   if (g->verts) fr::launch_normals_backward(d, s->verts, acc_n, d.gnorm, acc_v, hs);
   const int ns = o->edge_samples < 0 ? s->width * s->height : o->edge_samples;
   if (ns > 0 && (g->verts || g->cam || o->dbg_hit))
     fr::launch_edges(d, a, d_dEdp, ns, g->verts ? acc_v : nullptr, g->cam ? acc_cam : nullptr, o->dbg_hit,
                      o->dbg_pflag, std::tan(0.5 * (double)s->fov_y), hs);
-  if (g->verts) fr::launch_fix_to_float(acc_v, g->verts, 3 * d.N, hs);
-  if (fg.diffuse) fr::launch_fix_to_float(acc_c, g->diffuse, 3 * d.N, hs);
-  if (fg.specular) fr::launch_fix_to_float(acc_s, g->specular, 3 * d.N, hs);
-  if (fg.roughness) fr::launch_fix_to_float(acc_r, g->roughness, d.N, hs);
-  if (fg.tex_c) fr::launch_fix_to_float(fg.tex_c, g->tex_diffuse, (int)(3 * MM), hs);
-  if (fg.tex_s) fr::launch_fix_to_float(fg.tex_s, g->tex_specular, (int)(3 * MM), hs);
-  if (fg.tex_r) fr::launch_fix_to_float(fg.tex_r, g->tex_roughness, (int)MM, hs);
-  if (g->cam) fr::launch_fix_to_float(acc_cam, g->cam, 12, hs);
+  if (g->verts) fr::launch_fix_to_float(acc_v, g->verts, 3 * d.N, hs, gmax);
+  if (fg.diffuse) fr::launch_fix_to_float(acc_c, g->diffuse, 3 * d.N, hs, gmax);
+  if (fg.specular) fr::launch_fix_to_float(acc_s, g->specular, 3 * d.N, hs, gmax);
+  if (fg.roughness) fr::launch_fix_to_float(acc_r, g->roughness, d.N, hs, gmax);
+  if (fg.tex_c) fr::launch_fix_to_float(fg.tex_c, g->tex_diffuse, (int)(3 * MM), hs, gmax);
+  if (fg.tex_s) fr::launch_fix_to_float(fg.tex_s, g->tex_specular, (int)(3 * MM), hs, gmax);
+  if (fg.tex_r) fr::launch_fix_to_float(fg.tex_r, g->tex_roughness, (int)MM, hs, gmax);
+  if (g->cam) fr::launch_fix_to_float(acc_cam, g->cam, 12, hs, gmax);
   FR_HIP(m->ctx, hipGetLastError());
   return FR_OK;
 }
@@ -708,7 +714,7 @@ int fr_shadow_edges(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, cons
   WsState st;
   if ((rc = ws_open(m, s, o, &base, &st)) != FR_OK) return rc;
   const size_t pb = ws_prim_bytes(s), lb = ws_light_bytes(s), roff = pb + lb + st.vis_bytes;
-  const size_t N = m->d.N, L = s->n_lights, nacc = 3 * N + 9 * L + 12;
+  const size_t N = m->d.N, L = s->n_lights, nacc = 3 * N + 9 * L + 13;
   if ((rc = ws_need(m, o, roff + ws_se_region(m->d, s))) != FR_OK) return rc;
   // the hits and any kept masks stay as they are (this call traces its own camera rays)
   ws_store(m, base, st);
@@ -717,7 +723,9 @@ int fr_shadow_edges(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, cons
   a.lights = lights;
   fr::fix_t* acc = reinterpret_cast<fr::fix_t*>(base + roff);
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  uint32_t* gmax = reinterpret_cast<uint32_t*>(acc + nacc - 1);   // max |dE/dp|: the sums' scale
   fr::launch_zero_fix(acc, nacc, hs);
+  fr::launch_abs_max(d_dEdp, 3 * s->width * s->height, gmax, hs);
   fr::launch_light_setup(*s, lights, hs);
   fr::ShadowEdgeArgs e;
   e.nbr = m->d.face_nbr;
@@ -728,11 +736,12 @@ int fr_shadow_edges(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, cons
   e.gcam = g->cam ? acc + 3 * N + 9 * L : nullptr;
   e.dbg_rec = d_rec;
   e.dbg_flag = d_flag;
+  e.gmax = gmax;
   fr::launch_shadow_edges(a, e, hs);
   FR_HIP(m->ctx, hipGetLastError());
-  if (g->verts) fr::launch_fix_to_float(acc, g->verts, (int)(3 * N), hs);
-  if (g->light_geom) fr::launch_fix_to_float(acc + 3 * N, g->light_geom, (int)(9 * L), hs);
-  if (g->cam) fr::launch_fix_to_float(acc + 3 * N + 9 * L, g->cam, 12, hs);
+  if (g->verts) fr::launch_fix_to_float(acc, g->verts, (int)(3 * N), hs, gmax);
+  if (g->light_geom) fr::launch_fix_to_float(acc + 3 * N, g->light_geom, (int)(9 * L), hs, gmax);
+  if (g->cam) fr::launch_fix_to_float(acc + 3 * N + 9 * L, g->cam, 12, hs, gmax);
   FR_HIP(m->ctx, hipGetLastError());
   return FR_OK;
 }
@@ -1013,6 +1022,7 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   J.ea.th = std::tan(0.5 * (double)d->fov_y);
   J.ea.aspect = (double)d->width / (double)d->height;
   J.ea.dEdp = J.dEdp; J.ea.gverts = md_.acc; J.ea.gcam = nullptr; J.ea.dbg_rec = nullptr; J.ea.dbg_flag = nullptr;
+  J.ea.gmax = nullptr;   // the batch's dE/dp is the photometric loss's (smoothed) sign image, within [-1, 1]: no scale
   // shadow-edge term: vertex gradients only (the batch optimises no light geometry or camera)
   J.se = fr::ShadowEdgeArgs{};
   J.se.nbr = md_.face_nbr;

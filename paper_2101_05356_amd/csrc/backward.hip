@@ -86,7 +86,7 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
     const PixelSample ps = pixel_sample(a, tile, lane);
     float gbar[3] = {0.0f, 0.0f, 0.0f};
     if (ps.valid) {
-      const float inv = 1.0f / (float)a.S;
+      const float inv = grad_scale(a.gmax) / (float)a.S;   // s a power of two: exactly s times 1 / S
       gbar[0] = dEdp[3 * ps.pid] * inv; gbar[1] = dEdp[3 * ps.pid + 1] * inv; gbar[2] = dEdp[3 * ps.pid + 2] * inv;
     }
     const bool want = ps.valid && (gbar[0] != 0.0f || gbar[1] != 0.0f || gbar[2] != 0.0f);
@@ -475,7 +475,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // coefficients'.
 __device__ __forceinline__ void slots_reduce_block(const fix_t* __restrict__ slots, int nl, int L,
                                                    float* __restrict__ glight, float* __restrict__ grad,
-                                                   float* __restrict__ gcam, float* __restrict__ gsh, int bid) {
+                                                   float* __restrict__ gcam, float* __restrict__ gsh, int bid,
+                                                   const uint32_t* gmax = nullptr) {
   const int i = bid;   // one block per value
   __shared__ fix_t red[256];
   fix_t acc = 0;
@@ -487,7 +488,7 @@ __device__ __forceinline__ void slots_reduce_block(const fix_t* __restrict__ slo
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
-  const float v = (float)from_fix(red[0]);
+  const float v = (float)(from_fix(red[0]) / (double)grad_scale(gmax));
   if (i < 12 * L) {
     const int j = i / 12, k = i % 12;
     if (k < 9) { if (glight) glight[9 * j + k] += v; }
@@ -501,8 +502,9 @@ __device__ __forceinline__ void slots_reduce_block(const fix_t* __restrict__ slo
 
 __global__ __launch_bounds__(256) void k_slots_reduce(const fix_t* __restrict__ slots, int nl, int L,
                                                       float* __restrict__ glight, float* __restrict__ grad,
-                                                      float* __restrict__ gcam, float* __restrict__ gsh) {
-  slots_reduce_block(slots, nl, L, glight, grad, gcam, gsh, blockIdx.x);
+                                                      float* __restrict__ gcam, float* __restrict__ gsh,
+                                                      const uint32_t* gmax) {
+  slots_reduce_block(slots, nl, L, glight, grad, gcam, gsh, blockIdx.x, gmax);
 }
 
 // `slots` holds kSlots * (12 min(L, 128) + 12) accumulators (the caller sizes
@@ -541,7 +543,8 @@ void launch_render_backward(const RenderArgs& a, const float* dEdp, const FixGra
     if (e1 && g0 + kBwdMaxLights >= a.L) (void)hipEventRecord(e1, st);
     hipLaunchKernelGGL(k_slots_reduce, dim3(nl), dim3(256), 0, st, slots, nl, ag.L,
                        g.light_geom ? g.light_geom + (size_t)9 * g0 : nullptr,
-                       g.light_rad ? g.light_rad + (size_t)3 * g0 : nullptr, g.cam, ag.sh_bands > 0 ? g.sh : nullptr);
+                       g.light_rad ? g.light_rad + (size_t)3 * g0 : nullptr, g.cam, ag.sh_bands > 0 ? g.sh : nullptr,
+                       a.gmax);
   }
 }
 

@@ -306,7 +306,7 @@ __device__ __forceinline__ void edge_samples_block(const RenderArgs& a, const Ed
   if (active) {
     const float dl = (Sm.x - Sp.x) * e.dEdp[3 * pid] + (Sm.y - Sp.y) * e.dEdp[3 * pid + 1] +
                      (Sm.z - Sp.z) * e.dEdp[3 * pid + 2];
-    const float wgt = (float)(ltot / (double)e.n_samples) * dl;
+    const float wgt = (float)(ltot / (double)e.n_samples) * (dl * grad_scale(e.gmax));
     if (wgt != 0.0f) {
       // film velocity of X(w) = (1 - w) A + w B, w perspective-correct
       const float w = (float)(((double)u1 / pbz) / ((1.0 - (double)u1) / paz + (double)u1 / pbz));
@@ -352,6 +352,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 
 void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samples, fix_t* gverts, fix_t* gcam,
                   int32_t* dbg_rec, uint8_t* dbg_flag, double tan_half, hipStream_t st) {
+  // the edge samples read dE/dp under the same scale as the interior adjoint (a.gmax)
   hipLaunchKernelGGL(k_face_front, dim3((m.F + 255) / 256), dim3(256), 0, st, a.verts, m.tris, m.F, a.cam,
                      m.face_front);
   const double aspect = (double)a.W / (double)a.H;
@@ -362,7 +363,7 @@ void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samp
   hipLaunchKernelGGL(k_edge_scan_add, dim3(tiles), dim3(256), 0, st, m.edge_cdf, m.E, m.scan_part);
   EdgeArgs e;
   e.edges = m.edges; e.cdf = m.edge_cdf; e.E = m.E; e.n_samples = n_samples;
-  e.th = tan_half; e.aspect = aspect; e.dEdp = dEdp; e.gverts = gverts; e.gcam = gcam;
+  e.th = tan_half; e.aspect = aspect; e.dEdp = dEdp; e.gmax = a.gmax; e.gverts = gverts; e.gcam = gcam;
   e.dbg_rec = dbg_rec; e.dbg_flag = dbg_flag;
   edge_groups(a.L, n_samples, e);
   const int blocks = e.bx * e.n_groups;

@@ -47,6 +47,21 @@ __device__ __forceinline__ void fix_add_d(fix_t* p, double v) {
 }
 __host__ __device__ __forceinline__ double from_fix(fix_t a) { return (double)(long long)a * (1.0 / kFixOne); }
 
+// The quantum 2^-32 is absolute, so a backward scales its input dE/dp by a
+// power of two s chosen from max |dE/dp| (the bits of that maximum, gathered
+// by k_abs_max): s = 1 when the maximum is at least 1 (the photometric
+// loss's own dE/dp, at most 1 per channel), else 2^-floor(log2 max) (at most
+// 2^60).  Every contribution then sits in the same range whatever the
+// caller's scale; the conversions to FP32 divide by s.  Scaling by a power
+// of two is exact, and s = 1 leaves every value as it was.  gmax null: s = 1.
+__device__ __forceinline__ float grad_scale(const uint32_t* gmax) {
+  if (!gmax) return 1.0f;
+  const uint32_t b = *gmax;
+  const int e = (int)((b >> 23) & 0xffu) - 127;   // floor(log2 max); -127 for 0 and subnormals
+  if (b == 0u || e >= 0) return 1.0f;
+  return ldexpf(1.0f, min(-e, 60));
+}
+
 // Fixed-point accumulators of the per-vertex gradients (each nullable).
 struct FixGrads {
   fix_t* verts;       // [N*3]
@@ -64,6 +79,7 @@ struct ShadowEdgeArgs {
   const int32_t* nbr;   // [F*3] face across edge k (tris[3f+k], tris[3f+(k+1)%3]) of face f, -1 if none
   int n_samples;
   const float* dEdp;    // [H*W*3]
+  const uint32_t* gmax; // bits of max |dE/dp| (grad_scale; nullable)
   fix_t* gverts;        // [N*3] fixed-point (nullable)
   fix_t* glight;        // [L*9] fixed-point p0, e1, e2 (nullable)
   fix_t* gcam;          // [12] fixed-point (nullable)
@@ -78,6 +94,7 @@ struct EdgeArgs {
   int E, n_samples;
   double th, aspect;
   const float* dEdp;
+  const uint32_t* gmax; // bits of max |dE/dp| (grad_scale; nullable)
   fix_t* gverts;        // [N*3] fixed-point
   fix_t* gcam;          // [12] fixed-point
   int32_t* dbg_rec;     // [n*4]: edge, pixel, hit-, hit+
@@ -178,6 +195,7 @@ struct RenderArgs {
   int lanes_per_pixel;    // min(S, 64)
   int lc, n_lchunks;      // lights per work item, light chunks per tile
   int shadow_traversal;   // forward: 0 wave packet, 1 per-lane walk
+  const uint32_t* gmax;   // adjoint: bits of max |dE/dp| (grad_scale; nullable)
   int light0;             // global index of lights[0] (> 0 in the adjoint's later light groups)
   // spherical-harmonics lighting: coefficients [B*B*3] (B = sh_bands, 0 =
   // none), A_l, and the basis normalisation per (l, m >= 0) at
@@ -215,7 +233,10 @@ int normals_blocks(int N);
 void launch_normals(MeshDev& m, const float* d_verts, hipStream_t st);
 void launch_normals_backward(MeshDev& m, const float* d_verts, const fix_t* acc_n, float* gn_tmp, fix_t* acc_v,
                              hipStream_t st);
-void launch_fix_to_float(const fix_t* acc, float* out, int n, hipStream_t st);   // out += acc
+// out += acc / grad_scale(gmax)
+void launch_fix_to_float(const fix_t* acc, float* out, int n, hipStream_t st, const uint32_t* gmax = nullptr);
+// *gmax = max(*gmax, bits of max |x[i]|) (the caller zeroes *gmax)
+void launch_abs_max(const float* x, int n, uint32_t* gmax, hipStream_t st);
 void launch_zero_fix(fix_t* p, size_t n, hipStream_t st);
 void launch_blend(const float* mean, const float* basis, const float* coef, int K, int M, float* out, hipStream_t st);
 void launch_blend_backward(const float* basis, const float* gout, int K, int M, float* gcoef, hipStream_t st);

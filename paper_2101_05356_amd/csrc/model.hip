@@ -153,17 +153,33 @@ void launch_normals_backward(MeshDev& m, const float* d_verts, const fix_t* acc_
 }
 
 __device__ __forceinline__ void fix_to_float_block(const fix_t* __restrict__ acc, float* __restrict__ out, int n,
-                                                   int bid) {
+                                                   int bid, const uint32_t* gmax = nullptr) {
   const int i = bid * 256 + threadIdx.x;
-  if (i < n) out[i] += (float)from_fix(acc[i]);
+  if (i < n) out[i] += (float)(from_fix(acc[i]) / (double)grad_scale(gmax));
 }
 
-__global__ __launch_bounds__(256) void k_fix_to_float(const fix_t* __restrict__ acc, float* __restrict__ out, int n) {
-  fix_to_float_block(acc, out, n, blockIdx.x);
+__global__ __launch_bounds__(256) void k_fix_to_float(const fix_t* __restrict__ acc, float* __restrict__ out, int n,
+                                                      const uint32_t* gmax) {
+  fix_to_float_block(acc, out, n, blockIdx.x, gmax);
 }
 
-void launch_fix_to_float(const fix_t* acc, float* out, int n, hipStream_t st) {
-  if (n > 0) hipLaunchKernelGGL(k_fix_to_float, dim3(cdiv(n, 256)), dim3(256), 0, st, acc, out, n);
+void launch_fix_to_float(const fix_t* acc, float* out, int n, hipStream_t st, const uint32_t* gmax) {
+  if (n > 0) hipLaunchKernelGGL(k_fix_to_float, dim3(cdiv(n, 256)), dim3(256), 0, st, acc, out, n, gmax);
+}
+
+// Maximum of |x| as float bits (non-negative floats order like their bits).
+__global__ __launch_bounds__(256) void k_abs_max(const float* __restrict__ x, int n, uint32_t* __restrict__ gmax) {
+  uint32_t m = 0u;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const float v = fabsf(x[i]);
+    if (v == v) m = max(m, __float_as_uint(v));   // NaN left out
+  }
+  for (int off = 32; off >= 1; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
+  if ((threadIdx.x & 63) == 0 && m != 0u) atomicMax(gmax, m);
+}
+
+void launch_abs_max(const float* x, int n, uint32_t* gmax, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_abs_max, dim3(std::min(cdiv(n, 256), 1024)), dim3(256), 0, st, x, n, gmax);
 }
 
 __global__ __launch_bounds__(256) void k_zero_fix(fix_t* p, size_t n) {

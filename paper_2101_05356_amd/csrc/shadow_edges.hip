@@ -135,7 +135,8 @@ __device__ __forceinline__ void shadow_edge_sample(const RenderArgs& a, const Sh
                                   pick_prob((uint64_t)max(j, 0), (uint64_t)a.L))
                          : 0.0;
   const float* g = e.dEdp + 3 * (size_t)pid;
-  const V3 gpix = valid ? V3{g[0], g[1], g[2]} : V3{0.0f, 0.0f, 0.0f};
+  const float gs = grad_scale(e.gmax);   // exact power of two; the conversions divide by it
+  const V3 gpix = valid ? V3{g[0] * gs, g[1] * gs, g[2] * gs} : V3{0.0f, 0.0f, 0.0f};
   int n_ok = 0;
   long long key = 0;
   D3 gx_tot = {0.0, 0.0, 0.0};

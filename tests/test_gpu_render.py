@@ -310,3 +310,38 @@ def test_per_lane_shadow_traversal_gives_the_packet_results(oracle_lib, textured
     from paper_2101_05356_amd import _lib
     with pytest.raises(_lib.FrError, match="shadow_traversal"):
         G.R.render_forward(m, ds, shadow_traversal=2)
+
+
+def test_fixed_point_sums_at_small_gradient_scales(oracle_lib):
+    """Every cross-wave gradient sum rounds each contribution to a multiple
+    of 2^-32 (an absolute quantum).  The library multiplies dE/dp by the
+    power of two that brings max |dE/dp| into [1, 2) when it is below 1 and
+    divides the sums by it again, so the quantum stays relative to the
+    gradient's size: with dE/dp scaled by 2^-k the gradients meet the parity
+    bar against the oracle's (scaled the same way, exactly) at every k, and
+    once the scale is active (k >= 6 here) they are the k = 6 results times
+    2^(6-k) bit for bit."""
+    import oracle
+    sc = scenes.patch_scene()
+    m, ds, img, hit, vis, mh, mv = _forward_parity(sc)
+    W, H = sc.camera.W, sc.camera.H
+    dEdp = np.random.default_rng(8).normal(size=(H * W, 3)).astype(np.float32)
+    go = oracle.grad(sc, mh, mv, dEdp.astype(np.float64))
+    pairs = [("verts", "verts"), ("diffuse", "diffuse"), ("roughness", "rough"), ("light_rad", "rad"),
+             ("cam", "cam"), ("light_geom", "light")]
+    ref6 = None
+    for k in (0, 6, 12, 18, 24):
+        s = 2.0 ** -k
+        g = G.R.render_backward(m, ds, torch.tensor((dEdp * np.float32(s)).reshape(H, W, 3)).cuda(),   # exact
+                                groups=tuple(p[0] for p in pairs))
+        torch.cuda.synchronize()
+        res = {gk: G.grad_tol_ok(G.to_np(g[gk]), go[ok_] * s) for gk, ok_ in pairs}
+        _note(f"dE/dp x 2^-{k}: " + ", ".join(f"{gk} l2 {r[1]:.2e} worst {r[2]:.2e}" for gk, r in res.items()))
+        for gk, r in res.items():
+            assert r[0], (k, gk, r)
+        if k >= 6:
+            up = {gk: G.to_np(g[gk]).astype(np.float64) * 2.0 ** (k - 6) for gk, _ in pairs}
+            if ref6 is None:
+                ref6 = up
+            for gk in up:
+                np.testing.assert_array_equal(up[gk], ref6[gk], err_msg=f"{gk} at k = {k}")
