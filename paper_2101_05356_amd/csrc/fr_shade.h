@@ -367,7 +367,7 @@ __device__ __forceinline__ uint32_t shadow_mask(const RenderArgs& a, int j0, int
     const bool lit = shaded && light_point(Lj, unit24(r.x), unit24(r.y), fr, ls);
     Ray sr;
     sr.o = fr.x; sr.d = ls.l; sr.tmin = kShadowTmin; sr.tmax = ls.dist;
-    ray_setup(sr);
+    ray_setup<!DUMP>(sr);   // production: hardware 1/d (same answers; the dumps keep the division)
     HitState sh;
     sh.tamb = 3.4e38f;
     bool occ = false;
