@@ -92,12 +92,13 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
     const bool want = ps.valid && (gbar[0] != 0.0f || gbar[1] != 0.0f || gbar[2] != 0.0f);
     for (int chunk = 0; chunk < a.chunks; ++chunk) {
       const int s = ps.s0 + chunk * 64;
-      Sample sm;
-      camera_sample(a, ps, s, sm);
       const size_t rs = (size_t)ps.pid * a.S + s;
       double bd0[3] = {1.0, 0.0, 0.0};
       PrimHit ph = {-1, 0.0f, 0.0, 0.0};
       if (want) ph = load_prim(a, rs, bd0);
+      // the camera ray (for the view direction) only where a sample has a shading point
+      Sample sm;
+      if (ballot(want && ph.id >= 0)) camera_sample(a, ps, s, sm);
       Frame fr = {};
       const bool shaded = want && ph.id >= 0 && shading_frame<TEX>(a, sm, ph.id, ph.t, bd0, fr);
       // sample-level adjoint accumulators
