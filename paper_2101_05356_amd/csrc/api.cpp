@@ -66,6 +66,11 @@ struct fr_mesh {
   std::mutex mu;          // guards ws
   std::map<const void*, WsState> ws;   // keyed by workspace address
   std::vector<int32_t> h_edges, h_edge_faces;
+  // the backward's second stream: the boundary term runs there beside the
+  // interior adjoint (created by the first backward; default priority)
+  std::mutex fork_mu;     // one backward's fork/join enqueue at a time
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -405,6 +410,9 @@ int fr_mesh_destroy(fr_mesh* m) {
                   d.scan_part, d.acc, d.nodes4, d.n4_src, d.top_nodes, d.top_level_off};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (m->aux) (void)hipStreamDestroy(m->aux);   // released once its work is done
+  if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+  if (m->ev_join) (void)hipEventDestroy(m->ev_join);
   delete m;
   return FR_OK;
 }
@@ -674,6 +682,43 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
     a.vis_in = reinterpret_cast<const uint32_t*>(base + st.vis_off);
     a.vis_lc = st.vis.lc;
   }
+  // The primary-visibility term (Sec. 4 "Edge Sampling") needs only the zeroed
+  // accumulators, the geometry and dE/dp: it runs on the mesh's second stream
+  // beside the interior adjoint, both adding into the vertex accumulators with
+  // integer atomics (the sums do not depend on the order).  Serial on the
+  // caller's stream if that stream cannot be made.
+  const int ns = o->edge_samples < 0 ? s->width * s->height : o->edge_samples;
+  const bool with_edges = ns > 0 && (g->verts || g->cam || o->dbg_hit);
+  const auto edges_on = [&](hipStream_t es) {
+    fr::launch_edges(d, a, d_dEdp, ns, g->verts ? acc_v : nullptr, g->cam ? acc_cam : nullptr, o->dbg_hit,
+                     o->dbg_pflag, std::tan(0.5 * (double)s->fov_y), es);
+  };
+  std::unique_lock<std::mutex> fork(m->fork_mu, std::defer_lock);
+  bool forked = false;
+  if (with_edges) {
+    fork.lock();
+    if (!m->aux) {
+      hipStream_t x = nullptr;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) == hipSuccess &&
+          hipEventCreateWithFlags(&e0, hipEventDisableTiming) == hipSuccess &&
+          hipEventCreateWithFlags(&e1, hipEventDisableTiming) == hipSuccess) {
+        m->aux = x; m->ev_fork = e0; m->ev_join = e1;
+      } else {
+        if (x) (void)hipStreamDestroy(x);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipGetLastError();
+      }
+    }
+    if (m->aux) {
+      FR_HIP(m->ctx, hipEventRecord(m->ev_fork, hs));
+      FR_HIP(m->ctx, hipStreamWaitEvent(m->aux, m->ev_fork, 0));
+      edges_on(m->aux);
+      FR_HIP(m->ctx, hipEventRecord(m->ev_join, m->aux));
+      forked = true;
+    }
+  }
   fr::launch_render_backward(a, d_dEdp, fg, w.slots, *g, hs, static_cast<hipEvent_t>(o->ev_kernel_begin),
                              static_cast<hipEvent_t>(o->ev_kernel_end), !reuse);
   FR_HIP(m->ctx, hipGetLastError());
@@ -684,10 +729,9 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
   ws_store(m, base, now);
   if (g->normals) fr::launch_fix_to_float(acc_n, g->normals, 3 * d.N, hs, gmax);
   if (g->verts) fr::launch_normals_backward(d, s->verts, acc_n, d.gnorm, acc_v, hs);
-  const int ns = o->edge_samples < 0 ? s->width * s->height : o->edge_samples;
-  if (ns > 0 && (g->verts || g->cam || o->dbg_hit))
-    fr::launch_edges(d, a, d_dEdp, ns, g->verts ? acc_v : nullptr, g->cam ? acc_cam : nullptr, o->dbg_hit,
-                     o->dbg_pflag, std::tan(0.5 * (double)s->fov_y), hs);
+  if (with_edges && !forked) edges_on(hs);
+  if (forked) FR_HIP(m->ctx, hipStreamWaitEvent(hs, m->ev_join, 0));
+  if (fork.owns_lock()) fork.unlock();
   if (g->verts) fr::launch_fix_to_float(acc_v, g->verts, 3 * d.N, hs, gmax);
   if (fg.diffuse) fr::launch_fix_to_float(acc_c, g->diffuse, 3 * d.N, hs, gmax);
   if (fg.specular) fr::launch_fix_to_float(acc_s, g->specular, 3 * d.N, hs, gmax);

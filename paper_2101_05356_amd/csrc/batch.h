@@ -44,7 +44,11 @@ struct Batch {
   std::vector<int> total;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // second stream of the step: the boundary terms beside the interior adjoint
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~Batch();
+  void make_aux();
   int upload(hipStream_t st);
   void launch_step(hipStream_t st);
   int step(hipStream_t st, int n, bool use_graph);

@@ -195,6 +195,27 @@ Batch::~Batch() {
   if (graph) (void)hipGraphDestroy(graph);
   if (d_jobs) (void)hipFree(d_jobs);
   if (d_prefix) (void)hipFree(d_prefix);
+  if (aux) (void)hipStreamDestroy(aux);
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+}
+
+// The step's second stream and its fork/join events (default priority); left
+// null (the step then runs serially) if any cannot be made.
+void Batch::make_aux() {
+  if (aux) return;
+  hipStream_t x = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) == hipSuccess &&
+      hipEventCreateWithFlags(&e0, hipEventDisableTiming) == hipSuccess &&
+      hipEventCreateWithFlags(&e1, hipEventDisableTiming) == hipSuccess) {
+    aux = x; ev_fork = e0; ev_join = e1;
+    return;
+  }
+  if (x) (void)hipStreamDestroy(x);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipGetLastError();
 }
 
 int Batch::upload(hipStream_t st) {
@@ -257,16 +278,28 @@ void Batch::launch_step(hipStream_t st) {
   FR_LAUNCH(kb_loss_final, S_LOSS_FINAL, 256, 0);
   FR_LAUNCH(kb_smooth_adjoint, S_SMOOTH_ADJ, 256, 0);
   FR_LAUNCH(kb_zero_grads, S_ZERO_GRADS, 256, 0);
+  // the boundary terms on the second stream, beside the interior adjoint: both
+  // need only the zeroed accumulators, the geometry and dE/dp, and add into the
+  // vertex accumulators with integer atomics (order-free sums)
+  const bool fork = aux && hipEventRecord(ev_fork, st) == hipSuccess &&
+                    hipStreamWaitEvent(aux, ev_fork, 0) == hipSuccess;
+  {
+    const hipStream_t main_st = st;
+    st = fork ? aux : main_st;
+    FR_LAUNCH(kb_face_front, S_FACE_FRONT, 256, 0);
+    FR_LAUNCH(kb_edge_len, S_EDGE_LEN, 256, 0);
+    FR_LAUNCH(kb_edge_scan, S_EDGE_SCAN, 256, 0);
+    FR_LAUNCH(kb_edge_scan_add, S_EDGE_SCAN_ADD, 256, 0);
+    FR_LAUNCH(kb_edge_samples, S_EDGE_SAMPLES, 256, 0);
+    FR_LAUNCH(kb_shadow_edges, S_SHADOW_EDGES, 256, 0);
+    if (fork) (void)hipEventRecord(ev_join, aux);
+    st = main_st;
+  }
   FR_LAUNCH(kb_render_bwd, S_BWD, 256, max_nl * sizeof(fix_t) + kBwdPartBytes);
   FR_LAUNCH(kb_slots_reduce, S_SLOTS, 256, 0);
   FR_LAUNCH(kb_normals_bwd_project, S_NBWD_P, 256, 0);
   FR_LAUNCH(kb_normals_bwd_gather, S_NBWD_G, 256, 0);
-  FR_LAUNCH(kb_face_front, S_FACE_FRONT, 256, 0);
-  FR_LAUNCH(kb_edge_len, S_EDGE_LEN, 256, 0);
-  FR_LAUNCH(kb_edge_scan, S_EDGE_SCAN, 256, 0);
-  FR_LAUNCH(kb_edge_scan_add, S_EDGE_SCAN_ADD, 256, 0);
-  FR_LAUNCH(kb_edge_samples, S_EDGE_SAMPLES, 256, 0);
-  FR_LAUNCH(kb_shadow_edges, S_SHADOW_EDGES, 256, 0);
+  if (fork) (void)hipStreamWaitEvent(st, ev_join, 0);
   FR_LAUNCH(kb_fix_finalize, S_FIX_FINALIZE, 256, 0);
   FR_LAUNCH(kb_pose_bwd_v, S_POSE_BWD_V, 256, 0);
   FR_LAUNCH(kb_pose_bwd_p, S_POSE_BWD_P, 1024, 0);
@@ -279,6 +312,7 @@ void Batch::launch_step(hipStream_t st) {
 
 int Batch::step(hipStream_t st, int n, bool use_graph) {
   if (njobs_dev == 0) return FR_OK;
+  make_aux();
   if (!use_graph) {
     for (int i = 0; i < n; ++i) launch_step(st);
     return hipGetLastError() == hipSuccess ? FR_OK : FR_ERR_DEVICE;

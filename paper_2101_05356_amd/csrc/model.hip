@@ -126,8 +126,10 @@ __device__ __forceinline__ void normals_bwd_gather_block(const float* __restrict
   }
   acc = group8_sum(acc);
   if (i >= N || sub != 0) return;
-  // one lane owns vertex i: a plain read-modify-write of its accumulator
-  gv[3 * i] += to_fix_d(acc.x); gv[3 * i + 1] += to_fix_d(acc.y); gv[3 * i + 2] += to_fix_d(acc.z);
+  // one lane owns vertex i; atomic all the same: the primary-edge and
+  // shadow-edge terms may be adding into the same accumulators concurrently
+  atomicAdd(gv + 3 * i, to_fix_d(acc.x)); atomicAdd(gv + 3 * i + 1, to_fix_d(acc.y));
+  atomicAdd(gv + 3 * i + 2, to_fix_d(acc.z));
 }
 
 __global__ __launch_bounds__(256) void k_normals_bwd_gather(const float* __restrict__ v, const int32_t* __restrict__ tris,
@@ -167,19 +169,26 @@ void launch_fix_to_float(const fix_t* acc, float* out, int n, hipStream_t st, co
   if (n > 0) hipLaunchKernelGGL(k_fix_to_float, dim3(cdiv(n, 256)), dim3(256), 0, st, acc, out, n, gmax);
 }
 
-// Maximum of |x| as float bits (non-negative floats order like their bits).
+// Maximum of |x| as float bits (non-negative floats order like their bits):
+// a grid-stride pass, the block's maximum through LDS, one atomic per block.
 __global__ __launch_bounds__(256) void k_abs_max(const float* __restrict__ x, int n, uint32_t* __restrict__ gmax) {
+  __shared__ uint32_t wmax[4];
   uint32_t m = 0u;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const float v = fabsf(x[i]);
     if (v == v) m = max(m, __float_as_uint(v));   // NaN left out
   }
   for (int off = 32; off >= 1; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
-  if ((threadIdx.x & 63) == 0 && m != 0u) atomicMax(gmax, m);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+    if (m != 0u) atomicMax(gmax, m);
+  }
 }
 
 void launch_abs_max(const float* x, int n, uint32_t* gmax, hipStream_t st) {
-  if (n > 0) hipLaunchKernelGGL(k_abs_max, dim3(std::min(cdiv(n, 256), 1024)), dim3(256), 0, st, x, n, gmax);
+  if (n > 0) hipLaunchKernelGGL(k_abs_max, dim3(std::min(cdiv(n, 256 * 8), 256)), dim3(256), 0, st, x, n, gmax);
 }
 
 __global__ __launch_bounds__(256) void k_zero_fix(fix_t* p, size_t n) {
