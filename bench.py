@@ -8,7 +8,13 @@ edge-sampling boundary term, pose and blend adjoints, Adam.  Inputs are
 synthetic and resident in HBM before the timed region.
 
 Prints one JSON line (see the "metric" field).  The headline value is nominal
-forward rays per second of whole steps: W*H*spp*(1 + L) / step time.  The
+forward rays per second of whole steps: W*H*spp*(1 + L) / step time, the
+step being the library's native one (the face as a one-job batch, its launch
+sequence replayed from a hipGraph); the Python-driven step, one C-ABI call
+per stage, is timed first ("eager": its kernel events give the roofline's
+kernel times) and "graph_vs_eager" checks that both give the same losses bit
+for bit.  In both, the primary-edge term runs on a second stream beside the
+interior adjoint; the adjoint's roofline time is taken without it.  The
 same line carries the roofline of the dominant kernel, traversal statistics,
 the forward with the per-lane shadow-ray walk beside the wave packet
 ("shadow_traversal"), the adjoint that traces its own decisions
@@ -287,9 +293,44 @@ def settle_clocks(rc, seconds):
         torch.cuda.synchronize()
 
 
-def isolated_adjoint_ms(rc, n):
-    """Mean duration of the interior adjoint kernel (the step's, with the
-    forward's decisions) over n calls with no boundary term beside it."""
+def graph_step_ms(ctx, mt, job, steps, warmup):
+    """The face step as the library's native step: the job alone in a batch
+    (fr_batch_step), its launch sequence captured once into a hipGraph and
+    replayed.  Returns (ms per step, seconds for `steps` steps)."""
+    import dataclasses
+    import torch
+    from paper_2101_05356_amd import recon
+    b = recon.Batch(recon.Model(ctx, mt))
+    b.add(dataclasses.replace(job, hist_cap=1))
+    b.step(max(warmup, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return 1e3 * dt / steps, dt
+
+
+def graph_matches_eager(ctx, W, S, L, ns, n=10):
+    """Losses of n steps from the same start: the Python-driven step against
+    the replayed native step (bit for bit)."""
+    import dataclasses
+    import torch
+    from paper_2101_05356_amd import recon
+    mt, rc = make_c2(ctx, W, S, L, ns)
+    le = [float(rc.step().item()) for _ in range(n)]
+    b = recon.Batch(recon.Model(ctx, mt))
+    jid = b.add(dataclasses.replace(rc.job, hist_cap=n))
+    b.step(n)
+    torch.cuda.synchronize()
+    lb = [float(x) for x in b.read(jid)["losses"]]
+    return {"steps": n, "losses_equal": le == lb, "loss_first_last": [le[0], le[-1]]}
+
+
+def isolated_adjoint_ms(rc, n, reuse=True):
+    """Mean duration of the interior adjoint kernel (the step's: with the
+    forward's decisions, or tracing them again when `reuse` is False) over n
+    calls with no boundary term beside it."""
     import torch
     from paper_2101_05356_amd import render as R
     sc = rc.scene()
@@ -299,7 +340,7 @@ def isolated_adjoint_ms(rc, n):
     for _ in range(n):
         pair = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
         R.render_backward(rc.mesh, sc, dEdp, rc.job.brdf_variant, edge_samples=0,
-                          groups=("verts", "diffuse", "light_rad"), verts=rc.v_w, events=pair, reuse_forward=True)
+                          groups=("verts", "diffuse", "light_rad"), verts=rc.v_w, events=pair, reuse_forward=reuse)
         ev.append(pair)
     torch.cuda.synchronize()
     return float(np.mean([a.elapsed_time(b) for a, b in ev]))
@@ -752,13 +793,24 @@ def main():
     # (--profile-only leaves it out, so that its trace holds the step's kernels only)
     bwd_ms = bwd_step_ms if args.profile_only else isolated_adjoint_ms(rc, args.steps)
     nominal = W * H * S * (1 + L)
+    eager = {"ms_per_step": ms_step, "rays_per_s": nominal * args.steps / dt,
+             "path": "Python-driven step: one C-ABI call per stage, kernels launched from the host"}
+    path = "eager"
+    if not args.profile_only:
+        # the headline: the same step through the library's native step (a
+        # one-job batch), replayed from a hipGraph
+        ms_step, dt = graph_step_ms(ctx, mt, rc.job, args.steps, args.warmup)
+        path = "graph"
     value = nominal * args.steps / dt
     out = {"metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{W}x{H} face: 28,002-vertex / 56,000-triangle morphable mesh, {S} spp, {L} "
                                   f"area lights, blend+pose+refit+render+loss+backward with {ns} edge samples+Adam",
-                      "global_batch": 1, "seq_len": W * H, "parallelism": "single GPU"},
+                      "global_batch": 1, "seq_len": W * H, "parallelism": "single GPU",
+                      "step": "one-job fr_batch_step replayed from a hipGraph" if path == "graph"
+                      else "Python-driven step"},
+           "eager": eager,
            "render_fwd_kernel_ms": fwd_ms, "render_bwd_kernel_ms": bwd_ms,
            "render_bwd_kernel_ms_in_step": bwd_step_ms, "loss": float(E.item())}
     if not args.profile_only:
@@ -790,6 +842,7 @@ def main():
         out["rays_cast_per_s"] = (W * H * S + sh_rays) * args.steps / dt
         out["camera_samples_shaded"] = stats[10]
         out["shadow_traversal"] = traversal_compare(rc)
+        out["graph_vs_eager"] = graph_matches_eager(ctx, W, S, L, args.edge_samples)
     if args.recompute_steps > 0:
         # the same step with an adjoint that traces its camera and shadow rays again
         evr = []
@@ -801,9 +854,11 @@ def main():
             evr.append(pair)
         torch.cuda.synchronize()
         dtr = time.perf_counter() - t0
-        bwd_r = float(np.mean([p["bwd"][0].elapsed_time(p["bwd"][1]) for p in evr]))
+        bwd_r_step = float(np.mean([p["bwd"][0].elapsed_time(p["bwd"][1]) for p in evr]))
+        bwd_r = bwd_r_step if args.profile_only else isolated_adjoint_ms(rc, args.recompute_steps, reuse=False)
         rec = {"steps": args.recompute_steps, "ms_per_step": 1e3 * dtr / args.recompute_steps,
                "rays_per_s": nominal * args.recompute_steps / dtr, "render_bwd_kernel_ms": bwd_r,
+               "render_bwd_kernel_ms_in_step": bwd_r_step,
                "adjoint": "k_render_bwd: camera and shadow rays traced again from the same counters"}
         if not args.profile_only:
             ops_r = algorithmic_ops(stats, W, H, S, L, backward=True, traced=True)
