@@ -57,7 +57,7 @@ FR_BATCH_KERNEL(kb_gather4, 256) { FR_JOB_PROLOGUE gather4_block(J.nodes, J.n4_s
 FR_BATCH_KERNEL(kb_light_setup, 256) {
   FR_JOB_PROLOGUE light_setup_block(J.lp0, J.le1, J.le2, J.param + J.off_rad, J.lshape, J.ra.L, J.lights, lb);
 }
-FR_BATCH_KERNEL(kb_primary, 256) { FR_JOB_PROLOGUE primary_block<false>(J.ra, lb); }
+__attribute__((amdgpu_waves_per_eu(8))) FR_BATCH_KERNEL(kb_primary, 256) { FR_JOB_PROLOGUE primary_block<false>(J.ra, lb); }
 __attribute__((amdgpu_waves_per_eu(8))) FR_BATCH_KERNEL(kb_render_fwd, 256) {
   FR_JOB_PROLOGUE render_fwd_block<false, false>(J.ra, J.ra.n_lchunks > 1 ? nullptr : J.image, lb);
 }
@@ -258,17 +258,42 @@ int Batch::upload(hipStream_t st) {
 void Batch::launch_step(hipStream_t st) {
   const int nj = njobs_dev;
   auto P = [&](int s) { return d_prefix + (size_t)s * (nj + 1); };
+  // Independent stages go to the second stream, forked from and joined back
+  // to the step's stream by events (in a captured graph: parallel branches).
+  // The same two events serve every fork/join pair: a wait binds to the
+  // record enqueued before it.
+  const hipStream_t main_st = st;
+  const auto fork = [&]() {
+    const bool f = aux && hipEventRecord(ev_fork, main_st) == hipSuccess &&
+                   hipStreamWaitEvent(aux, ev_fork, 0) == hipSuccess;
+    st = f ? aux : main_st;
+    return f;
+  };
+  const auto join = [&](bool f) {
+    if (f) {
+      (void)hipEventRecord(ev_join, aux);
+      (void)hipStreamWaitEvent(main_st, ev_join, 0);
+    }
+    st = main_st;
+  };
 #define FR_LAUNCH(kernel, stage, threads, lds)                                                      \
   if (total[stage] > 0)                                                                              \
     hipLaunchKernelGGL(kernel, dim3(total[stage]), dim3(threads), lds, st, d_jobs, P(stage), nj);
-  FR_LAUNCH(kb_blend_geo, S_BLEND_GEO, 256, 0);
+  // beside the geometry chain: the albedo blend, the light records and the
+  // zeroing of this step's gradient accumulators (nothing reads them before
+  // the adjoint)
+  bool f = fork();
   FR_LAUNCH(kb_blend_alb, S_BLEND_ALB, 256, 0);
+  FR_LAUNCH(kb_light_setup, S_LIGHTS, 256, 0);
+  FR_LAUNCH(kb_zero_grads, S_ZERO_GRADS, 256, 0);
+  st = main_st;
+  FR_LAUNCH(kb_blend_geo, S_BLEND_GEO, 256, 0);
   FR_LAUNCH(kb_pose, S_POSE, 256, 0);
   FR_LAUNCH(kb_normals, S_NORMALS, 256, 0);
   FR_LAUNCH(kb_refit, S_REFIT, kRefitTile, 0);
   FR_LAUNCH(kb_refit_top, S_REFIT_TOP, 1024, 0);
   FR_LAUNCH(kb_gather4, S_GATHER4, 256, 0);
-  FR_LAUNCH(kb_light_setup, S_LIGHTS, 256, 0);
+  join(f);
   // camera-ray hits of every sample, read by the forward and again by the
   // adjoint (nothing between them moves the geometry or the counters)
   FR_LAUNCH(kb_primary, S_PRIM, 256, 0);
@@ -277,29 +302,24 @@ void Batch::launch_step(hipStream_t st) {
   FR_LAUNCH(kb_loss, S_LOSS, 256, 0);
   FR_LAUNCH(kb_loss_final, S_LOSS_FINAL, 256, 0);
   FR_LAUNCH(kb_smooth_adjoint, S_SMOOTH_ADJ, 256, 0);
-  FR_LAUNCH(kb_zero_grads, S_ZERO_GRADS, 256, 0);
-  // the boundary terms on the second stream, beside the interior adjoint: both
-  // need only the zeroed accumulators, the geometry and dE/dp, and add into the
-  // vertex accumulators with integer atomics (order-free sums)
-  const bool fork = aux && hipEventRecord(ev_fork, st) == hipSuccess &&
-                    hipStreamWaitEvent(aux, ev_fork, 0) == hipSuccess;
-  {
-    const hipStream_t main_st = st;
-    st = fork ? aux : main_st;
-    FR_LAUNCH(kb_face_front, S_FACE_FRONT, 256, 0);
-    FR_LAUNCH(kb_edge_len, S_EDGE_LEN, 256, 0);
-    FR_LAUNCH(kb_edge_scan, S_EDGE_SCAN, 256, 0);
-    FR_LAUNCH(kb_edge_scan_add, S_EDGE_SCAN_ADD, 256, 0);
-    FR_LAUNCH(kb_edge_samples, S_EDGE_SAMPLES, 256, 0);
-    FR_LAUNCH(kb_shadow_edges, S_SHADOW_EDGES, 256, 0);
-    if (fork) (void)hipEventRecord(ev_join, aux);
-    st = main_st;
-  }
+  // the boundary terms beside the interior adjoint: both need only the zeroed
+  // accumulators, the geometry and dE/dp, and add into the vertex
+  // accumulators with integer atomics (order-free sums)
+  f = fork();
+  FR_LAUNCH(kb_face_front, S_FACE_FRONT, 256, 0);
+  FR_LAUNCH(kb_edge_len, S_EDGE_LEN, 256, 0);
+  FR_LAUNCH(kb_edge_scan, S_EDGE_SCAN, 256, 0);
+  FR_LAUNCH(kb_edge_scan_add, S_EDGE_SCAN_ADD, 256, 0);
+  FR_LAUNCH(kb_edge_samples, S_EDGE_SAMPLES, 256, 0);
+  FR_LAUNCH(kb_shadow_edges, S_SHADOW_EDGES, 256, 0);
+  st = main_st;
   FR_LAUNCH(kb_render_bwd, S_BWD, 256, max_nl * sizeof(fix_t) + kBwdPartBytes);
   FR_LAUNCH(kb_slots_reduce, S_SLOTS, 256, 0);
   FR_LAUNCH(kb_normals_bwd_project, S_NBWD_P, 256, 0);
   FR_LAUNCH(kb_normals_bwd_gather, S_NBWD_G, 256, 0);
-  if (fork) (void)hipStreamWaitEvent(st, ev_join, 0);
+  join(f);
+  // (each cross-stream wait costs ~10 us even when already met, so the short
+  // stages after the adjoint stay in one chain)
   FR_LAUNCH(kb_fix_finalize, S_FIX_FINALIZE, 256, 0);
   FR_LAUNCH(kb_pose_bwd_v, S_POSE_BWD_V, 256, 0);
   FR_LAUNCH(kb_pose_bwd_p, S_POSE_BWD_P, 1024, 0);
