@@ -342,7 +342,15 @@ int fr_map_regularizers(const float* d_c, const float* d_s, const float* d_r, co
  * Any number of lights: more than 128 are taken in groups of 128, one
  * adjoint and one boundary-term launch per group (the sample-level chain
  * is linear in the summed per-light adjoints, so the groups' chains add).
- * Scratch and the forward's decisions come from opts->workspace. */
+ * Scratch and the forward's decisions come from opts->workspace.
+ * Streams: the boundary term runs on a second stream that the mesh creates
+ * at its first backward (default priority; destroyed with the mesh), forked
+ * from `stream` after the accumulators are zeroed and joined back before
+ * the conversions, by events; the call stays ordered on `stream` (also
+ * under stream capture, where the fork and join are captured as graph
+ * edges), and backward calls on one mesh from several threads serialise
+ * their enqueue.  The gradients are fixed-point integer sums, so they do
+ * not depend on how the two streams interleave. */
 int fr_render_backward(fr_mesh* mesh, const fr_scene* scene, const fr_render_opts* opts, const float* d_dEdp,
                        fr_grads* grads, fr_stream stream);
 
@@ -501,6 +509,13 @@ int fr_batch_add(fr_batch* batch, const fr_job_desc* desc, int32_t* job_id, fr_s
 /* Free a job (synchronises the device first). */
 int fr_batch_remove(fr_batch* batch, int32_t job_id);
 int32_t fr_batch_size(const fr_batch* batch);
+/* n_steps optimisation steps of every job (Sec. 4: blend, pose, refit,
+ * render, loss, adjoint with its boundary terms, pose and blend adjoints,
+ * Adam), one launch per stage for all jobs.  use_graph != 0: the launch
+ * sequence is captured into a hipGraph at the first step after the job set
+ * changes and replayed.  Part of each step runs on a second stream of the
+ * batch (default priority), forked from and joined back to `stream` by
+ * events, so the call stays ordered on `stream`.  Asynchronous. */
 int fr_batch_step(fr_batch* batch, int32_t n_steps, int32_t use_graph, fr_stream stream);
 /* Copy a job's state to host buffers (each nullable): parameters [n_param],
  * gradient of the last step [n_param], per-step losses [hist_cap] (loss of the
