@@ -142,6 +142,21 @@ def test_patch_backward_parity(oracle_lib, variant):
     _backward_parity(sc, variant=variant)
 
 
+def test_lights_inside_the_mesh_bounds(oracle_lib):
+    """Two small lights placed inside the patch's bounding boxes, just above
+    its surface, beside lights outside them: the production shadow walk keeps
+    its exit clamp for packets whose rays end inside a box of the tree (its
+    clamp-free walk needs every ray to leave the root's boxes first), so
+    both walks run.  The production forward equals the dump build bit for
+    bit, the decisions and pixels match the oracle, and so does the adjoint
+    that traces its own shadow rays."""
+    sc = scenes.patch_scene(W=48, H=40, spp=4, n_lights=4)
+    inside = scenes.square_lights(np.array([[0.2, 0.2, 0.2], [-0.25, 0.1, 0.15]]), 0.05, np.full((2, 3), 2.0))
+    lights = scenes.Lights(*(np.ascontiguousarray(np.concatenate([getattr(sc.lights, f), getattr(inside, f)]))
+                             for f in ("p0", "e1", "e2", "rad", "shape")))
+    _backward_parity(dataclasses.replace(sc, lights=lights))
+
+
 def test_face_backward_parity_subset(oracle_lib):
     sc = scenes.face_render_scene()
     px = scenes.random_pixel_subset(np.random.default_rng(5), sc.camera.W, sc.camera.H, 32)
