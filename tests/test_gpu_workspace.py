@@ -132,3 +132,35 @@ def test_workspace_errors(oracle_lib):
     # a workspace of exactly the queried size works
     G.R.render_forward(m, ds, workspace=big[:n])
     torch.cuda.synchronize()
+
+
+def test_backward_with_its_boundary_term_under_stream_capture(oracle_lib):
+    """The backward runs its boundary term on the mesh's second stream,
+    forked from the caller's stream and joined back by events.  Captured into
+    a graph (torch.cuda.graph), the fork and the join become graph edges:
+    every replay gives the eager call's gradients bit for bit."""
+    sc = scenes.face_render_scene(W=64, H=64, spp=4, n_lights=12)
+    m, ds = G.gpu_setup(sc)
+    ws = torch.empty(m.workspace_bytes(ds, keep_shadows=True), dtype=torch.uint8, device="cuda")
+    G.R.render_forward(m, ds, keep_shadows=True, workspace=ws)
+    dEdp = torch.tensor(np.random.default_rng(4).normal(size=(64, 64, 3)).astype(np.float32)).cuda()
+    groups = ("verts", "cam", "diffuse")
+    ref = G.R.render_backward(m, ds, dEdp, edge_samples=-1, groups=groups, reuse_forward=True, workspace=ws)
+    torch.cuda.synchronize()
+    want = {k: G.to_np(ref[k]) for k in groups}
+    assert np.abs(want["cam"]).sum() > 0
+    out = {k: torch.zeros_like(ref[k]) for k in groups}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        G.R.render_backward(m, ds, dEdp, edge_samples=-1, groups=groups, reuse_forward=True, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for t in out.values():
+            t.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for k in groups:
+            assert np.array_equal(G.to_np(out[k]), want[k]), (rep, k)
