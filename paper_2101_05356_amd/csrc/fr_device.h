@@ -206,7 +206,8 @@ __device__ __forceinline__ V3 unit_axis(int k, float s) {
 
 // FAST_INV: the slab test's 1/d from the hardware reciprocal (1 ulp) instead
 // of the IEEE division.  The boxes' kBoxPad padding covers that extra ulp by
-// orders of magnitude (1e-5 absolute against ~1e-7 of the distances here),
+// orders of magnitude (1e-5 absolute, against ~1e-7 times the distance along
+// the ray for scenes of unit size),
 // so every leaf holding a triangle the ray hits is still entered and the
 // traversal's answer (any hit, or the closest hit with its id) is the same;
 // only the set of extra leaves visited may differ.  The shear of the

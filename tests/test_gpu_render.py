@@ -143,13 +143,13 @@ def test_patch_backward_parity(oracle_lib, variant):
 
 
 def test_lights_inside_the_mesh_bounds(oracle_lib):
-    """Two small lights placed inside the patch's bounding boxes, just above
-    its surface, beside lights outside them: the production shadow walk keeps
-    its exit clamp for packets whose rays end inside a box of the tree (its
-    clamp-free walk needs every ray to leave the root's boxes first), so
-    both walks run.  The production forward equals the dump build bit for
-    bit, the decisions and pixels match the oracle, and so does the adjoint
-    that traces its own shadow rays."""
+    """Two small lights placed inside the patch's bounding box, just above
+    its surface, beside lights outside it: a production shadow packet whose
+    rays end inside one of the root's child boxes keeps the exit clamp (the
+    clamp-free walk needs every ray to leave those boxes before its light).
+    The production forward equals the dump build bit for bit, the decisions
+    and pixels match the oracle, and so does the adjoint that traces its own
+    shadow rays."""
     sc = scenes.patch_scene(W=48, H=40, spp=4, n_lights=4)
     inside = scenes.square_lights(np.array([[0.2, 0.2, 0.2], [-0.25, 0.1, 0.15]]), 0.05, np.full((2, 3), 2.0))
     lights = scenes.Lights(*(np.ascontiguousarray(np.concatenate([getattr(sc.lights, f), getattr(inside, f)]))
