@@ -14,6 +14,22 @@ pytestmark = pytest.mark.usefixtures("oracle_lib")
 
 # ---------------------------------------------------------------- generator
 
+def test_philox_known_answers(oracle_lib):
+    """Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): the published
+    known-answer vectors of the 4x32, 10-round generator (counter words 0..3,
+    key words 0..1; the oracle's 64-bit key holds key word 1 in its high half)."""
+    o = oracle_lib
+    cases = [((0x00000000, 0x00000000, 0x00000000, 0x00000000), (0x00000000, 0x00000000),
+              (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+             ((0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF), (0xFFFFFFFF, 0xFFFFFFFF),
+              (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+             ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+              (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1))]
+    for ctr, (k0, k1), want in cases:
+        got = o.philox((k1 << 32) | k0, np.array([ctr], np.uint32))[0]
+        assert [int(x) for x in got] == list(want), (ctr, [hex(int(x)) for x in got])
+
+
 def test_philox_is_a_bijection_per_key_and_uniform(oracle_lib):
     o = oracle_lib
     n = 1 << 16
