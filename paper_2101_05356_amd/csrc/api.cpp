@@ -116,7 +116,14 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 size_t ws_prim_bytes(const fr_scene* s) {
   return al256((size_t)s->width * s->height * s->spp * sizeof(fr::PrimHit));
 }
-size_t ws_light_bytes(const fr_scene* s) { return al256((size_t)std::max(s->n_lights, 1) * sizeof(fr::LightRec)); }
+// the light records, then the device copies of the call's kernel arguments
+size_t ws_light_rec_bytes(const fr_scene* s) { return al256((size_t)std::max(s->n_lights, 1) * sizeof(fr::LightRec)); }
+size_t ws_light_bytes(const fr_scene* s) {
+  return ws_light_rec_bytes(s) + al256(fr::kRenderArgSlots * sizeof(fr::RenderArgs));
+}
+fr::RenderArgs* ws_args(const fr_scene* s, char* base) {
+  return reinterpret_cast<fr::RenderArgs*>(base + ws_prim_bytes(s) + ws_light_rec_bytes(s));
+}
 int fwd_chunk(const fr_render_opts* o) { return o->light_chunk > 0 ? o->light_chunk : fr::kLightChunkFwd; }
 size_t ws_vis_bytes(const fr_scene* s, int lc) {
   return s->n_lights > 0 ? al256((size_t)fr::cdiv(s->n_lights, lc) * s->width * s->height * s->spp * 4) : 0;
@@ -557,7 +564,7 @@ int fr_render_forward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, fl
   if (a.n_lchunks > 1) a.partial = reinterpret_cast<float*>(base + pb + lb + vb);
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
   if (s->n_lights > 0) fr::launch_light_setup(*s, lights, hs);
-  fr::launch_render_forward(a, d_image, hs, static_cast<hipEvent_t>(o->ev_kernel_begin),
+  fr::launch_render_forward(a, ws_args(s, base), d_image, hs, static_cast<hipEvent_t>(o->ev_kernel_begin),
                             static_cast<hipEvent_t>(o->ev_kernel_end));
   FR_HIP(m->ctx, hipGetLastError());
   WsState now;
@@ -719,8 +726,9 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
       forked = true;
     }
   }
-  fr::launch_render_backward(a, d_dEdp, fg, w.slots, *g, hs, static_cast<hipEvent_t>(o->ev_kernel_begin),
-                             static_cast<hipEvent_t>(o->ev_kernel_end), !reuse);
+  fr::launch_render_backward(a, ws_args(s, base), d_dEdp, fg, w.slots, *g, hs,
+                             static_cast<hipEvent_t>(o->ev_kernel_begin), static_cast<hipEvent_t>(o->ev_kernel_end),
+                             !reuse);
   FR_HIP(m->ctx, hipGetLastError());
   // the hits now belong to this call; the masks stay only if they were this call's
   WsState now;

@@ -460,15 +460,15 @@ __device__ __forceinline__ void render_bwd_block(const RenderArgs& a, const floa
 // fit five waves per SIMD without spilling; the kept-mask kernel runs at the
 // occupancy that measured fastest.
 template <bool TEX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_render_bwd(RenderArgs a, const float* __restrict__ dEdp, FixGrads g,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_render_bwd(const RenderArgs* __restrict__ pa, const float* __restrict__ dEdp, FixGrads g,
                                                     fix_t* __restrict__ slots) {
-  render_bwd_block<TEX, false>(a, dEdp, g, slots, blockIdx.x);
+  render_bwd_block<TEX, false>(*pa, dEdp, g, slots, blockIdx.x);
 }
 
 template <bool TEX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_render_bwd_kept(RenderArgs a, const float* __restrict__ dEdp, FixGrads g,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_render_bwd_kept(const RenderArgs* __restrict__ pa, const float* __restrict__ dEdp, FixGrads g,
                                                     fix_t* __restrict__ slots) {
-  render_bwd_block<TEX, true>(a, dEdp, g, slots, blockIdx.x);
+  render_bwd_block<TEX, true>(*pa, dEdp, g, slots, blockIdx.x);
 }
 
 // Sum the slots (exact integer sums) into the caller's light and camera gradients.
@@ -513,33 +513,42 @@ __global__ __launch_bounds__(256) void k_slots_reduce(const fix_t* __restrict__ 
 // sample-level chain is linear in the per-sample adjoint it starts from, so
 // the groups' chains and scatters add up to the chain of the full sum (the
 // vertex, texel and slot sums are exact integer sums).
-void launch_render_backward(const RenderArgs& a, const float* dEdp, const FixGrads& fg, fix_t* slots,
-                            const fr_grads& g, hipStream_t st, hipEvent_t e0, hipEvent_t e1, bool trace_primary) {
+void launch_render_backward(const RenderArgs& a, RenderArgs* d_args, const float* dEdp, const FixGrads& fg,
+                            fix_t* slots, const fr_grads& g, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                            bool trace_primary) {
   const int blocks = tile_blocks(a);
-  if (e0) (void)hipEventRecord(e0, st);
-  if (trace_primary) launch_primary(a, st);
-  const int user_lc = a.lc;
-  for (int g0 = 0; g0 == 0 || g0 < a.L; g0 += kBwdMaxLights) {
+  // slot 0: the call's arguments (camera pass); slot 1: the light group's
+  const auto group_args = [&](int g0) {
     RenderArgs ag = a;
     ag.L = std::min(kBwdMaxLights, a.L - g0);
     ag.light0 = a.light0 + g0;
     ag.lights = a.lights + g0;
-    ag.lc = std::max(user_lc, std::max(1, cdiv(ag.L, 4)));
+    ag.lc = std::max(a.lc, std::max(1, cdiv(ag.L, 4)));
     ag.n_lchunks = std::max(1, cdiv(ag.L, ag.lc));
     if (g0 > 0) ag.sh_bands = 0;   // the SH light goes with the first group
+    return ag;
+  };
+  if (trace_primary) launch_put_args(a, d_args, st);
+  launch_put_args(group_args(0), d_args + 1, st);
+  if (e0) (void)hipEventRecord(e0, st);
+  if (trace_primary) launch_primary(a, d_args, st);
+  for (int g0 = 0; g0 == 0 || g0 < a.L; g0 += kBwdMaxLights) {
+    const RenderArgs ag = group_args(g0);
+    if (g0 > 0) launch_put_args(ag, d_args + 1, st);   // the previous group's kernel has finished
     const int nl = ag.L * 12 + 12 + 3 * ag.sh_bands * ag.sh_bands;
     launch_zero_fix(slots, (size_t)kSlots * nl, st);
     const size_t lds = nl * sizeof(fix_t) + kBwdPartBytes;
+    const RenderArgs* pg = d_args + 1;
     if (ag.vis_in) {
       if (ag.M > 0)
-        hipLaunchKernelGGL(k_render_bwd_kept<true>, dim3(blocks), dim3(256), lds, st, ag, dEdp, fg, slots);
+        hipLaunchKernelGGL(k_render_bwd_kept<true>, dim3(blocks), dim3(256), lds, st, pg, dEdp, fg, slots);
       else
-        hipLaunchKernelGGL(k_render_bwd_kept<false>, dim3(blocks), dim3(256), lds, st, ag, dEdp, fg, slots);
+        hipLaunchKernelGGL(k_render_bwd_kept<false>, dim3(blocks), dim3(256), lds, st, pg, dEdp, fg, slots);
     } else {
       if (ag.M > 0)
-        hipLaunchKernelGGL(k_render_bwd<true>, dim3(blocks), dim3(256), lds, st, ag, dEdp, fg, slots);
+        hipLaunchKernelGGL(k_render_bwd<true>, dim3(blocks), dim3(256), lds, st, pg, dEdp, fg, slots);
       else
-        hipLaunchKernelGGL(k_render_bwd<false>, dim3(blocks), dim3(256), lds, st, ag, dEdp, fg, slots);
+        hipLaunchKernelGGL(k_render_bwd<false>, dim3(blocks), dim3(256), lds, st, pg, dEdp, fg, slots);
     }
     if (e1 && g0 + kBwdMaxLights >= a.L) (void)hipEventRecord(e1, st);
     hipLaunchKernelGGL(k_slots_reduce, dim3(nl), dim3(256), 0, st, slots, nl, ag.L,

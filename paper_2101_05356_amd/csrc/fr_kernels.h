@@ -255,10 +255,18 @@ void launch_bake_map(const int32_t* tris, const float* uv, int F, const float* a
 void launch_zero(float* p, int n, hipStream_t st);
 void launch_axpy(float* dst, const float* src, float a, const float* s, int n, hipStream_t st);   // dst += a s[0] src
 // render.hip
-// The primary pass (camera-ray hits into a.prim); the render launchers run it first.
-void launch_primary(const RenderArgs& a, hipStream_t st);
-void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st, hipEvent_t e0 = nullptr,
-                           hipEvent_t e1 = nullptr);
+// The render kernels of single calls read their arguments from device memory
+// (`d_args`, kRenderArgSlots copies from the call's workspace), written by
+// launch_put_args on the same stream: read through a pointer, the arguments
+// leave the kernels' scalar registers free (passed by value they were held
+// in them, and spilled).
+constexpr int kRenderArgSlots = 2;   // the call's arguments, and an adjoint light group's
+void launch_put_args(const RenderArgs& a, RenderArgs* d_slot, hipStream_t st);
+// The primary pass (camera-ray hits into a.prim) with the arguments already
+// in d_slot; the render launchers run it first.
+void launch_primary(const RenderArgs& a, const RenderArgs* d_slot, hipStream_t st);
+void launch_render_forward(const RenderArgs& a, RenderArgs* d_args, float* image, hipStream_t st,
+                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Default lights per work item: short items balance the forward launch; the
 // backward repeats more per-item work (primary trace, chain, scatter), so it
 // takes longer items.
@@ -291,9 +299,9 @@ size_t map_reg_scratch_bytes(int M);
 // Interior adjoint: per-vertex gradients into `fg`, light and camera
 // gradients into the slots and then added to g.light_geom, g.light_rad, g.cam.
 // With trace_primary false, a.prim already holds this call's camera-ray hits.
-void launch_render_backward(const RenderArgs& a, const float* dEdp, const FixGrads& fg, fix_t* slots,
-                            const fr_grads& g, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
-                            bool trace_primary = true);
+void launch_render_backward(const RenderArgs& a, RenderArgs* d_args, const float* dEdp, const FixGrads& fg,
+                            fix_t* slots, const fr_grads& g, hipStream_t st, hipEvent_t e0 = nullptr,
+                            hipEvent_t e1 = nullptr, bool trace_primary = true);
 // edges.hip
 void launch_edges(MeshDev& m, const RenderArgs& a, const float* dEdp, int n_samples, fix_t* gverts, fix_t* gcam,
                   int32_t* dbg_rec, uint8_t* dbg_flag, double tan_half, hipStream_t st);

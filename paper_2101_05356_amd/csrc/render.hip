@@ -74,16 +74,28 @@ __device__ __forceinline__ void primary_block(const RenderArgs& a, int bid) {
 
 // eight waves per SIMD (64 VGPRs): 133 us against 139 us at six on the face render
 template <bool DUMP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_primary(RenderArgs a) {
-  primary_block<DUMP>(a, blockIdx.x);
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_primary(const RenderArgs* __restrict__ pa) {
+  primary_block<DUMP>(*pa, blockIdx.x);
 }
 
-void launch_primary(const RenderArgs& a, hipStream_t st) {
+// One call's arguments into its device slot (word by word).
+__global__ __launch_bounds__(256) void k_put_args(RenderArgs a, RenderArgs* __restrict__ dst) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&a);
+  uint32_t* out = reinterpret_cast<uint32_t*>(dst);
+  for (int i = threadIdx.x; i < (int)(sizeof(RenderArgs) / 4); i += 256) out[i] = src[i];
+}
+static_assert(sizeof(RenderArgs) % 4 == 0, "RenderArgs copied as 32-bit words");
+
+void launch_put_args(const RenderArgs& a, RenderArgs* d_slot, hipStream_t st) {
+  hipLaunchKernelGGL(k_put_args, dim3(1), dim3(256), 0, st, a, d_slot);
+}
+
+void launch_primary(const RenderArgs& a, const RenderArgs* d_slot, hipStream_t st) {
   const int blocks = wave_blocks_items(a, 1);
   if (a.dbg_hit)
-    hipLaunchKernelGGL(k_primary<true>, dim3(blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_primary<true>, dim3(blocks), dim3(256), 0, st, d_slot);
   else
-    hipLaunchKernelGGL(k_primary<false>, dim3(blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_primary<false>, dim3(blocks), dim3(256), 0, st, d_slot);
 }
 
 template <bool DUMP, bool TEX, bool LANE = false>
@@ -175,16 +187,16 @@ __device__ __forceinline__ void render_fwd_block(const RenderArgs& a, float* __r
 }
 
 template <bool DUMP, bool TEX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_render_fwd(RenderArgs a, float* __restrict__ image) {
-  render_fwd_block<DUMP, TEX>(a, image, blockIdx.x);
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_render_fwd(const RenderArgs* __restrict__ pa, float* __restrict__ image) {
+  render_fwd_block<DUMP, TEX>(*pa, image, blockIdx.x);
 }
 
 // The forward with the per-lane shadow-ray traversal (fr_render_opts.
 // shadow_traversal = 1; production builds only): same results, measured
 // against the wave packet.
 template <bool TEX>
-__global__ __launch_bounds__(256) void k_render_fwd_lane(RenderArgs a, float* __restrict__ image) {
-  render_fwd_block<false, TEX, true>(a, image, blockIdx.x);
+__global__ __launch_bounds__(256) void k_render_fwd_lane(const RenderArgs* __restrict__ pa, float* __restrict__ image) {
+  render_fwd_block<false, TEX, true>(*pa, image, blockIdx.x);
 }
 
 // image = sum over light chunks of the partial images, in chunk order.
@@ -202,22 +214,24 @@ __global__ __launch_bounds__(256) void k_sum_chunks(const float* __restrict__ pa
   sum_chunks_block(partial, n, nch, image, blockIdx.x);
 }
 
-void launch_render_forward(const RenderArgs& a, float* image, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+void launch_render_forward(const RenderArgs& a, RenderArgs* d_args, float* image, hipStream_t st, hipEvent_t e0,
+                           hipEvent_t e1) {
   const int blocks = wave_blocks_items(a);
+  launch_put_args(a, d_args, st);
   if (e0) (void)hipEventRecord(e0, st);
-  launch_primary(a, st);
+  launch_primary(a, d_args, st);
   if (a.shadow_traversal == 1 && !a.dbg_hit) {
-    if (a.M > 0) hipLaunchKernelGGL((k_render_fwd_lane<true>), dim3(blocks), dim3(256), 0, st, a, image);
-    else hipLaunchKernelGGL((k_render_fwd_lane<false>), dim3(blocks), dim3(256), 0, st, a, image);
+    if (a.M > 0) hipLaunchKernelGGL((k_render_fwd_lane<true>), dim3(blocks), dim3(256), 0, st, d_args, image);
+    else hipLaunchKernelGGL((k_render_fwd_lane<false>), dim3(blocks), dim3(256), 0, st, d_args, image);
   } else if (a.M > 0) {
     if (a.dbg_hit)
-      hipLaunchKernelGGL((k_render_fwd<true, true>), dim3(blocks), dim3(256), 0, st, a, image);
+      hipLaunchKernelGGL((k_render_fwd<true, true>), dim3(blocks), dim3(256), 0, st, d_args, image);
     else
-      hipLaunchKernelGGL((k_render_fwd<false, true>), dim3(blocks), dim3(256), 0, st, a, image);
+      hipLaunchKernelGGL((k_render_fwd<false, true>), dim3(blocks), dim3(256), 0, st, d_args, image);
   } else if (a.dbg_hit) {
-    hipLaunchKernelGGL((k_render_fwd<true, false>), dim3(blocks), dim3(256), 0, st, a, image);
+    hipLaunchKernelGGL((k_render_fwd<true, false>), dim3(blocks), dim3(256), 0, st, d_args, image);
   } else {
-    hipLaunchKernelGGL((k_render_fwd<false, false>), dim3(blocks), dim3(256), 0, st, a, image);
+    hipLaunchKernelGGL((k_render_fwd<false, false>), dim3(blocks), dim3(256), 0, st, d_args, image);
   }
   if (e1) (void)hipEventRecord(e1, st);
   if (a.n_lchunks > 1) {

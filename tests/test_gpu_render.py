@@ -305,23 +305,36 @@ def test_backward_reusing_the_forward_decisions_is_bit_identical(oracle_lib):
 def test_per_lane_shadow_traversal_gives_the_packet_results(oracle_lib, textured):
     """The per-lane shadow-ray walk (fr_render_opts.shadow_traversal = 1)
     answers the same any-hit queries as the wave packet, so the production
-    forward's image and kept shadow decisions are the packet's bit for bit."""
+    forward's image, camera hits and light records are the packet's bit for
+    bit, and so are the gradients of the adjoint that takes its kept shadow
+    decisions."""
     if textured:
         sc = scenes.patch_scene(W=40, H=24, spp=4)
         sc = scenes.with_maps(sc, scenes.patch_corner_uv(sc), 16, seed=5)
     else:
         sc = scenes.face_render_scene(W=64, H=64, spp=4, n_lights=12)
     m, ds = G.gpu_setup(sc)
+    # the workspace opens with the camera hits and the light records (each
+    # padded to 256 bytes); the kept shadow masks follow after the call's
+    # own argument slots, which differ in the traversal option
+    head = (-(-sc.camera.W * sc.camera.H * sc.spp * 24 // 256) * 256 +
+            -(-max(sc.lights.count, 1) * 64 // 256) * 256)
+    dEdp = torch.tensor(np.random.default_rng(6).normal(size=(sc.camera.H, sc.camera.W, 3)).astype(np.float32)).cuda()
     outs = []
     for trav in (0, 1):
-        # zero-filled, so that the workspaces' padding compares equal too:
-        # hits, light records, kept shadow masks and partial images
         ws = torch.zeros(m.workspace_bytes(ds, keep_shadows=True), dtype=torch.uint8, device="cuda")
         img = G.R.render_forward(m, ds, keep_shadows=True, workspace=ws, shadow_traversal=trav)
         torch.cuda.synchronize()
-        outs.append((G.to_np(img), G.to_np(ws)))
+        head_bytes = G.to_np(ws[:head])
+        # the adjoint that takes the kept decisions: equal gradients, equal decisions
+        g = G.R.render_backward(m, ds, dEdp, groups=("verts", "light_rad", "light_geom"), reuse_forward=True,
+                                workspace=ws)
+        torch.cuda.synchronize()
+        outs.append((G.to_np(img), head_bytes, {k: G.to_np(v) for k, v in g.items()}))
     assert np.array_equal(outs[0][0], outs[1][0]), "images differ"
-    assert np.array_equal(outs[0][1], outs[1][1]), "kept decisions differ"
+    assert np.array_equal(outs[0][1], outs[1][1]), "hits or light records differ"
+    for k in outs[0][2]:
+        assert np.array_equal(outs[0][2][k], outs[1][2][k]), f"gradients from the kept decisions differ: {k}"
     from paper_2101_05356_amd import _lib
     with pytest.raises(_lib.FrError, match="shadow_traversal"):
         G.R.render_forward(m, ds, shadow_traversal=2)
