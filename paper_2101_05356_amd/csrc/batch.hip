@@ -118,7 +118,7 @@ FR_BATCH_KERNEL(kb_edge_len, 256) {
 }
 FR_BATCH_KERNEL(kb_edge_scan, 256) { FR_JOB_PROLOGUE edge_scan_local_block(J.edge_len, J.ea.E, J.edge_cdf, J.scan_part, lb); }
 FR_BATCH_KERNEL(kb_edge_scan_add, 256) { FR_JOB_PROLOGUE edge_scan_add_block(J.edge_cdf, J.ea.E, J.scan_part, lb); }
-__attribute__((amdgpu_waves_per_eu(6))) FR_BATCH_KERNEL(kb_edge_samples, 256) { FR_JOB_PROLOGUE edge_samples_block<false, false>(J.rb, J.ea, lb); }
+__attribute__((amdgpu_waves_per_eu(8))) FR_BATCH_KERNEL(kb_edge_samples, 256) { FR_JOB_PROLOGUE edge_samples_block<false, false>(J.rb, J.ea, lb); }
 // shadow-edge term into the vertex accumulators (its jumps' light points are
 // shaded with the step's light records; the camera rays are traced again)
 FR_BATCH_KERNEL(kb_shadow_edges, 256) {
