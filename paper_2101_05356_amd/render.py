@@ -277,7 +277,10 @@ def render_backward(mesh: Mesh, sc: DeviceScene, dEdp: torch.Tensor, brdf_varian
     when it had the same size, samples, counters, vertex and camera buffers,
     and its shadow decisions when it kept them for the same light buffers
     (their contents unchanged since; the library checks the rest).  `out`:
-    tensors (by group name) the gradients are added into instead of new ones."""
+    tensors (by group name) the gradients are added into instead of new ones.
+    The edge-sampling term runs on a second stream of the mesh, forked from
+    and joined back to the current stream, so the call stays ordered on it
+    (also inside torch.cuda.graph capture)."""
     dev = sc.verts.device
     N, L, M = mesh.n_verts, sc.n_lights, sc.tex_size
     B = sc.sh_bands
