@@ -83,12 +83,15 @@ def replay_rgb(sc, orc, merged_hit, merged_vis, pixels=None, **kw):
 
 
 def pixel_tol_ok(gpu, ref):
+    """|gpu - ref| <= 1e-4 max(|ref|, 1e-3 max |ref|) per channel (a black
+    reference demands a black image); returns (ok, worst relative error)."""
     gpu = np.asarray(gpu, np.float64).reshape(-1, 3)
     ref = np.asarray(ref, np.float64).reshape(-1, 3)
     floor = 1e-3 * np.abs(ref).max()
-    tol = 1e-4 * np.maximum(np.abs(ref), floor)
+    scale = np.maximum(np.abs(ref), floor)
     err = np.abs(gpu - ref)
-    return bool(np.all(err <= tol)), float((err / np.maximum(np.abs(ref), floor)).max())
+    rel = np.divide(err, scale, out=np.where(err > 0, np.inf, 0.0), where=scale > 0)
+    return bool(np.all(err <= 1e-4 * scale)), float(rel.max()) if rel.size else 0.0
 
 
 def grad_tol_ok(gpu, ref, rel=1e-4, floor_frac=1e-2, mag=None, cond_max=10.0):

@@ -174,6 +174,62 @@ def test_face_parity_4096_pixels(oracle_lib):
     _backward_parity(sc, pixels=px, conditioned=True)
 
 
+def _one_triangle(sc):
+    """The scene's lights and camera over a single triangle facing the
+    camera: no tree (the traversal tests its one leaf directly), no occluder
+    for the shadow rays, and three border edges for the boundary term."""
+    rng = np.random.default_rng(23)
+    verts = np.array([[-0.6, -0.5, 0.0], [0.7, -0.4, 0.1], [-0.1, 0.6, -0.05]], np.float32)
+    return dataclasses.replace(sc, verts=verts, tris=np.array([[0, 1, 2]], np.int32),
+                               diffuse=rng.uniform(0.3, 0.8, (3, 3)).astype(np.float32),
+                               specular=rng.uniform(0.1, 0.5, (3, 3)).astype(np.float32),
+                               roughness=rng.uniform(0.2, 0.6, 3).astype(np.float32))
+
+
+def test_degenerate_renders(oracle_lib):
+    """Degenerate inputs of the render path against the oracle.  A
+    one-triangle mesh on a 1 x 1 image at 16 spp and on a ragged 7 x 5 image
+    at 1 spp: forward decisions and pixels, interior adjoint, boundary term.
+    A camera turned away from the patch (every camera ray misses, every
+    silhouette edge lies behind it, so the sampling CDF is empty): image,
+    interior adjoint and boundary term exactly zero.  No lights and no SH
+    light: a black image and zero gradients."""
+    import oracle
+    for (W, H, S) in [(1, 1, 16), (7, 5, 1)]:
+        sc = _one_triangle(scenes.patch_scene(W=W, H=H, spp=S, n_lights=3))
+        _note(f"one triangle, {W}x{H}, spp {S}")
+        _backward_parity(sc)
+        m, ds = G.gpu_setup(sc)
+        w = np.random.default_rng(29).normal(size=(W * H, 3)).astype(np.float32)
+        G.edge_term_parity(sc, m, ds, w, 256, flag_max=0.02, note=_note)
+    sc = scenes.patch_scene(W=16, H=12, spp=4)
+    away = dataclasses.replace(sc, camera=dataclasses.replace(
+        sc.camera, R=np.diag([-1.0, 1.0, -1.0]).astype(np.float32)))
+    _note("camera turned away")
+    m, ds, img, hit, vis, mh, mv = _forward_parity(away)
+    assert np.all(hit == -1) and not np.any(img)
+    dEdp = torch.tensor(np.random.default_rng(31).normal(size=(12, 16, 3)).astype(np.float32)).cuda()
+    g = G.R.render_backward(m, ds, dEdp, edge_samples=16 * 12, groups=("verts", "cam", "light_geom"))
+    torch.cuda.synchronize()
+    eo = oracle.edge_grad(away, G.to_np(dEdp).reshape(-1, 3).astype(np.float64), 16 * 12)
+    assert not np.any(eo["verts"]) and not np.any(eo["cam"])
+    for k in ("verts", "cam", "light_geom"):
+        assert not np.any(G.to_np(g[k])), k
+    # (a dump has no shadow decisions to hold here: the production kernels)
+    dark = dataclasses.replace(sc, lights=scenes.square_lights(np.zeros((0, 3)), 0.2, np.zeros((0, 3))))
+    _note("no lights")
+    m, ds = G.gpu_setup(dark)
+    img = G.to_np(G.R.render_forward(m, ds))
+    g = G.R.render_backward(m, ds, dEdp, edge_samples=16 * 12)
+    torch.cuda.synchronize()
+    ref = oracle.render(dark)
+    go = oracle.grad(dark, ref["hit"], ref["vis"], G.to_np(dEdp).reshape(-1, 3).astype(np.float64))
+    assert np.any(np.asarray(ref["hit"]) >= 0) and not np.any(ref["rgb"]) and not np.any(img)
+    assert not any(np.any(v) for v in go.values())
+    for k, v in g.items():
+        assert not np.any(G.to_np(v)), k
+
+
 def test_refit_matches_rebuild(oracle_lib):
     """Traversal results do not depend on the BVH: a refit of moved vertices
     renders bit-identically to a fresh build over the same vertices."""
