@@ -96,6 +96,33 @@ def test_job_alone_equals_job_in_mix(env):
     assert same(r2["image"], r1["image"])
 
 
+def test_tiny_jobs(env):
+    """A 1 x 1 job (16 spp, one light) and a 3 x 3 job (1 spp): each equals
+    the same job run alone when it shares its batch with a full-size job,
+    and the 1 x 1 job equals its per-call composition step for step."""
+    recon, ctx, mt = env
+    one = make_job(env, 13, W=1, spp=16, L=1)
+    three = make_job(env, 14, W=3, spp=1, L=2)
+    big = make_job(env, 15, W=40, spp=4, L=6)
+    b1, (i1,) = run_batch(env, [one], 4)
+    b3, (i3,) = run_batch(env, [three], 4)
+    bm, ids = run_batch(env, [big, one, three], 4)
+    for alone, k in ((b1.read(i1, image=True), ids[1]), (b3.read(i3, image=True), ids[2])):
+        mixed = bm.read(k, image=True)
+        assert alone["t"] == mixed["t"] == 4
+        for f in ("losses", "params", "grad", "image"):
+            assert same(mixed[f], alone[f]), f
+    single = recon.Reconstruction(ctx, mt, one)
+    losses = [float(single.step().item()) for _ in range(4)]
+    torch.cuda.synchronize()
+    out = b1.read(i1, image=True)
+    assert np.all(np.isfinite(out["losses"]))
+    assert same(out["losses"], np.array(losses, np.float32))
+    assert same(out["grad"], single.grad.cpu().numpy())
+    assert same(out["params"], single.param.cpu().numpy())
+    assert same(out["image"], single.last_image.cpu().numpy())
+
+
 def test_continuous_batching_add_remove(env):
     """Jobs join and leave between steps; the others carry on unchanged."""
     recon, ctx, mt = env
