@@ -662,10 +662,11 @@ int fr_render_backward(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, c
   fr::fix_t* acc_s = d.acc + 9 * N;
   fr::fix_t* acc_r = d.acc + 12 * N;
   fr::fix_t* acc_cam = d.acc + 13 * N;
-  // max |dE/dp| sets the power-of-two scale of the fixed-point sums
+  // max |dE/dp| / spp (the largest per-sample seed) sets the power-of-two
+  // scale of the fixed-point sums
   uint32_t* gmax = reinterpret_cast<uint32_t*>(d.acc + 13 * N + 12);
   fr::launch_zero_fix(d.acc, 13 * N + 13, hs);
-  fr::launch_abs_max(d_dEdp, 3 * a.W * a.H, gmax, hs);
+  fr::launch_abs_max(d_dEdp, 3 * a.W * a.H, a.S, gmax, hs);
   a.gmax = gmax;
   // texel accumulators [7 M^2]: diffuse, specular (3 M^2 each), roughness (M^2)
   const size_t MM = (size_t)a.M * a.M;
@@ -775,9 +776,9 @@ int fr_shadow_edges(fr_mesh* m, const fr_scene* s, const fr_render_opts* o, cons
   a.lights = lights;
   fr::fix_t* acc = reinterpret_cast<fr::fix_t*>(base + roff);
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
-  uint32_t* gmax = reinterpret_cast<uint32_t*>(acc + nacc - 1);   // max |dE/dp|: the sums' scale
+  uint32_t* gmax = reinterpret_cast<uint32_t*>(acc + nacc - 1);   // max |dE/dp| / spp: the sums' scale
   fr::launch_zero_fix(acc, nacc, hs);
-  fr::launch_abs_max(d_dEdp, 3 * s->width * s->height, gmax, hs);
+  fr::launch_abs_max(d_dEdp, 3 * s->width * s->height, s->spp, gmax, hs);
   fr::launch_light_setup(*s, lights, hs);
   fr::ShadowEdgeArgs e;
   e.nbr = m->d.face_nbr;
@@ -884,6 +885,7 @@ struct JobHost {
   char* arena = nullptr;
   size_t bytes = 0;
   int n_param = 0, W = 0, H = 0, hist_cap = 0;
+  uint32_t gmax_bits = 0;   // source of the job's scale word (lives until the job is destroyed)
   fr::JobDev dev{};
 };
 
@@ -909,6 +911,7 @@ void layout_job(Carver& c, const fr_model* md, const fr_job_desc* d, fr::JobDev&
   J.lp0 = c.take<float>(3 * L); J.le1 = c.take<float>(3 * L); J.le2 = c.take<float>(3 * L);
   J.lshape = c.take<int32_t>(L);
   J.ra.cam = c.take<float>(12);
+  J.gmax = c.take<uint32_t>(1);
 }
 
 int validate_job(fr_model* md, const fr_job_desc* d) {
@@ -1029,7 +1032,12 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   auto cp = [&](const void* dst, const void* src, size_t bytes) {
     return hipMemcpyAsync(const_cast<void*>(dst), src, bytes, hipMemcpyDefault, st) == hipSuccess;
   };
-  bool ok = cp(J.param, d->params, 4 * n_param) && cp(J.lr, d->lr, 4 * n_param) && cp(J.target, d->target, 4 * px3) &&
+  // the sums' scale as a per-call backward takes it when max |dE/dp| = 1:
+  // the batch's dE/dp is the photometric loss's (smoothed) sign image
+  const float inv_spp = 1.0f / (float)d->spp;
+  std::memcpy(&jh->gmax_bits, &inv_spp, sizeof(inv_spp));
+  bool ok = cp(J.gmax, &jh->gmax_bits, 4) &&
+            cp(J.param, d->params, 4 * n_param) && cp(J.lr, d->lr, 4 * n_param) && cp(J.target, d->target, 4 * px3) &&
             cp(J.lp0, d->light_p0, 12 * L) && cp(J.le1, d->light_e1, 12 * L) && cp(J.le2, d->light_e2, 12 * L) &&
             cp(J.lshape, d->light_shape, 4 * L) && cp(J.ra.cam, d->cam, 48);
   ok = ok && hipMemsetAsync(J.adam_m, 0, 4 * n_param, st) == hipSuccess &&
@@ -1067,6 +1075,7 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   J.rb.vis_in = vis; J.rb.vis_lc = J.ra.lc;
   J.ra.lights = J.lights; J.rb.lights = J.lights;
   J.ra.cam = cam; J.rb.cam = cam;
+  J.rb.gmax = J.gmax;   // the interior adjoint's seeds dE/dp / spp under the job's scale
   const fr::MeshDev& md_ = jh->mesh->d;
   J.ea.edges = md_.edges; J.ea.cdf = md_.edge_cdf; J.ea.E = md_.E;
   J.ea.n_samples = d->edge_samples < 0 ? d->width * d->height : d->edge_samples;
@@ -1074,12 +1083,12 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   J.ea.th = std::tan(0.5 * (double)d->fov_y);
   J.ea.aspect = (double)d->width / (double)d->height;
   J.ea.dEdp = J.dEdp; J.ea.gverts = md_.acc; J.ea.gcam = nullptr; J.ea.dbg_rec = nullptr; J.ea.dbg_flag = nullptr;
-  J.ea.gmax = nullptr;   // the batch's dE/dp is the photometric loss's (smoothed) sign image, within [-1, 1]: no scale
+  J.ea.gmax = J.gmax;
   // shadow-edge term: vertex gradients only (the batch optimises no light geometry or camera)
   J.se = fr::ShadowEdgeArgs{};
   J.se.nbr = md_.face_nbr;
   J.se.n_samples = d->shadow_edge_samples < 0 ? d->width * d->height : d->shadow_edge_samples;
-  J.se.dEdp = J.dEdp; J.se.gverts = md_.acc;
+  J.se.dEdp = J.dEdp; J.se.gverts = md_.acc; J.se.gmax = J.gmax;
   J.mean_geo = md->mean_geo; J.basis_geo = md->basis_geo; J.mean_alb = md->mean_alb; J.basis_alb = md->basis_alb;
   J.K_geo = md->K_geo; J.K_alb = md->K_alb; J.N = N; J.F = md->topo.F; J.M = M;
   J.hist_cap = jh->hist_cap;

@@ -21,6 +21,7 @@ struct JobDev {
   float* loss_hist; int hist_cap;
   float* g_verts; float* g_diffuse; float* g_vobj; float* gnorm; fix_t* lslots; int zero_stride;
   fix_t* acc;               // fixed-point accumulators: verts [3N], normals [3N], diffuse [3N]
+  uint32_t* gmax;           // the sums' scale: bits of max |dE/dp| / spp = 1 / spp (grad_scale)
   float* param; float* grad; float* adam_m; float* adam_v; const float* lr;
   int n_param, off_alb, off_pose, off_rad;
   const int32_t* tris; const int32_t* vf_off; const int32_t* vf_idx; float* normals; float* nlen;

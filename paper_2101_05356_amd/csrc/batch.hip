@@ -98,12 +98,13 @@ FR_BATCH_KERNEL(kb_fix_finalize, 256) {
   FR_JOB_PROLOGUE
   const int i = lb * 256 + threadIdx.x;
   if (i >= 3 * J.N) return;
-  J.g_verts[i] = (float)from_fix(J.acc[i]);
-  J.g_diffuse[i] = (float)from_fix(J.acc[6 * J.N + i]);
+  const double s = (double)grad_scale(J.gmax);
+  J.g_verts[i] = (float)(from_fix(J.acc[i]) / s);
+  J.g_diffuse[i] = (float)(from_fix(J.acc[6 * J.N + i]) / s);
 }
 FR_BATCH_KERNEL(kb_slots_reduce, 256) {
   FR_JOB_PROLOGUE slots_reduce_block(J.lslots, 12 * J.ra.L + 12, J.ra.L, nullptr, J.grad + J.off_rad, nullptr, nullptr,
-                                     lb);
+                                     lb, J.gmax);
 }
 FR_BATCH_KERNEL(kb_normals_bwd_project, 256) {
   FR_JOB_PROLOGUE normals_bwd_project_block(J.v_w, J.tris, J.vf_off, J.vf_idx, J.N, J.acc + 3 * J.N, J.gnorm, lb);

@@ -47,19 +47,20 @@ __device__ __forceinline__ void fix_add_d(fix_t* p, double v) {
 }
 __host__ __device__ __forceinline__ double from_fix(fix_t a) { return (double)(long long)a * (1.0 / kFixOne); }
 
-// The quantum 2^-32 is absolute, so a backward scales its input dE/dp by a
-// power of two s chosen from max |dE/dp| (the bits of that maximum, gathered
-// by k_abs_max): s = 1 when the maximum is at least 1 (the photometric
-// loss's own dE/dp, at most 1 per channel), else 2^-floor(log2 max) (at most
-// 2^60).  Every contribution then sits in the same range whatever the
-// caller's scale; the conversions to FP32 divide by s.  Scaling by a power
-// of two is exact, and s = 1 leaves every value as it was.  gmax null: s = 1.
+// The quantum 2^-32 is absolute, so a backward scales its per-sample seeds
+// dE/dp / S by a power of two s chosen from their maximum (the bits of
+// max |dE/dp| / S, gathered by k_abs_max): s = 2^-floor(log2(max / S)),
+// clamped to [2^-60, 2^60], which brings the largest seed into [1, 2) at any
+// sample count and any scale of the caller's dE/dp; the conversions to FP32
+// divide by s.  Scaling by a power of two is exact.  The sums then hold s
+// times the gradient, well inside the range for the renders this library
+// takes.  gmax null: s = 1.
 __device__ __forceinline__ float grad_scale(const uint32_t* gmax) {
   if (!gmax) return 1.0f;
   const uint32_t b = *gmax;
-  const int e = (int)((b >> 23) & 0xffu) - 127;   // floor(log2 max); -127 for 0 and subnormals
-  if (b == 0u || e >= 0) return 1.0f;
-  return ldexpf(1.0f, min(-e, 60));
+  if (b == 0u) return 1.0f;
+  const int e = (int)((b >> 23) & 0xffu) - 127;   // floor(log2 max); -127 for subnormals
+  return ldexpf(1.0f, max(-60, min(-e, 60)));
 }
 
 // Fixed-point accumulators of the per-vertex gradients (each nullable).
@@ -236,7 +237,7 @@ void launch_normals_backward(MeshDev& m, const float* d_verts, const fix_t* acc_
 // out += acc / grad_scale(gmax)
 void launch_fix_to_float(const fix_t* acc, float* out, int n, hipStream_t st, const uint32_t* gmax = nullptr);
 // *gmax = max(*gmax, bits of max |x[i]|) (the caller zeroes *gmax)
-void launch_abs_max(const float* x, int n, uint32_t* gmax, hipStream_t st);
+void launch_abs_max(const float* x, int n, int spp, uint32_t* gmax, hipStream_t st);
 void launch_zero_fix(fix_t* p, size_t n, hipStream_t st);
 void launch_blend(const float* mean, const float* basis, const float* coef, int K, int M, float* out, hipStream_t st);
 void launch_blend_backward(const float* basis, const float* gout, int K, int M, float* gcoef, hipStream_t st);

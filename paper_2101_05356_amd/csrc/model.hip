@@ -169,9 +169,11 @@ void launch_fix_to_float(const fix_t* acc, float* out, int n, hipStream_t st, co
   if (n > 0) hipLaunchKernelGGL(k_fix_to_float, dim3(cdiv(n, 256)), dim3(256), 0, st, acc, out, n, gmax);
 }
 
-// Maximum of |x| as float bits (non-negative floats order like their bits):
-// a grid-stride pass, the block's maximum through LDS, one atomic per block.
-__global__ __launch_bounds__(256) void k_abs_max(const float* __restrict__ x, int n, uint32_t* __restrict__ gmax) {
+// Maximum of |x| / spp as float bits (non-negative floats order like their
+// bits; spp a power of two, so the division is exact): a grid-stride pass,
+// the block's maximum through LDS, one atomic per block.
+__global__ __launch_bounds__(256) void k_abs_max(const float* __restrict__ x, int n, float inv_spp,
+                                                 uint32_t* __restrict__ gmax) {
   __shared__ uint32_t wmax[4];
   uint32_t m = 0u;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
@@ -183,12 +185,15 @@ __global__ __launch_bounds__(256) void k_abs_max(const float* __restrict__ x, in
   __syncthreads();
   if (threadIdx.x == 0) {
     m = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
-    if (m != 0u) atomicMax(gmax, m);
+    const uint32_t q = __float_as_uint(__uint_as_float(m) * inv_spp);
+    if (q != 0u) atomicMax(gmax, q);
   }
 }
 
-void launch_abs_max(const float* x, int n, uint32_t* gmax, hipStream_t st) {
-  if (n > 0) hipLaunchKernelGGL(k_abs_max, dim3(std::min(cdiv(n, 256 * 8), 256)), dim3(256), 0, st, x, n, gmax);
+void launch_abs_max(const float* x, int n, int spp, uint32_t* gmax, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_abs_max, dim3(std::min(cdiv(n, 256 * 8), 256)), dim3(256), 0, st, x, n,
+                       1.0f / (float)spp, gmax);
 }
 
 __global__ __launch_bounds__(256) void k_zero_fix(fix_t* p, size_t n) {

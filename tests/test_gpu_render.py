@@ -142,6 +142,13 @@ def test_patch_backward_parity(oracle_lib, variant):
     _backward_parity(sc, variant=variant)
 
 
+def test_patch_parity_at_the_largest_spp(oracle_lib):
+    """spp 1024, the largest the library takes: each wave walks one pixel's
+    samples in sixteen chunks of 64; decisions, pixels and every gradient
+    group of the interior adjoint against the oracle."""
+    _backward_parity(scenes.patch_scene(W=5, H=4, spp=1024))
+
+
 def test_lights_inside_the_mesh_bounds(oracle_lib):
     """Two small lights placed inside the patch's bounding box, just above
     its surface, beside lights outside it: a production shadow packet whose
@@ -398,13 +405,13 @@ def test_per_lane_shadow_traversal_gives_the_packet_results(oracle_lib, textured
 
 def test_fixed_point_sums_at_small_gradient_scales(oracle_lib):
     """Every cross-wave gradient sum rounds each contribution to a multiple
-    of 2^-32 (an absolute quantum).  The library multiplies dE/dp by the
-    power of two that brings max |dE/dp| into [1, 2) when it is below 1 and
-    divides the sums by it again, so the quantum stays relative to the
-    gradient's size: with dE/dp scaled by 2^-k the gradients meet the parity
-    bar against the oracle's (scaled the same way, exactly) at every k, and
-    once the scale is active (k >= 6 here) they are the k = 6 results times
-    2^(6-k) bit for bit."""
+    of 2^-32 (an absolute quantum).  The library multiplies the per-sample
+    seeds dE/dp / S by the power of two that brings their maximum into
+    [1, 2) and divides the sums by it again, so the quantum stays relative
+    to the gradient's size: with dE/dp scaled by 2^-k (k = -6 scales it
+    up) the gradients meet the parity bar against the oracle's (scaled the
+    same way, exactly) at every k, and they are the k = 0 results times
+    2^-k bit for bit."""
     import oracle
     sc = scenes.patch_scene()
     m, ds, img, hit, vis, mh, mv = _forward_parity(sc)
@@ -413,19 +420,18 @@ def test_fixed_point_sums_at_small_gradient_scales(oracle_lib):
     go = oracle.grad(sc, mh, mv, dEdp.astype(np.float64))
     pairs = [("verts", "verts"), ("diffuse", "diffuse"), ("roughness", "rough"), ("light_rad", "rad"),
              ("cam", "cam"), ("light_geom", "light")]
-    ref6 = None
-    for k in (0, 6, 12, 18, 24):
+    ref0 = None
+    for k in (0, -6, 6, 12, 18, 24):
         s = 2.0 ** -k
         g = G.R.render_backward(m, ds, torch.tensor((dEdp * np.float32(s)).reshape(H, W, 3)).cuda(),   # exact
                                 groups=tuple(p[0] for p in pairs))
         torch.cuda.synchronize()
         res = {gk: G.grad_tol_ok(G.to_np(g[gk]), go[ok_] * s) for gk, ok_ in pairs}
-        _note(f"dE/dp x 2^-{k}: " + ", ".join(f"{gk} l2 {r[1]:.2e} worst {r[2]:.2e}" for gk, r in res.items()))
+        _note(f"dE/dp x 2^{-k}: " + ", ".join(f"{gk} l2 {r[1]:.2e} worst {r[2]:.2e}" for gk, r in res.items()))
         for gk, r in res.items():
             assert r[0], (k, gk, r)
-        if k >= 6:
-            up = {gk: G.to_np(g[gk]).astype(np.float64) * 2.0 ** (k - 6) for gk, _ in pairs}
-            if ref6 is None:
-                ref6 = up
-            for gk in up:
-                np.testing.assert_array_equal(up[gk], ref6[gk], err_msg=f"{gk} at k = {k}")
+        up = {gk: G.to_np(g[gk]).astype(np.float64) * 2.0 ** k for gk, _ in pairs}
+        if ref0 is None:
+            ref0 = up
+        for gk in up:
+            np.testing.assert_array_equal(up[gk], ref0[gk], err_msg=f"{gk} at k = {k}")
