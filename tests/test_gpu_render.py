@@ -145,8 +145,14 @@ def test_patch_backward_parity(oracle_lib, variant):
 def test_patch_parity_at_the_largest_spp(oracle_lib):
     """spp 1024, the largest the library takes: each wave walks one pixel's
     samples in sixteen chunks of 64; decisions, pixels and every gradient
-    group of the interior adjoint against the oracle."""
-    _backward_parity(scenes.patch_scene(W=5, H=4, spp=1024))
+    group of the interior adjoint against the oracle, then the boundary
+    term (whose per-sample weights carry no 1/S, so the fixed-point scale
+    of the seeds dE/dp / S puts its terms S times higher)."""
+    sc = scenes.patch_scene(W=5, H=4, spp=1024)
+    _backward_parity(sc)
+    m, ds = G.gpu_setup(sc)
+    w = np.random.default_rng(37).normal(size=(20, 3)).astype(np.float32)
+    G.edge_term_parity(sc, m, ds, w, 1024, flag_max=0.02, note=_note)
 
 
 def test_lights_inside_the_mesh_bounds(oracle_lib):
