@@ -885,7 +885,6 @@ struct JobHost {
   char* arena = nullptr;
   size_t bytes = 0;
   int n_param = 0, W = 0, H = 0, hist_cap = 0;
-  uint32_t gmax_bits = 0;   // source of the job's scale word (lives until the job is destroyed)
   fr::JobDev dev{};
 };
 
@@ -1032,11 +1031,15 @@ int fr_batch_add(fr_batch* b, const fr_job_desc* d, int32_t* job_id, fr_stream s
   auto cp = [&](const void* dst, const void* src, size_t bytes) {
     return hipMemcpyAsync(const_cast<void*>(dst), src, bytes, hipMemcpyDefault, st) == hipSuccess;
   };
-  // the sums' scale as a per-call backward takes it when max |dE/dp| = 1:
-  // the batch's dE/dp is the photometric loss's (smoothed) sign image
-  const float inv_spp = 1.0f / (float)d->spp;
-  std::memcpy(&jh->gmax_bits, &inv_spp, sizeof(inv_spp));
-  bool ok = cp(J.gmax, &jh->gmax_bits, 4) &&
+  // the sums' scale as a per-call backward takes it when max |dE/dp| = 1
+  // (the batch's dE/dp is the photometric loss's smoothed sign image): the
+  // bits of 1 / spp, copied from static storage so that no error path can
+  // free the source of the asynchronous copy
+  static const float kInvSpp[11] = {1.0f,       0.5f,        0.25f,        0.125f,        0.0625f,      0.03125f,
+                                    0.015625f,  0.0078125f,  0.00390625f,  0.001953125f,  0.0009765625f};
+  int log2_spp = 0;
+  while ((1 << log2_spp) < d->spp) ++log2_spp;   // spp: a power of two in [1, 1024] (validate_job)
+  bool ok = cp(J.gmax, &kInvSpp[log2_spp], 4) &&
             cp(J.param, d->params, 4 * n_param) && cp(J.lr, d->lr, 4 * n_param) && cp(J.target, d->target, 4 * px3) &&
             cp(J.lp0, d->light_p0, 12 * L) && cp(J.le1, d->light_e1, 12 * L) && cp(J.le2, d->light_e2, 12 * L) &&
             cp(J.lshape, d->light_shape, 4 * L) && cp(J.ra.cam, d->cam, 48);
